@@ -1,0 +1,163 @@
+"""One IPCS + BCE-IB time step (oracle; test infrastructure).
+
+Order of Section 2.4 of the paper, with the readings listed in the design
+notes (dynamic viscosity mu = rho nu, component-wise viscous form mu (grad u,
+grad v), semi-implicit advection u^n . grad u*, minus sign in the velocity
+correction, rho restored in the pressure equation, correction starting from
+the IB-corrected velocity):
+
+1. tentative velocity (Eq. 9, backward Euler):
+   A = (rho/dt) M + rho C(u^n) + mu K,
+   A_FF u*_F = (rho/dt)(M u^n)_F - (G_d p^n)_F - A_FD g(t^{n+1}),  u*_D = g(t^{n+1});
+2.-4. BCE-IB force and velocity correction (Eqs. 15-24): u_ib = u* + I_F^T Lambda with
+   (I_F I_F^T) Lambda = U_B - I u*;
+5. pressure increment (Eq. 12 with rho): K_{P'P'} Phi = -(rho/dt) (B u_ib)_{P'},
+   Phi = 0 on outlet nodes, natural Neumann elsewhere; on a connected part of the
+   domain without outlet the right-hand side is projected onto mean zero and the
+   nodal mean of Phi is removed;
+6. correction (L2 projection with the consistent mass):
+   M_FF u^{n+1}_F = M_FF u_ib_F - (dt/rho)(G_d Phi)_F,  u^{n+1}_D = g(t^{n+1}),
+   p^{n+1} = p^n + Phi.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.csgraph as csgraph
+
+from . import fem, grid, ib, krylov
+
+
+@dataclasses.dataclass
+class StepInfo:
+    u_star: np.ndarray
+    u_ib: np.ndarray
+    phi: np.ndarray
+    lam: np.ndarray
+    iters: dict
+    residuals: dict
+
+
+class Problem:
+    """Everything that depends only on the geometry and the parameters."""
+
+    def __init__(self, nx, ny, nz, h, origin, node_mask, bc_tag, X, dS, U_B, rho, mu, dt,
+                 inlet_K, inlet_omega, inlet_ids, inlet_shape):
+        self.nx, self.ny, self.nz, self.h = nx, ny, nz, float(h)
+        self.origin = np.asarray(origin, np.float64)
+        self.mask = np.asarray(node_mask, np.uint8)
+        self.rho, self.mu, self.dt = float(rho), float(mu), float(dt)
+        self.sets = grid.derive_sets(nx, ny, nz, self.mask, bc_tag)
+        if self.sets.P.size == 0:
+            raise ValueError("empty domain: no kept cell")
+        self.inlet_K, self.inlet_omega = int(inlet_K), float(inlet_omega)
+        self.inlet_ids = np.asarray(inlet_ids, np.int64)
+        self.inlet_shape = np.asarray(inlet_shape, np.float64)
+        grid.check_inlet_table(self.sets, self.mask, self.inlet_ids)
+        self.ops = fem.Operators(self.sets, self.h)
+        self.X = np.asarray(X, np.float64).reshape(-1, 3)
+        self.dS = float(dS)
+        self.U_B = np.zeros_like(self.X) if U_B is None else np.asarray(U_B, np.float64)
+        self.I = ib.interpolation_matrix(self.X, nx, ny, nz, self.h, self.origin)
+        self._pressure_setup()
+
+    @classmethod
+    def from_case(cls, c):
+        return cls(c.nx, c.ny, c.nz, c.h, c.origin, c.node_mask, c.bc_tag, c.X, c.dS, c.U_B,
+                   c.rho, c.mu, c.dt, c.inlet_K, c.inlet_omega, c.inlet_ids, c.inlet_shape)
+
+    # -- step 5 helpers -------------------------------------------------------
+    def _pressure_setup(self):
+        s = self.sets
+        Pp = s.Pp
+        self.K_pp = self.ops.K[Pp][:, Pp].tocsr()
+        # Connected parts of the kept region (through shared cells) without an outlet node.
+        KP = self.ops.K[s.P][:, s.P]
+        ncomp, label = csgraph.connected_components(KP, directed=False)
+        has_outlet = np.zeros(ncomp, bool)
+        has_outlet[label[s.p_dir[s.P]]] = True
+        pos_in_P = -np.ones(s.in_P.size, np.int64)
+        pos_in_P[s.P] = np.arange(s.P.size)
+        lab_pp = label[pos_in_P[Pp]]
+        self.floating = [np.nonzero(lab_pp == c)[0] for c in range(ncomp) if not has_outlet[c]]
+
+    def g(self, t: float) -> np.ndarray:
+        return grid.dirichlet_values(self.sets, self.mask, self.inlet_ids, self.inlet_shape,
+                                     self.inlet_K, self.inlet_omega, t)
+
+    # -- the time step -------------------------------------------------------
+    def step(self, u: np.ndarray, p: np.ndarray, t: float):
+        """Advance (u^n, p^n, t^n) -> (u^{n+1}, p^{n+1}, t^n + dt)."""
+        s, ops = self.sets, self.ops
+        rho, mu, dt = self.rho, self.mu, self.dt
+        F, D = s.F, s.D
+        t1 = t + dt
+        g = self.g(t1)
+        iters, resid = {}, {}
+
+        # 1. tentative velocity
+        A = ((rho / dt) * ops.M + rho * ops.advection(u) + mu * ops.K).tocsr()
+        A_FF = A[F][:, F].tocsr()
+        diag = A_FF.diagonal()
+        u_star = np.zeros_like(u)
+        for d in range(3):
+            rhs = (rho / dt) * (ops.M @ u[d]) - ops.G[d] @ p - A @ g[d]
+            x, it, res = krylov.bicgstab(A_FF, rhs[F], x0=u[d][F], diag=diag)
+            u_star[d] = g[d]
+            u_star[d][F] = x
+            iters[f"s1_{d}"], resid[f"s1_{d}"] = it, res
+
+        # 2.-4. BCE-IB correction
+        u_ib, lam, info = ib.bce_correction(self.I, s.in_F, self.U_B, u_star)
+        iters["ib"] = info.get("iters", info.get("method"))
+
+        # 5. pressure increment
+        rhs = -(rho / dt) * ops.divergence(u_ib)
+        b = rhs[s.Pp]
+        for comp in self.floating:
+            b[comp] -= b[comp].mean()
+        x, it, res = krylov.cg(self.K_pp, b, diag=self.K_pp.diagonal())
+        for comp in self.floating:
+            x[comp] -= x[comp].mean()
+        phi = np.zeros(s.in_P.size)
+        phi[s.Pp] = x
+        iters["s3"], resid["s3"] = it, res
+
+        # 6. correction
+        M_FF = ops.M[F][:, F].tocsr()
+        mdiag = M_FF.diagonal()
+        u_new = np.zeros_like(u)
+        for d in range(3):
+            rhs = M_FF @ u_ib[d][F] - (dt / rho) * (ops.G[d] @ phi)[F]
+            x, it, res = krylov.cg(M_FF, rhs, x0=u_ib[d][F], diag=mdiag)
+            u_new[d] = g[d]
+            u_new[d][F] = x
+            iters[f"s4_{d}"], resid[f"s4_{d}"] = it, res
+        p_new = np.where(s.in_P, p + phi, 0.0)
+        return u_new, p_new, t1, StepInfo(u_star, u_ib, phi, lam, iters, resid)
+
+    def initial_state(self, u0: np.ndarray, p0: np.ndarray):
+        """Restrict an initial field to P (zero elsewhere)."""
+        u = np.where(self.sets.in_P[None, :], u0, 0.0)
+        p = np.where(self.sets.in_P, p0, 0.0)
+        return u, p
+
+    def run(self, u0, p0, nsteps: int, t0: float = 0.0):
+        u, p = self.initial_state(u0, p0)
+        t = t0
+        infos = []
+        for _ in range(nsteps):
+            u, p, t, info = self.step(u, p, t)
+            infos.append(info)
+        return u, p, t, infos
+
+
+def divergence_norm(problem: Problem, u: np.ndarray) -> float:
+    """|(B u)_{P'}|_2, the discrete divergence on pressure-free nodes."""
+    return float(np.linalg.norm(problem.ops.divergence(u)[problem.sets.Pp]))
+
+
+def sparse_row(A: sp.csr_matrix, i: int):
+    return A.indices[A.indptr[i]:A.indptr[i + 1]], A.data[A.indptr[i]:A.indptr[i + 1]]
