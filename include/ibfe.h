@@ -1,0 +1,237 @@
+/*
+ * ibfe.h - C ABI of the MI355X (gfx950) IPCS + BCE-IB finite-element time step.
+ *
+ * The library advances the incompressible Navier-Stokes equations with an
+ * immersed boundary (Bourantas et al., "Immersed boundary finite element method
+ * for blood flow simulation", Section 2): each step is the incremental pressure
+ * correction scheme of Section 2.2 (tentative velocity, pressure increment,
+ * velocity/pressure correction) combined with the boundary-condition-enforced IB
+ * correction of Section 2.3 in the order of Section 2.4.  The discretisation is
+ * trilinear (Q1) on a uniform Cartesian grid reduced to the vessel by a node
+ * mask (domain reduction, Section 4).
+ *
+ * Conventions
+ *  - Grid: nx*ny*nz cells of side h, nodes (i,j,k) with 0<=i<=nx etc., node id
+ *    n = i + (nx+1)*(j + (ny+1)*k) (x fastest), N = (nx+1)(ny+1)(nz+1).
+ *  - Kept cells: cells with at least one corner of mask 1.  P = corners of kept
+ *    cells: velocity and pressure live on P, in ascending node id ("canonical
+ *    order"); every array exchanged through this ABI uses that order.
+ *  - Velocity arrays are structure-of-arrays: u[d*n + q] is component d of the
+ *    q-th node of P.  All floating point data crossing the ABI is FP64.
+ *  - Return codes: 0 on success, a negative IBFE_E* code on failure;
+ *    ibfe_last_error() returns a thread-local message for the last failure.
+ *  - Host arrays passed in are copied before the call returns; the caller keeps
+ *    ownership.  Device memory is obtained from the caller's allocator if one is
+ *    given (else hipMalloc) and belongs to the context until ibfe_destroy.  The
+ *    HIP stream is borrowed: every kernel of a context runs on it.
+ *  - A context is not thread-safe; different contexts may be used concurrently
+ *    from different threads on different streams.
+ */
+#ifndef IBFE_H
+#define IBFE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IBFE_OK 0
+#define IBFE_EINVAL (-1)     /* bad shape, value or call order                      */
+#define IBFE_ENOMEM (-2)     /* device or host allocation failed                     */
+#define IBFE_EHIP (-3)       /* HIP runtime error (no device, launch failure)        */
+#define IBFE_ENOCONV (-4)    /* a Krylov solve hit its iteration cap                 */
+#define IBFE_ENONFINITE (-5) /* NaN/Inf in a residual                                */
+#define IBFE_ESINGULAR (-6)  /* Lagrangian point without free support / breakdown    */
+
+/* Boundary tags per node (only meaningful on box-face nodes). */
+#define IBFE_TAG_NONE 0
+#define IBFE_TAG_WALL 1
+#define IBFE_TAG_INLET 2
+#define IBFE_TAG_OUTLET 3
+
+/* Node flag bits returned by ibfe_plan_node_flags. */
+#define IBFE_FLAG_P 1u      /* corner of a kept cell                            */
+#define IBFE_FLAG_F 2u      /* free velocity node                               */
+#define IBFE_FLAG_DU 4u     /* velocity Dirichlet node                          */
+#define IBFE_FLAG_PDIR 8u   /* pressure Dirichlet (outlet) node                 */
+
+/*
+ * Grid and domain reduction (Section 2.3: uniform Cartesian Eulerian nodes of
+ * spacing h; Section 4: elements outside the vessel removed).
+ *   node_mask : N bytes, 1 = inside the vessel, 0 = outside (required)
+ *   bc_tag    : N bytes of IBFE_TAG_*, or NULL for the defaults: z = 0 face
+ *               inlet, z = nz face outlet, the x and y faces wall, wall winning
+ *               on shared edges/corners.
+ *   refine_cell: reserved, must be NULL.
+ * Velocity Dirichlet nodes D_u: nodes of P with mask 0 (value 0), wall-tagged
+ * nodes of P (value 0), inlet-tagged nodes of P (inlet table value, else 0).
+ * Free velocity nodes F = P \ D_u.  Pressure Dirichlet: outlet-tagged nodes of
+ * P (pressure increment 0).  A connected part of the kept region without an
+ * outlet node has its pressure increment normalised to zero nodal mean.
+ */
+typedef struct ibfe_grid {
+  int32_t nx, ny, nz;
+  double h;
+  double origin[3];
+  const uint8_t* node_mask;
+  const uint8_t* bc_tag;
+  const uint8_t* refine_cell;
+} ibfe_grid;
+
+/*
+ * Lagrangian wall points (Section 2.3, Eqs. 17-24): X is M x 3 (row major),
+ * dS the uniform surface element of each point (Section 2.5), U_B the
+ * prescribed wall velocity, M x 3, or NULL for a wall at rest.  The IB
+ * correction solves G Lambda = U_B - I u* with G = I_F I_F^T, where
+ * I_ij = prod_d delta4((x_j,d - X_i,d)/h) over the 4x4x4 support starting at
+ * floor((X_i - origin)/h) - 1 (Eq. 17 times h^3, kernel of Eq. 18); support
+ * nodes outside the box are dropped.  Every point needs
+ * sum_{j in F} I_ij^2 >= 1e-12, else IBFE_ESINGULAR.  M may be 0.
+ */
+typedef struct ibfe_ib {
+  int64_t M;
+  const double* X;
+  double dS;
+  const double* U_B;
+} ibfe_ib;
+
+/*
+ * Physical and numerical parameters.
+ *   rho, mu, dt : density, dynamic viscosity, time step (all > 0)
+ *   precision   : 0 = FP64 throughout; 1 = FP32 inner Krylov solves inside FP64
+ *                 iterative refinement (FP64 outer residuals, dots, IB solve)
+ *   rtol        : relative residual target of the velocity and pressure solves
+ *                 (<= 0 selects 1e-13 in FP64 mode, 1e-8 in mixed mode)
+ *   max_iters   : iteration cap per Krylov solve (<= 0 selects 20000)
+ *   precond     : 0 = Jacobi (only value accepted by this version)
+ *   advection   : 0 = semi-implicit u^n . grad u* (only value accepted)
+ *   ib_rtol     : relative residual target of the IB force solve (<= 0: 1e-13)
+ */
+typedef struct ibfe_params {
+  double rho, mu, dt;
+  int32_t precision;
+  double rtol;
+  int32_t max_iters;
+  int32_t precond;
+  int32_t advection;
+  double ib_rtol;
+} ibfe_params;
+
+/*
+ * Inlet velocity table.  The prescribed velocity at table node q and time t is
+ *   u_in = W_0 + sum_{k=1..K} [ Re W_k cos(k omega t) - Im W_k sin(k omega t) ]
+ * (the real part of sum_k W_k e^{i k omega t}).  shape holds (2K+1) blocks of
+ * n x 3 doubles: W_0, Re W_1, Im W_1, ..., Re W_K, Im W_K (each block row major
+ * n x 3).  Every listed node must be an inlet-tagged node of P with mask 1.
+ */
+typedef struct ibfe_inlet {
+  int32_t K;
+  double omega;
+  int64_t n;
+  const int64_t* node_ids;
+  const double* shape;
+} ibfe_inlet;
+
+/* Device allocator used for every device buffer of a context.  alloc returns
+ * NULL on failure; stream is the context's stream. */
+typedef struct ibfe_alloc {
+  void* (*alloc)(size_t bytes, void* stream, void* user);
+  void (*free)(void* ptr, void* user);
+  void* user;
+} ibfe_alloc;
+
+/* Statistics of the last completed step. */
+typedef struct ibfe_stats {
+  int64_t steps;          /* completed steps since the last ibfe_set_state      */
+  double t;               /* current time                                       */
+  int32_t s1_iters;       /* tentative velocity solve (BiCGStab iterations)     */
+  int32_t ib_iters;       /* IB force solve (CG iterations)                     */
+  int32_t s3_iters;       /* pressure increment solve (CG iterations)           */
+  int32_t s4_iters;       /* velocity correction solve (CG iterations)          */
+  int32_t s1_outer, s3_outer, s4_outer; /* refinement sweeps (mixed mode)       */
+  double s1_res, ib_res, s3_res, s4_res; /* final relative residuals            */
+  double poisson_apply_ms;   /* summed duration of the pressure stiffness apply  */
+  int64_t poisson_applies;   /* number of those launches (timed if enabled)      */
+} ibfe_stats;
+
+typedef struct ibfe_plan ibfe_plan;
+typedef struct ibfe_ctx ibfe_ctx;
+
+/* ---- host-only set-up (no GPU needed) ---------------------------------- */
+
+/* Validate the inputs and derive kept cells, P, F, D_u, pressure Dirichlet
+ * nodes, the canonical order and the IB stencils on the host. */
+int ibfe_plan_create(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* params,
+                     const ibfe_inlet* inlet, ibfe_plan** out);
+/* Sizes: |P|, |F|, |P minus outlet|, kept cells, outlet-less components. */
+int ibfe_plan_sizes(const ibfe_plan* plan, int64_t* n_p, int64_t* n_free, int64_t* n_pfree,
+                    int64_t* n_kept_cells, int64_t* n_floating);
+/* Node ids of P in canonical (ascending) order: n_p int64 values. */
+int ibfe_plan_node_ids(const ibfe_plan* plan, int64_t* ids);
+/* IBFE_FLAG_* bits for every one of the N grid nodes. */
+int ibfe_plan_node_flags(const ibfe_plan* plan, uint8_t* flags);
+void ibfe_plan_destroy(ibfe_plan* plan);
+
+/* ---- device context ----------------------------------------------------- */
+
+/* Create a context on the current HIP device.  alloc may be NULL (hipMalloc);
+ * hip_stream is a hipStream_t (NULL = the null stream).  The initial state is
+ * u = 0, p = 0, t = 0. */
+int ibfe_create(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* params,
+                const ibfe_inlet* inlet, const ibfe_alloc* alloc, void* hip_stream,
+                ibfe_ctx** out);
+/* Number of velocity nodes and pressure nodes (both |P|). */
+int ibfe_num_nodes(const ibfe_ctx* ctx, int64_t* n_u, int64_t* n_p);
+/* Canonical node ids of the velocity and pressure unknowns (either may be NULL). */
+int ibfe_get_node_ids(const ibfe_ctx* ctx, int64_t* vel_ids, int64_t* p_ids);
+/* Set u (3 x n_u SoA), p (n_p) and t.  on_device != 0: pointers are device
+ * memory readable on the context's stream; else host memory. */
+int ibfe_set_state(ibfe_ctx* ctx, const double* u, const double* p, double t, int on_device);
+/* Advance nsteps steps (Section 2.4).  On failure the state of the last
+ * completed step is kept. */
+int ibfe_step(ibfe_ctx* ctx, int nsteps);
+/* Read u, p (either may be NULL) and t; synchronises the stream for host output. */
+int ibfe_get_state(ibfe_ctx* ctx, double* u, double* p, double* t, int on_device);
+int ibfe_get_stats(const ibfe_ctx* ctx, ibfe_stats* stats);
+/* Enable (1) or disable (0) HIP-event timing of the pressure stiffness apply. */
+int ibfe_set_kernel_timing(ibfe_ctx* ctx, int enable);
+
+/* Intermediate fields of the last step, canonical order:
+ *   IBFE_FIELD_USTAR (3 x n_u)  tentative velocity after the first sub-step
+ *   IBFE_FIELD_UIB   (3 x n_u)  velocity after the IB correction
+ *   IBFE_FIELD_PHI   (n_p)      pressure increment */
+#define IBFE_FIELD_USTAR 0
+#define IBFE_FIELD_UIB 1
+#define IBFE_FIELD_PHI 2
+int ibfe_get_field(ibfe_ctx* ctx, int which, double* out, int on_device);
+
+/* Apply one discrete operator of the step (for verification), canonical order,
+ * rows on all of P, columns on all of P:
+ *   IBFE_OP_MASS    y = M x            x: n_p,      y: n_p
+ *   IBFE_OP_STIFF   y = K x            x: n_p,      y: n_p
+ *   IBFE_OP_GRAD    y_d = G_d x        x: n_p,      y: 3 x n_u
+ *   IBFE_OP_DIV     y = sum_d G_d x_d  x: 3 x n_u,  y: n_p
+ *   IBFE_OP_ADVDIFF y_d = A x_d with A = (rho/dt) M + rho C(u) + mu K and u the
+ *                   current state velocity      x: 3 x n_u, y: 3 x n_u
+ *   IBFE_OP_INTERP  y = I x            x: 3 x n_u,  y: M x 3 (row major)
+ *   IBFE_OP_SPREAD  y = I_F^T x        x: M x 3,    y: 3 x n_u
+ * precision 0 runs the FP64 kernels, 1 the FP32 kernels (MASS, STIFF, ADVDIFF;
+ * others are FP64 only).  Host or device pointers as for ibfe_set_state. */
+#define IBFE_OP_MASS 0
+#define IBFE_OP_STIFF 1
+#define IBFE_OP_GRAD 2
+#define IBFE_OP_DIV 3
+#define IBFE_OP_ADVDIFF 4
+#define IBFE_OP_INTERP 5
+#define IBFE_OP_SPREAD 6
+int ibfe_apply(ibfe_ctx* ctx, int op, int precision, const double* x, double* y, int on_device);
+
+void ibfe_destroy(ibfe_ctx* ctx);
+const char* ibfe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IBFE_H */

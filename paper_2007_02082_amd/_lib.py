@@ -1,0 +1,319 @@
+"""ctypes binding of libibfe.so (include/ibfe.h).  Argument marshalling only:
+every step of the time step runs in the HIP library."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libibfe.so")
+
+IBFE_OK = 0
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOCONV", -5: "ENONFINITE", -6: "ESINGULAR"}
+FIELD_USTAR, FIELD_UIB, FIELD_PHI = 0, 1, 2
+OP_MASS, OP_STIFF, OP_GRAD, OP_DIV, OP_ADVDIFF, OP_INTERP, OP_SPREAD = range(7)
+FLAG_P, FLAG_F, FLAG_DU, FLAG_PDIR = 1, 2, 4, 8
+
+u8p = C.POINTER(C.c_uint8)
+dp = C.POINTER(C.c_double)
+i64p = C.POINTER(C.c_int64)
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("h", C.c_double),
+                ("origin", C.c_double * 3), ("node_mask", u8p), ("bc_tag", u8p),
+                ("refine_cell", u8p)]
+
+
+class IB(C.Structure):
+    _fields_ = [("M", C.c_int64), ("X", dp), ("dS", C.c_double), ("U_B", dp)]
+
+
+class Params(C.Structure):
+    _fields_ = [("rho", C.c_double), ("mu", C.c_double), ("dt", C.c_double),
+                ("precision", C.c_int32), ("rtol", C.c_double), ("max_iters", C.c_int32),
+                ("precond", C.c_int32), ("advection", C.c_int32), ("ib_rtol", C.c_double)]
+
+
+class Inlet(C.Structure):
+    _fields_ = [("K", C.c_int32), ("omega", C.c_double), ("n", C.c_int64), ("node_ids", i64p),
+                ("shape", dp)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class Alloc(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", C.c_void_p)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("t", C.c_double), ("s1_iters", C.c_int32),
+                ("ib_iters", C.c_int32), ("s3_iters", C.c_int32), ("s4_iters", C.c_int32),
+                ("s1_outer", C.c_int32), ("s3_outer", C.c_int32), ("s4_outer", C.c_int32),
+                ("s1_res", C.c_double), ("ib_res", C.c_double), ("s3_res", C.c_double),
+                ("s4_res", C.c_double), ("poisson_apply_ms", C.c_double),
+                ("poisson_applies", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# name -> (restype, argtypes); the full exported surface of include/ibfe.h
+SIGNATURES = {
+    "ibfe_plan_create": (C.c_int, [C.POINTER(Grid), C.POINTER(IB), C.POINTER(Params),
+                                   C.POINTER(Inlet), C.POINTER(C.c_void_p)]),
+    "ibfe_plan_sizes": (C.c_int, [C.c_void_p, i64p, i64p, i64p, i64p, i64p]),
+    "ibfe_plan_node_ids": (C.c_int, [C.c_void_p, i64p]),
+    "ibfe_plan_node_flags": (C.c_int, [C.c_void_p, u8p]),
+    "ibfe_plan_destroy": (None, [C.c_void_p]),
+    "ibfe_create": (C.c_int, [C.POINTER(Grid), C.POINTER(IB), C.POINTER(Params), C.POINTER(Inlet),
+                              C.POINTER(Alloc), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "ibfe_num_nodes": (C.c_int, [C.c_void_p, i64p, i64p]),
+    "ibfe_get_node_ids": (C.c_int, [C.c_void_p, i64p, i64p]),
+    "ibfe_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int]),
+    "ibfe_step": (C.c_int, [C.c_void_p, C.c_int]),
+    "ibfe_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, dp, C.c_int]),
+    "ibfe_get_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
+    "ibfe_set_kernel_timing": (C.c_int, [C.c_void_p, C.c_int]),
+    "ibfe_get_field": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int]),
+    "ibfe_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
+    "ibfe_destroy": (None, [C.c_void_p]),
+    "ibfe_last_error": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+class IbfeError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    """Load the HIP library; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2007_02082_amd.build`")
+    # PyTorch ships its own HIP runtime under the same soname (libamdhip64.so.7).
+    # Importing it first makes the dynamic loader bind this library to that same
+    # runtime, so torch's allocator and streams and this library share one
+    # runtime instance; loading this library first would put two in the process.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(rc: int) -> None:
+    if rc != IBFE_OK:
+        raise IbfeError(rc, load().ibfe_last_error().decode(errors="replace"))
+
+
+def _ptr(a: np.ndarray | None, ctype):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+class _Inputs:
+    """Keeps the ctypes structs and the numpy buffers they point to alive."""
+
+    def __init__(self, nx, ny, nz, h, origin, node_mask, bc_tag, X, dS, U_B, rho, mu, dt,
+                 inlet_K, inlet_omega, inlet_ids, inlet_shape, precision=0, rtol=0.0,
+                 max_iters=0, ib_rtol=0.0, precond=0, advection=0):
+        self.mask = np.ascontiguousarray(node_mask, dtype=np.uint8)
+        self.tag = None if bc_tag is None else np.ascontiguousarray(bc_tag, dtype=np.uint8)
+        self.X = np.ascontiguousarray(np.asarray(X, np.float64).reshape(-1, 3))
+        self.UB = None if U_B is None else np.ascontiguousarray(np.asarray(U_B, np.float64).reshape(-1, 3))
+        self.ids = np.ascontiguousarray(inlet_ids, dtype=np.int64)
+        self.shape = np.ascontiguousarray(inlet_shape, dtype=np.float64)
+        self.grid = Grid(int(nx), int(ny), int(nz), float(h), (C.c_double * 3)(*map(float, origin)),
+                         _ptr(self.mask, C.c_uint8), _ptr(self.tag, C.c_uint8), None)
+        self.ib = IB(self.X.shape[0], _ptr(self.X, C.c_double) if self.X.size else None, float(dS),
+                     _ptr(self.UB, C.c_double))
+        self.params = Params(float(rho), float(mu), float(dt), int(precision), float(rtol),
+                             int(max_iters), int(precond), int(advection), float(ib_rtol))
+        self.inlet = Inlet(int(inlet_K), float(inlet_omega), self.ids.size,
+                           _ptr(self.ids, C.c_int64) if self.ids.size else None,
+                           _ptr(self.shape, C.c_double) if self.shape.size else None)
+
+
+def inputs_from_case(case, **kw) -> dict:
+    """Keyword arguments for Plan/Solver from any object with the fields of a flow case."""
+    return dict(nx=case.nx, ny=case.ny, nz=case.nz, h=case.h, origin=case.origin,
+                node_mask=case.node_mask, bc_tag=case.bc_tag, X=case.X, dS=case.dS, U_B=case.U_B,
+                rho=case.rho, mu=case.mu, dt=case.dt, inlet_K=case.inlet_K,
+                inlet_omega=case.inlet_omega, inlet_ids=case.inlet_ids,
+                inlet_shape=case.inlet_shape, **kw)
+
+
+class Plan:
+    """Host-only set-up (ibfe_plan_*): derived sets and canonical order."""
+
+    def __init__(self, **kw):
+        lib = load()
+        self._in = _Inputs(**kw)
+        h = C.c_void_p()
+        check(lib.ibfe_plan_create(C.byref(self._in.grid), C.byref(self._in.ib),
+                                   C.byref(self._in.params), C.byref(self._in.inlet), C.byref(h)))
+        self._h = h
+        self.N = (int(kw["nx"]) + 1) * (int(kw["ny"]) + 1) * (int(kw["nz"]) + 1)
+
+    def sizes(self) -> dict:
+        v = [C.c_int64() for _ in range(5)]
+        check(load().ibfe_plan_sizes(self._h, *[C.byref(x) for x in v]))
+        return dict(zip(["n_p", "n_free", "n_pfree", "n_kept_cells", "n_floating"], [x.value for x in v]))
+
+    def node_ids(self) -> np.ndarray:
+        out = np.empty(self.sizes()["n_p"], np.int64)
+        check(load().ibfe_plan_node_ids(self._h, _ptr(out, C.c_int64)))
+        return out
+
+    def node_flags(self) -> np.ndarray:
+        out = np.empty(self.N, np.uint8)
+        check(load().ibfe_plan_node_flags(self._h, _ptr(out, C.c_uint8)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().ibfe_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _torch_allocator():
+    """Device allocator callbacks backed by torch's caching allocator."""
+    import torch
+
+    dev = torch.cuda.current_device()
+
+    @ALLOC_FN
+    def _alloc(nbytes, stream, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream or 0)
+        except Exception:
+            return None
+
+    @FREE_FN
+    def _free(ptr, user):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return Alloc(_alloc, _free, None), (_alloc, _free)
+
+
+class Solver:
+    """One flow problem on the current GPU (ibfe_create ... ibfe_destroy)."""
+
+    def __init__(self, stream=None, torch_alloc: bool = True, **kw):
+        lib = load()
+        self._in = _Inputs(**kw)
+        self._keep = None
+        alloc = None
+        if torch_alloc:
+            a, self._keep = _torch_allocator()
+            self._alloc = a
+            alloc = C.byref(a)
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        h = C.c_void_p()
+        check(lib.ibfe_create(C.byref(self._in.grid), C.byref(self._in.ib), C.byref(self._in.params),
+                              C.byref(self._in.inlet), alloc, C.c_void_p(stream), C.byref(h)))
+        self._h = h
+        nu, npr = C.c_int64(), C.c_int64()
+        check(lib.ibfe_num_nodes(h, C.byref(nu), C.byref(npr)))
+        self.n_u, self.n_p = nu.value, npr.value
+        self.M = self._in.X.shape[0]
+
+    # -- helpers ---------------------------------------------------------------
+    @staticmethod
+    def _arg(x):
+        """(pointer, on_device) for a numpy array or a torch tensor."""
+        if isinstance(x, np.ndarray):
+            return C.c_void_p(x.ctypes.data), 0
+        return C.c_void_p(x.data_ptr()), 1 if x.is_cuda else 0
+
+    def node_ids(self) -> np.ndarray:
+        out = np.empty(self.n_u, np.int64)
+        check(load().ibfe_get_node_ids(self._h, _ptr(out, C.c_int64), None))
+        return out
+
+    def set_state(self, u, p, t: float = 0.0):
+        if isinstance(u, np.ndarray):
+            u = np.ascontiguousarray(u, np.float64)
+            p = np.ascontiguousarray(p, np.float64)
+            assert u.size == 3 * self.n_u and p.size == self.n_p
+        pu, du = self._arg(u)
+        pp, _ = self._arg(p)
+        check(load().ibfe_set_state(self._h, pu, pp, float(t), du))
+
+    def step(self, n: int = 1):
+        check(load().ibfe_step(self._h, int(n)))
+
+    def get_state(self):
+        u = np.empty(3 * self.n_u)
+        p = np.empty(self.n_p)
+        t = C.c_double()
+        check(load().ibfe_get_state(self._h, C.c_void_p(u.ctypes.data), C.c_void_p(p.ctypes.data),
+                                    C.byref(t), 0))
+        return u.reshape(3, self.n_u), p, t.value
+
+    def get_state_device(self, u, p):
+        """Write the state into device tensors (3*n_u and n_p doubles) without a host copy."""
+        t = C.c_double()
+        check(load().ibfe_get_state(self._h, C.c_void_p(u.data_ptr()), C.c_void_p(p.data_ptr()),
+                                    C.byref(t), 1))
+        return t.value
+
+    def field(self, which: int) -> np.ndarray:
+        n = self.n_p if which == FIELD_PHI else 3 * self.n_u
+        out = np.empty(n)
+        check(load().ibfe_get_field(self._h, int(which), C.c_void_p(out.ctypes.data), 0))
+        return out if which == FIELD_PHI else out.reshape(3, self.n_u)
+
+    def apply(self, op: int, x: np.ndarray, precision: int = 0) -> np.ndarray:
+        x = np.ascontiguousarray(x, np.float64)
+        out_len = {OP_MASS: self.n_p, OP_STIFF: self.n_p, OP_GRAD: 3 * self.n_u, OP_DIV: self.n_p,
+                   OP_ADVDIFF: 3 * self.n_u, OP_INTERP: 3 * self.M, OP_SPREAD: 3 * self.n_u}[op]
+        y = np.empty(out_len)
+        check(load().ibfe_apply(self._h, int(op), int(precision), C.c_void_p(x.ctypes.data),
+                                C.c_void_p(y.ctypes.data), 0))
+        return y
+
+    def stats(self) -> dict:
+        s = Stats()
+        check(load().ibfe_get_stats(self._h, C.byref(s)))
+        return s.as_dict()
+
+    def set_kernel_timing(self, on: bool):
+        check(load().ibfe_set_kernel_timing(self._h, 1 if on else 0))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().ibfe_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,894 @@
+// Step driver and C ABI of the IPCS + BCE-IB time step (Section 2.4 order):
+// tentative velocity (BiCGStab), IB force solve (CG on G = I_F I_F^T) and
+// spreading, pressure increment (PCG), L2 velocity correction (PCG).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "ibfe.h"
+#include "plan.hpp"
+#include "step_kernels.hpp"
+
+using namespace ibfe;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(IBFE_EHIP, std::string(#expr " failed: ") + hipGetErrorString(e_));   \
+  } while (0)
+
+#define CHECK_LAUNCH() HIP_TRY(hipGetLastError())
+
+constexpr uint32_t kFlagPp = 16u;  // pressure unknown: node of P that is not an outlet node
+constexpr int kMaxBlocksRed = 8;   // reduce_last<K> uses K <= 8 partial rows
+
+enum ScalSlot { kScS1 = 0, kScIB, kScS3, kScS4, kScS1i, kScS3i, kScS4i, kScMisc, kNumScal };
+
+int blocks_for(int nchunks) { return (nchunks + kWaves - 1) / kWaves; }
+int blocks_lin(int64_t n) { return int((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+struct ibfe_plan {
+  Plan p;
+};
+
+struct ibfe_ctx {
+  Plan plan;
+  hipStream_t stream = nullptr;
+  ibfe_alloc alloc{};
+  bool user_alloc = false;
+  std::vector<void*> blocks;
+
+  int64_t halo = 0, stride = 0;   // padded plane length
+  int nchunks = 0;
+  int ib_nchunks = 0;
+  int64_t mstride = 0;            // padded plane length of IB vectors
+  int nP = 0;
+
+  // geometry (node-0 pointers)
+  uint8_t* emask = nullptr;
+  uint8_t* flags = nullptr;
+  int8_t* slot = nullptr;
+  int* chunks = nullptr;
+  int* ib_chunks = nullptr;
+  int64_t* pids = nullptr;
+  double* float_count = nullptr;
+  double* float_means = nullptr;
+
+  // state and fields (node-0 pointers; velocities have 3 planes)
+  double *u = nullptr, *p = nullptr, *u_next = nullptr, *p_next = nullptr;
+  double *g = nullptr, *ustar = nullptr, *uib = nullptr, *phi = nullptr;
+  double* coef64 = nullptr;
+  float* coef32 = nullptr;
+  double* w[10] = {};   // FP64 Krylov work vectors, 3 planes each
+  float* v32[10] = {};  // FP32 Krylov work vectors (mixed mode), 3 planes each
+  double* compact = nullptr;
+
+  // immersed boundary
+  int32_t* ib_idx = nullptr;
+  double* ib_w = nullptr;
+  double* UB = nullptr;
+  int64_t* G_ptr = nullptr;
+  int32_t* G_col = nullptr;
+  double* G_val = nullptr;
+  double* G_diag = nullptr;
+  int32_t* sp_node = nullptr;
+  int64_t* sp_ptr = nullptr;
+  int32_t* sp_pt = nullptr;
+  double* sp_wt = nullptr;
+  double* ibv[5] = {};  // b, lam, r, p, q (3 planes of mstride)
+
+  // inlet
+  int64_t* inlet_ids = nullptr;
+  double* inlet_shape = nullptr;
+
+  // reductions
+  double* partials = nullptr;
+  unsigned* counter = nullptr;
+  KScal* scal = nullptr;
+  KScal* host_scal = nullptr;  // pinned
+
+  FormCoefs fc{};
+  double t = 0.0;
+  int64_t steps = 0;
+  ibfe_stats stats{};
+  bool timing = false;
+  std::vector<hipEvent_t> ev;
+  int est[kNumScal] = {};
+
+  ~ibfe_ctx() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    for (void* b : blocks) {
+      if (user_alloc)
+        alloc.free(b, alloc.user);
+      else
+        (void)hipFree(b);
+    }
+    if (host_scal) (void)hipHostFree(host_scal);
+  }
+
+  int dalloc(void** out, size_t bytes) {
+    bytes = (bytes + 255) & ~size_t(255);
+    void* ptr = nullptr;
+    if (user_alloc) {
+      ptr = alloc.alloc(bytes, (void*)stream, alloc.user);
+      if (!ptr) return fail(IBFE_ENOMEM, "device allocator returned NULL");
+    } else {
+      hipError_t e = hipMalloc(&ptr, bytes);
+      if (e != hipSuccess) return fail(IBFE_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    blocks.push_back(ptr);
+    HIP_TRY(hipMemsetAsync(ptr, 0, bytes, stream));
+    *out = ptr;
+    return IBFE_OK;
+  }
+  template <typename T>
+  int field(T** out, int planes) {  // zeroed, padded, returns node-0 pointer
+    void* base = nullptr;
+    int rc = dalloc(&base, sizeof(T) * size_t(stride) * planes);
+    if (rc) return rc;
+    *out = reinterpret_cast<T*>(base) + halo;
+    return IBFE_OK;
+  }
+  template <typename T>
+  int upload(T** out, const T* src, size_t count, size_t min_count = 1) {
+    void* base = nullptr;
+    int rc = dalloc(&base, sizeof(T) * std::max(count, min_count));
+    if (rc) return rc;
+    if (count) HIP_TRY(hipMemcpyAsync(base, src, sizeof(T) * count, hipMemcpyHostToDevice, stream));
+    *out = reinterpret_cast<T*>(base);
+    return IBFE_OK;
+  }
+};
+
+namespace {
+
+// -------------------------------------------------------------------------
+// set-up
+// -------------------------------------------------------------------------
+
+int setup_device(ibfe_ctx& c) {
+  Plan& P = c.plan;
+  const int64_t nch_total = (P.N + kChunk - 1) / kChunk;
+  c.halo = ((P.sz + P.sy + 1 + kChunk - 1) / kChunk) * kChunk;
+  c.stride = 2 * c.halo + nch_total * kChunk;
+  c.nchunks = int(P.chunks.size());
+  c.nP = int(P.P_ids.size());
+  c.fc = form_coefs(P.h);
+  int rc;
+  // per-node geometry, padded like the fields
+  std::vector<uint8_t> fl(P.N);
+  for (int64_t n = 0; n < P.N; ++n) {
+    uint8_t f = P.flags[n];
+    if ((f & IBFE_FLAG_P) && !(f & IBFE_FLAG_PDIR)) f |= kFlagPp;
+    fl[n] = f;
+  }
+  if ((rc = c.field(&c.emask, 1))) return rc;
+  if ((rc = c.field(&c.flags, 1))) return rc;
+  if ((rc = c.field(&c.slot, 1))) return rc;
+  HIP_TRY(hipMemcpyAsync(c.emask, P.emask.data(), P.N, hipMemcpyHostToDevice, c.stream));
+  HIP_TRY(hipMemcpyAsync(c.flags, fl.data(), P.N, hipMemcpyHostToDevice, c.stream));
+  HIP_TRY(hipMemcpyAsync(c.slot, P.float_slot.data(), P.N, hipMemcpyHostToDevice, c.stream));
+  // nodes past N in the last chunk carry slot 0 after the memset: mark them -1
+  {
+    int64_t tail = nch_total * kChunk - P.N;
+    if (tail > 0) HIP_TRY(hipMemsetAsync(c.slot + P.N, 0xFF, tail, c.stream));
+  }
+  if ((rc = c.upload(&c.chunks, P.chunks.data(), P.chunks.size()))) return rc;
+  if ((rc = c.upload(&c.pids, P.P_ids.data(), P.P_ids.size()))) return rc;
+  {
+    std::vector<double> cnt(kMaxFloating, 1.0);
+    for (int s = 0; s < P.n_floating; ++s) cnt[s] = double(P.float_count[s]);
+    if ((rc = c.upload(&c.float_count, cnt.data(), cnt.size()))) return rc;
+    std::vector<double> zero(kMaxFloating, 0.0);
+    if ((rc = c.upload(&c.float_means, zero.data(), zero.size()))) return rc;
+  }
+  // fields
+  if ((rc = c.field(&c.u, 3))) return rc;
+  if ((rc = c.field(&c.u_next, 3))) return rc;
+  if ((rc = c.field(&c.p, 1))) return rc;
+  if ((rc = c.field(&c.p_next, 1))) return rc;
+  if ((rc = c.field(&c.g, 3))) return rc;
+  if ((rc = c.field(&c.ustar, 3))) return rc;
+  if ((rc = c.field(&c.uib, 3))) return rc;
+  if ((rc = c.field(&c.phi, 1))) return rc;
+  if ((rc = c.field(&c.coef64, 27))) return rc;
+  for (int i = 0; i < 10; ++i)
+    if ((rc = c.field(&c.w[i], 3))) return rc;
+  if (P.params.precision == 1) {
+    if ((rc = c.field(&c.coef32, 27))) return rc;
+    for (int i = 0; i < 10; ++i)
+      if ((rc = c.field(&c.v32[i], 3))) return rc;
+  }
+  {
+    void* base = nullptr;
+    if ((rc = c.dalloc(&base, sizeof(double) * 3 * std::max<int64_t>(1, P.P_ids.size() + P.M))))
+      return rc;
+    c.compact = reinterpret_cast<double*>(base);
+  }
+  // immersed boundary
+  const int64_t M = P.M;
+  c.ib_nchunks = int((M + kChunk - 1) / kChunk);
+  c.mstride = std::max<int64_t>(kChunk, int64_t(c.ib_nchunks) * kChunk);
+  if (M > 0) {
+    std::vector<int> ibc(c.ib_nchunks);
+    for (int i = 0; i < c.ib_nchunks; ++i) ibc[i] = i;
+    if ((rc = c.upload(&c.ib_chunks, ibc.data(), ibc.size()))) return rc;
+    if ((rc = c.upload(&c.ib_idx, P.ib_idx.data(), P.ib_idx.size()))) return rc;
+    if ((rc = c.upload(&c.ib_w, P.ib_w.data(), P.ib_w.size()))) return rc;
+    if ((rc = c.upload(&c.UB, P.U_B.data(), P.U_B.size()))) return rc;
+    if ((rc = c.upload(&c.G_ptr, P.G_ptr.data(), P.G_ptr.size()))) return rc;
+    if ((rc = c.upload(&c.G_col, P.G_col.data(), P.G_col.size()))) return rc;
+    if ((rc = c.upload(&c.G_val, P.G_val.data(), P.G_val.size()))) return rc;
+    if ((rc = c.upload(&c.G_diag, P.G_diag.data(), P.G_diag.size()))) return rc;
+    if ((rc = c.upload(&c.sp_node, P.sp_node.data(), P.sp_node.size()))) return rc;
+    if ((rc = c.upload(&c.sp_ptr, P.sp_ptr.data(), P.sp_ptr.size()))) return rc;
+    if ((rc = c.upload(&c.sp_pt, P.sp_pt.data(), P.sp_pt.size()))) return rc;
+    if ((rc = c.upload(&c.sp_wt, P.sp_w.data(), P.sp_w.size()))) return rc;
+    for (int i = 0; i < 5; ++i) {
+      void* base = nullptr;
+      if ((rc = c.dalloc(&base, sizeof(double) * 3 * c.mstride))) return rc;
+      c.ibv[i] = reinterpret_cast<double*>(base);
+    }
+  }
+  if (!P.inlet_ids.empty()) {
+    if ((rc = c.upload(&c.inlet_ids, P.inlet_ids.data(), P.inlet_ids.size()))) return rc;
+    if ((rc = c.upload(&c.inlet_shape, P.inlet_shape.data(), P.inlet_shape.size()))) return rc;
+  }
+  // reductions
+  {
+    const int maxb = std::max(blocks_for(c.nchunks), blocks_for(std::max(1, c.ib_nchunks)));
+    void* base = nullptr;
+    if ((rc = c.dalloc(&base, sizeof(double) * kMaxBlocksRed * size_t(maxb)))) return rc;
+    c.partials = reinterpret_cast<double*>(base);
+    if ((rc = c.dalloc(&base, 256))) return rc;
+    c.counter = reinterpret_cast<unsigned*>(base);
+    if ((rc = c.dalloc(&base, sizeof(KScal) * kNumScal))) return rc;
+    c.scal = reinterpret_cast<KScal*>(base);
+  }
+  HIP_TRY(hipHostMalloc((void**)&c.host_scal, sizeof(KScal) * kNumScal, hipHostMallocDefault));
+  std::memset(c.host_scal, 0, sizeof(KScal) * kNumScal);
+  HIP_TRY(hipStreamSynchronize(c.stream));
+  return IBFE_OK;
+}
+
+// -------------------------------------------------------------------------
+// Krylov drivers.  The kernels keep every scalar on the device; the host only
+// polls the `done` flag between batches of iterations.
+// -------------------------------------------------------------------------
+
+int poll(ibfe_ctx& c, int slot, KScal& out) {
+  HIP_TRY(hipMemcpyAsync(&c.host_scal[slot], &c.scal[slot], sizeof(KScal), hipMemcpyDeviceToHost,
+                         c.stream));
+  HIP_TRY(hipStreamSynchronize(c.stream));
+  out = c.host_scal[slot];
+  return IBFE_OK;
+}
+
+int finish_status(const KScal& s, const char* what) {
+  if (s.status == 2) return fail(IBFE_ENONFINITE, std::string(what) + ": non-finite residual");
+  if (s.status == 1) return fail(IBFE_ESINGULAR, std::string(what) + ": Krylov breakdown");
+  if (!s.done || (s.iters >= s.max_iters && s.rr > s.tol2 * s.bb))
+    return fail(IBFE_ENOCONV, std::string(what) + ": iteration cap reached");
+  return IBFE_OK;
+}
+
+struct SolveOut {
+  int iters = 0;
+  double res = 0.0;
+};
+
+int next_batch(int est, int done_so_far) {
+  if (done_so_far == 0) return std::max(4, est - 2);
+  return 8;
+}
+
+template <typename T, class Op>
+int run_cg(ibfe_ctx& c, const Op& op, const int* chunks, int nchunks, const T* b, T* x, T* r, T* p,
+           T* q, int slot, double rtol, int max_iters, bool zero_guess, SolveOut& out,
+           bool timed = false) {
+  const int nb = blocks_for(nchunks);
+  KScal* sc = &c.scal[slot];
+  hipLaunchKernelGGL((k_cg_init<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, chunks, nchunks, op, b,
+                     x, r, p, c.partials, c.counter, sc, zero_guess ? 1 : 0, rtol * rtol, max_iters);
+  CHECK_LAUNCH();
+  int launched = 0;
+  KScal s{};
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
+  while (true) {
+    const int batch = std::min(next_batch(c.est[slot], launched), max_iters + 1 - launched);
+    for (int k = 0; k < batch; ++k) {
+      if (timed) {
+        hipEvent_t e0, e1;
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        HIP_TRY(hipEventRecord(e0, c.stream));
+        hipLaunchKernelGGL((k_cg_q<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, chunks, nchunks, op,
+                           p, q, c.partials, c.counter, sc);
+        HIP_TRY(hipEventRecord(e1, c.stream));
+        evs.push_back({e0, e1});
+      } else {
+        hipLaunchKernelGGL((k_cg_q<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, chunks, nchunks, op,
+                           p, q, c.partials, c.counter, sc);
+      }
+      CHECK_LAUNCH();
+      hipLaunchKernelGGL((k_cg_xr<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, chunks, nchunks, op, x,
+                         r, p, q, c.partials, c.counter, sc);
+      CHECK_LAUNCH();
+      hipLaunchKernelGGL((k_cg_p<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, chunks, nchunks, op, r,
+                         p, (const KScal*)sc);
+      CHECK_LAUNCH();
+    }
+    launched += batch;
+    int rc = poll(c, slot, s);
+    if (rc) return rc;
+    if (s.done || launched > max_iters) break;
+  }
+  if (timed) {
+    for (size_t k = 0; k < evs.size(); ++k) {
+      if (int(k) < s.iters) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, evs[k].first, evs[k].second));
+        c.stats.poisson_apply_ms += ms;
+        c.stats.poisson_applies += 1;
+      }
+      (void)hipEventDestroy(evs[k].first);
+      (void)hipEventDestroy(evs[k].second);
+    }
+  }
+  c.est[slot] = std::max(1, s.iters);
+  out.iters = s.iters;
+  out.res = s.bb > 0.0 ? std::sqrt(s.rr / s.bb) : 0.0;
+  return finish_status(s, "CG");
+}
+
+template <typename T, class Op>
+int run_bicgstab(ibfe_ctx& c, const Op& op, const T* b, T* x, T* const* wv, int slot, double rtol,
+                 int max_iters, SolveOut& out) {
+  const int nb = blocks_for(c.nchunks);
+  const int* ch = c.chunks;
+  const int nch = c.nchunks;
+  T *r = wv[0], *rhat = wv[1], *p = wv[2], *v = wv[3], *phat = wv[4], *s = wv[5], *shat = wv[6],
+    *t = wv[7];
+  KScal* sc = &c.scal[slot];
+  hipLaunchKernelGGL((k_bi_init<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, ch, nch, op, b, x, r, rhat,
+                     p, v, c.partials, c.counter, sc, rtol * rtol, max_iters);
+  CHECK_LAUNCH();
+  int launched = 0;
+  KScal st{};
+  while (true) {
+    const int batch = std::min(next_batch(c.est[slot], launched), max_iters + 1 - launched);
+    for (int k = 0; k < batch; ++k) {
+      hipLaunchKernelGGL((k_bi_p<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, ch, nch, op, r, p, v,
+                         phat, (const KScal*)sc);
+      hipLaunchKernelGGL((k_bi_apply<T, Op, 0>), dim3(nb), dim3(kBlock), 0, c.stream, ch, nch, op, phat,
+                         v, rhat, c.partials, c.counter, sc);
+      hipLaunchKernelGGL((k_bi_s<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, ch, nch, op, r, v, s,
+                         shat, (const KScal*)sc);
+      hipLaunchKernelGGL((k_bi_apply<T, Op, 1>), dim3(nb), dim3(kBlock), 0, c.stream, ch, nch, op, shat,
+                         t, s, c.partials, c.counter, sc);
+      hipLaunchKernelGGL((k_bi_x<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, ch, nch, op, x, r, rhat,
+                         phat, shat, s, t, c.partials, c.counter, sc);
+      CHECK_LAUNCH();
+    }
+    launched += batch;
+    int rc = poll(c, slot, st);
+    if (rc) return rc;
+    if (st.done || launched > max_iters) break;
+  }
+  c.est[slot] = std::max(1, st.iters);
+  out.iters = st.iters;
+  out.res = st.bb > 0.0 ? std::sqrt(st.rr / st.bb) : 0.0;
+  return finish_status(st, "BiCGStab");
+}
+
+// -------------------------------------------------------------------------
+// operators
+// -------------------------------------------------------------------------
+
+template <typename T, int NC>
+OpSym<T, NC> sym_op(const ibfe_ctx& c, const double (&coef)[4], uint32_t rowbit) {
+  OpSym<T, NC> op{};
+  op.emask = c.emask;
+  op.flags = c.flags;
+  op.rowbit = rowbit;
+  op.sy = int(c.plan.sy);
+  op.sz = int(c.plan.sz);
+  op.stride = c.stride;
+  for (int t = 0; t < 4; ++t) op.c[t] = T(coef[t]);
+  return op;
+}
+
+template <typename T>
+OpStencil<T, 3> stencil_op(const ibfe_ctx& c, const T* coef, uint32_t rowbit) {
+  OpStencil<T, 3> op{};
+  op.coef = coef;
+  op.flags = c.flags;
+  op.rowbit = rowbit;
+  op.sy = int(c.plan.sy);
+  op.sz = int(c.plan.sz);
+  op.stride = c.stride;
+  return op;
+}
+
+OpCSR<3> gram_op(const ibfe_ctx& c) {
+  OpCSR<3> op{};
+  op.ptr = c.G_ptr;
+  op.col = c.G_col;
+  op.val = c.G_val;
+  op.diag = c.G_diag;
+  op.nrows = int(c.plan.M);
+  op.stride = c.mstride;
+  return op;
+}
+
+// -------------------------------------------------------------------------
+// one time step
+// -------------------------------------------------------------------------
+
+int build_s1(ibfe_ctx& c) {
+  const Plan& P = c.plan;
+  const double rdt = P.params.rho / P.params.dt, mu = P.params.mu;
+  double cm[4];
+  for (int t = 0; t < 4; ++t) cm[t] = rdt * c.fc.m[t] + mu * c.fc.k[t];
+  hipLaunchKernelGGL(k_s1_build, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream, c.chunks,
+                     c.nchunks, c.emask, c.flags, c.u, c.stride, int(P.sy), int(P.sz), P.h, cm[0], cm[1],
+                     cm[2], cm[3], P.params.rho, c.coef64, c.coef32);
+  CHECK_LAUNCH();
+  return IBFE_OK;
+}
+
+int step_once(ibfe_ctx& c) {
+  const Plan& P = c.plan;
+  const double rho = P.params.rho, dt = P.params.dt;
+  const double t1 = c.t + dt;
+  const int nb = blocks_for(c.nchunks);
+  const int sy = int(P.sy), sz = int(P.sz);
+  const int64_t S = c.stride;
+  const bool mixed = P.params.precision == 1;
+  int rc;
+  (void)mixed;
+
+  // Dirichlet data g(t^{n+1}) at the inlet table nodes (zero elsewhere)
+  if (!P.inlet_ids.empty()) {
+    Harmonics hm{};
+    hm.K = P.K;
+    for (int k = 1; k <= P.K; ++k) {
+      hm.c[k - 1] = std::cos(k * P.omega * t1);
+      hm.s[k - 1] = std::sin(k * P.omega * t1);
+    }
+    hipLaunchKernelGGL(k_inlet, dim3(blocks_lin(int64_t(P.inlet_ids.size()))), dim3(kBlock), 0,
+                       c.stream, int(P.inlet_ids.size()), c.inlet_ids, c.inlet_shape, hm, c.g, S);
+    CHECK_LAUNCH();
+  }
+
+  // 1. tentative velocity: A_FF u*_F = (rho/dt) M u^n - G p^n - A_FD g
+  if ((rc = build_s1(c))) return rc;
+  double* b1 = c.w[8];
+  double* x1 = c.w[9];
+  {
+    double cm[4];
+    for (int t = 0; t < 4; ++t) cm[t] = rho / dt * c.fc.m[t];
+    hipLaunchKernelGGL(k_s1_rhs, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.emask,
+                       c.flags, c.coef64, c.u, c.p, c.g, b1, S, sy, sz, cm[0], cm[1], cm[2], cm[3],
+                       c.fc.g2[0], c.fc.g2[1], c.fc.g2[2]);
+    CHECK_LAUNCH();
+    hipLaunchKernelGGL((k_masked_copy<double, double>), dim3(nb), dim3(kBlock), 0, c.stream, c.chunks,
+                       c.nchunks, c.flags, kFlagF, c.u, x1, 3, S);
+    CHECK_LAUNCH();
+    auto op = stencil_op<double>(c, c.coef64, kFlagF);
+    SolveOut so;
+    if ((rc = run_bicgstab<double>(c, op, b1, x1, c.w, kScS1, P.params.rtol, P.params.max_iters, so)))
+      return rc;
+    c.stats.s1_iters = so.iters;
+    c.stats.s1_res = so.res;
+    c.stats.s1_outer = 1;
+    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, 1.0, x1, 1.0,
+                       c.g, c.ustar, 3, S);
+    CHECK_LAUNCH();
+  }
+
+  // 2.-4. BCE-IB correction: G Lambda = U_B - I u*, u_ib = u* + I_F^T Lambda
+  hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, 1.0, c.ustar,
+                     0.0, c.ustar, c.uib, 3, S);
+  CHECK_LAUNCH();
+  c.stats.ib_iters = 0;
+  c.stats.ib_res = 0.0;
+  if (P.M > 0) {
+    const int M = int(P.M);
+    hipLaunchKernelGGL(k_ib_interp, dim3(blocks_lin(M)), dim3(kBlock), 0, c.stream, M, c.ib_idx, c.ib_w,
+                       c.UB, c.ustar, S, c.ibv[0], c.mstride, 1);
+    CHECK_LAUNCH();
+    auto op = gram_op(c);
+    SolveOut so;
+    if ((rc = run_cg<double>(c, op, c.ib_chunks, c.ib_nchunks, c.ibv[0], c.ibv[1], c.ibv[2], c.ibv[3],
+                             c.ibv[4], kScIB, P.params.ib_rtol, P.params.max_iters, true, so)))
+      return rc;
+    c.stats.ib_iters = so.iters;
+    c.stats.ib_res = so.res;
+    const int nn = int(P.sp_node.size());
+    hipLaunchKernelGGL(k_ib_spread, dim3(blocks_lin(nn)), dim3(kBlock), 0, c.stream, nn, c.sp_node,
+                       c.sp_ptr, c.sp_pt, c.sp_wt, c.ibv[1], c.mstride, c.uib, S);
+    CHECK_LAUNCH();
+  }
+
+  // 5. pressure increment: K_{P'P'} Phi = -(rho/dt) (B u_ib)_{P'}
+  double* b3 = c.w[8];
+  {
+    hipLaunchKernelGGL(k_div, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.emask, c.flags,
+                       kFlagPp, 0u, c.uib, b3, S, sy, sz, c.fc.g2[0], c.fc.g2[1], c.fc.g2[2], -rho / dt);
+    CHECK_LAUNCH();
+    if (P.n_floating > 0) {
+      hipLaunchKernelGGL(k_slot_mean, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.slot,
+                         b3, P.n_floating, c.float_count, c.partials, c.counter, c.float_means);
+      hipLaunchKernelGGL(k_slot_sub, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.slot, b3,
+                         c.float_means);
+      CHECK_LAUNCH();
+    }
+    const double kc[4] = {c.fc.k[0], c.fc.k[1], c.fc.k[2], c.fc.k[3]};
+    auto op = sym_op<double, 1>(c, kc, kFlagPp);
+    SolveOut so;
+    if ((rc = run_cg<double>(c, op, c.chunks, c.nchunks, b3, c.phi, c.w[0], c.w[1], c.w[2], kScS3,
+                             P.params.rtol, P.params.max_iters, true, so, c.timing)))
+      return rc;
+    c.stats.s3_iters = so.iters;
+    c.stats.s3_res = so.res;
+    c.stats.s3_outer = 1;
+    if (P.n_floating > 0) {
+      hipLaunchKernelGGL(k_slot_mean, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.slot,
+                         c.phi, P.n_floating, c.float_count, c.partials, c.counter, c.float_means);
+      hipLaunchKernelGGL(k_slot_sub, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.slot,
+                         c.phi, c.float_means);
+      CHECK_LAUNCH();
+    }
+  }
+
+  // 6. correction: M_FF delta = (G Phi)_F, u^{n+1} = u_ib - (dt/rho) delta, p^{n+1} = p^n + Phi
+  {
+    double* b4 = c.w[8];
+    double* delta = c.w[9];
+    hipLaunchKernelGGL(k_grad, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.emask, c.flags,
+                       kFlagF, c.phi, b4, S, sy, sz, c.fc.g2[0], c.fc.g2[1], c.fc.g2[2]);
+    CHECK_LAUNCH();
+    const double mc[4] = {c.fc.m[0], c.fc.m[1], c.fc.m[2], c.fc.m[3]};
+    auto op = sym_op<double, 3>(c, mc, kFlagF);
+    SolveOut so;
+    if ((rc = run_cg<double>(c, op, c.chunks, c.nchunks, b4, delta, c.w[0], c.w[1], c.w[2], kScS4,
+                             P.params.rtol, P.params.max_iters, true, so)))
+      return rc;
+    c.stats.s4_iters = so.iters;
+    c.stats.s4_res = so.res;
+    c.stats.s4_outer = 1;
+    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, 1.0, c.uib,
+                       -dt / rho, delta, c.u_next, 3, S);
+    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, 1.0, c.p, 1.0,
+                       c.phi, c.p_next, 1, S);
+    CHECK_LAUNCH();
+  }
+  std::swap(c.u, c.u_next);
+  std::swap(c.p, c.p_next);
+  c.t = t1;
+  c.steps += 1;
+  c.stats.steps = c.steps;
+  c.stats.t = c.t;
+  return IBFE_OK;
+}
+
+int copy_in(ibfe_ctx& c, double* dense, int nc, const double* src, int on_device) {
+  const int64_t n = c.nP;
+  const double* comp = src;
+  if (!on_device) {
+    HIP_TRY(hipMemcpyAsync(c.compact, src, sizeof(double) * nc * n, hipMemcpyHostToDevice, c.stream));
+    comp = c.compact;
+  }
+  HIP_TRY(hipMemsetAsync(dense - c.halo, 0, sizeof(double) * c.stride * nc, c.stream));
+  hipLaunchKernelGGL(k_scatter, dim3(blocks_lin(n)), dim3(kBlock), 0, c.stream, n, c.pids, comp, dense, nc,
+                     c.stride);
+  CHECK_LAUNCH();
+  if (!on_device) HIP_TRY(hipStreamSynchronize(c.stream));
+  return IBFE_OK;
+}
+
+int copy_out(ibfe_ctx& c, const double* dense, int nc, double* dst, int on_device) {
+  const int64_t n = c.nP;
+  double* comp = on_device ? dst : c.compact;
+  hipLaunchKernelGGL(k_gather, dim3(blocks_lin(n)), dim3(kBlock), 0, c.stream, n, c.pids, dense, comp, nc,
+                     c.stride);
+  CHECK_LAUNCH();
+  if (!on_device) {
+    HIP_TRY(hipMemcpyAsync(dst, c.compact, sizeof(double) * nc * n, hipMemcpyDeviceToHost, c.stream));
+    HIP_TRY(hipStreamSynchronize(c.stream));
+  }
+  return IBFE_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+const char* ibfe_last_error(void) { return g_err.c_str(); }
+
+int ibfe_plan_create(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* params,
+                     const ibfe_inlet* inlet, ibfe_plan** out) {
+  if (!out) return fail(IBFE_EINVAL, "out is NULL");
+  *out = nullptr;
+  std::unique_ptr<ibfe_plan> pl(new (std::nothrow) ibfe_plan());
+  if (!pl) return fail(IBFE_ENOMEM, "host allocation failed");
+  std::string err;
+  int rc = build_plan(grid, ib, params, inlet, pl->p, err);
+  if (rc) return fail(rc, err);
+  *out = pl.release();
+  return IBFE_OK;
+}
+
+int ibfe_plan_sizes(const ibfe_plan* plan, int64_t* n_p, int64_t* n_free, int64_t* n_pfree,
+                    int64_t* n_kept_cells, int64_t* n_floating) {
+  if (!plan) return fail(IBFE_EINVAL, "plan is NULL");
+  const Plan& P = plan->p;
+  if (n_p) *n_p = int64_t(P.P_ids.size());
+  if (n_free) *n_free = P.n_free;
+  if (n_pfree) *n_pfree = P.n_pfree;
+  if (n_kept_cells) *n_kept_cells = P.n_kept;
+  if (n_floating) *n_floating = P.n_floating;
+  return IBFE_OK;
+}
+
+int ibfe_plan_node_ids(const ibfe_plan* plan, int64_t* ids) {
+  if (!plan || !ids) return fail(IBFE_EINVAL, "NULL argument");
+  std::memcpy(ids, plan->p.P_ids.data(), sizeof(int64_t) * plan->p.P_ids.size());
+  return IBFE_OK;
+}
+
+int ibfe_plan_node_flags(const ibfe_plan* plan, uint8_t* flags) {
+  if (!plan || !flags) return fail(IBFE_EINVAL, "NULL argument");
+  std::memcpy(flags, plan->p.flags.data(), plan->p.flags.size());
+  return IBFE_OK;
+}
+
+void ibfe_plan_destroy(ibfe_plan* plan) { delete plan; }
+
+int ibfe_create(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* params,
+                const ibfe_inlet* inlet, const ibfe_alloc* alloc, void* hip_stream, ibfe_ctx** out) {
+  if (!out) return fail(IBFE_EINVAL, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(IBFE_EHIP, "no HIP device");
+  std::unique_ptr<ibfe_ctx> c(new (std::nothrow) ibfe_ctx());
+  if (!c) return fail(IBFE_ENOMEM, "host allocation failed");
+  std::string err;
+  int rc = build_plan(grid, ib, params, inlet, c->plan, err);
+  if (rc) return fail(rc, err);
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  if (alloc && alloc->alloc && alloc->free) {
+    c->alloc = *alloc;
+    c->user_alloc = true;
+  }
+  if ((rc = setup_device(*c))) return rc;
+  *out = c.release();
+  return IBFE_OK;
+}
+
+int ibfe_num_nodes(const ibfe_ctx* c, int64_t* n_u, int64_t* n_p) {
+  if (!c) return fail(IBFE_EINVAL, "ctx is NULL");
+  if (n_u) *n_u = c->nP;
+  if (n_p) *n_p = c->nP;
+  return IBFE_OK;
+}
+
+int ibfe_get_node_ids(const ibfe_ctx* c, int64_t* vel_ids, int64_t* p_ids) {
+  if (!c) return fail(IBFE_EINVAL, "ctx is NULL");
+  if (vel_ids) std::memcpy(vel_ids, c->plan.P_ids.data(), sizeof(int64_t) * c->nP);
+  if (p_ids) std::memcpy(p_ids, c->plan.P_ids.data(), sizeof(int64_t) * c->nP);
+  return IBFE_OK;
+}
+
+int ibfe_set_state(ibfe_ctx* c, const double* u, const double* p, double t, int on_device) {
+  if (!c || !u || !p) return fail(IBFE_EINVAL, "NULL argument");
+  if (!std::isfinite(t)) return fail(IBFE_EINVAL, "t must be finite");
+  int rc;
+  if ((rc = copy_in(*c, c->u, 3, u, on_device))) return rc;
+  if ((rc = copy_in(*c, c->p, 1, p, on_device))) return rc;
+  c->t = t;
+  c->steps = 0;
+  c->stats = ibfe_stats{};
+  c->stats.t = t;
+  return IBFE_OK;
+}
+
+int ibfe_step(ibfe_ctx* c, int nsteps) {
+  if (!c || nsteps < 0) return fail(IBFE_EINVAL, "bad argument");
+  for (int k = 0; k < nsteps; ++k) {
+    const double t_save = c->t;
+    int rc = step_once(*c);
+    if (rc) {
+      c->t = t_save;  // u, p were not swapped: the last completed state is intact
+      return rc;
+    }
+  }
+  return IBFE_OK;
+}
+
+int ibfe_get_state(ibfe_ctx* c, double* u, double* p, double* t, int on_device) {
+  if (!c) return fail(IBFE_EINVAL, "ctx is NULL");
+  int rc;
+  if (u && (rc = copy_out(*c, c->u, 3, u, on_device))) return rc;
+  if (p && (rc = copy_out(*c, c->p, 1, p, on_device))) return rc;
+  if (t) *t = c->t;
+  return IBFE_OK;
+}
+
+int ibfe_get_stats(const ibfe_ctx* c, ibfe_stats* stats) {
+  if (!c || !stats) return fail(IBFE_EINVAL, "NULL argument");
+  *stats = c->stats;
+  return IBFE_OK;
+}
+
+int ibfe_set_kernel_timing(ibfe_ctx* c, int enable) {
+  if (!c) return fail(IBFE_EINVAL, "ctx is NULL");
+  c->timing = enable != 0;
+  c->stats.poisson_apply_ms = 0.0;
+  c->stats.poisson_applies = 0;
+  return IBFE_OK;
+}
+
+int ibfe_get_field(ibfe_ctx* c, int which, double* out, int on_device) {
+  if (!c || !out) return fail(IBFE_EINVAL, "NULL argument");
+  switch (which) {
+    case IBFE_FIELD_USTAR: return copy_out(*c, c->ustar, 3, out, on_device);
+    case IBFE_FIELD_UIB: return copy_out(*c, c->uib, 3, out, on_device);
+    case IBFE_FIELD_PHI: return copy_out(*c, c->phi, 1, out, on_device);
+    default: return fail(IBFE_EINVAL, "unknown field");
+  }
+}
+
+int ibfe_apply(ibfe_ctx* c, int op, int precision, const double* x, double* y, int on_device) {
+  if (!c || !x || !y) return fail(IBFE_EINVAL, "NULL argument");
+  if (precision != 0 && precision != 1) return fail(IBFE_EINVAL, "precision must be 0 or 1");
+  if (precision == 1 && op != IBFE_OP_MASS && op != IBFE_OP_STIFF && op != IBFE_OP_ADVDIFF)
+    return fail(IBFE_EINVAL, "FP32 is available for MASS, STIFF and ADVDIFF only");
+  ibfe_ctx& C = *c;
+  const Plan& P = C.plan;
+  const int nb = blocks_for(C.nchunks);
+  const int sy = int(P.sy), sz = int(P.sz);
+  const int64_t S = C.stride;
+  double* xin = C.w[0];
+  double* yout = C.w[1];
+  int rc;
+  const int nc_in = (op == IBFE_OP_DIV || op == IBFE_OP_ADVDIFF || op == IBFE_OP_INTERP) ? 3 : 1;
+  if (op == IBFE_OP_SPREAD) {
+    if (P.M == 0) return fail(IBFE_EINVAL, "no Lagrangian points");
+    // x is M x 3 row major -> planes of mstride
+    std::vector<double> h(3 * C.mstride, 0.0);
+    std::vector<double> hx(3 * P.M);
+    if (on_device) {
+      HIP_TRY(hipMemcpyAsync(hx.data(), x, sizeof(double) * 3 * P.M, hipMemcpyDeviceToHost, C.stream));
+      HIP_TRY(hipStreamSynchronize(C.stream));
+    } else {
+      std::memcpy(hx.data(), x, sizeof(double) * 3 * P.M);
+    }
+    for (int64_t i = 0; i < P.M; ++i)
+      for (int d = 0; d < 3; ++d) h[d * C.mstride + i] = hx[3 * i + d];
+    HIP_TRY(hipMemcpyAsync(C.ibv[1], h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, C.stream));
+    HIP_TRY(hipMemsetAsync(yout - C.halo, 0, sizeof(double) * 3 * S, C.stream));
+    const int nn = int(P.sp_node.size());
+    hipLaunchKernelGGL(k_ib_spread, dim3(blocks_lin(nn)), dim3(kBlock), 0, C.stream, nn, C.sp_node, C.sp_ptr,
+                       C.sp_pt, C.sp_wt, C.ibv[1], C.mstride, yout, S);
+    CHECK_LAUNCH();
+    return copy_out(C, yout, 3, y, on_device);
+  }
+  if ((rc = copy_in(C, xin, nc_in, x, on_device))) return rc;
+  switch (op) {
+    case IBFE_OP_MASS:
+    case IBFE_OP_STIFF: {
+      const double* f = op == IBFE_OP_MASS ? C.fc.m : C.fc.k;
+      const double cf[4] = {f[0], f[1], f[2], f[3]};
+      if (precision == 0) {
+        auto o = sym_op<double, 1>(C, cf, kFlagP);
+        hipLaunchKernelGGL((k_apply<double, 1, OpSym<double, 1>>), dim3(nb), dim3(kBlock), 0, C.stream,
+                           C.chunks, C.nchunks, o, xin, yout);
+      } else {
+        float* x32 = reinterpret_cast<float*>(C.w[2]);
+        float* y32 = reinterpret_cast<float*>(C.w[3]);
+        hipLaunchKernelGGL((k_masked_copy<double, float>), dim3(nb), dim3(kBlock), 0, C.stream, C.chunks,
+                           C.nchunks, C.flags, kFlagP, xin, x32, 1, S);
+        auto o = sym_op<float, 1>(C, cf, kFlagP);
+        hipLaunchKernelGGL((k_apply<float, 1, OpSym<float, 1>>), dim3(nb), dim3(kBlock), 0, C.stream,
+                           C.chunks, C.nchunks, o, x32, y32);
+        hipLaunchKernelGGL((k_masked_copy<float, double>), dim3(nb), dim3(kBlock), 0, C.stream, C.chunks,
+                           C.nchunks, C.flags, kFlagP, y32, yout, 1, S);
+      }
+      CHECK_LAUNCH();
+      return copy_out(C, yout, 1, y, on_device);
+    }
+    case IBFE_OP_GRAD:
+      hipLaunchKernelGGL(k_grad, dim3(nb), dim3(kBlock), 0, C.stream, C.chunks, C.nchunks, C.emask, C.flags,
+                         kFlagP, xin, yout, S, sy, sz, C.fc.g2[0], C.fc.g2[1], C.fc.g2[2]);
+      CHECK_LAUNCH();
+      return copy_out(C, yout, 3, y, on_device);
+    case IBFE_OP_DIV:
+      hipLaunchKernelGGL(k_div, dim3(nb), dim3(kBlock), 0, C.stream, C.chunks, C.nchunks, C.emask, C.flags,
+                         kFlagP, 0u, xin, yout, S, sy, sz, C.fc.g2[0], C.fc.g2[1], C.fc.g2[2], 1.0);
+      CHECK_LAUNCH();
+      return copy_out(C, yout, 1, y, on_device);
+    case IBFE_OP_ADVDIFF: {
+      float* c32 = C.coef32;
+      if (precision == 1 && !c32) {
+        // FP64-mode context: build a temporary FP32 copy in unused work space
+        if (!C.v32[0]) {
+          int rc2;
+          if ((rc2 = C.field(&C.coef32, 27))) return rc2;
+          for (int i = 0; i < 10; ++i)
+            if ((rc2 = C.field(&C.v32[i], 3))) return rc2;
+        }
+        c32 = C.coef32;
+      }
+      if ((rc = build_s1(C))) return rc;
+      if (precision == 0) {
+        auto o = stencil_op<double>(C, C.coef64, kFlagP);
+        hipLaunchKernelGGL((k_apply<double, 3, OpStencil<double, 3>>), dim3(nb), dim3(kBlock), 0, C.stream,
+                           C.chunks, C.nchunks, o, xin, yout);
+      } else {
+        float* x32 = C.v32[0];
+        float* y32 = C.v32[1];
+        hipLaunchKernelGGL((k_masked_copy<double, float>), dim3(nb), dim3(kBlock), 0, C.stream, C.chunks,
+                           C.nchunks, C.flags, kFlagP, xin, x32, 3, S);
+        auto o = stencil_op<float>(C, c32, kFlagP);
+        hipLaunchKernelGGL((k_apply<float, 3, OpStencil<float, 3>>), dim3(nb), dim3(kBlock), 0, C.stream,
+                           C.chunks, C.nchunks, o, x32, y32);
+        hipLaunchKernelGGL((k_masked_copy<float, double>), dim3(nb), dim3(kBlock), 0, C.stream, C.chunks,
+                           C.nchunks, C.flags, kFlagP, y32, yout, 3, S);
+      }
+      CHECK_LAUNCH();
+      return copy_out(C, yout, 3, y, on_device);
+    }
+    case IBFE_OP_INTERP: {
+      if (P.M == 0) return fail(IBFE_EINVAL, "no Lagrangian points");
+      const int M = int(P.M);
+      hipLaunchKernelGGL(k_ib_interp, dim3(blocks_lin(M)), dim3(kBlock), 0, C.stream, M, C.ib_idx, C.ib_w,
+                         C.UB, xin, S, C.ibv[0], C.mstride, 0);
+      CHECK_LAUNCH();
+      std::vector<double> h(3 * C.mstride);
+      HIP_TRY(hipMemcpyAsync(h.data(), C.ibv[0], sizeof(double) * h.size(), hipMemcpyDeviceToHost, C.stream));
+      HIP_TRY(hipStreamSynchronize(C.stream));
+      std::vector<double> o(3 * M);
+      for (int i = 0; i < M; ++i)
+        for (int d = 0; d < 3; ++d) o[3 * i + d] = -h[d * C.mstride + i];
+      if (on_device) {
+        HIP_TRY(hipMemcpyAsync(y, o.data(), sizeof(double) * o.size(), hipMemcpyHostToDevice, C.stream));
+        HIP_TRY(hipStreamSynchronize(C.stream));
+      } else {
+        std::memcpy(y, o.data(), sizeof(double) * o.size());
+      }
+      return IBFE_OK;
+    }
+    default: return fail(IBFE_EINVAL, "unknown operator");
+  }
+}
+
+void ibfe_destroy(ibfe_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  delete c;
+}
+
+}  // extern "C"

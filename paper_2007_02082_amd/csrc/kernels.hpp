@@ -1,0 +1,609 @@
+// gfx950 kernels of the IPCS + BCE-IB step on the masked Q1 grid.
+//
+// Data layout: every nodal field is a dense array over all grid nodes (id
+// n = i + sy j + sz k), offset by a zero halo so that the 27 neighbours of any
+// node are addressable without bounds checks; base pointers passed to kernels
+// point at node 0.  Work is distributed over a list of 64-node chunks that
+// contain at least one node of P; a wavefront owns one chunk, so every load
+// and store of a chunk is one coalesced 256/512-byte transaction.  Multi-
+// component fields are `nc` planes of `stride` values.
+//
+// Matrix-free Q1 operators on a uniform grid: within one cube the entry
+// between nodes i and j = i + o depends only on o, and the assembled entry is
+// that value times the number of kept cells that contain both nodes.  With
+// emask(i) = bits of the 8 cells around node i (bit s = sx + 2 sy + 4 sz for
+// the cell (i-1+sx, j-1+sy, k-1+sz)), the cells shared with i + o are
+// emask & X(ox) & Y(oy) & Z(oz), X(+1) = cells with sx = 1, X(-1) with sx = 0.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ibfe {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+
+// ---------------------------------------------------------------------------
+// launch geometry
+// ---------------------------------------------------------------------------
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Remap so that XCD x processes one contiguous range of chunks: the
+// stencil's neighbour rows are then reused from that XCD's L2.
+__device__ __forceinline__ int xcd_block() {
+  const int B = gridDim.x, b = blockIdx.x;
+  const int xcd = b & 7, idx = b >> 3;
+  const int per = B >> 3, rem = B & 7;
+  return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+// Node handled by this thread, or -1.
+__device__ __forceinline__ int chunk_node(const int* __restrict__ chunks, int nchunks) {
+  const int c = xcd_block() * kWaves + (threadIdx.x >> 6);
+  if (c >= nchunks) return -1;
+  return chunks[c] * 64 + (threadIdx.x & 63);
+}
+
+// ---------------------------------------------------------------------------
+// deterministic block reductions (FP64)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Reduce K per-thread values over the block; writes partials[k * nb + blockIdx.x]
+// and returns true in the block that arrived last (which then holds the full
+// sums in `tot`, reduced in a fixed order independent of arrival order).
+template <int K>
+__device__ bool reduce_last(double (&v)[K], double* __restrict__ partials,
+                            unsigned* __restrict__ counter, double (&tot)[K]) {
+  __shared__ double sh[K][kWaves];
+  __shared__ bool last;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nb = gridDim.x;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double s = wave_sum(v[k]);
+    if (lane == 0) sh[k][wave] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < kWaves; ++w) s += sh[k][w];
+      partials[k * nb + blockIdx.x] = s;
+    }
+    __threadfence();
+    unsigned ticket = atomicAdd(counter, 1u);
+    last = (ticket == unsigned(nb - 1));
+  }
+  __syncthreads();
+  if (!last) return false;
+  __threadfence();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) s += __builtin_nontemporal_load(&partials[k * nb + b]);
+    s = wave_sum(s);
+    __syncthreads();
+    if (lane == 0) sh[k][wave] = s;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < kWaves; ++w) t += sh[k][w];
+    tot[k] = t;
+  }
+  if (threadIdx.x == 0) *counter = 0u;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// stencil coefficient helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ constexpr uint32_t side_mask(int axis, int o) {
+  // cells whose side along `axis` is compatible with neighbour offset o
+  return o == 0 ? 0xFFu
+                 : (axis == 0 ? (o > 0 ? 0xAAu : 0x55u)
+                              : axis == 1 ? (o > 0 ? 0xCCu : 0x33u) : (o > 0 ? 0xF0u : 0x0Fu));
+}
+__device__ __forceinline__ constexpr uint32_t compat(int ox, int oy, int oz) {
+  return side_mask(0, ox) & side_mask(1, oy) & side_mask(2, oz);
+}
+
+// y = sum_o c[|ox|+|oy|+|oz|] * popcount(e & compat(o)) * x[n + o]
+// (symmetric operators alpha M + beta K: c[t] = per-cell entry for offset type t).
+template <typename T>
+__device__ __forceinline__ T apply_sym(const T* __restrict__ x, int n, uint32_t e,
+                                       const T (&c)[4], int sy, int sz) {
+  T acc = T(0);
+  if (e == 0xFFu) {  // interior: constant 27-point stencil
+#pragma unroll
+    for (int oz = -1; oz <= 1; ++oz)
+#pragma unroll
+      for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
+        for (int ox = -1; ox <= 1; ++ox) {
+          const int t = (ox != 0) + (oy != 0) + (oz != 0);
+          const T w = c[t] * T(8 >> t);
+          acc += w * x[n + ox + sy * oy + sz * oz];
+        }
+  } else {
+#pragma unroll
+    for (int oz = -1; oz <= 1; ++oz)
+#pragma unroll
+      for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
+        for (int ox = -1; ox <= 1; ++ox) {
+          const int t = (ox != 0) + (oy != 0) + (oz != 0);
+          const T w = c[t] * T(__builtin_popcount(e & compat(ox, oy, oz)));
+          acc += w * x[n + ox + sy * oy + sz * oz];
+        }
+  }
+  return acc;
+}
+
+// Weak gradient G_d x at node n: entry(o) = sum over shared kept cells of
+// (1/2)(+-1) * prod_{e != d} m(o_e), m(0) = h/3, m(1) = h/6; the sign is that
+// of o_d, or for o_d = 0 +1 on cells below the node (s_d = 0), -1 above.
+// g2[c] = (1/2) (h/3)^(2-c) (h/6)^c with c = nonzeros among the two other axes.
+template <typename T, int D>
+__device__ __forceinline__ T apply_grad(const T* __restrict__ x, int n, uint32_t e,
+                                        const T (&g2)[3], int sy, int sz) {
+  T acc = T(0);
+#pragma unroll
+  for (int oz = -1; oz <= 1; ++oz)
+#pragma unroll
+    for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
+      for (int ox = -1; ox <= 1; ++ox) {
+        const int o[3] = {ox, oy, oz};
+        const int cnt_other = (D != 0 && ox != 0) + (D != 1 && oy != 0) + (D != 2 && oz != 0);
+        const uint32_t cm = e & compat(ox, oy, oz);
+        int mult;
+        if (o[D] != 0) {
+          mult = o[D] * __builtin_popcount(cm);
+        } else {
+          mult = __builtin_popcount(cm & side_mask(D, -1)) - __builtin_popcount(cm & side_mask(D, 1));
+        }
+        acc += g2[cnt_other] * T(mult) * x[n + ox + sy * oy + sz * oz];
+      }
+  return acc;
+}
+
+// ---------------------------------------------------------------------------
+// operators used inside the Krylov kernels
+// ---------------------------------------------------------------------------
+
+// alpha M + beta K restricted to rows with (flags & rowbit); nc identical
+// components.  diag = c[0] * popcount(emask).
+template <typename T, int NC>
+struct OpSym {
+  static constexpr int kNC = NC;
+  const uint8_t* emask;
+  const uint8_t* flags;
+  uint32_t rowbit;
+  int sy, sz;
+  int64_t stride;
+  T c[4];
+  __device__ __forceinline__ bool row(int n) const { return flags[n] & rowbit; }
+  __device__ __forceinline__ void apply(int n, const T* __restrict__ x, T (&y)[NC]) const {
+    const uint32_t e = emask[n];
+    T cc[4] = {c[0], c[1], c[2], c[3]};
+#pragma unroll
+    for (int d = 0; d < NC; ++d) y[d] = apply_sym<T>(x + d * stride, n, e, cc, sy, sz);
+  }
+  __device__ __forceinline__ T inv_diag(int n) const {
+    return T(1) / (c[0] * T(__builtin_popcount(uint32_t(emask[n]))));
+  }
+};
+
+// Stored 27-point stencil (advection-diffusion operator of the tentative
+// velocity), coefficient plane t = (ox+1) + 3 (oy+1) + 9 (oz+1).
+template <typename T, int NC>
+struct OpStencil {
+  static constexpr int kNC = NC;
+  const T* coef;  // [27][stride]
+  const uint8_t* flags;
+  uint32_t rowbit;
+  int sy, sz;
+  int64_t stride;
+  __device__ __forceinline__ bool row(int n) const { return flags[n] & rowbit; }
+  __device__ __forceinline__ void apply(int n, const T* __restrict__ x, T (&y)[NC]) const {
+#pragma unroll
+    for (int d = 0; d < NC; ++d) y[d] = T(0);
+#pragma unroll
+    for (int oz = -1; oz <= 1; ++oz)
+#pragma unroll
+      for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
+        for (int ox = -1; ox <= 1; ++ox) {
+          const int t = (ox + 1) + 3 * (oy + 1) + 9 * (oz + 1);
+          const T w = coef[t * stride + n];
+          const int m = n + ox + sy * oy + sz * oz;
+#pragma unroll
+          for (int d = 0; d < NC; ++d) y[d] += w * x[d * stride + m];
+        }
+  }
+  __device__ __forceinline__ T inv_diag(int n) const { return T(1) / coef[13 * stride + n]; }
+};
+
+// CSR matrix (the IB Gram matrix) over rows [0, nrows), NC right-hand sides.
+template <int NC>
+struct OpCSR {
+  static constexpr int kNC = NC;
+  const int64_t* ptr;
+  const int32_t* col;
+  const double* val;
+  const double* diag;
+  int nrows;
+  int64_t stride;
+  __device__ __forceinline__ bool row(int n) const { return n < nrows; }
+  __device__ __forceinline__ void apply(int n, const double* __restrict__ x, double (&y)[NC]) const {
+#pragma unroll
+    for (int d = 0; d < NC; ++d) y[d] = 0.0;
+    for (int64_t q = ptr[n]; q < ptr[n + 1]; ++q) {
+      const double w = val[q];
+      const int c = col[q];
+#pragma unroll
+      for (int d = 0; d < NC; ++d) y[d] += w * x[d * stride + c];
+    }
+  }
+  __device__ __forceinline__ double inv_diag(int n) const { return 1.0 / diag[n]; }
+};
+
+// ---------------------------------------------------------------------------
+// Krylov scalar state (device resident; updated by the last block of each
+// reducing kernel so that no host round trip is needed between kernels)
+// ---------------------------------------------------------------------------
+
+struct KScal {
+  double rz, rr, bb, alpha, beta, tol2;        // CG
+  double rho, rho_old, omega, ts, tt, rv;      // BiCGStab (alpha shared)
+  int32_t done, iters, max_iters, status;      // status: 0 ok, 1 breakdown, 2 non-finite
+};
+
+__device__ __forceinline__ bool bad(double v) { return !(v == v) || v - v != 0.0; }
+
+// ---------------------------------------------------------------------------
+// CG kernels (Jacobi preconditioned): x, r, p, q are NC-plane vectors
+// ---------------------------------------------------------------------------
+
+// r = b - A x; p = D^-1 r; rz = r.p, rr = r.r, bb = b.b
+template <typename T, class Op>
+__global__ __launch_bounds__(kBlock) void k_cg_init(const int* __restrict__ chunks, int nchunks,
+                                                    Op op, const T* __restrict__ b, T* __restrict__ x,
+                                                    T* __restrict__ r, T* __restrict__ p,
+                                                    double* partials, unsigned* counter, KScal* sc,
+                                                    int zero_guess, double tol2, int max_iters) {
+  constexpr int NC = Op::kNC;
+  double v[3] = {0.0, 0.0, 0.0};
+  const int n = chunk_node(chunks, nchunks);
+  if (n >= 0) {
+    const bool rw = op.row(n);
+    T ax[NC];
+    if (!zero_guess && rw) op.apply(n, x, ax);
+    const T di = rw ? op.inv_diag(n) : T(0);
+#pragma unroll
+    for (int d = 0; d < NC; ++d) {
+      const int64_t i = d * op.stride + n;
+      if (zero_guess) x[i] = T(0);
+      const T bi = rw ? b[i] : T(0);
+      const T ri = rw ? (zero_guess ? bi : T(bi - ax[d])) : T(0);
+      const T zi = ri * di;
+      r[i] = ri;
+      p[i] = zi;
+      v[0] += double(ri) * double(zi);
+      v[1] += double(ri) * double(ri);
+      v[2] += double(bi) * double(bi);
+    }
+  }
+  double tot[3];
+  if (reduce_last<3>(v, partials, counter, tot) && threadIdx.x == 0) {
+    sc->tol2 = tol2;
+    sc->max_iters = max_iters;
+    sc->rz = tot[0];
+    sc->rr = tot[1];
+    sc->bb = tot[2];
+    sc->iters = 0;
+    sc->status = 0;
+    sc->done = (tot[1] <= tol2 * tot[2]) ? 1 : 0;
+    if (bad(tot[0]) || bad(tot[1]) || bad(tot[2])) {
+      sc->status = 2;
+      sc->done = 1;
+    }
+  }
+}
+
+// q = A p; alpha = rz / (p . q)
+template <typename T, class Op>
+__global__ __launch_bounds__(kBlock) void k_cg_q(const int* __restrict__ chunks, int nchunks, Op op,
+                                                 const T* __restrict__ p, T* __restrict__ q,
+                                                 double* partials, unsigned* counter, KScal* sc) {
+  if (sc->done) return;
+  constexpr int NC = Op::kNC;
+  double v[1] = {0.0};
+  const int n = chunk_node(chunks, nchunks);
+  if (n >= 0) {
+    T y[NC];
+    const bool rw = op.row(n);
+    if (rw) op.apply(n, p, y);
+#pragma unroll
+    for (int d = 0; d < NC; ++d) {
+      const int64_t i = d * op.stride + n;
+      const T qi = rw ? y[d] : T(0);
+      q[i] = qi;
+      v[0] += double(p[i]) * double(qi);
+    }
+  }
+  double tot[1];
+  if (reduce_last<1>(v, partials, counter, tot) && threadIdx.x == 0) {
+    const double pq = tot[0];
+    if (!(pq > 0.0) || bad(pq)) {
+      sc->status = bad(pq) ? 2 : 1;
+      sc->done = 1;
+      sc->alpha = 0.0;
+    } else {
+      sc->alpha = sc->rz / pq;
+    }
+  }
+}
+
+// x += alpha p; r -= alpha q; rz = r.D^-1 r; rr = r.r; beta = rz_new / rz
+template <typename T, class Op>
+__global__ __launch_bounds__(kBlock) void k_cg_xr(const int* __restrict__ chunks, int nchunks, Op op,
+                                                  T* __restrict__ x, T* __restrict__ r,
+                                                  const T* __restrict__ p, const T* __restrict__ q,
+                                                  double* partials, unsigned* counter, KScal* sc) {
+  if (sc->done) return;
+  constexpr int NC = Op::kNC;
+  const T alpha = T(sc->alpha);
+  double v[2] = {0.0, 0.0};
+  const int n = chunk_node(chunks, nchunks);
+  if (n >= 0 && op.row(n)) {
+    const T di = op.inv_diag(n);
+#pragma unroll
+    for (int d = 0; d < NC; ++d) {
+      const int64_t i = d * op.stride + n;
+      x[i] += alpha * p[i];
+      const T ri = r[i] - alpha * q[i];
+      r[i] = ri;
+      v[0] += double(ri) * double(ri * di);
+      v[1] += double(ri) * double(ri);
+    }
+  }
+  double tot[2];
+  if (reduce_last<2>(v, partials, counter, tot) && threadIdx.x == 0) {
+    const double rz_new = tot[0];
+    sc->beta = rz_new / sc->rz;
+    sc->rz = rz_new;
+    sc->rr = tot[1];
+    sc->iters += 1;
+    if (bad(rz_new) || bad(tot[1])) {
+      sc->status = 2;
+      sc->done = 1;
+    } else if (tot[1] <= sc->tol2 * sc->bb || sc->iters >= sc->max_iters) {
+      sc->done = 1;
+    }
+  }
+}
+
+// p = D^-1 r + beta p
+template <typename T, class Op>
+__global__ __launch_bounds__(kBlock) void k_cg_p(const int* __restrict__ chunks, int nchunks, Op op,
+                                                 const T* __restrict__ r, T* __restrict__ p,
+                                                 const KScal* sc) {
+  if (sc->done) return;
+  constexpr int NC = Op::kNC;
+  const T beta = T(sc->beta);
+  const int n = chunk_node(chunks, nchunks);
+  if (n >= 0 && op.row(n)) {
+    const T di = op.inv_diag(n);
+#pragma unroll
+    for (int d = 0; d < NC; ++d) {
+      const int64_t i = d * op.stride + n;
+      p[i] = r[i] * di + beta * p[i];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// BiCGStab kernels (right Jacobi preconditioning), NC-plane vectors
+// ---------------------------------------------------------------------------
+
+// r = b - A x, rhat = r, p = v = 0; rho = rr = r.r, bb = b.b
+template <typename T, class Op>
+__global__ __launch_bounds__(kBlock) void k_bi_init(const int* __restrict__ chunks, int nchunks, Op op,
+                                                    const T* __restrict__ b, const T* __restrict__ x,
+                                                    T* __restrict__ r, T* __restrict__ rhat,
+                                                    T* __restrict__ p, T* __restrict__ v,
+                                                    double* partials, unsigned* counter, KScal* sc,
+                                                    double tol2, int max_iters) {
+  constexpr int NC = Op::kNC;
+  double s[2] = {0.0, 0.0};
+  const int n = chunk_node(chunks, nchunks);
+  if (n >= 0) {
+    const bool rw = op.row(n);
+    T ax[NC];
+    if (rw) op.apply(n, x, ax);
+#pragma unroll
+    for (int d = 0; d < NC; ++d) {
+      const int64_t i = d * op.stride + n;
+      const T bi = rw ? b[i] : T(0);
+      const T ri = rw ? T(bi - ax[d]) : T(0);
+      r[i] = ri;
+      rhat[i] = ri;
+      p[i] = T(0);
+      v[i] = T(0);
+      s[0] += double(ri) * double(ri);
+      s[1] += double(bi) * double(bi);
+    }
+  }
+  double tot[2];
+  if (reduce_last<2>(s, partials, counter, tot) && threadIdx.x == 0) {
+    sc->tol2 = tol2;
+    sc->max_iters = max_iters;
+    sc->rho = tot[0];
+    sc->rr = tot[0];
+    sc->bb = tot[1];
+    sc->rho_old = 1.0;
+    sc->alpha = 1.0;
+    sc->omega = 1.0;
+    sc->iters = 0;
+    sc->status = 0;
+    sc->done = (tot[0] <= tol2 * tot[1]) ? 1 : 0;
+    if (bad(tot[0]) || bad(tot[1])) {
+      sc->status = 2;
+      sc->done = 1;
+    }
+  }
+}
+
+// p = r + beta (p - omega v), phat = D^-1 p
+template <typename T, class Op>
+__global__ __launch_bounds__(kBlock) void k_bi_p(const int* __restrict__ chunks, int nchunks, Op op,
+                                                 const T* __restrict__ r, T* __restrict__ p,
+                                                 const T* __restrict__ v, T* __restrict__ phat,
+                                                 const KScal* sc) {
+  if (sc->done) return;
+  constexpr int NC = Op::kNC;
+  const T beta = T((sc->rho / sc->rho_old) * (sc->alpha / sc->omega));
+  const T omega = T(sc->omega);
+  const int n = chunk_node(chunks, nchunks);
+  if (n >= 0 && op.row(n)) {
+    const T di = op.inv_diag(n);
+#pragma unroll
+    for (int d = 0; d < NC; ++d) {
+      const int64_t i = d * op.stride + n;
+      const T pi = r[i] + beta * (p[i] - omega * v[i]);
+      p[i] = pi;
+      phat[i] = pi * di;
+    }
+  } else if (n >= 0) {
+#pragma unroll
+    for (int d = 0; d < NC; ++d) phat[d * op.stride + n] = T(0);
+  }
+}
+
+// y = A xin; reduce rhat.y (mode 0: alpha = rho / rhat.v) or
+// (t.s, t.t) (mode 1: omega = t.s / t.t)
+template <typename T, class Op, int MODE>
+__global__ __launch_bounds__(kBlock) void k_bi_apply(const int* __restrict__ chunks, int nchunks, Op op,
+                                                     const T* __restrict__ xin, T* __restrict__ y,
+                                                     const T* __restrict__ w, double* partials,
+                                                     unsigned* counter, KScal* sc) {
+  if (sc->done) return;
+  constexpr int NC = Op::kNC;
+  double s[2] = {0.0, 0.0};
+  const int n = chunk_node(chunks, nchunks);
+  if (n >= 0) {
+    const bool rw = op.row(n);
+    T ay[NC];
+    if (rw) op.apply(n, xin, ay);
+#pragma unroll
+    for (int d = 0; d < NC; ++d) {
+      const int64_t i = d * op.stride + n;
+      const T yi = rw ? ay[d] : T(0);
+      y[i] = yi;
+      s[0] += double(w[i]) * double(yi);
+      if (MODE == 1) s[1] += double(yi) * double(yi);
+    }
+  }
+  double tot[2];
+  if (reduce_last<2>(s, partials, counter, tot) && threadIdx.x == 0) {
+    if (MODE == 0) {
+      sc->rv = tot[0];
+      if (tot[0] == 0.0 || bad(tot[0])) {
+        sc->status = bad(tot[0]) ? 2 : 1;
+        sc->done = 1;
+      } else {
+        sc->alpha = sc->rho / tot[0];
+      }
+    } else {
+      sc->ts = tot[0];
+      sc->tt = tot[1];
+      if (bad(tot[0]) || bad(tot[1])) {
+        sc->status = 2;
+        sc->done = 1;
+      } else {
+        sc->omega = tot[1] > 0.0 ? tot[0] / tot[1] : 0.0;
+      }
+    }
+  }
+}
+
+// s = r - alpha v, shat = D^-1 s
+template <typename T, class Op>
+__global__ __launch_bounds__(kBlock) void k_bi_s(const int* __restrict__ chunks, int nchunks, Op op,
+                                                 const T* __restrict__ r, const T* __restrict__ v,
+                                                 T* __restrict__ s, T* __restrict__ shat,
+                                                 const KScal* sc) {
+  if (sc->done) return;
+  constexpr int NC = Op::kNC;
+  const T alpha = T(sc->alpha);
+  const int n = chunk_node(chunks, nchunks);
+  if (n >= 0 && op.row(n)) {
+    const T di = op.inv_diag(n);
+#pragma unroll
+    for (int d = 0; d < NC; ++d) {
+      const int64_t i = d * op.stride + n;
+      const T si = r[i] - alpha * v[i];
+      s[i] = si;
+      shat[i] = si * di;
+    }
+  } else if (n >= 0) {
+#pragma unroll
+    for (int d = 0; d < NC; ++d) {
+      s[d * op.stride + n] = T(0);
+      shat[d * op.stride + n] = T(0);
+    }
+  }
+}
+
+// x += alpha phat + omega shat; r = s - omega t; rho = rhat.r; rr = r.r
+template <typename T, class Op>
+__global__ __launch_bounds__(kBlock) void k_bi_x(const int* __restrict__ chunks, int nchunks, Op op,
+                                                 T* __restrict__ x, T* __restrict__ r,
+                                                 const T* __restrict__ rhat, const T* __restrict__ phat,
+                                                 const T* __restrict__ shat, const T* __restrict__ s,
+                                                 const T* __restrict__ t, double* partials,
+                                                 unsigned* counter, KScal* sc) {
+  if (sc->done) return;
+  constexpr int NC = Op::kNC;
+  const T alpha = T(sc->alpha), omega = T(sc->omega);
+  double v[2] = {0.0, 0.0};
+  const int n = chunk_node(chunks, nchunks);
+  if (n >= 0 && op.row(n)) {
+#pragma unroll
+    for (int d = 0; d < NC; ++d) {
+      const int64_t i = d * op.stride + n;
+      x[i] += alpha * phat[i] + omega * shat[i];
+      const T ri = s[i] - omega * t[i];
+      r[i] = ri;
+      v[0] += double(rhat[i]) * double(ri);
+      v[1] += double(ri) * double(ri);
+    }
+  }
+  double tot[2];
+  if (reduce_last<2>(v, partials, counter, tot) && threadIdx.x == 0) {
+    sc->rho_old = sc->rho;
+    sc->rho = tot[0];
+    sc->rr = tot[1];
+    sc->iters += 1;
+    if (bad(tot[0]) || bad(tot[1])) {
+      sc->status = 2;
+      sc->done = 1;
+    } else if (tot[1] <= sc->tol2 * sc->bb || sc->iters >= sc->max_iters) {
+      sc->done = 1;
+    } else if (sc->omega == 0.0 || tot[0] == 0.0) {
+      sc->status = 1;
+      sc->done = 1;
+    }
+  }
+}
+
+}  // namespace ibfe

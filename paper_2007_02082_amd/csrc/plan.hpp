@@ -1,0 +1,62 @@
+// Host-side set-up of one flow problem: validation, derived node sets on the
+// masked Q1 grid, canonical ordering, IB stencils and the IB Gram matrix.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ibfe.h"
+
+namespace ibfe {
+
+constexpr int kChunk = 64;      // nodes per chunk (one wavefront)
+constexpr int kMaxHarmonics = 16;
+constexpr int kMaxFloating = 8; // outlet-less connected parts supported
+
+struct Plan {
+  // grid
+  int nx = 0, ny = 0, nz = 0;
+  double h = 0.0, origin[3] = {0, 0, 0};
+  int64_t N = 0;                 // grid nodes
+  int64_t sy = 0, sz = 0;        // id strides in y and z
+  // physics
+  ibfe_params params{};
+  // per node
+  std::vector<uint8_t> mask, tag;
+  std::vector<uint8_t> emask;    // bit s = sx + 2 sy + 4 sz: cell (i-1+sx, j-1+sy, k-1+sz) kept
+  std::vector<uint8_t> flags;    // IBFE_FLAG_* bits
+  std::vector<int8_t> float_slot;// -1, or slot of the outlet-less part the node belongs to
+  int n_floating = 0;
+  std::vector<int64_t> float_count; // P' nodes per floating slot
+  // sets
+  std::vector<int64_t> P_ids;    // canonical order
+  int64_t n_free = 0, n_pfree = 0, n_kept = 0;
+  std::vector<int32_t> chunks;   // 64-node chunks holding at least one node of P
+  // inlet table
+  int K = 0;
+  double omega = 0.0;
+  std::vector<int64_t> inlet_ids;
+  std::vector<double> inlet_shape;   // (2K+1) x n x 3
+  // immersed boundary
+  int64_t M = 0;
+  double dS = 0.0;
+  std::vector<double> X, U_B;        // M x 3
+  std::vector<int32_t> ib_idx;       // [64][M]: support node id or -1
+  std::vector<double> ib_w;          // [64][M]: weights (0 where idx = -1)
+  std::vector<int64_t> G_ptr;        // CSR of G = I_F I_F^T (M x M)
+  std::vector<int32_t> G_col;
+  std::vector<double> G_val, G_diag;
+  std::vector<int32_t> sp_node;      // nodes of F inside some support
+  std::vector<int64_t> sp_ptr;       // CSR rows over sp_node: (point, weight)
+  std::vector<int32_t> sp_pt;
+  std::vector<double> sp_w;
+};
+
+// Returns IBFE_OK or an error code with `err` set.
+int build_plan(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* params,
+               const ibfe_inlet* inlet, Plan& plan, std::string& err);
+
+double delta4(double r);
+
+}  // namespace ibfe

@@ -1,0 +1,91 @@
+"""CPU-only checks of the C ABI library: it loads, exports every symbol that
+include/ibfe.h declares, and its host set-up (derived sets, canonical order,
+input validation) agrees bit for bit with the oracle."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2007_02082_amd as ibfe
+import synth
+from oracle import grid
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "ibfe.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ibfe_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ibfe.load()
+    names = _declared_symbols()
+    assert len(names) >= 17
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(ibfe.SIGNATURES), "binding and header disagree"
+
+
+CASES = [
+    lambda: synth.random_blob_case(seed=1),
+    lambda: synth.random_blob_case(cells=(7, 4, 5), seed=9),
+    lambda: synth.poiseuille_c1(),
+    lambda: synth.small_cylinder(8, 16),
+    lambda: synth.closed_box(4),
+    lambda: synth.channel_case(),
+    lambda: synth.shear_advection_case(),
+]
+
+
+@pytest.mark.parametrize("make", CASES)
+def test_plan_sets_match_oracle_bit_exactly(make):
+    c = make()
+    pl = ibfe.Plan(**ibfe.inputs_from_case(c))
+    s = grid.derive_sets(c.nx, c.ny, c.nz, c.node_mask, c.bc_tag)
+    np.testing.assert_array_equal(pl.node_ids(), s.P)
+    f = pl.node_flags()
+    np.testing.assert_array_equal((f & ibfe.FLAG_P) > 0, s.in_P)
+    np.testing.assert_array_equal((f & ibfe.FLAG_F) > 0, s.in_F)
+    np.testing.assert_array_equal((f & ibfe.FLAG_DU) > 0, s.in_Du)
+    np.testing.assert_array_equal((f & ibfe.FLAG_PDIR) > 0, s.p_dir)
+    sz = pl.sizes()
+    assert sz["n_p"] == s.P.size and sz["n_free"] == s.F.size and sz["n_pfree"] == s.Pp.size
+    assert sz["n_kept_cells"] == int(s.kept_cells.sum())
+
+
+def test_c1_counts():
+    c = synth.poiseuille_c1()
+    sz = ibfe.Plan(**ibfe.inputs_from_case(c)).sizes()
+    assert (sz["n_p"], sz["n_free"], sz["n_kept_cells"]) == (16705, 12352, 14336)
+
+
+def test_floating_part_detected():
+    assert ibfe.Plan(**ibfe.inputs_from_case(synth.closed_box(4))).sizes()["n_floating"] == 1
+    assert ibfe.Plan(**ibfe.inputs_from_case(synth.shear_advection_case())).sizes()["n_floating"] == 1
+    assert ibfe.Plan(**ibfe.inputs_from_case(synth.poiseuille_c1())).sizes()["n_floating"] == 0
+
+
+def test_input_errors():
+    c = synth.random_blob_case(seed=1)
+    kw = ibfe.inputs_from_case(c)
+    bad = dict(kw, node_mask=np.zeros_like(c.node_mask))
+    with pytest.raises(ibfe.IbfeError, match="EINVAL"):
+        ibfe.Plan(**bad)
+    bad = dict(kw, node_mask=np.full_like(c.node_mask, 2))
+    with pytest.raises(ibfe.IbfeError, match="EINVAL"):
+        ibfe.Plan(**bad)
+    bad = dict(kw, mu=-1.0)
+    with pytest.raises(ibfe.IbfeError, match="EINVAL"):
+        ibfe.Plan(**bad)
+    # an inlet table node that is not an inlet-tagged node of P
+    bad = dict(kw, inlet_ids=np.array([c.N - 1]), inlet_shape=np.zeros((5, 1, 3)))
+    with pytest.raises(ibfe.IbfeError, match="EINVAL"):
+        ibfe.Plan(**bad)
+    # a Lagrangian point whose support holds no free node
+    far = np.array([[100.0, 100.0, 100.0]])
+    bad = dict(kw, X=far, U_B=None)
+    with pytest.raises(ibfe.IbfeError, match="ESINGULAR"):
+        ibfe.Plan(**bad)
