@@ -13,6 +13,7 @@
 #include "ibfe.h"
 #include "plan.hpp"
 #include "step_kernels.hpp"
+#include "zblock.hpp"
 
 using namespace ibfe;
 
@@ -35,11 +36,15 @@ int fail(int code, const std::string& msg) {
 #define CHECK_LAUNCH() HIP_TRY(hipGetLastError())
 
 constexpr uint32_t kFlagPp = 16u;  // pressure unknown: node of P that is not an outlet node
-constexpr int kMaxBlocksRed = 8;   // reduce_last<K> uses K <= 8 partial rows
+constexpr int kMaxRows = 8;        // partial rows per reduction (K <= 8)
+constexpr int kRedBlocks = 2048;   // workgroups of a reducing kernel (8 per CU)
+constexpr int kMaxSweeps = 12;     // refinement sweeps of a mixed-precision solve
+constexpr double kInnerRtol = 1e-4;
 
 enum ScalSlot { kScS1 = 0, kScIB, kScS3, kScS4, kScS1i, kScS3i, kScS4i, kScMisc, kNumScal };
 
 int blocks_for(int nchunks) { return (nchunks + kWaves - 1) / kWaves; }
+int red_blocks(int nchunks) { return std::max(1, std::min(kRedBlocks, blocks_for(nchunks))); }
 int blocks_lin(int64_t n) { return int((n + kBlock - 1) / kBlock); }
 
 }  // namespace
@@ -67,6 +72,8 @@ struct ibfe_ctx {
   int8_t* slot = nullptr;
   int* chunks = nullptr;
   int* ib_chunks = nullptr;
+  int* zitems = nullptr;          // z-blocked column items (plane_block * cpp + chunk)
+  int nzitems = 0, cpp = 0;
   int64_t* pids = nullptr;
   double* float_count = nullptr;
   double* float_means = nullptr;
@@ -100,7 +107,8 @@ struct ibfe_ctx {
 
   // reductions
   double* partials = nullptr;
-  unsigned* counter = nullptr;
+  double* res2 = nullptr;      // refinement residual: r.r, b.b
+  double* host_res2 = nullptr; // pinned
   KScal* scal = nullptr;
   KScal* host_scal = nullptr;  // pinned
 
@@ -121,6 +129,7 @@ struct ibfe_ctx {
         (void)hipFree(b);
     }
     if (host_scal) (void)hipHostFree(host_scal);
+    if (host_res2) (void)hipHostFree(host_res2);
   }
 
   int dalloc(void** out, size_t bytes) {
@@ -191,6 +200,25 @@ int setup_device(ibfe_ctx& c) {
     if (tail > 0) HIP_TRY(hipMemsetAsync(c.slot + P.N, 0xFF, tail, c.stream));
   }
   if ((rc = c.upload(&c.chunks, P.chunks.data(), P.chunks.size()))) return rc;
+  {
+    // column items of the z-blocked applies: kZB planes x 64 in-plane nodes
+    c.cpp = int((P.sz + kChunk - 1) / kChunk);
+    const int nplanes = P.nz + 1, npb = (nplanes + kZB - 1) / kZB;
+    std::vector<int> items;
+    for (int pb = 0; pb < npb; ++pb)
+      for (int ch = 0; ch < c.cpp; ++ch) {
+        bool any = false;
+        for (int k = pb * kZB; k < std::min(nplanes, (pb + 1) * kZB) && !any; ++k)
+          for (int64_t l = int64_t(ch) * kChunk; l < std::min<int64_t>(P.sz, (ch + 1) * int64_t(kChunk)); ++l)
+            if (P.emask[k * P.sz + l]) {
+              any = true;
+              break;
+            }
+        if (any) items.push_back(pb * c.cpp + ch);
+      }
+    c.nzitems = int(items.size());
+    if ((rc = c.upload(&c.zitems, items.data(), items.size()))) return rc;
+  }
   if ((rc = c.upload(&c.pids, P.P_ids.data(), P.P_ids.size()))) return rc;
   {
     std::vector<double> cnt(kMaxFloating, 1.0);
@@ -253,17 +281,17 @@ int setup_device(ibfe_ctx& c) {
   }
   // reductions
   {
-    const int maxb = std::max(blocks_for(c.nchunks), blocks_for(std::max(1, c.ib_nchunks)));
     void* base = nullptr;
-    if ((rc = c.dalloc(&base, sizeof(double) * kMaxBlocksRed * size_t(maxb)))) return rc;
+    if ((rc = c.dalloc(&base, sizeof(double) * kMaxRows * size_t(kRedBlocks)))) return rc;
     c.partials = reinterpret_cast<double*>(base);
     if ((rc = c.dalloc(&base, 256))) return rc;
-    c.counter = reinterpret_cast<unsigned*>(base);
+    c.res2 = reinterpret_cast<double*>(base);
     if ((rc = c.dalloc(&base, sizeof(KScal) * kNumScal))) return rc;
     c.scal = reinterpret_cast<KScal*>(base);
   }
   HIP_TRY(hipHostMalloc((void**)&c.host_scal, sizeof(KScal) * kNumScal, hipHostMallocDefault));
   std::memset(c.host_scal, 0, sizeof(KScal) * kNumScal);
+  HIP_TRY(hipHostMalloc((void**)&c.host_res2, 2 * sizeof(double), hipHostMallocDefault));
   HIP_TRY(hipStreamSynchronize(c.stream));
   return IBFE_OK;
 }
@@ -292,6 +320,7 @@ int finish_status(const KScal& s, const char* what) {
 struct SolveOut {
   int iters = 0;
   double res = 0.0;
+  int outer = 1;  // refinement sweeps (mixed precision)
 };
 
 int next_batch(int est, int done_so_far) {
@@ -299,40 +328,57 @@ int next_batch(int est, int done_so_far) {
   return 8;
 }
 
+// q = A p with partial p.q; returns the number of partials written.
+template <typename T, class Op>
+int launch_q(ibfe_ctx& c, const Op& op, const int* chunks, int nchunks, const T* p, T* q,
+             const KScal* sc) {
+  const int nr = red_blocks(nchunks);
+  hipLaunchKernelGGL((k_cg_q<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, chunks, nchunks, op, p, q,
+                     c.partials, sc);
+  return nr;
+}
+template <typename T, int NC>
+int launch_q(ibfe_ctx& c, const OpSym<T, NC>& op, const int*, int, const T* p, T* q, const KScal* sc) {
+  const int nr = red_blocks(c.nzitems);
+  hipLaunchKernelGGL((k_cg_q_zb<T, NC>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
+                     c.nzitems, c.cpp, c.plan.nz + 1, op, p, q, c.partials, sc);
+  return nr;
+}
+
 template <typename T, class Op>
 int run_cg(ibfe_ctx& c, const Op& op, const int* chunks, int nchunks, const T* b, T* x, T* r, T* p,
            T* q, int slot, double rtol, int max_iters, bool zero_guess, SolveOut& out,
            bool timed = false) {
-  const int nb = blocks_for(nchunks);
+  const int nb = blocks_for(nchunks), nr = red_blocks(nchunks);
   KScal* sc = &c.scal[slot];
-  hipLaunchKernelGGL((k_cg_init<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, chunks, nchunks, op, b,
-                     x, r, p, c.partials, c.counter, sc, zero_guess ? 1 : 0, rtol * rtol, max_iters);
+  hipLaunchKernelGGL((k_cg_init<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, chunks, nchunks, op, b, x,
+                     r, p, c.partials, zero_guess ? 1 : 0);
+  hipLaunchKernelGGL(k_fin_cg_init, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr, sc,
+                     rtol * rtol, max_iters);
   CHECK_LAUNCH();
   int launched = 0;
   KScal s{};
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
   while (true) {
     const int batch = std::min(next_batch(c.est[slot], launched), max_iters + 1 - launched);
     for (int k = 0; k < batch; ++k) {
+      const size_t e = 2 * size_t(launched + k);
       if (timed) {
-        hipEvent_t e0, e1;
-        HIP_TRY(hipEventCreate(&e0));
-        HIP_TRY(hipEventCreate(&e1));
-        HIP_TRY(hipEventRecord(e0, c.stream));
-        hipLaunchKernelGGL((k_cg_q<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, chunks, nchunks, op,
-                           p, q, c.partials, c.counter, sc);
-        HIP_TRY(hipEventRecord(e1, c.stream));
-        evs.push_back({e0, e1});
-      } else {
-        hipLaunchKernelGGL((k_cg_q<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, chunks, nchunks, op,
-                           p, q, c.partials, c.counter, sc);
+        while (c.ev.size() < e + 2) {
+          hipEvent_t ne;
+          HIP_TRY(hipEventCreate(&ne));
+          c.ev.push_back(ne);
+        }
+        HIP_TRY(hipEventRecord(c.ev[e], c.stream));
       }
-      CHECK_LAUNCH();
-      hipLaunchKernelGGL((k_cg_xr<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, chunks, nchunks, op, x,
-                         r, p, q, c.partials, c.counter, sc);
-      CHECK_LAUNCH();
-      hipLaunchKernelGGL((k_cg_p<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, chunks, nchunks, op, r,
-                         p, (const KScal*)sc);
+      const int nq = launch_q<T>(c, op, chunks, nchunks, p, q, (const KScal*)sc);
+      if (timed) HIP_TRY(hipEventRecord(c.ev[e + 1], c.stream));
+      hipLaunchKernelGGL(k_fin_cg_q, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nq, sc);
+      hipLaunchKernelGGL((k_cg_xr<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, chunks, nchunks, op, x, r,
+                         p, q, c.partials, (const KScal*)sc);
+      hipLaunchKernelGGL(k_fin_cg_xr, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr,
+                         sc);
+      hipLaunchKernelGGL((k_cg_p<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, chunks, nchunks, op, r, p,
+                         (const KScal*)sc);
       CHECK_LAUNCH();
     }
     launched += batch;
@@ -341,15 +387,12 @@ int run_cg(ibfe_ctx& c, const Op& op, const int* chunks, int nchunks, const T* b
     if (s.done || launched > max_iters) break;
   }
   if (timed) {
-    for (size_t k = 0; k < evs.size(); ++k) {
-      if (int(k) < s.iters) {
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, evs[k].first, evs[k].second));
-        c.stats.poisson_apply_ms += ms;
-        c.stats.poisson_applies += 1;
-      }
-      (void)hipEventDestroy(evs[k].first);
-      (void)hipEventDestroy(evs[k].second);
+    // launches past convergence return at once; only the s.iters real applies count
+    for (int k = 0; k < s.iters && k < launched; ++k) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, c.ev[2 * k], c.ev[2 * k + 1]));
+      c.stats.poisson_apply_ms += ms;
+      c.stats.poisson_applies += 1;
     }
   }
   c.est[slot] = std::max(1, s.iters);
@@ -361,30 +404,36 @@ int run_cg(ibfe_ctx& c, const Op& op, const int* chunks, int nchunks, const T* b
 template <typename T, class Op>
 int run_bicgstab(ibfe_ctx& c, const Op& op, const T* b, T* x, T* const* wv, int slot, double rtol,
                  int max_iters, SolveOut& out) {
-  const int nb = blocks_for(c.nchunks);
+  const int nb = blocks_for(c.nchunks), nr = red_blocks(c.nchunks);
   const int* ch = c.chunks;
   const int nch = c.nchunks;
+  const double* pa = c.partials;
   T *r = wv[0], *rhat = wv[1], *p = wv[2], *v = wv[3], *phat = wv[4], *s = wv[5], *shat = wv[6],
     *t = wv[7];
   KScal* sc = &c.scal[slot];
-  hipLaunchKernelGGL((k_bi_init<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, ch, nch, op, b, x, r, rhat,
-                     p, v, c.partials, c.counter, sc, rtol * rtol, max_iters);
+  const KScal* csc = sc;
+  hipLaunchKernelGGL((k_bi_init<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, ch, nch, op, b, x, r, rhat, p,
+                     v, c.partials);
+  hipLaunchKernelGGL(k_fin_bi_init, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc, rtol * rtol, max_iters);
   CHECK_LAUNCH();
   int launched = 0;
   KScal st{};
   while (true) {
     const int batch = std::min(next_batch(c.est[slot], launched), max_iters + 1 - launched);
     for (int k = 0; k < batch; ++k) {
-      hipLaunchKernelGGL((k_bi_p<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, ch, nch, op, r, p, v,
-                         phat, (const KScal*)sc);
-      hipLaunchKernelGGL((k_bi_apply<T, Op, 0>), dim3(nb), dim3(kBlock), 0, c.stream, ch, nch, op, phat,
-                         v, rhat, c.partials, c.counter, sc);
-      hipLaunchKernelGGL((k_bi_s<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, ch, nch, op, r, v, s,
-                         shat, (const KScal*)sc);
-      hipLaunchKernelGGL((k_bi_apply<T, Op, 1>), dim3(nb), dim3(kBlock), 0, c.stream, ch, nch, op, shat,
-                         t, s, c.partials, c.counter, sc);
-      hipLaunchKernelGGL((k_bi_x<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, ch, nch, op, x, r, rhat,
-                         phat, shat, s, t, c.partials, c.counter, sc);
+      hipLaunchKernelGGL((k_bi_p<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, ch, nch, op, r, p, v, phat,
+                         csc);
+      hipLaunchKernelGGL((k_bi_apply<T, Op, 0>), dim3(nr), dim3(kBlock), 0, c.stream, ch, nch, op, phat, v,
+                         rhat, c.partials, csc);
+      hipLaunchKernelGGL(k_fin_bi_apply<0>, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc);
+      hipLaunchKernelGGL((k_bi_s<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, ch, nch, op, r, v, s, shat,
+                         csc);
+      hipLaunchKernelGGL((k_bi_apply<T, Op, 1>), dim3(nr), dim3(kBlock), 0, c.stream, ch, nch, op, shat, t,
+                         s, c.partials, csc);
+      hipLaunchKernelGGL(k_fin_bi_apply<1>, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc);
+      hipLaunchKernelGGL((k_bi_x<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, ch, nch, op, x, r, rhat,
+                         phat, shat, s, t, c.partials, csc);
+      hipLaunchKernelGGL(k_fin_bi_x, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc);
       CHECK_LAUNCH();
     }
     launched += batch;
@@ -396,6 +445,63 @@ int run_bicgstab(ibfe_ctx& c, const Op& op, const T* b, T* x, T* const* wv, int 
   out.iters = st.iters;
   out.res = st.bb > 0.0 ? std::sqrt(st.rr / st.bb) : 0.0;
   return finish_status(st, "BiCGStab");
+}
+
+// FP64 residual of the refinement loop: returns |r|^2 and |b|^2 on the host and
+// leaves r in FP32 in r32.
+template <class Op64>
+int ir_residual(ibfe_ctx& c, const Op64& op, const double* b, const double* x, float* r32, double& rr,
+                double& bb) {
+  const int nr = red_blocks(c.nchunks);
+  hipLaunchKernelGGL((k_residual<Op64>), dim3(nr), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, op, b, x,
+                     r32, c.partials);
+  hipLaunchKernelGGL(k_fin_residual, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr,
+                     c.res2);
+  CHECK_LAUNCH();
+  HIP_TRY(hipMemcpyAsync(c.host_res2, c.res2, 2 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  HIP_TRY(hipStreamSynchronize(c.stream));
+  rr = c.host_res2[0];
+  bb = c.host_res2[1];
+  if (!std::isfinite(rr) || !std::isfinite(bb)) return fail(IBFE_ENONFINITE, "refinement residual");
+  return IBFE_OK;
+}
+
+// Mixed-precision solve A x = b: FP64 residuals and updates, FP32 inner Krylov
+// corrections (CG if SPD, else BiCGStab).  x holds the initial guess (zero off rows).
+template <bool SPD, class Op64, class Op32>
+int run_refined(ibfe_ctx& c, const Op64& op64, const Op32& op32, const double* b, double* x, float* const* w32,
+                int slot, double rtol, int max_iters, SolveOut& out, bool timed = false) {
+  const int nb = blocks_for(c.nchunks);
+  float* r32 = w32[8];
+  float* d32 = w32[9];
+  int total = 0;
+  double rr = 0, bb = 0, res = 0;
+  int sweeps = 0;
+  for (; sweeps <= kMaxSweeps; ++sweeps) {
+    int rc = ir_residual(c, op64, b, x, r32, rr, bb);
+    if (rc) return rc;
+    res = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
+    if (res <= rtol || sweeps == kMaxSweeps) break;
+    const double inner = std::min(0.5, std::max(kInnerRtol, 0.5 * rtol / res));
+    SolveOut so;
+    if (SPD)
+      rc = run_cg<float>(c, op32, c.chunks, c.nchunks, (const float*)r32, d32, w32[0], w32[1], w32[2], slot,
+                         inner, max_iters, true, so, timed);
+    else {
+      HIP_TRY(hipMemsetAsync(d32 - c.halo, 0, sizeof(float) * Op32::kNC * c.stride, c.stream));
+      rc = run_bicgstab<float>(c, op32, (const float*)r32, d32, w32, slot, inner, max_iters, so);
+    }
+    total += so.iters;
+    if (rc && rc != IBFE_ENOCONV) return rc;
+    hipLaunchKernelGGL(k_add_correction<float>, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks,
+                       c.flags, op32.rowbit, (const float*)d32, x, Op32::kNC, c.stride);
+    CHECK_LAUNCH();
+  }
+  out.iters = total;
+  out.res = res;
+  out.outer = sweeps;
+  if (res > rtol) return fail(IBFE_ENOCONV, "iterative refinement did not reach the tolerance");
+  return IBFE_OK;
 }
 
 // -------------------------------------------------------------------------
@@ -454,6 +560,19 @@ int build_s1(ibfe_ctx& c) {
   return IBFE_OK;
 }
 
+int remove_slot_means(ibfe_ctx& c, double* x) {
+  const Plan& P = c.plan;
+  const int nr = red_blocks(c.nchunks);
+  hipLaunchKernelGGL(k_slot_sum, dim3(nr), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.slot,
+                     (const double*)x, c.partials);
+  hipLaunchKernelGGL(k_fin_slot, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr,
+                     P.n_floating, (const double*)c.float_count, c.float_means);
+  hipLaunchKernelGGL(k_slot_sub, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks,
+                     c.slot, x, (const double*)c.float_means);
+  CHECK_LAUNCH();
+  return IBFE_OK;
+}
+
 int step_once(ibfe_ctx& c) {
   const Plan& P = c.plan;
   const double rho = P.params.rho, dt = P.params.dt;
@@ -462,8 +581,9 @@ int step_once(ibfe_ctx& c) {
   const int sy = int(P.sy), sz = int(P.sz);
   const int64_t S = c.stride;
   const bool mixed = P.params.precision == 1;
+  const double rtol = P.params.rtol;
+  const int maxit = P.params.max_iters;
   int rc;
-  (void)mixed;
 
   // Dirichlet data g(t^{n+1}) at the inlet table nodes (zero elsewhere)
   if (!P.inlet_ids.empty()) {
@@ -494,17 +614,22 @@ int step_once(ibfe_ctx& c) {
     CHECK_LAUNCH();
     auto op = stencil_op<double>(c, c.coef64, kFlagF);
     SolveOut so;
-    if ((rc = run_bicgstab<double>(c, op, b1, x1, c.w, kScS1, P.params.rtol, P.params.max_iters, so)))
-      return rc;
+    if (mixed) {
+      auto op32 = stencil_op<float>(c, c.coef32, kFlagF);
+      rc = run_refined<false>(c, op, op32, b1, x1, c.v32, kScS1, rtol, maxit, so);
+    } else {
+      rc = run_bicgstab<double>(c, op, b1, x1, c.w, kScS1, rtol, maxit, so);
+    }
+    if (rc) return rc;
     c.stats.s1_iters = so.iters;
     c.stats.s1_res = so.res;
-    c.stats.s1_outer = 1;
+    c.stats.s1_outer = so.outer;
     hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, 1.0, x1, 1.0,
                        c.g, c.ustar, 3, S);
     CHECK_LAUNCH();
   }
 
-  // 2.-4. BCE-IB correction: G Lambda = U_B - I u*, u_ib = u* + I_F^T Lambda
+  // 2.-4. BCE-IB correction: G Lambda = U_B - I u*, u_ib = u* + I_F^T Lambda (FP64)
   hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, 1.0, c.ustar,
                      0.0, c.ustar, c.uib, 3, S);
   CHECK_LAUNCH();
@@ -518,7 +643,7 @@ int step_once(ibfe_ctx& c) {
     auto op = gram_op(c);
     SolveOut so;
     if ((rc = run_cg<double>(c, op, c.ib_chunks, c.ib_nchunks, c.ibv[0], c.ibv[1], c.ibv[2], c.ibv[3],
-                             c.ibv[4], kScIB, P.params.ib_rtol, P.params.max_iters, true, so)))
+                             c.ibv[4], kScIB, P.params.ib_rtol, maxit, true, so)))
       return rc;
     c.stats.ib_iters = so.iters;
     c.stats.ib_res = so.res;
@@ -534,29 +659,23 @@ int step_once(ibfe_ctx& c) {
     hipLaunchKernelGGL(k_div, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.emask, c.flags,
                        kFlagPp, 0u, c.uib, b3, S, sy, sz, c.fc.g2[0], c.fc.g2[1], c.fc.g2[2], -rho / dt);
     CHECK_LAUNCH();
-    if (P.n_floating > 0) {
-      hipLaunchKernelGGL(k_slot_mean, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.slot,
-                         b3, P.n_floating, c.float_count, c.partials, c.counter, c.float_means);
-      hipLaunchKernelGGL(k_slot_sub, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.slot, b3,
-                         c.float_means);
-      CHECK_LAUNCH();
-    }
+    if (P.n_floating > 0 && (rc = remove_slot_means(c, b3))) return rc;
     const double kc[4] = {c.fc.k[0], c.fc.k[1], c.fc.k[2], c.fc.k[3]};
     auto op = sym_op<double, 1>(c, kc, kFlagPp);
     SolveOut so;
-    if ((rc = run_cg<double>(c, op, c.chunks, c.nchunks, b3, c.phi, c.w[0], c.w[1], c.w[2], kScS3,
-                             P.params.rtol, P.params.max_iters, true, so, c.timing)))
-      return rc;
+    if (mixed) {
+      auto op32 = sym_op<float, 1>(c, kc, kFlagPp);
+      HIP_TRY(hipMemsetAsync(c.phi - c.halo, 0, sizeof(double) * S, c.stream));
+      rc = run_refined<true>(c, op, op32, b3, c.phi, c.v32, kScS3, rtol, maxit, so, c.timing);
+    } else {
+      rc = run_cg<double>(c, op, c.chunks, c.nchunks, b3, c.phi, c.w[0], c.w[1], c.w[2], kScS3, rtol, maxit,
+                          true, so, c.timing);
+    }
+    if (rc) return rc;
     c.stats.s3_iters = so.iters;
     c.stats.s3_res = so.res;
-    c.stats.s3_outer = 1;
-    if (P.n_floating > 0) {
-      hipLaunchKernelGGL(k_slot_mean, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.slot,
-                         c.phi, P.n_floating, c.float_count, c.partials, c.counter, c.float_means);
-      hipLaunchKernelGGL(k_slot_sub, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.slot,
-                         c.phi, c.float_means);
-      CHECK_LAUNCH();
-    }
+    c.stats.s3_outer = so.outer;
+    if (P.n_floating > 0 && (rc = remove_slot_means(c, c.phi))) return rc;
   }
 
   // 6. correction: M_FF delta = (G Phi)_F, u^{n+1} = u_ib - (dt/rho) delta, p^{n+1} = p^n + Phi
@@ -569,12 +688,18 @@ int step_once(ibfe_ctx& c) {
     const double mc[4] = {c.fc.m[0], c.fc.m[1], c.fc.m[2], c.fc.m[3]};
     auto op = sym_op<double, 3>(c, mc, kFlagF);
     SolveOut so;
-    if ((rc = run_cg<double>(c, op, c.chunks, c.nchunks, b4, delta, c.w[0], c.w[1], c.w[2], kScS4,
-                             P.params.rtol, P.params.max_iters, true, so)))
-      return rc;
+    if (mixed) {
+      auto op32 = sym_op<float, 3>(c, mc, kFlagF);
+      HIP_TRY(hipMemsetAsync(delta - c.halo, 0, sizeof(double) * 3 * S, c.stream));
+      rc = run_refined<true>(c, op, op32, b4, delta, c.v32, kScS4, rtol, maxit, so);
+    } else {
+      rc = run_cg<double>(c, op, c.chunks, c.nchunks, b4, delta, c.w[0], c.w[1], c.w[2], kScS4, rtol, maxit,
+                          true, so);
+    }
+    if (rc) return rc;
     c.stats.s4_iters = so.iters;
     c.stats.s4_res = so.res;
-    c.stats.s4_outer = 1;
+    c.stats.s4_outer = so.outer;
     hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, 1.0, c.uib,
                        -dt / rho, delta, c.u_next, 3, S);
     hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, 1.0, c.p, 1.0,

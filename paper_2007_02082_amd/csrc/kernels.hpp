@@ -29,8 +29,8 @@ constexpr int kWaves = kBlock / 64;
 // ---------------------------------------------------------------------------
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
-// L2).  Remap so that XCD x processes one contiguous range of chunks: the
-// stencil's neighbour rows are then reused from that XCD's L2.
+// L2).  Remap so that XCD x runs a contiguous range of logical blocks: a
+// block's neighbour rows are then mostly reused from that XCD's L2.
 __device__ __forceinline__ int xcd_block() {
   const int B = gridDim.x, b = blockIdx.x;
   const int xcd = b & 7, idx = b >> 3;
@@ -38,15 +38,29 @@ __device__ __forceinline__ int xcd_block() {
   return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
 }
 
-// Node handled by this thread, or -1.
+// Contiguous range of chunks [c0, c1) owned by this block; each wavefront
+// walks it with stride kWaves (one 64-node chunk per wavefront per trip).
+struct ChunkRange {
+  int c0, c1;
+};
+__device__ __forceinline__ ChunkRange block_chunks(int nchunks) {
+  const int b = xcd_block(), B = gridDim.x;
+  const int per = nchunks / B, rem = nchunks % B;
+  const int c0 = b * per + (b < rem ? b : rem);
+  return {c0, c0 + per + (b < rem ? 1 : 0)};
+}
+
+// Node of the one-node-per-thread kernels (grid = ceil(nchunks / kWaves)), or -1.
 __device__ __forceinline__ int chunk_node(const int* __restrict__ chunks, int nchunks) {
-  const int c = xcd_block() * kWaves + (threadIdx.x >> 6);
+  const int c = xcd_block() * kWaves + int(threadIdx.x >> 6);
   if (c >= nchunks) return -1;
-  return chunks[c] * 64 + (threadIdx.x & 63);
+  return chunks[c] * 64 + int(threadIdx.x & 63);
 }
 
 // ---------------------------------------------------------------------------
-// deterministic block reductions (FP64)
+// deterministic FP64 reductions: every reducing kernel writes one partial per
+// block (plain stores; the kernel boundary publishes them) and a one-block
+// finalize kernel sums them in a fixed order.  No atomics, no fences.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -55,16 +69,11 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Reduce K per-thread values over the block; writes partials[k * nb + blockIdx.x]
-// and returns true in the block that arrived last (which then holds the full
-// sums in `tot`, reduced in a fixed order independent of arrival order).
+// Block sum of K values; thread 0 stores partials[k * gridDim.x + blockIdx.x].
 template <int K>
-__device__ bool reduce_last(double (&v)[K], double* __restrict__ partials,
-                            unsigned* __restrict__ counter, double (&tot)[K]) {
+__device__ __forceinline__ void block_partials(double (&v)[K], double* __restrict__ partials) {
   __shared__ double sh[K][kWaves];
-  __shared__ bool last;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nb = gridDim.x;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     double s = wave_sum(v[k]);
@@ -75,30 +84,34 @@ __device__ bool reduce_last(double (&v)[K], double* __restrict__ partials,
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       double s = 0.0;
+#pragma unroll
       for (int w = 0; w < kWaves; ++w) s += sh[k][w];
-      partials[k * nb + blockIdx.x] = s;
+      partials[k * gridDim.x + blockIdx.x] = s;
     }
-    __threadfence();
-    unsigned ticket = atomicAdd(counter, 1u);
-    last = (ticket == unsigned(nb - 1));
   }
-  __syncthreads();
-  if (!last) return false;
-  __threadfence();
+}
+
+// One-block sum of K rows of nb partials (fixed order); result valid in thread 0.
+template <int K>
+__device__ __forceinline__ void sum_partials(const double* __restrict__ partials, int nb,
+                                             double (&tot)[K]) {
+  __shared__ double sh[K][kWaves];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += kBlock) s += __builtin_nontemporal_load(&partials[k * nb + b]);
+    for (int b = threadIdx.x; b < nb; b += kBlock) s += partials[k * nb + b];
     s = wave_sum(s);
-    __syncthreads();
     if (lane == 0) sh[k][wave] = s;
-    __syncthreads();
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
     double t = 0.0;
+#pragma unroll
     for (int w = 0; w < kWaves; ++w) t += sh[k][w];
     tot[k] = t;
   }
-  if (threadIdx.x == 0) *counter = 0u;
-  return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -257,8 +270,8 @@ struct OpCSR {
 };
 
 // ---------------------------------------------------------------------------
-// Krylov scalar state (device resident; updated by the last block of each
-// reducing kernel so that no host round trip is needed between kernels)
+// Krylov scalar state (device resident; updated by one-block finalize kernels
+// so that no host round trip is needed between kernels)
 // ---------------------------------------------------------------------------
 
 struct KScal {
@@ -270,20 +283,20 @@ struct KScal {
 __device__ __forceinline__ bool bad(double v) { return !(v == v) || v - v != 0.0; }
 
 // ---------------------------------------------------------------------------
-// CG kernels (Jacobi preconditioned): x, r, p, q are NC-plane vectors
+// CG (Jacobi preconditioned): x, r, p, q are NC-plane vectors
 // ---------------------------------------------------------------------------
 
-// r = b - A x; p = D^-1 r; rz = r.p, rr = r.r, bb = b.b
+// r = b - A x (x = 0 if zero_guess); p = D^-1 r; partials: r.p, r.r, b.b
 template <typename T, class Op>
 __global__ __launch_bounds__(kBlock) void k_cg_init(const int* __restrict__ chunks, int nchunks,
                                                     Op op, const T* __restrict__ b, T* __restrict__ x,
                                                     T* __restrict__ r, T* __restrict__ p,
-                                                    double* partials, unsigned* counter, KScal* sc,
-                                                    int zero_guess, double tol2, int max_iters) {
+                                                    double* __restrict__ partials, int zero_guess) {
   constexpr int NC = Op::kNC;
   double v[3] = {0.0, 0.0, 0.0};
-  const int n = chunk_node(chunks, nchunks);
-  if (n >= 0) {
+  const ChunkRange cr = block_chunks(nchunks);
+  for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
+    const int n = chunks[c] * 64 + int(threadIdx.x & 63);
     const bool rw = op.row(n);
     T ax[NC];
     if (!zero_guess && rw) op.apply(n, x, ax);
@@ -302,33 +315,39 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(const int* __restrict__ chun
       v[2] += double(bi) * double(bi);
     }
   }
+  block_partials<3>(v, partials);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fin_cg_init(const double* __restrict__ partials, int nb,
+                                                        KScal* sc, double tol2, int max_iters) {
   double tot[3];
-  if (reduce_last<3>(v, partials, counter, tot) && threadIdx.x == 0) {
-    sc->tol2 = tol2;
-    sc->max_iters = max_iters;
-    sc->rz = tot[0];
-    sc->rr = tot[1];
-    sc->bb = tot[2];
-    sc->iters = 0;
-    sc->status = 0;
-    sc->done = (tot[1] <= tol2 * tot[2]) ? 1 : 0;
-    if (bad(tot[0]) || bad(tot[1]) || bad(tot[2])) {
-      sc->status = 2;
-      sc->done = 1;
-    }
+  sum_partials<3>(partials, nb, tot);
+  if (threadIdx.x != 0) return;
+  sc->tol2 = tol2;
+  sc->max_iters = max_iters;
+  sc->rz = tot[0];
+  sc->rr = tot[1];
+  sc->bb = tot[2];
+  sc->iters = 0;
+  sc->status = 0;
+  sc->done = (tot[1] <= tol2 * tot[2]) ? 1 : 0;
+  if (bad(tot[0]) || bad(tot[1]) || bad(tot[2])) {
+    sc->status = 2;
+    sc->done = 1;
   }
 }
 
-// q = A p; alpha = rz / (p . q)
+// q = A p; partial p.q
 template <typename T, class Op>
 __global__ __launch_bounds__(kBlock) void k_cg_q(const int* __restrict__ chunks, int nchunks, Op op,
                                                  const T* __restrict__ p, T* __restrict__ q,
-                                                 double* partials, unsigned* counter, KScal* sc) {
+                                                 double* __restrict__ partials, const KScal* sc) {
   if (sc->done) return;
   constexpr int NC = Op::kNC;
   double v[1] = {0.0};
-  const int n = chunk_node(chunks, nchunks);
-  if (n >= 0) {
+  const ChunkRange cr = block_chunks(nchunks);
+  for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
+    const int n = chunks[c] * 64 + int(threadIdx.x & 63);
     T y[NC];
     const bool rw = op.row(n);
     if (rw) op.apply(n, p, y);
@@ -340,55 +359,72 @@ __global__ __launch_bounds__(kBlock) void k_cg_q(const int* __restrict__ chunks,
       v[0] += double(p[i]) * double(qi);
     }
   }
+  block_partials<1>(v, partials);
+}
+
+// alpha = rz / p.q
+__global__ __launch_bounds__(kBlock) void k_fin_cg_q(const double* __restrict__ partials, int nb,
+                                                     KScal* sc) {
+  if (sc->done) return;
   double tot[1];
-  if (reduce_last<1>(v, partials, counter, tot) && threadIdx.x == 0) {
-    const double pq = tot[0];
-    if (!(pq > 0.0) || bad(pq)) {
-      sc->status = bad(pq) ? 2 : 1;
-      sc->done = 1;
-      sc->alpha = 0.0;
-    } else {
-      sc->alpha = sc->rz / pq;
-    }
+  sum_partials<1>(partials, nb, tot);
+  if (threadIdx.x != 0) return;
+  const double pq = tot[0];
+  if (!(pq > 0.0) || bad(pq)) {
+    sc->status = bad(pq) ? 2 : 1;
+    sc->done = 1;
+    sc->alpha = 0.0;
+  } else {
+    sc->alpha = sc->rz / pq;
   }
 }
 
-// x += alpha p; r -= alpha q; rz = r.D^-1 r; rr = r.r; beta = rz_new / rz
+// x += alpha p; r -= alpha q; partials r.D^-1 r, r.r
 template <typename T, class Op>
 __global__ __launch_bounds__(kBlock) void k_cg_xr(const int* __restrict__ chunks, int nchunks, Op op,
                                                   T* __restrict__ x, T* __restrict__ r,
                                                   const T* __restrict__ p, const T* __restrict__ q,
-                                                  double* partials, unsigned* counter, KScal* sc) {
+                                                  double* __restrict__ partials, const KScal* sc) {
   if (sc->done) return;
   constexpr int NC = Op::kNC;
   const T alpha = T(sc->alpha);
   double v[2] = {0.0, 0.0};
-  const int n = chunk_node(chunks, nchunks);
-  if (n >= 0 && op.row(n)) {
-    const T di = op.inv_diag(n);
+  const ChunkRange cr = block_chunks(nchunks);
+  for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
+    const int n = chunks[c] * 64 + int(threadIdx.x & 63);
+    if (op.row(n)) {
+      const T di = op.inv_diag(n);
 #pragma unroll
-    for (int d = 0; d < NC; ++d) {
-      const int64_t i = d * op.stride + n;
-      x[i] += alpha * p[i];
-      const T ri = r[i] - alpha * q[i];
-      r[i] = ri;
-      v[0] += double(ri) * double(ri * di);
-      v[1] += double(ri) * double(ri);
+      for (int d = 0; d < NC; ++d) {
+        const int64_t i = d * op.stride + n;
+        x[i] += alpha * p[i];
+        const T ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        v[0] += double(ri) * double(ri * di);
+        v[1] += double(ri) * double(ri);
+      }
     }
   }
+  block_partials<2>(v, partials);
+}
+
+// beta = rz_new / rz; convergence test on |r|^2 <= tol2 |b|^2
+__global__ __launch_bounds__(kBlock) void k_fin_cg_xr(const double* __restrict__ partials, int nb,
+                                                      KScal* sc) {
+  if (sc->done) return;
   double tot[2];
-  if (reduce_last<2>(v, partials, counter, tot) && threadIdx.x == 0) {
-    const double rz_new = tot[0];
-    sc->beta = rz_new / sc->rz;
-    sc->rz = rz_new;
-    sc->rr = tot[1];
-    sc->iters += 1;
-    if (bad(rz_new) || bad(tot[1])) {
-      sc->status = 2;
-      sc->done = 1;
-    } else if (tot[1] <= sc->tol2 * sc->bb || sc->iters >= sc->max_iters) {
-      sc->done = 1;
-    }
+  sum_partials<2>(partials, nb, tot);
+  if (threadIdx.x != 0) return;
+  const double rz_new = tot[0];
+  sc->beta = rz_new / sc->rz;
+  sc->rz = rz_new;
+  sc->rr = tot[1];
+  sc->iters += 1;
+  if (bad(rz_new) || bad(tot[1])) {
+    sc->status = 2;
+    sc->done = 1;
+  } else if (tot[1] <= sc->tol2 * sc->bb || sc->iters >= sc->max_iters) {
+    sc->done = 1;
   }
 }
 
@@ -400,33 +436,36 @@ __global__ __launch_bounds__(kBlock) void k_cg_p(const int* __restrict__ chunks,
   if (sc->done) return;
   constexpr int NC = Op::kNC;
   const T beta = T(sc->beta);
-  const int n = chunk_node(chunks, nchunks);
-  if (n >= 0 && op.row(n)) {
-    const T di = op.inv_diag(n);
+  const ChunkRange cr = block_chunks(nchunks);
+  for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
+    const int n = chunks[c] * 64 + int(threadIdx.x & 63);
+    if (op.row(n)) {
+      const T di = op.inv_diag(n);
 #pragma unroll
-    for (int d = 0; d < NC; ++d) {
-      const int64_t i = d * op.stride + n;
-      p[i] = r[i] * di + beta * p[i];
+      for (int d = 0; d < NC; ++d) {
+        const int64_t i = d * op.stride + n;
+        p[i] = r[i] * di + beta * p[i];
+      }
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// BiCGStab kernels (right Jacobi preconditioning), NC-plane vectors
+// BiCGStab (right Jacobi preconditioning), NC-plane vectors
 // ---------------------------------------------------------------------------
 
-// r = b - A x, rhat = r, p = v = 0; rho = rr = r.r, bb = b.b
+// r = b - A x, rhat = r, p = v = 0; partials r.r, b.b
 template <typename T, class Op>
 __global__ __launch_bounds__(kBlock) void k_bi_init(const int* __restrict__ chunks, int nchunks, Op op,
                                                     const T* __restrict__ b, const T* __restrict__ x,
                                                     T* __restrict__ r, T* __restrict__ rhat,
                                                     T* __restrict__ p, T* __restrict__ v,
-                                                    double* partials, unsigned* counter, KScal* sc,
-                                                    double tol2, int max_iters) {
+                                                    double* __restrict__ partials) {
   constexpr int NC = Op::kNC;
   double s[2] = {0.0, 0.0};
-  const int n = chunk_node(chunks, nchunks);
-  if (n >= 0) {
+  const ChunkRange cr = block_chunks(nchunks);
+  for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
+    const int n = chunks[c] * 64 + int(threadIdx.x & 63);
     const bool rw = op.row(n);
     T ax[NC];
     if (rw) op.apply(n, x, ax);
@@ -443,23 +482,28 @@ __global__ __launch_bounds__(kBlock) void k_bi_init(const int* __restrict__ chun
       s[1] += double(bi) * double(bi);
     }
   }
+  block_partials<2>(s, partials);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fin_bi_init(const double* __restrict__ partials, int nb,
+                                                        KScal* sc, double tol2, int max_iters) {
   double tot[2];
-  if (reduce_last<2>(s, partials, counter, tot) && threadIdx.x == 0) {
-    sc->tol2 = tol2;
-    sc->max_iters = max_iters;
-    sc->rho = tot[0];
-    sc->rr = tot[0];
-    sc->bb = tot[1];
-    sc->rho_old = 1.0;
-    sc->alpha = 1.0;
-    sc->omega = 1.0;
-    sc->iters = 0;
-    sc->status = 0;
-    sc->done = (tot[0] <= tol2 * tot[1]) ? 1 : 0;
-    if (bad(tot[0]) || bad(tot[1])) {
-      sc->status = 2;
-      sc->done = 1;
-    }
+  sum_partials<2>(partials, nb, tot);
+  if (threadIdx.x != 0) return;
+  sc->tol2 = tol2;
+  sc->max_iters = max_iters;
+  sc->rho = tot[0];
+  sc->rr = tot[0];
+  sc->bb = tot[1];
+  sc->rho_old = 1.0;
+  sc->alpha = 1.0;
+  sc->omega = 1.0;
+  sc->iters = 0;
+  sc->status = 0;
+  sc->done = (tot[0] <= tol2 * tot[1]) ? 1 : 0;
+  if (bad(tot[0]) || bad(tot[1])) {
+    sc->status = 2;
+    sc->done = 1;
   }
 }
 
@@ -473,34 +517,37 @@ __global__ __launch_bounds__(kBlock) void k_bi_p(const int* __restrict__ chunks,
   constexpr int NC = Op::kNC;
   const T beta = T((sc->rho / sc->rho_old) * (sc->alpha / sc->omega));
   const T omega = T(sc->omega);
-  const int n = chunk_node(chunks, nchunks);
-  if (n >= 0 && op.row(n)) {
-    const T di = op.inv_diag(n);
+  const ChunkRange cr = block_chunks(nchunks);
+  for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
+    const int n = chunks[c] * 64 + int(threadIdx.x & 63);
+    if (op.row(n)) {
+      const T di = op.inv_diag(n);
 #pragma unroll
-    for (int d = 0; d < NC; ++d) {
-      const int64_t i = d * op.stride + n;
-      const T pi = r[i] + beta * (p[i] - omega * v[i]);
-      p[i] = pi;
-      phat[i] = pi * di;
+      for (int d = 0; d < NC; ++d) {
+        const int64_t i = d * op.stride + n;
+        const T pi = r[i] + beta * (p[i] - omega * v[i]);
+        p[i] = pi;
+        phat[i] = pi * di;
+      }
+    } else {
+#pragma unroll
+      for (int d = 0; d < NC; ++d) phat[d * op.stride + n] = T(0);
     }
-  } else if (n >= 0) {
-#pragma unroll
-    for (int d = 0; d < NC; ++d) phat[d * op.stride + n] = T(0);
   }
 }
 
-// y = A xin; reduce rhat.y (mode 0: alpha = rho / rhat.v) or
-// (t.s, t.t) (mode 1: omega = t.s / t.t)
+// y = A xin; partials w.y (and y.y for MODE 1)
 template <typename T, class Op, int MODE>
 __global__ __launch_bounds__(kBlock) void k_bi_apply(const int* __restrict__ chunks, int nchunks, Op op,
                                                      const T* __restrict__ xin, T* __restrict__ y,
-                                                     const T* __restrict__ w, double* partials,
-                                                     unsigned* counter, KScal* sc) {
+                                                     const T* __restrict__ w,
+                                                     double* __restrict__ partials, const KScal* sc) {
   if (sc->done) return;
   constexpr int NC = Op::kNC;
   double s[2] = {0.0, 0.0};
-  const int n = chunk_node(chunks, nchunks);
-  if (n >= 0) {
+  const ChunkRange cr = block_chunks(nchunks);
+  for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
+    const int n = chunks[c] * 64 + int(threadIdx.x & 63);
     const bool rw = op.row(n);
     T ay[NC];
     if (rw) op.apply(n, xin, ay);
@@ -513,25 +560,33 @@ __global__ __launch_bounds__(kBlock) void k_bi_apply(const int* __restrict__ chu
       if (MODE == 1) s[1] += double(yi) * double(yi);
     }
   }
+  block_partials<2>(s, partials);
+}
+
+// MODE 0: alpha = rho / rhat.v;  MODE 1: omega = t.s / t.t
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_fin_bi_apply(const double* __restrict__ partials, int nb,
+                                                         KScal* sc) {
+  if (sc->done) return;
   double tot[2];
-  if (reduce_last<2>(s, partials, counter, tot) && threadIdx.x == 0) {
-    if (MODE == 0) {
-      sc->rv = tot[0];
-      if (tot[0] == 0.0 || bad(tot[0])) {
-        sc->status = bad(tot[0]) ? 2 : 1;
-        sc->done = 1;
-      } else {
-        sc->alpha = sc->rho / tot[0];
-      }
+  sum_partials<2>(partials, nb, tot);
+  if (threadIdx.x != 0) return;
+  if (MODE == 0) {
+    sc->rv = tot[0];
+    if (tot[0] == 0.0 || bad(tot[0])) {
+      sc->status = bad(tot[0]) ? 2 : 1;
+      sc->done = 1;
     } else {
-      sc->ts = tot[0];
-      sc->tt = tot[1];
-      if (bad(tot[0]) || bad(tot[1])) {
-        sc->status = 2;
-        sc->done = 1;
-      } else {
-        sc->omega = tot[1] > 0.0 ? tot[0] / tot[1] : 0.0;
-      }
+      sc->alpha = sc->rho / tot[0];
+    }
+  } else {
+    sc->ts = tot[0];
+    sc->tt = tot[1];
+    if (bad(tot[0]) || bad(tot[1])) {
+      sc->status = 2;
+      sc->done = 1;
+    } else {
+      sc->omega = tot[1] > 0.0 ? tot[0] / tot[1] : 0.0;
     }
   }
 }
@@ -545,65 +600,118 @@ __global__ __launch_bounds__(kBlock) void k_bi_s(const int* __restrict__ chunks,
   if (sc->done) return;
   constexpr int NC = Op::kNC;
   const T alpha = T(sc->alpha);
-  const int n = chunk_node(chunks, nchunks);
-  if (n >= 0 && op.row(n)) {
-    const T di = op.inv_diag(n);
+  const ChunkRange cr = block_chunks(nchunks);
+  for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
+    const int n = chunks[c] * 64 + int(threadIdx.x & 63);
+    if (op.row(n)) {
+      const T di = op.inv_diag(n);
 #pragma unroll
-    for (int d = 0; d < NC; ++d) {
-      const int64_t i = d * op.stride + n;
-      const T si = r[i] - alpha * v[i];
-      s[i] = si;
-      shat[i] = si * di;
-    }
-  } else if (n >= 0) {
+      for (int d = 0; d < NC; ++d) {
+        const int64_t i = d * op.stride + n;
+        const T si = r[i] - alpha * v[i];
+        s[i] = si;
+        shat[i] = si * di;
+      }
+    } else {
 #pragma unroll
-    for (int d = 0; d < NC; ++d) {
-      s[d * op.stride + n] = T(0);
-      shat[d * op.stride + n] = T(0);
+      for (int d = 0; d < NC; ++d) {
+        s[d * op.stride + n] = T(0);
+        shat[d * op.stride + n] = T(0);
+      }
     }
   }
 }
 
-// x += alpha phat + omega shat; r = s - omega t; rho = rhat.r; rr = r.r
+// x += alpha phat + omega shat; r = s - omega t; partials rhat.r, r.r
 template <typename T, class Op>
 __global__ __launch_bounds__(kBlock) void k_bi_x(const int* __restrict__ chunks, int nchunks, Op op,
                                                  T* __restrict__ x, T* __restrict__ r,
                                                  const T* __restrict__ rhat, const T* __restrict__ phat,
                                                  const T* __restrict__ shat, const T* __restrict__ s,
-                                                 const T* __restrict__ t, double* partials,
-                                                 unsigned* counter, KScal* sc) {
+                                                 const T* __restrict__ t, double* __restrict__ partials,
+                                                 const KScal* sc) {
   if (sc->done) return;
   constexpr int NC = Op::kNC;
   const T alpha = T(sc->alpha), omega = T(sc->omega);
   double v[2] = {0.0, 0.0};
-  const int n = chunk_node(chunks, nchunks);
-  if (n >= 0 && op.row(n)) {
+  const ChunkRange cr = block_chunks(nchunks);
+  for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
+    const int n = chunks[c] * 64 + int(threadIdx.x & 63);
+    if (op.row(n)) {
+#pragma unroll
+      for (int d = 0; d < NC; ++d) {
+        const int64_t i = d * op.stride + n;
+        x[i] += alpha * phat[i] + omega * shat[i];
+        const T ri = s[i] - omega * t[i];
+        r[i] = ri;
+        v[0] += double(rhat[i]) * double(ri);
+        v[1] += double(ri) * double(ri);
+      }
+    }
+  }
+  block_partials<2>(v, partials);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fin_bi_x(const double* __restrict__ partials, int nb,
+                                                     KScal* sc) {
+  if (sc->done) return;
+  double tot[2];
+  sum_partials<2>(partials, nb, tot);
+  if (threadIdx.x != 0) return;
+  sc->rho_old = sc->rho;
+  sc->rho = tot[0];
+  sc->rr = tot[1];
+  sc->iters += 1;
+  if (bad(tot[0]) || bad(tot[1])) {
+    sc->status = 2;
+    sc->done = 1;
+  } else if (tot[1] <= sc->tol2 * sc->bb || sc->iters >= sc->max_iters) {
+    sc->done = 1;
+  } else if (sc->omega == 0.0 || tot[0] == 0.0) {
+    sc->status = 1;
+    sc->done = 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// iterative refinement: FP64 residual r = b - A x on rows, its FP32 copy, and
+// partials r.r, b.b
+// ---------------------------------------------------------------------------
+template <class Op>
+__global__ __launch_bounds__(kBlock) void k_residual(const int* __restrict__ chunks, int nchunks, Op op,
+                                                     const double* __restrict__ b,
+                                                     const double* __restrict__ x,
+                                                     float* __restrict__ r32,
+                                                     double* __restrict__ partials) {
+  constexpr int NC = Op::kNC;
+  double v[2] = {0.0, 0.0};
+  const ChunkRange cr = block_chunks(nchunks);
+  for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
+    const int n = chunks[c] * 64 + int(threadIdx.x & 63);
+    const bool rw = op.row(n);
+    double ax[NC];
+    if (rw) op.apply(n, x, ax);
 #pragma unroll
     for (int d = 0; d < NC; ++d) {
       const int64_t i = d * op.stride + n;
-      x[i] += alpha * phat[i] + omega * shat[i];
-      const T ri = s[i] - omega * t[i];
-      r[i] = ri;
-      v[0] += double(rhat[i]) * double(ri);
-      v[1] += double(ri) * double(ri);
+      const double bi = rw ? b[i] : 0.0;
+      const double ri = rw ? bi - ax[d] : 0.0;
+      r32[i] = float(ri);
+      v[0] += ri * ri;
+      v[1] += bi * bi;
     }
   }
+  block_partials<2>(v, partials);
+}
+
+// out[0] = r.r, out[1] = b.b of the refinement residual
+__global__ __launch_bounds__(kBlock) void k_fin_residual(const double* __restrict__ partials, int nb,
+                                                         double* __restrict__ out) {
   double tot[2];
-  if (reduce_last<2>(v, partials, counter, tot) && threadIdx.x == 0) {
-    sc->rho_old = sc->rho;
-    sc->rho = tot[0];
-    sc->rr = tot[1];
-    sc->iters += 1;
-    if (bad(tot[0]) || bad(tot[1])) {
-      sc->status = 2;
-      sc->done = 1;
-    } else if (tot[1] <= sc->tol2 * sc->bb || sc->iters >= sc->max_iters) {
-      sc->done = 1;
-    } else if (sc->omega == 0.0 || tot[0] == 0.0) {
-      sc->status = 1;
-      sc->done = 1;
-    }
-  }
+  sum_partials<2>(partials, nb, tot);
+  if (threadIdx.x != 0) return;
+  out[0] = tot[0];
+  out[1] = tot[1];
 }
 
 }  // namespace ibfe

@@ -341,26 +341,30 @@ __global__ __launch_bounds__(kBlock) void k_gather(int64_t n, const int64_t* __r
   for (int d = 0; d < nc; ++d) comp[d * n + q] = dense[d * stride + ids[q]];
 }
 
-// Per-slot sums over nodes of outlet-less parts (slot >= 0); the last block
-// stores sums[s] / count[s] into means[s].
-__global__ __launch_bounds__(kBlock) void k_slot_mean(const int* __restrict__ chunks, int nchunks,
-                                                      const int8_t* __restrict__ slot,
-                                                      const double* __restrict__ x, int nslots,
-                                                      const double* __restrict__ count,
-                                                      double* partials, unsigned* counter,
-                                                      double* __restrict__ means) {
+// Per-slot partial sums over nodes of outlet-less parts (slot >= 0), then a
+// one-block finalize that stores means[s] = sum_s / count_s.
+__global__ __launch_bounds__(kBlock) void k_slot_sum(const int* __restrict__ chunks, int nchunks,
+                                                     const int8_t* __restrict__ slot,
+                                                     const double* __restrict__ x,
+                                                     double* __restrict__ partials) {
   double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  const int n = chunk_node(chunks, nchunks);
-  if (n >= 0) {
+  const ChunkRange cr = block_chunks(nchunks);
+  for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
+    const int n = chunks[c] * 64 + int(threadIdx.x & 63);
     const int s = slot[n];
 #pragma unroll
     for (int k = 0; k < 8; ++k)
-      if (s == k) v[k] = x[n];
+      if (s == k) v[k] += x[n];
   }
+  block_partials<8>(v, partials);
+}
+__global__ __launch_bounds__(kBlock) void k_fin_slot(const double* __restrict__ partials, int nb,
+                                                     int nslots, const double* __restrict__ count,
+                                                     double* __restrict__ means) {
   double tot[8];
-  if (reduce_last<8>(v, partials, counter, tot) && threadIdx.x == 0) {
-    for (int k = 0; k < nslots; ++k) means[k] = tot[k] / count[k];
-  }
+  sum_partials<8>(partials, nb, tot);
+  if (threadIdx.x != 0) return;
+  for (int k = 0; k < nslots; ++k) means[k] = tot[k] / count[k];
 }
 __global__ __launch_bounds__(kBlock) void k_slot_sub(const int* __restrict__ chunks, int nchunks,
                                                      const int8_t* __restrict__ slot,

@@ -227,3 +227,29 @@ def test_full_size_steps_fp64_properties(c2):
         assert d_new < 0.5 * d_ib
         assert st["s3_res"] <= 1e-13 and st["s1_res"] <= 1e-13 and st["s4_res"] <= 1e-13
     s.close()
+
+
+# ---------------------------------------------------------------------------
+# mixed precision: FP32 inner solves inside FP64 refinement, 1e-6 relative L2
+# ---------------------------------------------------------------------------
+
+TOL_MIXED = 1e-6
+
+
+@pytest.mark.parametrize("make", [lambda: synth.random_blob_case(seed=1),
+                                  lambda: synth.small_cylinder(8, 16, pulsatile=True, nsteps=3),
+                                  lambda: synth.closed_box(6)])
+def test_step_parity_mixed_small(make):
+    case = make()
+    say("case", case.name, "mixed precision")
+    _, out = run_pair(case, 3, precision=1)
+    _check_steps(out, TOL_MIXED, case.name + "/mixed")
+
+
+def test_step_parity_mixed_poiseuille_16x16x64():
+    case = synth.poiseuille_c1()
+    say("case", case.name, "mixed precision, 20 steps")
+    _, out = run_pair(case, case.nsteps, precision=1)
+    _check_steps(out, TOL_MIXED, case.name + "/mixed")
+    st = out[-1]["stats"]
+    assert st["s3_outer"] >= 1 and st["s3_res"] <= 1e-8
