@@ -23,6 +23,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+CSRC = os.path.join(ROOT, "paper_2007_02082_amd", "csrc")
+
+
+def counted_traffic(precision: str):
+    """HBM bytes per dispatch of the pressure apply from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a copy of known size), or None when the
+    kernel sources changed after the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"pressure_apply_traffic_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for name in ("kernels.hpp", "zblock.hpp"):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return rec["traffic_bytes"] if h.hexdigest()[:16] == rec["source_hash"] else None
 METRIC = "IPCS steps/sec + apply HBM GB/s at 1e-6 rel; served solves/sec, p50/p99"
 
 
@@ -64,9 +83,14 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--precond", choices=["mg", "jacobi"], default="mg",
+                    help="pressure preconditioner: geometric multigrid or Jacobi")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", action="store_true",
                     help="also run the same steps in FP64 mode and report the difference")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="after the run, copy a device buffer of this size 5 times (a plain copy "
+                         "kernel of known size for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the boxes have one GPU); --gpus {args.gpus} "
@@ -82,7 +106,8 @@ def main() -> int:
     torch.cuda.set_device(0)
     case = synth.pulsatile_c2()
     prec = 1 if args.precision == "mixed" else 0
-    s = ibfe.Solver(**ibfe.inputs_from_case(case, precision=prec))
+    pc = 2 if args.precond == "mg" else 0
+    s = ibfe.Solver(**ibfe.inputs_from_case(case, precision=prec, precond=pc))
     n = s.n_u
     u0 = np.zeros(3 * n)
     p0 = np.zeros(n)
@@ -104,16 +129,19 @@ def main() -> int:
     alg_bytes = (2 * bytes_per_value + 0.125) * n_p
     avg_ms = st["poisson_apply_ms"] / max(1, st["poisson_applies"])
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    traffic = counted_traffic(args.precision) if pc == 2 else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_cg_q<OpSym stiffness>", "avg_us": round(avg_ms * 1e3, 3),
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": round(traffic) if traffic else None,
+            "kernel": "k_cg_q_zb<%s,1> (masked Q1 stiffness apply + p.q)" % (
+                "float" if prec == 1 else "double"), "avg_us": round(avg_ms * 1e3, 3),
             "launches": st["poisson_applies"], "alg_bytes_per_launch": int(alg_bytes)}
 
     extra = {"iters_last_step": {k: st[k] for k in ("s1_iters", "ib_iters", "s3_iters", "s4_iters",
                                                       "s1_outer", "s3_outer", "s4_outer")}}
     if args.check:
         u_a, p_a, _ = s.get_state()
-        ref = ibfe.Solver(**ibfe.inputs_from_case(case, precision=0))
+        ref = ibfe.Solver(**ibfe.inputs_from_case(case, precision=0, precond=pc))
         ref.set_state(u0, p0, 0.0)
         ref.step(args.warmup + args.steps)
         u_b, p_b, _ = ref.get_state()
@@ -121,6 +149,14 @@ def main() -> int:
                                    "p": float(np.linalg.norm(p_a - p_b) / np.linalg.norm(p_b))}
         ref.close()
     s.close()
+    if args.copy_calibration_mib > 0:
+        nbytes = args.copy_calibration_mib << 20
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     out = {
         "metric": METRIC, "value": round(args.steps / elapsed, 3), "unit": "steps/s", "n_gpus": 1,
@@ -129,7 +165,7 @@ def main() -> int:
         "dtype": "f32-inner/f64-outer" if prec == 1 else "f64", "data": "synthetic",
         "config": {"workload": case.name, "grid": [case.nx, case.ny, case.nz], "n_nodes": case.N,
                    "n_active": n_p, "lagrangian_points": case.M, "dt": case.dt,
-                   "precision": args.precision},
+                   "precision": args.precision, "pressure_preconditioner": args.precond},
         "roofline": roof,
     }
     out.update(extra)

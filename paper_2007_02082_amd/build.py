@@ -41,13 +41,17 @@ def _run(cmd, verbose):
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     inc = ["-I", INCLUDE, "-I", CSRC]
-    plan_o = os.path.join(BUILD, "plan.o")
+    objs = []
+    for src in ("plan.cpp", "mg_plan.cpp"):
+        obj = os.path.join(BUILD, src.replace(".cpp", ".o"))
+        _run(["g++", *CXX_FLAGS, *inc, "-I", os.path.join(ROCM, "include"), "-c",
+              os.path.join(CSRC, src), "-o", obj], verbose)
+        objs.append(obj)
     ibfe_o = os.path.join(BUILD, "ibfe.o")
-    _run(["g++", *CXX_FLAGS, *inc, "-I", os.path.join(ROCM, "include"), "-c",
-          os.path.join(CSRC, "plan.cpp"), "-o", plan_o], verbose)
     _run([HIPCC, *HIP_FLAGS, *inc, "-c", os.path.join(CSRC, "ibfe.hip"), "-o", ibfe_o], verbose)
+    objs.append(ibfe_o)
     tmp = LIB + ".tmp"
-    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", plan_o, ibfe_o, "-o", tmp], verbose)
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -1,6 +1,7 @@
 // Step driver and C ABI of the IPCS + BCE-IB time step (Section 2.4 order):
 // tentative velocity (BiCGStab), IB force solve (CG on G = I_F I_F^T) and
 // spreading, pressure increment (PCG), L2 velocity correction (PCG).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -14,6 +15,7 @@
 #include "plan.hpp"
 #include "step_kernels.hpp"
 #include "zblock.hpp"
+#include "mg.hpp"
 
 using namespace ibfe;
 
@@ -51,6 +53,22 @@ int blocks_lin(int64_t n) { return int((n + kBlock - 1) / kBlock); }
 
 struct ibfe_plan {
   Plan p;
+};
+
+// Device copy of one multigrid level (node-0 pointers into padded planes).
+template <typename T>
+struct MGDev {
+  int nx = 0, ny = 0, nz = 0, nchunks = 0, nzitems = 0, cpp = 0;
+  int64_t N = 0, sy = 0, sz = 0, halo = 0, stride = 0;
+  uint8_t* emask = nullptr;
+  uint8_t* flags = nullptr;
+  int* chunks = nullptr;
+  int* zitems = nullptr;
+  T *b = nullptr, *x = nullptr, *xt = nullptr, *d = nullptr, *r = nullptr;
+  double kc[4] = {0, 0, 0, 0};  // per-cell stiffness entries at this spacing
+  int m = 0;                    // coarsest: unknowns with a dense inverse
+  int64_t* ids = nullptr;
+  T* inv = nullptr;
 };
 
 struct ibfe_ctx {
@@ -112,6 +130,9 @@ struct ibfe_ctx {
   KScal* scal = nullptr;
   KScal* host_scal = nullptr;  // pinned
 
+  std::vector<MGDev<double>> mg64;
+  std::vector<MGDev<float>> mg32;
+
   FormCoefs fc{};
   double t = 0.0;
   int64_t steps = 0;
@@ -171,6 +192,70 @@ namespace {
 // -------------------------------------------------------------------------
 // set-up
 // -------------------------------------------------------------------------
+
+// Multigrid levels on the device.  Level 0 shares the grid's node bits, chunk
+// and column lists; its work vectors are taken from the Krylov work space.
+template <typename T>
+int setup_mg(ibfe_ctx& c, std::vector<MGDev<T>>& out, T* xt0, T* d0, T* r0) {
+  const Plan& P = c.plan;
+  out.clear();
+  int rc;
+  for (size_t l = 0; l < P.mg.size(); ++l) {
+    const MGLevel& L = P.mg[l];
+    MGDev<T> D;
+    D.nx = L.nx;
+    D.ny = L.ny;
+    D.nz = L.nz;
+    D.N = L.N;
+    D.sy = L.sy;
+    D.sz = L.sz;
+    D.cpp = L.cpp;
+    const FormCoefs f = form_coefs(L.h);
+    for (int t = 0; t < 4; ++t) D.kc[t] = f.k[t];
+    if (l == 0) {
+      D.halo = c.halo;
+      D.stride = c.stride;
+      D.emask = c.emask;
+      D.flags = c.flags;
+      D.chunks = c.chunks;
+      D.nchunks = c.nchunks;
+      D.zitems = c.zitems;
+      D.nzitems = c.nzitems;
+      D.xt = xt0;
+      D.d = d0;
+      D.r = r0;
+    } else {
+      const int64_t nch = (L.N + kChunk - 1) / kChunk;
+      D.halo = ((L.sz + L.sy + 1 + kChunk - 1) / kChunk) * kChunk;
+      D.stride = 2 * D.halo + nch * kChunk;
+      auto plane = [&](size_t bytes_per, void** base) { return c.dalloc(base, bytes_per * size_t(D.stride)); };
+      void* base = nullptr;
+      if ((rc = plane(1, &base))) return rc;
+      D.emask = reinterpret_cast<uint8_t*>(base) + D.halo;
+      HIP_TRY(hipMemcpyAsync(D.emask, L.emask.data(), L.N, hipMemcpyHostToDevice, c.stream));
+      if ((rc = plane(1, &base))) return rc;
+      D.flags = reinterpret_cast<uint8_t*>(base) + D.halo;
+      HIP_TRY(hipMemcpyAsync(D.flags, L.flags.data(), L.N, hipMemcpyHostToDevice, c.stream));
+      if ((rc = c.upload(&D.chunks, L.chunks.data(), L.chunks.size()))) return rc;
+      D.nchunks = int(L.chunks.size());
+      if ((rc = c.upload(&D.zitems, L.zitems.data(), L.zitems.size()))) return rc;
+      D.nzitems = int(L.zitems.size());
+      T** vecs[5] = {&D.b, &D.x, &D.xt, &D.d, &D.r};
+      for (T** v : vecs) {
+        if ((rc = plane(sizeof(T), &base))) return rc;
+        *v = reinterpret_cast<T*>(base) + D.halo;
+      }
+    }
+    if (l + 1 == P.mg.size() && !L.inv.empty()) {
+      D.m = int(L.unknowns.size());
+      if ((rc = c.upload(&D.ids, L.unknowns.data(), L.unknowns.size()))) return rc;
+      std::vector<T> inv(L.inv.begin(), L.inv.end());
+      if ((rc = c.upload(&D.inv, inv.data(), inv.size()))) return rc;
+    }
+    out.push_back(D);
+  }
+  return IBFE_OK;
+}
 
 int setup_device(ibfe_ctx& c) {
   Plan& P = c.plan;
@@ -279,6 +364,13 @@ int setup_device(ibfe_ctx& c) {
     if ((rc = c.upload(&c.inlet_ids, P.inlet_ids.data(), P.inlet_ids.size()))) return rc;
     if ((rc = c.upload(&c.inlet_shape, P.inlet_shape.data(), P.inlet_shape.size()))) return rc;
   }
+  if (P.params.precond == 2) {
+    if (P.params.precision == 1)
+      rc = setup_mg<float>(c, c.mg32, c.v32[4], c.v32[5], c.v32[6]);
+    else
+      rc = setup_mg<double>(c, c.mg64, c.w[4], c.w[5], c.w[6]);
+    if (rc) return rc;
+  }
   // reductions
   {
     void* base = nullptr;
@@ -328,21 +420,45 @@ int next_batch(int est, int done_so_far) {
   return 8;
 }
 
-// q = A p with partial p.q; returns the number of partials written.
+// q = A p with partial p.q; returns the number of partials written.  With
+// events, the dispatch itself records its start and end (no extra packets).
 template <typename T, class Op>
 int launch_q(ibfe_ctx& c, const Op& op, const int* chunks, int nchunks, const T* p, T* q,
-             const KScal* sc) {
+             const KScal* sc, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   const int nr = red_blocks(nchunks);
-  hipLaunchKernelGGL((k_cg_q<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, chunks, nchunks, op, p, q,
-                     c.partials, sc);
+  if (e0)
+    hipExtLaunchKernelGGL((k_cg_q<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, e0, e1, 0, chunks, nchunks,
+                          op, p, q, c.partials, sc);
+  else
+    hipLaunchKernelGGL((k_cg_q<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, chunks, nchunks, op, p, q,
+                       c.partials, sc);
   return nr;
 }
 template <typename T, int NC>
-int launch_q(ibfe_ctx& c, const OpSym<T, NC>& op, const int*, int, const T* p, T* q, const KScal* sc) {
+int launch_q(ibfe_ctx& c, const OpSym<T, NC>& op, const int*, int, const T* p, T* q, const KScal* sc,
+             hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   const int nr = red_blocks(c.nzitems);
-  hipLaunchKernelGGL((k_cg_q_zb<T, NC>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
-                     c.nzitems, c.cpp, c.plan.nz + 1, op, p, q, c.partials, sc);
+  ZOp<T> z{op.emask, op.flags, op.rowbit, op.sy, op.sz, c.plan.nz + 1, c.cpp,
+           {op.c[0], op.c[1], op.c[2], op.c[3]}};
+  if (e0)
+    hipExtLaunchKernelGGL((k_cg_q_zb<T, NC>), dim3(nr), dim3(kBlock), 0, c.stream, e0, e1, 0,
+                          (const int*)c.zitems, c.nzitems, z, op.stride, p, q, c.partials, sc);
+  else
+    hipLaunchKernelGGL((k_cg_q_zb<T, NC>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
+                       c.nzitems, z, op.stride, p, q, c.partials, sc);
   return nr;
+}
+
+// Event pair k of the kernel timer (created on first use).
+int timer_events(ibfe_ctx& c, size_t k, hipEvent_t& e0, hipEvent_t& e1) {
+  while (c.ev.size() < 2 * k + 2) {
+    hipEvent_t ne;
+    HIP_TRY(hipEventCreate(&ne));
+    c.ev.push_back(ne);
+  }
+  e0 = c.ev[2 * k];
+  e1 = c.ev[2 * k + 1];
+  return IBFE_OK;
 }
 
 template <typename T, class Op>
@@ -361,17 +477,9 @@ int run_cg(ibfe_ctx& c, const Op& op, const int* chunks, int nchunks, const T* b
   while (true) {
     const int batch = std::min(next_batch(c.est[slot], launched), max_iters + 1 - launched);
     for (int k = 0; k < batch; ++k) {
-      const size_t e = 2 * size_t(launched + k);
-      if (timed) {
-        while (c.ev.size() < e + 2) {
-          hipEvent_t ne;
-          HIP_TRY(hipEventCreate(&ne));
-          c.ev.push_back(ne);
-        }
-        HIP_TRY(hipEventRecord(c.ev[e], c.stream));
-      }
-      const int nq = launch_q<T>(c, op, chunks, nchunks, p, q, (const KScal*)sc);
-      if (timed) HIP_TRY(hipEventRecord(c.ev[e + 1], c.stream));
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (timed && timer_events(c, size_t(launched + k), e0, e1)) return IBFE_EHIP;
+      const int nq = launch_q<T>(c, op, chunks, nchunks, p, q, (const KScal*)sc, e0, e1);
       hipLaunchKernelGGL(k_fin_cg_q, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nq, sc);
       hipLaunchKernelGGL((k_cg_xr<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, chunks, nchunks, op, x, r,
                          p, q, c.partials, (const KScal*)sc);
@@ -449,12 +557,12 @@ int run_bicgstab(ibfe_ctx& c, const Op& op, const T* b, T* x, T* const* wv, int 
 
 // FP64 residual of the refinement loop: returns |r|^2 and |b|^2 on the host and
 // leaves r in FP32 in r32.
-template <class Op64>
-int ir_residual(ibfe_ctx& c, const Op64& op, const double* b, const double* x, float* r32, double& rr,
+template <class Op64, typename TR>
+int ir_residual(ibfe_ctx& c, const Op64& op, const double* b, const double* x, TR* r32, double& rr,
                 double& bb) {
   const int nr = red_blocks(c.nchunks);
-  hipLaunchKernelGGL((k_residual<Op64>), dim3(nr), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, op, b, x,
-                     r32, c.partials);
+  hipLaunchKernelGGL((k_residual<Op64, TR>), dim3(nr), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, op, b,
+                     x, r32, c.partials);
   hipLaunchKernelGGL(k_fin_residual, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr,
                      c.res2);
   CHECK_LAUNCH();
@@ -467,13 +575,12 @@ int ir_residual(ibfe_ctx& c, const Op64& op, const double* b, const double* x, f
 }
 
 // Mixed-precision solve A x = b: FP64 residuals and updates, FP32 inner Krylov
-// corrections (CG if SPD, else BiCGStab).  x holds the initial guess (zero off rows).
-template <bool SPD, class Op64, class Op32>
-int run_refined(ibfe_ctx& c, const Op64& op64, const Op32& op32, const double* b, double* x, float* const* w32,
-                int slot, double rtol, int max_iters, SolveOut& out, bool timed = false) {
+// corrections computed by inner(r32, d32, inner_rtol, SolveOut&).  x holds the
+// initial guess (zero off rows).
+template <class Op64, class Inner>
+int run_refined(ibfe_ctx& c, const Op64& op64, uint32_t rowbit, int nc, const double* b, double* x,
+                float* r32, float* d32, double rtol, SolveOut& out, Inner&& inner) {
   const int nb = blocks_for(c.nchunks);
-  float* r32 = w32[8];
-  float* d32 = w32[9];
   int total = 0;
   double rr = 0, bb = 0, res = 0;
   int sweeps = 0;
@@ -482,19 +589,13 @@ int run_refined(ibfe_ctx& c, const Op64& op64, const Op32& op32, const double* b
     if (rc) return rc;
     res = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
     if (res <= rtol || sweeps == kMaxSweeps) break;
-    const double inner = std::min(0.5, std::max(kInnerRtol, 0.5 * rtol / res));
+    const double tol_in = std::min(0.5, std::max(kInnerRtol, 0.5 * rtol / res));
     SolveOut so;
-    if (SPD)
-      rc = run_cg<float>(c, op32, c.chunks, c.nchunks, (const float*)r32, d32, w32[0], w32[1], w32[2], slot,
-                         inner, max_iters, true, so, timed);
-    else {
-      HIP_TRY(hipMemsetAsync(d32 - c.halo, 0, sizeof(float) * Op32::kNC * c.stride, c.stream));
-      rc = run_bicgstab<float>(c, op32, (const float*)r32, d32, w32, slot, inner, max_iters, so);
-    }
+    rc = inner((const float*)r32, d32, tol_in, so);
     total += so.iters;
     if (rc && rc != IBFE_ENOCONV) return rc;
     hipLaunchKernelGGL(k_add_correction<float>, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks,
-                       c.flags, op32.rowbit, (const float*)d32, x, Op32::kNC, c.stride);
+                       c.flags, rowbit, (const float*)d32, x, nc, c.stride);
     CHECK_LAUNCH();
   }
   out.iters = total;
@@ -542,6 +643,256 @@ OpCSR<3> gram_op(const ibfe_ctx& c) {
   op.nrows = int(c.plan.M);
   op.stride = c.mstride;
   return op;
+}
+
+
+// -------------------------------------------------------------------------
+// multigrid-preconditioned CG for the pressure increment
+// -------------------------------------------------------------------------
+
+// Chebyshev-Jacobi smoother on [lambda_max / 4, lambda_max] with the bound
+// lambda_max = 2 of D^-1 K (Gershgorin: every off-diagonal of the Q1
+// stiffness is <= 0 and its rows sum to zero).
+struct Cheb {
+  double c1[32], c2[32];
+};
+Cheb cheb_coefs(int m) {
+  const double lmax = 2.0, lmin = 0.5;
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+  Cheb ch{};
+  double rho = 1.0 / sigma;
+  ch.c1[0] = 0.0;
+  ch.c2[0] = 1.0 / theta;
+  for (int k = 1; k < m && k < 32; ++k) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    ch.c1[k] = rn * rho;
+    ch.c2[k] = 2.0 * rn / delta;
+    rho = rn;
+  }
+  return ch;
+}
+
+constexpr int kSmooth = 2;        // Chebyshev degree of pre- and post-smoothing
+constexpr int kCoarseSmooth = 16; // coarsest-level smoothing when no dense inverse
+
+template <typename T>
+ZOp<T> level_op(const MGDev<T>& L) {
+  ZOp<T> z{};
+  z.emask = L.emask;
+  z.flags = L.flags;
+  z.rowbit = kMgRow;
+  z.sy = int(L.sy);
+  z.sz = int(L.sz);
+  z.nplanes = L.nz + 1;
+  z.cpp = L.cpp;
+  for (int t = 0; t < 4; ++t) z.c[t] = T(L.kc[t]);
+  return z;
+}
+
+// m Chebyshev steps on level L for b, continuing from *x (zero_start: from x = 0);
+// ping-pongs between *x and *alt.  With dot, the last step writes partials of b.x.
+template <typename T>
+int smooth(ibfe_ctx& c, const MGDev<T>& L, const T* b, T*& x, T*& alt, int m, bool zero_start,
+           bool dot, const KScal* sc, int& nparts) {
+  const Cheb ch = cheb_coefs(m);
+  const ZOp<T> op = level_op(L);
+  const int nr = red_blocks(L.nzitems);
+  for (int k = 0; k < m; ++k) {
+    const bool last = k == m - 1;
+    if (k == 0 && zero_start && !(last && dot)) {
+      hipLaunchKernelGGL(k_mg_cheb0<T>, dim3(blocks_for(L.nchunks)), dim3(kBlock), 0, c.stream,
+                         (const int*)L.chunks, L.nchunks, (const uint8_t*)L.emask, (const uint8_t*)L.flags,
+                         T(L.kc[0]), T(ch.c2[0]), b, L.d, x, sc);
+      continue;  // x already holds the result: no swap
+    }
+    const T* xin = x;
+    if (k == 0 && zero_start) {
+      // degree-1 smoothing from zero with a dot: x is zero on entry
+      hipLaunchKernelGGL(k_mg_cheb0<T>, dim3(blocks_for(L.nchunks)), dim3(kBlock), 0, c.stream,
+                         (const int*)L.chunks, L.nchunks, (const uint8_t*)L.emask, (const uint8_t*)L.flags,
+                         T(L.kc[0]), T(0), b, L.d, x, sc);
+      xin = x;
+    }
+    if (last && dot)
+      hipLaunchKernelGGL((k_zb_cheb<T, true>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)L.zitems,
+                         L.nzitems, op, xin, b, L.d, alt, T(ch.c1[k]), T(ch.c2[k]), c.partials, sc);
+    else
+      hipLaunchKernelGGL((k_zb_cheb<T, false>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)L.zitems,
+                         L.nzitems, op, xin, b, L.d, alt, T(ch.c1[k]), T(ch.c2[k]), c.partials, sc);
+    std::swap(x, alt);
+  }
+  nparts = nr;
+  CHECK_LAUNCH();
+  return IBFE_OK;
+}
+
+// z = V(r): one symmetric V(kSmooth, kSmooth) cycle.  Writes the partials of r.z
+// and returns their count in nparts.
+template <typename T>
+int vcycle(ibfe_ctx& c, std::vector<MGDev<T>>& lv, const T* r0, T* z0, const KScal* sc, int& nparts) {
+  const int L = int(lv.size());
+  std::vector<T*> cur(L), alt(L);
+  // level 0 result must end in z0: pre (m-1 swaps) + post (m swaps) is odd
+  cur[0] = lv[0].xt;
+  alt[0] = z0;
+  for (int l = 1; l < L; ++l) {
+    cur[l] = lv[l].x;
+    alt[l] = lv[l].xt;
+  }
+  int np = 0, rc;
+  for (int l = 0; l + 1 < L; ++l) {
+    const MGDev<T>& A = lv[l];
+    const T* b = l == 0 ? r0 : A.b;
+    if ((rc = smooth<T>(c, A, b, cur[l], alt[l], kSmooth, true, false, sc, np))) return rc;
+    hipLaunchKernelGGL(k_zb_resid<T>, dim3(red_blocks(A.nzitems)), dim3(kBlock), 0, c.stream,
+                       (const int*)A.zitems, A.nzitems, level_op(A), (const T*)cur[l], b, A.r, sc);
+    const MGDev<T>& C = lv[l + 1];
+    hipLaunchKernelGGL(k_mg_restrict<T>, dim3(blocks_for(C.nchunks)), dim3(kBlock), 0, c.stream,
+                       (const int*)C.chunks, C.nchunks, (const uint8_t*)C.flags, int(C.sy), int(C.sz),
+                       int(A.sy), int(A.sz), A.nx, A.ny, A.nz, (const T*)A.r, C.b, sc);
+    CHECK_LAUNCH();
+  }
+  {
+    const MGDev<T>& C = lv[L - 1];
+    const T* b = L == 1 ? r0 : C.b;
+    if (C.m > 0) {
+      if (L == 1) cur[0] = z0;  // single level: the dense solve is the whole cycle
+      hipLaunchKernelGGL(k_mg_dense<T>, dim3((C.m + kBlock - 1) / kBlock), dim3(kBlock), 0, c.stream, C.m,
+                         (const int64_t*)C.ids, (const T*)C.inv, b, cur[L - 1], sc);
+      if (L == 1) {
+        np = red_blocks(C.nchunks);
+        hipLaunchKernelGGL(k_mg_dot<T>, dim3(np), dim3(kBlock), 0, c.stream, (const int*)C.chunks, C.nchunks,
+                           (const uint8_t*)C.flags, b, (const T*)z0, c.partials, sc);
+      }
+      CHECK_LAUNCH();
+    } else if ((rc = smooth<T>(c, C, b, cur[L - 1], alt[L - 1], kCoarseSmooth, true, L == 1, sc, np))) {
+      return rc;
+    }
+  }
+  for (int l = L - 2; l >= 0; --l) {
+    const MGDev<T>& A = lv[l];
+    const MGDev<T>& C = lv[l + 1];
+    hipLaunchKernelGGL(k_mg_prolong<T>, dim3(blocks_for(A.nchunks)), dim3(kBlock), 0, c.stream,
+                       (const int*)A.chunks, A.nchunks, (const uint8_t*)A.flags, int(A.sy), int(A.sz),
+                       int(C.sy), int(C.sz), (const T*)cur[l + 1], cur[l], sc);
+    CHECK_LAUNCH();
+    const T* b = l == 0 ? r0 : A.b;
+    if ((rc = smooth<T>(c, A, b, cur[l], alt[l], kSmooth, false, l == 0, sc, np))) return rc;
+  }
+  if (cur[0] != z0) return fail(IBFE_EINVAL, "internal: V-cycle result buffer");
+  nparts = np;
+  return IBFE_OK;
+}
+
+// CG on K_{P'P'} x = b preconditioned by one V-cycle per iteration; x starts at 0.
+template <typename T>
+int run_pcg_mg(ibfe_ctx& c, std::vector<MGDev<T>>& lv, const T* b, T* x, T* r, T* p, T* q, T* z, int slot,
+               double rtol, int max_iters, SolveOut& out, bool timed) {
+  const int nr = red_blocks(c.nchunks);
+  KScal* sc = &c.scal[slot];
+  const KScal* csc = sc;
+  const double kc[4] = {c.fc.k[0], c.fc.k[1], c.fc.k[2], c.fc.k[3]};
+  auto op = sym_op<T, 1>(c, kc, kFlagPp);
+  int rc, np = 0;
+  hipLaunchKernelGGL(k_mgcg_init<T>, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.chunks, c.nchunks,
+                     (const uint8_t*)c.flags, b, x, r, c.partials);
+  hipLaunchKernelGGL(k_fin_mgcg_init, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr, sc,
+                     rtol * rtol, max_iters);
+  CHECK_LAUNCH();
+  if ((rc = vcycle<T>(c, lv, r, z, csc, np))) return rc;
+  hipLaunchKernelGGL(k_fin_mgcg_rz, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, np, sc, 1);
+  hipLaunchKernelGGL(k_mgcg_p<T>, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream, (const int*)c.chunks,
+                     c.nchunks, (const uint8_t*)c.flags, (const T*)z, p, csc);
+  CHECK_LAUNCH();
+  int launched = 0;
+  KScal s{};
+  while (true) {
+    const int batch = std::min(launched == 0 ? std::max(2, c.est[slot] - 1) : 2, max_iters + 1 - launched);
+    for (int k = 0; k < batch; ++k) {
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (timed && timer_events(c, size_t(launched + k), e0, e1)) return IBFE_EHIP;
+      const int nq = launch_q<T>(c, op, c.chunks, c.nchunks, (const T*)p, q, csc, e0, e1);
+      hipLaunchKernelGGL(k_fin_cg_q, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nq, sc);
+      hipLaunchKernelGGL(k_mgcg_xr<T>, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.chunks, c.nchunks,
+                         (const uint8_t*)c.flags, x, r, (const T*)p, (const T*)q, c.partials, csc);
+      hipLaunchKernelGGL(k_fin_mgcg_xr, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr, sc);
+      CHECK_LAUNCH();
+      if ((rc = vcycle<T>(c, lv, r, z, csc, np))) return rc;
+      hipLaunchKernelGGL(k_fin_mgcg_rz, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, np, sc,
+                         0);
+      hipLaunchKernelGGL(k_mgcg_p<T>, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
+                         (const int*)c.chunks, c.nchunks, (const uint8_t*)c.flags, (const T*)z, p, csc);
+      CHECK_LAUNCH();
+    }
+    launched += batch;
+    if ((rc = poll(c, slot, s))) return rc;
+    if (s.done || launched > max_iters) break;
+  }
+  if (timed) {
+    for (int k = 0; k < s.iters && k < launched; ++k) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, c.ev[2 * k], c.ev[2 * k + 1]));
+      c.stats.poisson_apply_ms += ms;
+      c.stats.poisson_applies += 1;
+    }
+  }
+  c.est[slot] = std::max(1, s.iters);
+  out.iters = s.iters;
+  out.res = s.bb > 0.0 ? std::sqrt(s.rr / s.bb) : 0.0;
+  return finish_status(s, "multigrid CG");
+}
+
+
+// -------------------------------------------------------------------------
+// Chebyshev iteration for the consistent-mass correction M_FF x = b.  For Q1
+// cubes the generalized eigenvalues of (M, diag M) lie in [1/8, 27/8]: the
+// Rayleigh quotient is a ratio of sums of element quadratic forms and each
+// element gives diag(M_e)^-1 M_e = (1/2..3/2)^3; a principal submatrix (free
+// rows) stays inside.  No inner products are needed.
+// -------------------------------------------------------------------------
+
+constexpr double kMassLmin = 1.0 / 8.0, kMassLmax = 27.0 / 8.0;
+
+int mass_cheb_steps(double tol) {
+  const double kappa = kMassLmax / kMassLmin;
+  const double q = (std::sqrt(kappa) - 1.0) / (std::sqrt(kappa) + 1.0);
+  return int(std::ceil((std::log(2.0 / tol) + 0.5 * std::log(kappa)) / std::log(1.0 / q)));
+}
+
+// x = Cheb_iters(b) from x = 0 (x, xalt, d: 3-plane vectors).
+template <typename T>
+int run_cheb_mass(ibfe_ctx& c, const T* b, T* x, T* xalt, T* d, int iters) {
+  const Plan& P = c.plan;
+  const double theta = 0.5 * (kMassLmax + kMassLmin), delta = 0.5 * (kMassLmax - kMassLmin);
+  const double sigma = theta / delta;
+  ZOp<T> op{};
+  op.emask = c.emask;
+  op.flags = c.flags;
+  op.rowbit = kFlagF;
+  op.sy = int(P.sy);
+  op.sz = int(P.sz);
+  op.nplanes = P.nz + 1;
+  op.cpp = c.cpp;
+  for (int t = 0; t < 4; ++t) op.c[t] = T(c.fc.m[t]);
+  T* cur = ((iters - 1) % 2 == 0) ? x : xalt;
+  T* alt = cur == x ? xalt : x;
+  hipLaunchKernelGGL((k_mg_cheb0<T, 3>), dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
+                     (const int*)c.chunks, c.nchunks, (const uint8_t*)c.emask, (const uint8_t*)c.flags,
+                     T(c.fc.m[0]), T(1.0 / theta), b, d, cur, (const KScal*)nullptr, kFlagF, c.stride);
+  const int nr = red_blocks(c.nzitems);
+  double rho = 1.0 / sigma;
+  for (int k = 1; k < iters; ++k) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    const T c1 = T(rn * rho), c2 = T(2.0 * rn / delta);
+    rho = rn;
+    hipLaunchKernelGGL((k_zb_cheb<T, false, 3>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
+                       c.nzitems, op, (const T*)cur, b, d, alt, c1, c2, c.partials, (const KScal*)nullptr,
+                       c.stride);
+    std::swap(cur, alt);
+  }
+  CHECK_LAUNCH();
+  if (cur != x) return fail(IBFE_EINVAL, "internal: Chebyshev result buffer");
+  return IBFE_OK;
 }
 
 // -------------------------------------------------------------------------
@@ -616,7 +967,11 @@ int step_once(ibfe_ctx& c) {
     SolveOut so;
     if (mixed) {
       auto op32 = stencil_op<float>(c, c.coef32, kFlagF);
-      rc = run_refined<false>(c, op, op32, b1, x1, c.v32, kScS1, rtol, maxit, so);
+      rc = run_refined(c, op, kFlagF, 3, b1, x1, c.v32[8], c.v32[9], rtol, so,
+                       [&](const float* r32, float* d32, double tol, SolveOut& o) {
+                         HIP_TRY(hipMemsetAsync(d32 - c.halo, 0, sizeof(float) * 3 * S, c.stream));
+                         return run_bicgstab<float>(c, op32, r32, d32, c.v32, kScS1, tol, maxit, o);
+                       });
     } else {
       rc = run_bicgstab<double>(c, op, b1, x1, c.w, kScS1, rtol, maxit, so);
     }
@@ -663,10 +1018,22 @@ int step_once(ibfe_ctx& c) {
     const double kc[4] = {c.fc.k[0], c.fc.k[1], c.fc.k[2], c.fc.k[3]};
     auto op = sym_op<double, 1>(c, kc, kFlagPp);
     SolveOut so;
+    const bool mg = P.params.precond == 2;
     if (mixed) {
       auto op32 = sym_op<float, 1>(c, kc, kFlagPp);
       HIP_TRY(hipMemsetAsync(c.phi - c.halo, 0, sizeof(double) * S, c.stream));
-      rc = run_refined<true>(c, op, op32, b3, c.phi, c.v32, kScS3, rtol, maxit, so, c.timing);
+      float* const* v = c.v32;
+      rc = run_refined(c, op, kFlagPp, 1, b3, c.phi, v[8], v[9], rtol, so,
+                       [&](const float* r32, float* d32, double tol, SolveOut& o) {
+                         if (mg)
+                           return run_pcg_mg<float>(c, c.mg32, r32, d32, v[0], v[1], v[2], v[3], kScS3, tol,
+                                                    maxit, o, c.timing);
+                         return run_cg<float>(c, op32, c.chunks, c.nchunks, r32, d32, v[0], v[1], v[2], kScS3,
+                                              tol, maxit, true, o, c.timing);
+                       });
+    } else if (mg) {
+      rc = run_pcg_mg<double>(c, c.mg64, b3, c.phi, c.w[0], c.w[1], c.w[2], c.w[3], kScS3, rtol, maxit, so,
+                              c.timing);
     } else {
       rc = run_cg<double>(c, op, c.chunks, c.nchunks, b3, c.phi, c.w[0], c.w[1], c.w[2], kScS3, rtol, maxit,
                           true, so, c.timing);
@@ -688,13 +1055,33 @@ int step_once(ibfe_ctx& c) {
     const double mc[4] = {c.fc.m[0], c.fc.m[1], c.fc.m[2], c.fc.m[3]};
     auto op = sym_op<double, 3>(c, mc, kFlagF);
     SolveOut so;
+    HIP_TRY(hipMemsetAsync(delta - c.halo, 0, sizeof(double) * 3 * S, c.stream));
     if (mixed) {
-      auto op32 = sym_op<float, 3>(c, mc, kFlagF);
-      HIP_TRY(hipMemsetAsync(delta - c.halo, 0, sizeof(double) * 3 * S, c.stream));
-      rc = run_refined<true>(c, op, op32, b4, delta, c.v32, kScS4, rtol, maxit, so);
+      float* const* v = c.v32;
+      rc = run_refined(c, op, kFlagF, 3, b4, delta, v[8], v[9], rtol, so,
+                       [&](const float* r32, float* d32, double tol, SolveOut& o) {
+                         o.iters = mass_cheb_steps(tol);
+                         return run_cheb_mass<float>(c, r32, d32, v[0], v[1], o.iters);
+                       });
     } else {
-      rc = run_cg<double>(c, op, c.chunks, c.nchunks, b4, delta, c.w[0], c.w[1], c.w[2], kScS4, rtol, maxit,
-                          true, so);
+      // FP64: refinement sweeps whose corrections are FP64 Chebyshev solves
+      double* r64 = c.w[3];
+      so.iters = 0;
+      so.outer = 0;
+      for (int sweep = 0;; ++sweep) {
+        double rr = 0, bb = 0;
+        if ((rc = ir_residual(c, op, b4, delta, r64, rr, bb))) return rc;
+        so.res = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
+        if (so.res <= rtol || sweep == 4) break;
+        const int it = mass_cheb_steps(std::max(rtol / std::max(so.res, 1e-300), 1e-15));
+        if ((rc = run_cheb_mass<double>(c, (const double*)r64, c.w[0], c.w[1], c.w[2], it))) return rc;
+        hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, 1.0, delta, 1.0,
+                           c.w[0], delta, 3, S);
+        CHECK_LAUNCH();
+        so.iters += it;
+        so.outer += 1;
+      }
+      rc = so.res <= rtol ? IBFE_OK : fail(IBFE_ENOCONV, "mass correction did not converge");
     }
     if (rc) return rc;
     c.stats.s4_iters = so.iters;

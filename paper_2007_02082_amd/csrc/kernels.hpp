@@ -128,36 +128,82 @@ __device__ __forceinline__ constexpr uint32_t compat(int ox, int oy, int oz) {
   return side_mask(0, ox) & side_mask(1, oy) & side_mask(2, oz);
 }
 
-// y = sum_o c[|ox|+|oy|+|oz|] * popcount(e & compat(o)) * x[n + o]
+template <typename T>
+__device__ __forceinline__ void load_plane(const T* __restrict__ x, int node, int sy, T (&w)[9]) {
+#pragma unroll
+  for (int y = -1; y <= 1; ++y) {
+    const T* row = x + (node + y * sy);
+    w[(y + 1) * 3 + 0] = row[-1];
+    w[(y + 1) * 3 + 1] = row[0];
+    w[(y + 1) * 3 + 2] = row[1];
+  }
+}
+
+// y = sum_o cw(o) x(o) over the window planes lo (z-1), mid (z), hi (z+1), with
+// cw(o) = c[t(o)] * (number of kept cells shared by the node and node + o).
+// The counts are formed from the 8 cell bits as floating-point sums: a corner
+// neighbour lies in one cell, an edge neighbour in two, a face neighbour in four.
+template <typename T>
+__device__ __forceinline__ T window_apply(const T (&lo)[9], const T (&mid)[9], const T (&hi)[9],
+                                          uint32_t e, bool interior, const T (&c)[4]) {
+  const T* pl[3] = {lo, mid, hi};
+  // W(i, j, k): window value at offset (i-1, j-1, k-1)
+#define W_(i, j, k) pl[k][(j) * 3 + (i)]
+  if (interior) {
+    T s[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int z = 0; z < 3; ++z)
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const int ox = k % 3 - 1, oy = k / 3 - 1, oz = z - 1;
+        const int t = (ox != 0) + (oy != 0) + (oz != 0);
+        s[t] += pl[z][k];
+      }
+    return c[0] * T(8) * s[0] + c[1] * T(4) * s[1] + c[2] * T(2) * s[2] + c[3] * s[3];
+  }
+  T b[2][2][2];  // b[sz][sy][sx]: cell (i-1+sx, j-1+sy, k-1+sz) kept
+#pragma unroll
+  for (int q = 0; q < 8; ++q) b[q >> 2][(q >> 1) & 1][q & 1] = T((e >> q) & 1u);
+  T n = T(0), a3 = T(0), a2 = T(0);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int sx = q & 1, sy = (q >> 1) & 1, sz = q >> 2;
+    n += b[sz][sy][sx];
+    a3 += b[sz][sy][sx] * W_(2 * sx, 2 * sy, 2 * sz);
+  }
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      a2 += (b[0][v][u] + b[1][v][u]) * W_(2 * u, 2 * v, 1);   // edge (ox, oy, 0)
+      a2 += (b[v][0][u] + b[v][1][u]) * W_(2 * u, 1, 2 * v);   // edge (ox, 0, oz)
+      a2 += (b[v][u][0] + b[v][u][1]) * W_(1, 2 * u, 2 * v);   // edge (0, oy, oz)
+    }
+  T acc = c[0] * n * W_(1, 1, 1) + c[2] * a2 + c[3] * a3;
+  if (c[1] != T(0)) {  // face neighbours (zero per-cell entry for the stiffness)
+    T a1 = T(0);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      a1 += (b[0][0][u] + b[0][1][u] + b[1][0][u] + b[1][1][u]) * W_(2 * u, 1, 1);
+      a1 += (b[0][u][0] + b[0][u][1] + b[1][u][0] + b[1][u][1]) * W_(1, 2 * u, 1);
+      a1 += (b[u][0][0] + b[u][0][1] + b[u][1][0] + b[u][1][1]) * W_(1, 1, 2 * u);
+    }
+    acc += c[1] * a1;
+  }
+#undef W_
+  return acc;
+}
+
+// y = sum_o c[|ox|+|oy|+|oz|] * (kept cells shared with node n + o) * x[n + o]
 // (symmetric operators alpha M + beta K: c[t] = per-cell entry for offset type t).
 template <typename T>
 __device__ __forceinline__ T apply_sym(const T* __restrict__ x, int n, uint32_t e,
                                        const T (&c)[4], int sy, int sz) {
-  T acc = T(0);
-  if (e == 0xFFu) {  // interior: constant 27-point stencil
-#pragma unroll
-    for (int oz = -1; oz <= 1; ++oz)
-#pragma unroll
-      for (int oy = -1; oy <= 1; ++oy)
-#pragma unroll
-        for (int ox = -1; ox <= 1; ++ox) {
-          const int t = (ox != 0) + (oy != 0) + (oz != 0);
-          const T w = c[t] * T(8 >> t);
-          acc += w * x[n + ox + sy * oy + sz * oz];
-        }
-  } else {
-#pragma unroll
-    for (int oz = -1; oz <= 1; ++oz)
-#pragma unroll
-      for (int oy = -1; oy <= 1; ++oy)
-#pragma unroll
-        for (int ox = -1; ox <= 1; ++ox) {
-          const int t = (ox != 0) + (oy != 0) + (oz != 0);
-          const T w = c[t] * T(__builtin_popcount(e & compat(ox, oy, oz)));
-          acc += w * x[n + ox + sy * oy + sz * oz];
-        }
-  }
-  return acc;
+  T w0[9], w1[9], w2[9];
+  load_plane(x, n - sz, sy, w0);
+  load_plane(x, n, sy, w1);
+  load_plane(x, n + sz, sy, w2);
+  return window_apply<T>(w0, w1, w2, e, __all(e == 0xFFu), c);
 }
 
 // Weak gradient G_d x at node n: entry(o) = sum over shared kept cells of
@@ -677,11 +723,11 @@ __global__ __launch_bounds__(kBlock) void k_fin_bi_x(const double* __restrict__ 
 // iterative refinement: FP64 residual r = b - A x on rows, its FP32 copy, and
 // partials r.r, b.b
 // ---------------------------------------------------------------------------
-template <class Op>
+template <class Op, typename TR = float>
 __global__ __launch_bounds__(kBlock) void k_residual(const int* __restrict__ chunks, int nchunks, Op op,
                                                      const double* __restrict__ b,
                                                      const double* __restrict__ x,
-                                                     float* __restrict__ r32,
+                                                     TR* __restrict__ r32,
                                                      double* __restrict__ partials) {
   constexpr int NC = Op::kNC;
   double v[2] = {0.0, 0.0};
@@ -696,7 +742,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(const int* __restrict__ chu
       const int64_t i = d * op.stride + n;
       const double bi = rw ? b[i] : 0.0;
       const double ri = rw ? bi - ax[d] : 0.0;
-      r32[i] = float(ri);
+      r32[i] = TR(ri);
       v[0] += ri * ri;
       v[1] += bi * bi;
     }

@@ -1,0 +1,257 @@
+// Geometric multigrid kernels for the pressure increment equation: the first
+// Chebyshev step from a zero guess, full-weighting restriction (transpose of
+// trilinear prolongation), prolongation with correction, the dense coarsest
+// solve, and the vector kernels of multigrid-preconditioned CG.
+#pragma once
+
+#include "zblock.hpp"
+
+namespace ibfe {
+
+constexpr uint32_t kMgRow = 16u;  // pressure unknown bit of the level flags
+
+// x = d = c2 D^-1 b on rows (Chebyshev step from x = 0), 0 elsewhere; D is
+// c0 times the number of kept cells around the node; NC planes of `stride`.
+template <typename T, int NC = 1>
+__global__ __launch_bounds__(kBlock) void k_mg_cheb0(const int* __restrict__ chunks, int nchunks,
+                                                     const uint8_t* __restrict__ emask,
+                                                     const uint8_t* __restrict__ flags, T c0, T c2,
+                                                     const T* __restrict__ b, T* __restrict__ d,
+                                                     T* __restrict__ x, const KScal* sc,
+                                                     uint32_t rowbit = kMgRow, int64_t stride = 0) {
+  if (sc && sc->done) return;
+  const int n = chunk_node(chunks, nchunks);
+  if (n < 0) return;
+  const bool rw = flags[n] & rowbit;
+  const T dinv = rw ? T(1) / (c0 * T(__builtin_popcount(uint32_t(emask[n])))) : T(0);
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    const T v = rw ? T(c2 * b[q * stride + n] * dinv) : T(0);
+    d[q * stride + n] = v;
+    x[q * stride + n] = v;
+  }
+}
+
+__device__ __forceinline__ void node_ijk(int n, int sy, int sz, int& i, int& j, int& k) {
+  k = n / sz;
+  const int rem = n - k * sz;
+  j = rem / sy;
+  i = rem - j * sy;
+}
+
+// bc[I] = sum_j P_jI rf[j] for coarse unknowns I (0 elsewhere); the fine nodes j
+// are the 27 around the node at the same place (2I), weight prod_d (1 - |o_d|/2).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mg_restrict(const int* __restrict__ chunks, int nchunks,
+                                                        const uint8_t* __restrict__ cflags, int csy,
+                                                        int csz, int fsy, int fsz, int fnx, int fny,
+                                                        int fnz, const T* __restrict__ rf,
+                                                        T* __restrict__ bc, const KScal* sc) {
+  if (sc->done) return;
+  const int n = chunk_node(chunks, nchunks);
+  if (n < 0) return;
+  if (!(cflags[n] & kMgRow)) {
+    bc[n] = T(0);
+    return;
+  }
+  int ic, jc, kc;
+  node_ijk(n, csy, csz, ic, jc, kc);
+  const int fi = 2 * ic, fj = 2 * jc, fk = 2 * kc;
+  const int fc = fi + fsy * fj + fsz * fk;
+  T acc = T(0);
+#pragma unroll
+  for (int oz = -1; oz <= 1; ++oz) {
+    if (fk + oz < 0 || fk + oz > fnz) continue;
+#pragma unroll
+    for (int oy = -1; oy <= 1; ++oy) {
+      if (fj + oy < 0 || fj + oy > fny) continue;
+#pragma unroll
+      for (int ox = -1; ox <= 1; ++ox) {
+        if (fi + ox < 0 || fi + ox > fnx) continue;
+        const int t = (ox != 0) + (oy != 0) + (oz != 0);
+        acc += T(1.0 / double(1 << t)) * rf[fc + ox + fsy * oy + fsz * oz];
+      }
+    }
+  }
+  bc[n] = acc;
+}
+
+// xf[j] += sum_I P_jI xc[I] on fine unknowns (trilinear interpolation).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mg_prolong(const int* __restrict__ chunks, int nchunks,
+                                                       const uint8_t* __restrict__ fflags, int fsy,
+                                                       int fsz, int csy, int csz,
+                                                       const T* __restrict__ xc, T* __restrict__ xf,
+                                                       const KScal* sc) {
+  if (sc->done) return;
+  const int n = chunk_node(chunks, nchunks);
+  if (n < 0 || !(fflags[n] & kMgRow)) return;
+  int i, j, k;
+  node_ijk(n, fsy, fsz, i, j, k);
+  const int i0 = i >> 1, j0 = j >> 1, k0 = k >> 1;
+  const int i1 = i0 + (i & 1), j1 = j0 + (j & 1), k1 = k0 + (k & 1);
+  const T wx = (i & 1) ? T(0.5) : T(1), wy = (j & 1) ? T(0.5) : T(1), wz = (k & 1) ? T(0.5) : T(1);
+  T acc = T(0);
+  const int cz[2] = {k0, k1}, cyy[2] = {j0, j1}, cx[2] = {i0, i1};
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int a = c & 1, bq = (c >> 1) & 1, e = (c >> 2) & 1;
+    if ((a && !(i & 1)) || (bq && !(j & 1)) || (e && !(k & 1))) continue;
+    acc += wx * wy * wz * xc[cx[a] + csy * cyy[bq] + csz * cz[e]];
+  }
+  xf[n] += acc;
+}
+
+// Coarsest level: x[u_i] = sum_j inv[i][j] b[u_j]; one thread per row, every
+// workgroup stages b in LDS (m <= 1024).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mg_dense(int m, const int64_t* __restrict__ ids,
+                                                     const T* __restrict__ inv, const T* __restrict__ b,
+                                                     T* __restrict__ x, const KScal* sc) {
+  if (sc->done) return;
+  __shared__ T bs[1024];
+  for (int j = threadIdx.x; j < m; j += kBlock) bs[j] = b[ids[j]];
+  __syncthreads();
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= m) return;
+  T acc0 = T(0), acc1 = T(0), acc2 = T(0), acc3 = T(0);
+  int j = 0;
+  for (; j + 3 < m; j += 4) {
+    acc0 += inv[int64_t(j) * m + i] * bs[j];
+    acc1 += inv[int64_t(j + 1) * m + i] * bs[j + 1];
+    acc2 += inv[int64_t(j + 2) * m + i] * bs[j + 2];
+    acc3 += inv[int64_t(j + 3) * m + i] * bs[j + 3];
+  }
+  for (; j < m; ++j) acc0 += inv[int64_t(j) * m + i] * bs[j];
+  x[ids[i]] = (acc0 + acc1) + (acc2 + acc3);
+}
+
+// partials of a.b over rows
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mg_dot(const int* __restrict__ chunks, int nchunks,
+                                                   const uint8_t* __restrict__ flags,
+                                                   const T* __restrict__ a, const T* __restrict__ b,
+                                                   double* __restrict__ partials, const KScal* sc) {
+  if (sc->done) return;
+  double v[1] = {0.0};
+  const ChunkRange cr = block_chunks(nchunks);
+  for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
+    const int n = chunks[c] * 64 + int(threadIdx.x & 63);
+    if (flags[n] & kMgRow) v[0] += double(a[n]) * double(b[n]);
+  }
+  block_partials<1>(v, partials);
+}
+
+// ---- multigrid-preconditioned CG (vectors over the level-0 unknowns) -------
+
+// x = 0, r = b on rows (0 elsewhere); partials r.r, b.b
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mgcg_init(const int* __restrict__ chunks, int nchunks,
+                                                      const uint8_t* __restrict__ flags,
+                                                      const T* __restrict__ b, T* __restrict__ x,
+                                                      T* __restrict__ r, double* __restrict__ partials) {
+  double v[2] = {0.0, 0.0};
+  const ChunkRange cr = block_chunks(nchunks);
+  for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
+    const int n = chunks[c] * 64 + int(threadIdx.x & 63);
+    const T bi = (flags[n] & kMgRow) ? b[n] : T(0);
+    x[n] = T(0);
+    r[n] = bi;
+    v[0] += double(bi) * double(bi);
+  }
+  v[1] = v[0];
+  block_partials<2>(v, partials);
+}
+
+// rr, bb -> convergence test; rz is set later by k_fin_mgcg_rz
+__global__ __launch_bounds__(kBlock) void k_fin_mgcg_init(const double* __restrict__ partials, int nb,
+                                                          KScal* sc, double tol2, int max_iters) {
+  double tot[2];
+  sum_partials<2>(partials, nb, tot);
+  if (threadIdx.x != 0) return;
+  sc->tol2 = tol2;
+  sc->max_iters = max_iters;
+  sc->rr = tot[0];
+  sc->bb = tot[1];
+  sc->rz = 1.0;
+  sc->beta = 0.0;
+  sc->iters = 0;
+  sc->status = 0;
+  sc->done = (tot[0] <= tol2 * tot[1]) ? 1 : 0;
+  if (bad(tot[0]) || bad(tot[1])) {
+    sc->status = 2;
+    sc->done = 1;
+  }
+}
+
+// rz_new = r.z (from the partials of the last smoothing step): beta = rz_new / rz
+// (beta = 0 on the first call, flagged by iters == 0 and rz == 1 set at init)
+__global__ __launch_bounds__(kBlock) void k_fin_mgcg_rz(const double* __restrict__ partials, int nb,
+                                                        KScal* sc, int first) {
+  if (sc->done) return;
+  double tot[1];
+  sum_partials<1>(partials, nb, tot);
+  if (threadIdx.x != 0) return;
+  const double rz_new = tot[0];
+  if (bad(rz_new) || !(rz_new > 0.0)) {
+    sc->status = bad(rz_new) ? 2 : 1;
+    sc->done = 1;
+    return;
+  }
+  sc->beta = first ? 0.0 : rz_new / sc->rz;
+  sc->rz = rz_new;
+}
+
+// x += alpha p, r -= alpha q on rows; partial r.r
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mgcg_xr(const int* __restrict__ chunks, int nchunks,
+                                                    const uint8_t* __restrict__ flags, T* __restrict__ x,
+                                                    T* __restrict__ r, const T* __restrict__ p,
+                                                    const T* __restrict__ q, double* __restrict__ partials,
+                                                    const KScal* sc) {
+  if (sc->done) return;
+  const T alpha = T(sc->alpha);
+  double v[1] = {0.0};
+  const ChunkRange cr = block_chunks(nchunks);
+  for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
+    const int n = chunks[c] * 64 + int(threadIdx.x & 63);
+    if (flags[n] & kMgRow) {
+      x[n] += alpha * p[n];
+      const T ri = r[n] - alpha * q[n];
+      r[n] = ri;
+      v[0] += double(ri) * double(ri);
+    }
+  }
+  block_partials<1>(v, partials);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fin_mgcg_xr(const double* __restrict__ partials, int nb,
+                                                        KScal* sc) {
+  if (sc->done) return;
+  double tot[1];
+  sum_partials<1>(partials, nb, tot);
+  if (threadIdx.x != 0) return;
+  sc->rr = tot[0];
+  sc->iters += 1;
+  if (bad(tot[0])) {
+    sc->status = 2;
+    sc->done = 1;
+  } else if (tot[0] <= sc->tol2 * sc->bb || sc->iters >= sc->max_iters) {
+    sc->done = 1;
+  }
+}
+
+// p = z + beta p on rows
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mgcg_p(const int* __restrict__ chunks, int nchunks,
+                                                   const uint8_t* __restrict__ flags,
+                                                   const T* __restrict__ z, T* __restrict__ p,
+                                                   const KScal* sc) {
+  if (sc->done) return;
+  const T beta = T(sc->beta);
+  const int n = chunk_node(chunks, nchunks);
+  if (n < 0) return;
+  p[n] = (flags[n] & kMgRow) ? T(z[n] + beta * p[n]) : T(0);
+}
+
+}  // namespace ibfe

@@ -72,8 +72,8 @@ int build_plan(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* para
     err = "precision must be 0 (FP64) or 1 (FP32 inner / FP64 refinement)";
     return IBFE_EINVAL;
   }
-  if (pr.precond != 0 || pr.advection != 0) {
-    err = "only precond = 0 (Jacobi) and advection = 0 (semi-implicit) are supported";
+  if ((pr.precond != 0 && pr.precond != 2) || pr.advection != 0) {
+    err = "precond must be 0 (Jacobi) or 2 (multigrid); advection must be 0 (semi-implicit)";
     return IBFE_EINVAL;
   }
   P.nx = grid->nx;
@@ -359,6 +359,10 @@ int build_plan(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* para
       }
       P.G_ptr.push_back(int64_t(P.G_col.size()));
     }
+  }
+  if (P.params.precond == 2) {
+    int rc = build_multigrid(P, err);
+    if (rc) return rc;
   }
   return IBFE_OK;
 }

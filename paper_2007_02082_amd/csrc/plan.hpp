@@ -14,6 +14,25 @@ constexpr int kChunk = 64;      // nodes per chunk (one wavefront)
 constexpr int kMaxHarmonics = 16;
 constexpr int kMaxFloating = 8; // outlet-less connected parts supported
 
+// One level of the geometric multigrid hierarchy of the pressure Poisson
+// operator (level 0 = the grid itself).  Node flags use bit 0 = in P, bit 4 =
+// pressure unknown (P minus Dirichlet).
+struct MGLevel {
+  int nx = 0, ny = 0, nz = 0;
+  double h = 0.0;
+  int64_t N = 0, sy = 0, sz = 0;
+  std::vector<uint8_t> emask, flags;
+  std::vector<int32_t> chunks;    // 64-node chunks holding a node of P
+  std::vector<int32_t> zitems;    // z-blocked column items holding a node of P
+  int cpp = 0;                    // chunks per plane of the column items
+  std::vector<int64_t> unknowns;  // ids of pressure unknowns (coarsest level only)
+  std::vector<double> inv;        // dense inverse on `unknowns` (coarsest level only)
+};
+
+constexpr uint8_t kMgP = 1u, kMgPp = 16u;
+constexpr int kZBPlanes = 8;     // planes per z-blocked column item
+constexpr int kMgCoarsestMax = 512;
+
 struct Plan {
   // grid
   int nx = 0, ny = 0, nz = 0;
@@ -51,7 +70,15 @@ struct Plan {
   std::vector<int64_t> sp_ptr;       // CSR rows over sp_node: (point, weight)
   std::vector<int32_t> sp_pt;
   std::vector<double> sp_w;
+  // multigrid hierarchy of the pressure operator (empty unless precond == 2)
+  std::vector<MGLevel> mg;
 };
+
+// Build the multigrid hierarchy from level 0 (already holding emask/flags).
+int build_multigrid(Plan& plan, std::string& err);
+// z-blocked column items of a level (kZBPlanes planes x 64 in-plane nodes).
+void column_items(const std::vector<uint8_t>& emask, int64_t sz, int nplanes, std::vector<int32_t>& items,
+                  int& cpp);
 
 // Returns IBFE_OK or an error code with `err` set.
 int build_plan(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* params,

@@ -1,5 +1,4 @@
-// Z-blocked matrix-free apply of the symmetric masked Q1 forms (alpha M + beta K)
-// fused with the CG dot product p.q.
+// Z-blocked matrix-free apply of the symmetric masked Q1 forms (alpha M + beta K).
 //
 // A wavefront owns one "column item": 64 consecutive node ids of one z-plane
 // (a row segment in the x-fastest numbering, clamped to the plane) and walks it
@@ -8,7 +7,8 @@
 // instead of 27 gathers, and the y/z row addresses are shared by the x shifts.
 // When every lane of the wavefront sits in the interior (all 8 cells kept) the
 // constant 27-point stencil is used; otherwise the per-neighbour kept-cell
-// counts are evaluated.
+// counts are evaluated.  The per-node result is handed to an epilogue (CG
+// product with dot, residual, Chebyshev smoothing step).
 #pragma once
 
 #include "kernels.hpp"
@@ -17,92 +17,128 @@ namespace ibfe {
 
 constexpr int kZB = 8;
 
+// Symmetric masked operator of one grid level.
 template <typename T>
-__device__ __forceinline__ void load_plane(const T* __restrict__ x, int node, int sy, T (&w)[9]) {
-#pragma unroll
-  for (int y = -1; y <= 1; ++y) {
-    const T* row = x + (node + y * sy);
-    w[(y + 1) * 3 + 0] = row[-1];
-    w[(y + 1) * 3 + 1] = row[0];
-    w[(y + 1) * 3 + 2] = row[1];
-  }
-}
+struct ZOp {
+  const uint8_t* emask;
+  const uint8_t* flags;
+  uint32_t rowbit;
+  int sy, sz, nplanes, cpp;
+  T c[4];
+};
 
-// y = sum_o cw(o) x(o) over the window planes lo (z-1), mid (z), hi (z+1).
-template <typename T>
-__device__ __forceinline__ T window_apply(const T (&lo)[9], const T (&mid)[9], const T (&hi)[9],
-                                          uint32_t e, bool interior, const T (&c)[4]) {
-  const T* pl[3] = {lo, mid, hi};
-  if (interior) {
-    T s[4] = {T(0), T(0), T(0), T(0)};
-#pragma unroll
-    for (int z = 0; z < 3; ++z)
-#pragma unroll
-      for (int k = 0; k < 9; ++k) {
-        const int ox = k % 3 - 1, oy = k / 3 - 1, oz = z - 1;
-        const int t = (ox != 0) + (oy != 0) + (oz != 0);
-        s[t] += pl[z][k];
-      }
-    return c[0] * T(8) * s[0] + c[1] * T(4) * s[1] + c[2] * T(2) * s[2] + c[3] * s[3];
-  }
-  T acc = T(0);
-#pragma unroll
-  for (int z = 0; z < 3; ++z)
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      const int ox = k % 3 - 1, oy = k / 3 - 1, oz = z - 1;
-      const int t = (ox != 0) + (oy != 0) + (oz != 0);
-      acc += c[t] * T(__builtin_popcount(e & compat(ox, oy, oz))) * pl[z][k];
-    }
-  return acc;
-}
-
-// q = A p on rows (0 elsewhere), partial p.q.  items: plane_block * cpp + chunk.
-template <typename T, int NC>
-__global__ __launch_bounds__(kBlock) void k_cg_q_zb(const int* __restrict__ items, int nitems, int cpp,
-                                                    int nplanes, OpSym<T, NC> op,
-                                                    const T* __restrict__ p, T* __restrict__ q,
-                                                    double* __restrict__ partials, const KScal* sc) {
-  if (sc->done) return;
+// Walk the column items of this block; epi(node, lane_ok, row, emask, Ax, x_centre).
+// All kZB + 2 planes of an item are loaded before any output is formed, so a
+// wavefront keeps up to 9 (kZB + 2) row loads in flight (memory-level
+// parallelism within the wavefront instead of one latency per plane).
+template <typename T, class Epi>
+__device__ __forceinline__ void zb_walk(const int* __restrict__ items, int nitems, const ZOp<T>& op,
+                                        const T* __restrict__ x, Epi& epi) {
   const int lane = threadIdx.x & 63;
   const int sy = op.sy, sz = op.sz;
   const T c[4] = {op.c[0], op.c[1], op.c[2], op.c[3]};
-  double dot[1] = {0.0};
   const ChunkRange cr = block_chunks(nitems);
   for (int it = cr.c0 + int(threadIdx.x >> 6); it < cr.c1; it += kWaves) {
     const int item = items[it];
-    const int pb = item / cpp, ch = item - pb * cpp;
+    const int pb = item / op.cpp, ch = item - pb * op.cpp;
     const int inplane = ch * 64 + lane;
     const bool lane_ok = inplane < sz;
     const int k0 = pb * kZB;
-    const int kend = min(kZB, nplanes - k0);
+    const int kend = min(kZB, op.nplanes - k0);
     const int base = k0 * sz + (lane_ok ? inplane : sz - 1);
+    T w[kZB + 2][9];
 #pragma unroll
-    for (int d = 0; d < NC; ++d) {
-      const T* pd = p + d * op.stride;
-      T* qd = q + d * op.stride;
-      T w0[9], w1[9], w2[9];
-      load_plane(pd, base - sz, sy, w0);
-      load_plane(pd, base, sy, w1);
-      for (int k = 0; k < kend; ++k) {
-        const int node = base + k * sz;
-        load_plane(pd, node + sz, sy, w2);
-        const uint32_t e = op.emask[node];
-        const bool rw = lane_ok && (op.flags[node] & op.rowbit);
-        const bool interior = __all((!lane_ok) || e == 0xFFu);
-        const T y = window_apply<T>(w0, w1, w2, e, interior, c);
-        const T qv = rw ? y : T(0);
-        if (lane_ok) qd[node] = qv;
-        dot[0] += double(w1[4]) * double(qv);
+    for (int j = 0; j < kZB + 2; ++j)
+      if (j < kend + 2) load_plane(x, base + (j - 1) * sz, sy, w[j]);
+    uint32_t em[kZB];
+    uint32_t fl[kZB];
 #pragma unroll
-        for (int j = 0; j < 9; ++j) {
-          w0[j] = w1[j];
-          w1[j] = w2[j];
-        }
+    for (int k = 0; k < kZB; ++k)
+      if (k < kend) {
+        em[k] = op.emask[base + k * sz];
+        fl[k] = op.flags[base + k * sz];
       }
+#pragma unroll
+    for (int k = 0; k < kZB; ++k) {
+      if (k >= kend) break;
+      const int node = base + k * sz;
+      const uint32_t e = em[k];
+      const bool rw = lane_ok && (fl[k] & op.rowbit);
+      const bool interior = __all((!lane_ok) || e == 0xFFu);
+      const T y = window_apply<T>(w[k], w[k + 1], w[k + 2], e, interior, c);
+      epi(node, lane_ok, rw, e, y, w[k + 1][4]);
     }
   }
+}
+
+// q = A p on rows (0 elsewhere), partial p.q; NC identical components.
+template <typename T, int NC>
+__global__ __launch_bounds__(kBlock) void k_cg_q_zb(const int* __restrict__ items, int nitems, ZOp<T> op,
+                                                    int64_t stride, const T* __restrict__ p,
+                                                    T* __restrict__ q, double* __restrict__ partials,
+                                                    const KScal* sc) {
+  if (sc->done) return;
+  double dot[1] = {0.0};
+#pragma unroll
+  for (int d = 0; d < NC; ++d) {
+    T* qd = q + d * stride;
+    auto epi = [&](int node, bool ok, bool rw, uint32_t, T y, T xc) {
+      const T qv = rw ? y : T(0);
+      if (ok) qd[node] = qv;
+      dot[0] += double(xc) * double(qv);
+    };
+    zb_walk<T>(items, nitems, op, p + d * stride, epi);
+  }
   block_partials<1>(dot, partials);
+}
+
+// r = b - A x on rows, 0 elsewhere (multigrid residual).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_zb_resid(const int* __restrict__ items, int nitems, ZOp<T> op,
+                                                     const T* __restrict__ x, const T* __restrict__ b,
+                                                     T* __restrict__ r, const KScal* sc) {
+  if (sc->done) return;
+  auto epi = [&](int node, bool ok, bool rw, uint32_t, T y, T) {
+    if (ok) r[node] = rw ? T(b[node] - y) : T(0);
+  };
+  zb_walk<T>(items, nitems, op, x, epi);
+}
+
+// Chebyshev-Jacobi step on rows, NC identical components (planes of `stride`):
+//   d <- c1 d + c2 D^-1 (b - A x_in),  x_out = x_in + d;  0 off rows.
+// With DOT, also the partial sum of b . x_out (the preconditioned residual dot).
+template <typename T, bool DOT, int NC = 1>
+__global__ __launch_bounds__(kBlock) void k_zb_cheb(const int* __restrict__ items, int nitems, ZOp<T> op,
+                                                    const T* __restrict__ x_in, const T* __restrict__ b,
+                                                    T* __restrict__ d, T* __restrict__ x_out, T c1, T c2,
+                                                    double* __restrict__ partials, const KScal* sc,
+                                                    int64_t stride = 0) {
+  if (sc && sc->done) return;
+  double dot[1] = {0.0};
+  const T c0 = op.c[0];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    const T* bq = b + q * stride;
+    T* dq = d + q * stride;
+    T* xq = x_out + q * stride;
+    auto epi = [&](int node, bool ok, bool rw, uint32_t e, T y, T xc) {
+      if (!ok) return;
+      if (rw) {
+        const T dinv = T(1) / (c0 * T(__builtin_popcount(e)));
+        const T dold = (c1 != T(0)) ? dq[node] : T(0);
+        const T dn = c1 * dold + c2 * dinv * (bq[node] - y);
+        const T xn = xc + dn;
+        dq[node] = dn;
+        xq[node] = xn;
+        if (DOT) dot[0] += double(bq[node]) * double(xn);
+      } else {
+        dq[node] = T(0);
+        xq[node] = T(0);
+      }
+    };
+    zb_walk<T>(items, nitems, op, x_in + q * stride, epi);
+  }
+  if (DOT) block_partials<1>(dot, partials);
 }
 
 }  // namespace ibfe

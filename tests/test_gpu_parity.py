@@ -253,3 +253,27 @@ def test_step_parity_mixed_poiseuille_16x16x64():
     _check_steps(out, TOL_MIXED, case.name + "/mixed")
     st = out[-1]["stats"]
     assert st["s3_outer"] >= 1 and st["s3_res"] <= 1e-8
+
+
+# ---------------------------------------------------------------------------
+# multigrid-preconditioned pressure solve (precond = 2): same discrete solution
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision,tol", [(0, TOL64), (1, TOL_MIXED)])
+@pytest.mark.parametrize("make", [lambda: synth.random_blob_case(seed=3),
+                                  lambda: synth.closed_box(8),
+                                  lambda: synth.small_cylinder(8, 16, pulsatile=True, nsteps=3)])
+def test_step_parity_multigrid_small(make, precision, tol):
+    case = make()
+    say("case", case.name, "multigrid, precision", precision)
+    _, out = run_pair(case, 3, precision=precision, precond=2)
+    _check_steps(out, tol, case.name + "/mg")
+
+
+@pytest.mark.parametrize("precision,tol", [(0, TOL64), (1, TOL_MIXED)])
+def test_step_parity_multigrid_poiseuille_16x16x64(precision, tol):
+    case = synth.poiseuille_c1()
+    say("case", case.name, "multigrid, precision", precision)
+    _, out = run_pair(case, case.nsteps, precision=precision, precond=2)
+    _check_steps(out, tol, case.name + "/mg")
+    assert out[-1]["stats"]["s3_iters"] < 60
