@@ -77,6 +77,52 @@ def cpu_baseline(seconds_hint: float = 15.0) -> dict:
                       f"node ratio {scale:.2f} to the 64x64x512 grid"}
 
 
+def serve_stream(n: int, slots: int, nsteps: int) -> dict:
+    """Serving stream: n seeded requests (cylinder / aneurysm / Y-branch vessels, radius
+    0.4-2.5, grids 32^3 .. 128x128x256, 50 steps each, mixed precision, multigrid) submitted
+    at their Poisson arrival times (4 per second) to a server with `slots` concurrent
+    slots; latency = completion - submission, solves/s = n / (last completion - first
+    submission)."""
+    import numpy as np
+
+    import paper_2007_02082_amd as ibfe
+    import synth
+
+    reqs = synth.request_stream(n=n, nsteps=nsteps)
+    kws = [ibfe.inputs_from_case(r.case, precision=1, precond=2) for r in reqs]
+    srv = ibfe.Server(max_slots=slots)
+    ids = []
+    t0 = time.perf_counter()
+    for r, kw in zip(reqs, kws):
+        delay = r.arrival - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        ids.append(srv.submit(nsteps, **kw))
+    res = [srv.wait(i) for i in ids]
+    peak = srv.peak_concurrency()
+    for i, r in zip(ids, res):
+        if r["status"] == ibfe.REQ_DONE:
+            srv.fetch(i, r["n_u"], r["n_p"])
+    srv.close()
+    failed = sum(r["status"] != ibfe.REQ_DONE for r in res)
+    lat = np.array([r["t_done"] - r["t_submit"] for r in res])
+    wait = np.array([r["t_admit"] - r["t_submit"] for r in res])
+    span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
+    busy = sum(r["t_done"] - r["t_admit"] for r in res)
+    nodes = [int(kw["node_mask"].size) for kw in kws]
+
+    def nearest_rank(a, q):
+        a = np.sort(a)
+        return float(a[max(0, int(np.ceil(q * len(a))) - 1)])
+
+    return {"requests": n, "failed": failed, "steps_each": nsteps, "slots": slots,
+            "solves_per_s": round(n / span, 3), "p50_latency_s": round(nearest_rank(lat, 0.5), 3),
+            "p99_latency_s": round(nearest_rank(lat, 0.99), 3), "mean_latency_s": round(float(lat.mean()), 3),
+            "mean_admission_wait_s": round(float(wait.mean()), 3),
+            "mean_concurrency": round(busy / span, 2), "peak_concurrency": peak,
+            "wall_s": round(span, 2), "grid_nodes_total": int(sum(nodes))}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +134,10 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", action="store_true",
                     help="also run the same steps in FP64 mode and report the difference")
+    ap.add_argument("--serve", action="store_true",
+                    help="also run the serving stream (64 requests, Poisson arrivals at 4/s)")
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the run, copy a device buffer of this size 5 times (a plain copy "
                          "kernel of known size for scaling hardware byte counters)")
@@ -169,6 +219,8 @@ def main() -> int:
         "roofline": roof,
     }
     out.update(extra)
+    if args.serve:
+        out["serving"] = serve_stream(args.serve_requests, args.serve_slots, 50)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

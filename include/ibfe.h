@@ -231,6 +231,62 @@ int ibfe_apply(ibfe_ctx* ctx, int op, int precision, const double* x, double* y,
 void ibfe_destroy(ibfe_ctx* ctx);
 const char* ibfe_last_error(void);
 
+/* ---- serving: continuous batching of independent flow solves ------------- */
+
+/* One flow solve: the inputs of ibfe_create plus the number of steps, starting
+ * from rest (u = 0, p = 0) at time t0.  All arrays are copied by submit. */
+typedef struct ibfe_request {
+  const ibfe_grid* grid;
+  const ibfe_ib* ib;
+  const ibfe_params* params;
+  const ibfe_inlet* inlet;
+  int32_t nsteps;
+  double t0;
+} ibfe_request;
+
+#define IBFE_REQ_QUEUED 0
+#define IBFE_REQ_RUNNING 1
+#define IBFE_REQ_DONE 2
+#define IBFE_REQ_FAILED 3
+
+/* Progress and timing of a request (times in seconds since server creation). */
+typedef struct ibfe_result {
+  int32_t status;       /* IBFE_REQ_*                                        */
+  int32_t error;        /* IBFE_E* code when FAILED                          */
+  int64_t n_u, n_p;     /* sizes of the fetched arrays (valid when DONE)     */
+  size_t footprint;     /* device bytes reserved for the request            */
+  double t_submit, t_admit, t_done;
+  ibfe_stats stats;     /* statistics of the last step                       */
+} ibfe_result;
+
+typedef struct ibfe_server ibfe_server;
+
+/* Device bytes a request reserves (estimate from the grid size, the number
+ * of Lagrangian points, precision and preconditioner; an upper bound of what
+ * its context allocates). */
+int ibfe_request_footprint(const ibfe_request* req, size_t* bytes);
+
+/* Create a server on the current HIP device with max_slots worker slots (each
+ * slot runs one request at a time on its own HIP stream; slots run
+ * concurrently, so admitted requests overlap on the GPU).  budget_bytes caps
+ * the summed footprint of running requests (0 = 90 % of the free device
+ * memory).  Requests are admitted first-in first-out as slots and memory free
+ * up; a request larger than the budget fails with IBFE_ENOMEM at submit. */
+int ibfe_server_create(size_t budget_bytes, int32_t max_slots, ibfe_server** out);
+/* Queue a request; returns at once with its id. */
+int ibfe_server_submit(ibfe_server* srv, const ibfe_request* req, int64_t* id);
+/* Current status of a request (non-blocking). */
+int ibfe_server_poll(ibfe_server* srv, int64_t id, ibfe_result* out);
+/* Block until the request is DONE or FAILED, or timeout_s elapses (< 0: no limit). */
+int ibfe_server_wait(ibfe_server* srv, int64_t id, double timeout_s, ibfe_result* out);
+/* Copy the final state of a DONE request (canonical order, host memory; any
+ * pointer may be NULL) and release it; node_ids receives n_u ids. */
+int ibfe_server_fetch(ibfe_server* srv, int64_t id, double* u, double* p, int64_t* node_ids);
+/* Largest number of requests that ran at the same time so far. */
+int ibfe_server_peak_concurrency(const ibfe_server* srv, int32_t* peak);
+/* Finish running requests, fail the queued ones, release everything. */
+void ibfe_server_destroy(ibfe_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

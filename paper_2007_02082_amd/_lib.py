@@ -62,6 +62,24 @@ class Stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Request(C.Structure):
+    _fields_ = [("grid", C.POINTER(Grid)), ("ib", C.POINTER(IB)), ("params", C.POINTER(Params)),
+                ("inlet", C.POINTER(Inlet)), ("nsteps", C.c_int32), ("t0", C.c_double)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("error", C.c_int32), ("n_u", C.c_int64), ("n_p", C.c_int64),
+                ("footprint", C.c_size_t), ("t_submit", C.c_double), ("t_admit", C.c_double),
+                ("t_done", C.c_double), ("stats", Stats)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "stats"}
+        d["stats"] = self.stats.as_dict()
+        return d
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
+
 # name -> (restype, argtypes); the full exported surface of include/ibfe.h
 SIGNATURES = {
     "ibfe_plan_create": (C.c_int, [C.POINTER(Grid), C.POINTER(IB), C.POINTER(Params),
@@ -83,6 +101,14 @@ SIGNATURES = {
     "ibfe_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
     "ibfe_destroy": (None, [C.c_void_p]),
     "ibfe_last_error": (C.c_char_p, []),
+    "ibfe_request_footprint": (C.c_int, [C.POINTER(Request), C.POINTER(C.c_size_t)]),
+    "ibfe_server_create": (C.c_int, [C.c_size_t, C.c_int32, C.POINTER(C.c_void_p)]),
+    "ibfe_server_submit": (C.c_int, [C.c_void_p, C.POINTER(Request), i64p]),
+    "ibfe_server_poll": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(Result)]),
+    "ibfe_server_wait": (C.c_int, [C.c_void_p, C.c_int64, C.c_double, C.POINTER(Result)]),
+    "ibfe_server_fetch": (C.c_int, [C.c_void_p, C.c_int64, dp, dp, i64p]),
+    "ibfe_server_peak_concurrency": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "ibfe_server_destroy": (None, [C.c_void_p]),
 }
 
 _lib = None
@@ -310,6 +336,70 @@ class Solver:
     def close(self):
         if getattr(self, "_h", None):
             load().ibfe_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def request_footprint(**kw) -> int:
+    """Device bytes a request reserves (host-only estimate)."""
+    nsteps = kw.pop("nsteps", 1)
+    inp = _Inputs(**kw)
+    req = Request(C.pointer(inp.grid), C.pointer(inp.ib), C.pointer(inp.params), C.pointer(inp.inlet),
+                  int(nsteps), 0.0)
+    out = C.c_size_t()
+    check(load().ibfe_request_footprint(C.byref(req), C.byref(out)))
+    return out.value
+
+
+class Server:
+    """Continuous-batching server (ibfe_server_*): requests run concurrently in
+    worker slots, each on its own HIP stream, admitted by device footprint."""
+
+    def __init__(self, budget_bytes: int = 0, max_slots: int = 4):
+        lib = load()
+        h = C.c_void_p()
+        check(lib.ibfe_server_create(C.c_size_t(int(budget_bytes)), int(max_slots), C.byref(h)))
+        self._h = h
+
+    def submit(self, nsteps: int, t0: float = 0.0, **kw) -> int:
+        inp = _Inputs(**kw)
+        req = Request(C.pointer(inp.grid), C.pointer(inp.ib), C.pointer(inp.params), C.pointer(inp.inlet),
+                      int(nsteps), float(t0))
+        rid = C.c_int64()
+        check(load().ibfe_server_submit(self._h, C.byref(req), C.byref(rid)))
+        return rid.value
+
+    def poll(self, rid: int) -> dict:
+        r = Result()
+        check(load().ibfe_server_poll(self._h, int(rid), C.byref(r)))
+        return r.as_dict()
+
+    def wait(self, rid: int, timeout: float = -1.0) -> dict:
+        r = Result()
+        check(load().ibfe_server_wait(self._h, int(rid), float(timeout), C.byref(r)))
+        return r.as_dict()
+
+    def fetch(self, rid: int, n_u: int, n_p: int):
+        u = np.empty(3 * n_u)
+        p = np.empty(n_p)
+        ids = np.empty(n_u, np.int64)
+        check(load().ibfe_server_fetch(self._h, int(rid), _ptr(u, C.c_double), _ptr(p, C.c_double),
+                                       _ptr(ids, C.c_int64)))
+        return u.reshape(3, n_u), p, ids
+
+    def peak_concurrency(self) -> int:
+        v = C.c_int32()
+        check(load().ibfe_server_peak_concurrency(self._h, C.byref(v)))
+        return v.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().ibfe_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -2,8 +2,8 @@
 
     python -m paper_2007_02082_amd.build        # or build() from Python
 
-The host set-up (plan.cpp) is compiled by g++; the kernels and the C ABI
-(ibfe.hip) by hipcc for gfx950 only.
+The host set-up (plan.cpp, mg_plan.cpp) is compiled by g++; the kernels, the C
+ABI (ibfe.hip) and the serving loop (server.hip) by hipcc for gfx950 only.
 """
 from __future__ import annotations
 
@@ -47,9 +47,10 @@ def build(verbose: bool = False) -> str:
         _run(["g++", *CXX_FLAGS, *inc, "-I", os.path.join(ROCM, "include"), "-c",
               os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)
-    ibfe_o = os.path.join(BUILD, "ibfe.o")
-    _run([HIPCC, *HIP_FLAGS, *inc, "-c", os.path.join(CSRC, "ibfe.hip"), "-o", ibfe_o], verbose)
-    objs.append(ibfe_o)
+    for src in ("ibfe.hip", "server.hip"):
+        obj = os.path.join(BUILD, src.replace(".hip", ".o"))
+        _run([HIPCC, *HIP_FLAGS, *inc, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
+        objs.append(obj)
     tmp = LIB + ".tmp"
     _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)

@@ -19,12 +19,18 @@
 
 using namespace ibfe;
 
+namespace ibfe {
+// Thread-local message of the last failure (shared by every translation unit).
+std::string& last_error_message() {
+  thread_local std::string msg;
+  return msg;
+}
+}  // namespace ibfe
+
 namespace {
 
-thread_local std::string g_err;
-
 int fail(int code, const std::string& msg) {
-  g_err = msg;
+  ibfe::last_error_message() = msg;
   return code;
 }
 
@@ -1138,7 +1144,7 @@ int copy_out(ibfe_ctx& c, const double* dense, int nc, double* dst, int on_devic
 
 extern "C" {
 
-const char* ibfe_last_error(void) { return g_err.c_str(); }
+const char* ibfe_last_error(void) { return ibfe::last_error_message().c_str(); }
 
 int ibfe_plan_create(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* params,
                      const ibfe_inlet* inlet, ibfe_plan** out) {

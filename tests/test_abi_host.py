@@ -89,3 +89,21 @@ def test_input_errors():
     bad = dict(kw, X=far, U_B=None)
     with pytest.raises(ibfe.IbfeError, match="ESINGULAR"):
         ibfe.Plan(**bad)
+
+
+def test_request_footprint_estimate_grows_with_size():
+    small = ibfe.request_footprint(**ibfe.inputs_from_case(synth.small_cylinder(8, 16), precision=1, precond=2))
+    big = ibfe.request_footprint(**ibfe.inputs_from_case(synth.small_cylinder(16, 32), precision=1, precond=2))
+    fp64 = ibfe.request_footprint(**ibfe.inputs_from_case(synth.small_cylinder(16, 32), precision=0, precond=2))
+    assert 0 < small < big
+    assert fp64 < big          # the FP32 work space is extra
+    c2 = ibfe.request_footprint(**ibfe.inputs_from_case(synth.pulsatile_c2(), precision=1, precond=2))
+    assert 1e9 < c2 < 4e9      # 64x64x512: a few GB of the 288 GB
+
+
+def test_serving_stream_is_seeded_and_sized():
+    a = synth.request_stream(build=False)
+    b = synth.request_stream(build=False)
+    assert [(r.kind, r.radius, r.arrival) for r in a] == [(r.kind, r.radius, r.arrival) for r in b]
+    assert len(a) == 64 and 8.0 < a[-1].arrival < 24.0   # Poisson arrivals at 4 per second
+    assert {r.kind for r in a} == {"cylinder", "aneurysm", "branch"}
