@@ -111,12 +111,19 @@ def dirichlet_values(sets: Sets, mask: np.ndarray, inlet_ids: np.ndarray,
     for k in range(1, K + 1):
         val += inlet_shape[2 * k - 1] * np.cos(k * omega * t)
         val -= inlet_shape[2 * k] * np.sin(k * omega * t)
-    g[:, inlet_ids] = val.T
+    keep = sets.in_P[inlet_ids]                      # all of them on a uniform grid
+    g[:, inlet_ids[keep]] = val[keep].T
     return g
 
 
-def check_inlet_table(sets: Sets, mask: np.ndarray, inlet_ids: np.ndarray) -> None:
-    ok = (sets.in_P[inlet_ids] & (sets.tag[inlet_ids] == TAG_INLET) & (mask[inlet_ids] == 1))
+def check_inlet_table(sets: Sets, mask: np.ndarray, inlet_ids: np.ndarray,
+                      skip_non_mesh: bool = False) -> None:
+    """Every listed node must be an in-vessel inlet node of P.  On a refined lattice
+    (skip_non_mesh) listed points that are not nodes of P (interior points of unrefined
+    cells, hanging nodes) carry no unknown and are skipped."""
+    sel = sets.in_P[inlet_ids] if skip_non_mesh else np.ones(inlet_ids.size, bool)
+    ids = inlet_ids[sel]
+    ok = (sets.in_P[ids] & (sets.tag[ids] == TAG_INLET) & (mask[ids] == 1))
     if not ok.all():
         raise ValueError("inlet table lists a node that is not an in-vessel inlet node of P")
     if np.unique(inlet_ids).size != inlet_ids.size:

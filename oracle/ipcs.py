@@ -27,7 +27,7 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.csgraph as csgraph
 
-from . import fem, grid, ib, krylov
+from . import fem, grid, ib, krylov, refine
 
 
 @dataclasses.dataclass
@@ -44,29 +44,56 @@ class Problem:
     """Everything that depends only on the geometry and the parameters."""
 
     def __init__(self, nx, ny, nz, h, origin, node_mask, bc_tag, X, dS, U_B, rho, mu, dt,
-                 inlet_K, inlet_omega, inlet_ids, inlet_shape):
+                 inlet_K, inlet_omega, inlet_ids, inlet_shape, refine_cell=None):
         self.nx, self.ny, self.nz, self.h = nx, ny, nz, float(h)
         self.origin = np.asarray(origin, np.float64)
         self.mask = np.asarray(node_mask, np.uint8)
         self.rho, self.mu, self.dt = float(rho), float(mu), float(dt)
-        self.sets = grid.derive_sets(nx, ny, nz, self.mask, bc_tag)
+        self.mesh = None
+        if refine_cell is not None:
+            # 2:1 refined band: every array lives on the fine lattice (spacing h/2)
+            self.mesh = refine.CompositeMesh(nx, ny, nz, h, self.mask, bc_tag, refine_cell)
+            self.sets = self.mesh.derive_sets(bc_tag)
+            self.ops = refine.CompositeOperators(self.mesh)
+            lat, hk = (2 * nx, 2 * ny, 2 * nz), self.h / 2.0
+        else:
+            self.sets = grid.derive_sets(nx, ny, nz, self.mask, bc_tag)
+            self.ops = fem.Operators(self.sets, self.h)
+            lat, hk = (nx, ny, nz), self.h
         if self.sets.P.size == 0:
             raise ValueError("empty domain: no kept cell")
         self.inlet_K, self.inlet_omega = int(inlet_K), float(inlet_omega)
         self.inlet_ids = np.asarray(inlet_ids, np.int64)
         self.inlet_shape = np.asarray(inlet_shape, np.float64)
-        grid.check_inlet_table(self.sets, self.mask, self.inlet_ids)
-        self.ops = fem.Operators(self.sets, self.h)
+        grid.check_inlet_table(self.sets, self.mask, self.inlet_ids, skip_non_mesh=self.mesh is not None)
         self.X = np.asarray(X, np.float64).reshape(-1, 3)
         self.dS = float(dS)
         self.U_B = np.zeros_like(self.X) if U_B is None else np.asarray(U_B, np.float64)
-        self.I = ib.interpolation_matrix(self.X, nx, ny, nz, self.h, self.origin)
+        self.I = ib.interpolation_matrix(self.X, *lat, hk, self.origin)
+        if self.mesh is not None:
+            self._check_support_in_fine_band()
         self._pressure_setup()
 
     @classmethod
     def from_case(cls, c):
         return cls(c.nx, c.ny, c.nz, c.h, c.origin, c.node_mask, c.bc_tag, c.X, c.dS, c.U_B,
-                   c.rho, c.mu, c.dt, c.inlet_K, c.inlet_omega, c.inlet_ids, c.inlet_shape)
+                   c.rho, c.mu, c.dt, c.inlet_K, c.inlet_omega, c.inlet_ids, c.inlet_shape,
+                   getattr(c, "refine_cell", None))
+
+    def _check_support_in_fine_band(self):
+        """Reading of the refined band: the kernel support of every Lagrangian point
+        lies in the closure of refined cells and holds no hanging node."""
+        m = self.mesh
+        ok = np.zeros(m.N, bool)
+        bk, bj, bi = np.nonzero(m.refine)
+        for dz in range(3):
+            for dy in range(3):
+                for dx in range(3):
+                    ok[(2 * bi + dx) + m.sy * ((2 * bj + dy) + (m.ly + 1) * (2 * bk + dz))] = True
+        ok &= ~m.is_hanging
+        cols = self.I.indices
+        if cols.size and not ok[cols].all():
+            raise ValueError("a Lagrangian point's kernel support leaves the refined band")
 
     # -- step 5 helpers -------------------------------------------------------
     def _pressure_setup(self):

@@ -1,5 +1,5 @@
 """Seeded synthetic workloads (inputs only; no method arithmetic)."""
-from .cases import (Case, channel_case, shear_advection_case, TAG_INLET, TAG_NONE, TAG_OUTLET, TAG_WALL, closed_box,  # noqa: F401
+from .cases import (Case, channel_case, refined_cylinder, shear_advection_case, TAG_INLET, TAG_NONE, TAG_OUTLET, TAG_WALL, closed_box,  # noqa: F401
                     cylinder_case, poiseuille_c1, pulsatile_c2, random_blob_case,
                     small_cylinder)
 from .serving import GRIDS, Request, request_stream, vessel_case  # noqa: F401,E402

@@ -47,22 +47,26 @@ class Case:
     inlet_shape: np.ndarray     # (2K+1, n, 3) float64: W_0, then Re W_k, Im W_k per harmonic
     u0: np.ndarray              # (3, N) float64 initial velocity on every node
     p0: np.ndarray              # (N,) float64 initial pressure on every node
+    refine_cell: np.ndarray | None = None   # (nx*ny*nz,) uint8: base cells split 2:1
 
     @property
     def N(self) -> int:
-        return (self.nx + 1) * (self.ny + 1) * (self.nz + 1)
+        """Nodes of the grid the arrays live on (the fine lattice when refined)."""
+        f = 2 if self.refine_cell is not None else 1
+        return (f * self.nx + 1) * (f * self.ny + 1) * (f * self.nz + 1)
 
     @property
     def M(self) -> int:
         return int(self.X.shape[0])
 
     def node_coords(self) -> np.ndarray:
-        """(N,3) physical coordinates, x fastest."""
-        i = np.arange(self.nx + 1, dtype=np.float64)
-        j = np.arange(self.ny + 1, dtype=np.float64)
-        k = np.arange(self.nz + 1, dtype=np.float64)
+        """(N,3) physical coordinates of the array nodes, x fastest."""
+        f = 2 if self.refine_cell is not None else 1
+        i = np.arange(f * self.nx + 1, dtype=np.float64)
+        j = np.arange(f * self.ny + 1, dtype=np.float64)
+        k = np.arange(f * self.nz + 1, dtype=np.float64)
         K, J, I = np.meshgrid(k, j, i, indexing="ij")
-        xyz = np.stack([I.ravel(), J.ravel(), K.ravel()], axis=1) * self.h
+        xyz = np.stack([I.ravel(), J.ravel(), K.ravel()], axis=1) * (self.h / f)
         return xyz + self.origin[None, :]
 
 
@@ -320,4 +324,45 @@ def shear_advection_case(cells_x: int = 10, U: float = 0.8, force: float = 0.6,
     c.u0[2] = np.sin(math.pi * xyz[:, 0])
     c.u0[2][xface] = 0.0
     c.p0 = -force * xyz[:, 2]
+    return c
+
+
+def refined_cylinder(cells_xy: int = 8, cells_z: int = 8, length: float = 1.0, radius: float = 0.5,
+                     band: float = 0.2, width: float = 1.25, rho: float = 1.0, mu: float = 0.01,
+                     dt: float = 0.02, nsteps: int = 3, mask_all: bool = False) -> Case:
+    """Cylinder along z on a base grid whose cells within `band` of the wall are split
+    2:1 (cell centre distance to the wall).  Arrays live on the fine lattice (spacing
+    h/2): mask x^2 + y^2 < R^2, Lagrangian rings at spacing close to 2 h_f (= h) placed
+    at least 2 h_f inside the box, parabolic inlet on the lattice z = 0 face."""
+    h = width / cells_xy
+    if abs(h * cells_z - length) > 1e-12 * length:
+        raise ValueError("length must be a whole number of cells")
+    nx = ny = cells_xy
+    nz = cells_z
+    origin = np.array([-width / 2, -width / 2, 0.0])
+    ci = (np.arange(nx) + 0.5) * h + origin[0]
+    cz_, cy_, cx_ = np.meshgrid(np.arange(nz), ci, ci, indexing="ij")
+    rc = np.sqrt(cx_ ** 2 + cy_ ** 2)
+    refine = (np.abs(rc - radius) <= band).astype(np.uint8).ravel()
+    c = Case(name=f"refined_cyl_{nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz, h=h, origin=origin,
+             node_mask=np.zeros(0, np.uint8), bc_tag=None, X=np.zeros((0, 3)), dS=h * h, U_B=None,
+             rho=rho, mu=mu, dt=dt, nsteps=nsteps, inlet_K=0, inlet_omega=0.0,
+             inlet_ids=np.zeros(0, np.int64), inlet_shape=np.zeros((1, 0, 3)),
+             u0=np.zeros((3, 0)), p0=np.zeros(0), refine_cell=refine)
+    xyz = c.node_coords()
+    r2 = xyz[:, 0] ** 2 + xyz[:, 1] ** 2
+    c.node_mask = np.ones(c.N, np.uint8) if mask_all else (r2 < radius * radius).astype(np.uint8)
+    hf = h / 2
+    spacing = 2 * hf
+    nr = max(1, int(round((length - 4 * hf) / spacing)))
+    zl = 2 * hf + (np.arange(nr) + 0.5) * ((length - 4 * hf) / nr)
+    c.X = _ring_points(radius, zl, max(6, int(round(2 * math.pi * radius / spacing))))
+    c.dS = spacing * spacing
+    on_inlet = (xyz[:, 2] == 0.0) & (c.node_mask == 1)
+    ids = np.nonzero(on_inlet)[0].astype(np.int64)
+    shape = np.zeros((1, ids.size, 3))
+    shape[0, :, 2] = np.maximum(0.0, 1.0 - r2[ids] / (radius * radius))
+    c.inlet_ids, c.inlet_shape = ids, shape
+    c.u0 = np.zeros((3, c.N))
+    c.p0 = np.zeros(c.N)
     return c
