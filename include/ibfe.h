@@ -56,6 +56,7 @@ extern "C" {
 #define IBFE_FLAG_F 2u      /* free velocity node                               */
 #define IBFE_FLAG_DU 4u     /* velocity Dirichlet node                          */
 #define IBFE_FLAG_PDIR 8u   /* pressure Dirichlet (outlet) node                 */
+#define IBFE_FLAG_HANG 32u  /* hanging lattice node of a refined grid (not in P) */
 
 /*
  * Grid and domain reduction (Section 2.3: uniform Cartesian Eulerian nodes of
@@ -64,12 +65,29 @@ extern "C" {
  *   bc_tag    : N bytes of IBFE_TAG_*, or NULL for the defaults: z = 0 face
  *               inlet, z = nz face outlet, the x and y faces wall, wall winning
  *               on shared edges/corners.
- *   refine_cell: reserved, must be NULL.
+ *   refine_cell: nx*ny*nz bytes (cell c = i + nx*(j + ny*k)), 1 = split the
+ *               cell 2:1, or NULL for a uniform grid.
  * Velocity Dirichlet nodes D_u: nodes of P with mask 0 (value 0), wall-tagged
  * nodes of P (value 0), inlet-tagged nodes of P (inlet table value, else 0).
  * Free velocity nodes F = P \ D_u.  Pressure Dirichlet: outlet-tagged nodes of
  * P (pressure increment 0).  A connected part of the kept region without an
  * outlet node has its pressure increment normalised to zero nodal mean.
+ *
+ * Local 2:1 refinement (the paper refines its mesh near the immersed boundary,
+ * Section 4).  With refine_cell, nx, ny, nz and h describe the base grid and
+ * every node array (node_mask, bc_tag, inlet node ids, the canonical ids
+ * returned by the library) lives on the fine lattice of (2nx+1)(2ny+1)(2nz+1)
+ * nodes of spacing h/2, id n = i + (2nx+1)*(j + (2ny+1)*k).  Elements: the
+ * 2x2x2 children (side h/2) of flagged cells and the unflagged cells (side h),
+ * each kept when one of its 8 corners has mask 1.  A lattice node that is a
+ * corner of a kept child and lies strictly inside an edge or a face of a kept
+ * unflagged cell is hanging: its value is the mean of the 2 edge end points or
+ * the 4 face corners, and every operator is C^T A C with that constraint C.
+ * P = corners of kept elements minus hanging nodes; the sets above follow on
+ * the lattice.  The IB kernel uses the lattice spacing h/2, and every support
+ * node of every Lagrangian point must lie in the closure of a flagged cell and
+ * not be hanging (else IBFE_EINVAL).  Inlet table entries at lattice nodes
+ * outside P (interior points of unflagged cells, hanging nodes) are skipped.
  */
 typedef struct ibfe_grid {
   int32_t nx, ny, nz;
@@ -105,7 +123,8 @@ typedef struct ibfe_ib {
  *   rtol        : relative residual target of the velocity and pressure solves
  *                 (<= 0 selects 1e-13 in FP64 mode, 1e-8 in mixed mode)
  *   max_iters   : iteration cap per Krylov solve (<= 0 selects 20000)
- *   precond     : 0 = Jacobi (only value accepted by this version)
+ *   precond     : 0 = Jacobi; 2 = geometric multigrid V-cycle for the pressure
+ *                 increment (Jacobi for the other solves)
  *   advection   : 0 = semi-implicit u^n . grad u* (only value accepted)
  *   ib_rtol     : relative residual target of the IB force solve (<= 0: 1e-13)
  */

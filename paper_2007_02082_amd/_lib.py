@@ -14,7 +14,7 @@ IBFE_OK = 0
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOCONV", -5: "ENONFINITE", -6: "ESINGULAR"}
 FIELD_USTAR, FIELD_UIB, FIELD_PHI = 0, 1, 2
 OP_MASS, OP_STIFF, OP_GRAD, OP_DIV, OP_ADVDIFF, OP_INTERP, OP_SPREAD = range(7)
-FLAG_P, FLAG_F, FLAG_DU, FLAG_PDIR = 1, 2, 4, 8
+FLAG_P, FLAG_F, FLAG_DU, FLAG_PDIR, FLAG_HANG = 1, 2, 4, 8, 32
 
 u8p = C.POINTER(C.c_uint8)
 dp = C.POINTER(C.c_double)
@@ -160,15 +160,17 @@ class _Inputs:
 
     def __init__(self, nx, ny, nz, h, origin, node_mask, bc_tag, X, dS, U_B, rho, mu, dt,
                  inlet_K, inlet_omega, inlet_ids, inlet_shape, precision=0, rtol=0.0,
-                 max_iters=0, ib_rtol=0.0, precond=0, advection=0):
+                 max_iters=0, ib_rtol=0.0, precond=0, advection=0, refine_cell=None):
         self.mask = np.ascontiguousarray(node_mask, dtype=np.uint8)
+        self.refine = None if refine_cell is None else np.ascontiguousarray(refine_cell, dtype=np.uint8)
         self.tag = None if bc_tag is None else np.ascontiguousarray(bc_tag, dtype=np.uint8)
         self.X = np.ascontiguousarray(np.asarray(X, np.float64).reshape(-1, 3))
         self.UB = None if U_B is None else np.ascontiguousarray(np.asarray(U_B, np.float64).reshape(-1, 3))
         self.ids = np.ascontiguousarray(inlet_ids, dtype=np.int64)
         self.shape = np.ascontiguousarray(inlet_shape, dtype=np.float64)
         self.grid = Grid(int(nx), int(ny), int(nz), float(h), (C.c_double * 3)(*map(float, origin)),
-                         _ptr(self.mask, C.c_uint8), _ptr(self.tag, C.c_uint8), None)
+                         _ptr(self.mask, C.c_uint8), _ptr(self.tag, C.c_uint8),
+                         _ptr(self.refine, C.c_uint8))
         self.ib = IB(self.X.shape[0], _ptr(self.X, C.c_double) if self.X.size else None, float(dS),
                      _ptr(self.UB, C.c_double))
         self.params = Params(float(rho), float(mu), float(dt), int(precision), float(rtol),
@@ -184,7 +186,7 @@ def inputs_from_case(case, **kw) -> dict:
                 node_mask=case.node_mask, bc_tag=case.bc_tag, X=case.X, dS=case.dS, U_B=case.U_B,
                 rho=case.rho, mu=case.mu, dt=case.dt, inlet_K=case.inlet_K,
                 inlet_omega=case.inlet_omega, inlet_ids=case.inlet_ids,
-                inlet_shape=case.inlet_shape, **kw)
+                inlet_shape=case.inlet_shape, refine_cell=getattr(case, "refine_cell", None), **kw)
 
 
 class Plan:
@@ -197,7 +199,8 @@ class Plan:
         check(lib.ibfe_plan_create(C.byref(self._in.grid), C.byref(self._in.ib),
                                    C.byref(self._in.params), C.byref(self._in.inlet), C.byref(h)))
         self._h = h
-        self.N = (int(kw["nx"]) + 1) * (int(kw["ny"]) + 1) * (int(kw["nz"]) + 1)
+        f = 1 if kw.get("refine_cell") is None else 2   # refined: the fine lattice
+        self.N = (f * int(kw["nx"]) + 1) * (f * int(kw["ny"]) + 1) * (f * int(kw["nz"]) + 1)
 
     def sizes(self) -> dict:
         v = [C.c_int64() for _ in range(5)]

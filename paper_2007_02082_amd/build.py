@@ -2,7 +2,7 @@
 
     python -m paper_2007_02082_amd.build        # or build() from Python
 
-The host set-up (plan.cpp, mg_plan.cpp) is compiled by g++; the kernels, the C
+The host set-up (plan.cpp, mg_plan.cpp, refine_plan.cpp) is compiled by g++; the kernels, the C
 ABI (ibfe.hip) and the serving loop (server.hip) by hipcc for gfx950 only.
 """
 from __future__ import annotations
@@ -42,7 +42,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     inc = ["-I", INCLUDE, "-I", CSRC]
     objs = []
-    for src in ("plan.cpp", "mg_plan.cpp"):
+    for src in ("plan.cpp", "mg_plan.cpp", "refine_plan.cpp"):
         obj = os.path.join(BUILD, src.replace(".cpp", ".o"))
         _run(["g++", *CXX_FLAGS, *inc, "-I", os.path.join(ROCM, "include"), "-c",
               os.path.join(CSRC, src), "-o", obj], verbose)

@@ -1196,6 +1196,7 @@ int ibfe_create(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* par
   std::string err;
   int rc = build_plan(grid, ib, params, inlet, c->plan, err);
   if (rc) return fail(rc, err);
+  if (c->plan.refined) return fail(IBFE_EINVAL, "refined grids are not supported on the device yet");
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   if (alloc && alloc->alloc && alloc->free) {
     c->alloc = *alloc;

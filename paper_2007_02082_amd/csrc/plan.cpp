@@ -12,24 +12,21 @@ namespace {
 
 bool finite(double v) { return std::isfinite(v); }
 
-struct UnionFind {
-  std::vector<int64_t> parent;
-  explicit UnionFind(int64_t n) : parent(n) { std::iota(parent.begin(), parent.end(), 0); }
-  int64_t find(int64_t a) {
-    while (parent[a] != a) {
-      parent[a] = parent[parent[a]];
-      a = parent[a];
-    }
-    return a;
-  }
-  void unite(int64_t a, int64_t b) {
-    a = find(a);
-    b = find(b);
-    if (a != b) parent[std::max(a, b)] = std::min(a, b);
-  }
-};
-
 }  // namespace
+
+UnionFind::UnionFind(int64_t n) : parent(n) { std::iota(parent.begin(), parent.end(), 0); }
+int64_t UnionFind::find(int64_t a) {
+  while (parent[a] != a) {
+    parent[a] = parent[parent[a]];
+    a = parent[a];
+  }
+  return a;
+}
+void UnionFind::unite(int64_t a, int64_t b) {
+  a = find(a);
+  b = find(b);
+  if (a != b) parent[std::max(a, b)] = std::min(a, b);
+}
 
 // Four-point regularised delta of Eq. 18 (support |r| < 2).
 double delta4(double r) {
@@ -58,10 +55,6 @@ int build_plan(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* para
     err = "node_mask is required";
     return IBFE_EINVAL;
   }
-  if (grid->refine_cell) {
-    err = "refine_cell is not supported by this version (pass NULL)";
-    return IBFE_EINVAL;
-  }
   const ibfe_params& pr = *params;
   if (!(pr.rho > 0.0) || !(pr.mu > 0.0) || !(pr.dt > 0.0) || !finite(pr.rho) ||
       !finite(pr.mu) || !finite(pr.dt)) {
@@ -76,10 +69,27 @@ int build_plan(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* para
     err = "precond must be 0 (Jacobi) or 2 (multigrid); advection must be 0 (semi-implicit)";
     return IBFE_EINVAL;
   }
-  P.nx = grid->nx;
-  P.ny = grid->ny;
-  P.nz = grid->nz;
-  P.h = grid->h;
+  P.refined = grid->refine_cell != nullptr;
+  if (P.refined) {
+    // every node array lives on the fine lattice of spacing h/2
+    if (grid->nx > (1 << 29) || grid->ny > (1 << 29) || grid->nz > (1 << 29)) {
+      err = "grid too large";
+      return IBFE_EINVAL;
+    }
+    P.bnx = grid->nx;
+    P.bny = grid->ny;
+    P.bnz = grid->nz;
+    P.hb = grid->h;
+    P.nx = 2 * grid->nx;
+    P.ny = 2 * grid->ny;
+    P.nz = 2 * grid->nz;
+    P.h = 0.5 * grid->h;
+  } else {
+    P.nx = grid->nx;
+    P.ny = grid->ny;
+    P.nz = grid->nz;
+    P.h = grid->h;
+  }
   for (int d = 0; d < 3; ++d) P.origin[d] = grid->origin[d];
   P.sy = int64_t(P.nx) + 1;
   P.sz = P.sy * (int64_t(P.ny) + 1);
@@ -88,6 +98,15 @@ int build_plan(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* para
   if (P.N + 4 * (P.sz + P.sy + 1) + 4 * kChunk > (int64_t(1) << 31) - 1) {
     err = "grid too large for 32-bit node indexing";
     return IBFE_EINVAL;
+  }
+  if (P.refined) {
+    const int64_t nc = int64_t(P.bnx) * P.bny * P.bnz;
+    P.refine.assign(grid->refine_cell, grid->refine_cell + nc);
+    for (uint8_t v : P.refine)
+      if (v > 1) {
+        err = "refine_cell values must be 0 or 1";
+        return IBFE_EINVAL;
+      }
   }
   P.params = pr;
   if (P.params.rtol <= 0.0) P.params.rtol = pr.precision == 0 ? 1e-13 : 1e-8;
@@ -124,35 +143,42 @@ int build_plan(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* para
         }
   }
 
-  // kept cells -> per-node cell bits and the set P
-  P.emask.assign(N, 0);
-  P.n_kept = 0;
+  // kept cells (elements) -> per-node cell bits, hanging nodes and the set P
   UnionFind uf(N);
-  for (int k = 0; k < nz; ++k)
-    for (int j = 0; j < ny; ++j)
-      for (int i = 0; i < nx; ++i) {
-        int64_t c0 = i + P.sy * j + P.sz * k;
-        bool kept = false;
-        for (int a = 0; a < 8; ++a) {
-          int64_t n = c0 + (a & 1) + P.sy * ((a >> 1) & 1) + P.sz * ((a >> 2) & 1);
-          if (P.mask[n]) kept = true;
+  if (P.refined) {
+    int rc = build_composite_cells(P, uf, err);
+    if (rc) return rc;
+  } else {
+    P.emask.assign(N, 0);
+    P.n_kept = 0;
+    for (int k = 0; k < nz; ++k)
+      for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+          int64_t c0 = i + P.sy * j + P.sz * k;
+          bool kept = false;
+          for (int a = 0; a < 8; ++a) {
+            int64_t n = c0 + (a & 1) + P.sy * ((a >> 1) & 1) + P.sz * ((a >> 2) & 1);
+            if (P.mask[n]) kept = true;
+          }
+          if (!kept) continue;
+          ++P.n_kept;
+          for (int a = 0; a < 8; ++a) {
+            int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
+            int64_t n = c0 + ax + P.sy * ay + P.sz * az;
+            // the cell sits on the side s = 1 - a of corner node n
+            int s = (1 - ax) + 2 * (1 - ay) + 4 * (1 - az);
+            P.emask[n] |= uint8_t(1u << s);
+            uf.unite(c0, n);
+          }
         }
-        if (!kept) continue;
-        ++P.n_kept;
-        for (int a = 0; a < 8; ++a) {
-          int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
-          int64_t n = c0 + ax + P.sy * ay + P.sz * az;
-          // the cell sits on the side s = 1 - a of corner node n
-          int s = (1 - ax) + 2 * (1 - ay) + 4 * (1 - az);
-          P.emask[n] |= uint8_t(1u << s);
-          uf.unite(c0, n);
-        }
-      }
+  }
   P.flags.assign(N, 0);
+  for (int32_t n : P.hang_ids) P.flags[n] = IBFE_FLAG_HANG;
   P.P_ids.clear();
   P.n_free = P.n_pfree = 0;
   for (int64_t n = 0; n < N; ++n) {
-    if (!P.emask[n]) continue;
+    if (!P.emask[n] && !(P.refined && P.cmask[n])) continue;
+    if (P.flags[n] & IBFE_FLAG_HANG) continue;
     uint8_t f = IBFE_FLAG_P;
     uint8_t t = P.tag[n];
     bool du = P.mask[n] == 0 || t == IBFE_TAG_WALL || t == IBFE_TAG_INLET;
@@ -195,11 +221,12 @@ int build_plan(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* para
   for (int64_t c = 0; c < nch; ++c) {
     int64_t lo = c * kChunk, hi = std::min<int64_t>(N, lo + kChunk);
     for (int64_t n = lo; n < hi; ++n)
-      if (P.emask[n]) {
+      if (P.flags[n] & (IBFE_FLAG_P | IBFE_FLAG_HANG)) {
         P.chunks.push_back(int32_t(c));
         break;
       }
   }
+  if (P.refined) composite_diagonals(P);
 
   // inlet table
   P.K = 0;
@@ -214,26 +241,43 @@ int build_plan(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* para
     }
     P.K = inlet->K;
     P.omega = inlet->omega;
-    P.inlet_ids.assign(inlet->node_ids, inlet->node_ids + inlet->n);
+    const int64_t nin = inlet->n;
     std::vector<uint8_t> seen(N, 0);
-    for (int64_t id : P.inlet_ids) {
-      if (id < 0 || id >= N || !(P.flags[id] & IBFE_FLAG_P) || P.tag[id] != IBFE_TAG_INLET ||
-          P.mask[id] != 1) {
-        err = "inlet table lists a node that is not an in-vessel inlet node of P";
+    std::vector<int64_t> keep;  // table rows that carry an unknown
+    for (int64_t q = 0; q < nin; ++q) {
+      const int64_t id = inlet->node_ids[q];
+      if (id < 0 || id >= N) {
+        err = "inlet node id out of range";
         return IBFE_EINVAL;
       }
       if (seen[id]++) {
         err = "duplicate inlet node";
         return IBFE_EINVAL;
       }
+      // on a refined lattice, points that are not nodes of P carry no unknown
+      if (P.refined && !(P.flags[id] & IBFE_FLAG_P)) continue;
+      if (!(P.flags[id] & IBFE_FLAG_P) || P.tag[id] != IBFE_TAG_INLET || P.mask[id] != 1) {
+        err = "inlet table lists a node that is not an in-vessel inlet node of P";
+        return IBFE_EINVAL;
+      }
+      keep.push_back(q);
     }
-    size_t len = size_t(2 * P.K + 1) * size_t(inlet->n) * 3;
-    P.inlet_shape.assign(inlet->shape, inlet->shape + len);
-    for (double v : P.inlet_shape)
-      if (!finite(v)) {
+    const size_t len = size_t(2 * P.K + 1) * size_t(nin) * 3;
+    for (size_t q = 0; q < len; ++q)
+      if (!finite(inlet->shape[q])) {
         err = "inlet shape must be finite";
         return IBFE_EINVAL;
       }
+    const int64_t nk = int64_t(keep.size());
+    P.inlet_ids.resize(nk);
+    P.inlet_shape.assign(size_t(2 * P.K + 1) * size_t(nk) * 3, 0.0);
+    for (int64_t r = 0; r < nk; ++r) {
+      const int64_t q = keep[r];
+      P.inlet_ids[r] = inlet->node_ids[q];
+      for (int b = 0; b < 2 * P.K + 1; ++b)
+        for (int d = 0; d < 3; ++d)
+          P.inlet_shape[(size_t(b) * nk + r) * 3 + d] = inlet->shape[(size_t(b) * nin + q) * 3 + d];
+    }
   } else if (inlet && inlet->n < 0) {
     err = "inlet n must be >= 0";
     return IBFE_EINVAL;
@@ -265,6 +309,7 @@ int build_plan(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* para
   P.ib_idx.assign(64 * M, -1);
   P.ib_w.assign(64 * M, 0.0);
   const int dims[3] = {nx, ny, nz};
+  int64_t first_singular = -1;
   for (int64_t i = 0; i < M; ++i) {
     int64_t base[3];
     double wd[3][4];
@@ -289,10 +334,15 @@ int build_plan(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* para
           P.ib_w[s * M + i] = w;
           if (P.flags[n] & IBFE_FLAG_F) free2 += w * w;
         }
-    if (free2 < 1e-12) {
-      err = "Lagrangian point " + std::to_string(i) + " has no free support node";
-      return IBFE_ESINGULAR;
-    }
+    if (free2 < 1e-12 && first_singular < 0) first_singular = i;
+  }
+  if (P.refined && M > 0) {
+    int rc = check_ib_support_refined(P, err);
+    if (rc) return rc;
+  }
+  if (first_singular >= 0) {
+    err = "Lagrangian point " + std::to_string(first_singular) + " has no free support node";
+    return IBFE_ESINGULAR;
   }
   // node -> (point, weight) lists over free nodes (the spreading operator I_F^T)
   P.sp_node.clear();
@@ -359,6 +409,10 @@ int build_plan(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* para
       }
       P.G_ptr.push_back(int64_t(P.G_col.size()));
     }
+  }
+  if (P.params.precond == 2 && P.refined) {
+    err = "multigrid is not available on refined grids yet (use precond 0)";
+    return IBFE_EINVAL;
   }
   if (P.params.precond == 2) {
     int rc = build_multigrid(P, err);

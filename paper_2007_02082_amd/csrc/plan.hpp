@@ -33,10 +33,36 @@ constexpr uint8_t kMgP = 1u, kMgPp = 16u;
 constexpr int kZBPlanes = 8;     // planes per z-blocked column item
 constexpr int kMgCoarsestMax = 512;
 
+struct UnionFind {
+  std::vector<int64_t> parent;
+  explicit UnionFind(int64_t n);
+  int64_t find(int64_t a);
+  void unite(int64_t a, int64_t b);
+};
+
 struct Plan {
-  // grid
+  // grid: the node lattice (with refinement: the fine lattice of spacing h/2)
   int nx = 0, ny = 0, nz = 0;
   double h = 0.0, origin[3] = {0, 0, 0};
+  // 2:1 refinement: base cells, base spacing, per-node bits of the kept
+  // unrefined cells around an all-even lattice node (bit s as in emask, for the
+  // base cell (I-1+sx, J-1+sy, K-1+sz) around base node (I, J, K))
+  bool refined = false;
+  int bnx = 0, bny = 0, bnz = 0;
+  double hb = 0.0;
+  std::vector<uint8_t> refine;   // base cells (refined only)
+  std::vector<uint8_t> cmask;    // per lattice node (refined only)
+  // hanging nodes (ascending ids) with their 2 or 4 parents ([4][nh], -1 unused)
+  std::vector<int32_t> hang_ids;
+  std::vector<int32_t> hang_par;
+  // parents: ascending ids, CSR of (hanging index, weight); slot per lattice node
+  std::vector<int32_t> par_ids, par_ptr, par_child;
+  std::vector<double> par_w;
+  std::vector<int32_t> par_slot;
+  // lumped diagonals of the constrained mass and stiffness forms (refined only):
+  // d'(n) = a_nn + sum over hanging children h of w_h a_hh
+  std::vector<double> dmass, dstiff;
+  double mass_lmin = 0.125;      // lower bound of eig(D'^-1 M) on F
   int64_t N = 0;                 // grid nodes
   int64_t sy = 0, sz = 0;        // id strides in y and z
   // physics
@@ -79,6 +105,15 @@ int build_multigrid(Plan& plan, std::string& err);
 // z-blocked column items of a level (kZBPlanes planes x 64 in-plane nodes).
 void column_items(const std::vector<uint8_t>& emask, int64_t sz, int nplanes, std::vector<int32_t>& items,
                   int& cpp);
+
+// Kept elements, hanging nodes and parents of a refined lattice: fills emask
+// (children of refined cells), cmask, the hanging and parent tables and joins
+// the corners of every kept element (and hanging nodes with their parents).
+int build_composite_cells(Plan& plan, UnionFind& uf, std::string& err);
+// Lumped diagonals and the Chebyshev lower bound of a refined plan (after flags).
+void composite_diagonals(Plan& plan);
+// Every IB support node inside the closure of a refined cell and not hanging.
+int check_ib_support_refined(const Plan& plan, std::string& err);
 
 // Returns IBFE_OK or an error code with `err` set.
 int build_plan(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* params,

@@ -3,3 +3,4 @@ from .cases import (Case, channel_case, refined_cylinder, shear_advection_case, 
                     cylinder_case, poiseuille_c1, pulsatile_c2, random_blob_case,
                     small_cylinder)
 from .serving import GRIDS, Request, request_stream, vessel_case  # noqa: F401,E402
+from .aneurysm import aneurysm_case  # noqa: F401,E402

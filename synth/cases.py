@@ -358,7 +358,9 @@ def refined_cylinder(cells_xy: int = 8, cells_z: int = 8, length: float = 1.0, r
     zl = 2 * hf + (np.arange(nr) + 0.5) * ((length - 4 * hf) / nr)
     c.X = _ring_points(radius, zl, max(6, int(round(2 * math.pi * radius / spacing))))
     c.dS = spacing * spacing
-    on_inlet = (xyz[:, 2] == 0.0) & (c.node_mask == 1)
+    lo, hi = origin[0], origin[0] + width
+    side = (xyz[:, 0] == lo) | (xyz[:, 0] == hi) | (xyz[:, 1] == lo) | (xyz[:, 1] == hi)
+    on_inlet = (xyz[:, 2] == 0.0) & (c.node_mask == 1) & ~side
     ids = np.nonzero(on_inlet)[0].astype(np.int64)
     shape = np.zeros((1, ids.size, 3))
     shape[0, :, 2] = np.maximum(0.0, 1.0 - r2[ids] / (radius * radius))

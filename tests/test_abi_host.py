@@ -107,3 +107,61 @@ def test_serving_stream_is_seeded_and_sized():
     assert [(r.kind, r.radius, r.arrival) for r in a] == [(r.kind, r.radius, r.arrival) for r in b]
     assert len(a) == 64 and 8.0 < a[-1].arrival < 24.0   # Poisson arrivals at 4 per second
     assert {r.kind for r in a} == {"cylinder", "aneurysm", "branch"}
+
+
+REFINED = [
+    lambda: synth.refined_cylinder(8, 8, length=1.25, band=0.3),
+    lambda: _no_points(synth.refined_cylinder(6, 4, length=1.25 * 4 / 6, band=0.25, mask_all=True)),
+    lambda: synth.aneurysm_case((16, 16, 40), band=1.2, nsteps=2),
+]
+
+
+def _no_points(c):
+    c.X = np.zeros((0, 3))
+    return c
+
+
+@pytest.mark.parametrize("make", REFINED)
+def test_refined_plan_sets_match_oracle_bit_exactly(make):
+    """2:1 refined lattice: P, F, D_u, outlet and hanging nodes, canonical order."""
+    from oracle import refine
+
+    c = make()
+    pl = ibfe.Plan(**ibfe.inputs_from_case(c))
+    mesh = refine.CompositeMesh(c.nx, c.ny, c.nz, c.h, c.node_mask, c.bc_tag, c.refine_cell)
+    s = mesh.derive_sets(c.bc_tag)
+    np.testing.assert_array_equal(pl.node_ids(), s.P)
+    f = pl.node_flags()
+    np.testing.assert_array_equal((f & ibfe.FLAG_P) > 0, s.in_P)
+    np.testing.assert_array_equal((f & ibfe.FLAG_F) > 0, s.in_F)
+    np.testing.assert_array_equal((f & ibfe.FLAG_DU) > 0, s.in_Du)
+    np.testing.assert_array_equal((f & ibfe.FLAG_PDIR) > 0, s.p_dir)
+    np.testing.assert_array_equal(np.nonzero(f & ibfe.FLAG_HANG)[0], mesh.hanging)
+    sz = pl.sizes()
+    assert sz["n_kept_cells"] == len(mesh.fine) + len(mesh.coarse)
+    assert sz["n_p"] == s.P.size and sz["n_free"] == s.F.size and sz["n_pfree"] == s.Pp.size
+    assert mesh.hanging.size > 0 or c.refine_cell.all()
+
+
+def test_refined_input_errors():
+    c = synth.refined_cylinder(8, 8, length=1.25, band=0.3)
+    kw = ibfe.inputs_from_case(c)
+    bad = dict(kw, refine_cell=np.full_like(c.refine_cell, 2))
+    with pytest.raises(ibfe.IbfeError, match="EINVAL"):
+        ibfe.Plan(**bad)
+    # a point whose kernel support leaves the refined band
+    X = np.concatenate([c.X, [[0.0, 0.0, 0.6]]])
+    with pytest.raises(ibfe.IbfeError, match="refined band"):
+        ibfe.Plan(**dict(kw, X=X))
+    # an inlet entry at a lattice point that is not a node of P is skipped, one at a
+    # node of P that is not an inlet node is rejected
+    from oracle import refine
+
+    mesh = refine.CompositeMesh(c.nx, c.ny, c.nz, c.h, c.node_mask, c.bc_tag, c.refine_cell)
+    s = mesh.derive_sets(c.bc_tag)
+    assert not s.in_P[c.inlet_ids].all()
+    ibfe.Plan(**kw)
+    interior = s.P[(s.tag[s.P] == 0)][:1]
+    with pytest.raises(ibfe.IbfeError, match="inlet"):
+        ibfe.Plan(**dict(kw, inlet_ids=np.concatenate([c.inlet_ids, interior]),
+                         inlet_shape=np.zeros((1, c.inlet_ids.size + 1, 3))))
