@@ -16,6 +16,7 @@
 #include "step_kernels.hpp"
 #include "zblock.hpp"
 #include "mg.hpp"
+#include "composite.hpp"
 
 using namespace ibfe;
 
@@ -139,6 +140,22 @@ struct ibfe_ctx {
   std::vector<MGDev<double>> mg64;
   std::vector<MGDev<float>> mg32;
 
+  // 2:1 refined lattice (empty on uniform grids)
+  uint8_t* cmask = nullptr;
+  int32_t* pslot = nullptr;
+  int nh = 0;
+  int32_t* hang_ids = nullptr;
+  int32_t* hang_par = nullptr;
+  int32_t* par_ptr = nullptr;
+  int32_t* par_child = nullptr;
+  double* pw64 = nullptr;
+  float* pw32 = nullptr;
+  double *dinvM64 = nullptr, *dinvK64 = nullptr;
+  float *dinvM32 = nullptr, *dinvK32 = nullptr;
+  double* yh64 = nullptr;
+  float* yh32 = nullptr;
+  FormCoefs fcc{};   // forms of the coarse elements (spacing 2h)
+
   FormCoefs fc{};
   double t = 0.0;
   int64_t steps = 0;
@@ -187,7 +204,11 @@ struct ibfe_ctx {
     void* base = nullptr;
     int rc = dalloc(&base, sizeof(T) * std::max(count, min_count));
     if (rc) return rc;
-    if (count) HIP_TRY(hipMemcpyAsync(base, src, sizeof(T) * count, hipMemcpyHostToDevice, stream));
+    if (count) {
+      // src may be a temporary: wait until the copy has consumed it
+      HIP_TRY(hipMemcpyAsync(base, src, sizeof(T) * count, hipMemcpyHostToDevice, stream));
+      HIP_TRY(hipStreamSynchronize(stream));
+    }
     *out = reinterpret_cast<T*>(base);
     return IBFE_OK;
   }
@@ -263,10 +284,57 @@ int setup_mg(ibfe_ctx& c, std::vector<MGDev<T>>& out, T* xt0, T* d0, T* r0) {
   return IBFE_OK;
 }
 
+// Device tables of a refined lattice: coarse cell bits, parent slots, the
+// hanging and parent lists, inverse lumped diagonals and the hanging-row buffers.
+int setup_refined(ibfe_ctx& c) {
+  const Plan& P = c.plan;
+  int rc;
+  c.fcc = form_coefs(P.hb);
+  if ((rc = c.field(&c.cmask, 1))) return rc;
+  HIP_TRY(hipMemcpyAsync(c.cmask, P.cmask.data(), P.N, hipMemcpyHostToDevice, c.stream));
+  if ((rc = c.field(&c.pslot, 1))) return rc;
+  HIP_TRY(hipMemcpyAsync(c.pslot, P.par_slot.data(), sizeof(int32_t) * P.N, hipMemcpyHostToDevice, c.stream));
+  c.nh = int(P.hang_ids.size());
+  if ((rc = c.upload(&c.hang_ids, P.hang_ids.data(), P.hang_ids.size()))) return rc;
+  if ((rc = c.upload(&c.hang_par, P.hang_par.data(), P.hang_par.size()))) return rc;
+  if ((rc = c.upload(&c.par_ptr, P.par_ptr.data(), P.par_ptr.size()))) return rc;
+  if ((rc = c.upload(&c.par_child, P.par_child.data(), P.par_child.size()))) return rc;
+  if ((rc = c.upload(&c.pw64, P.par_w.data(), P.par_w.size()))) return rc;
+  {
+    std::vector<float> w32(P.par_w.begin(), P.par_w.end());
+    if ((rc = c.upload(&c.pw32, w32.data(), w32.size()))) return rc;
+  }
+  std::vector<double> im(P.N, 0.0), ik(P.N, 0.0);
+  for (int64_t n = 0; n < P.N; ++n) {
+    if (P.dmass[n] > 0.0) im[n] = 1.0 / P.dmass[n];
+    if (P.dstiff[n] > 0.0) ik[n] = 1.0 / P.dstiff[n];
+  }
+  if ((rc = c.field(&c.dinvM64, 1))) return rc;
+  if ((rc = c.field(&c.dinvK64, 1))) return rc;
+  if ((rc = c.field(&c.dinvM32, 1))) return rc;
+  if ((rc = c.field(&c.dinvK32, 1))) return rc;
+  HIP_TRY(hipMemcpyAsync(c.dinvM64, im.data(), sizeof(double) * P.N, hipMemcpyHostToDevice, c.stream));
+  HIP_TRY(hipMemcpyAsync(c.dinvK64, ik.data(), sizeof(double) * P.N, hipMemcpyHostToDevice, c.stream));
+  {
+    std::vector<float> m32(im.begin(), im.end()), k32(ik.begin(), ik.end());
+    HIP_TRY(hipMemcpyAsync(c.dinvM32, m32.data(), sizeof(float) * P.N, hipMemcpyHostToDevice, c.stream));
+    HIP_TRY(hipMemcpyAsync(c.dinvK32, k32.data(), sizeof(float) * P.N, hipMemcpyHostToDevice, c.stream));
+    HIP_TRY(hipStreamSynchronize(c.stream));  // the host staging vectors go out of scope
+  }
+  void* base = nullptr;
+  if ((rc = c.dalloc(&base, sizeof(double) * 3 * std::max(1, c.nh)))) return rc;
+  c.yh64 = reinterpret_cast<double*>(base);
+  if ((rc = c.dalloc(&base, sizeof(float) * 3 * std::max(1, c.nh)))) return rc;
+  c.yh32 = reinterpret_cast<float*>(base);
+  return IBFE_OK;
+}
+
 int setup_device(ibfe_ctx& c) {
   Plan& P = c.plan;
   const int64_t nch_total = (P.N + kChunk - 1) / kChunk;
-  c.halo = ((P.sz + P.sy + 1 + kChunk - 1) / kChunk) * kChunk;
+  // the coarse elements of a refined lattice reach neighbours at offset 2
+  const int64_t reach = (P.refined ? 2 : 1) * (P.sz + P.sy + 1);
+  c.halo = ((reach + kChunk - 1) / kChunk) * kChunk;
   c.stride = 2 * c.halo + nch_total * kChunk;
   c.nchunks = int(P.chunks.size());
   c.nP = int(P.P_ids.size());
@@ -277,6 +345,7 @@ int setup_device(ibfe_ctx& c) {
   for (int64_t n = 0; n < P.N; ++n) {
     uint8_t f = P.flags[n];
     if ((f & IBFE_FLAG_P) && !(f & IBFE_FLAG_PDIR)) f |= kFlagPp;
+    if (P.refined && P.par_slot[n] >= 0) f |= kFlagPar;
     fl[n] = f;
   }
   if ((rc = c.field(&c.emask, 1))) return rc;
@@ -327,11 +396,13 @@ int setup_device(ibfe_ctx& c) {
   if ((rc = c.field(&c.ustar, 3))) return rc;
   if ((rc = c.field(&c.uib, 3))) return rc;
   if ((rc = c.field(&c.phi, 1))) return rc;
-  if ((rc = c.field(&c.coef64, 27))) return rc;
+  const int ncoef = P.refined ? 54 : 27;
+  if ((rc = c.field(&c.coef64, ncoef))) return rc;
   for (int i = 0; i < 10; ++i)
     if ((rc = c.field(&c.w[i], 3))) return rc;
+  if (P.refined && (rc = setup_refined(c))) return rc;
   if (P.params.precision == 1) {
-    if ((rc = c.field(&c.coef32, 27))) return rc;
+    if ((rc = c.field(&c.coef32, ncoef))) return rc;
     for (int i = 0; i < 10; ++i)
       if ((rc = c.field(&c.v32[i], 3))) return rc;
   }
@@ -455,6 +526,35 @@ int launch_q(ibfe_ctx& c, const OpSym<T, NC>& op, const int*, int, const T* p, T
   return nr;
 }
 
+// Operators of a refined lattice need C x at the hanging nodes and the
+// element rows there before every apply (see composite.hpp); uniform
+// operators need nothing.
+template <typename T, class Op>
+int pre_apply(ibfe_ctx&, const Op&, T*, const KScal*) {
+  return IBFE_OK;
+}
+
+template <typename T, class Op>
+int hang_prepare(ibfe_ctx& c, const Op& op, T* x, const KScal* sc) {
+  if (c.nh == 0) return IBFE_OK;
+  const int nb = blocks_lin(c.nh);
+  hipLaunchKernelGGL(k_hang_fill<T>, dim3(nb), dim3(kBlock), 0, c.stream, c.nh, (const int32_t*)c.hang_ids,
+                     (const int32_t*)c.hang_par, x, int(Op::kNC), c.stride, sc);
+  OpElem<T, Op> f{op, x};
+  hipLaunchKernelGGL((k_hang_elem<T, OpElem<T, Op>>), dim3(nb), dim3(kBlock), 0, c.stream, c.nh,
+                     (const int32_t*)c.hang_ids, f, const_cast<T*>(op.yh), sc);
+  CHECK_LAUNCH();
+  return IBFE_OK;
+}
+template <typename T, int NC>
+int pre_apply(ibfe_ctx& c, const OpCSym<T, NC>& op, T* x, const KScal* sc) {
+  return hang_prepare<T>(c, op, x, sc);
+}
+template <typename T, int NC>
+int pre_apply(ibfe_ctx& c, const OpCStencil<T, NC>& op, T* x, const KScal* sc) {
+  return hang_prepare<T>(c, op, x, sc);
+}
+
 // Event pair k of the kernel timer (created on first use).
 int timer_events(ibfe_ctx& c, size_t k, hipEvent_t& e0, hipEvent_t& e1) {
   while (c.ev.size() < 2 * k + 2) {
@@ -473,6 +573,8 @@ int run_cg(ibfe_ctx& c, const Op& op, const int* chunks, int nchunks, const T* b
            bool timed = false) {
   const int nb = blocks_for(nchunks), nr = red_blocks(nchunks);
   KScal* sc = &c.scal[slot];
+  int prc;
+  if (!zero_guess && (prc = pre_apply(c, op, x, (const KScal*)nullptr))) return prc;
   hipLaunchKernelGGL((k_cg_init<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, chunks, nchunks, op, b, x,
                      r, p, c.partials, zero_guess ? 1 : 0);
   hipLaunchKernelGGL(k_fin_cg_init, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr, sc,
@@ -485,6 +587,7 @@ int run_cg(ibfe_ctx& c, const Op& op, const int* chunks, int nchunks, const T* b
     for (int k = 0; k < batch; ++k) {
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (timed && timer_events(c, size_t(launched + k), e0, e1)) return IBFE_EHIP;
+      if ((prc = pre_apply(c, op, p, (const KScal*)sc))) return prc;
       const int nq = launch_q<T>(c, op, chunks, nchunks, p, q, (const KScal*)sc, e0, e1);
       hipLaunchKernelGGL(k_fin_cg_q, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nq, sc);
       hipLaunchKernelGGL((k_cg_xr<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, chunks, nchunks, op, x, r,
@@ -526,6 +629,8 @@ int run_bicgstab(ibfe_ctx& c, const Op& op, const T* b, T* x, T* const* wv, int 
     *t = wv[7];
   KScal* sc = &c.scal[slot];
   const KScal* csc = sc;
+  int prc;
+  if ((prc = pre_apply(c, op, x, (const KScal*)nullptr))) return prc;
   hipLaunchKernelGGL((k_bi_init<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, ch, nch, op, b, x, r, rhat, p,
                      v, c.partials);
   hipLaunchKernelGGL(k_fin_bi_init, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc, rtol * rtol, max_iters);
@@ -537,11 +642,13 @@ int run_bicgstab(ibfe_ctx& c, const Op& op, const T* b, T* x, T* const* wv, int 
     for (int k = 0; k < batch; ++k) {
       hipLaunchKernelGGL((k_bi_p<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, ch, nch, op, r, p, v, phat,
                          csc);
+      if ((prc = pre_apply(c, op, phat, csc))) return prc;
       hipLaunchKernelGGL((k_bi_apply<T, Op, 0>), dim3(nr), dim3(kBlock), 0, c.stream, ch, nch, op, phat, v,
                          rhat, c.partials, csc);
       hipLaunchKernelGGL(k_fin_bi_apply<0>, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc);
       hipLaunchKernelGGL((k_bi_s<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, ch, nch, op, r, v, s, shat,
                          csc);
+      if ((prc = pre_apply(c, op, shat, csc))) return prc;
       hipLaunchKernelGGL((k_bi_apply<T, Op, 1>), dim3(nr), dim3(kBlock), 0, c.stream, ch, nch, op, shat, t,
                          s, c.partials, csc);
       hipLaunchKernelGGL(k_fin_bi_apply<1>, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc);
@@ -564,9 +671,11 @@ int run_bicgstab(ibfe_ctx& c, const Op& op, const T* b, T* x, T* const* wv, int 
 // FP64 residual of the refinement loop: returns |r|^2 and |b|^2 on the host and
 // leaves r in FP32 in r32.
 template <class Op64, typename TR>
-int ir_residual(ibfe_ctx& c, const Op64& op, const double* b, const double* x, TR* r32, double& rr,
+int ir_residual(ibfe_ctx& c, const Op64& op, const double* b, double* x, TR* r32, double& rr,
                 double& bb) {
   const int nr = red_blocks(c.nchunks);
+  int prc;
+  if ((prc = pre_apply(c, op, x, (const KScal*)nullptr))) return prc;
   hipLaunchKernelGGL((k_residual<Op64, TR>), dim3(nr), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, op, b,
                      x, r32, c.partials);
   hipLaunchKernelGGL(k_fin_residual, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr,
@@ -912,7 +1021,7 @@ int build_s1(ibfe_ctx& c) {
   for (int t = 0; t < 4; ++t) cm[t] = rdt * c.fc.m[t] + mu * c.fc.k[t];
   hipLaunchKernelGGL(k_s1_build, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream, c.chunks,
                      c.nchunks, c.emask, c.flags, c.u, c.stride, int(P.sy), int(P.sz), P.h, cm[0], cm[1],
-                     cm[2], cm[3], P.params.rho, c.coef64, c.coef32);
+                     cm[2], cm[3], P.params.rho, c.coef64, c.coef32, 1, kFlagP);
   CHECK_LAUNCH();
   return IBFE_OK;
 }
@@ -1108,6 +1217,427 @@ int step_once(ibfe_ctx& c) {
   return IBFE_OK;
 }
 
+// -------------------------------------------------------------------------
+// 2:1 refined lattice: composite operators (fine + coarse elements with the
+// hanging-node constraint) behind the same Krylov drivers
+// -------------------------------------------------------------------------
+
+Children children_of(const ibfe_ctx& c) { return Children{c.pslot, c.par_ptr, c.par_child, c.nh}; }
+
+template <typename T>
+struct RefBufs;
+template <>
+struct RefBufs<double> {
+  static const double* pw(const ibfe_ctx& c) { return c.pw64; }
+  static double* yh(const ibfe_ctx& c) { return c.yh64; }
+  static const double* dinvM(const ibfe_ctx& c) { return c.dinvM64; }
+  static const double* dinvK(const ibfe_ctx& c) { return c.dinvK64; }
+};
+template <>
+struct RefBufs<float> {
+  static const float* pw(const ibfe_ctx& c) { return c.pw32; }
+  static float* yh(const ibfe_ctx& c) { return c.yh32; }
+  static const float* dinvM(const ibfe_ctx& c) { return c.dinvM32; }
+  static const float* dinvK(const ibfe_ctx& c) { return c.dinvK32; }
+};
+
+// alpha M + beta K of the composite mesh: coef(h) = alpha m(h) + beta k(h)
+template <typename T, int NC>
+OpCSym<T, NC> csym_op(const ibfe_ctx& c, double alpha, double beta, uint32_t rowbit, const T* dinv) {
+  OpCSym<T, NC> op{};
+  op.emask = c.emask;
+  op.cmask = c.cmask;
+  op.flags = c.flags;
+  op.rowbit = rowbit;
+  op.sy = int(c.plan.sy);
+  op.sz = int(c.plan.sz);
+  op.stride = c.stride;
+  for (int t = 0; t < 4; ++t) {
+    op.cf[t] = T(alpha * c.fc.m[t] + beta * c.fc.k[t]);
+    op.cc[t] = T(alpha * c.fcc.m[t] + beta * c.fcc.k[t]);
+  }
+  op.dinv = dinv;
+  op.ch = children_of(c);
+  op.pw = RefBufs<T>::pw(c);
+  op.yh = RefBufs<T>::yh(c);
+  return op;
+}
+
+template <typename T>
+OpCStencil<T, 3> cstencil_op(const ibfe_ctx& c, const T* coef, uint32_t rowbit) {
+  OpCStencil<T, 3> op{};
+  op.coef = coef;
+  op.cmask = c.cmask;
+  op.flags = c.flags;
+  op.rowbit = rowbit;
+  op.sy = int(c.plan.sy);
+  op.sz = int(c.plan.sz);
+  op.stride = c.stride;
+  op.ch = children_of(c);
+  op.pw = RefBufs<T>::pw(c);
+  op.yh = RefBufs<T>::yh(c);
+  return op;
+}
+
+GradElem grad_elem(const ibfe_ctx& c, const double* x) {
+  GradElem g{};
+  g.emask = c.emask;
+  g.cmask = c.cmask;
+  g.x = x;
+  g.sy = int(c.plan.sy);
+  g.sz = int(c.plan.sz);
+  for (int k = 0; k < 3; ++k) {
+    g.gf[k] = c.fc.g2[k];
+    g.gc[k] = c.fcc.g2[k];
+  }
+  return g;
+}
+
+// x[h] = mean of the parents of every hanging node (nc planes)
+template <typename T>
+int fill_hanging(ibfe_ctx& c, T* x, int nc) {
+  if (c.nh == 0) return IBFE_OK;
+  hipLaunchKernelGGL(k_hang_fill<T>, dim3(blocks_lin(c.nh)), dim3(kBlock), 0, c.stream, c.nh,
+                     (const int32_t*)c.hang_ids, (const int32_t*)c.hang_par, x, nc, c.stride,
+                     (const KScal*)nullptr);
+  CHECK_LAUNCH();
+  return IBFE_OK;
+}
+
+// out = scale * C^T (element rows of f) on rows; f's inputs must be filled.
+template <typename T, class F>
+int comp_rows(ibfe_ctx& c, const F& f, uint32_t rowbit, uint32_t exclude, T scale, T* out) {
+  T* yh = RefBufs<T>::yh(c);
+  if (c.nh)
+    hipLaunchKernelGGL((k_hang_elem<T, F>), dim3(blocks_lin(c.nh)), dim3(kBlock), 0, c.stream, c.nh,
+                       (const int32_t*)c.hang_ids, f, yh, (const KScal*)nullptr);
+  hipLaunchKernelGGL((k_comp_rows<T, F>), dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
+                     (const int*)c.chunks, c.nchunks, f, (const uint8_t*)c.flags, rowbit, exclude, scale,
+                     children_of(c), RefBufs<T>::pw(c), (const T*)yh, out, c.stride);
+  CHECK_LAUNCH();
+  return IBFE_OK;
+}
+
+int cheb_steps(double tol, double lmin, double lmax) {
+  const double kappa = lmax / lmin;
+  const double q = (std::sqrt(kappa) - 1.0) / (std::sqrt(kappa) + 1.0);
+  return int(std::ceil((std::log(2.0 / tol) + 0.5 * std::log(kappa)) / std::log(1.0 / q)));
+}
+
+// x = Cheb_iters(b) from x = 0 for any operator on [lmin, lmax] of D^-1 A.
+template <typename T, class Op>
+int run_cheb_gen(ibfe_ctx& c, const Op& op, const T* b, T* x, T* xalt, T* d, int iters, double lmin,
+                 double lmax) {
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+  T* cur = ((iters - 1) % 2 == 0) ? x : xalt;
+  T* alt = cur == x ? xalt : x;
+  hipLaunchKernelGGL((k_cheb0_gen<T, Op>), dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
+                     (const int*)c.chunks, c.nchunks, op, b, d, cur, T(1.0 / theta), (const KScal*)nullptr);
+  const int nr = red_blocks(c.nchunks);
+  double rho = 1.0 / sigma;
+  int rc;
+  for (int k = 1; k < iters; ++k) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    const T c1 = T(rn * rho), c2 = T(2.0 * rn / delta);
+    rho = rn;
+    if ((rc = pre_apply(c, op, cur, (const KScal*)nullptr))) return rc;
+    hipLaunchKernelGGL((k_cheb_gen<T, Op, false>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.chunks,
+                       c.nchunks, op, (const T*)cur, b, d, alt, c1, c2, c.partials, (const KScal*)nullptr);
+    std::swap(cur, alt);
+  }
+  CHECK_LAUNCH();
+  if (cur != x) return fail(IBFE_EINVAL, "internal: Chebyshev result buffer");
+  return IBFE_OK;
+}
+
+// Tentative-velocity stencil of the composite mesh: fine-element part (rows of
+// P and hanging nodes) into planes 0..26, coarse-element part into 27..53.
+int build_s1_refined(ibfe_ctx& c) {
+  const Plan& P = c.plan;
+  const double rdt = P.params.rho / P.params.dt, mu = P.params.mu;
+  double cf[4], cc[4];
+  for (int t = 0; t < 4; ++t) {
+    cf[t] = rdt * c.fc.m[t] + mu * c.fc.k[t];
+    cc[t] = rdt * c.fcc.m[t] + mu * c.fcc.k[t];
+  }
+  const int nb = blocks_for(c.nchunks);
+  const int64_t S = c.stride;
+  hipLaunchKernelGGL(k_s1_build, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.emask, c.flags,
+                     c.u, S, int(P.sy), int(P.sz), P.h, cf[0], cf[1], cf[2], cf[3], P.params.rho, c.coef64,
+                     c.coef32, 1, kFlagP | kFlagHang);
+  hipLaunchKernelGGL(k_s1_build, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.cmask, c.flags,
+                     c.u, S, int(P.sy), int(P.sz), P.hb, cc[0], cc[1], cc[2], cc[3], P.params.rho,
+                     c.coef64 + 27 * S, c.coef32 ? c.coef32 + 27 * S : nullptr, 2, kFlagP);
+  CHECK_LAUNCH();
+  return IBFE_OK;
+}
+
+int step_once_refined(ibfe_ctx& c) {
+  const Plan& P = c.plan;
+  const double rho = P.params.rho, dt = P.params.dt;
+  const double t1 = c.t + dt;
+  const int nb = blocks_for(c.nchunks);
+  const int64_t S = c.stride;
+  const bool mixed = P.params.precision == 1;
+  const double rtol = P.params.rtol;
+  const int maxit = P.params.max_iters;
+  int rc;
+
+  if (!P.inlet_ids.empty()) {
+    Harmonics hm{};
+    hm.K = P.K;
+    for (int k = 1; k <= P.K; ++k) {
+      hm.c[k - 1] = std::cos(k * P.omega * t1);
+      hm.s[k - 1] = std::sin(k * P.omega * t1);
+    }
+    hipLaunchKernelGGL(k_inlet, dim3(blocks_lin(int64_t(P.inlet_ids.size()))), dim3(kBlock), 0,
+                       c.stream, int(P.inlet_ids.size()), c.inlet_ids, c.inlet_shape, hm, c.g, S);
+    CHECK_LAUNCH();
+  }
+  // the element forms read the hanging values C x of u^n, p^n and g
+  if ((rc = fill_hanging<double>(c, c.u, 3)) || (rc = fill_hanging<double>(c, c.p, 1)) ||
+      (rc = fill_hanging<double>(c, c.g, 3)))
+    return rc;
+
+  // 1. tentative velocity
+  if ((rc = build_s1_refined(c))) return rc;
+  double* b1 = c.w[8];
+  double* x1 = c.w[9];
+  {
+    S1RhsElem f{};
+    f.mass = csym_op<double, 3>(c, rho / dt, 0.0, kFlagF, c.dinvM64);
+    f.A = cstencil_op<double>(c, c.coef64, kFlagF);
+    f.grad = grad_elem(c, c.p);
+    f.u = c.u;
+    f.g = c.g;
+    if ((rc = comp_rows<double>(c, f, kFlagF, 0u, 1.0, b1))) return rc;
+    hipLaunchKernelGGL((k_masked_copy<double, double>), dim3(nb), dim3(kBlock), 0, c.stream, c.chunks,
+                       c.nchunks, c.flags, kFlagF, c.u, x1, 3, S);
+    CHECK_LAUNCH();
+    auto op = cstencil_op<double>(c, c.coef64, kFlagF);
+    SolveOut so;
+    if (mixed) {
+      auto op32 = cstencil_op<float>(c, c.coef32, kFlagF);
+      rc = run_refined(c, op, kFlagF, 3, b1, x1, c.v32[8], c.v32[9], rtol, so,
+                       [&](const float* r32, float* d32, double tol, SolveOut& o) {
+                         HIP_TRY(hipMemsetAsync(d32 - c.halo, 0, sizeof(float) * 3 * S, c.stream));
+                         return run_bicgstab<float>(c, op32, r32, d32, c.v32, kScS1, tol, maxit, o);
+                       });
+    } else {
+      rc = run_bicgstab<double>(c, op, b1, x1, c.w, kScS1, rtol, maxit, so);
+    }
+    if (rc) return rc;
+    c.stats.s1_iters = so.iters;
+    c.stats.s1_res = so.res;
+    c.stats.s1_outer = so.outer;
+    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, 1.0, x1, 1.0,
+                       c.g, c.ustar, 3, S);
+    CHECK_LAUNCH();
+  }
+
+  // 2.-4. BCE-IB correction (every support node is a fine, non-hanging node)
+  hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, 1.0, c.ustar,
+                     0.0, c.ustar, c.uib, 3, S);
+  CHECK_LAUNCH();
+  c.stats.ib_iters = 0;
+  c.stats.ib_res = 0.0;
+  if (P.M > 0) {
+    const int M = int(P.M);
+    hipLaunchKernelGGL(k_ib_interp, dim3(blocks_lin(M)), dim3(kBlock), 0, c.stream, M, c.ib_idx, c.ib_w,
+                       c.UB, c.ustar, S, c.ibv[0], c.mstride, 1);
+    CHECK_LAUNCH();
+    auto op = gram_op(c);
+    SolveOut so;
+    if ((rc = run_cg<double>(c, op, c.ib_chunks, c.ib_nchunks, c.ibv[0], c.ibv[1], c.ibv[2], c.ibv[3],
+                             c.ibv[4], kScIB, P.params.ib_rtol, maxit, true, so)))
+      return rc;
+    c.stats.ib_iters = so.iters;
+    c.stats.ib_res = so.res;
+    const int nn = int(P.sp_node.size());
+    hipLaunchKernelGGL(k_ib_spread, dim3(blocks_lin(nn)), dim3(kBlock), 0, c.stream, nn, c.sp_node,
+                       c.sp_ptr, c.sp_pt, c.sp_wt, c.ibv[1], c.mstride, c.uib, S);
+    CHECK_LAUNCH();
+  }
+
+  // 5. pressure increment
+  double* b3 = c.w[8];
+  {
+    if ((rc = fill_hanging<double>(c, c.uib, 3))) return rc;
+    DivElem f{};
+    f.emask = c.emask;
+    f.cmask = c.cmask;
+    f.u = c.uib;
+    f.stride = S;
+    f.sy = int(P.sy);
+    f.sz = int(P.sz);
+    for (int k = 0; k < 3; ++k) {
+      f.gf[k] = c.fc.g2[k];
+      f.gc[k] = c.fcc.g2[k];
+    }
+    if ((rc = comp_rows<double>(c, f, kFlagPp, 0u, -rho / dt, b3))) return rc;
+    if (P.n_floating > 0 && (rc = remove_slot_means(c, b3))) return rc;
+    auto op = csym_op<double, 1>(c, 0.0, 1.0, kFlagPp, c.dinvK64);
+    SolveOut so;
+    if (mixed) {
+      auto op32 = csym_op<float, 1>(c, 0.0, 1.0, kFlagPp, c.dinvK32);
+      HIP_TRY(hipMemsetAsync(c.phi - c.halo, 0, sizeof(double) * S, c.stream));
+      float* const* v = c.v32;
+      rc = run_refined(c, op, kFlagPp, 1, b3, c.phi, v[8], v[9], rtol, so,
+                       [&](const float* r32, float* d32, double tol, SolveOut& o) {
+                         return run_cg<float>(c, op32, c.chunks, c.nchunks, r32, d32, v[0], v[1], v[2], kScS3,
+                                              tol, maxit, true, o, false);
+                       });
+    } else {
+      rc = run_cg<double>(c, op, c.chunks, c.nchunks, b3, c.phi, c.w[0], c.w[1], c.w[2], kScS3, rtol, maxit,
+                          true, so, false);
+    }
+    if (rc) return rc;
+    c.stats.s3_iters = so.iters;
+    c.stats.s3_res = so.res;
+    c.stats.s3_outer = so.outer;
+    if (P.n_floating > 0 && (rc = remove_slot_means(c, c.phi))) return rc;
+  }
+
+  // 6. correction: M_FF delta = (G Phi)_F with Chebyshev on [lmin, 27/8] of D'^-1 M
+  {
+    double* b4 = c.w[8];
+    double* delta = c.w[9];
+    if ((rc = fill_hanging<double>(c, c.phi, 1))) return rc;
+    if ((rc = comp_rows<double>(c, grad_elem(c, c.phi), kFlagF, 0u, 1.0, b4))) return rc;
+    auto op = csym_op<double, 3>(c, 1.0, 0.0, kFlagF, c.dinvM64);
+    const double lmin = P.mass_lmin, lmax = kMassLmax;
+    SolveOut so;
+    HIP_TRY(hipMemsetAsync(delta - c.halo, 0, sizeof(double) * 3 * S, c.stream));
+    if (mixed) {
+      auto op32 = csym_op<float, 3>(c, 1.0, 0.0, kFlagF, c.dinvM32);
+      float* const* v = c.v32;
+      rc = run_refined(c, op, kFlagF, 3, b4, delta, v[8], v[9], rtol, so,
+                       [&](const float* r32, float* d32, double tol, SolveOut& o) {
+                         o.iters = cheb_steps(tol, lmin, lmax);
+                         return run_cheb_gen<float>(c, op32, r32, d32, v[0], v[1], o.iters, lmin, lmax);
+                       });
+    } else {
+      double* r64 = c.w[3];
+      so.iters = 0;
+      so.outer = 0;
+      for (int sweep = 0;; ++sweep) {
+        double rr = 0, bb = 0;
+        if ((rc = ir_residual(c, op, b4, delta, r64, rr, bb))) return rc;
+        so.res = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
+        if (so.res <= rtol || sweep == 4) break;
+        const int it = cheb_steps(std::max(rtol / std::max(so.res, 1e-300), 1e-15), lmin, lmax);
+        if ((rc = run_cheb_gen<double>(c, op, (const double*)r64, c.w[0], c.w[1], c.w[2], it, lmin, lmax)))
+          return rc;
+        hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, 1.0, delta, 1.0,
+                           c.w[0], delta, 3, S);
+        CHECK_LAUNCH();
+        so.iters += it;
+        so.outer += 1;
+      }
+      rc = so.res <= rtol ? IBFE_OK : fail(IBFE_ENOCONV, "mass correction did not converge");
+    }
+    if (rc) return rc;
+    c.stats.s4_iters = so.iters;
+    c.stats.s4_res = so.res;
+    c.stats.s4_outer = so.outer;
+    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, 1.0, c.uib,
+                       -dt / rho, delta, c.u_next, 3, S);
+    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, 1.0, c.p, 1.0,
+                       c.phi, c.p_next, 1, S);
+    CHECK_LAUNCH();
+  }
+  std::swap(c.u, c.u_next);
+  std::swap(c.p, c.p_next);
+  c.t = t1;
+  c.steps += 1;
+  c.stats.steps = c.steps;
+  c.stats.t = c.t;
+  return IBFE_OK;
+}
+
+// Verification applies on a refined lattice: rows and columns on all of P,
+// C^T A C with the hanging-node constraint.
+int apply_refined(ibfe_ctx& C, int op, int precision, double* xin, double* yout, int& nc_out) {
+  const Plan& P = C.plan;
+  const int nb = blocks_for(C.nchunks);
+  const int64_t S = C.stride;
+  int rc;
+  switch (op) {
+    case IBFE_OP_MASS:
+    case IBFE_OP_STIFF: {
+      const double a = op == IBFE_OP_MASS ? 1.0 : 0.0, b = 1.0 - a;
+      nc_out = 1;
+      if (precision == 0) {
+        if ((rc = fill_hanging<double>(C, xin, 1))) return rc;
+        auto o = csym_op<double, 1>(C, a, b, kFlagP, C.dinvM64);
+        return comp_rows<double>(C, OpElem<double, OpCSym<double, 1>>{o, xin}, kFlagP, 0u, 1.0, yout);
+      }
+      float* x32 = reinterpret_cast<float*>(C.w[2]);
+      float* y32 = reinterpret_cast<float*>(C.w[3]);
+      hipLaunchKernelGGL((k_masked_copy<double, float>), dim3(nb), dim3(kBlock), 0, C.stream, C.chunks,
+                         C.nchunks, C.flags, kFlagP, xin, x32, 1, S);
+      CHECK_LAUNCH();
+      if ((rc = fill_hanging<float>(C, x32, 1))) return rc;
+      auto o = csym_op<float, 1>(C, a, b, kFlagP, C.dinvM32);
+      if ((rc = comp_rows<float>(C, OpElem<float, OpCSym<float, 1>>{o, x32}, kFlagP, 0u, 1.0f, y32))) return rc;
+      hipLaunchKernelGGL((k_masked_copy<float, double>), dim3(nb), dim3(kBlock), 0, C.stream, C.chunks,
+                         C.nchunks, C.flags, kFlagP, y32, yout, 1, S);
+      CHECK_LAUNCH();
+      return IBFE_OK;
+    }
+    case IBFE_OP_GRAD:
+      nc_out = 3;
+      if ((rc = fill_hanging<double>(C, xin, 1))) return rc;
+      return comp_rows<double>(C, grad_elem(C, xin), kFlagP, 0u, 1.0, yout);
+    case IBFE_OP_DIV: {
+      nc_out = 1;
+      if ((rc = fill_hanging<double>(C, xin, 3))) return rc;
+      DivElem f{};
+      f.emask = C.emask;
+      f.cmask = C.cmask;
+      f.u = xin;
+      f.stride = S;
+      f.sy = int(P.sy);
+      f.sz = int(P.sz);
+      for (int k = 0; k < 3; ++k) {
+        f.gf[k] = C.fc.g2[k];
+        f.gc[k] = C.fcc.g2[k];
+      }
+      return comp_rows<double>(C, f, kFlagP, 0u, 1.0, yout);
+    }
+    case IBFE_OP_ADVDIFF: {
+      nc_out = 3;
+      if (precision == 1 && !C.coef32) {
+        if ((rc = C.field(&C.coef32, 54))) return rc;
+        if (!C.v32[0])
+          for (int i = 0; i < 10; ++i)
+            if ((rc = C.field(&C.v32[i], 3))) return rc;
+      }
+      if ((rc = fill_hanging<double>(C, C.u, 3))) return rc;
+      if ((rc = build_s1_refined(C))) return rc;
+      if (precision == 0) {
+        if ((rc = fill_hanging<double>(C, xin, 3))) return rc;
+        auto o = cstencil_op<double>(C, C.coef64, kFlagP);
+        return comp_rows<double>(C, OpElem<double, OpCStencil<double, 3>>{o, xin}, kFlagP, 0u, 1.0, yout);
+      }
+      float* x32 = C.v32[0];
+      float* y32 = C.v32[1];
+      hipLaunchKernelGGL((k_masked_copy<double, float>), dim3(nb), dim3(kBlock), 0, C.stream, C.chunks,
+                         C.nchunks, C.flags, kFlagP, xin, x32, 3, S);
+      CHECK_LAUNCH();
+      if ((rc = fill_hanging<float>(C, x32, 3))) return rc;
+      auto o = cstencil_op<float>(C, C.coef32, kFlagP);
+      if ((rc = comp_rows<float>(C, OpElem<float, OpCStencil<float, 3>>{o, x32}, kFlagP, 0u, 1.0f, y32)))
+        return rc;
+      hipLaunchKernelGGL((k_masked_copy<float, double>), dim3(nb), dim3(kBlock), 0, C.stream, C.chunks,
+                         C.nchunks, C.flags, kFlagP, y32, yout, 3, S);
+      CHECK_LAUNCH();
+      return IBFE_OK;
+    }
+    default: return fail(IBFE_EINVAL, "unknown operator");
+  }
+}
+
 int copy_in(ibfe_ctx& c, double* dense, int nc, const double* src, int on_device) {
   const int64_t n = c.nP;
   const double* comp = src;
@@ -1196,7 +1726,6 @@ int ibfe_create(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* par
   std::string err;
   int rc = build_plan(grid, ib, params, inlet, c->plan, err);
   if (rc) return fail(rc, err);
-  if (c->plan.refined) return fail(IBFE_EINVAL, "refined grids are not supported on the device yet");
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   if (alloc && alloc->alloc && alloc->free) {
     c->alloc = *alloc;
@@ -1238,7 +1767,7 @@ int ibfe_step(ibfe_ctx* c, int nsteps) {
   if (!c || nsteps < 0) return fail(IBFE_EINVAL, "bad argument");
   for (int k = 0; k < nsteps; ++k) {
     const double t_save = c->t;
-    int rc = step_once(*c);
+    int rc = c->plan.refined ? step_once_refined(*c) : step_once(*c);
     if (rc) {
       c->t = t_save;  // u, p were not swapped: the last completed state is intact
       return rc;
@@ -1316,6 +1845,11 @@ int ibfe_apply(ibfe_ctx* c, int op, int precision, const double* x, double* y, i
     return copy_out(C, yout, 3, y, on_device);
   }
   if ((rc = copy_in(C, xin, nc_in, x, on_device))) return rc;
+  if (P.refined && op != IBFE_OP_INTERP) {
+    int nc_out = 1;
+    if ((rc = apply_refined(C, op, precision, xin, yout, nc_out))) return rc;
+    return copy_out(C, yout, nc_out, y, on_device);
+  }
   switch (op) {
     case IBFE_OP_MASS:
     case IBFE_OP_STIFF: {

@@ -128,14 +128,18 @@ __device__ __forceinline__ constexpr uint32_t compat(int ox, int oy, int oz) {
   return side_mask(0, ox) & side_mask(1, oy) & side_mask(2, oz);
 }
 
+// 3x3 window of one plane around `node`; neighbours at x offsets +-st and row
+// offsets +-sy (st = 2 with doubled sy, sz addresses the coarse elements of a
+// refined lattice).
 template <typename T>
-__device__ __forceinline__ void load_plane(const T* __restrict__ x, int node, int sy, T (&w)[9]) {
+__device__ __forceinline__ void load_plane(const T* __restrict__ x, int node, int sy, T (&w)[9],
+                                           int st = 1) {
 #pragma unroll
   for (int y = -1; y <= 1; ++y) {
     const T* row = x + (node + y * sy);
-    w[(y + 1) * 3 + 0] = row[-1];
+    w[(y + 1) * 3 + 0] = row[-st];
     w[(y + 1) * 3 + 1] = row[0];
-    w[(y + 1) * 3 + 2] = row[1];
+    w[(y + 1) * 3 + 2] = row[st];
   }
 }
 
@@ -198,11 +202,11 @@ __device__ __forceinline__ T window_apply(const T (&lo)[9], const T (&mid)[9], c
 // (symmetric operators alpha M + beta K: c[t] = per-cell entry for offset type t).
 template <typename T>
 __device__ __forceinline__ T apply_sym(const T* __restrict__ x, int n, uint32_t e,
-                                       const T (&c)[4], int sy, int sz) {
+                                       const T (&c)[4], int sy, int sz, int st = 1) {
   T w0[9], w1[9], w2[9];
-  load_plane(x, n - sz, sy, w0);
-  load_plane(x, n, sy, w1);
-  load_plane(x, n + sz, sy, w2);
+  load_plane(x, n - sz, sy, w0, st);
+  load_plane(x, n, sy, w1, st);
+  load_plane(x, n + sz, sy, w2, st);
   return window_apply<T>(w0, w1, w2, e, __all(e == 0xFFu), c);
 }
 
@@ -212,7 +216,7 @@ __device__ __forceinline__ T apply_sym(const T* __restrict__ x, int n, uint32_t 
 // g2[c] = (1/2) (h/3)^(2-c) (h/6)^c with c = nonzeros among the two other axes.
 template <typename T, int D>
 __device__ __forceinline__ T apply_grad(const T* __restrict__ x, int n, uint32_t e,
-                                        const T (&g2)[3], int sy, int sz) {
+                                        const T (&g2)[3], int sy, int sz, int st = 1) {
   T acc = T(0);
 #pragma unroll
   for (int oz = -1; oz <= 1; ++oz)
@@ -229,7 +233,7 @@ __device__ __forceinline__ T apply_grad(const T* __restrict__ x, int n, uint32_t
         } else {
           mult = __builtin_popcount(cm & side_mask(D, -1)) - __builtin_popcount(cm & side_mask(D, 1));
         }
-        acc += g2[cnt_other] * T(mult) * x[n + ox + sy * oy + sz * oz];
+        acc += g2[cnt_other] * T(mult) * x[n + st * ox + sy * oy + sz * oz];
       }
   return acc;
 }

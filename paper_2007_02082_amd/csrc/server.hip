@@ -40,7 +40,7 @@ struct Job {
   ibfe_inlet inlet{};
   int32_t nsteps = 0;
   double t0 = 0.0;
-  std::vector<uint8_t> mask, tag;
+  std::vector<uint8_t> mask, tag, refine;
   std::vector<double> X, UB, shape;
   std::vector<int64_t> inlet_ids;
   size_t footprint = 0;
@@ -51,12 +51,19 @@ struct Job {
 };
 
 size_t footprint_of(const ibfe_grid& g, int64_t M, const ibfe_params& pr) {
-  const int64_t sy = int64_t(g.nx) + 1, sz = sy * (int64_t(g.ny) + 1);
-  const int64_t N = sz * (int64_t(g.nz) + 1);
-  const int64_t halo = ((sz + sy + 1 + 63) / 64) * 64;
+  const bool ref = g.refine_cell != nullptr;
+  const int64_t f = ref ? 2 : 1;
+  const int64_t sy = f * g.nx + 1, sz = sy * (f * g.ny + 1);
+  const int64_t N = sz * (f * g.nz + 1);
+  const int64_t halo = ((f * (sz + sy + 1) + 63) / 64) * 64;
   const int64_t stride = 2 * halo + ((N + 63) / 64) * 64;
   double bytes = double(stride) * (75.0 * 8.0 + 3.0);              // FP64 fields, node bytes
   if (pr.precision == 1) bytes += double(stride) * 57.0 * 4.0;     // FP32 stencil and work space
+  if (ref) {
+    // coarse stencil planes, coarse cell bits, parent slots, inverse diagonals
+    bytes += double(stride) * (27.0 * 8.0 + 1.0 + 4.0 + 24.0);
+    if (pr.precision == 1) bytes += double(stride) * 27.0 * 4.0;
+  }
   if (pr.precond == 2) bytes += 0.15 * double(stride) * (5.0 * (pr.precision == 1 ? 4 : 8) + 2.0);
   bytes += double(M) * (64.0 * 12.0 * 2.0 + 150.0 * 12.0 + 15.0 * 8.0 + 64.0);  // IB arrays, Gram CSR
   bytes += 3.0 * 8.0 * double(N + M) + 8.0 * 2048.0 * 8.0;         // compact copies, partials
@@ -176,8 +183,13 @@ int ibfe_server_submit(ibfe_server* S, const ibfe_request* req, int64_t* id) {
   if (g.nx < 1 || g.ny < 1 || g.nz < 1 || !g.node_mask) return sfail(IBFE_EINVAL, "bad grid");
   if (req->nsteps < 0) return sfail(IBFE_EINVAL, "nsteps must be >= 0");
   auto J = std::make_shared<Job>();
-  const int64_t N = (int64_t(g.nx) + 1) * (int64_t(g.ny) + 1) * (int64_t(g.nz) + 1);
+  const int64_t f = g.refine_cell ? 2 : 1;  // refined: node arrays live on the fine lattice
+  const int64_t N = (f * g.nx + 1) * (f * g.ny + 1) * (f * g.nz + 1);
   J->grid = g;
+  if (g.refine_cell) {
+    J->refine.assign(g.refine_cell, g.refine_cell + int64_t(g.nx) * g.ny * g.nz);
+    J->grid.refine_cell = J->refine.data();
+  }
   J->mask.assign(g.node_mask, g.node_mask + N);
   J->grid.node_mask = J->mask.data();
   if (g.bc_tag) {

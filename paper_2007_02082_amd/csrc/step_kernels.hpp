@@ -64,14 +64,17 @@ __global__ __launch_bounds__(kBlock) void k_s1_build(const int* __restrict__ chu
                                                      int sy, int sz, double h, double cm0, double cm1,
                                                      double cm2, double cm3, double rho,
                                                      double* __restrict__ coef64,
-                                                     float* __restrict__ coef32) {
+                                                     float* __restrict__ coef32, int st,
+                                                     uint32_t rowbit) {
+  // st = 2 (with sy, sz of the lattice) builds the coarse-element part of a
+  // refined lattice from the coarse cell bits in `emask`
   const int n = chunk_node(chunks, nchunks);
   if (n < 0) return;
   double A[27];
 #pragma unroll
   for (int t = 0; t < 27; ++t) A[t] = 0.0;
   const uint32_t e = emask[n];
-  if (flags[n] & kFlagP) {
+  if (flags[n] & rowbit) {
     const double cmk[4] = {cm0, cm1, cm2, cm3};
 #pragma unroll
     for (int oz = -1; oz <= 1; ++oz)
@@ -92,7 +95,7 @@ __global__ __launch_bounds__(kBlock) void k_s1_build(const int* __restrict__ chu
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
         const int lc[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
-        const int off = (lc[0] - li[0]) + sy * (lc[1] - li[1]) + sz * (lc[2] - li[2]);
+        const int off = st * ((lc[0] - li[0]) + sy * (lc[1] - li[1]) + sz * (lc[2] - li[2]));
 #pragma unroll
         for (int d = 0; d < 3; ++d) a[c][d] = u[d * stride + n + off];
       }

@@ -1,0 +1,141 @@
+"""GPU parity on 2:1 refined lattices (hanging-node constraints): composite
+operator applies within rounding bounds, whole steps against the FP64 oracle
+in FP64 (1e-10) and mixed precision (1e-6), and the null-space treatment of a
+refined vessel without outlet."""
+import numpy as np
+import pytest
+
+import paper_2007_02082_amd as ibfe
+import synth
+from gpu_util import make_solver, rel_l2, run_pair, say
+from oracle import fem, grid, ipcs, refine
+
+pytestmark = pytest.mark.gpu
+
+
+def _cyl():
+    return synth.refined_cylinder(8, 8, length=1.25, band=0.3)
+
+
+def _aneurysm():
+    return synth.aneurysm_case((16, 16, 40), band=1.2, nsteps=2)
+
+
+def _abs_bound(mesh, lf, lc, x):
+    """|C|^T |A| |C| |x| with |A| assembled from absolute element entries: the scale of
+    the rounding error of any summation order of the constrained row."""
+    N = mesh.N
+    A = refine._assemble(mesh.fine, np.abs(lf), N) + refine._assemble(mesh.coarse, np.abs(lc), N)
+    C = abs(mesh.C)
+    return C.T @ (A @ (C @ np.abs(x)))
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-13), (1, 2e-6)])
+def test_refined_symmetric_applies(precision, tol):
+    case = _cyl()
+    pr = ipcs.Problem.from_case(case)
+    s = make_solver(case)
+    P = pr.sets.P
+    x = np.random.default_rng(21).standard_normal(P.size)
+    xf = np.zeros(case.N)
+    xf[P] = x
+    Mf, Kf, _, _ = fem.element_matrices(case.h / 2)
+    Mc, Kc, _, _ = fem.element_matrices(case.h)
+    for op, A, lf, lc in ((ibfe.OP_MASS, pr.ops.M, Mf, Mc), (ibfe.OP_STIFF, pr.ops.K, Kf, Kc)):
+        say("refined apply", op, "precision", precision)
+        y = s.apply(op, x, precision)
+        yo = (A @ xf)[P]
+        bound = _abs_bound(pr.mesh, lf, lc, xf)[P]
+        err = np.abs(y - yo)
+        assert np.all(err <= tol * bound + 1e-300), (op, float((err / np.maximum(bound, 1e-300)).max()))
+    s.close()
+
+
+def test_refined_gradient_divergence_fp64():
+    case = _cyl()
+    pr = ipcs.Problem.from_case(case)
+    s = make_solver(case)
+    P = pr.sets.P
+    rng = np.random.default_rng(22)
+    x = rng.standard_normal(P.size)
+    xf = np.zeros(case.N)
+    xf[P] = x
+    _, _, Gf, _ = fem.element_matrices(case.h / 2)
+    _, _, Gc, _ = fem.element_matrices(case.h)
+    g = s.apply(ibfe.OP_GRAD, x).reshape(3, -1)
+    for d in range(3):
+        bound = _abs_bound(pr.mesh, Gf[d], Gc[d], xf)[P]
+        assert np.all(np.abs(g[d] - (pr.ops.G[d] @ xf)[P]) <= 1e-13 * bound + 1e-300), d
+    u = rng.standard_normal((3, P.size))
+    uf = np.zeros((3, case.N))
+    uf[:, P] = u
+    dv = s.apply(ibfe.OP_DIV, u.ravel())
+    bound = sum(_abs_bound(pr.mesh, Gf[d], Gc[d], uf[d]) for d in range(3))[P]
+    assert np.all(np.abs(dv - pr.ops.divergence(uf)[P]) <= 1e-13 * bound + 1e-300)
+    s.close()
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-6)])
+def test_refined_advection_diffusion_apply(precision, tol):
+    case = _cyl()
+    pr = ipcs.Problem.from_case(case)
+    s = make_solver(case)
+    P = pr.sets.P
+    rng = np.random.default_rng(23)
+    a = rng.standard_normal((3, P.size))
+    s.set_state(a, np.zeros(P.size), 0.0)
+    af = np.zeros((3, case.N))
+    af[:, P] = a
+    A = (case.rho / case.dt) * pr.ops.M + case.rho * pr.ops.advection(af) + case.mu * pr.ops.K
+    x = rng.standard_normal((3, P.size))
+    xf = np.zeros((3, case.N))
+    xf[:, P] = x
+    y = s.apply(ibfe.OP_ADVDIFF, x.ravel(), precision).reshape(3, -1)
+    for d in range(3):
+        e = rel_l2(y[d], (A @ xf[d])[P])
+        say("advdiff", precision, d, e)
+        assert e <= tol
+    s.close()
+
+
+def _check(out, tol, label):
+    for k, r in enumerate(out):
+        errs = {f: rel_l2(r["g_" + f], r["o_" + f]) for f in ("ustar", "uib", "u", "p")}
+        floor = max(np.linalg.norm(r["o_phi"]), np.linalg.norm(r["o_p"]))
+        errs["phi"] = float(np.linalg.norm(r["g_phi"] - r["o_phi"]) / floor)
+        say(f"{label} step {k}: " + " ".join(f"{f}={e:.2e}" for f, e in errs.items()),
+            "gpu iters", {x: r["stats"][x] for x in ("s1_iters", "ib_iters", "s3_iters", "s4_iters")})
+        for f, e in errs.items():
+            assert e <= tol, (label, k, f, e)
+
+
+@pytest.mark.parametrize("make", [_cyl, _aneurysm])
+def test_refined_step_parity_fp64(make):
+    case = make()
+    say("refined case", case.name, "N", case.N, "M", case.M)
+    _, out = run_pair(case, 3)
+    _check(out, 1e-10, case.name)
+
+
+@pytest.mark.parametrize("make", [_cyl, _aneurysm])
+def test_refined_step_parity_mixed(make):
+    case = make()
+    say("refined case mixed", case.name)
+    _, out = run_pair(case, 3, precision=1)
+    _check(out, 1e-6, case.name + " mixed")
+
+
+def test_refined_without_outlet_null_space():
+    """No outlet: the pressure increment is normalised to zero nodal mean."""
+    case = _cyl()
+    tag = grid.default_tags(2 * case.nx, 2 * case.ny, 2 * case.nz)
+    tag[tag == grid.TAG_OUTLET] = grid.TAG_WALL
+    case.bc_tag = tag
+    rng = np.random.default_rng(24)
+    case.u0 = 0.1 * rng.standard_normal((3, case.N))
+    say("refined closed", case.name)
+    pr, out = run_pair(case, 2)
+    assert len(pr.floating) == 1
+    _check(out, 1e-10, "refined closed")
+    phi = out[-1]["g_phi"]
+    assert abs(phi.mean()) < 1e-12 * np.abs(phi).max()
