@@ -73,6 +73,7 @@ struct MGDev {
   int* zitems = nullptr;
   T *b = nullptr, *x = nullptr, *xt = nullptr, *d = nullptr, *r = nullptr;
   double kc[4] = {0, 0, 0, 0};  // per-cell stiffness entries at this spacing
+  bool composite = false;       // level 0 of a refined lattice (composite operator)
   int m = 0;                    // coarsest: unknowns with a dense inverse
   int64_t* ids = nullptr;
   T* inv = nullptr;
@@ -251,6 +252,7 @@ int setup_mg(ibfe_ctx& c, std::vector<MGDev<T>>& out, T* xt0, T* d0, T* r0) {
       D.xt = xt0;
       D.d = d0;
       D.r = r0;
+      D.composite = P.refined;
     } else {
       const int64_t nch = (L.N + kChunk - 1) / kChunk;
       D.halo = ((L.sz + L.sy + 1 + kChunk - 1) / kChunk) * kChunk;
@@ -762,6 +764,139 @@ OpCSR<3> gram_op(const ibfe_ctx& c) {
 
 
 // -------------------------------------------------------------------------
+// 2:1 refined lattice: composite operators (fine + coarse elements with the
+// hanging-node constraint) behind the same Krylov drivers
+// -------------------------------------------------------------------------
+
+Children children_of(const ibfe_ctx& c) { return Children{c.pslot, c.par_ptr, c.par_child, c.nh}; }
+
+template <typename T>
+struct RefBufs;
+template <>
+struct RefBufs<double> {
+  static const double* pw(const ibfe_ctx& c) { return c.pw64; }
+  static double* yh(const ibfe_ctx& c) { return c.yh64; }
+  static const double* dinvM(const ibfe_ctx& c) { return c.dinvM64; }
+  static const double* dinvK(const ibfe_ctx& c) { return c.dinvK64; }
+};
+template <>
+struct RefBufs<float> {
+  static const float* pw(const ibfe_ctx& c) { return c.pw32; }
+  static float* yh(const ibfe_ctx& c) { return c.yh32; }
+  static const float* dinvM(const ibfe_ctx& c) { return c.dinvM32; }
+  static const float* dinvK(const ibfe_ctx& c) { return c.dinvK32; }
+};
+
+// alpha M + beta K of the composite mesh: coef(h) = alpha m(h) + beta k(h)
+template <typename T, int NC>
+OpCSym<T, NC> csym_op(const ibfe_ctx& c, double alpha, double beta, uint32_t rowbit, const T* dinv) {
+  OpCSym<T, NC> op{};
+  op.emask = c.emask;
+  op.cmask = c.cmask;
+  op.flags = c.flags;
+  op.rowbit = rowbit;
+  op.sy = int(c.plan.sy);
+  op.sz = int(c.plan.sz);
+  op.stride = c.stride;
+  for (int t = 0; t < 4; ++t) {
+    op.cf[t] = T(alpha * c.fc.m[t] + beta * c.fc.k[t]);
+    op.cc[t] = T(alpha * c.fcc.m[t] + beta * c.fcc.k[t]);
+  }
+  op.dinv = dinv;
+  op.ch = children_of(c);
+  op.pw = RefBufs<T>::pw(c);
+  op.yh = RefBufs<T>::yh(c);
+  return op;
+}
+
+template <typename T>
+OpCStencil<T, 3> cstencil_op(const ibfe_ctx& c, const T* coef, uint32_t rowbit) {
+  OpCStencil<T, 3> op{};
+  op.coef = coef;
+  op.cmask = c.cmask;
+  op.flags = c.flags;
+  op.rowbit = rowbit;
+  op.sy = int(c.plan.sy);
+  op.sz = int(c.plan.sz);
+  op.stride = c.stride;
+  op.ch = children_of(c);
+  op.pw = RefBufs<T>::pw(c);
+  op.yh = RefBufs<T>::yh(c);
+  return op;
+}
+
+GradElem grad_elem(const ibfe_ctx& c, const double* x) {
+  GradElem g{};
+  g.emask = c.emask;
+  g.cmask = c.cmask;
+  g.x = x;
+  g.sy = int(c.plan.sy);
+  g.sz = int(c.plan.sz);
+  for (int k = 0; k < 3; ++k) {
+    g.gf[k] = c.fc.g2[k];
+    g.gc[k] = c.fcc.g2[k];
+  }
+  return g;
+}
+
+// x[h] = mean of the parents of every hanging node (nc planes)
+template <typename T>
+int fill_hanging(ibfe_ctx& c, T* x, int nc) {
+  if (c.nh == 0) return IBFE_OK;
+  hipLaunchKernelGGL(k_hang_fill<T>, dim3(blocks_lin(c.nh)), dim3(kBlock), 0, c.stream, c.nh,
+                     (const int32_t*)c.hang_ids, (const int32_t*)c.hang_par, x, nc, c.stride,
+                     (const KScal*)nullptr);
+  CHECK_LAUNCH();
+  return IBFE_OK;
+}
+
+// out = scale * C^T (element rows of f) on rows; f's inputs must be filled.
+template <typename T, class F>
+int comp_rows(ibfe_ctx& c, const F& f, uint32_t rowbit, uint32_t exclude, T scale, T* out) {
+  T* yh = RefBufs<T>::yh(c);
+  if (c.nh)
+    hipLaunchKernelGGL((k_hang_elem<T, F>), dim3(blocks_lin(c.nh)), dim3(kBlock), 0, c.stream, c.nh,
+                       (const int32_t*)c.hang_ids, f, yh, (const KScal*)nullptr);
+  hipLaunchKernelGGL((k_comp_rows<T, F>), dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
+                     (const int*)c.chunks, c.nchunks, f, (const uint8_t*)c.flags, rowbit, exclude, scale,
+                     children_of(c), RefBufs<T>::pw(c), (const T*)yh, out, c.stride);
+  CHECK_LAUNCH();
+  return IBFE_OK;
+}
+
+int cheb_steps(double tol, double lmin, double lmax) {
+  const double kappa = lmax / lmin;
+  const double q = (std::sqrt(kappa) - 1.0) / (std::sqrt(kappa) + 1.0);
+  return int(std::ceil((std::log(2.0 / tol) + 0.5 * std::log(kappa)) / std::log(1.0 / q)));
+}
+
+// x = Cheb_iters(b) from x = 0 for any operator on [lmin, lmax] of D^-1 A.
+template <typename T, class Op>
+int run_cheb_gen(ibfe_ctx& c, const Op& op, const T* b, T* x, T* xalt, T* d, int iters, double lmin,
+                 double lmax) {
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+  T* cur = ((iters - 1) % 2 == 0) ? x : xalt;
+  T* alt = cur == x ? xalt : x;
+  hipLaunchKernelGGL((k_cheb0_gen<T, Op>), dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
+                     (const int*)c.chunks, c.nchunks, op, b, d, cur, T(1.0 / theta), (const KScal*)nullptr);
+  const int nr = red_blocks(c.nchunks);
+  double rho = 1.0 / sigma;
+  int rc;
+  for (int k = 1; k < iters; ++k) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    const T c1 = T(rn * rho), c2 = T(2.0 * rn / delta);
+    rho = rn;
+    if ((rc = pre_apply(c, op, cur, (const KScal*)nullptr))) return rc;
+    hipLaunchKernelGGL((k_cheb_gen<T, Op, false>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.chunks,
+                       c.nchunks, op, (const T*)cur, b, d, alt, c1, c2, c.partials, (const KScal*)nullptr);
+    std::swap(cur, alt);
+  }
+  CHECK_LAUNCH();
+  if (cur != x) return fail(IBFE_EINVAL, "internal: Chebyshev result buffer");
+  return IBFE_OK;
+}
+
+// -------------------------------------------------------------------------
 // multigrid-preconditioned CG for the pressure increment
 // -------------------------------------------------------------------------
 
@@ -806,9 +941,46 @@ ZOp<T> level_op(const MGDev<T>& L) {
 
 // m Chebyshev steps on level L for b, continuing from *x (zero_start: from x = 0);
 // ping-pongs between *x and *alt.  With dot, the last step writes partials of b.x.
+// The same smoother on the composite level of a refined lattice: Jacobi with
+// the lumped constrained diagonal D', whose D'^-1 K spectrum is also bounded by
+// 2 (every element stiffness has non-positive off-diagonal entries and zero row
+// sums, and the constraint only adds the children's diagonals to the parents).
+template <typename T>
+int smooth_comp(ibfe_ctx& c, const MGDev<T>& L, const T* b, T*& x, T*& alt, int m, bool zero_start,
+                bool dot, const KScal* sc, int& nparts) {
+  const Cheb ch = cheb_coefs(m);
+  const auto op = csym_op<T, 1>(c, 0.0, 1.0, kMgRow, RefBufs<T>::dinvK(c));
+  using Op = OpCSym<T, 1>;
+  const int nr = red_blocks(c.nchunks), nb = blocks_for(c.nchunks);
+  int rc;
+  for (int k = 0; k < m; ++k) {
+    const bool last = k == m - 1;
+    if (k == 0 && zero_start && !(last && dot)) {
+      hipLaunchKernelGGL((k_cheb0_gen<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, (const int*)c.chunks,
+                         c.nchunks, op, b, L.d, x, T(ch.c2[0]), sc);
+      continue;
+    }
+    if (k == 0 && zero_start)
+      hipLaunchKernelGGL((k_cheb0_gen<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, (const int*)c.chunks,
+                         c.nchunks, op, b, L.d, x, T(0), sc);
+    if ((rc = pre_apply(c, op, x, sc))) return rc;
+    if (last && dot)
+      hipLaunchKernelGGL((k_cheb_gen<T, Op, true>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.chunks,
+                         c.nchunks, op, (const T*)x, b, L.d, alt, T(ch.c1[k]), T(ch.c2[k]), c.partials, sc);
+    else
+      hipLaunchKernelGGL((k_cheb_gen<T, Op, false>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.chunks,
+                         c.nchunks, op, (const T*)x, b, L.d, alt, T(ch.c1[k]), T(ch.c2[k]), c.partials, sc);
+    std::swap(x, alt);
+  }
+  nparts = nr;
+  CHECK_LAUNCH();
+  return IBFE_OK;
+}
+
 template <typename T>
 int smooth(ibfe_ctx& c, const MGDev<T>& L, const T* b, T*& x, T*& alt, int m, bool zero_start,
            bool dot, const KScal* sc, int& nparts) {
+  if (L.composite) return smooth_comp<T>(c, L, b, x, alt, m, zero_start, dot, sc, nparts);
   const Cheb ch = cheb_coefs(m);
   const ZOp<T> op = level_op(L);
   const int nr = red_blocks(L.nzitems);
@@ -859,8 +1031,15 @@ int vcycle(ibfe_ctx& c, std::vector<MGDev<T>>& lv, const T* r0, T* z0, const KSc
     const MGDev<T>& A = lv[l];
     const T* b = l == 0 ? r0 : A.b;
     if ((rc = smooth<T>(c, A, b, cur[l], alt[l], kSmooth, true, false, sc, np))) return rc;
-    hipLaunchKernelGGL(k_zb_resid<T>, dim3(red_blocks(A.nzitems)), dim3(kBlock), 0, c.stream,
-                       (const int*)A.zitems, A.nzitems, level_op(A), (const T*)cur[l], b, A.r, sc);
+    if (A.composite) {
+      const auto op = csym_op<T, 1>(c, 0.0, 1.0, kMgRow, RefBufs<T>::dinvK(c));
+      if ((rc = pre_apply(c, op, cur[l], sc))) return rc;
+      hipLaunchKernelGGL((k_resid_gen<T, OpCSym<T, 1>>), dim3(blocks_for(c.nchunks)), dim3(kBlock), 0,
+                         c.stream, (const int*)c.chunks, c.nchunks, op, (const T*)cur[l], b, A.r, sc);
+    } else {
+      hipLaunchKernelGGL(k_zb_resid<T>, dim3(red_blocks(A.nzitems)), dim3(kBlock), 0, c.stream,
+                         (const int*)A.zitems, A.nzitems, level_op(A), (const T*)cur[l], b, A.r, sc);
+    }
     const MGDev<T>& C = lv[l + 1];
     hipLaunchKernelGGL(k_mg_restrict<T>, dim3(blocks_for(C.nchunks)), dim3(kBlock), 0, c.stream,
                        (const int*)C.chunks, C.nchunks, (const uint8_t*)C.flags, int(C.sy), int(C.sz),
@@ -900,14 +1079,12 @@ int vcycle(ibfe_ctx& c, std::vector<MGDev<T>>& lv, const T* r0, T* z0, const KSc
 }
 
 // CG on K_{P'P'} x = b preconditioned by one V-cycle per iteration; x starts at 0.
-template <typename T>
-int run_pcg_mg(ibfe_ctx& c, std::vector<MGDev<T>>& lv, const T* b, T* x, T* r, T* p, T* q, T* z, int slot,
-               double rtol, int max_iters, SolveOut& out, bool timed) {
+template <typename T, class Op>
+int run_pcg_mg(ibfe_ctx& c, const Op& op, std::vector<MGDev<T>>& lv, const T* b, T* x, T* r, T* p, T* q,
+               T* z, int slot, double rtol, int max_iters, SolveOut& out, bool timed) {
   const int nr = red_blocks(c.nchunks);
   KScal* sc = &c.scal[slot];
   const KScal* csc = sc;
-  const double kc[4] = {c.fc.k[0], c.fc.k[1], c.fc.k[2], c.fc.k[3]};
-  auto op = sym_op<T, 1>(c, kc, kFlagPp);
   int rc, np = 0;
   hipLaunchKernelGGL(k_mgcg_init<T>, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.chunks, c.nchunks,
                      (const uint8_t*)c.flags, b, x, r, c.partials);
@@ -926,6 +1103,7 @@ int run_pcg_mg(ibfe_ctx& c, std::vector<MGDev<T>>& lv, const T* b, T* x, T* r, T
     for (int k = 0; k < batch; ++k) {
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (timed && timer_events(c, size_t(launched + k), e0, e1)) return IBFE_EHIP;
+      if ((rc = pre_apply(c, op, p, csc))) return rc;
       const int nq = launch_q<T>(c, op, c.chunks, c.nchunks, (const T*)p, q, csc, e0, e1);
       hipLaunchKernelGGL(k_fin_cg_q, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nq, sc);
       hipLaunchKernelGGL(k_mgcg_xr<T>, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.chunks, c.nchunks,
@@ -1141,14 +1319,14 @@ int step_once(ibfe_ctx& c) {
       rc = run_refined(c, op, kFlagPp, 1, b3, c.phi, v[8], v[9], rtol, so,
                        [&](const float* r32, float* d32, double tol, SolveOut& o) {
                          if (mg)
-                           return run_pcg_mg<float>(c, c.mg32, r32, d32, v[0], v[1], v[2], v[3], kScS3, tol,
-                                                    maxit, o, c.timing);
+                           return run_pcg_mg<float>(c, op32, c.mg32, r32, d32, v[0], v[1], v[2], v[3], kScS3,
+                                                    tol, maxit, o, c.timing);
                          return run_cg<float>(c, op32, c.chunks, c.nchunks, r32, d32, v[0], v[1], v[2], kScS3,
                                               tol, maxit, true, o, c.timing);
                        });
     } else if (mg) {
-      rc = run_pcg_mg<double>(c, c.mg64, b3, c.phi, c.w[0], c.w[1], c.w[2], c.w[3], kScS3, rtol, maxit, so,
-                              c.timing);
+      rc = run_pcg_mg<double>(c, op, c.mg64, b3, c.phi, c.w[0], c.w[1], c.w[2], c.w[3], kScS3, rtol, maxit,
+                              so, c.timing);
     } else {
       rc = run_cg<double>(c, op, c.chunks, c.nchunks, b3, c.phi, c.w[0], c.w[1], c.w[2], kScS3, rtol, maxit,
                           true, so, c.timing);
@@ -1214,139 +1392,6 @@ int step_once(ibfe_ctx& c) {
   c.steps += 1;
   c.stats.steps = c.steps;
   c.stats.t = c.t;
-  return IBFE_OK;
-}
-
-// -------------------------------------------------------------------------
-// 2:1 refined lattice: composite operators (fine + coarse elements with the
-// hanging-node constraint) behind the same Krylov drivers
-// -------------------------------------------------------------------------
-
-Children children_of(const ibfe_ctx& c) { return Children{c.pslot, c.par_ptr, c.par_child, c.nh}; }
-
-template <typename T>
-struct RefBufs;
-template <>
-struct RefBufs<double> {
-  static const double* pw(const ibfe_ctx& c) { return c.pw64; }
-  static double* yh(const ibfe_ctx& c) { return c.yh64; }
-  static const double* dinvM(const ibfe_ctx& c) { return c.dinvM64; }
-  static const double* dinvK(const ibfe_ctx& c) { return c.dinvK64; }
-};
-template <>
-struct RefBufs<float> {
-  static const float* pw(const ibfe_ctx& c) { return c.pw32; }
-  static float* yh(const ibfe_ctx& c) { return c.yh32; }
-  static const float* dinvM(const ibfe_ctx& c) { return c.dinvM32; }
-  static const float* dinvK(const ibfe_ctx& c) { return c.dinvK32; }
-};
-
-// alpha M + beta K of the composite mesh: coef(h) = alpha m(h) + beta k(h)
-template <typename T, int NC>
-OpCSym<T, NC> csym_op(const ibfe_ctx& c, double alpha, double beta, uint32_t rowbit, const T* dinv) {
-  OpCSym<T, NC> op{};
-  op.emask = c.emask;
-  op.cmask = c.cmask;
-  op.flags = c.flags;
-  op.rowbit = rowbit;
-  op.sy = int(c.plan.sy);
-  op.sz = int(c.plan.sz);
-  op.stride = c.stride;
-  for (int t = 0; t < 4; ++t) {
-    op.cf[t] = T(alpha * c.fc.m[t] + beta * c.fc.k[t]);
-    op.cc[t] = T(alpha * c.fcc.m[t] + beta * c.fcc.k[t]);
-  }
-  op.dinv = dinv;
-  op.ch = children_of(c);
-  op.pw = RefBufs<T>::pw(c);
-  op.yh = RefBufs<T>::yh(c);
-  return op;
-}
-
-template <typename T>
-OpCStencil<T, 3> cstencil_op(const ibfe_ctx& c, const T* coef, uint32_t rowbit) {
-  OpCStencil<T, 3> op{};
-  op.coef = coef;
-  op.cmask = c.cmask;
-  op.flags = c.flags;
-  op.rowbit = rowbit;
-  op.sy = int(c.plan.sy);
-  op.sz = int(c.plan.sz);
-  op.stride = c.stride;
-  op.ch = children_of(c);
-  op.pw = RefBufs<T>::pw(c);
-  op.yh = RefBufs<T>::yh(c);
-  return op;
-}
-
-GradElem grad_elem(const ibfe_ctx& c, const double* x) {
-  GradElem g{};
-  g.emask = c.emask;
-  g.cmask = c.cmask;
-  g.x = x;
-  g.sy = int(c.plan.sy);
-  g.sz = int(c.plan.sz);
-  for (int k = 0; k < 3; ++k) {
-    g.gf[k] = c.fc.g2[k];
-    g.gc[k] = c.fcc.g2[k];
-  }
-  return g;
-}
-
-// x[h] = mean of the parents of every hanging node (nc planes)
-template <typename T>
-int fill_hanging(ibfe_ctx& c, T* x, int nc) {
-  if (c.nh == 0) return IBFE_OK;
-  hipLaunchKernelGGL(k_hang_fill<T>, dim3(blocks_lin(c.nh)), dim3(kBlock), 0, c.stream, c.nh,
-                     (const int32_t*)c.hang_ids, (const int32_t*)c.hang_par, x, nc, c.stride,
-                     (const KScal*)nullptr);
-  CHECK_LAUNCH();
-  return IBFE_OK;
-}
-
-// out = scale * C^T (element rows of f) on rows; f's inputs must be filled.
-template <typename T, class F>
-int comp_rows(ibfe_ctx& c, const F& f, uint32_t rowbit, uint32_t exclude, T scale, T* out) {
-  T* yh = RefBufs<T>::yh(c);
-  if (c.nh)
-    hipLaunchKernelGGL((k_hang_elem<T, F>), dim3(blocks_lin(c.nh)), dim3(kBlock), 0, c.stream, c.nh,
-                       (const int32_t*)c.hang_ids, f, yh, (const KScal*)nullptr);
-  hipLaunchKernelGGL((k_comp_rows<T, F>), dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
-                     (const int*)c.chunks, c.nchunks, f, (const uint8_t*)c.flags, rowbit, exclude, scale,
-                     children_of(c), RefBufs<T>::pw(c), (const T*)yh, out, c.stride);
-  CHECK_LAUNCH();
-  return IBFE_OK;
-}
-
-int cheb_steps(double tol, double lmin, double lmax) {
-  const double kappa = lmax / lmin;
-  const double q = (std::sqrt(kappa) - 1.0) / (std::sqrt(kappa) + 1.0);
-  return int(std::ceil((std::log(2.0 / tol) + 0.5 * std::log(kappa)) / std::log(1.0 / q)));
-}
-
-// x = Cheb_iters(b) from x = 0 for any operator on [lmin, lmax] of D^-1 A.
-template <typename T, class Op>
-int run_cheb_gen(ibfe_ctx& c, const Op& op, const T* b, T* x, T* xalt, T* d, int iters, double lmin,
-                 double lmax) {
-  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
-  T* cur = ((iters - 1) % 2 == 0) ? x : xalt;
-  T* alt = cur == x ? xalt : x;
-  hipLaunchKernelGGL((k_cheb0_gen<T, Op>), dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
-                     (const int*)c.chunks, c.nchunks, op, b, d, cur, T(1.0 / theta), (const KScal*)nullptr);
-  const int nr = red_blocks(c.nchunks);
-  double rho = 1.0 / sigma;
-  int rc;
-  for (int k = 1; k < iters; ++k) {
-    const double rn = 1.0 / (2.0 * sigma - rho);
-    const T c1 = T(rn * rho), c2 = T(2.0 * rn / delta);
-    rho = rn;
-    if ((rc = pre_apply(c, op, cur, (const KScal*)nullptr))) return rc;
-    hipLaunchKernelGGL((k_cheb_gen<T, Op, false>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.chunks,
-                       c.nchunks, op, (const T*)cur, b, d, alt, c1, c2, c.partials, (const KScal*)nullptr);
-    std::swap(cur, alt);
-  }
-  CHECK_LAUNCH();
-  if (cur != x) return fail(IBFE_EINVAL, "internal: Chebyshev result buffer");
   return IBFE_OK;
 }
 
@@ -1477,6 +1522,7 @@ int step_once_refined(ibfe_ctx& c) {
     if ((rc = comp_rows<double>(c, f, kFlagPp, 0u, -rho / dt, b3))) return rc;
     if (P.n_floating > 0 && (rc = remove_slot_means(c, b3))) return rc;
     auto op = csym_op<double, 1>(c, 0.0, 1.0, kFlagPp, c.dinvK64);
+    const bool mg = P.params.precond == 2;
     SolveOut so;
     if (mixed) {
       auto op32 = csym_op<float, 1>(c, 0.0, 1.0, kFlagPp, c.dinvK32);
@@ -1484,12 +1530,18 @@ int step_once_refined(ibfe_ctx& c) {
       float* const* v = c.v32;
       rc = run_refined(c, op, kFlagPp, 1, b3, c.phi, v[8], v[9], rtol, so,
                        [&](const float* r32, float* d32, double tol, SolveOut& o) {
+                         if (mg)
+                           return run_pcg_mg<float>(c, op32, c.mg32, r32, d32, v[0], v[1], v[2], v[3], kScS3,
+                                                    tol, maxit, o, c.timing);
                          return run_cg<float>(c, op32, c.chunks, c.nchunks, r32, d32, v[0], v[1], v[2], kScS3,
-                                              tol, maxit, true, o, false);
+                                              tol, maxit, true, o, c.timing);
                        });
+    } else if (mg) {
+      rc = run_pcg_mg<double>(c, op, c.mg64, b3, c.phi, c.w[0], c.w[1], c.w[2], c.w[3], kScS3, rtol, maxit,
+                              so, c.timing);
     } else {
       rc = run_cg<double>(c, op, c.chunks, c.nchunks, b3, c.phi, c.w[0], c.w[1], c.w[2], kScS3, rtol, maxit,
-                          true, so, false);
+                          true, so, c.timing);
     }
     if (rc) return rc;
     c.stats.s3_iters = so.iters;

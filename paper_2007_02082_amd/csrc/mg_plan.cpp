@@ -198,8 +198,54 @@ int build_multigrid(Plan& P, std::string& err) {
     if (f & IBFE_FLAG_P) L0.flags[n] = kMgP | ((f & IBFE_FLAG_PDIR) ? 0 : kMgPp);
   }
   L0.chunks = P.chunks;
-  column_items(L0.emask, L0.sz, L0.nz + 1, L0.zitems, L0.cpp);
+  if (!P.refined) column_items(L0.emask, L0.sz, L0.nz + 1, L0.zitems, L0.cpp);
   P.mg.push_back(std::move(L0));
+  if (P.refined) {
+    // level 1 = the base grid: a base cell is kept when it is a kept unrefined
+    // cell or one of its 2x2x2 children is kept; Dirichlet colocated as below
+    const MGLevel& F = P.mg.back();
+    MGLevel C;
+    C.nx = P.bnx;
+    C.ny = P.bny;
+    C.nz = P.bnz;
+    C.h = P.hb;
+    C.sy = C.nx + 1;
+    C.sz = C.sy * (C.ny + 1);
+    C.N = C.sz * (C.nz + 1);
+    C.emask.assign(C.N, 0);
+    for (int k = 0; k < C.nz; ++k)
+      for (int j = 0; j < C.ny; ++j)
+        for (int i = 0; i < C.nx; ++i) {
+          const int64_t f0 = 2 * i + F.sy * 2 * j + F.sz * 2 * k;
+          bool kept;
+          if (P.refine[i + int64_t(C.nx) * (j + int64_t(C.ny) * k)]) {
+            kept = false;
+            for (int a = 0; a < 8 && !kept; ++a)
+              kept = (P.emask[f0 + (a & 1) + F.sy * ((a >> 1) & 1) + F.sz * ((a >> 2) & 1)] >> 7) & 1u;
+          } else {
+            kept = (P.cmask[f0] >> 7) & 1u;
+          }
+          if (!kept) continue;
+          for (int a = 0; a < 8; ++a) {
+            const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
+            const int64_t cn = (i + ax) + C.sy * (j + ay) + C.sz * (k + az);
+            C.emask[cn] |= uint8_t(1u << ((1 - ax) + 2 * (1 - ay) + 4 * (1 - az)));
+          }
+        }
+    C.flags.assign(C.N, 0);
+    for (int k = 0; k <= C.nz; ++k)
+      for (int j = 0; j <= C.ny; ++j)
+        for (int i = 0; i <= C.nx; ++i) {
+          const int64_t cn = i + C.sy * j + C.sz * k;
+          if (!C.emask[cn]) continue;
+          const int64_t fn = 2 * i + F.sy * 2 * j + F.sz * 2 * k;
+          const bool dir = (F.flags[fn] & kMgP) && !(F.flags[fn] & kMgPp);
+          C.flags[cn] = kMgP | (dir ? 0 : kMgPp);
+        }
+    chunk_list(C.emask, C.chunks);
+    column_items(C.emask, C.sz, C.nz + 1, C.zitems, C.cpp);
+    P.mg.push_back(std::move(C));
+  }
   auto unknowns = [](const MGLevel& L) {
     int64_t c = 0;
     for (uint8_t f : L.flags) c += (f & kMgPp) ? 1 : 0;

@@ -410,10 +410,6 @@ int build_plan(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* para
       P.G_ptr.push_back(int64_t(P.G_col.size()));
     }
   }
-  if (P.params.precond == 2 && P.refined) {
-    err = "multigrid is not available on refined grids yet (use precond 0)";
-    return IBFE_EINVAL;
-  }
   if (P.params.precond == 2) {
     int rc = build_multigrid(P, err);
     if (rc) return rc;

@@ -139,3 +139,17 @@ def test_refined_without_outlet_null_space():
     _check(out, 1e-10, "refined closed")
     phi = out[-1]["g_phi"]
     assert abs(phi.mean()) < 1e-12 * np.abs(phi).max()
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-6)])
+@pytest.mark.parametrize("make", [_cyl, _aneurysm])
+def test_refined_step_parity_multigrid(make, precision, tol):
+    """Pressure increment with the composite-level V-cycle (base grid below it)."""
+    case = make()
+    say("refined multigrid", case.name, precision)
+    _, out = run_pair(case, 3, precision=precision, precond=2)
+    _check(out, tol, f"{case.name} mg p{precision}")
+    _, out_j = run_pair(case, 1, precision=precision, precond=0)
+    mg_it, j_it = out[0]["stats"]["s3_iters"], out_j[0]["stats"]["s3_iters"]
+    say("s3 iterations: multigrid", mg_it, "Jacobi", j_it)
+    assert mg_it < j_it
