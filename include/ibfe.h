@@ -173,6 +173,8 @@ typedef struct ibfe_stats {
   double s1_res, ib_res, s3_res, s4_res; /* final relative residuals            */
   double poisson_apply_ms;   /* summed duration of the pressure stiffness apply  */
   int64_t poisson_applies;   /* number of those launches (timed if enabled)      */
+  double mass_apply_ms;      /* summed duration of the mass Chebyshev steps of   */
+  int64_t mass_applies;      /* the velocity correction, and their number        */
 } ibfe_stats;
 
 typedef struct ibfe_plan ibfe_plan;
@@ -214,7 +216,9 @@ int ibfe_step(ibfe_ctx* ctx, int nsteps);
 /* Read u, p (either may be NULL) and t; synchronises the stream for host output. */
 int ibfe_get_state(ibfe_ctx* ctx, double* u, double* p, double* t, int on_device);
 int ibfe_get_stats(const ibfe_ctx* ctx, ibfe_stats* stats);
-/* Enable (1) or disable (0) HIP-event timing of the pressure stiffness apply. */
+/* Enable (1) or disable (0) HIP-event timing of the pressure stiffness apply
+ * and of the mass Chebyshev step of the velocity correction (both counters are
+ * reset by this call; statistics accumulate until the next call). */
 int ibfe_set_kernel_timing(ibfe_ctx* ctx, int enable);
 
 /* Intermediate fields of the last step, canonical order:

@@ -56,7 +56,8 @@ class Stats(C.Structure):
                 ("s1_outer", C.c_int32), ("s3_outer", C.c_int32), ("s4_outer", C.c_int32),
                 ("s1_res", C.c_double), ("ib_res", C.c_double), ("s3_res", C.c_double),
                 ("s4_res", C.c_double), ("poisson_apply_ms", C.c_double),
-                ("poisson_applies", C.c_int64)]
+                ("poisson_applies", C.c_int64), ("mass_apply_ms", C.c_double),
+                ("mass_applies", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -163,10 +163,12 @@ struct ibfe_ctx {
   ibfe_stats stats{};
   bool timing = false;
   std::vector<hipEvent_t> ev;
+  std::vector<hipEvent_t> ev_mass;  // timer events of the mass Chebyshev steps
   int est[kNumScal] = {};
 
   ~ibfe_ctx() {
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ev_mass) (void)hipEventDestroy(e);
     for (void* b : blocks) {
       if (user_alloc)
         alloc.free(b, alloc.user);
@@ -569,6 +571,31 @@ int timer_events(ibfe_ctx& c, size_t k, hipEvent_t& e0, hipEvent_t& e1) {
   return IBFE_OK;
 }
 
+// Event pair k of the mass-step timer.
+int mass_events(ibfe_ctx& c, size_t k, hipEvent_t& e0, hipEvent_t& e1) {
+  while (c.ev_mass.size() < 2 * k + 2) {
+    hipEvent_t ne;
+    HIP_TRY(hipEventCreate(&ne));
+    c.ev_mass.push_back(ne);
+  }
+  e0 = c.ev_mass[2 * k];
+  e1 = c.ev_mass[2 * k + 1];
+  return IBFE_OK;
+}
+
+// Add the durations of the first n timed mass steps to the statistics.
+int collect_mass_events(ibfe_ctx& c, int n) {
+  if (n <= 0) return IBFE_OK;
+  HIP_TRY(hipEventSynchronize(c.ev_mass[2 * (n - 1) + 1]));
+  for (int k = 0; k < n; ++k) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, c.ev_mass[2 * k], c.ev_mass[2 * k + 1]));
+    c.stats.mass_apply_ms += ms;
+    c.stats.mass_applies += 1;
+  }
+  return IBFE_OK;
+}
+
 template <typename T, class Op>
 int run_cg(ibfe_ctx& c, const Op& op, const int* chunks, int nchunks, const T* b, T* x, T* r, T* p,
            T* q, int slot, double rtol, int max_iters, bool zero_guess, SolveOut& out,
@@ -887,11 +914,19 @@ int run_cheb_gen(ibfe_ctx& c, const Op& op, const T* b, T* x, T* xalt, T* d, int
     const T c1 = T(rn * rho), c2 = T(2.0 * rn / delta);
     rho = rn;
     if ((rc = pre_apply(c, op, cur, (const KScal*)nullptr))) return rc;
-    hipLaunchKernelGGL((k_cheb_gen<T, Op, false>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.chunks,
-                       c.nchunks, op, (const T*)cur, b, d, alt, c1, c2, c.partials, (const KScal*)nullptr);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c.timing && mass_events(c, size_t(k - 1), e0, e1)) return IBFE_EHIP;
+    if (e0)
+      hipExtLaunchKernelGGL((k_cheb_gen<T, Op, false>), dim3(nr), dim3(kBlock), 0, c.stream, e0, e1, 0,
+                            (const int*)c.chunks, c.nchunks, op, (const T*)cur, b, d, alt, c1, c2, c.partials,
+                            (const KScal*)nullptr);
+    else
+      hipLaunchKernelGGL((k_cheb_gen<T, Op, false>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.chunks,
+                         c.nchunks, op, (const T*)cur, b, d, alt, c1, c2, c.partials, (const KScal*)nullptr);
     std::swap(cur, alt);
   }
   CHECK_LAUNCH();
+  if (c.timing && (rc = collect_mass_events(c, iters - 1))) return rc;
   if (cur != x) return fail(IBFE_EINVAL, "internal: Chebyshev result buffer");
   return IBFE_OK;
 }
@@ -1178,12 +1213,23 @@ int run_cheb_mass(ibfe_ctx& c, const T* b, T* x, T* xalt, T* d, int iters) {
     const double rn = 1.0 / (2.0 * sigma - rho);
     const T c1 = T(rn * rho), c2 = T(2.0 * rn / delta);
     rho = rn;
-    hipLaunchKernelGGL((k_zb_cheb<T, false, 3>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
-                       c.nzitems, op, (const T*)cur, b, d, alt, c1, c2, c.partials, (const KScal*)nullptr,
-                       c.stride);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c.timing && mass_events(c, size_t(k - 1), e0, e1)) return IBFE_EHIP;
+    if (e0)
+      hipExtLaunchKernelGGL((k_zb_cheb<T, false, 3>), dim3(nr), dim3(kBlock), 0, c.stream, e0, e1, 0,
+                            (const int*)c.zitems, c.nzitems, op, (const T*)cur, b, d, alt, c1, c2, c.partials,
+                            (const KScal*)nullptr, c.stride);
+    else
+      hipLaunchKernelGGL((k_zb_cheb<T, false, 3>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
+                         c.nzitems, op, (const T*)cur, b, d, alt, c1, c2, c.partials, (const KScal*)nullptr,
+                         c.stride);
     std::swap(cur, alt);
   }
   CHECK_LAUNCH();
+  if (c.timing) {
+    int rc = collect_mass_events(c, iters - 1);
+    if (rc) return rc;
+  }
   if (cur != x) return fail(IBFE_EINVAL, "internal: Chebyshev result buffer");
   return IBFE_OK;
 }
@@ -1262,7 +1308,8 @@ int step_once(ibfe_ctx& c) {
       auto op32 = stencil_op<float>(c, c.coef32, kFlagF);
       rc = run_refined(c, op, kFlagF, 3, b1, x1, c.v32[8], c.v32[9], rtol, so,
                        [&](const float* r32, float* d32, double tol, SolveOut& o) {
-                         HIP_TRY(hipMemsetAsync(d32 - c.halo, 0, sizeof(float) * 3 * S, c.stream));
+                         hipLaunchKernelGGL(k_zero<float>, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks,
+                                            c.nchunks, d32, 3, S);
                          return run_bicgstab<float>(c, op32, r32, d32, c.v32, kScS1, tol, maxit, o);
                        });
     } else {
@@ -1314,7 +1361,8 @@ int step_once(ibfe_ctx& c) {
     const bool mg = P.params.precond == 2;
     if (mixed) {
       auto op32 = sym_op<float, 1>(c, kc, kFlagPp);
-      HIP_TRY(hipMemsetAsync(c.phi - c.halo, 0, sizeof(double) * S, c.stream));
+      hipLaunchKernelGGL(k_zero<double>, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.phi, 1,
+                         S);
       float* const* v = c.v32;
       rc = run_refined(c, op, kFlagPp, 1, b3, c.phi, v[8], v[9], rtol, so,
                        [&](const float* r32, float* d32, double tol, SolveOut& o) {
@@ -1348,7 +1396,7 @@ int step_once(ibfe_ctx& c) {
     const double mc[4] = {c.fc.m[0], c.fc.m[1], c.fc.m[2], c.fc.m[3]};
     auto op = sym_op<double, 3>(c, mc, kFlagF);
     SolveOut so;
-    HIP_TRY(hipMemsetAsync(delta - c.halo, 0, sizeof(double) * 3 * S, c.stream));
+    hipLaunchKernelGGL(k_zero<double>, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, delta, 3, S);
     if (mixed) {
       float* const* v = c.v32;
       rc = run_refined(c, op, kFlagF, 3, b4, delta, v[8], v[9], rtol, so,
@@ -1465,7 +1513,8 @@ int step_once_refined(ibfe_ctx& c) {
       auto op32 = cstencil_op<float>(c, c.coef32, kFlagF);
       rc = run_refined(c, op, kFlagF, 3, b1, x1, c.v32[8], c.v32[9], rtol, so,
                        [&](const float* r32, float* d32, double tol, SolveOut& o) {
-                         HIP_TRY(hipMemsetAsync(d32 - c.halo, 0, sizeof(float) * 3 * S, c.stream));
+                         hipLaunchKernelGGL(k_zero<float>, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks,
+                                            c.nchunks, d32, 3, S);
                          return run_bicgstab<float>(c, op32, r32, d32, c.v32, kScS1, tol, maxit, o);
                        });
     } else {
@@ -1526,7 +1575,8 @@ int step_once_refined(ibfe_ctx& c) {
     SolveOut so;
     if (mixed) {
       auto op32 = csym_op<float, 1>(c, 0.0, 1.0, kFlagPp, c.dinvK32);
-      HIP_TRY(hipMemsetAsync(c.phi - c.halo, 0, sizeof(double) * S, c.stream));
+      hipLaunchKernelGGL(k_zero<double>, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.phi, 1,
+                         S);
       float* const* v = c.v32;
       rc = run_refined(c, op, kFlagPp, 1, b3, c.phi, v[8], v[9], rtol, so,
                        [&](const float* r32, float* d32, double tol, SolveOut& o) {
@@ -1559,7 +1609,7 @@ int step_once_refined(ibfe_ctx& c) {
     auto op = csym_op<double, 3>(c, 1.0, 0.0, kFlagF, c.dinvM64);
     const double lmin = P.mass_lmin, lmax = kMassLmax;
     SolveOut so;
-    HIP_TRY(hipMemsetAsync(delta - c.halo, 0, sizeof(double) * 3 * S, c.stream));
+    hipLaunchKernelGGL(k_zero<double>, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, delta, 3, S);
     if (mixed) {
       auto op32 = csym_op<float, 3>(c, 1.0, 0.0, kFlagF, c.dinvM32);
       float* const* v = c.v32;
@@ -1607,6 +1657,16 @@ int step_once_refined(ibfe_ctx& c) {
   return IBFE_OK;
 }
 
+// FP32 work vectors for the verification applies of an FP64-mode context
+// (allocated on first use).
+int ensure_fp32_work(ibfe_ctx& C) {
+  int rc;
+  if (!C.v32[0])
+    for (int i = 0; i < 10; ++i)
+      if ((rc = C.field(&C.v32[i], 3))) return rc;
+  return IBFE_OK;
+}
+
 // Verification applies on a refined lattice: rows and columns on all of P,
 // C^T A C with the hanging-node constraint.
 int apply_refined(ibfe_ctx& C, int op, int precision, double* xin, double* yout, int& nc_out) {
@@ -1624,8 +1684,9 @@ int apply_refined(ibfe_ctx& C, int op, int precision, double* xin, double* yout,
         auto o = csym_op<double, 1>(C, a, b, kFlagP, C.dinvM64);
         return comp_rows<double>(C, OpElem<double, OpCSym<double, 1>>{o, xin}, kFlagP, 0u, 1.0, yout);
       }
-      float* x32 = reinterpret_cast<float*>(C.w[2]);
-      float* y32 = reinterpret_cast<float*>(C.w[3]);
+      if ((rc = ensure_fp32_work(C))) return rc;
+      float* x32 = C.v32[0];
+      float* y32 = C.v32[1];
       hipLaunchKernelGGL((k_masked_copy<double, float>), dim3(nb), dim3(kBlock), 0, C.stream, C.chunks,
                          C.nchunks, C.flags, kFlagP, xin, x32, 1, S);
       CHECK_LAUNCH();
@@ -1661,9 +1722,7 @@ int apply_refined(ibfe_ctx& C, int op, int precision, double* xin, double* yout,
       nc_out = 3;
       if (precision == 1 && !C.coef32) {
         if ((rc = C.field(&C.coef32, 54))) return rc;
-        if (!C.v32[0])
-          for (int i = 0; i < 10; ++i)
-            if ((rc = C.field(&C.v32[i], 3))) return rc;
+        if ((rc = ensure_fp32_work(C))) return rc;
       }
       if ((rc = fill_hanging<double>(C, C.u, 3))) return rc;
       if ((rc = build_s1_refined(C))) return rc;
@@ -1848,6 +1907,8 @@ int ibfe_set_kernel_timing(ibfe_ctx* c, int enable) {
   c->timing = enable != 0;
   c->stats.poisson_apply_ms = 0.0;
   c->stats.poisson_applies = 0;
+  c->stats.mass_apply_ms = 0.0;
+  c->stats.mass_applies = 0;
   return IBFE_OK;
 }
 
@@ -1912,8 +1973,9 @@ int ibfe_apply(ibfe_ctx* c, int op, int precision, const double* x, double* y, i
         hipLaunchKernelGGL((k_apply<double, 1, OpSym<double, 1>>), dim3(nb), dim3(kBlock), 0, C.stream,
                            C.chunks, C.nchunks, o, xin, yout);
       } else {
-        float* x32 = reinterpret_cast<float*>(C.w[2]);
-        float* y32 = reinterpret_cast<float*>(C.w[3]);
+        if ((rc = ensure_fp32_work(C))) return rc;
+        float* x32 = C.v32[0];
+        float* y32 = C.v32[1];
         hipLaunchKernelGGL((k_masked_copy<double, float>), dim3(nb), dim3(kBlock), 0, C.stream, C.chunks,
                            C.nchunks, C.flags, kFlagP, xin, x32, 1, S);
         auto o = sym_op<float, 1>(C, cf, kFlagP);
@@ -1938,13 +2000,9 @@ int ibfe_apply(ibfe_ctx* c, int op, int precision, const double* x, double* y, i
     case IBFE_OP_ADVDIFF: {
       float* c32 = C.coef32;
       if (precision == 1 && !c32) {
-        // FP64-mode context: build a temporary FP32 copy in unused work space
-        if (!C.v32[0]) {
-          int rc2;
-          if ((rc2 = C.field(&C.coef32, 27))) return rc2;
-          for (int i = 0; i < 10; ++i)
-            if ((rc2 = C.field(&C.v32[i], 3))) return rc2;
-        }
+        // FP64-mode context: build an FP32 copy of the stencil in extra work space
+        if ((rc = C.field(&C.coef32, 27))) return rc;
+        if ((rc = ensure_fp32_work(C))) return rc;
         c32 = C.coef32;
       }
       if ((rc = build_s1(C))) return rc;

@@ -315,6 +315,16 @@ __global__ __launch_bounds__(kBlock) void k_axpby(const int* __restrict__ chunks
   }
 }
 
+// x = 0 on every chunk node (nc planes); positions outside the chunks are never
+// written and stay zero from the allocation
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_zero(const int* __restrict__ chunks, int nchunks,
+                                                 T* __restrict__ x, int nc, int64_t stride) {
+  const int n = chunk_node(chunks, nchunks);
+  if (n < 0) return;
+  for (int d = 0; d < nc; ++d) x[d * stride + n] = T(0);
+}
+
 // x += TO(d) on rows (mixed precision update of an FP64 iterate by an FP32 correction)
 template <typename TD>
 __global__ __launch_bounds__(kBlock) void k_add_correction(const int* __restrict__ chunks, int nchunks,

@@ -28,12 +28,17 @@ struct ZOp {
 };
 
 // Walk the column items of this block; epi(node, lane_ok, row, emask, Ax, x_centre).
-// All kZB + 2 planes of an item are loaded before any output is formed, so a
-// wavefront keeps up to 9 (kZB + 2) row loads in flight (memory-level
-// parallelism within the wavefront instead of one latency per plane).
+// The 3-plane window slides through a ring of kZBPF + 3 planes: the row loads of
+// the plane kZBPF + 1 steps ahead are issued before the current output is formed,
+// so each wavefront keeps 9 (kZBPF + 1) row loads in flight while computing, and
+// the window takes 9 (kZBPF + 3) registers instead of 9 (kZB + 2) (more waves per
+// SIMD to hide the memory latency).
+constexpr int kZBPF = 2;
+
 template <typename T, class Epi>
 __device__ __forceinline__ void zb_walk(const int* __restrict__ items, int nitems, const ZOp<T>& op,
                                         const T* __restrict__ x, Epi& epi) {
+  constexpr int R = kZBPF + 3;
   const int lane = threadIdx.x & 63;
   const int sy = op.sy, sz = op.sz;
   const T c[4] = {op.c[0], op.c[1], op.c[2], op.c[3]};
@@ -46,27 +51,36 @@ __device__ __forceinline__ void zb_walk(const int* __restrict__ items, int nitem
     const int k0 = pb * kZB;
     const int kend = min(kZB, op.nplanes - k0);
     const int base = k0 * sz + (lane_ok ? inplane : sz - 1);
-    T w[kZB + 2][9];
+    // plane j of the item is grid plane k0 - 1 + j (j = 0 .. kend + 1), kept in
+    // slot j % R; the cell bits and flags of output plane k in slot k % R
+    T w[R][9];
+    uint32_t em[R], fl[R];
 #pragma unroll
-    for (int j = 0; j < kZB + 2; ++j)
-      if (j < kend + 2) load_plane(x, base + (j - 1) * sz, sy, w[j]);
-    uint32_t em[kZB];
-    uint32_t fl[kZB];
+    for (int j = 0; j < kZBPF + 2; ++j)
+      if (j < kend + 2) load_plane(x, base + (j - 1) * sz, sy, w[j % R]);
 #pragma unroll
-    for (int k = 0; k < kZB; ++k)
+    for (int k = 0; k <= kZBPF; ++k)
       if (k < kend) {
-        em[k] = op.emask[base + k * sz];
-        fl[k] = op.flags[base + k * sz];
+        em[k % R] = op.emask[base + k * sz];
+        fl[k % R] = op.flags[base + k * sz];
       }
 #pragma unroll
     for (int k = 0; k < kZB; ++k) {
       if (k >= kend) break;
+      // prefetch: plane j = k + kZBPF + 2 replaces plane k - 1 (no longer needed)
+      const int j = k + kZBPF + 2;
+      if (j < kZB + 2 && j < kend + 2) load_plane(x, base + (j - 1) * sz, sy, w[j % R]);
+      const int kn = k + kZBPF + 1;
+      if (kn < kZB && kn < kend) {
+        em[kn % R] = op.emask[base + kn * sz];
+        fl[kn % R] = op.flags[base + kn * sz];
+      }
       const int node = base + k * sz;
-      const uint32_t e = em[k];
-      const bool rw = lane_ok && (fl[k] & op.rowbit);
+      const uint32_t e = em[k % R];
+      const bool rw = lane_ok && (fl[k % R] & op.rowbit);
       const bool interior = __all((!lane_ok) || e == 0xFFu);
-      const T y = window_apply<T>(w[k], w[k + 1], w[k + 2], e, interior, c);
-      epi(node, lane_ok, rw, e, y, w[k + 1][4]);
+      const T y = window_apply<T>(w[k % R], w[(k + 1) % R], w[(k + 2) % R], e, interior, c);
+      epi(node, lane_ok, rw, e, y, w[(k + 1) % R][4]);
     }
   }
 }

@@ -6,7 +6,8 @@ seeded height on a seeded side (+y or -y).  Base cells whose centre lies within
 `band` of the vessel wall (|signed distance| <= band) are split 2:1; every node
 array lives on the fine lattice (spacing h/2).  The Lagrangian points sample
 the union surface (rings on the tube, a Fibonacci set on the sphere) at spacing
-close to the base spacing h = 2 h_f; the inlet is a parabolic profile on the
+close to the base spacing h = 2 h_f, thinned to a Poisson-disk set (no two points
+closer than 0.7 h); the inlet is a parabolic profile on the
 lattice z = 0 face.  This stands in for the paper's aneurysmal vessels
 (Section 4), whose meshes are not available.  Signed distances only decide the
 mask and the refinement flags, which are inputs: the rule does not have to be
@@ -32,6 +33,24 @@ def _tube_distance(x, y, z, amp, k, iters=6):
         gp = dcx * dcx - (x - cx) * ddcx + 1.0
         s = s - g / gp
     return np.sqrt((x - amp * np.sin(k * s)) ** 2 + y * y + (z - s) ** 2)
+
+
+def _poisson_disk(X, rmin):
+    """Greedy Poisson-disk thinning in input order: a point is kept unless a kept point
+    lies closer than rmin (removes the near-duplicates where the two surfaces meet)."""
+    from scipy.spatial import cKDTree
+
+    pairs = cKDTree(X).query_pairs(rmin, output_type="ndarray")
+    if pairs.size == 0:
+        return X
+    nbrs = [[] for _ in range(len(X))]
+    for a, b in pairs:
+        nbrs[max(a, b)].append(min(a, b))
+    keep = np.ones(len(X), bool)
+    for i in range(len(X)):
+        if any(keep[j] for j in nbrs[i]):
+            keep[i] = False
+    return X[keep]
 
 
 def aneurysm_case(base=(128, 128, 320), length: float = 20.0, width: float = 8.0, radius: float = 1.0,
@@ -103,6 +122,7 @@ def aneurysm_case(base=(128, 128, 320), length: float = 20.0, width: float = 8.0
     d_sph = np.linalg.norm(tube_pts - cb[None, :], axis=1) - bulge
     d_tube = _tube_distance(sph_pts[:, 0], sph_pts[:, 1], sph_pts[:, 2], amp, k) - radius
     X = np.concatenate([tube_pts[d_sph > 0.25 * hf], sph_pts[d_tube > 0.25 * hf]], 0)
+    X = _poisson_disk(X, 0.7 * spacing)
     lo = origin + 3 * hf
     hi = origin + np.array([nx, ny, nz]) * h - 3 * hf
     X = X[np.all((X >= lo) & (X <= hi), axis=1)]
