@@ -1215,14 +1215,17 @@ int run_cheb_mass(ibfe_ctx& c, const T* b, T* x, T* xalt, T* d, int iters) {
     rho = rn;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c.timing && mass_events(c, size_t(k - 1), e0, e1)) return IBFE_EHIP;
+    // the first step writes the zeros off the free rows into the second buffer
+    // (the zero-start step did so for the first one and for d)
+    const int zero_off = k == 1 ? 1 : 0;
     if (e0)
       hipExtLaunchKernelGGL((k_zb_cheb<T, false, 3>), dim3(nr), dim3(kBlock), 0, c.stream, e0, e1, 0,
                             (const int*)c.zitems, c.nzitems, op, (const T*)cur, b, d, alt, c1, c2, c.partials,
-                            (const KScal*)nullptr, c.stride);
+                            (const KScal*)nullptr, c.stride, zero_off);
     else
       hipLaunchKernelGGL((k_zb_cheb<T, false, 3>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
                          c.nzitems, op, (const T*)cur, b, d, alt, c1, c2, c.partials, (const KScal*)nullptr,
-                         c.stride);
+                         c.stride, zero_off);
     std::swap(cur, alt);
   }
   CHECK_LAUNCH();

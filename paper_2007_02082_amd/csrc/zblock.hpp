@@ -126,7 +126,9 @@ __global__ __launch_bounds__(kBlock) void k_zb_cheb(const int* __restrict__ item
                                                     const T* __restrict__ x_in, const T* __restrict__ b,
                                                     T* __restrict__ d, T* __restrict__ x_out, T c1, T c2,
                                                     double* __restrict__ partials, const KScal* sc,
-                                                    int64_t stride = 0) {
+                                                    int64_t stride = 0, int zero_off_rows = 1) {
+  // zero_off_rows = 0: d and x_out already hold 0 off rows (written by an earlier
+  // step of the same sequence), so only the rows are stored
   if (sc && sc->done) return;
   double dot[1] = {0.0};
   const T c0 = op.c[0];
@@ -145,7 +147,7 @@ __global__ __launch_bounds__(kBlock) void k_zb_cheb(const int* __restrict__ item
         dq[node] = dn;
         xq[node] = xn;
         if (DOT) dot[0] += double(bq[node]) * double(xn);
-      } else {
+      } else if (zero_off_rows) {
         dq[node] = T(0);
         xq[node] = T(0);
       }
