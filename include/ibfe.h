@@ -221,6 +221,13 @@ int ibfe_get_stats(const ibfe_ctx* ctx, ibfe_stats* stats);
  * reset by this call; statistics accumulate until the next call). */
 int ibfe_set_kernel_timing(ibfe_ctx* ctx, int enable);
 
+/* Replay the fixed kernel sequences of the solves (iteration batches between
+ * convergence checks, Chebyshev sequences) through HIP graphs captured on their
+ * first use (1, the default) or launch every kernel directly (0).  Graphs are
+ * only used on a non-null stream and not while kernel timing is enabled; the
+ * results are bitwise the same either way.  Switching frees the graphs. */
+int ibfe_set_graphs(ibfe_ctx* ctx, int enable);
+
 /* Intermediate fields of the last step, canonical order:
  *   IBFE_FIELD_USTAR (3 x n_u)  tentative velocity after the first sub-step
  *   IBFE_FIELD_UIB   (3 x n_u)  velocity after the IB correction

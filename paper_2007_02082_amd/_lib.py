@@ -98,6 +98,7 @@ SIGNATURES = {
     "ibfe_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, dp, C.c_int]),
     "ibfe_get_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
     "ibfe_set_kernel_timing": (C.c_int, [C.c_void_p, C.c_int]),
+    "ibfe_set_graphs": (C.c_int, [C.c_void_p, C.c_int]),
     "ibfe_get_field": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int]),
     "ibfe_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
     "ibfe_destroy": (None, [C.c_void_p]),
@@ -262,9 +263,15 @@ class Solver:
             a, self._keep = _torch_allocator()
             self._alloc = a
             alloc = C.byref(a)
+        import torch
+
         if stream is None:
-            import torch
-            stream = torch.cuda.current_stream().cuda_stream
+            # a stream of its own (default priority): the null stream cannot be captured
+            # into graphs; device tensors passed in are ordered against the current stream
+            self._stream = torch.cuda.Stream()
+            stream = self._stream.cuda_stream
+        else:
+            self._stream = None
         h = C.c_void_p()
         check(lib.ibfe_create(C.byref(self._in.grid), C.byref(self._in.ib), C.byref(self._in.params),
                               C.byref(self._in.inlet), alloc, C.c_void_p(stream), C.byref(h)))
@@ -287,7 +294,24 @@ class Solver:
         check(load().ibfe_get_node_ids(self._h, _ptr(out, C.c_int64), None))
         return out
 
+    def _after_caller(self):
+        """Order the library's stream after the caller's current stream (device inputs)."""
+        if self._stream is not None:
+            import torch
+            self._stream.wait_stream(torch.cuda.current_stream())
+
+    def _before_caller(self):
+        """Order the caller's current stream after the library's stream (device outputs)."""
+        if self._stream is not None:
+            import torch
+            torch.cuda.current_stream().wait_stream(self._stream)
+
+    def set_graphs(self, enable: bool):
+        check(load().ibfe_set_graphs(self._h, 1 if enable else 0))
+
     def set_state(self, u, p, t: float = 0.0):
+        if not isinstance(u, np.ndarray):
+            self._after_caller()
         if isinstance(u, np.ndarray):
             u = np.ascontiguousarray(u, np.float64)
             p = np.ascontiguousarray(p, np.float64)
@@ -310,8 +334,10 @@ class Solver:
     def get_state_device(self, u, p):
         """Write the state into device tensors (3*n_u and n_p doubles) without a host copy."""
         t = C.c_double()
+        self._after_caller()
         check(load().ibfe_get_state(self._h, C.c_void_p(u.data_ptr()), C.c_void_p(p.data_ptr()),
                                     C.byref(t), 1))
+        self._before_caller()
         return t.value
 
     def field(self, which: int) -> np.ndarray:

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -164,9 +165,14 @@ struct ibfe_ctx {
   bool timing = false;
   std::vector<hipEvent_t> ev;
   std::vector<hipEvent_t> ev_mass;  // timer events of the mass Chebyshev steps
+  // executable graphs of fixed kernel sequences (iteration batches, Chebyshev
+  // sequences), captured on first use; only on a non-null stream
+  bool graphs = true;
+  std::map<uint64_t, hipGraphExec_t> graph_cache;
   int est[kNumScal] = {};
 
   ~ibfe_ctx() {
+    for (auto& kv : graph_cache) (void)hipGraphExecDestroy(kv.second);
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : ev_mass) (void)hipEventDestroy(e);
     for (void* b : blocks) {
@@ -571,6 +577,41 @@ int timer_events(ibfe_ctx& c, size_t k, hipEvent_t& e0, hipEvent_t& e1) {
   return IBFE_OK;
 }
 
+// Graph keys: call site, Krylov slot, scalar size, sequence length.
+enum GraphSite : uint64_t { kGsCg = 1, kGsBicg, kGsPcgMg, kGsChebMass, kGsChebGen };
+uint64_t graph_key(GraphSite site, int slot, int tbytes, int len) {
+  return (uint64_t(site) << 56) | (uint64_t(slot & 0xff) << 48) | (uint64_t(tbytes & 0xff) << 40) |
+         uint64_t(uint32_t(len));
+}
+
+// Issue the kernels of body() on the context's stream, through an executable
+// graph captured on the first call with this key (the sequence and every kernel
+// argument are fixed per key: buffers and scalar slots belong to the context,
+// convergence is read by the kernels from the device scalar block).  Eager when
+// graphs are off, kernel timing is on or the stream is the null stream.
+template <class Body>
+int graph_run(ibfe_ctx& c, uint64_t key, Body&& body) {
+  if (!c.graphs || c.timing || c.stream == nullptr) return body();
+  auto it = c.graph_cache.find(key);
+  if (it == c.graph_cache.end()) {
+    HIP_TRY(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
+    const int rc = body();
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c.stream, &g);
+    if (rc || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc ? rc : fail(IBFE_EHIP, std::string("stream capture failed: ") + hipGetErrorString(e));
+    }
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return fail(IBFE_EHIP, std::string("graph instantiation: ") + hipGetErrorString(ei));
+    it = c.graph_cache.emplace(key, ex).first;
+  }
+  HIP_TRY(hipGraphLaunch(it->second, c.stream));
+  return IBFE_OK;
+}
+
 // Event pair k of the mass-step timer.
 int mass_events(ibfe_ctx& c, size_t k, hipEvent_t& e0, hipEvent_t& e1) {
   while (c.ev_mass.size() < 2 * k + 2) {
@@ -613,20 +654,25 @@ int run_cg(ibfe_ctx& c, const Op& op, const int* chunks, int nchunks, const T* b
   KScal s{};
   while (true) {
     const int batch = std::min(next_batch(c.est[slot], launched), max_iters + 1 - launched);
-    for (int k = 0; k < batch; ++k) {
-      hipEvent_t e0 = nullptr, e1 = nullptr;
-      if (timed && timer_events(c, size_t(launched + k), e0, e1)) return IBFE_EHIP;
-      if ((prc = pre_apply(c, op, p, (const KScal*)sc))) return prc;
-      const int nq = launch_q<T>(c, op, chunks, nchunks, p, q, (const KScal*)sc, e0, e1);
-      hipLaunchKernelGGL(k_fin_cg_q, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nq, sc);
-      hipLaunchKernelGGL((k_cg_xr<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, chunks, nchunks, op, x, r,
-                         p, q, c.partials, (const KScal*)sc);
-      hipLaunchKernelGGL(k_fin_cg_xr, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr,
-                         sc);
-      hipLaunchKernelGGL((k_cg_p<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, chunks, nchunks, op, r, p,
-                         (const KScal*)sc);
-      CHECK_LAUNCH();
-    }
+    auto body = [&]() -> int {
+      for (int k = 0; k < batch; ++k) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (timed && timer_events(c, size_t(launched + k), e0, e1)) return IBFE_EHIP;
+        int rc2;
+        if ((rc2 = pre_apply(c, op, p, (const KScal*)sc))) return rc2;
+        const int nq = launch_q<T>(c, op, chunks, nchunks, p, q, (const KScal*)sc, e0, e1);
+        hipLaunchKernelGGL(k_fin_cg_q, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nq, sc);
+        hipLaunchKernelGGL((k_cg_xr<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, chunks, nchunks, op, x, r,
+                           p, q, c.partials, (const KScal*)sc);
+        hipLaunchKernelGGL(k_fin_cg_xr, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr,
+                           sc);
+        hipLaunchKernelGGL((k_cg_p<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, chunks, nchunks, op, r, p,
+                           (const KScal*)sc);
+        CHECK_LAUNCH();
+      }
+      return IBFE_OK;
+    };
+    if ((prc = timed ? body() : graph_run(c, graph_key(kGsCg, slot, sizeof(T), batch), body))) return prc;
     launched += batch;
     int rc = poll(c, slot, s);
     if (rc) return rc;
@@ -668,24 +714,29 @@ int run_bicgstab(ibfe_ctx& c, const Op& op, const T* b, T* x, T* const* wv, int 
   KScal st{};
   while (true) {
     const int batch = std::min(next_batch(c.est[slot], launched), max_iters + 1 - launched);
-    for (int k = 0; k < batch; ++k) {
-      hipLaunchKernelGGL((k_bi_p<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, ch, nch, op, r, p, v, phat,
-                         csc);
-      if ((prc = pre_apply(c, op, phat, csc))) return prc;
-      hipLaunchKernelGGL((k_bi_apply<T, Op, 0>), dim3(nr), dim3(kBlock), 0, c.stream, ch, nch, op, phat, v,
-                         rhat, c.partials, csc);
-      hipLaunchKernelGGL(k_fin_bi_apply<0>, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc);
-      hipLaunchKernelGGL((k_bi_s<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, ch, nch, op, r, v, s, shat,
-                         csc);
-      if ((prc = pre_apply(c, op, shat, csc))) return prc;
-      hipLaunchKernelGGL((k_bi_apply<T, Op, 1>), dim3(nr), dim3(kBlock), 0, c.stream, ch, nch, op, shat, t,
-                         s, c.partials, csc);
-      hipLaunchKernelGGL(k_fin_bi_apply<1>, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc);
-      hipLaunchKernelGGL((k_bi_x<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, ch, nch, op, x, r, rhat,
-                         phat, shat, s, t, c.partials, csc);
-      hipLaunchKernelGGL(k_fin_bi_x, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc);
-      CHECK_LAUNCH();
-    }
+    auto body = [&]() -> int {
+      for (int k = 0; k < batch; ++k) {
+        int rc2;
+        hipLaunchKernelGGL((k_bi_p<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, ch, nch, op, r, p, v, phat,
+                           csc);
+        if ((rc2 = pre_apply(c, op, phat, csc))) return rc2;
+        hipLaunchKernelGGL((k_bi_apply<T, Op, 0>), dim3(nr), dim3(kBlock), 0, c.stream, ch, nch, op, phat, v,
+                           rhat, c.partials, csc);
+        hipLaunchKernelGGL(k_fin_bi_apply<0>, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc);
+        hipLaunchKernelGGL((k_bi_s<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, ch, nch, op, r, v, s, shat,
+                           csc);
+        if ((rc2 = pre_apply(c, op, shat, csc))) return rc2;
+        hipLaunchKernelGGL((k_bi_apply<T, Op, 1>), dim3(nr), dim3(kBlock), 0, c.stream, ch, nch, op, shat, t,
+                           s, c.partials, csc);
+        hipLaunchKernelGGL(k_fin_bi_apply<1>, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc);
+        hipLaunchKernelGGL((k_bi_x<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, ch, nch, op, x, r, rhat,
+                           phat, shat, s, t, c.partials, csc);
+        hipLaunchKernelGGL(k_fin_bi_x, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc);
+        CHECK_LAUNCH();
+      }
+      return IBFE_OK;
+    };
+    if ((prc = graph_run(c, graph_key(kGsBicg, slot, sizeof(T), batch), body))) return prc;
     launched += batch;
     int rc = poll(c, slot, st);
     if (rc) return rc;
@@ -907,25 +958,35 @@ int run_cheb_gen(ibfe_ctx& c, const Op& op, const T* b, T* x, T* xalt, T* d, int
   hipLaunchKernelGGL((k_cheb0_gen<T, Op>), dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
                      (const int*)c.chunks, c.nchunks, op, b, d, cur, T(1.0 / theta), (const KScal*)nullptr);
   const int nr = red_blocks(c.nchunks);
-  double rho = 1.0 / sigma;
   int rc;
-  for (int k = 1; k < iters; ++k) {
-    const double rn = 1.0 / (2.0 * sigma - rho);
-    const T c1 = T(rn * rho), c2 = T(2.0 * rn / delta);
-    rho = rn;
-    if ((rc = pre_apply(c, op, cur, (const KScal*)nullptr))) return rc;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c.timing && mass_events(c, size_t(k - 1), e0, e1)) return IBFE_EHIP;
-    if (e0)
-      hipExtLaunchKernelGGL((k_cheb_gen<T, Op, false>), dim3(nr), dim3(kBlock), 0, c.stream, e0, e1, 0,
-                            (const int*)c.chunks, c.nchunks, op, (const T*)cur, b, d, alt, c1, c2, c.partials,
-                            (const KScal*)nullptr);
-    else
-      hipLaunchKernelGGL((k_cheb_gen<T, Op, false>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.chunks,
-                         c.nchunks, op, (const T*)cur, b, d, alt, c1, c2, c.partials, (const KScal*)nullptr);
-    std::swap(cur, alt);
-  }
-  CHECK_LAUNCH();
+  T* const cur0 = cur;
+  T* const alt0 = alt;
+  auto body = [&]() -> int {
+    double rho = 1.0 / sigma;
+    int rc2;
+    for (int k = 1; k < iters; ++k) {
+      const double rn = 1.0 / (2.0 * sigma - rho);
+      const T c1 = T(rn * rho), c2 = T(2.0 * rn / delta);
+      rho = rn;
+      if ((rc2 = pre_apply(c, op, cur, (const KScal*)nullptr))) return rc2;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (c.timing && mass_events(c, size_t(k - 1), e0, e1)) return IBFE_EHIP;
+      if (e0)
+        hipExtLaunchKernelGGL((k_cheb_gen<T, Op, false>), dim3(nr), dim3(kBlock), 0, c.stream, e0, e1, 0,
+                              (const int*)c.chunks, c.nchunks, op, (const T*)cur, b, d, alt, c1, c2, c.partials,
+                              (const KScal*)nullptr);
+      else
+        hipLaunchKernelGGL((k_cheb_gen<T, Op, false>), dim3(nr), dim3(kBlock), 0, c.stream,
+                           (const int*)c.chunks, c.nchunks, op, (const T*)cur, b, d, alt, c1, c2, c.partials,
+                           (const KScal*)nullptr);
+      std::swap(cur, alt);
+    }
+    CHECK_LAUNCH();
+    return IBFE_OK;
+  };
+  if ((rc = graph_run(c, graph_key(kGsChebGen, 0, sizeof(T), iters), body))) return rc;
+  // the sequence swaps the buffers iters - 1 times (a graph replay does not run body)
+  cur = ((iters - 1) % 2 == 0) ? cur0 : alt0;
   if (c.timing && (rc = collect_mass_events(c, iters - 1))) return rc;
   if (cur != x) return fail(IBFE_EINVAL, "internal: Chebyshev result buffer");
   return IBFE_OK;
@@ -1135,23 +1196,29 @@ int run_pcg_mg(ibfe_ctx& c, const Op& op, std::vector<MGDev<T>>& lv, const T* b,
   KScal s{};
   while (true) {
     const int batch = std::min(launched == 0 ? std::max(2, c.est[slot] - 1) : 2, max_iters + 1 - launched);
-    for (int k = 0; k < batch; ++k) {
-      hipEvent_t e0 = nullptr, e1 = nullptr;
-      if (timed && timer_events(c, size_t(launched + k), e0, e1)) return IBFE_EHIP;
-      if ((rc = pre_apply(c, op, p, csc))) return rc;
-      const int nq = launch_q<T>(c, op, c.chunks, c.nchunks, (const T*)p, q, csc, e0, e1);
-      hipLaunchKernelGGL(k_fin_cg_q, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nq, sc);
-      hipLaunchKernelGGL(k_mgcg_xr<T>, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.chunks, c.nchunks,
-                         (const uint8_t*)c.flags, x, r, (const T*)p, (const T*)q, c.partials, csc);
-      hipLaunchKernelGGL(k_fin_mgcg_xr, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr, sc);
-      CHECK_LAUNCH();
-      if ((rc = vcycle<T>(c, lv, r, z, csc, np))) return rc;
-      hipLaunchKernelGGL(k_fin_mgcg_rz, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, np, sc,
-                         0);
-      hipLaunchKernelGGL(k_mgcg_p<T>, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
-                         (const int*)c.chunks, c.nchunks, (const uint8_t*)c.flags, (const T*)z, p, csc);
-      CHECK_LAUNCH();
-    }
+    auto body = [&]() -> int {
+      for (int k = 0; k < batch; ++k) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (timed && timer_events(c, size_t(launched + k), e0, e1)) return IBFE_EHIP;
+        int rc2;
+        if ((rc2 = pre_apply(c, op, p, csc))) return rc2;
+        const int nq = launch_q<T>(c, op, c.chunks, c.nchunks, (const T*)p, q, csc, e0, e1);
+        hipLaunchKernelGGL(k_fin_cg_q, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nq, sc);
+        hipLaunchKernelGGL(k_mgcg_xr<T>, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.chunks, c.nchunks,
+                           (const uint8_t*)c.flags, x, r, (const T*)p, (const T*)q, c.partials, csc);
+        hipLaunchKernelGGL(k_fin_mgcg_xr, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr,
+                           sc);
+        CHECK_LAUNCH();
+        if ((rc2 = vcycle<T>(c, lv, r, z, csc, np))) return rc2;
+        hipLaunchKernelGGL(k_fin_mgcg_rz, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, np,
+                           sc, 0);
+        hipLaunchKernelGGL(k_mgcg_p<T>, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
+                           (const int*)c.chunks, c.nchunks, (const uint8_t*)c.flags, (const T*)z, p, csc);
+        CHECK_LAUNCH();
+      }
+      return IBFE_OK;
+    };
+    if ((rc = timed ? body() : graph_run(c, graph_key(kGsPcgMg, slot, sizeof(T), batch), body))) return rc;
     launched += batch;
     if ((rc = poll(c, slot, s))) return rc;
     if (s.done || launched > max_iters) break;
@@ -1208,27 +1275,35 @@ int run_cheb_mass(ibfe_ctx& c, const T* b, T* x, T* xalt, T* d, int iters) {
                      (const int*)c.chunks, c.nchunks, (const uint8_t*)c.emask, (const uint8_t*)c.flags,
                      T(c.fc.m[0]), T(1.0 / theta), b, d, cur, (const KScal*)nullptr, kFlagF, c.stride);
   const int nr = red_blocks(c.nzitems);
-  double rho = 1.0 / sigma;
-  for (int k = 1; k < iters; ++k) {
-    const double rn = 1.0 / (2.0 * sigma - rho);
-    const T c1 = T(rn * rho), c2 = T(2.0 * rn / delta);
-    rho = rn;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c.timing && mass_events(c, size_t(k - 1), e0, e1)) return IBFE_EHIP;
-    // the first step writes the zeros off the free rows into the second buffer
-    // (the zero-start step did so for the first one and for d)
-    const int zero_off = k == 1 ? 1 : 0;
-    if (e0)
-      hipExtLaunchKernelGGL((k_zb_cheb<T, false, 3>), dim3(nr), dim3(kBlock), 0, c.stream, e0, e1, 0,
-                            (const int*)c.zitems, c.nzitems, op, (const T*)cur, b, d, alt, c1, c2, c.partials,
-                            (const KScal*)nullptr, c.stride, zero_off);
-    else
-      hipLaunchKernelGGL((k_zb_cheb<T, false, 3>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
-                         c.nzitems, op, (const T*)cur, b, d, alt, c1, c2, c.partials, (const KScal*)nullptr,
-                         c.stride, zero_off);
-    std::swap(cur, alt);
-  }
-  CHECK_LAUNCH();
+  T* const cur0 = cur;
+  T* const alt0 = alt;
+  auto body = [&]() -> int {
+    double rho = 1.0 / sigma;
+    for (int k = 1; k < iters; ++k) {
+      const double rn = 1.0 / (2.0 * sigma - rho);
+      const T c1 = T(rn * rho), c2 = T(2.0 * rn / delta);
+      rho = rn;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (c.timing && mass_events(c, size_t(k - 1), e0, e1)) return IBFE_EHIP;
+      // the first step writes the zeros off the free rows into the second buffer
+      // (the zero-start step did so for the first one and for d)
+      const int zero_off = k == 1 ? 1 : 0;
+      if (e0)
+        hipExtLaunchKernelGGL((k_zb_cheb<T, false, 3>), dim3(nr), dim3(kBlock), 0, c.stream, e0, e1, 0,
+                              (const int*)c.zitems, c.nzitems, op, (const T*)cur, b, d, alt, c1, c2, c.partials,
+                              (const KScal*)nullptr, c.stride, zero_off);
+      else
+        hipLaunchKernelGGL((k_zb_cheb<T, false, 3>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
+                           c.nzitems, op, (const T*)cur, b, d, alt, c1, c2, c.partials, (const KScal*)nullptr,
+                           c.stride, zero_off);
+      std::swap(cur, alt);
+    }
+    CHECK_LAUNCH();
+    return IBFE_OK;
+  };
+  if (int rcb = graph_run(c, graph_key(kGsChebMass, 0, sizeof(T), iters), body)) return rcb;
+  // the sequence swaps the buffers iters - 1 times (a graph replay does not run body)
+  cur = ((iters - 1) % 2 == 0) ? cur0 : alt0;
   if (c.timing) {
     int rc = collect_mass_events(c, iters - 1);
     if (rc) return rc;
@@ -1912,6 +1987,17 @@ int ibfe_set_kernel_timing(ibfe_ctx* c, int enable) {
   c->stats.poisson_applies = 0;
   c->stats.mass_apply_ms = 0.0;
   c->stats.mass_applies = 0;
+  return IBFE_OK;
+}
+
+int ibfe_set_graphs(ibfe_ctx* c, int enable) {
+  if (!c) return fail(IBFE_EINVAL, "ctx is NULL");
+  if ((enable != 0) != c->graphs) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (auto& kv : c->graph_cache) (void)hipGraphExecDestroy(kv.second);
+    c->graph_cache.clear();
+  }
+  c->graphs = enable != 0;
   return IBFE_OK;
 }
 
