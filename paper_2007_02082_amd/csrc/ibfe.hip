@@ -66,7 +66,7 @@ struct ibfe_plan {
 // Device copy of one multigrid level (node-0 pointers into padded planes).
 template <typename T>
 struct MGDev {
-  int nx = 0, ny = 0, nz = 0, nchunks = 0, nzitems = 0, cpp = 0;
+  int nx = 0, ny = 0, nz = 0, nchunks = 0, nzitems = 0, cpp = 0, zb = kZBPlanes;
   int64_t N = 0, sy = 0, sz = 0, halo = 0, stride = 0;
   uint8_t* emask = nullptr;
   uint8_t* flags = nullptr;
@@ -100,7 +100,7 @@ struct ibfe_ctx {
   int* chunks = nullptr;
   int* ib_chunks = nullptr;
   int* zitems = nullptr;          // z-blocked column items (plane_block * cpp + chunk)
-  int nzitems = 0, cpp = 0;
+  int nzitems = 0, cpp = 0, zb = kZBPlanes;
   int64_t* pids = nullptr;
   double* float_count = nullptr;
   double* float_means = nullptr;
@@ -246,6 +246,7 @@ int setup_mg(ibfe_ctx& c, std::vector<MGDev<T>>& out, T* xt0, T* d0, T* r0) {
     D.sy = L.sy;
     D.sz = L.sz;
     D.cpp = L.cpp;
+    D.zb = L.zb;
     const FormCoefs f = form_coefs(L.h);
     for (int t = 0; t < 4; ++t) D.kc[t] = f.k[t];
     if (l == 0) {
@@ -257,6 +258,7 @@ int setup_mg(ibfe_ctx& c, std::vector<MGDev<T>>& out, T* xt0, T* d0, T* r0) {
       D.nchunks = c.nchunks;
       D.zitems = c.zitems;
       D.nzitems = c.nzitems;
+      D.zb = c.zb;
       D.xt = xt0;
       D.d = d0;
       D.r = r0;
@@ -371,21 +373,9 @@ int setup_device(ibfe_ctx& c) {
   }
   if ((rc = c.upload(&c.chunks, P.chunks.data(), P.chunks.size()))) return rc;
   {
-    // column items of the z-blocked applies: kZB planes x 64 in-plane nodes
-    c.cpp = int((P.sz + kChunk - 1) / kChunk);
-    const int nplanes = P.nz + 1, npb = (nplanes + kZB - 1) / kZB;
+    // column items of the z-blocked applies: zb planes x 64 in-plane nodes
     std::vector<int> items;
-    for (int pb = 0; pb < npb; ++pb)
-      for (int ch = 0; ch < c.cpp; ++ch) {
-        bool any = false;
-        for (int k = pb * kZB; k < std::min(nplanes, (pb + 1) * kZB) && !any; ++k)
-          for (int64_t l = int64_t(ch) * kChunk; l < std::min<int64_t>(P.sz, (ch + 1) * int64_t(kChunk)); ++l)
-            if (P.emask[k * P.sz + l]) {
-              any = true;
-              break;
-            }
-        if (any) items.push_back(pb * c.cpp + ch);
-      }
+    c.zb = choose_column_items(P.emask, P.sz, P.nz + 1, items, c.cpp);
     c.nzitems = int(items.size());
     if ((rc = c.upload(&c.zitems, items.data(), items.size()))) return rc;
   }
@@ -526,7 +516,7 @@ int launch_q(ibfe_ctx& c, const OpSym<T, NC>& op, const int*, int, const T* p, T
              hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   const int nr = red_blocks(c.nzitems);
   ZOp<T> z{op.emask, op.flags, op.rowbit, op.sy, op.sz, c.plan.nz + 1, c.cpp,
-           {op.c[0], op.c[1], op.c[2], op.c[3]}};
+           {op.c[0], op.c[1], op.c[2], op.c[3]}, c.zb};
   if (e0)
     hipExtLaunchKernelGGL((k_cg_q_zb<T, NC>), dim3(nr), dim3(kBlock), 0, c.stream, e0, e1, 0,
                           (const int*)c.zitems, c.nzitems, z, op.stride, p, q, c.partials, sc);
@@ -1031,6 +1021,7 @@ ZOp<T> level_op(const MGDev<T>& L) {
   z.sz = int(L.sz);
   z.nplanes = L.nz + 1;
   z.cpp = L.cpp;
+  z.zb = L.zb;
   for (int t = 0; t < 4; ++t) z.c[t] = T(L.kc[t]);
   return z;
 }
@@ -1268,6 +1259,7 @@ int run_cheb_mass(ibfe_ctx& c, const T* b, T* x, T* xalt, T* d, int iters) {
   op.sz = int(P.sz);
   op.nplanes = P.nz + 1;
   op.cpp = c.cpp;
+  op.zb = c.zb;
   for (int t = 0; t < 4; ++t) op.c[t] = T(c.fc.m[t]);
   T* cur = ((iters - 1) % 2 == 0) ? x : xalt;
   T* alt = cur == x ? xalt : x;

@@ -162,15 +162,15 @@ void coarsest_inverse(MGLevel& L) {
 
 }  // namespace
 
-void column_items(const std::vector<uint8_t>& emask, int64_t sz, int nplanes, std::vector<int32_t>& items,
-                  int& cpp) {
+void column_items(const std::vector<uint8_t>& emask, int64_t sz, int nplanes, int zb,
+                  std::vector<int32_t>& items, int& cpp) {
   cpp = int((sz + kChunk - 1) / kChunk);
-  const int npb = (nplanes + kZBPlanes - 1) / kZBPlanes;
+  const int npb = (nplanes + zb - 1) / zb;
   items.clear();
   for (int pb = 0; pb < npb; ++pb)
     for (int ch = 0; ch < cpp; ++ch) {
       bool any = false;
-      for (int k = pb * kZBPlanes; k < std::min(nplanes, (pb + 1) * kZBPlanes) && !any; ++k)
+      for (int k = pb * zb; k < std::min(nplanes, (pb + 1) * zb) && !any; ++k)
         for (int64_t l = int64_t(ch) * kChunk; l < std::min<int64_t>(sz, (ch + 1) * int64_t(kChunk)); ++l)
           if (emask[k * sz + l]) {
             any = true;
@@ -178,6 +178,17 @@ void column_items(const std::vector<uint8_t>& emask, int64_t sz, int nplanes, st
           }
       if (any) items.push_back(pb * cpp + ch);
     }
+}
+
+int choose_column_items(const std::vector<uint8_t>& emask, int64_t sz, int nplanes,
+                        std::vector<int32_t>& items, int& cpp) {
+  int zb = kZBPlanes;
+  column_items(emask, sz, nplanes, zb, items, cpp);
+  while (zb > 2 && int64_t(items.size()) < kZBMinItems) {
+    zb /= 2;
+    column_items(emask, sz, nplanes, zb, items, cpp);
+  }
+  return zb;
 }
 
 int build_multigrid(Plan& P, std::string& err) {
@@ -198,7 +209,7 @@ int build_multigrid(Plan& P, std::string& err) {
     if (f & IBFE_FLAG_P) L0.flags[n] = kMgP | ((f & IBFE_FLAG_PDIR) ? 0 : kMgPp);
   }
   L0.chunks = P.chunks;
-  if (!P.refined) column_items(L0.emask, L0.sz, L0.nz + 1, L0.zitems, L0.cpp);
+  if (!P.refined) L0.zb = choose_column_items(L0.emask, L0.sz, L0.nz + 1, L0.zitems, L0.cpp);
   P.mg.push_back(std::move(L0));
   if (P.refined) {
     // level 1 = the base grid: a base cell is kept when it is a kept unrefined
@@ -243,7 +254,7 @@ int build_multigrid(Plan& P, std::string& err) {
           C.flags[cn] = kMgP | (dir ? 0 : kMgPp);
         }
     chunk_list(C.emask, C.chunks);
-    column_items(C.emask, C.sz, C.nz + 1, C.zitems, C.cpp);
+    C.zb = choose_column_items(C.emask, C.sz, C.nz + 1, C.zitems, C.cpp);
     P.mg.push_back(std::move(C));
   }
   auto unknowns = [](const MGLevel& L) {
@@ -290,7 +301,7 @@ int build_multigrid(Plan& P, std::string& err) {
           C.flags[cn] = kMgP | (dir ? 0 : kMgPp);
         }
     chunk_list(C.emask, C.chunks);
-    column_items(C.emask, C.sz, C.nz + 1, C.zitems, C.cpp);
+    C.zb = choose_column_items(C.emask, C.sz, C.nz + 1, C.zitems, C.cpp);
     P.mg.push_back(std::move(C));
   }
   coarsest_inverse(P.mg.back());

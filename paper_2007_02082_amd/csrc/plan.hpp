@@ -14,6 +14,11 @@ constexpr int kChunk = 64;      // nodes per chunk (one wavefront)
 constexpr int kMaxHarmonics = 16;
 constexpr int kMaxFloating = 8; // outlet-less connected parts supported
 
+constexpr uint8_t kMgP = 1u, kMgPp = 16u;
+constexpr int kZBPlanes = 8;     // most planes per z-blocked column item
+constexpr int kZBMinItems = 4096;
+constexpr int kMgCoarsestMax = 512;
+
 // One level of the geometric multigrid hierarchy of the pressure Poisson
 // operator (level 0 = the grid itself).  Node flags use bit 0 = in P, bit 4 =
 // pressure unknown (P minus Dirichlet).
@@ -25,13 +30,11 @@ struct MGLevel {
   std::vector<int32_t> chunks;    // 64-node chunks holding a node of P
   std::vector<int32_t> zitems;    // z-blocked column items holding a node of P
   int cpp = 0;                    // chunks per plane of the column items
+  int zb = kZBPlanes;             // planes per column item
   std::vector<int64_t> unknowns;  // ids of pressure unknowns (coarsest level only)
   std::vector<double> inv;        // dense inverse on `unknowns` (coarsest level only)
 };
 
-constexpr uint8_t kMgP = 1u, kMgPp = 16u;
-constexpr int kZBPlanes = 8;     // planes per z-blocked column item
-constexpr int kMgCoarsestMax = 512;
 
 struct UnionFind {
   std::vector<int64_t> parent;
@@ -102,9 +105,13 @@ struct Plan {
 
 // Build the multigrid hierarchy from level 0 (already holding emask/flags).
 int build_multigrid(Plan& plan, std::string& err);
-// z-blocked column items of a level (kZBPlanes planes x 64 in-plane nodes).
-void column_items(const std::vector<uint8_t>& emask, int64_t sz, int nplanes, std::vector<int32_t>& items,
-                  int& cpp);
+// z-blocked column items of a level (zb planes x 64 in-plane nodes).
+void column_items(const std::vector<uint8_t>& emask, int64_t sz, int nplanes, int zb,
+                  std::vector<int32_t>& items, int& cpp);
+// Column items with the most planes per item (8, 4 or 2) that still gives at
+// least kZBMinItems items (enough wavefronts to fill the chip); returns zb.
+int choose_column_items(const std::vector<uint8_t>& emask, int64_t sz, int nplanes,
+                        std::vector<int32_t>& items, int& cpp);
 
 // Kept elements, hanging nodes and parents of a refined lattice: fills emask
 // (children of refined cells), cmask, the hanging and parent tables and joins

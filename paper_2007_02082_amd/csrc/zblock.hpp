@@ -25,6 +25,7 @@ struct ZOp {
   uint32_t rowbit;
   int sy, sz, nplanes, cpp;
   T c[4];
+  int zb;  // planes per column item (<= kZB)
 };
 
 // Walk the column items of this block; epi(node, lane_ok, row, emask, Ax, x_centre).
@@ -48,8 +49,8 @@ __device__ __forceinline__ void zb_walk(const int* __restrict__ items, int nitem
     const int pb = item / op.cpp, ch = item - pb * op.cpp;
     const int inplane = ch * 64 + lane;
     const bool lane_ok = inplane < sz;
-    const int k0 = pb * kZB;
-    const int kend = min(kZB, op.nplanes - k0);
+    const int k0 = pb * op.zb;
+    const int kend = min(op.zb, op.nplanes - k0);
     const int base = k0 * sz + (lane_ok ? inplane : sz - 1);
     // plane j of the item is grid plane k0 - 1 + j (j = 0 .. kend + 1), kept in
     // slot j % R; the cell bits and flags of output plane k in slot k % R
