@@ -123,8 +123,11 @@ typedef struct ibfe_ib {
  *   rtol        : relative residual target of the velocity and pressure solves
  *                 (<= 0 selects 1e-13 in FP64 mode, 1e-8 in mixed mode)
  *   max_iters   : iteration cap per Krylov solve (<= 0 selects 20000)
- *   precond     : 0 = Jacobi; 2 = geometric multigrid V-cycle for the pressure
- *                 increment (Jacobi for the other solves)
+ *   precond     : preconditioner of the pressure increment CG (Jacobi for the
+ *                 other solves): 0 = Jacobi; 1 = Chebyshev-Jacobi polynomial of
+ *                 degree 16 on [lambda_max/4, lambda_max] of D^-1 K with the bound
+ *                 lambda_max = 2; 2 = geometric multigrid V(2,2) cycle with
+ *                 Chebyshev-Jacobi smoothing and a dense coarsest solve
  *   advection   : 0 = semi-implicit u^n . grad u* (only value accepted)
  *   ib_rtol     : relative residual target of the IB force solve (<= 0: 1e-13)
  */

@@ -441,7 +441,7 @@ int setup_device(ibfe_ctx& c) {
     if ((rc = c.upload(&c.inlet_ids, P.inlet_ids.data(), P.inlet_ids.size()))) return rc;
     if ((rc = c.upload(&c.inlet_shape, P.inlet_shape.data(), P.inlet_shape.size()))) return rc;
   }
-  if (P.params.precond == 2) {
+  if (P.params.precond >= 1) {
     if (P.params.precision == 1)
       rc = setup_mg<float>(c, c.mg32, c.v32[4], c.v32[5], c.v32[6]);
     else
@@ -1009,7 +1009,8 @@ Cheb cheb_coefs(int m) {
 }
 
 constexpr int kSmooth = 2;        // Chebyshev degree of pre- and post-smoothing
-constexpr int kCoarseSmooth = 16; // coarsest-level smoothing when no dense inverse
+constexpr int kCoarseSmooth = 16; // coarsest-level smoothing when no dense inverse; with a
+                                  // single level this is the Chebyshev preconditioner
 
 template <typename T>
 ZOp<T> level_op(const MGDev<T>& L) {
@@ -1428,7 +1429,7 @@ int step_once(ibfe_ctx& c) {
     const double kc[4] = {c.fc.k[0], c.fc.k[1], c.fc.k[2], c.fc.k[3]};
     auto op = sym_op<double, 1>(c, kc, kFlagPp);
     SolveOut so;
-    const bool mg = P.params.precond == 2;
+    const bool mg = P.params.precond >= 1;  // multigrid or Chebyshev (one level)
     if (mixed) {
       auto op32 = sym_op<float, 1>(c, kc, kFlagPp);
       hipLaunchKernelGGL(k_zero<double>, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.phi, 1,
@@ -1641,7 +1642,7 @@ int step_once_refined(ibfe_ctx& c) {
     if ((rc = comp_rows<double>(c, f, kFlagPp, 0u, -rho / dt, b3))) return rc;
     if (P.n_floating > 0 && (rc = remove_slot_means(c, b3))) return rc;
     auto op = csym_op<double, 1>(c, 0.0, 1.0, kFlagPp, c.dinvK64);
-    const bool mg = P.params.precond == 2;
+    const bool mg = P.params.precond >= 1;  // multigrid or Chebyshev (one level)
     SolveOut so;
     if (mixed) {
       auto op32 = csym_op<float, 1>(c, 0.0, 1.0, kFlagPp, c.dinvK32);

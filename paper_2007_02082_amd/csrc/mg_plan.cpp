@@ -211,6 +211,8 @@ int build_multigrid(Plan& P, std::string& err) {
   L0.chunks = P.chunks;
   if (!P.refined) L0.zb = choose_column_items(L0.emask, L0.sz, L0.nz + 1, L0.zitems, L0.cpp);
   P.mg.push_back(std::move(L0));
+  // Chebyshev preconditioner: the grid level alone, smoothed without a coarse correction
+  if (P.params.precond == 1) return IBFE_OK;
   if (P.refined) {
     // level 1 = the base grid: a base cell is kept when it is a kept unrefined
     // cell or one of its 2x2x2 children is kept; Dirichlet colocated as below

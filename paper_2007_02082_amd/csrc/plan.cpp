@@ -65,8 +65,8 @@ int build_plan(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* para
     err = "precision must be 0 (FP64) or 1 (FP32 inner / FP64 refinement)";
     return IBFE_EINVAL;
   }
-  if ((pr.precond != 0 && pr.precond != 2) || pr.advection != 0) {
-    err = "precond must be 0 (Jacobi) or 2 (multigrid); advection must be 0 (semi-implicit)";
+  if (pr.precond < 0 || pr.precond > 2 || pr.advection != 0) {
+    err = "precond must be 0 (Jacobi), 1 (Chebyshev) or 2 (multigrid); advection must be 0 (semi-implicit)";
     return IBFE_EINVAL;
   }
   P.refined = grid->refine_cell != nullptr;
@@ -410,7 +410,7 @@ int build_plan(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* para
       P.G_ptr.push_back(int64_t(P.G_col.size()));
     }
   }
-  if (P.params.precond == 2) {
+  if (P.params.precond >= 1) {
     int rc = build_multigrid(P, err);
     if (rc) return rc;
   }

@@ -277,3 +277,21 @@ def test_step_parity_multigrid_poiseuille_16x16x64(precision, tol):
     _, out = run_pair(case, case.nsteps, precision=precision, precond=2)
     _check_steps(out, tol, case.name + "/mg")
     assert out[-1]["stats"]["s3_iters"] < 60
+
+
+# ---------------------------------------------------------------------------
+# Chebyshev-Jacobi polynomial preconditioner for the pressure increment
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision,tol", [(0, TOL64), (1, TOL_MIXED)])
+@pytest.mark.parametrize("make", [lambda: synth.poiseuille_c1(),
+                                  lambda: synth.closed_box(6),
+                                  lambda: synth.refined_cylinder(8, 8, length=1.25, band=0.3)])
+def test_step_parity_chebyshev_preconditioner(make, precision, tol):
+    case = make()
+    say("case", case.name, "Chebyshev preconditioner, precision", precision)
+    _, out = run_pair(case, 3, precision=precision, precond=1)
+    _check_steps(out, tol, case.name + "/cheb")
+    _, out_j = run_pair(case, 1, precision=precision, precond=0)
+    say("s3 iterations: Chebyshev", out[0]["stats"]["s3_iters"], "Jacobi", out_j[0]["stats"]["s3_iters"])
+    assert out[0]["stats"]["s3_iters"] < out_j[0]["stats"]["s3_iters"]
