@@ -9,6 +9,9 @@ the IB-corrected velocity):
 1. tentative velocity (Eq. 9, backward Euler):
    A = (rho/dt) M + rho C(u^n) + mu K,
    A_FF u*_F = (rho/dt)(M u^n)_F - (G_d p^n)_F - A_FD g(t^{n+1}),  u*_D = g(t^{n+1});
+   with explicit advection (the fully explicit convection of Eq. 13, an option):
+   A = (rho/dt) M + mu K (symmetric positive definite) and the right-hand side
+   also carries - rho (C(u^n) u^n)_F;
 2.-4. BCE-IB force and velocity correction (Eqs. 15-24): u_ib = u* + I_F^T Lambda with
    (I_F I_F^T) Lambda = U_B - I u*;
 5. pressure increment (Eq. 12 with rho): K_{P'P'} Phi = -(rho/dt) (B u_ib)_{P'},
@@ -44,8 +47,11 @@ class Problem:
     """Everything that depends only on the geometry and the parameters."""
 
     def __init__(self, nx, ny, nz, h, origin, node_mask, bc_tag, X, dS, U_B, rho, mu, dt,
-                 inlet_K, inlet_omega, inlet_ids, inlet_shape, refine_cell=None):
+                 inlet_K, inlet_omega, inlet_ids, inlet_shape, refine_cell=None, advection=0):
         self.nx, self.ny, self.nz, self.h = nx, ny, nz, float(h)
+        if advection not in (0, 1):
+            raise ValueError("advection must be 0 (semi-implicit) or 1 (explicit)")
+        self.advection = int(advection)
         self.origin = np.asarray(origin, np.float64)
         self.mask = np.asarray(node_mask, np.uint8)
         self.rho, self.mu, self.dt = float(rho), float(mu), float(dt)
@@ -75,10 +81,10 @@ class Problem:
         self._pressure_setup()
 
     @classmethod
-    def from_case(cls, c):
+    def from_case(cls, c, advection=0):
         return cls(c.nx, c.ny, c.nz, c.h, c.origin, c.node_mask, c.bc_tag, c.X, c.dS, c.U_B,
                    c.rho, c.mu, c.dt, c.inlet_K, c.inlet_omega, c.inlet_ids, c.inlet_shape,
-                   getattr(c, "refine_cell", None))
+                   getattr(c, "refine_cell", None), advection)
 
     def _check_support_in_fine_band(self):
         """Reading of the refined band: the kernel support of every Lagrangian point
@@ -125,13 +131,21 @@ class Problem:
         iters, resid = {}, {}
 
         # 1. tentative velocity
-        A = ((rho / dt) * ops.M + rho * ops.advection(u) + mu * ops.K).tocsr()
+        C = ops.advection(u)
+        if self.advection == 0:
+            A = ((rho / dt) * ops.M + rho * C + mu * ops.K).tocsr()
+        else:
+            A = ((rho / dt) * ops.M + mu * ops.K).tocsr()
         A_FF = A[F][:, F].tocsr()
         diag = A_FF.diagonal()
         u_star = np.zeros_like(u)
         for d in range(3):
             rhs = (rho / dt) * (ops.M @ u[d]) - ops.G[d] @ p - A @ g[d]
-            x, it, res = krylov.bicgstab(A_FF, rhs[F], x0=u[d][F], diag=diag)
+            if self.advection == 0:
+                x, it, res = krylov.bicgstab(A_FF, rhs[F], x0=u[d][F], diag=diag)
+            else:
+                rhs = rhs - rho * (C @ u[d])
+                x, it, res = krylov.cg(A_FF, rhs[F], x0=u[d][F], diag=diag)
             u_star[d] = g[d]
             u_star[d][F] = x
             iters[f"s1_{d}"], resid[f"s1_{d}"] = it, res

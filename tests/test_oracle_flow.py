@@ -188,9 +188,10 @@ def test_paper_table1_grid_counts():
         assert 6 * n_xy * n_xy * n_z == row["tets"]
 
 
-def _one_d_advection(nx, U, force, mu, rho, dt, nsteps):
+def _one_d_advection(nx, U, force, mu, rho, dt, nsteps, explicit=False):
     """Backward-Euler Q1 solution of rho (w_t + U w_x) = mu w_xx + force on (0,1),
-    w(0) = w(1) = 0, w(x, 0) = sin(pi x): independent 1-D computation."""
+    w(0) = w(1) = 0, w(x, 0) = sin(pi x): independent 1-D computation.  explicit:
+    the convection term is taken at the old time level."""
     h = 1.0 / nx
     n = nx + 1
     M = np.zeros((n, n))
@@ -204,10 +205,12 @@ def _one_d_advection(nx, U, force, mu, rho, dt, nsteps):
     x = np.arange(n) * h
     w = np.sin(np.pi * x)
     w[[0, -1]] = 0.0
-    A = rho / dt * M + rho * U * C + mu * K
+    A = rho / dt * M + mu * K + (0.0 if explicit else rho * U) * C
     inner = slice(1, n - 1)
     for _ in range(nsteps):
         rhs = rho / dt * M @ w + force * M @ np.ones(n)
+        if explicit:
+            rhs = rhs - rho * U * C @ w
         wn = np.zeros(n)
         wn[inner] = np.linalg.solve(A[inner, inner], rhs[inner])
         w = wn
@@ -226,3 +229,37 @@ def test_advected_shear_profile_matches_one_dimensional_scheme():
     np.testing.assert_allclose(uz, np.broadcast_to(w[None, None, :], uz.shape), atol=1e-12)
     np.testing.assert_allclose(u[0], 0.8, atol=1e-12)
     assert np.abs(u[1]).max() < 1e-12
+
+
+def test_explicit_advection_shear_profile_matches_one_dimensional_scheme():
+    """The explicit-advection option: same exact solution with the convection term at
+    the old time level (pins its sign, rho factor and the old-velocity argument)."""
+    c = synth.shear_advection_case(cells_x=10, U=0.8, force=0.6, mu=0.03, rho=1.1, dt=0.05)
+    pr = ipcs.Problem.from_case(c, advection=1)
+    u, p, _, _ = pr.run(c.u0, c.p0, 3)
+    w = _one_d_advection(10, 0.8, 0.6, 0.03, 1.1, 0.05, 3, explicit=True)
+    w_semi = _one_d_advection(10, 0.8, 0.6, 0.03, 1.1, 0.05, 3)
+    assert np.abs(w - w_semi).max() > 1e-4          # the two schemes do differ here
+    uz = u[2].reshape(c.nz + 1, c.ny + 1, c.nx + 1)
+    np.testing.assert_allclose(uz, np.broadcast_to(w[None, None, :], uz.shape), atol=1e-12)
+    np.testing.assert_allclose(u[0], 0.8, atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", [1, 3])
+def test_explicit_advection_step_matches_dense_direct_solve(seed):
+    c = synth.random_blob_case(seed=seed)
+    pr = ipcs.Problem.from_case(c, advection=1)
+    s, ops = pr.sets, pr.ops
+    u, p = pr.initial_state(c.u0, c.p0)
+    t = 0.1
+    un, pn, t1, info = pr.step(u, p, t)
+    rho, mu, dt, F = pr.rho, pr.mu, pr.dt, s.F
+    g = pr.g(t + dt)
+    A = ((rho / dt) * ops.M + mu * ops.K).toarray()
+    Cu = ops.advection(u)
+    scale = np.abs(info.u_star).max()
+    for d in range(3):
+        rhs = (rho / dt) * (ops.M @ u[d]) - rho * (Cu @ u[d]) - ops.G[d] @ p - A @ g[d]
+        us = g[d].copy()
+        us[F] = np.linalg.solve(A[np.ix_(F, F)], rhs[F])
+        assert np.abs(info.u_star[d] - us).max() < 1e-11 * scale
