@@ -128,7 +128,10 @@ typedef struct ibfe_ib {
  *                 degree 16 on [lambda_max/4, lambda_max] of D^-1 K with the bound
  *                 lambda_max = 2; 2 = geometric multigrid V(2,2) cycle with
  *                 Chebyshev-Jacobi smoothing and a dense coarsest solve
- *   advection   : 0 = semi-implicit u^n . grad u* (only value accepted)
+ *   advection   : 0 = semi-implicit u^n . grad u* (BiCGStab on the advection-
+ *                 diffusion operator); 1 = explicit u^n . grad u^n (the convection
+ *                 of Eq. 13 at the old velocity on the right-hand side; CG on the
+ *                 symmetric (rho/dt) M + mu K)
  *   ib_rtol     : relative residual target of the IB force solve (<= 0: 1e-13)
  */
 typedef struct ibfe_params {

@@ -218,6 +218,27 @@ struct S1RhsElem {
   }
 };
 
+// Explicit advection on the composite mesh:
+// (rho/dt) M u_d - rho C(u^n) u_d - G_d p - A' g_d with A' = (rho/dt) M + mu K.
+struct S1RhsExplicitElem {
+  static constexpr int kNO = 3;
+  OpCSym<double, 3> mass;     // (rho/dt) M
+  OpCStencil<double, 3> adv;  // stored rho C(u^n)
+  OpCSym<double, 3> aprime;   // (rho/dt) M + mu K
+  GradElem grad;              // on p
+  const double* u;
+  const double* g;
+  __device__ __forceinline__ void elem(int n, double (&y)[3]) const {
+    double mu_[3], cu[3], gp[3], ag[3];
+    mass.elem(n, u, mu_);
+    adv.elem(n, u, cu);
+    grad.elem(n, gp);
+    aprime.elem(n, g, ag);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) y[d] = mu_[d] - cu[d] - gp[d] - ag[d];
+  }
+};
+
 // x[h] = mean of x over the 2 or 4 parents of hanging node h (nc planes).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_hang_fill(int nh, const int32_t* __restrict__ hang_ids,

@@ -152,8 +152,8 @@ struct ibfe_ctx {
   int32_t* par_child = nullptr;
   double* pw64 = nullptr;
   float* pw32 = nullptr;
-  double *dinvM64 = nullptr, *dinvK64 = nullptr;
-  float *dinvM32 = nullptr, *dinvK32 = nullptr;
+  double *dinvM64 = nullptr, *dinvK64 = nullptr, *dinvA64 = nullptr;
+  float *dinvM32 = nullptr, *dinvK32 = nullptr, *dinvA32 = nullptr;  // A: (rho/dt) M + mu K
   double* yh64 = nullptr;
   float* yh32 = nullptr;
   FormCoefs fcc{};   // forms of the coarse elements (spacing 2h)
@@ -320,6 +320,21 @@ int setup_refined(ibfe_ctx& c) {
   for (int64_t n = 0; n < P.N; ++n) {
     if (P.dmass[n] > 0.0) im[n] = 1.0 / P.dmass[n];
     if (P.dstiff[n] > 0.0) ik[n] = 1.0 / P.dstiff[n];
+  }
+  if (P.params.advection == 1) {
+    // Jacobi scaling of the symmetric tentative-velocity operator (rho/dt) M + mu K
+    const double rdt = P.params.rho / P.params.dt, mu = P.params.mu;
+    std::vector<double> ia(P.N, 0.0);
+    for (int64_t n = 0; n < P.N; ++n) {
+      const double dA = rdt * P.dmass[n] + mu * P.dstiff[n];
+      if (dA > 0.0) ia[n] = 1.0 / dA;
+    }
+    std::vector<float> ia32(ia.begin(), ia.end());
+    if ((rc = c.field(&c.dinvA64, 1))) return rc;
+    if ((rc = c.field(&c.dinvA32, 1))) return rc;
+    HIP_TRY(hipMemcpyAsync(c.dinvA64, ia.data(), sizeof(double) * P.N, hipMemcpyHostToDevice, c.stream));
+    HIP_TRY(hipMemcpyAsync(c.dinvA32, ia32.data(), sizeof(float) * P.N, hipMemcpyHostToDevice, c.stream));
+    HIP_TRY(hipStreamSynchronize(c.stream));
   }
   if ((rc = c.field(&c.dinvM64, 1))) return rc;
   if ((rc = c.field(&c.dinvK64, 1))) return rc;
@@ -1321,6 +1336,54 @@ int build_s1(ibfe_ctx& c) {
   return IBFE_OK;
 }
 
+// Tentative velocity with explicit advection (uniform grid): the stencil of
+// rho C(u^n) alone, the right-hand side (rho/dt) M u^n - rho C(u^n) u^n - G p^n
+// - A' g, and CG on the symmetric A' = (rho/dt) M + mu K over the free rows.
+// Leaves the free part of u* in w[9].
+int s1_explicit(ibfe_ctx& c) {
+  const Plan& P = c.plan;
+  const double rho = P.params.rho, dt = P.params.dt, mu = P.params.mu, rdt = rho / dt;
+  const int nb = blocks_for(c.nchunks);
+  const int64_t S = c.stride;
+  double* b1 = c.w[8];
+  double* x1 = c.w[9];
+  hipLaunchKernelGGL(k_s1_build, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.emask, c.flags,
+                     c.u, S, int(P.sy), int(P.sz), P.h, 0.0, 0.0, 0.0, 0.0, rho, c.coef64, (float*)nullptr, 1,
+                     kFlagP);
+  double cm[4], ca[4];
+  for (int t = 0; t < 4; ++t) {
+    cm[t] = rdt * c.fc.m[t];
+    ca[t] = rdt * c.fc.m[t] + mu * c.fc.k[t];
+  }
+  hipLaunchKernelGGL(k_s1_rhs_explicit, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.emask,
+                     c.flags, c.coef64, c.u, c.p, c.g, b1, S, int(P.sy), int(P.sz), cm[0], cm[1], cm[2], cm[3],
+                     ca[0], ca[1], ca[2], ca[3], c.fc.g2[0], c.fc.g2[1], c.fc.g2[2]);
+  hipLaunchKernelGGL((k_masked_copy<double, double>), dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks,
+                     c.flags, kFlagF, c.u, x1, 3, S);
+  CHECK_LAUNCH();
+  auto op = sym_op<double, 3>(c, ca, kFlagF);
+  SolveOut so;
+  int rc;
+  const int maxit = P.params.max_iters;
+  if (P.params.precision == 1) {
+    auto op32 = sym_op<float, 3>(c, ca, kFlagF);
+    float* const* v = c.v32;
+    rc = run_refined(c, op, kFlagF, 3, b1, x1, v[8], v[9], P.params.rtol, so,
+                     [&](const float* r32, float* d32, double tol, SolveOut& o) {
+                       return run_cg<float>(c, op32, c.chunks, c.nchunks, r32, d32, v[0], v[1], v[2], kScS1, tol,
+                                            maxit, true, o);
+                     });
+  } else {
+    rc = run_cg<double>(c, op, c.chunks, c.nchunks, b1, x1, c.w[0], c.w[1], c.w[2], kScS1, P.params.rtol,
+                        maxit, false, so);
+  }
+  if (rc) return rc;
+  c.stats.s1_iters = so.iters;
+  c.stats.s1_res = so.res;
+  c.stats.s1_outer = so.outer;
+  return IBFE_OK;
+}
+
 int remove_slot_means(ibfe_ctx& c, double* x) {
   const Plan& P = c.plan;
   const int nr = red_blocks(c.nchunks);
@@ -1360,10 +1423,12 @@ int step_once(ibfe_ctx& c) {
   }
 
   // 1. tentative velocity: A_FF u*_F = (rho/dt) M u^n - G p^n - A_FD g
-  if ((rc = build_s1(c))) return rc;
   double* b1 = c.w[8];
   double* x1 = c.w[9];
-  {
+  if (P.params.advection == 1) {
+    if ((rc = s1_explicit(c))) return rc;
+  } else {
+    if ((rc = build_s1(c))) return rc;
     double cm[4];
     for (int t = 0; t < 4; ++t) cm[t] = rho / dt * c.fc.m[t];
     hipLaunchKernelGGL(k_s1_rhs, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.emask,
@@ -1390,10 +1455,10 @@ int step_once(ibfe_ctx& c) {
     c.stats.s1_iters = so.iters;
     c.stats.s1_res = so.res;
     c.stats.s1_outer = so.outer;
-    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, 1.0, x1, 1.0,
-                       c.g, c.ustar, 3, S);
-    CHECK_LAUNCH();
   }
+  hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, 1.0, x1, 1.0, c.g,
+                     c.ustar, 3, S);
+  CHECK_LAUNCH();
 
   // 2.-4. BCE-IB correction: G Lambda = U_B - I u*, u_ib = u* + I_F^T Lambda (FP64)
   hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, 1.0, c.ustar,
@@ -1536,6 +1601,56 @@ int build_s1_refined(ibfe_ctx& c) {
   return IBFE_OK;
 }
 
+// Tentative velocity with explicit advection on the composite mesh (see
+// s1_explicit); the inputs u, p, g already hold their hanging values.
+int s1_explicit_refined(ibfe_ctx& c) {
+  const Plan& P = c.plan;
+  const double rho = P.params.rho, dt = P.params.dt, mu = P.params.mu, rdt = rho / dt;
+  const int nb = blocks_for(c.nchunks);
+  const int64_t S = c.stride;
+  double* b1 = c.w[8];
+  double* x1 = c.w[9];
+  hipLaunchKernelGGL(k_s1_build, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.emask, c.flags,
+                     c.u, S, int(P.sy), int(P.sz), P.h, 0.0, 0.0, 0.0, 0.0, rho, c.coef64, (float*)nullptr, 1,
+                     kFlagP | kFlagHang);
+  hipLaunchKernelGGL(k_s1_build, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.cmask, c.flags,
+                     c.u, S, int(P.sy), int(P.sz), P.hb, 0.0, 0.0, 0.0, 0.0, rho, c.coef64 + 27 * S,
+                     (float*)nullptr, 2, kFlagP);
+  CHECK_LAUNCH();
+  int rc;
+  S1RhsExplicitElem f{};
+  f.mass = csym_op<double, 3>(c, rdt, 0.0, kFlagF, c.dinvM64);
+  f.adv = cstencil_op<double>(c, c.coef64, kFlagF);
+  f.aprime = csym_op<double, 3>(c, rdt, mu, kFlagF, c.dinvA64);
+  f.grad = grad_elem(c, c.p);
+  f.u = c.u;
+  f.g = c.g;
+  if ((rc = comp_rows<double>(c, f, kFlagF, 0u, 1.0, b1))) return rc;
+  hipLaunchKernelGGL((k_masked_copy<double, double>), dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks,
+                     c.flags, kFlagF, c.u, x1, 3, S);
+  CHECK_LAUNCH();
+  auto op = csym_op<double, 3>(c, rdt, mu, kFlagF, c.dinvA64);
+  SolveOut so;
+  const int maxit = P.params.max_iters;
+  if (P.params.precision == 1) {
+    auto op32 = csym_op<float, 3>(c, rdt, mu, kFlagF, c.dinvA32);
+    float* const* v = c.v32;
+    rc = run_refined(c, op, kFlagF, 3, b1, x1, v[8], v[9], P.params.rtol, so,
+                     [&](const float* r32, float* d32, double tol, SolveOut& o) {
+                       return run_cg<float>(c, op32, c.chunks, c.nchunks, r32, d32, v[0], v[1], v[2], kScS1, tol,
+                                            maxit, true, o);
+                     });
+  } else {
+    rc = run_cg<double>(c, op, c.chunks, c.nchunks, b1, x1, c.w[0], c.w[1], c.w[2], kScS1, P.params.rtol,
+                        maxit, false, so);
+  }
+  if (rc) return rc;
+  c.stats.s1_iters = so.iters;
+  c.stats.s1_res = so.res;
+  c.stats.s1_outer = so.outer;
+  return IBFE_OK;
+}
+
 int step_once_refined(ibfe_ctx& c) {
   const Plan& P = c.plan;
   const double rho = P.params.rho, dt = P.params.dt;
@@ -1564,10 +1679,12 @@ int step_once_refined(ibfe_ctx& c) {
     return rc;
 
   // 1. tentative velocity
-  if ((rc = build_s1_refined(c))) return rc;
   double* b1 = c.w[8];
   double* x1 = c.w[9];
-  {
+  if (P.params.advection == 1) {
+    if ((rc = s1_explicit_refined(c))) return rc;
+  } else {
+    if ((rc = build_s1_refined(c))) return rc;
     S1RhsElem f{};
     f.mass = csym_op<double, 3>(c, rho / dt, 0.0, kFlagF, c.dinvM64);
     f.A = cstencil_op<double>(c, c.coef64, kFlagF);
@@ -1595,10 +1712,10 @@ int step_once_refined(ibfe_ctx& c) {
     c.stats.s1_iters = so.iters;
     c.stats.s1_res = so.res;
     c.stats.s1_outer = so.outer;
-    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, 1.0, x1, 1.0,
-                       c.g, c.ustar, 3, S);
-    CHECK_LAUNCH();
   }
+  hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, 1.0, x1, 1.0, c.g,
+                     c.ustar, 3, S);
+  CHECK_LAUNCH();
 
   // 2.-4. BCE-IB correction (every support node is a fine, non-hanging node)
   hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, 1.0, c.ustar,

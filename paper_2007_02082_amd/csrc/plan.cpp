@@ -65,8 +65,8 @@ int build_plan(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* para
     err = "precision must be 0 (FP64) or 1 (FP32 inner / FP64 refinement)";
     return IBFE_EINVAL;
   }
-  if (pr.precond < 0 || pr.precond > 2 || pr.advection != 0) {
-    err = "precond must be 0 (Jacobi), 1 (Chebyshev) or 2 (multigrid); advection must be 0 (semi-implicit)";
+  if (pr.precond < 0 || pr.precond > 2 || pr.advection < 0 || pr.advection > 1) {
+    err = "precond must be 0 (Jacobi), 1 (Chebyshev) or 2 (multigrid); advection 0 (semi-implicit) or 1 (explicit)";
     return IBFE_EINVAL;
   }
   P.refined = grid->refine_cell != nullptr;

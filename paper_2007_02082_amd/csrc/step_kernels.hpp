@@ -159,6 +159,37 @@ __global__ __launch_bounds__(kBlock) void k_s1_rhs(const int* __restrict__ chunk
     b[d * stride + n] = apply_sym<double>(u + d * stride, n, e, cm, sy, sz) - gp[d] - ag[d];
 }
 
+// Explicit advection: b_d = (rho/dt)(M u_d) - (rho C(u^n) u^n)_d - G_d p - A' g_d on
+// free rows with A' = (rho/dt) M + mu K; `adv` holds the stencil of rho C(u^n).
+__global__ __launch_bounds__(kBlock) void k_s1_rhs_explicit(
+    const int* __restrict__ chunks, int nchunks, const uint8_t* __restrict__ emask,
+    const uint8_t* __restrict__ flags, const double* __restrict__ adv, const double* __restrict__ u,
+    const double* __restrict__ p, const double* __restrict__ g, double* __restrict__ b, int64_t stride, int sy,
+    int sz, double cm0, double cm1, double cm2, double cm3, double ca0, double ca1, double ca2, double ca3,
+    double g20, double g21, double g22) {
+  const int n = chunk_node(chunks, nchunks);
+  if (n < 0) return;
+  if (!(flags[n] & kFlagF)) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) b[d * stride + n] = 0.0;
+    return;
+  }
+  const uint32_t e = emask[n];
+  const double cm[4] = {cm0, cm1, cm2, cm3};
+  const double ca[4] = {ca0, ca1, ca2, ca3};
+  const double g2[3] = {g20, g21, g22};
+  const double gp[3] = {apply_grad<double, 0>(p, n, e, g2, sy, sz),
+                        apply_grad<double, 1>(p, n, e, g2, sy, sz),
+                        apply_grad<double, 2>(p, n, e, g2, sy, sz)};
+  OpStencil<double, 3> C{adv, flags, kFlagF, sy, sz, stride};
+  double cu[3];
+  C.apply(n, u, cu);
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    b[d * stride + n] = apply_sym<double>(u + d * stride, n, e, cm, sy, sz) - cu[d] - gp[d] -
+                        apply_sym<double>(g + d * stride, n, e, ca, sy, sz);
+}
+
 // b = scale * sum_d G_d u_d on rows with (flags & rowbit), 0 elsewhere.
 __global__ __launch_bounds__(kBlock) void k_div(const int* __restrict__ chunks, int nchunks,
                                                 const uint8_t* __restrict__ emask,

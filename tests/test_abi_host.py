@@ -84,6 +84,13 @@ def test_input_errors():
     bad = dict(kw, inlet_ids=np.array([c.N - 1]), inlet_shape=np.zeros((5, 1, 3)))
     with pytest.raises(ibfe.IbfeError, match="EINVAL"):
         ibfe.Plan(**bad)
+    bad = dict(kw, advection=2)
+    with pytest.raises(ibfe.IbfeError, match="EINVAL"):
+        ibfe.Plan(**bad)
+    bad = dict(kw, precond=3)
+    with pytest.raises(ibfe.IbfeError, match="EINVAL"):
+        ibfe.Plan(**bad)
+    ibfe.Plan(**dict(kw, advection=1, precond=1))
     # a Lagrangian point whose support holds no free node
     far = np.array([[100.0, 100.0, 100.0]])
     bad = dict(kw, X=far, U_B=None)

@@ -295,3 +295,19 @@ def test_step_parity_chebyshev_preconditioner(make, precision, tol):
     _, out_j = run_pair(case, 1, precision=precision, precond=0)
     say("s3 iterations: Chebyshev", out[0]["stats"]["s3_iters"], "Jacobi", out_j[0]["stats"]["s3_iters"])
     assert out[0]["stats"]["s3_iters"] < out_j[0]["stats"]["s3_iters"]
+
+
+# ---------------------------------------------------------------------------
+# explicit advection (the convection of Eq. 13 at the old velocity)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision,tol", [(0, TOL64), (1, TOL_MIXED)])
+@pytest.mark.parametrize("make", [lambda: synth.shear_advection_case(),
+                                  lambda: synth.random_blob_case(seed=3),
+                                  lambda: synth.small_cylinder(8, 16, pulsatile=True, nsteps=3),
+                                  lambda: synth.refined_cylinder(8, 8, length=1.25, band=0.3)])
+def test_step_parity_explicit_advection(make, precision, tol):
+    case = make()
+    say("case", case.name, "explicit advection, precision", precision)
+    _, out = run_pair(case, 3, t0=0.05, precision=precision, precond=2, advection=1)
+    _check_steps(out, tol, case.name + "/explicit")
