@@ -273,13 +273,13 @@ __global__ __launch_bounds__(kBlock) void k_hang_elem(int nh, const int32_t* __r
 // out[d][n] = scale * (element row + hanging children) on rows (flags & rowbit,
 // none of `exclude`), 0 elsewhere.
 template <typename T, class F>
-__global__ __launch_bounds__(kBlock) void k_comp_rows(const int* __restrict__ chunks, int nchunks, F f,
+__global__ __launch_bounds__(kBlock) void k_comp_rows(NodeList nl, F f,
                                                       const uint8_t* __restrict__ flags, uint32_t rowbit,
                                                       uint32_t exclude, T scale, Children ch,
                                                       const T* __restrict__ pw, const T* __restrict__ yh,
                                                       T* __restrict__ out, int64_t stride) {
   constexpr int NO = F::kNO;
-  const int n = chunk_node(chunks, nchunks);
+  const int n = chunk_node(nl);
   if (n < 0) return;
   const uint32_t fl = flags[n];
   const bool rw = (fl & rowbit) && !(fl & exclude);
@@ -296,16 +296,16 @@ __global__ __launch_bounds__(kBlock) void k_comp_rows(const int* __restrict__ ch
 //   d <- c1 d + c2 D^-1 (b - A x_in), x_out = x_in + d on rows, 0 elsewhere;
 // with DOT the partial sums of b . x_out.
 template <typename T, class Op, bool DOT>
-__global__ __launch_bounds__(kBlock) void k_cheb_gen(const int* __restrict__ chunks, int nchunks, Op op,
+__global__ __launch_bounds__(kBlock) void k_cheb_gen(NodeList nl, Op op,
                                                      const T* __restrict__ x_in, const T* __restrict__ b,
                                                      T* __restrict__ d, T* __restrict__ x_out, T c1, T c2,
                                                      double* __restrict__ partials, const KScal* sc) {
   if (sc && sc->done) return;
   constexpr int NC = Op::kNC;
   double dot[1] = {0.0};
-  const ChunkRange cr = block_chunks(nchunks);
+  const ChunkRange cr = block_chunks(nl.n);
   for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
-    const int n = chunks[c] * 64 + int(threadIdx.x & 63);
+    const int n = nl.node(c);
     const bool rw = op.row(n);
     T y[NC];
     if (rw) op.apply(n, x_in, y);
@@ -331,11 +331,11 @@ __global__ __launch_bounds__(kBlock) void k_cheb_gen(const int* __restrict__ chu
 
 // x = d = c2 D^-1 b on rows (Chebyshev step from x = 0), 0 elsewhere.
 template <typename T, class Op>
-__global__ __launch_bounds__(kBlock) void k_cheb0_gen(const int* __restrict__ chunks, int nchunks, Op op,
+__global__ __launch_bounds__(kBlock) void k_cheb0_gen(NodeList nl, Op op,
                                                       const T* __restrict__ b, T* __restrict__ d,
                                                       T* __restrict__ x, T c2, const KScal* sc) {
   if (sc && sc->done) return;
-  const int n = chunk_node(chunks, nchunks);
+  const int n = chunk_node(nl);
   if (n < 0) return;
   const bool rw = op.row(n);
   const T di = rw ? op.inv_diag(n) : T(0);
@@ -350,11 +350,11 @@ __global__ __launch_bounds__(kBlock) void k_cheb0_gen(const int* __restrict__ ch
 
 // r = b - A x on rows, 0 elsewhere (multigrid residual on the composite level).
 template <typename T, class Op>
-__global__ __launch_bounds__(kBlock) void k_resid_gen(const int* __restrict__ chunks, int nchunks, Op op,
+__global__ __launch_bounds__(kBlock) void k_resid_gen(NodeList nl, Op op,
                                                       const T* __restrict__ x, const T* __restrict__ b,
                                                       T* __restrict__ r, const KScal* sc) {
   if (sc && sc->done) return;
-  const int n = chunk_node(chunks, nchunks);
+  const int n = chunk_node(nl);
   if (n < 0) return;
   const bool rw = op.row(n);
   T y[Op::kNC];

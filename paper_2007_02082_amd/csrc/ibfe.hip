@@ -70,7 +70,7 @@ struct MGDev {
   int64_t N = 0, sy = 0, sz = 0, halo = 0, stride = 0;
   uint8_t* emask = nullptr;
   uint8_t* flags = nullptr;
-  int* chunks = nullptr;
+  NodeList nl;
   int* zitems = nullptr;
   T *b = nullptr, *x = nullptr, *xt = nullptr, *d = nullptr, *r = nullptr;
   double kc[4] = {0, 0, 0, 0};  // per-cell stiffness entries at this spacing
@@ -97,8 +97,8 @@ struct ibfe_ctx {
   uint8_t* emask = nullptr;
   uint8_t* flags = nullptr;
   int8_t* slot = nullptr;
-  int* chunks = nullptr;
-  int* ib_chunks = nullptr;
+  NodeList nl;                    // active nodes (P and hanging)
+  NodeList ib_nl;                 // Lagrangian points
   int* zitems = nullptr;          // z-blocked column items (plane_block * cpp + chunk)
   int nzitems = 0, cpp = 0, zb = kZBPlanes;
   int64_t* pids = nullptr;
@@ -254,7 +254,7 @@ int setup_mg(ibfe_ctx& c, std::vector<MGDev<T>>& out, T* xt0, T* d0, T* r0) {
       D.stride = c.stride;
       D.emask = c.emask;
       D.flags = c.flags;
-      D.chunks = c.chunks;
+      D.nl = c.nl;
       D.nchunks = c.nchunks;
       D.zitems = c.zitems;
       D.nzitems = c.nzitems;
@@ -275,8 +275,10 @@ int setup_mg(ibfe_ctx& c, std::vector<MGDev<T>>& out, T* xt0, T* d0, T* r0) {
       if ((rc = plane(1, &base))) return rc;
       D.flags = reinterpret_cast<uint8_t*>(base) + D.halo;
       HIP_TRY(hipMemcpyAsync(D.flags, L.flags.data(), L.N, hipMemcpyHostToDevice, c.stream));
-      if ((rc = c.upload(&D.chunks, L.chunks.data(), L.chunks.size()))) return rc;
+      int* lc = nullptr;
+      if ((rc = c.upload(&lc, L.chunks.data(), L.chunks.size()))) return rc;
       D.nchunks = int(L.chunks.size());
+      D.nl = NodeList{lc, D.nchunks, 0};
       if ((rc = c.upload(&D.zitems, L.zitems.data(), L.zitems.size()))) return rc;
       D.nzitems = int(L.zitems.size());
       T** vecs[5] = {&D.b, &D.x, &D.xt, &D.d, &D.r};
@@ -356,6 +358,38 @@ int setup_refined(ibfe_ctx& c) {
   return IBFE_OK;
 }
 
+// The active nodes (P and hanging) as 64-node chunks, or one node per lane when
+// they fill their chunks sparsely: a thin vessel in a large box leaves most
+// lanes of its chunks idle, and the per-lane list runs the same kernels on
+// 2-3x fewer wavefronts.  The padding node of a per-lane list is a lattice node
+// outside every set, so kernels see it as a non-row.
+int setup_node_list(ibfe_ctx& c) {
+  const Plan& P = c.plan;
+  int64_t active = 0;
+  for (int64_t n = 0; n < P.N; ++n) active += (P.flags[n] & (IBFE_FLAG_P | IBFE_FLAG_HANG)) ? 1 : 0;
+  const double fill = double(active) / (double(kChunk) * double(std::max<size_t>(1, P.chunks.size())));
+  int64_t pad = -1;
+  if (fill < kLaneFill)
+    for (int64_t n = 0; n < P.N && pad < 0; ++n)
+      if (P.flags[n] == 0 && P.emask[n] == 0 && (!P.refined || P.cmask[n] == 0) && P.float_slot[n] < 0) pad = n;
+  int rc;
+  int* ids = nullptr;
+  if (pad < 0) {
+    if ((rc = c.upload(&ids, P.chunks.data(), P.chunks.size()))) return rc;
+    c.nl = NodeList{ids, int(P.chunks.size()), 0};
+  } else {
+    std::vector<int32_t> lanes;
+    lanes.reserve(size_t(active + kChunk));
+    for (int64_t n = 0; n < P.N; ++n)
+      if (P.flags[n] & (IBFE_FLAG_P | IBFE_FLAG_HANG)) lanes.push_back(int32_t(n));
+    while (lanes.size() % kChunk) lanes.push_back(int32_t(pad));
+    if ((rc = c.upload(&ids, lanes.data(), lanes.size()))) return rc;
+    c.nl = NodeList{ids, int(lanes.size() / kChunk), 1};
+  }
+  c.nchunks = c.nl.n;
+  return IBFE_OK;
+}
+
 int setup_device(ibfe_ctx& c) {
   Plan& P = c.plan;
   const int64_t nch_total = (P.N + kChunk - 1) / kChunk;
@@ -363,7 +397,6 @@ int setup_device(ibfe_ctx& c) {
   const int64_t reach = (P.refined ? 2 : 1) * (P.sz + P.sy + 1);
   c.halo = ((reach + kChunk - 1) / kChunk) * kChunk;
   c.stride = 2 * c.halo + nch_total * kChunk;
-  c.nchunks = int(P.chunks.size());
   c.nP = int(P.P_ids.size());
   c.fc = form_coefs(P.h);
   int rc;
@@ -386,7 +419,7 @@ int setup_device(ibfe_ctx& c) {
     int64_t tail = nch_total * kChunk - P.N;
     if (tail > 0) HIP_TRY(hipMemsetAsync(c.slot + P.N, 0xFF, tail, c.stream));
   }
-  if ((rc = c.upload(&c.chunks, P.chunks.data(), P.chunks.size()))) return rc;
+  if ((rc = setup_node_list(c))) return rc;
   {
     // column items of the z-blocked applies: zb planes x 64 in-plane nodes
     std::vector<int> items;
@@ -434,7 +467,9 @@ int setup_device(ibfe_ctx& c) {
   if (M > 0) {
     std::vector<int> ibc(c.ib_nchunks);
     for (int i = 0; i < c.ib_nchunks; ++i) ibc[i] = i;
-    if ((rc = c.upload(&c.ib_chunks, ibc.data(), ibc.size()))) return rc;
+    int* ic = nullptr;
+    if ((rc = c.upload(&ic, ibc.data(), ibc.size()))) return rc;
+    c.ib_nl = NodeList{ic, c.ib_nchunks, 0};
     if ((rc = c.upload(&c.ib_idx, P.ib_idx.data(), P.ib_idx.size()))) return rc;
     if ((rc = c.upload(&c.ib_w, P.ib_w.data(), P.ib_w.size()))) return rc;
     if ((rc = c.upload(&c.UB, P.U_B.data(), P.U_B.size()))) return rc;
@@ -515,19 +550,19 @@ int next_batch(int est, int done_so_far) {
 // q = A p with partial p.q; returns the number of partials written.  With
 // events, the dispatch itself records its start and end (no extra packets).
 template <typename T, class Op>
-int launch_q(ibfe_ctx& c, const Op& op, const int* chunks, int nchunks, const T* p, T* q,
+int launch_q(ibfe_ctx& c, const Op& op, NodeList nl, const T* p, T* q,
              const KScal* sc, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
-  const int nr = red_blocks(nchunks);
+  const int nr = red_blocks(nl.n);
   if (e0)
-    hipExtLaunchKernelGGL((k_cg_q<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, e0, e1, 0, chunks, nchunks,
+    hipExtLaunchKernelGGL((k_cg_q<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, e0, e1, 0, nl,
                           op, p, q, c.partials, sc);
   else
-    hipLaunchKernelGGL((k_cg_q<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, chunks, nchunks, op, p, q,
+    hipLaunchKernelGGL((k_cg_q<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, nl, op, p, q,
                        c.partials, sc);
   return nr;
 }
 template <typename T, int NC>
-int launch_q(ibfe_ctx& c, const OpSym<T, NC>& op, const int*, int, const T* p, T* q, const KScal* sc,
+int launch_q(ibfe_ctx& c, const OpSym<T, NC>& op, NodeList, const T* p, T* q, const KScal* sc,
              hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   const int nr = red_blocks(c.nzitems);
   ZOp<T> z{op.emask, op.flags, op.rowbit, op.sy, op.sz, c.plan.nz + 1, c.cpp,
@@ -643,14 +678,14 @@ int collect_mass_events(ibfe_ctx& c, int n) {
 }
 
 template <typename T, class Op>
-int run_cg(ibfe_ctx& c, const Op& op, const int* chunks, int nchunks, const T* b, T* x, T* r, T* p,
+int run_cg(ibfe_ctx& c, const Op& op, NodeList nl, const T* b, T* x, T* r, T* p,
            T* q, int slot, double rtol, int max_iters, bool zero_guess, SolveOut& out,
            bool timed = false) {
-  const int nb = blocks_for(nchunks), nr = red_blocks(nchunks);
+  const int nb = blocks_for(nl.n), nr = red_blocks(nl.n);
   KScal* sc = &c.scal[slot];
   int prc;
   if (!zero_guess && (prc = pre_apply(c, op, x, (const KScal*)nullptr))) return prc;
-  hipLaunchKernelGGL((k_cg_init<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, chunks, nchunks, op, b, x,
+  hipLaunchKernelGGL((k_cg_init<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, nl, op, b, x,
                      r, p, c.partials, zero_guess ? 1 : 0);
   hipLaunchKernelGGL(k_fin_cg_init, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr, sc,
                      rtol * rtol, max_iters);
@@ -665,13 +700,13 @@ int run_cg(ibfe_ctx& c, const Op& op, const int* chunks, int nchunks, const T* b
         if (timed && timer_events(c, size_t(launched + k), e0, e1)) return IBFE_EHIP;
         int rc2;
         if ((rc2 = pre_apply(c, op, p, (const KScal*)sc))) return rc2;
-        const int nq = launch_q<T>(c, op, chunks, nchunks, p, q, (const KScal*)sc, e0, e1);
+        const int nq = launch_q<T>(c, op, nl, p, q, (const KScal*)sc, e0, e1);
         hipLaunchKernelGGL(k_fin_cg_q, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nq, sc);
-        hipLaunchKernelGGL((k_cg_xr<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, chunks, nchunks, op, x, r,
+        hipLaunchKernelGGL((k_cg_xr<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, nl, op, x, r,
                            p, q, c.partials, (const KScal*)sc);
         hipLaunchKernelGGL(k_fin_cg_xr, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr,
                            sc);
-        hipLaunchKernelGGL((k_cg_p<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, chunks, nchunks, op, r, p,
+        hipLaunchKernelGGL((k_cg_p<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, nl, op, r, p,
                            (const KScal*)sc);
         CHECK_LAUNCH();
       }
@@ -702,8 +737,7 @@ template <typename T, class Op>
 int run_bicgstab(ibfe_ctx& c, const Op& op, const T* b, T* x, T* const* wv, int slot, double rtol,
                  int max_iters, SolveOut& out) {
   const int nb = blocks_for(c.nchunks), nr = red_blocks(c.nchunks);
-  const int* ch = c.chunks;
-  const int nch = c.nchunks;
+  const NodeList nl = c.nl;
   const double* pa = c.partials;
   T *r = wv[0], *rhat = wv[1], *p = wv[2], *v = wv[3], *phat = wv[4], *s = wv[5], *shat = wv[6],
     *t = wv[7];
@@ -711,7 +745,7 @@ int run_bicgstab(ibfe_ctx& c, const Op& op, const T* b, T* x, T* const* wv, int 
   const KScal* csc = sc;
   int prc;
   if ((prc = pre_apply(c, op, x, (const KScal*)nullptr))) return prc;
-  hipLaunchKernelGGL((k_bi_init<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, ch, nch, op, b, x, r, rhat, p,
+  hipLaunchKernelGGL((k_bi_init<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, nl, op, b, x, r, rhat, p,
                      v, c.partials);
   hipLaunchKernelGGL(k_fin_bi_init, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc, rtol * rtol, max_iters);
   CHECK_LAUNCH();
@@ -722,19 +756,19 @@ int run_bicgstab(ibfe_ctx& c, const Op& op, const T* b, T* x, T* const* wv, int 
     auto body = [&]() -> int {
       for (int k = 0; k < batch; ++k) {
         int rc2;
-        hipLaunchKernelGGL((k_bi_p<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, ch, nch, op, r, p, v, phat,
+        hipLaunchKernelGGL((k_bi_p<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, nl, op, r, p, v, phat,
                            csc);
         if ((rc2 = pre_apply(c, op, phat, csc))) return rc2;
-        hipLaunchKernelGGL((k_bi_apply<T, Op, 0>), dim3(nr), dim3(kBlock), 0, c.stream, ch, nch, op, phat, v,
+        hipLaunchKernelGGL((k_bi_apply<T, Op, 0>), dim3(nr), dim3(kBlock), 0, c.stream, nl, op, phat, v,
                            rhat, c.partials, csc);
         hipLaunchKernelGGL(k_fin_bi_apply<0>, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc);
-        hipLaunchKernelGGL((k_bi_s<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, ch, nch, op, r, v, s, shat,
+        hipLaunchKernelGGL((k_bi_s<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, nl, op, r, v, s, shat,
                            csc);
         if ((rc2 = pre_apply(c, op, shat, csc))) return rc2;
-        hipLaunchKernelGGL((k_bi_apply<T, Op, 1>), dim3(nr), dim3(kBlock), 0, c.stream, ch, nch, op, shat, t,
+        hipLaunchKernelGGL((k_bi_apply<T, Op, 1>), dim3(nr), dim3(kBlock), 0, c.stream, nl, op, shat, t,
                            s, c.partials, csc);
         hipLaunchKernelGGL(k_fin_bi_apply<1>, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc);
-        hipLaunchKernelGGL((k_bi_x<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, ch, nch, op, x, r, rhat,
+        hipLaunchKernelGGL((k_bi_x<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, nl, op, x, r, rhat,
                            phat, shat, s, t, c.partials, csc);
         hipLaunchKernelGGL(k_fin_bi_x, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc);
         CHECK_LAUNCH();
@@ -761,7 +795,7 @@ int ir_residual(ibfe_ctx& c, const Op64& op, const double* b, double* x, TR* r32
   const int nr = red_blocks(c.nchunks);
   int prc;
   if ((prc = pre_apply(c, op, x, (const KScal*)nullptr))) return prc;
-  hipLaunchKernelGGL((k_residual<Op64, TR>), dim3(nr), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, op, b,
+  hipLaunchKernelGGL((k_residual<Op64, TR>), dim3(nr), dim3(kBlock), 0, c.stream, c.nl, op, b,
                      x, r32, c.partials);
   hipLaunchKernelGGL(k_fin_residual, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr,
                      c.res2);
@@ -794,7 +828,7 @@ int run_refined(ibfe_ctx& c, const Op64& op64, uint32_t rowbit, int nc, const do
     rc = inner((const float*)r32, d32, tol_in, so);
     total += so.iters;
     if (rc && rc != IBFE_ENOCONV) return rc;
-    hipLaunchKernelGGL(k_add_correction<float>, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks,
+    hipLaunchKernelGGL(k_add_correction<float>, dim3(nb), dim3(kBlock), 0, c.stream, c.nl,
                        c.flags, rowbit, (const float*)d32, x, nc, c.stride);
     CHECK_LAUNCH();
   }
@@ -941,7 +975,7 @@ int comp_rows(ibfe_ctx& c, const F& f, uint32_t rowbit, uint32_t exclude, T scal
     hipLaunchKernelGGL((k_hang_elem<T, F>), dim3(blocks_lin(c.nh)), dim3(kBlock), 0, c.stream, c.nh,
                        (const int32_t*)c.hang_ids, f, yh, (const KScal*)nullptr);
   hipLaunchKernelGGL((k_comp_rows<T, F>), dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
-                     (const int*)c.chunks, c.nchunks, f, (const uint8_t*)c.flags, rowbit, exclude, scale,
+                     c.nl, f, (const uint8_t*)c.flags, rowbit, exclude, scale,
                      children_of(c), RefBufs<T>::pw(c), (const T*)yh, out, c.stride);
   CHECK_LAUNCH();
   return IBFE_OK;
@@ -961,7 +995,7 @@ int run_cheb_gen(ibfe_ctx& c, const Op& op, const T* b, T* x, T* xalt, T* d, int
   T* cur = ((iters - 1) % 2 == 0) ? x : xalt;
   T* alt = cur == x ? xalt : x;
   hipLaunchKernelGGL((k_cheb0_gen<T, Op>), dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
-                     (const int*)c.chunks, c.nchunks, op, b, d, cur, T(1.0 / theta), (const KScal*)nullptr);
+                     c.nl, op, b, d, cur, T(1.0 / theta), (const KScal*)nullptr);
   const int nr = red_blocks(c.nchunks);
   int rc;
   T* const cur0 = cur;
@@ -978,11 +1012,11 @@ int run_cheb_gen(ibfe_ctx& c, const Op& op, const T* b, T* x, T* xalt, T* d, int
       if (c.timing && mass_events(c, size_t(k - 1), e0, e1)) return IBFE_EHIP;
       if (e0)
         hipExtLaunchKernelGGL((k_cheb_gen<T, Op, false>), dim3(nr), dim3(kBlock), 0, c.stream, e0, e1, 0,
-                              (const int*)c.chunks, c.nchunks, op, (const T*)cur, b, d, alt, c1, c2, c.partials,
+                              c.nl, op, (const T*)cur, b, d, alt, c1, c2, c.partials,
                               (const KScal*)nullptr);
       else
         hipLaunchKernelGGL((k_cheb_gen<T, Op, false>), dim3(nr), dim3(kBlock), 0, c.stream,
-                           (const int*)c.chunks, c.nchunks, op, (const T*)cur, b, d, alt, c1, c2, c.partials,
+                           c.nl, op, (const T*)cur, b, d, alt, c1, c2, c.partials,
                            (const KScal*)nullptr);
       std::swap(cur, alt);
     }
@@ -1059,20 +1093,16 @@ int smooth_comp(ibfe_ctx& c, const MGDev<T>& L, const T* b, T*& x, T*& alt, int 
   for (int k = 0; k < m; ++k) {
     const bool last = k == m - 1;
     if (k == 0 && zero_start && !(last && dot)) {
-      hipLaunchKernelGGL((k_cheb0_gen<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, (const int*)c.chunks,
-                         c.nchunks, op, b, L.d, x, T(ch.c2[0]), sc);
+      hipLaunchKernelGGL((k_cheb0_gen<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, c.nl, op, b, L.d, x, T(ch.c2[0]), sc);
       continue;
     }
     if (k == 0 && zero_start)
-      hipLaunchKernelGGL((k_cheb0_gen<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, (const int*)c.chunks,
-                         c.nchunks, op, b, L.d, x, T(0), sc);
+      hipLaunchKernelGGL((k_cheb0_gen<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, c.nl, op, b, L.d, x, T(0), sc);
     if ((rc = pre_apply(c, op, x, sc))) return rc;
     if (last && dot)
-      hipLaunchKernelGGL((k_cheb_gen<T, Op, true>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.chunks,
-                         c.nchunks, op, (const T*)x, b, L.d, alt, T(ch.c1[k]), T(ch.c2[k]), c.partials, sc);
+      hipLaunchKernelGGL((k_cheb_gen<T, Op, true>), dim3(nr), dim3(kBlock), 0, c.stream, c.nl, op, (const T*)x, b, L.d, alt, T(ch.c1[k]), T(ch.c2[k]), c.partials, sc);
     else
-      hipLaunchKernelGGL((k_cheb_gen<T, Op, false>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.chunks,
-                         c.nchunks, op, (const T*)x, b, L.d, alt, T(ch.c1[k]), T(ch.c2[k]), c.partials, sc);
+      hipLaunchKernelGGL((k_cheb_gen<T, Op, false>), dim3(nr), dim3(kBlock), 0, c.stream, c.nl, op, (const T*)x, b, L.d, alt, T(ch.c1[k]), T(ch.c2[k]), c.partials, sc);
     std::swap(x, alt);
   }
   nparts = nr;
@@ -1091,7 +1121,7 @@ int smooth(ibfe_ctx& c, const MGDev<T>& L, const T* b, T*& x, T*& alt, int m, bo
     const bool last = k == m - 1;
     if (k == 0 && zero_start && !(last && dot)) {
       hipLaunchKernelGGL(k_mg_cheb0<T>, dim3(blocks_for(L.nchunks)), dim3(kBlock), 0, c.stream,
-                         (const int*)L.chunks, L.nchunks, (const uint8_t*)L.emask, (const uint8_t*)L.flags,
+                         L.nl, (const uint8_t*)L.emask, (const uint8_t*)L.flags,
                          T(L.kc[0]), T(ch.c2[0]), b, L.d, x, sc);
       continue;  // x already holds the result: no swap
     }
@@ -1099,7 +1129,7 @@ int smooth(ibfe_ctx& c, const MGDev<T>& L, const T* b, T*& x, T*& alt, int m, bo
     if (k == 0 && zero_start) {
       // degree-1 smoothing from zero with a dot: x is zero on entry
       hipLaunchKernelGGL(k_mg_cheb0<T>, dim3(blocks_for(L.nchunks)), dim3(kBlock), 0, c.stream,
-                         (const int*)L.chunks, L.nchunks, (const uint8_t*)L.emask, (const uint8_t*)L.flags,
+                         L.nl, (const uint8_t*)L.emask, (const uint8_t*)L.flags,
                          T(L.kc[0]), T(0), b, L.d, x, sc);
       xin = x;
     }
@@ -1138,14 +1168,14 @@ int vcycle(ibfe_ctx& c, std::vector<MGDev<T>>& lv, const T* r0, T* z0, const KSc
       const auto op = csym_op<T, 1>(c, 0.0, 1.0, kMgRow, RefBufs<T>::dinvK(c));
       if ((rc = pre_apply(c, op, cur[l], sc))) return rc;
       hipLaunchKernelGGL((k_resid_gen<T, OpCSym<T, 1>>), dim3(blocks_for(c.nchunks)), dim3(kBlock), 0,
-                         c.stream, (const int*)c.chunks, c.nchunks, op, (const T*)cur[l], b, A.r, sc);
+                         c.stream, c.nl, op, (const T*)cur[l], b, A.r, sc);
     } else {
       hipLaunchKernelGGL(k_zb_resid<T>, dim3(red_blocks(A.nzitems)), dim3(kBlock), 0, c.stream,
                          (const int*)A.zitems, A.nzitems, level_op(A), (const T*)cur[l], b, A.r, sc);
     }
     const MGDev<T>& C = lv[l + 1];
     hipLaunchKernelGGL(k_mg_restrict<T>, dim3(blocks_for(C.nchunks)), dim3(kBlock), 0, c.stream,
-                       (const int*)C.chunks, C.nchunks, (const uint8_t*)C.flags, int(C.sy), int(C.sz),
+                       C.nl, (const uint8_t*)C.flags, int(C.sy), int(C.sz),
                        int(A.sy), int(A.sz), A.nx, A.ny, A.nz, (const T*)A.r, C.b, sc);
     CHECK_LAUNCH();
   }
@@ -1158,7 +1188,7 @@ int vcycle(ibfe_ctx& c, std::vector<MGDev<T>>& lv, const T* r0, T* z0, const KSc
                          (const int64_t*)C.ids, (const T*)C.inv, b, cur[L - 1], sc);
       if (L == 1) {
         np = red_blocks(C.nchunks);
-        hipLaunchKernelGGL(k_mg_dot<T>, dim3(np), dim3(kBlock), 0, c.stream, (const int*)C.chunks, C.nchunks,
+        hipLaunchKernelGGL(k_mg_dot<T>, dim3(np), dim3(kBlock), 0, c.stream, C.nl,
                            (const uint8_t*)C.flags, b, (const T*)z0, c.partials, sc);
       }
       CHECK_LAUNCH();
@@ -1170,7 +1200,7 @@ int vcycle(ibfe_ctx& c, std::vector<MGDev<T>>& lv, const T* r0, T* z0, const KSc
     const MGDev<T>& A = lv[l];
     const MGDev<T>& C = lv[l + 1];
     hipLaunchKernelGGL(k_mg_prolong<T>, dim3(blocks_for(A.nchunks)), dim3(kBlock), 0, c.stream,
-                       (const int*)A.chunks, A.nchunks, (const uint8_t*)A.flags, int(A.sy), int(A.sz),
+                       A.nl, (const uint8_t*)A.flags, int(A.sy), int(A.sz),
                        int(C.sy), int(C.sz), (const T*)cur[l + 1], cur[l], sc);
     CHECK_LAUNCH();
     const T* b = l == 0 ? r0 : A.b;
@@ -1189,15 +1219,14 @@ int run_pcg_mg(ibfe_ctx& c, const Op& op, std::vector<MGDev<T>>& lv, const T* b,
   KScal* sc = &c.scal[slot];
   const KScal* csc = sc;
   int rc, np = 0;
-  hipLaunchKernelGGL(k_mgcg_init<T>, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.chunks, c.nchunks,
+  hipLaunchKernelGGL(k_mgcg_init<T>, dim3(nr), dim3(kBlock), 0, c.stream, c.nl,
                      (const uint8_t*)c.flags, b, x, r, c.partials);
   hipLaunchKernelGGL(k_fin_mgcg_init, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr, sc,
                      rtol * rtol, max_iters);
   CHECK_LAUNCH();
   if ((rc = vcycle<T>(c, lv, r, z, csc, np))) return rc;
   hipLaunchKernelGGL(k_fin_mgcg_rz, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, np, sc, 1);
-  hipLaunchKernelGGL(k_mgcg_p<T>, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream, (const int*)c.chunks,
-                     c.nchunks, (const uint8_t*)c.flags, (const T*)z, p, csc);
+  hipLaunchKernelGGL(k_mgcg_p<T>, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream, c.nl, (const uint8_t*)c.flags, (const T*)z, p, csc);
   CHECK_LAUNCH();
   int launched = 0;
   KScal s{};
@@ -1209,9 +1238,9 @@ int run_pcg_mg(ibfe_ctx& c, const Op& op, std::vector<MGDev<T>>& lv, const T* b,
         if (timed && timer_events(c, size_t(launched + k), e0, e1)) return IBFE_EHIP;
         int rc2;
         if ((rc2 = pre_apply(c, op, p, csc))) return rc2;
-        const int nq = launch_q<T>(c, op, c.chunks, c.nchunks, (const T*)p, q, csc, e0, e1);
+        const int nq = launch_q<T>(c, op, c.nl, (const T*)p, q, csc, e0, e1);
         hipLaunchKernelGGL(k_fin_cg_q, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nq, sc);
-        hipLaunchKernelGGL(k_mgcg_xr<T>, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.chunks, c.nchunks,
+        hipLaunchKernelGGL(k_mgcg_xr<T>, dim3(nr), dim3(kBlock), 0, c.stream, c.nl,
                            (const uint8_t*)c.flags, x, r, (const T*)p, (const T*)q, c.partials, csc);
         hipLaunchKernelGGL(k_fin_mgcg_xr, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr,
                            sc);
@@ -1220,7 +1249,7 @@ int run_pcg_mg(ibfe_ctx& c, const Op& op, std::vector<MGDev<T>>& lv, const T* b,
         hipLaunchKernelGGL(k_fin_mgcg_rz, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, np,
                            sc, 0);
         hipLaunchKernelGGL(k_mgcg_p<T>, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
-                           (const int*)c.chunks, c.nchunks, (const uint8_t*)c.flags, (const T*)z, p, csc);
+                           c.nl, (const uint8_t*)c.flags, (const T*)z, p, csc);
         CHECK_LAUNCH();
       }
       return IBFE_OK;
@@ -1280,7 +1309,7 @@ int run_cheb_mass(ibfe_ctx& c, const T* b, T* x, T* xalt, T* d, int iters) {
   T* cur = ((iters - 1) % 2 == 0) ? x : xalt;
   T* alt = cur == x ? xalt : x;
   hipLaunchKernelGGL((k_mg_cheb0<T, 3>), dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
-                     (const int*)c.chunks, c.nchunks, (const uint8_t*)c.emask, (const uint8_t*)c.flags,
+                     c.nl, (const uint8_t*)c.emask, (const uint8_t*)c.flags,
                      T(c.fc.m[0]), T(1.0 / theta), b, d, cur, (const KScal*)nullptr, kFlagF, c.stride);
   const int nr = red_blocks(c.nzitems);
   T* const cur0 = cur;
@@ -1329,8 +1358,7 @@ int build_s1(ibfe_ctx& c) {
   const double rdt = P.params.rho / P.params.dt, mu = P.params.mu;
   double cm[4];
   for (int t = 0; t < 4; ++t) cm[t] = rdt * c.fc.m[t] + mu * c.fc.k[t];
-  hipLaunchKernelGGL(k_s1_build, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream, c.chunks,
-                     c.nchunks, c.emask, c.flags, c.u, c.stride, int(P.sy), int(P.sz), P.h, cm[0], cm[1],
+  hipLaunchKernelGGL(k_s1_build, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream, c.nl, c.emask, c.flags, c.u, c.stride, int(P.sy), int(P.sz), P.h, cm[0], cm[1],
                      cm[2], cm[3], P.params.rho, c.coef64, c.coef32, 1, kFlagP);
   CHECK_LAUNCH();
   return IBFE_OK;
@@ -1347,7 +1375,7 @@ int s1_explicit(ibfe_ctx& c) {
   const int64_t S = c.stride;
   double* b1 = c.w[8];
   double* x1 = c.w[9];
-  hipLaunchKernelGGL(k_s1_build, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.emask, c.flags,
+  hipLaunchKernelGGL(k_s1_build, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.emask, c.flags,
                      c.u, S, int(P.sy), int(P.sz), P.h, 0.0, 0.0, 0.0, 0.0, rho, c.coef64, (float*)nullptr, 1,
                      kFlagP);
   double cm[4], ca[4];
@@ -1355,10 +1383,10 @@ int s1_explicit(ibfe_ctx& c) {
     cm[t] = rdt * c.fc.m[t];
     ca[t] = rdt * c.fc.m[t] + mu * c.fc.k[t];
   }
-  hipLaunchKernelGGL(k_s1_rhs_explicit, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.emask,
+  hipLaunchKernelGGL(k_s1_rhs_explicit, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.emask,
                      c.flags, c.coef64, c.u, c.p, c.g, b1, S, int(P.sy), int(P.sz), cm[0], cm[1], cm[2], cm[3],
                      ca[0], ca[1], ca[2], ca[3], c.fc.g2[0], c.fc.g2[1], c.fc.g2[2]);
-  hipLaunchKernelGGL((k_masked_copy<double, double>), dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks,
+  hipLaunchKernelGGL((k_masked_copy<double, double>), dim3(nb), dim3(kBlock), 0, c.stream, c.nl,
                      c.flags, kFlagF, c.u, x1, 3, S);
   CHECK_LAUNCH();
   auto op = sym_op<double, 3>(c, ca, kFlagF);
@@ -1370,11 +1398,11 @@ int s1_explicit(ibfe_ctx& c) {
     float* const* v = c.v32;
     rc = run_refined(c, op, kFlagF, 3, b1, x1, v[8], v[9], P.params.rtol, so,
                      [&](const float* r32, float* d32, double tol, SolveOut& o) {
-                       return run_cg<float>(c, op32, c.chunks, c.nchunks, r32, d32, v[0], v[1], v[2], kScS1, tol,
+                       return run_cg<float>(c, op32, c.nl, r32, d32, v[0], v[1], v[2], kScS1, tol,
                                             maxit, true, o);
                      });
   } else {
-    rc = run_cg<double>(c, op, c.chunks, c.nchunks, b1, x1, c.w[0], c.w[1], c.w[2], kScS1, P.params.rtol,
+    rc = run_cg<double>(c, op, c.nl, b1, x1, c.w[0], c.w[1], c.w[2], kScS1, P.params.rtol,
                         maxit, false, so);
   }
   if (rc) return rc;
@@ -1387,11 +1415,11 @@ int s1_explicit(ibfe_ctx& c) {
 int remove_slot_means(ibfe_ctx& c, double* x) {
   const Plan& P = c.plan;
   const int nr = red_blocks(c.nchunks);
-  hipLaunchKernelGGL(k_slot_sum, dim3(nr), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.slot,
+  hipLaunchKernelGGL(k_slot_sum, dim3(nr), dim3(kBlock), 0, c.stream, c.nl, c.slot,
                      (const double*)x, c.partials);
   hipLaunchKernelGGL(k_fin_slot, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr,
                      P.n_floating, (const double*)c.float_count, c.float_means);
-  hipLaunchKernelGGL(k_slot_sub, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks,
+  hipLaunchKernelGGL(k_slot_sub, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream, c.nl,
                      c.slot, x, (const double*)c.float_means);
   CHECK_LAUNCH();
   return IBFE_OK;
@@ -1431,12 +1459,11 @@ int step_once(ibfe_ctx& c) {
     if ((rc = build_s1(c))) return rc;
     double cm[4];
     for (int t = 0; t < 4; ++t) cm[t] = rho / dt * c.fc.m[t];
-    hipLaunchKernelGGL(k_s1_rhs, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.emask,
+    hipLaunchKernelGGL(k_s1_rhs, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.emask,
                        c.flags, c.coef64, c.u, c.p, c.g, b1, S, sy, sz, cm[0], cm[1], cm[2], cm[3],
                        c.fc.g2[0], c.fc.g2[1], c.fc.g2[2]);
     CHECK_LAUNCH();
-    hipLaunchKernelGGL((k_masked_copy<double, double>), dim3(nb), dim3(kBlock), 0, c.stream, c.chunks,
-                       c.nchunks, c.flags, kFlagF, c.u, x1, 3, S);
+    hipLaunchKernelGGL((k_masked_copy<double, double>), dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.flags, kFlagF, c.u, x1, 3, S);
     CHECK_LAUNCH();
     auto op = stencil_op<double>(c, c.coef64, kFlagF);
     SolveOut so;
@@ -1444,8 +1471,7 @@ int step_once(ibfe_ctx& c) {
       auto op32 = stencil_op<float>(c, c.coef32, kFlagF);
       rc = run_refined(c, op, kFlagF, 3, b1, x1, c.v32[8], c.v32[9], rtol, so,
                        [&](const float* r32, float* d32, double tol, SolveOut& o) {
-                         hipLaunchKernelGGL(k_zero<float>, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks,
-                                            c.nchunks, d32, 3, S);
+                         hipLaunchKernelGGL(k_zero<float>, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, d32, 3, S);
                          return run_bicgstab<float>(c, op32, r32, d32, c.v32, kScS1, tol, maxit, o);
                        });
     } else {
@@ -1456,12 +1482,12 @@ int step_once(ibfe_ctx& c) {
     c.stats.s1_res = so.res;
     c.stats.s1_outer = so.outer;
   }
-  hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, 1.0, x1, 1.0, c.g,
+  hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, x1, 1.0, c.g,
                      c.ustar, 3, S);
   CHECK_LAUNCH();
 
   // 2.-4. BCE-IB correction: G Lambda = U_B - I u*, u_ib = u* + I_F^T Lambda (FP64)
-  hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, 1.0, c.ustar,
+  hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, c.ustar,
                      0.0, c.ustar, c.uib, 3, S);
   CHECK_LAUNCH();
   c.stats.ib_iters = 0;
@@ -1473,7 +1499,7 @@ int step_once(ibfe_ctx& c) {
     CHECK_LAUNCH();
     auto op = gram_op(c);
     SolveOut so;
-    if ((rc = run_cg<double>(c, op, c.ib_chunks, c.ib_nchunks, c.ibv[0], c.ibv[1], c.ibv[2], c.ibv[3],
+    if ((rc = run_cg<double>(c, op, c.ib_nl, c.ibv[0], c.ibv[1], c.ibv[2], c.ibv[3],
                              c.ibv[4], kScIB, P.params.ib_rtol, maxit, true, so)))
       return rc;
     c.stats.ib_iters = so.iters;
@@ -1487,7 +1513,7 @@ int step_once(ibfe_ctx& c) {
   // 5. pressure increment: K_{P'P'} Phi = -(rho/dt) (B u_ib)_{P'}
   double* b3 = c.w[8];
   {
-    hipLaunchKernelGGL(k_div, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.emask, c.flags,
+    hipLaunchKernelGGL(k_div, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.emask, c.flags,
                        kFlagPp, 0u, c.uib, b3, S, sy, sz, c.fc.g2[0], c.fc.g2[1], c.fc.g2[2], -rho / dt);
     CHECK_LAUNCH();
     if (P.n_floating > 0 && (rc = remove_slot_means(c, b3))) return rc;
@@ -1497,7 +1523,7 @@ int step_once(ibfe_ctx& c) {
     const bool mg = P.params.precond >= 1;  // multigrid or Chebyshev (one level)
     if (mixed) {
       auto op32 = sym_op<float, 1>(c, kc, kFlagPp);
-      hipLaunchKernelGGL(k_zero<double>, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.phi, 1,
+      hipLaunchKernelGGL(k_zero<double>, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.phi, 1,
                          S);
       float* const* v = c.v32;
       rc = run_refined(c, op, kFlagPp, 1, b3, c.phi, v[8], v[9], rtol, so,
@@ -1505,14 +1531,14 @@ int step_once(ibfe_ctx& c) {
                          if (mg)
                            return run_pcg_mg<float>(c, op32, c.mg32, r32, d32, v[0], v[1], v[2], v[3], kScS3,
                                                     tol, maxit, o, c.timing);
-                         return run_cg<float>(c, op32, c.chunks, c.nchunks, r32, d32, v[0], v[1], v[2], kScS3,
+                         return run_cg<float>(c, op32, c.nl, r32, d32, v[0], v[1], v[2], kScS3,
                                               tol, maxit, true, o, c.timing);
                        });
     } else if (mg) {
       rc = run_pcg_mg<double>(c, op, c.mg64, b3, c.phi, c.w[0], c.w[1], c.w[2], c.w[3], kScS3, rtol, maxit,
                               so, c.timing);
     } else {
-      rc = run_cg<double>(c, op, c.chunks, c.nchunks, b3, c.phi, c.w[0], c.w[1], c.w[2], kScS3, rtol, maxit,
+      rc = run_cg<double>(c, op, c.nl, b3, c.phi, c.w[0], c.w[1], c.w[2], kScS3, rtol, maxit,
                           true, so, c.timing);
     }
     if (rc) return rc;
@@ -1526,13 +1552,13 @@ int step_once(ibfe_ctx& c) {
   {
     double* b4 = c.w[8];
     double* delta = c.w[9];
-    hipLaunchKernelGGL(k_grad, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.emask, c.flags,
+    hipLaunchKernelGGL(k_grad, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.emask, c.flags,
                        kFlagF, c.phi, b4, S, sy, sz, c.fc.g2[0], c.fc.g2[1], c.fc.g2[2]);
     CHECK_LAUNCH();
     const double mc[4] = {c.fc.m[0], c.fc.m[1], c.fc.m[2], c.fc.m[3]};
     auto op = sym_op<double, 3>(c, mc, kFlagF);
     SolveOut so;
-    hipLaunchKernelGGL(k_zero<double>, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, delta, 3, S);
+    hipLaunchKernelGGL(k_zero<double>, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, delta, 3, S);
     if (mixed) {
       float* const* v = c.v32;
       rc = run_refined(c, op, kFlagF, 3, b4, delta, v[8], v[9], rtol, so,
@@ -1552,7 +1578,7 @@ int step_once(ibfe_ctx& c) {
         if (so.res <= rtol || sweep == 4) break;
         const int it = mass_cheb_steps(std::max(rtol / std::max(so.res, 1e-300), 1e-15));
         if ((rc = run_cheb_mass<double>(c, (const double*)r64, c.w[0], c.w[1], c.w[2], it))) return rc;
-        hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, 1.0, delta, 1.0,
+        hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, delta, 1.0,
                            c.w[0], delta, 3, S);
         CHECK_LAUNCH();
         so.iters += it;
@@ -1564,9 +1590,9 @@ int step_once(ibfe_ctx& c) {
     c.stats.s4_iters = so.iters;
     c.stats.s4_res = so.res;
     c.stats.s4_outer = so.outer;
-    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, 1.0, c.uib,
+    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, c.uib,
                        -dt / rho, delta, c.u_next, 3, S);
-    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, 1.0, c.p, 1.0,
+    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, c.p, 1.0,
                        c.phi, c.p_next, 1, S);
     CHECK_LAUNCH();
   }
@@ -1591,10 +1617,10 @@ int build_s1_refined(ibfe_ctx& c) {
   }
   const int nb = blocks_for(c.nchunks);
   const int64_t S = c.stride;
-  hipLaunchKernelGGL(k_s1_build, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.emask, c.flags,
+  hipLaunchKernelGGL(k_s1_build, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.emask, c.flags,
                      c.u, S, int(P.sy), int(P.sz), P.h, cf[0], cf[1], cf[2], cf[3], P.params.rho, c.coef64,
                      c.coef32, 1, kFlagP | kFlagHang);
-  hipLaunchKernelGGL(k_s1_build, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.cmask, c.flags,
+  hipLaunchKernelGGL(k_s1_build, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.cmask, c.flags,
                      c.u, S, int(P.sy), int(P.sz), P.hb, cc[0], cc[1], cc[2], cc[3], P.params.rho,
                      c.coef64 + 27 * S, c.coef32 ? c.coef32 + 27 * S : nullptr, 2, kFlagP);
   CHECK_LAUNCH();
@@ -1610,10 +1636,10 @@ int s1_explicit_refined(ibfe_ctx& c) {
   const int64_t S = c.stride;
   double* b1 = c.w[8];
   double* x1 = c.w[9];
-  hipLaunchKernelGGL(k_s1_build, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.emask, c.flags,
+  hipLaunchKernelGGL(k_s1_build, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.emask, c.flags,
                      c.u, S, int(P.sy), int(P.sz), P.h, 0.0, 0.0, 0.0, 0.0, rho, c.coef64, (float*)nullptr, 1,
                      kFlagP | kFlagHang);
-  hipLaunchKernelGGL(k_s1_build, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.cmask, c.flags,
+  hipLaunchKernelGGL(k_s1_build, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.cmask, c.flags,
                      c.u, S, int(P.sy), int(P.sz), P.hb, 0.0, 0.0, 0.0, 0.0, rho, c.coef64 + 27 * S,
                      (float*)nullptr, 2, kFlagP);
   CHECK_LAUNCH();
@@ -1626,7 +1652,7 @@ int s1_explicit_refined(ibfe_ctx& c) {
   f.u = c.u;
   f.g = c.g;
   if ((rc = comp_rows<double>(c, f, kFlagF, 0u, 1.0, b1))) return rc;
-  hipLaunchKernelGGL((k_masked_copy<double, double>), dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks,
+  hipLaunchKernelGGL((k_masked_copy<double, double>), dim3(nb), dim3(kBlock), 0, c.stream, c.nl,
                      c.flags, kFlagF, c.u, x1, 3, S);
   CHECK_LAUNCH();
   auto op = csym_op<double, 3>(c, rdt, mu, kFlagF, c.dinvA64);
@@ -1637,11 +1663,11 @@ int s1_explicit_refined(ibfe_ctx& c) {
     float* const* v = c.v32;
     rc = run_refined(c, op, kFlagF, 3, b1, x1, v[8], v[9], P.params.rtol, so,
                      [&](const float* r32, float* d32, double tol, SolveOut& o) {
-                       return run_cg<float>(c, op32, c.chunks, c.nchunks, r32, d32, v[0], v[1], v[2], kScS1, tol,
+                       return run_cg<float>(c, op32, c.nl, r32, d32, v[0], v[1], v[2], kScS1, tol,
                                             maxit, true, o);
                      });
   } else {
-    rc = run_cg<double>(c, op, c.chunks, c.nchunks, b1, x1, c.w[0], c.w[1], c.w[2], kScS1, P.params.rtol,
+    rc = run_cg<double>(c, op, c.nl, b1, x1, c.w[0], c.w[1], c.w[2], kScS1, P.params.rtol,
                         maxit, false, so);
   }
   if (rc) return rc;
@@ -1692,8 +1718,7 @@ int step_once_refined(ibfe_ctx& c) {
     f.u = c.u;
     f.g = c.g;
     if ((rc = comp_rows<double>(c, f, kFlagF, 0u, 1.0, b1))) return rc;
-    hipLaunchKernelGGL((k_masked_copy<double, double>), dim3(nb), dim3(kBlock), 0, c.stream, c.chunks,
-                       c.nchunks, c.flags, kFlagF, c.u, x1, 3, S);
+    hipLaunchKernelGGL((k_masked_copy<double, double>), dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.flags, kFlagF, c.u, x1, 3, S);
     CHECK_LAUNCH();
     auto op = cstencil_op<double>(c, c.coef64, kFlagF);
     SolveOut so;
@@ -1701,8 +1726,7 @@ int step_once_refined(ibfe_ctx& c) {
       auto op32 = cstencil_op<float>(c, c.coef32, kFlagF);
       rc = run_refined(c, op, kFlagF, 3, b1, x1, c.v32[8], c.v32[9], rtol, so,
                        [&](const float* r32, float* d32, double tol, SolveOut& o) {
-                         hipLaunchKernelGGL(k_zero<float>, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks,
-                                            c.nchunks, d32, 3, S);
+                         hipLaunchKernelGGL(k_zero<float>, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, d32, 3, S);
                          return run_bicgstab<float>(c, op32, r32, d32, c.v32, kScS1, tol, maxit, o);
                        });
     } else {
@@ -1713,12 +1737,12 @@ int step_once_refined(ibfe_ctx& c) {
     c.stats.s1_res = so.res;
     c.stats.s1_outer = so.outer;
   }
-  hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, 1.0, x1, 1.0, c.g,
+  hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, x1, 1.0, c.g,
                      c.ustar, 3, S);
   CHECK_LAUNCH();
 
   // 2.-4. BCE-IB correction (every support node is a fine, non-hanging node)
-  hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, 1.0, c.ustar,
+  hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, c.ustar,
                      0.0, c.ustar, c.uib, 3, S);
   CHECK_LAUNCH();
   c.stats.ib_iters = 0;
@@ -1730,7 +1754,7 @@ int step_once_refined(ibfe_ctx& c) {
     CHECK_LAUNCH();
     auto op = gram_op(c);
     SolveOut so;
-    if ((rc = run_cg<double>(c, op, c.ib_chunks, c.ib_nchunks, c.ibv[0], c.ibv[1], c.ibv[2], c.ibv[3],
+    if ((rc = run_cg<double>(c, op, c.ib_nl, c.ibv[0], c.ibv[1], c.ibv[2], c.ibv[3],
                              c.ibv[4], kScIB, P.params.ib_rtol, maxit, true, so)))
       return rc;
     c.stats.ib_iters = so.iters;
@@ -1763,7 +1787,7 @@ int step_once_refined(ibfe_ctx& c) {
     SolveOut so;
     if (mixed) {
       auto op32 = csym_op<float, 1>(c, 0.0, 1.0, kFlagPp, c.dinvK32);
-      hipLaunchKernelGGL(k_zero<double>, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, c.phi, 1,
+      hipLaunchKernelGGL(k_zero<double>, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.phi, 1,
                          S);
       float* const* v = c.v32;
       rc = run_refined(c, op, kFlagPp, 1, b3, c.phi, v[8], v[9], rtol, so,
@@ -1771,14 +1795,14 @@ int step_once_refined(ibfe_ctx& c) {
                          if (mg)
                            return run_pcg_mg<float>(c, op32, c.mg32, r32, d32, v[0], v[1], v[2], v[3], kScS3,
                                                     tol, maxit, o, c.timing);
-                         return run_cg<float>(c, op32, c.chunks, c.nchunks, r32, d32, v[0], v[1], v[2], kScS3,
+                         return run_cg<float>(c, op32, c.nl, r32, d32, v[0], v[1], v[2], kScS3,
                                               tol, maxit, true, o, c.timing);
                        });
     } else if (mg) {
       rc = run_pcg_mg<double>(c, op, c.mg64, b3, c.phi, c.w[0], c.w[1], c.w[2], c.w[3], kScS3, rtol, maxit,
                               so, c.timing);
     } else {
-      rc = run_cg<double>(c, op, c.chunks, c.nchunks, b3, c.phi, c.w[0], c.w[1], c.w[2], kScS3, rtol, maxit,
+      rc = run_cg<double>(c, op, c.nl, b3, c.phi, c.w[0], c.w[1], c.w[2], kScS3, rtol, maxit,
                           true, so, c.timing);
     }
     if (rc) return rc;
@@ -1797,7 +1821,7 @@ int step_once_refined(ibfe_ctx& c) {
     auto op = csym_op<double, 3>(c, 1.0, 0.0, kFlagF, c.dinvM64);
     const double lmin = P.mass_lmin, lmax = kMassLmax;
     SolveOut so;
-    hipLaunchKernelGGL(k_zero<double>, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, delta, 3, S);
+    hipLaunchKernelGGL(k_zero<double>, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, delta, 3, S);
     if (mixed) {
       auto op32 = csym_op<float, 3>(c, 1.0, 0.0, kFlagF, c.dinvM32);
       float* const* v = c.v32;
@@ -1818,7 +1842,7 @@ int step_once_refined(ibfe_ctx& c) {
         const int it = cheb_steps(std::max(rtol / std::max(so.res, 1e-300), 1e-15), lmin, lmax);
         if ((rc = run_cheb_gen<double>(c, op, (const double*)r64, c.w[0], c.w[1], c.w[2], it, lmin, lmax)))
           return rc;
-        hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, 1.0, delta, 1.0,
+        hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, delta, 1.0,
                            c.w[0], delta, 3, S);
         CHECK_LAUNCH();
         so.iters += it;
@@ -1830,9 +1854,9 @@ int step_once_refined(ibfe_ctx& c) {
     c.stats.s4_iters = so.iters;
     c.stats.s4_res = so.res;
     c.stats.s4_outer = so.outer;
-    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, 1.0, c.uib,
+    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, c.uib,
                        -dt / rho, delta, c.u_next, 3, S);
-    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.chunks, c.nchunks, 1.0, c.p, 1.0,
+    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, c.p, 1.0,
                        c.phi, c.p_next, 1, S);
     CHECK_LAUNCH();
   }
@@ -1875,14 +1899,12 @@ int apply_refined(ibfe_ctx& C, int op, int precision, double* xin, double* yout,
       if ((rc = ensure_fp32_work(C))) return rc;
       float* x32 = C.v32[0];
       float* y32 = C.v32[1];
-      hipLaunchKernelGGL((k_masked_copy<double, float>), dim3(nb), dim3(kBlock), 0, C.stream, C.chunks,
-                         C.nchunks, C.flags, kFlagP, xin, x32, 1, S);
+      hipLaunchKernelGGL((k_masked_copy<double, float>), dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, xin, x32, 1, S);
       CHECK_LAUNCH();
       if ((rc = fill_hanging<float>(C, x32, 1))) return rc;
       auto o = csym_op<float, 1>(C, a, b, kFlagP, C.dinvM32);
       if ((rc = comp_rows<float>(C, OpElem<float, OpCSym<float, 1>>{o, x32}, kFlagP, 0u, 1.0f, y32))) return rc;
-      hipLaunchKernelGGL((k_masked_copy<float, double>), dim3(nb), dim3(kBlock), 0, C.stream, C.chunks,
-                         C.nchunks, C.flags, kFlagP, y32, yout, 1, S);
+      hipLaunchKernelGGL((k_masked_copy<float, double>), dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, y32, yout, 1, S);
       CHECK_LAUNCH();
       return IBFE_OK;
     }
@@ -1921,15 +1943,13 @@ int apply_refined(ibfe_ctx& C, int op, int precision, double* xin, double* yout,
       }
       float* x32 = C.v32[0];
       float* y32 = C.v32[1];
-      hipLaunchKernelGGL((k_masked_copy<double, float>), dim3(nb), dim3(kBlock), 0, C.stream, C.chunks,
-                         C.nchunks, C.flags, kFlagP, xin, x32, 3, S);
+      hipLaunchKernelGGL((k_masked_copy<double, float>), dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, xin, x32, 3, S);
       CHECK_LAUNCH();
       if ((rc = fill_hanging<float>(C, x32, 3))) return rc;
       auto o = cstencil_op<float>(C, C.coef32, kFlagP);
       if ((rc = comp_rows<float>(C, OpElem<float, OpCStencil<float, 3>>{o, x32}, kFlagP, 0u, 1.0f, y32)))
         return rc;
-      hipLaunchKernelGGL((k_masked_copy<float, double>), dim3(nb), dim3(kBlock), 0, C.stream, C.chunks,
-                         C.nchunks, C.flags, kFlagP, y32, yout, 3, S);
+      hipLaunchKernelGGL((k_masked_copy<float, double>), dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, y32, yout, 3, S);
       CHECK_LAUNCH();
       return IBFE_OK;
     }
@@ -2170,29 +2190,27 @@ int ibfe_apply(ibfe_ctx* c, int op, int precision, const double* x, double* y, i
       if (precision == 0) {
         auto o = sym_op<double, 1>(C, cf, kFlagP);
         hipLaunchKernelGGL((k_apply<double, 1, OpSym<double, 1>>), dim3(nb), dim3(kBlock), 0, C.stream,
-                           C.chunks, C.nchunks, o, xin, yout);
+                           C.nl, o, xin, yout);
       } else {
         if ((rc = ensure_fp32_work(C))) return rc;
         float* x32 = C.v32[0];
         float* y32 = C.v32[1];
-        hipLaunchKernelGGL((k_masked_copy<double, float>), dim3(nb), dim3(kBlock), 0, C.stream, C.chunks,
-                           C.nchunks, C.flags, kFlagP, xin, x32, 1, S);
+        hipLaunchKernelGGL((k_masked_copy<double, float>), dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, xin, x32, 1, S);
         auto o = sym_op<float, 1>(C, cf, kFlagP);
         hipLaunchKernelGGL((k_apply<float, 1, OpSym<float, 1>>), dim3(nb), dim3(kBlock), 0, C.stream,
-                           C.chunks, C.nchunks, o, x32, y32);
-        hipLaunchKernelGGL((k_masked_copy<float, double>), dim3(nb), dim3(kBlock), 0, C.stream, C.chunks,
-                           C.nchunks, C.flags, kFlagP, y32, yout, 1, S);
+                           C.nl, o, x32, y32);
+        hipLaunchKernelGGL((k_masked_copy<float, double>), dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, y32, yout, 1, S);
       }
       CHECK_LAUNCH();
       return copy_out(C, yout, 1, y, on_device);
     }
     case IBFE_OP_GRAD:
-      hipLaunchKernelGGL(k_grad, dim3(nb), dim3(kBlock), 0, C.stream, C.chunks, C.nchunks, C.emask, C.flags,
+      hipLaunchKernelGGL(k_grad, dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.emask, C.flags,
                          kFlagP, xin, yout, S, sy, sz, C.fc.g2[0], C.fc.g2[1], C.fc.g2[2]);
       CHECK_LAUNCH();
       return copy_out(C, yout, 3, y, on_device);
     case IBFE_OP_DIV:
-      hipLaunchKernelGGL(k_div, dim3(nb), dim3(kBlock), 0, C.stream, C.chunks, C.nchunks, C.emask, C.flags,
+      hipLaunchKernelGGL(k_div, dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.emask, C.flags,
                          kFlagP, 0u, xin, yout, S, sy, sz, C.fc.g2[0], C.fc.g2[1], C.fc.g2[2], 1.0);
       CHECK_LAUNCH();
       return copy_out(C, yout, 1, y, on_device);
@@ -2208,17 +2226,15 @@ int ibfe_apply(ibfe_ctx* c, int op, int precision, const double* x, double* y, i
       if (precision == 0) {
         auto o = stencil_op<double>(C, C.coef64, kFlagP);
         hipLaunchKernelGGL((k_apply<double, 3, OpStencil<double, 3>>), dim3(nb), dim3(kBlock), 0, C.stream,
-                           C.chunks, C.nchunks, o, xin, yout);
+                           C.nl, o, xin, yout);
       } else {
         float* x32 = C.v32[0];
         float* y32 = C.v32[1];
-        hipLaunchKernelGGL((k_masked_copy<double, float>), dim3(nb), dim3(kBlock), 0, C.stream, C.chunks,
-                           C.nchunks, C.flags, kFlagP, xin, x32, 3, S);
+        hipLaunchKernelGGL((k_masked_copy<double, float>), dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, xin, x32, 3, S);
         auto o = stencil_op<float>(C, c32, kFlagP);
         hipLaunchKernelGGL((k_apply<float, 3, OpStencil<float, 3>>), dim3(nb), dim3(kBlock), 0, C.stream,
-                           C.chunks, C.nchunks, o, x32, y32);
-        hipLaunchKernelGGL((k_masked_copy<float, double>), dim3(nb), dim3(kBlock), 0, C.stream, C.chunks,
-                           C.nchunks, C.flags, kFlagP, y32, yout, 3, S);
+                           C.nl, o, x32, y32);
+        hipLaunchKernelGGL((k_masked_copy<float, double>), dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, y32, yout, 3, S);
       }
       CHECK_LAUNCH();
       return copy_out(C, yout, 3, y, on_device);

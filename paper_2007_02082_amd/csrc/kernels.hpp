@@ -3,10 +3,12 @@
 // Data layout: every nodal field is a dense array over all grid nodes (id
 // n = i + sy j + sz k), offset by a zero halo so that the 27 neighbours of any
 // node are addressable without bounds checks; base pointers passed to kernels
-// point at node 0.  Work is distributed over a list of 64-node chunks that
-// contain at least one node of P; a wavefront owns one chunk, so every load
-// and store of a chunk is one coalesced 256/512-byte transaction.  Multi-
-// component fields are `nc` planes of `stride` values.
+// point at node 0.  Work is distributed over a node list (NodeList): either
+// 64-node chunks that contain at least one active node (a wavefront owns one
+// chunk, so every load and store of a chunk is one coalesced 256/512-byte
+// transaction), or, where the active nodes fill their chunks sparsely (thin
+// vessels on a large box), the active nodes themselves, 64 per wavefront in
+// ascending order.  Multi-component fields are `nc` planes of `stride` values.
 //
 // Matrix-free Q1 operators on a uniform grid: within one cube the entry
 // between nodes i and j = i + o depends only on o, and the assembled entry is
@@ -38,6 +40,22 @@ __device__ __forceinline__ int xcd_block() {
   return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
 }
 
+// Nodes of a launch, one 64-lane group per wavefront trip.  With per_lane = 0
+// group c is the chunk ids[c] (node = 64 ids[c] + lane); with per_lane = 1 it
+// is ids[64 c .. 64 c + 63], ascending, the last group padded with a node that
+// is in no set (flags 0, no cells, no floating slot).  Every kernel treats such
+// a node as a non-row; padding lanes only ever store zeros there.
+struct NodeList {
+  const int* ids = nullptr;
+  int n = 0;
+  int per_lane = 0;
+  __device__ __forceinline__ int node(int c) const {
+    const int l = int(threadIdx.x & 63);
+    const int v = ids[per_lane ? c * 64 + l : c];
+    return per_lane ? v : v * 64 + l;
+  }
+};
+
 // Contiguous range of chunks [c0, c1) owned by this block; each wavefront
 // walks it with stride kWaves (one 64-node chunk per wavefront per trip).
 struct ChunkRange {
@@ -50,11 +68,11 @@ __device__ __forceinline__ ChunkRange block_chunks(int nchunks) {
   return {c0, c0 + per + (b < rem ? 1 : 0)};
 }
 
-// Node of the one-node-per-thread kernels (grid = ceil(nchunks / kWaves)), or -1.
-__device__ __forceinline__ int chunk_node(const int* __restrict__ chunks, int nchunks) {
+// Node of the one-node-per-thread kernels (grid = ceil(nl.n / kWaves)), or -1.
+__device__ __forceinline__ int chunk_node(const NodeList& nl) {
   const int c = xcd_block() * kWaves + int(threadIdx.x >> 6);
-  if (c >= nchunks) return -1;
-  return chunks[c] * 64 + int(threadIdx.x & 63);
+  if (c >= nl.n) return -1;
+  return nl.node(c);
 }
 
 // ---------------------------------------------------------------------------
@@ -338,15 +356,15 @@ __device__ __forceinline__ bool bad(double v) { return !(v == v) || v - v != 0.0
 
 // r = b - A x (x = 0 if zero_guess); p = D^-1 r; partials: r.p, r.r, b.b
 template <typename T, class Op>
-__global__ __launch_bounds__(kBlock) void k_cg_init(const int* __restrict__ chunks, int nchunks,
+__global__ __launch_bounds__(kBlock) void k_cg_init(NodeList nl,
                                                     Op op, const T* __restrict__ b, T* __restrict__ x,
                                                     T* __restrict__ r, T* __restrict__ p,
                                                     double* __restrict__ partials, int zero_guess) {
   constexpr int NC = Op::kNC;
   double v[3] = {0.0, 0.0, 0.0};
-  const ChunkRange cr = block_chunks(nchunks);
+  const ChunkRange cr = block_chunks(nl.n);
   for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
-    const int n = chunks[c] * 64 + int(threadIdx.x & 63);
+    const int n = nl.node(c);
     const bool rw = op.row(n);
     T ax[NC];
     if (!zero_guess && rw) op.apply(n, x, ax);
@@ -389,15 +407,15 @@ __global__ __launch_bounds__(kBlock) void k_fin_cg_init(const double* __restrict
 
 // q = A p; partial p.q
 template <typename T, class Op>
-__global__ __launch_bounds__(kBlock) void k_cg_q(const int* __restrict__ chunks, int nchunks, Op op,
+__global__ __launch_bounds__(kBlock) void k_cg_q(NodeList nl, Op op,
                                                  const T* __restrict__ p, T* __restrict__ q,
                                                  double* __restrict__ partials, const KScal* sc) {
   if (sc->done) return;
   constexpr int NC = Op::kNC;
   double v[1] = {0.0};
-  const ChunkRange cr = block_chunks(nchunks);
+  const ChunkRange cr = block_chunks(nl.n);
   for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
-    const int n = chunks[c] * 64 + int(threadIdx.x & 63);
+    const int n = nl.node(c);
     T y[NC];
     const bool rw = op.row(n);
     if (rw) op.apply(n, p, y);
@@ -431,7 +449,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_cg_q(const double* __restrict__ 
 
 // x += alpha p; r -= alpha q; partials r.D^-1 r, r.r
 template <typename T, class Op>
-__global__ __launch_bounds__(kBlock) void k_cg_xr(const int* __restrict__ chunks, int nchunks, Op op,
+__global__ __launch_bounds__(kBlock) void k_cg_xr(NodeList nl, Op op,
                                                   T* __restrict__ x, T* __restrict__ r,
                                                   const T* __restrict__ p, const T* __restrict__ q,
                                                   double* __restrict__ partials, const KScal* sc) {
@@ -439,9 +457,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_xr(const int* __restrict__ chunks
   constexpr int NC = Op::kNC;
   const T alpha = T(sc->alpha);
   double v[2] = {0.0, 0.0};
-  const ChunkRange cr = block_chunks(nchunks);
+  const ChunkRange cr = block_chunks(nl.n);
   for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
-    const int n = chunks[c] * 64 + int(threadIdx.x & 63);
+    const int n = nl.node(c);
     if (op.row(n)) {
       const T di = op.inv_diag(n);
 #pragma unroll
@@ -480,15 +498,15 @@ __global__ __launch_bounds__(kBlock) void k_fin_cg_xr(const double* __restrict__
 
 // p = D^-1 r + beta p
 template <typename T, class Op>
-__global__ __launch_bounds__(kBlock) void k_cg_p(const int* __restrict__ chunks, int nchunks, Op op,
+__global__ __launch_bounds__(kBlock) void k_cg_p(NodeList nl, Op op,
                                                  const T* __restrict__ r, T* __restrict__ p,
                                                  const KScal* sc) {
   if (sc->done) return;
   constexpr int NC = Op::kNC;
   const T beta = T(sc->beta);
-  const ChunkRange cr = block_chunks(nchunks);
+  const ChunkRange cr = block_chunks(nl.n);
   for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
-    const int n = chunks[c] * 64 + int(threadIdx.x & 63);
+    const int n = nl.node(c);
     if (op.row(n)) {
       const T di = op.inv_diag(n);
 #pragma unroll
@@ -506,16 +524,16 @@ __global__ __launch_bounds__(kBlock) void k_cg_p(const int* __restrict__ chunks,
 
 // r = b - A x, rhat = r, p = v = 0; partials r.r, b.b
 template <typename T, class Op>
-__global__ __launch_bounds__(kBlock) void k_bi_init(const int* __restrict__ chunks, int nchunks, Op op,
+__global__ __launch_bounds__(kBlock) void k_bi_init(NodeList nl, Op op,
                                                     const T* __restrict__ b, const T* __restrict__ x,
                                                     T* __restrict__ r, T* __restrict__ rhat,
                                                     T* __restrict__ p, T* __restrict__ v,
                                                     double* __restrict__ partials) {
   constexpr int NC = Op::kNC;
   double s[2] = {0.0, 0.0};
-  const ChunkRange cr = block_chunks(nchunks);
+  const ChunkRange cr = block_chunks(nl.n);
   for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
-    const int n = chunks[c] * 64 + int(threadIdx.x & 63);
+    const int n = nl.node(c);
     const bool rw = op.row(n);
     T ax[NC];
     if (rw) op.apply(n, x, ax);
@@ -559,7 +577,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_bi_init(const double* __restrict
 
 // p = r + beta (p - omega v), phat = D^-1 p
 template <typename T, class Op>
-__global__ __launch_bounds__(kBlock) void k_bi_p(const int* __restrict__ chunks, int nchunks, Op op,
+__global__ __launch_bounds__(kBlock) void k_bi_p(NodeList nl, Op op,
                                                  const T* __restrict__ r, T* __restrict__ p,
                                                  const T* __restrict__ v, T* __restrict__ phat,
                                                  const KScal* sc) {
@@ -567,9 +585,9 @@ __global__ __launch_bounds__(kBlock) void k_bi_p(const int* __restrict__ chunks,
   constexpr int NC = Op::kNC;
   const T beta = T((sc->rho / sc->rho_old) * (sc->alpha / sc->omega));
   const T omega = T(sc->omega);
-  const ChunkRange cr = block_chunks(nchunks);
+  const ChunkRange cr = block_chunks(nl.n);
   for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
-    const int n = chunks[c] * 64 + int(threadIdx.x & 63);
+    const int n = nl.node(c);
     if (op.row(n)) {
       const T di = op.inv_diag(n);
 #pragma unroll
@@ -588,16 +606,16 @@ __global__ __launch_bounds__(kBlock) void k_bi_p(const int* __restrict__ chunks,
 
 // y = A xin; partials w.y (and y.y for MODE 1)
 template <typename T, class Op, int MODE>
-__global__ __launch_bounds__(kBlock) void k_bi_apply(const int* __restrict__ chunks, int nchunks, Op op,
+__global__ __launch_bounds__(kBlock) void k_bi_apply(NodeList nl, Op op,
                                                      const T* __restrict__ xin, T* __restrict__ y,
                                                      const T* __restrict__ w,
                                                      double* __restrict__ partials, const KScal* sc) {
   if (sc->done) return;
   constexpr int NC = Op::kNC;
   double s[2] = {0.0, 0.0};
-  const ChunkRange cr = block_chunks(nchunks);
+  const ChunkRange cr = block_chunks(nl.n);
   for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
-    const int n = chunks[c] * 64 + int(threadIdx.x & 63);
+    const int n = nl.node(c);
     const bool rw = op.row(n);
     T ay[NC];
     if (rw) op.apply(n, xin, ay);
@@ -643,16 +661,16 @@ __global__ __launch_bounds__(kBlock) void k_fin_bi_apply(const double* __restric
 
 // s = r - alpha v, shat = D^-1 s
 template <typename T, class Op>
-__global__ __launch_bounds__(kBlock) void k_bi_s(const int* __restrict__ chunks, int nchunks, Op op,
+__global__ __launch_bounds__(kBlock) void k_bi_s(NodeList nl, Op op,
                                                  const T* __restrict__ r, const T* __restrict__ v,
                                                  T* __restrict__ s, T* __restrict__ shat,
                                                  const KScal* sc) {
   if (sc->done) return;
   constexpr int NC = Op::kNC;
   const T alpha = T(sc->alpha);
-  const ChunkRange cr = block_chunks(nchunks);
+  const ChunkRange cr = block_chunks(nl.n);
   for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
-    const int n = chunks[c] * 64 + int(threadIdx.x & 63);
+    const int n = nl.node(c);
     if (op.row(n)) {
       const T di = op.inv_diag(n);
 #pragma unroll
@@ -674,7 +692,7 @@ __global__ __launch_bounds__(kBlock) void k_bi_s(const int* __restrict__ chunks,
 
 // x += alpha phat + omega shat; r = s - omega t; partials rhat.r, r.r
 template <typename T, class Op>
-__global__ __launch_bounds__(kBlock) void k_bi_x(const int* __restrict__ chunks, int nchunks, Op op,
+__global__ __launch_bounds__(kBlock) void k_bi_x(NodeList nl, Op op,
                                                  T* __restrict__ x, T* __restrict__ r,
                                                  const T* __restrict__ rhat, const T* __restrict__ phat,
                                                  const T* __restrict__ shat, const T* __restrict__ s,
@@ -684,9 +702,9 @@ __global__ __launch_bounds__(kBlock) void k_bi_x(const int* __restrict__ chunks,
   constexpr int NC = Op::kNC;
   const T alpha = T(sc->alpha), omega = T(sc->omega);
   double v[2] = {0.0, 0.0};
-  const ChunkRange cr = block_chunks(nchunks);
+  const ChunkRange cr = block_chunks(nl.n);
   for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
-    const int n = chunks[c] * 64 + int(threadIdx.x & 63);
+    const int n = nl.node(c);
     if (op.row(n)) {
 #pragma unroll
       for (int d = 0; d < NC; ++d) {
@@ -728,16 +746,16 @@ __global__ __launch_bounds__(kBlock) void k_fin_bi_x(const double* __restrict__ 
 // partials r.r, b.b
 // ---------------------------------------------------------------------------
 template <class Op, typename TR = float>
-__global__ __launch_bounds__(kBlock) void k_residual(const int* __restrict__ chunks, int nchunks, Op op,
+__global__ __launch_bounds__(kBlock) void k_residual(NodeList nl, Op op,
                                                      const double* __restrict__ b,
                                                      const double* __restrict__ x,
                                                      TR* __restrict__ r32,
                                                      double* __restrict__ partials) {
   constexpr int NC = Op::kNC;
   double v[2] = {0.0, 0.0};
-  const ChunkRange cr = block_chunks(nchunks);
+  const ChunkRange cr = block_chunks(nl.n);
   for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
-    const int n = chunks[c] * 64 + int(threadIdx.x & 63);
+    const int n = nl.node(c);
     const bool rw = op.row(n);
     double ax[NC];
     if (rw) op.apply(n, x, ax);

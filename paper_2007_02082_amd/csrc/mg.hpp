@@ -13,14 +13,14 @@ constexpr uint32_t kMgRow = 16u;  // pressure unknown bit of the level flags
 // x = d = c2 D^-1 b on rows (Chebyshev step from x = 0), 0 elsewhere; D is
 // c0 times the number of kept cells around the node; NC planes of `stride`.
 template <typename T, int NC = 1>
-__global__ __launch_bounds__(kBlock) void k_mg_cheb0(const int* __restrict__ chunks, int nchunks,
+__global__ __launch_bounds__(kBlock) void k_mg_cheb0(NodeList nl,
                                                      const uint8_t* __restrict__ emask,
                                                      const uint8_t* __restrict__ flags, T c0, T c2,
                                                      const T* __restrict__ b, T* __restrict__ d,
                                                      T* __restrict__ x, const KScal* sc,
                                                      uint32_t rowbit = kMgRow, int64_t stride = 0) {
   if (sc && sc->done) return;
-  const int n = chunk_node(chunks, nchunks);
+  const int n = chunk_node(nl);
   if (n < 0) return;
   const bool rw = flags[n] & rowbit;
   const T dinv = rw ? T(1) / (c0 * T(__builtin_popcount(uint32_t(emask[n])))) : T(0);
@@ -42,13 +42,13 @@ __device__ __forceinline__ void node_ijk(int n, int sy, int sz, int& i, int& j, 
 // bc[I] = sum_j P_jI rf[j] for coarse unknowns I (0 elsewhere); the fine nodes j
 // are the 27 around the node at the same place (2I), weight prod_d (1 - |o_d|/2).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_mg_restrict(const int* __restrict__ chunks, int nchunks,
+__global__ __launch_bounds__(kBlock) void k_mg_restrict(NodeList nl,
                                                         const uint8_t* __restrict__ cflags, int csy,
                                                         int csz, int fsy, int fsz, int fnx, int fny,
                                                         int fnz, const T* __restrict__ rf,
                                                         T* __restrict__ bc, const KScal* sc) {
   if (sc->done) return;
-  const int n = chunk_node(chunks, nchunks);
+  const int n = chunk_node(nl);
   if (n < 0) return;
   if (!(cflags[n] & kMgRow)) {
     bc[n] = T(0);
@@ -78,13 +78,13 @@ __global__ __launch_bounds__(kBlock) void k_mg_restrict(const int* __restrict__ 
 
 // xf[j] += sum_I P_jI xc[I] on fine unknowns (trilinear interpolation).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_mg_prolong(const int* __restrict__ chunks, int nchunks,
+__global__ __launch_bounds__(kBlock) void k_mg_prolong(NodeList nl,
                                                        const uint8_t* __restrict__ fflags, int fsy,
                                                        int fsz, int csy, int csz,
                                                        const T* __restrict__ xc, T* __restrict__ xf,
                                                        const KScal* sc) {
   if (sc->done) return;
-  const int n = chunk_node(chunks, nchunks);
+  const int n = chunk_node(nl);
   if (n < 0 || !(fflags[n] & kMgRow)) return;
   int i, j, k;
   node_ijk(n, fsy, fsz, i, j, k);
@@ -128,15 +128,15 @@ __global__ __launch_bounds__(kBlock) void k_mg_dense(int m, const int64_t* __res
 
 // partials of a.b over rows
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_mg_dot(const int* __restrict__ chunks, int nchunks,
+__global__ __launch_bounds__(kBlock) void k_mg_dot(NodeList nl,
                                                    const uint8_t* __restrict__ flags,
                                                    const T* __restrict__ a, const T* __restrict__ b,
                                                    double* __restrict__ partials, const KScal* sc) {
   if (sc->done) return;
   double v[1] = {0.0};
-  const ChunkRange cr = block_chunks(nchunks);
+  const ChunkRange cr = block_chunks(nl.n);
   for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
-    const int n = chunks[c] * 64 + int(threadIdx.x & 63);
+    const int n = nl.node(c);
     if (flags[n] & kMgRow) v[0] += double(a[n]) * double(b[n]);
   }
   block_partials<1>(v, partials);
@@ -146,14 +146,14 @@ __global__ __launch_bounds__(kBlock) void k_mg_dot(const int* __restrict__ chunk
 
 // x = 0, r = b on rows (0 elsewhere); partials r.r, b.b
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_mgcg_init(const int* __restrict__ chunks, int nchunks,
+__global__ __launch_bounds__(kBlock) void k_mgcg_init(NodeList nl,
                                                       const uint8_t* __restrict__ flags,
                                                       const T* __restrict__ b, T* __restrict__ x,
                                                       T* __restrict__ r, double* __restrict__ partials) {
   double v[2] = {0.0, 0.0};
-  const ChunkRange cr = block_chunks(nchunks);
+  const ChunkRange cr = block_chunks(nl.n);
   for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
-    const int n = chunks[c] * 64 + int(threadIdx.x & 63);
+    const int n = nl.node(c);
     const T bi = (flags[n] & kMgRow) ? b[n] : T(0);
     x[n] = T(0);
     r[n] = bi;
@@ -204,7 +204,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_mgcg_rz(const double* __restrict
 
 // x += alpha p, r -= alpha q on rows; partial r.r
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_mgcg_xr(const int* __restrict__ chunks, int nchunks,
+__global__ __launch_bounds__(kBlock) void k_mgcg_xr(NodeList nl,
                                                     const uint8_t* __restrict__ flags, T* __restrict__ x,
                                                     T* __restrict__ r, const T* __restrict__ p,
                                                     const T* __restrict__ q, double* __restrict__ partials,
@@ -212,9 +212,9 @@ __global__ __launch_bounds__(kBlock) void k_mgcg_xr(const int* __restrict__ chun
   if (sc->done) return;
   const T alpha = T(sc->alpha);
   double v[1] = {0.0};
-  const ChunkRange cr = block_chunks(nchunks);
+  const ChunkRange cr = block_chunks(nl.n);
   for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
-    const int n = chunks[c] * 64 + int(threadIdx.x & 63);
+    const int n = nl.node(c);
     if (flags[n] & kMgRow) {
       x[n] += alpha * p[n];
       const T ri = r[n] - alpha * q[n];
@@ -243,13 +243,13 @@ __global__ __launch_bounds__(kBlock) void k_fin_mgcg_xr(const double* __restrict
 
 // p = z + beta p on rows
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_mgcg_p(const int* __restrict__ chunks, int nchunks,
+__global__ __launch_bounds__(kBlock) void k_mgcg_p(NodeList nl,
                                                    const uint8_t* __restrict__ flags,
                                                    const T* __restrict__ z, T* __restrict__ p,
                                                    const KScal* sc) {
   if (sc->done) return;
   const T beta = T(sc->beta);
-  const int n = chunk_node(chunks, nchunks);
+  const int n = chunk_node(nl);
   if (n < 0) return;
   p[n] = (flags[n] & kMgRow) ? T(z[n] + beta * p[n]) : T(0);
 }

@@ -11,6 +11,7 @@
 namespace ibfe {
 
 constexpr int kChunk = 64;      // nodes per chunk (one wavefront)
+constexpr double kLaneFill = 0.75;  // per-lane node lists below this fill of the chunks
 constexpr int kMaxHarmonics = 16;
 constexpr int kMaxFloating = 8; // outlet-less connected parts supported
 

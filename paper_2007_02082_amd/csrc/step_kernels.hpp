@@ -57,7 +57,7 @@ __device__ __forceinline__ constexpr double t1c(int a, int b, int c) {
   return (c == 1 ? 1.0 : -1.0) * (a == b ? (1.0 / 3.0) : (1.0 / 6.0));
 }
 
-__global__ __launch_bounds__(kBlock) void k_s1_build(const int* __restrict__ chunks, int nchunks,
+__global__ __launch_bounds__(kBlock) void k_s1_build(NodeList nl,
                                                      const uint8_t* __restrict__ emask,
                                                      const uint8_t* __restrict__ flags,
                                                      const double* __restrict__ u, int64_t stride,
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(kBlock) void k_s1_build(const int* __restrict__ chu
                                                      uint32_t rowbit) {
   // st = 2 (with sy, sz of the lattice) builds the coarse-element part of a
   // refined lattice from the coarse cell bits in `emask`
-  const int n = chunk_node(chunks, nchunks);
+  const int n = chunk_node(nl);
   if (n < 0) return;
   double A[27];
 #pragma unroll
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(kBlock) void k_s1_build(const int* __restrict__ chu
 
 // b_d = (rho/dt)(M u_d) - G_d p - A g_d on free rows, 0 elsewhere (Eq. 9 with
 // the Dirichlet lifting of g(t^{n+1})).
-__global__ __launch_bounds__(kBlock) void k_s1_rhs(const int* __restrict__ chunks, int nchunks,
+__global__ __launch_bounds__(kBlock) void k_s1_rhs(NodeList nl,
                                                    const uint8_t* __restrict__ emask,
                                                    const uint8_t* __restrict__ flags,
                                                    const double* __restrict__ coef,
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(kBlock) void k_s1_rhs(const int* __restrict__ chunk
                                                    int64_t stride, int sy, int sz, double cm0,
                                                    double cm1, double cm2, double cm3, double g20,
                                                    double g21, double g22) {
-  const int n = chunk_node(chunks, nchunks);
+  const int n = chunk_node(nl);
   if (n < 0) return;
   if (!(flags[n] & kFlagF)) {
 #pragma unroll
@@ -162,12 +162,12 @@ __global__ __launch_bounds__(kBlock) void k_s1_rhs(const int* __restrict__ chunk
 // Explicit advection: b_d = (rho/dt)(M u_d) - (rho C(u^n) u^n)_d - G_d p - A' g_d on
 // free rows with A' = (rho/dt) M + mu K; `adv` holds the stencil of rho C(u^n).
 __global__ __launch_bounds__(kBlock) void k_s1_rhs_explicit(
-    const int* __restrict__ chunks, int nchunks, const uint8_t* __restrict__ emask,
+    NodeList nl, const uint8_t* __restrict__ emask,
     const uint8_t* __restrict__ flags, const double* __restrict__ adv, const double* __restrict__ u,
     const double* __restrict__ p, const double* __restrict__ g, double* __restrict__ b, int64_t stride, int sy,
     int sz, double cm0, double cm1, double cm2, double cm3, double ca0, double ca1, double ca2, double ca3,
     double g20, double g21, double g22) {
-  const int n = chunk_node(chunks, nchunks);
+  const int n = chunk_node(nl);
   if (n < 0) return;
   if (!(flags[n] & kFlagF)) {
 #pragma unroll
@@ -191,13 +191,13 @@ __global__ __launch_bounds__(kBlock) void k_s1_rhs_explicit(
 }
 
 // b = scale * sum_d G_d u_d on rows with (flags & rowbit), 0 elsewhere.
-__global__ __launch_bounds__(kBlock) void k_div(const int* __restrict__ chunks, int nchunks,
+__global__ __launch_bounds__(kBlock) void k_div(NodeList nl,
                                                 const uint8_t* __restrict__ emask,
                                                 const uint8_t* __restrict__ flags, uint32_t rowbit,
                                                 uint32_t exclude, const double* __restrict__ u,
                                                 double* __restrict__ b, int64_t stride, int sy, int sz,
                                                 double g20, double g21, double g22, double scale) {
-  const int n = chunk_node(chunks, nchunks);
+  const int n = chunk_node(nl);
   if (n < 0) return;
   const uint32_t f = flags[n];
   if (!(f & rowbit) || (f & exclude)) {
@@ -213,13 +213,13 @@ __global__ __launch_bounds__(kBlock) void k_div(const int* __restrict__ chunks, 
 }
 
 // y_d = G_d x on rows with (flags & rowbit), 0 elsewhere.
-__global__ __launch_bounds__(kBlock) void k_grad(const int* __restrict__ chunks, int nchunks,
+__global__ __launch_bounds__(kBlock) void k_grad(NodeList nl,
                                                  const uint8_t* __restrict__ emask,
                                                  const uint8_t* __restrict__ flags, uint32_t rowbit,
                                                  const double* __restrict__ x, double* __restrict__ y,
                                                  int64_t stride, int sy, int sz, double g20, double g21,
                                                  double g22) {
-  const int n = chunk_node(chunks, nchunks);
+  const int n = chunk_node(nl);
   if (n < 0) return;
   if (!(flags[n] & rowbit)) {
 #pragma unroll
@@ -235,9 +235,9 @@ __global__ __launch_bounds__(kBlock) void k_grad(const int* __restrict__ chunks,
 
 // Plain apply of a symmetric form or the stored stencil (verification hooks).
 template <typename T, int NC, class Op>
-__global__ __launch_bounds__(kBlock) void k_apply(const int* __restrict__ chunks, int nchunks, Op op,
+__global__ __launch_bounds__(kBlock) void k_apply(NodeList nl, Op op,
                                                   const T* __restrict__ x, T* __restrict__ y) {
-  const int n = chunk_node(chunks, nchunks);
+  const int n = chunk_node(nl);
   if (n < 0) return;
   T v[NC];
   const bool rw = op.row(n);
@@ -323,22 +323,22 @@ __global__ __launch_bounds__(kBlock) void k_inlet(int n, const int64_t* __restri
 
 // y = (flags & bit) ? x : 0, nc planes
 template <typename TI, typename TO>
-__global__ __launch_bounds__(kBlock) void k_masked_copy(const int* __restrict__ chunks, int nchunks,
+__global__ __launch_bounds__(kBlock) void k_masked_copy(NodeList nl,
                                                         const uint8_t* __restrict__ flags, uint32_t bit,
                                                         const TI* __restrict__ x, TO* __restrict__ y,
                                                         int nc, int64_t stride) {
-  const int n = chunk_node(chunks, nchunks);
+  const int n = chunk_node(nl);
   if (n < 0) return;
   const bool on = flags[n] & bit;
   for (int d = 0; d < nc; ++d) y[d * stride + n] = on ? TO(x[d * stride + n]) : TO(0);
 }
 
 // z = a x + b y over all chunk nodes, nc planes
-__global__ __launch_bounds__(kBlock) void k_axpby(const int* __restrict__ chunks, int nchunks, double a,
+__global__ __launch_bounds__(kBlock) void k_axpby(NodeList nl, double a,
                                                   const double* __restrict__ x, double b,
                                                   const double* __restrict__ y, double* __restrict__ z,
                                                   int nc, int64_t stride) {
-  const int n = chunk_node(chunks, nchunks);
+  const int n = chunk_node(nl);
   if (n < 0) return;
   for (int d = 0; d < nc; ++d) {
     const int64_t i = d * stride + n;
@@ -349,21 +349,21 @@ __global__ __launch_bounds__(kBlock) void k_axpby(const int* __restrict__ chunks
 // x = 0 on every chunk node (nc planes); positions outside the chunks are never
 // written and stay zero from the allocation
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_zero(const int* __restrict__ chunks, int nchunks,
+__global__ __launch_bounds__(kBlock) void k_zero(NodeList nl,
                                                  T* __restrict__ x, int nc, int64_t stride) {
-  const int n = chunk_node(chunks, nchunks);
+  const int n = chunk_node(nl);
   if (n < 0) return;
   for (int d = 0; d < nc; ++d) x[d * stride + n] = T(0);
 }
 
 // x += TO(d) on rows (mixed precision update of an FP64 iterate by an FP32 correction)
 template <typename TD>
-__global__ __launch_bounds__(kBlock) void k_add_correction(const int* __restrict__ chunks, int nchunks,
+__global__ __launch_bounds__(kBlock) void k_add_correction(NodeList nl,
                                                            const uint8_t* __restrict__ flags,
                                                            uint32_t bit, const TD* __restrict__ dx,
                                                            double* __restrict__ x, int nc,
                                                            int64_t stride) {
-  const int n = chunk_node(chunks, nchunks);
+  const int n = chunk_node(nl);
   if (n < 0 || !(flags[n] & bit)) return;
   for (int d = 0; d < nc; ++d) x[d * stride + n] += double(dx[d * stride + n]);
 }
@@ -387,14 +387,14 @@ __global__ __launch_bounds__(kBlock) void k_gather(int64_t n, const int64_t* __r
 
 // Per-slot partial sums over nodes of outlet-less parts (slot >= 0), then a
 // one-block finalize that stores means[s] = sum_s / count_s.
-__global__ __launch_bounds__(kBlock) void k_slot_sum(const int* __restrict__ chunks, int nchunks,
+__global__ __launch_bounds__(kBlock) void k_slot_sum(NodeList nl,
                                                      const int8_t* __restrict__ slot,
                                                      const double* __restrict__ x,
                                                      double* __restrict__ partials) {
   double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  const ChunkRange cr = block_chunks(nchunks);
+  const ChunkRange cr = block_chunks(nl.n);
   for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
-    const int n = chunks[c] * 64 + int(threadIdx.x & 63);
+    const int n = nl.node(c);
     const int s = slot[n];
 #pragma unroll
     for (int k = 0; k < 8; ++k)
@@ -410,11 +410,11 @@ __global__ __launch_bounds__(kBlock) void k_fin_slot(const double* __restrict__ 
   if (threadIdx.x != 0) return;
   for (int k = 0; k < nslots; ++k) means[k] = tot[k] / count[k];
 }
-__global__ __launch_bounds__(kBlock) void k_slot_sub(const int* __restrict__ chunks, int nchunks,
+__global__ __launch_bounds__(kBlock) void k_slot_sub(NodeList nl,
                                                      const int8_t* __restrict__ slot,
                                                      double* __restrict__ x,
                                                      const double* __restrict__ means) {
-  const int n = chunk_node(chunks, nchunks);
+  const int n = chunk_node(nl);
   if (n < 0) return;
   const int s = slot[n];
   if (s >= 0) x[n] -= means[s];

@@ -79,7 +79,9 @@ __device__ __forceinline__ void zb_walk(const int* __restrict__ items, int nitem
       const int node = base + k * sz;
       const uint32_t e = em[k % R];
       const bool rw = lane_ok && (fl[k % R] & op.rowbit);
-      const bool interior = __all((!lane_ok) || e == 0xFFu);
+      // the constant stencil when every row lane has all 8 cells (non-row lanes'
+      // results are discarded by the epilogues)
+      const bool interior = __all((!rw) || e == 0xFFu);
       const T y = window_apply<T>(w[k % R], w[(k + 1) % R], w[(k + 2) % R], e, interior, c);
       epi(node, lane_ok, rw, e, y, w[(k + 1) % R][4]);
     }
