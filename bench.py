@@ -9,6 +9,10 @@ GPU.  `--workload aneurysm` runs the synthetic aneurysm instead: a tube of radiu
 along a sinusoidal centreline (amplitude 1, period 10, length 20) with a spherical
 bulge of radius 2.5, on a 128x128x320 base grid whose cells within 0.5 of the wall
 are split 2:1 (a 257x257x641 lattice, 2.8 M unknown nodes), parabolic inlet.
+`--workload aorta` runs the aorta-like arch (radius 1.2 along a cubic Bezier, three
+branches of radius 0.4-0.6) on a uniform 256x160x384 grid (15.9 M nodes, 5 % of
+them active), inlet and outlet disks on the same face, two-harmonic Womersley-type
+inlet, dt = 0.002.
 
 Prints one JSON line.  The two matrix-free applies that carry the step are timed
 with HIP events on the library's stream over the timed region: the masked Q1
@@ -35,7 +39,8 @@ CSRC = os.path.join(ROOT, "paper_2007_02082_amd", "csrc")
 
 
 KERNEL_SOURCES = {"pulsatile": ("kernels.hpp", "zblock.hpp"),
-                  "aneurysm": ("kernels.hpp", "composite.hpp")}
+                  "aneurysm": ("kernels.hpp", "composite.hpp"),
+                  "aorta": ("kernels.hpp", "zblock.hpp")}
 
 
 def counted_traffic(workload: str, precision: str, kernel: str):
@@ -81,6 +86,29 @@ def cpu_baseline_aneurysm(n_full: int) -> dict:
     return {"value": 1.0 / (sec * scale), "unit": "steps/s", "cores": 1, "kind": "oracle",
             "sample": f"1 oracle step of the aneurysm on a 48x48x120 base grid ({pr.sets.P.size} "
                       f"nodes, {sec:.2f} s/step), scaled by the node ratio {scale:.2f}"}
+
+
+def cpu_baseline_aorta(n_full: int) -> dict:
+    """Oracle (FP64, one thread) on a bounded sample: the same aorta-like geometry at half
+    resolution (128x80x192, same point spacing in units of h), one step after set-up,
+    scaled by the ratio of nodes of P to the 256x160x384 case (a lower bound on the
+    oracle's time at full size: its Jacobi-CG iteration counts grow with the resolution)."""
+    from threadpoolctl import threadpool_limits
+
+    import synth
+    from oracle import ipcs
+
+    sample = synth.aorta_case(scale=2, nsteps=1)
+    with threadpool_limits(1):
+        pr = ipcs.Problem.from_case(sample)
+        u, p = pr.initial_state(sample.u0, sample.p0)
+        t0 = time.perf_counter()
+        pr.step(u, p, 0.0)
+        sec = time.perf_counter() - t0
+    scale = n_full / pr.sets.P.size
+    return {"value": 1.0 / (sec * scale), "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 oracle step of the aorta-like arch at half resolution (128x80x192, "
+                      f"{pr.sets.P.size} nodes, {sec:.2f} s/step), scaled by the node ratio {scale:.2f}"}
 
 
 def cpu_baseline(seconds_hint: float = 15.0) -> dict:
@@ -166,8 +194,9 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["pulsatile", "aneurysm"], default="pulsatile",
-                    help="pulsatile cylinder on 64x64x512 (default) or the refined aneurysm")
+    ap.add_argument("--workload", choices=["pulsatile", "aneurysm", "aorta"], default="pulsatile",
+                    help="pulsatile cylinder on 64x64x512 (default), the refined aneurysm or the "
+                         "aorta-like arch on 256x160x384")
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--precond", choices=["mg", "jacobi"], default="mg",
                     help="pressure preconditioner: geometric multigrid or Jacobi")
@@ -195,7 +224,8 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     refined = args.workload == "aneurysm"
-    case = synth.aneurysm_case() if refined else synth.pulsatile_c2()
+    case = {"pulsatile": synth.pulsatile_c2, "aneurysm": synth.aneurysm_case,
+            "aorta": synth.aorta_case}[args.workload]()
     prec = 1 if args.precision == "mixed" else 0
     pc = 2 if args.precond == "mg" else 0
     s = ibfe.Solver(**ibfe.inputs_from_case(case, precision=prec, precond=pc))
@@ -287,7 +317,8 @@ def main() -> int:
     if args.serve:
         out["serving"] = serve_stream(args.serve_requests, args.serve_slots, 50)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_aneurysm(n_p) if refined else cpu_baseline()
+        out["cpu_baseline"] = {"pulsatile": cpu_baseline, "aneurysm": lambda: cpu_baseline_aneurysm(n_p),
+                               "aorta": lambda: cpu_baseline_aorta(n_p)}[args.workload]()
     print(json.dumps(out), flush=True)
     return 0
 

@@ -244,9 +244,14 @@ def _torch_allocator():
         except Exception:
             return None
 
+    delete = torch.cuda.caching_allocator_delete
+
     @FREE_FN
     def _free(ptr, user):
-        torch.cuda.caching_allocator_delete(ptr)
+        try:
+            delete(ptr)
+        except Exception:
+            pass  # torch is already torn down at interpreter exit; the process releases the memory
 
     return Alloc(_alloc, _free, None), (_alloc, _free)
 
