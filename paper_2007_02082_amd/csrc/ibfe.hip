@@ -66,12 +66,13 @@ struct ibfe_plan {
 // Device copy of one multigrid level (node-0 pointers into padded planes).
 template <typename T>
 struct MGDev {
-  int nx = 0, ny = 0, nz = 0, nchunks = 0, nzitems = 0, cpp = 0, zb = kZBPlanes;
+  int nx = 0, ny = 0, nz = 0, nchunks = 0, nzitems = 0, zb = kZBPlanes;
   int64_t N = 0, sy = 0, sz = 0, halo = 0, stride = 0;
   uint8_t* emask = nullptr;
   uint8_t* flags = nullptr;
   NodeList nl;
   int* zitems = nullptr;
+  int* zlanes = nullptr;
   T *b = nullptr, *x = nullptr, *xt = nullptr, *d = nullptr, *r = nullptr;
   double kc[4] = {0, 0, 0, 0};  // per-cell stiffness entries at this spacing
   bool composite = false;       // level 0 of a refined lattice (composite operator)
@@ -99,8 +100,9 @@ struct ibfe_ctx {
   int8_t* slot = nullptr;
   NodeList nl;                    // active nodes (P and hanging)
   NodeList ib_nl;                 // Lagrangian points
-  int* zitems = nullptr;          // z-blocked column items (plane_block * cpp + chunk)
-  int nzitems = 0, cpp = 0, zb = kZBPlanes;
+  int* zitems = nullptr;          // z-blocked column items (plane block of each item)
+  int* zlanes = nullptr;          // their 64 in-plane positions (-1 = none)
+  int nzitems = 0, zb = kZBPlanes;
   int64_t* pids = nullptr;
   double* float_count = nullptr;
   double* float_means = nullptr;
@@ -245,7 +247,6 @@ int setup_mg(ibfe_ctx& c, std::vector<MGDev<T>>& out, T* xt0, T* d0, T* r0) {
     D.N = L.N;
     D.sy = L.sy;
     D.sz = L.sz;
-    D.cpp = L.cpp;
     D.zb = L.zb;
     const FormCoefs f = form_coefs(L.h);
     for (int t = 0; t < 4; ++t) D.kc[t] = f.k[t];
@@ -257,6 +258,7 @@ int setup_mg(ibfe_ctx& c, std::vector<MGDev<T>>& out, T* xt0, T* d0, T* r0) {
       D.nl = c.nl;
       D.nchunks = c.nchunks;
       D.zitems = c.zitems;
+      D.zlanes = c.zlanes;
       D.nzitems = c.nzitems;
       D.zb = c.zb;
       D.xt = xt0;
@@ -280,6 +282,7 @@ int setup_mg(ibfe_ctx& c, std::vector<MGDev<T>>& out, T* xt0, T* d0, T* r0) {
       D.nchunks = int(L.chunks.size());
       D.nl = NodeList{lc, D.nchunks, 0};
       if ((rc = c.upload(&D.zitems, L.zitems.data(), L.zitems.size()))) return rc;
+      if ((rc = c.upload(&D.zlanes, L.zlanes.data(), L.zlanes.size()))) return rc;
       D.nzitems = int(L.zitems.size());
       T** vecs[5] = {&D.b, &D.x, &D.xt, &D.d, &D.r};
       for (T** v : vecs) {
@@ -421,11 +424,12 @@ int setup_device(ibfe_ctx& c) {
   }
   if ((rc = setup_node_list(c))) return rc;
   {
-    // column items of the z-blocked applies: zb planes x 64 in-plane nodes
-    std::vector<int> items;
-    c.zb = choose_column_items(P.emask, P.sz, P.nz + 1, items, c.cpp);
+    // column items of the z-blocked applies: zb planes x 64 in-plane positions
+    std::vector<int> items, lanes;
+    c.zb = choose_column_items(P.emask, P.sz, P.nz + 1, items, lanes);
     c.nzitems = int(items.size());
     if ((rc = c.upload(&c.zitems, items.data(), items.size()))) return rc;
+    if ((rc = c.upload(&c.zlanes, lanes.data(), lanes.size()))) return rc;
   }
   if ((rc = c.upload(&c.pids, P.P_ids.data(), P.P_ids.size()))) return rc;
   {
@@ -565,8 +569,8 @@ template <typename T, int NC>
 int launch_q(ibfe_ctx& c, const OpSym<T, NC>& op, NodeList, const T* p, T* q, const KScal* sc,
              hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   const int nr = red_blocks(c.nzitems);
-  ZOp<T> z{op.emask, op.flags, op.rowbit, op.sy, op.sz, c.plan.nz + 1, c.cpp,
-           {op.c[0], op.c[1], op.c[2], op.c[3]}, c.zb};
+  ZOp<T> z{op.emask, op.flags, op.rowbit, op.sy, op.sz, c.plan.nz + 1,
+           {op.c[0], op.c[1], op.c[2], op.c[3]}, c.zb, c.zlanes};
   if (e0)
     hipExtLaunchKernelGGL((k_cg_q_zb<T, NC>), dim3(nr), dim3(kBlock), 0, c.stream, e0, e1, 0,
                           (const int*)c.zitems, c.nzitems, z, op.stride, p, q, c.partials, sc);
@@ -1070,7 +1074,7 @@ ZOp<T> level_op(const MGDev<T>& L) {
   z.sy = int(L.sy);
   z.sz = int(L.sz);
   z.nplanes = L.nz + 1;
-  z.cpp = L.cpp;
+  z.lanes = L.zlanes;
   z.zb = L.zb;
   for (int t = 0; t < 4; ++t) z.c[t] = T(L.kc[t]);
   return z;
@@ -1303,7 +1307,7 @@ int run_cheb_mass(ibfe_ctx& c, const T* b, T* x, T* xalt, T* d, int iters) {
   op.sy = int(P.sy);
   op.sz = int(P.sz);
   op.nplanes = P.nz + 1;
-  op.cpp = c.cpp;
+  op.lanes = c.zlanes;
   op.zb = c.zb;
   for (int t = 0; t < 4; ++t) op.c[t] = T(c.fc.m[t]);
   T* cur = ((iters - 1) % 2 == 0) ? x : xalt;

@@ -163,30 +163,34 @@ void coarsest_inverse(MGLevel& L) {
 }  // namespace
 
 void column_items(const std::vector<uint8_t>& emask, int64_t sz, int nplanes, int zb,
-                  std::vector<int32_t>& items, int& cpp) {
-  cpp = int((sz + kChunk - 1) / kChunk);
+                  std::vector<int32_t>& items, std::vector<int32_t>& lanes) {
   const int npb = (nplanes + zb - 1) / zb;
   items.clear();
-  for (int pb = 0; pb < npb; ++pb)
-    for (int ch = 0; ch < cpp; ++ch) {
-      bool any = false;
-      for (int k = pb * zb; k < std::min(nplanes, (pb + 1) * zb) && !any; ++k)
-        for (int64_t l = int64_t(ch) * kChunk; l < std::min<int64_t>(sz, (ch + 1) * int64_t(kChunk)); ++l)
-          if (emask[k * sz + l]) {
-            any = true;
-            break;
-          }
-      if (any) items.push_back(pb * cpp + ch);
+  lanes.clear();
+  std::vector<uint8_t> used(size_t(sz), 0);
+  for (int pb = 0; pb < npb; ++pb) {
+    std::fill(used.begin(), used.end(), 0);
+    for (int k = pb * zb; k < std::min(nplanes, (pb + 1) * zb); ++k)
+      for (int64_t l = 0; l < sz; ++l) used[l] |= emask[k * sz + l] ? 1 : 0;
+    int fill = 0;
+    for (int64_t l = 0; l < sz; ++l) {
+      if (!used[l]) continue;
+      if (fill == 0) items.push_back(pb);
+      lanes.push_back(int32_t(l));
+      fill = (fill + 1) % kChunk;
     }
+    if (fill)
+      for (; fill < kChunk; ++fill) lanes.push_back(-1);
+  }
 }
 
 int choose_column_items(const std::vector<uint8_t>& emask, int64_t sz, int nplanes,
-                        std::vector<int32_t>& items, int& cpp) {
+                        std::vector<int32_t>& items, std::vector<int32_t>& lanes) {
   int zb = kZBPlanes;
-  column_items(emask, sz, nplanes, zb, items, cpp);
+  column_items(emask, sz, nplanes, zb, items, lanes);
   while (zb > 2 && int64_t(items.size()) < kZBMinItems) {
     zb /= 2;
-    column_items(emask, sz, nplanes, zb, items, cpp);
+    column_items(emask, sz, nplanes, zb, items, lanes);
   }
   return zb;
 }
@@ -209,7 +213,7 @@ int build_multigrid(Plan& P, std::string& err) {
     if (f & IBFE_FLAG_P) L0.flags[n] = kMgP | ((f & IBFE_FLAG_PDIR) ? 0 : kMgPp);
   }
   L0.chunks = P.chunks;
-  if (!P.refined) L0.zb = choose_column_items(L0.emask, L0.sz, L0.nz + 1, L0.zitems, L0.cpp);
+  if (!P.refined) L0.zb = choose_column_items(L0.emask, L0.sz, L0.nz + 1, L0.zitems, L0.zlanes);
   P.mg.push_back(std::move(L0));
   // Chebyshev preconditioner: the grid level alone, smoothed without a coarse correction
   if (P.params.precond == 1) return IBFE_OK;
@@ -256,7 +260,7 @@ int build_multigrid(Plan& P, std::string& err) {
           C.flags[cn] = kMgP | (dir ? 0 : kMgPp);
         }
     chunk_list(C.emask, C.chunks);
-    C.zb = choose_column_items(C.emask, C.sz, C.nz + 1, C.zitems, C.cpp);
+    C.zb = choose_column_items(C.emask, C.sz, C.nz + 1, C.zitems, C.zlanes);
     P.mg.push_back(std::move(C));
   }
   auto unknowns = [](const MGLevel& L) {
@@ -303,7 +307,7 @@ int build_multigrid(Plan& P, std::string& err) {
           C.flags[cn] = kMgP | (dir ? 0 : kMgPp);
         }
     chunk_list(C.emask, C.chunks);
-    C.zb = choose_column_items(C.emask, C.sz, C.nz + 1, C.zitems, C.cpp);
+    C.zb = choose_column_items(C.emask, C.sz, C.nz + 1, C.zitems, C.zlanes);
     P.mg.push_back(std::move(C));
   }
   coarsest_inverse(P.mg.back());

@@ -29,8 +29,8 @@ struct MGLevel {
   int64_t N = 0, sy = 0, sz = 0;
   std::vector<uint8_t> emask, flags;
   std::vector<int32_t> chunks;    // 64-node chunks holding a node of P
-  std::vector<int32_t> zitems;    // z-blocked column items holding a node of P
-  int cpp = 0;                    // chunks per plane of the column items
+  std::vector<int32_t> zitems;    // z-blocked column items: plane block of each item
+  std::vector<int32_t> zlanes;    // 64 in-plane positions per item (-1 = none)
   int zb = kZBPlanes;             // planes per column item
   std::vector<int64_t> unknowns;  // ids of pressure unknowns (coarsest level only)
   std::vector<double> inv;        // dense inverse on `unknowns` (coarsest level only)
@@ -106,13 +106,16 @@ struct Plan {
 
 // Build the multigrid hierarchy from level 0 (already holding emask/flags).
 int build_multigrid(Plan& plan, std::string& err);
-// z-blocked column items of a level (zb planes x 64 in-plane nodes).
+// z-blocked column items of a level: item q covers planes zb items[q] .. zb
+// items[q] + zb - 1 at the in-plane positions lanes[64 q .. 64 q + 63]: the
+// positions where some plane of the block has a kept cell, ascending, 64 per
+// item, the last item of a block padded with -1.
 void column_items(const std::vector<uint8_t>& emask, int64_t sz, int nplanes, int zb,
-                  std::vector<int32_t>& items, int& cpp);
+                  std::vector<int32_t>& items, std::vector<int32_t>& lanes);
 // Column items with the most planes per item (8, 4 or 2) that still gives at
 // least kZBMinItems items (enough wavefronts to fill the chip); returns zb.
 int choose_column_items(const std::vector<uint8_t>& emask, int64_t sz, int nplanes,
-                        std::vector<int32_t>& items, int& cpp);
+                        std::vector<int32_t>& items, std::vector<int32_t>& lanes);
 
 // Kept elements, hanging nodes and parents of a refined lattice: fills emask
 // (children of refined cells), cmask, the hanging and parent tables and joins

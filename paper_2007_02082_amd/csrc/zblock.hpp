@@ -1,8 +1,8 @@
 // Z-blocked matrix-free apply of the symmetric masked Q1 forms (alpha M + beta K).
 //
-// A wavefront owns one "column item": 64 consecutive node ids of one z-plane
-// (a row segment in the x-fastest numbering, clamped to the plane) and walks it
-// up through kZB planes.  A 3-plane sliding window of the 3x3 (y, x) neighbour
+// A wavefront owns one "column item": 64 in-plane positions (ascending, mostly
+// runs of consecutive x, where some plane of the item holds a kept cell) and
+// walks them up through the item's planes (at most kZB).  A 3-plane sliding window of the 3x3 (y, x) neighbour
 // rows stays in registers, so each output node costs 9 coalesced row loads
 // instead of 27 gathers, and the y/z row addresses are shared by the x shifts.
 // When every lane of the wavefront sits in the interior (all 8 cells kept) the
@@ -23,9 +23,10 @@ struct ZOp {
   const uint8_t* emask;
   const uint8_t* flags;
   uint32_t rowbit;
-  int sy, sz, nplanes, cpp;
+  int sy, sz, nplanes;
   T c[4];
-  int zb;  // planes per column item (<= kZB)
+  int zb;             // planes per column item (<= kZB)
+  const int* lanes;   // 64 in-plane positions per item, -1 = none
 };
 
 // Walk the column items of this block; epi(node, lane_ok, row, emask, Ax, x_centre).
@@ -45,13 +46,12 @@ __device__ __forceinline__ void zb_walk(const int* __restrict__ items, int nitem
   const T c[4] = {op.c[0], op.c[1], op.c[2], op.c[3]};
   const ChunkRange cr = block_chunks(nitems);
   for (int it = cr.c0 + int(threadIdx.x >> 6); it < cr.c1; it += kWaves) {
-    const int item = items[it];
-    const int pb = item / op.cpp, ch = item - pb * op.cpp;
-    const int inplane = ch * 64 + lane;
-    const bool lane_ok = inplane < sz;
+    const int pb = items[it];
+    const int inplane = op.lanes[it * 64 + lane];
+    const bool lane_ok = inplane >= 0;
     const int k0 = pb * op.zb;
     const int kend = min(op.zb, op.nplanes - k0);
-    const int base = k0 * sz + (lane_ok ? inplane : sz - 1);
+    const int base = k0 * sz + (lane_ok ? inplane : 0);
     // plane j of the item is grid plane k0 - 1 + j (j = 0 .. kend + 1), kept in
     // slot j % R; the cell bits and flags of output plane k in slot k % R
     T w[R][9];
