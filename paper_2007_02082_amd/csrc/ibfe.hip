@@ -18,6 +18,7 @@
 #include "zblock.hpp"
 #include "mg.hpp"
 #include "composite.hpp"
+#include "ib_pcg.hpp"
 
 using namespace ibfe;
 
@@ -124,11 +125,15 @@ struct ibfe_ctx {
   int32_t* G_col = nullptr;
   double* G_val = nullptr;
   double* G_diag = nullptr;
+  float* G_binv = nullptr;
   int32_t* sp_node = nullptr;
   int64_t* sp_ptr = nullptr;
   int32_t* sp_pt = nullptr;
   double* sp_wt = nullptr;
-  double* ibv[5] = {};  // b, lam, r, p, q (3 planes of mstride)
+  double* ibv[6] = {};  // b, lam, r, p, q, z (3 planes of mstride)
+  // ibv[1] holds the force of the last step: the initial guess of the next force
+  // solve (the right-hand side U_B - I u* changes little from step to step)
+  bool lam_warm = false;
 
   // inlet
   int64_t* inlet_ids = nullptr;
@@ -481,11 +486,12 @@ int setup_device(ibfe_ctx& c) {
     if ((rc = c.upload(&c.G_col, P.G_col.data(), P.G_col.size()))) return rc;
     if ((rc = c.upload(&c.G_val, P.G_val.data(), P.G_val.size()))) return rc;
     if ((rc = c.upload(&c.G_diag, P.G_diag.data(), P.G_diag.size()))) return rc;
+    if ((rc = c.upload(&c.G_binv, P.G_binv.data(), P.G_binv.size()))) return rc;
     if ((rc = c.upload(&c.sp_node, P.sp_node.data(), P.sp_node.size()))) return rc;
     if ((rc = c.upload(&c.sp_ptr, P.sp_ptr.data(), P.sp_ptr.size()))) return rc;
     if ((rc = c.upload(&c.sp_pt, P.sp_pt.data(), P.sp_pt.size()))) return rc;
     if ((rc = c.upload(&c.sp_wt, P.sp_w.data(), P.sp_w.size()))) return rc;
-    for (int i = 0; i < 5; ++i) {
+    for (int i = 0; i < 6; ++i) {
       void* base = nullptr;
       if ((rc = c.dalloc(&base, sizeof(double) * 3 * c.mstride))) return rc;
       c.ibv[i] = reinterpret_cast<double*>(base);
@@ -622,7 +628,7 @@ int timer_events(ibfe_ctx& c, size_t k, hipEvent_t& e0, hipEvent_t& e1) {
 }
 
 // Graph keys: call site, Krylov slot, scalar size, sequence length.
-enum GraphSite : uint64_t { kGsCg = 1, kGsBicg, kGsPcgMg, kGsChebMass, kGsChebGen };
+enum GraphSite : uint64_t { kGsCg = 1, kGsBicg, kGsPcgMg, kGsChebMass, kGsChebGen, kGsIbPcg };
 uint64_t graph_key(GraphSite site, int slot, int tbytes, int len) {
   return (uint64_t(site) << 56) | (uint64_t(slot & 0xff) << 48) | (uint64_t(tbytes & 0xff) << 40) |
          uint64_t(uint32_t(len));
@@ -1278,6 +1284,63 @@ int run_pcg_mg(ibfe_ctx& c, const Op& op, std::vector<MGDev<T>>& lv, const T* b,
 }
 
 
+// Force system G Lambda = b of the IB correction (FP64): CG with the block-Jacobi
+// preconditioner of ib_pcg.hpp, from x (the last step's force) unless zero_guess.
+int run_ib_pcg(ibfe_ctx& c, const double* b, double* x, double* r, double* p, double* q, double* z,
+               int slot, double rtol, int max_iters, bool zero_guess, SolveOut& out) {
+  const OpCSR<3> op = gram_op(c);
+  const NodeList nl = c.ib_nl;
+  const int M = int(c.plan.M);
+  const int nr = red_blocks(nl.n), nb = blocks_for(nl.n);
+  const int nblk = (M + kIBBlock - 1) / kIBBlock;
+  const int nj = std::max(1, std::min(kRedBlocks, nblk));
+  const int ng = std::max(1, std::min(kRedBlocks, (M + kBlock / kIBLanes - 1) / (kBlock / kIBLanes)));
+  const int64_t S = c.mstride;
+  KScal* sc = &c.scal[slot];
+  const KScal* csc = sc;
+  hipLaunchKernelGGL(k_ibcg_init, dim3(nr), dim3(kBlock), 0, c.stream, nl, op, b, x, r, c.partials,
+                     zero_guess ? 1 : 0);
+  hipLaunchKernelGGL(k_fin_mgcg_init, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr, sc,
+                     rtol * rtol, max_iters);
+  hipLaunchKernelGGL(k_ib_bjac, dim3(nj), dim3(kBlock), 0, c.stream, M, nblk, (const float*)c.G_binv,
+                     (const double*)r, z, S, c.partials, csc);
+  hipLaunchKernelGGL(k_fin_mgcg_rz, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nj, sc, 1);
+  hipLaunchKernelGGL(k_ibcg_p, dim3(nb), dim3(kBlock), 0, c.stream, nl, M, S, (const double*)z, p, csc);
+  CHECK_LAUNCH();
+  int launched = 0, rc;
+  KScal s{};
+  while (true) {
+    const int batch = std::min(next_batch(c.est[slot], launched), max_iters + 1 - launched);
+    auto body = [&]() -> int {
+      for (int k = 0; k < batch; ++k) {
+        hipLaunchKernelGGL(k_ibcg_q, dim3(ng), dim3(kBlock), 0, c.stream, M, (const int64_t*)c.G_ptr,
+                           (const int32_t*)c.G_col, (const double*)c.G_val, S, (const double*)p, q, c.partials,
+                           csc);
+        hipLaunchKernelGGL(k_fin_cg_q, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, ng, sc);
+        hipLaunchKernelGGL(k_ibcg_xr, dim3(nr), dim3(kBlock), 0, c.stream, nl, M, S, x, r, (const double*)p,
+                           (const double*)q, c.partials, csc);
+        hipLaunchKernelGGL(k_fin_mgcg_xr, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr,
+                           sc);
+        hipLaunchKernelGGL(k_ib_bjac, dim3(nj), dim3(kBlock), 0, c.stream, M, nblk, (const float*)c.G_binv,
+                           (const double*)r, z, S, c.partials, csc);
+        hipLaunchKernelGGL(k_fin_mgcg_rz, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nj,
+                           sc, 0);
+        hipLaunchKernelGGL(k_ibcg_p, dim3(nb), dim3(kBlock), 0, c.stream, nl, M, S, (const double*)z, p, csc);
+        CHECK_LAUNCH();
+      }
+      return IBFE_OK;
+    };
+    if ((rc = graph_run(c, graph_key(kGsIbPcg, slot, sizeof(double), batch), body))) return rc;
+    launched += batch;
+    if ((rc = poll(c, slot, s))) return rc;
+    if (s.done || launched > max_iters) break;
+  }
+  c.est[slot] = std::max(1, s.iters);
+  out.iters = s.iters;
+  out.res = s.bb > 0.0 ? std::sqrt(s.rr / s.bb) : 0.0;
+  return finish_status(s, "IB force CG");
+}
+
 // -------------------------------------------------------------------------
 // Chebyshev iteration for the consistent-mass correction M_FF x = b.  For Q1
 // cubes the generalized eigenvalues of (M, diag M) lie in [1/8, 27/8]: the
@@ -1501,11 +1564,13 @@ int step_once(ibfe_ctx& c) {
     hipLaunchKernelGGL(k_ib_interp, dim3(blocks_lin(M)), dim3(kBlock), 0, c.stream, M, c.ib_idx, c.ib_w,
                        c.UB, c.ustar, S, c.ibv[0], c.mstride, 1);
     CHECK_LAUNCH();
-    auto op = gram_op(c);
+    const bool warm = c.lam_warm;
     SolveOut so;
-    if ((rc = run_cg<double>(c, op, c.ib_nl, c.ibv[0], c.ibv[1], c.ibv[2], c.ibv[3],
-                             c.ibv[4], kScIB, P.params.ib_rtol, maxit, true, so)))
+    c.lam_warm = false;
+    if ((rc = run_ib_pcg(c, c.ibv[0], c.ibv[1], c.ibv[2], c.ibv[3], c.ibv[4], c.ibv[5], kScIB,
+                         P.params.ib_rtol, maxit, !warm, so)))
       return rc;
+    c.lam_warm = true;
     c.stats.ib_iters = so.iters;
     c.stats.ib_res = so.res;
     const int nn = int(P.sp_node.size());
@@ -1756,11 +1821,13 @@ int step_once_refined(ibfe_ctx& c) {
     hipLaunchKernelGGL(k_ib_interp, dim3(blocks_lin(M)), dim3(kBlock), 0, c.stream, M, c.ib_idx, c.ib_w,
                        c.UB, c.ustar, S, c.ibv[0], c.mstride, 1);
     CHECK_LAUNCH();
-    auto op = gram_op(c);
+    const bool warm = c.lam_warm;
     SolveOut so;
-    if ((rc = run_cg<double>(c, op, c.ib_nl, c.ibv[0], c.ibv[1], c.ibv[2], c.ibv[3],
-                             c.ibv[4], kScIB, P.params.ib_rtol, maxit, true, so)))
+    c.lam_warm = false;
+    if ((rc = run_ib_pcg(c, c.ibv[0], c.ibv[1], c.ibv[2], c.ibv[3], c.ibv[4], c.ibv[5], kScIB,
+                         P.params.ib_rtol, maxit, !warm, so)))
       return rc;
+    c.lam_warm = true;
     c.stats.ib_iters = so.iters;
     c.stats.ib_res = so.res;
     const int nn = int(P.sp_node.size());
@@ -2081,6 +2148,7 @@ int ibfe_set_state(ibfe_ctx* c, const double* u, const double* p, double t, int 
   if ((rc = copy_in(*c, c->p, 1, p, on_device))) return rc;
   c->t = t;
   c->steps = 0;
+  c->lam_warm = false;
   c->stats = ibfe_stats{};
   c->stats.t = t;
   return IBFE_OK;
@@ -2151,6 +2219,7 @@ int ibfe_apply(ibfe_ctx* c, int op, int precision, const double* x, double* y, i
   if (precision == 1 && op != IBFE_OP_MASS && op != IBFE_OP_STIFF && op != IBFE_OP_ADVDIFF)
     return fail(IBFE_EINVAL, "FP32 is available for MASS, STIFF and ADVDIFF only");
   ibfe_ctx& C = *c;
+  C.lam_warm = false;  // the IB applies use the force buffer
   const Plan& P = C.plan;
   const int nb = blocks_for(C.nchunks);
   const int sy = int(P.sy), sz = int(P.sz);

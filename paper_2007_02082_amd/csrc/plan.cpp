@@ -36,6 +36,58 @@ double delta4(double r) {
   return 0.0;
 }
 
+// Inverses of the diagonal blocks of G (kIBBlock consecutive points each): a
+// principal submatrix of the SPD G is SPD, so a Cholesky factor A = L L^T exists;
+// A^-1 = L^-T L^-1, symmetrised and rounded to FP32 (a preconditioner only shapes
+// the iteration, the solve itself stays FP64).
+static void ib_block_inverses(Plan& P) {
+  const int64_t M = P.M;
+  const int B = kIBBlock;
+  const int64_t nblk = (M + B - 1) / B;
+  P.G_binv.assign(size_t(nblk) * B * B, 0.0f);
+  std::vector<double> A(B * B), L(B * B), Li(B * B);
+  for (int64_t b = 0; b < nblk; ++b) {
+    const int64_t i0 = b * B;
+    const int n = int(std::min<int64_t>(B, M - i0));
+    std::fill(A.begin(), A.end(), 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int64_t q = P.G_ptr[i0 + i]; q < P.G_ptr[i0 + i + 1]; ++q) {
+        const int64_t k = P.G_col[q] - i0;
+        if (k >= 0 && k < n) A[i * B + k] = P.G_val[q];
+      }
+    std::fill(L.begin(), L.end(), 0.0);
+    for (int j = 0; j < n; ++j) {
+      double d = A[j * B + j];
+      for (int k = 0; k < j; ++k) d -= L[j * B + k] * L[j * B + k];
+      const double ljj = std::sqrt(std::max(d, 1e-300));
+      L[j * B + j] = ljj;
+      for (int i = j + 1; i < n; ++i) {
+        double v = A[i * B + j];
+        for (int k = 0; k < j; ++k) v -= L[i * B + k] * L[j * B + k];
+        L[i * B + j] = v / ljj;
+      }
+    }
+    // Li = L^-1 (lower triangular), column by column
+    std::fill(Li.begin(), Li.end(), 0.0);
+    for (int j = 0; j < n; ++j) {
+      Li[j * B + j] = 1.0 / L[j * B + j];
+      for (int i = j + 1; i < n; ++i) {
+        double v = 0.0;
+        for (int k = j; k < i; ++k) v -= L[i * B + k] * Li[k * B + j];
+        Li[i * B + j] = v / L[i * B + i];
+      }
+    }
+    float* out = &P.G_binv[size_t(b) * B * B];
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j <= i; ++j) {
+        double v = 0.0;  // (L^-T L^-1)_ij = sum_k Li_ki Li_kj
+        for (int k = i; k < n; ++k) v += Li[k * B + i] * Li[k * B + j];
+        out[j * B + i] = float(v);
+        out[i * B + j] = float(v);
+      }
+  }
+}
+
 int build_plan(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* params,
                const ibfe_inlet* inlet, Plan& P, std::string& err) {
   if (!grid || !params) {
@@ -410,6 +462,7 @@ int build_plan(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* para
       P.G_ptr.push_back(int64_t(P.G_col.size()));
     }
   }
+  ib_block_inverses(P);
   if (P.params.precond >= 1) {
     int rc = build_multigrid(P, err);
     if (rc) return rc;

@@ -11,7 +11,8 @@
 namespace ibfe {
 
 constexpr int kChunk = 64;      // nodes per chunk (one wavefront)
-constexpr double kLaneFill = 0.75;  // per-lane node lists below this fill of the chunks
+constexpr double kLaneFill = 0.75;
+constexpr int kIBBlock = 64;     // points per diagonal block of the force-solve preconditioner  // per-lane node lists below this fill of the chunks
 constexpr int kMaxHarmonics = 16;
 constexpr int kMaxFloating = 8; // outlet-less connected parts supported
 
@@ -96,6 +97,9 @@ struct Plan {
   std::vector<int64_t> G_ptr;        // CSR of G = I_F I_F^T (M x M)
   std::vector<int32_t> G_col;
   std::vector<double> G_val, G_diag;
+  // block-Jacobi preconditioner of the force solve: inverses of the diagonal
+  // blocks of G over kIBBlock consecutive points, [block][column j][row i]
+  std::vector<float> G_binv;
   std::vector<int32_t> sp_node;      // nodes of F inside some support
   std::vector<int64_t> sp_ptr;       // CSR rows over sp_node: (point, weight)
   std::vector<int32_t> sp_pt;
