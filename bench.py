@@ -39,7 +39,7 @@ CSRC = os.path.join(ROOT, "paper_2007_02082_amd", "csrc")
 
 
 KERNEL_SOURCES = {"pulsatile": ("kernels.hpp", "zblock.hpp"),
-                  "aneurysm": ("kernels.hpp", "composite.hpp"),
+                  "aneurysm": ("kernels.hpp", "zblock.hpp", "composite.hpp"),
                   "aorta": ("kernels.hpp", "zblock.hpp")}
 
 
@@ -253,13 +253,15 @@ def main() -> int:
     # the two matrix-free applies that carry most of the step, timed with HIP events
     kernels = {
         "pressure": {
-            "kernel": (f"k_cg_q<{tname}, OpCSym<{tname},1>> (composite Q1 stiffness apply + p.q)" if refined
+            "kernel": (f"k_cg_q_zb<{tname},1> (composite Q1 stiffness apply + p.q: fine-cell walk "
+                       "+ precomputed coarse/hanging terms)" if refined
                        else f"k_cg_q_zb<{tname},1> (masked Q1 stiffness apply + p.q)"),
             "ms": st["poisson_apply_ms"], "launches": st["poisson_applies"],
             # read p, write q per pressure node
             "alg_bytes_per_launch": (2 * bytes_per_value + bits) * n_p},
         "mass": {
-            "kernel": (f"k_cheb_gen<{tname}, OpCSym<{tname},3>, false> (composite Q1 mass Chebyshev step)"
+            "kernel": (f"k_zb_cheb<{tname}, false, 3> (composite Q1 mass Chebyshev step: fine-cell walk "
+                       "+ precomputed coarse/hanging terms)"
                        if refined else f"k_zb_cheb<{tname}, false, 3> (masked Q1 mass Chebyshev step)"),
             "ms": st["mass_apply_ms"], "launches": st["mass_applies"],
             # per free node and component: read x, b, d; write d, x

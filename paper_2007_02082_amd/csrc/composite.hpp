@@ -239,6 +239,30 @@ struct S1RhsExplicitElem {
   }
 };
 
+// extra[d][n] = coarse-element part of the row of n plus its hanging children
+// (the row terms the z-blocked fine walk does not see), at the listed nodes.
+template <typename T, int NC>
+__global__ __launch_bounds__(kBlock) void k_comp_extra(int nn, const int32_t* __restrict__ ids, OpCSym<T, NC> op,
+                                                       const T* __restrict__ x, T* __restrict__ extra,
+                                                       const KScal* sc) {
+  if (sc && sc->done) return;
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= nn) return;
+  const int n = ids[k];
+  T y[NC];
+#pragma unroll
+  for (int d = 0; d < NC; ++d) y[d] = T(0);
+  const uint32_t m = op.cmask[n];
+  if (m) {
+    const T c4[4] = {op.cc[0], op.cc[1], op.cc[2], op.cc[3]};
+#pragma unroll
+    for (int d = 0; d < NC; ++d) y[d] = apply_sym<T>(x + d * op.stride, n, m, c4, 2 * op.sy, 2 * op.sz, 2);
+  }
+  if (op.flags[n] & kFlagPar) add_children<T, NC>(op.ch, op.pw, op.yh, n, y);
+#pragma unroll
+  for (int d = 0; d < NC; ++d) extra[d * op.stride + n] = y[d];
+}
+
 // x[h] = mean of x over the 2 or 4 parents of hanging node h (nc planes).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_hang_fill(int nh, const int32_t* __restrict__ hang_ids,

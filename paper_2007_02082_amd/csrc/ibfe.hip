@@ -164,6 +164,10 @@ struct ibfe_ctx {
   double* yh64 = nullptr;
   float* yh32 = nullptr;
   FormCoefs fcc{};   // forms of the coarse elements (spacing 2h)
+  int32_t* xnodes = nullptr;  // nodes of P with kFlagExtra (coarse cells or hanging children)
+  int nxn = 0;
+  double* extra64 = nullptr;  // their extra row terms, 3 planes
+  float* extra32 = nullptr;
 
   FormCoefs fc{};
   double t = 0.0;
@@ -317,6 +321,15 @@ int setup_refined(ibfe_ctx& c) {
   if ((rc = c.field(&c.pslot, 1))) return rc;
   HIP_TRY(hipMemcpyAsync(c.pslot, P.par_slot.data(), sizeof(int32_t) * P.N, hipMemcpyHostToDevice, c.stream));
   c.nh = int(P.hang_ids.size());
+  {
+    std::vector<int32_t> xn;
+    for (int64_t n = 0; n < P.N; ++n)
+      if ((P.flags[n] & IBFE_FLAG_P) && (P.cmask[n] != 0 || P.par_slot[n] >= 0)) xn.push_back(int32_t(n));
+    c.nxn = int(xn.size());
+    if ((rc = c.upload(&c.xnodes, xn.data(), xn.size()))) return rc;
+    if ((rc = c.field(&c.extra64, 3))) return rc;
+    if (P.params.precision == 1 && (rc = c.field(&c.extra32, 3))) return rc;
+  }
   if ((rc = c.upload(&c.hang_ids, P.hang_ids.data(), P.hang_ids.size()))) return rc;
   if ((rc = c.upload(&c.hang_par, P.hang_par.data(), P.hang_par.size()))) return rc;
   if ((rc = c.upload(&c.par_ptr, P.par_ptr.data(), P.par_ptr.size()))) return rc;
@@ -414,6 +427,7 @@ int setup_device(ibfe_ctx& c) {
     uint8_t f = P.flags[n];
     if ((f & IBFE_FLAG_P) && !(f & IBFE_FLAG_PDIR)) f |= kFlagPp;
     if (P.refined && P.par_slot[n] >= 0) f |= kFlagPar;
+    if (P.refined && (f & IBFE_FLAG_P) && (P.cmask[n] != 0 || P.par_slot[n] >= 0)) f |= kFlagExtra;
     fl[n] = f;
   }
   if ((rc = c.field(&c.emask, 1))) return rc;
@@ -430,8 +444,15 @@ int setup_device(ibfe_ctx& c) {
   if ((rc = setup_node_list(c))) return rc;
   {
     // column items of the z-blocked applies: zb planes x 64 in-plane positions
+    // (on a refined lattice also the all-even nodes with unrefined cells only)
     std::vector<int> items, lanes;
-    c.zb = choose_column_items(P.emask, P.sz, P.nz + 1, items, lanes);
+    if (P.refined) {
+      std::vector<uint8_t> act(P.N);
+      for (int64_t n = 0; n < P.N; ++n) act[n] = P.emask[n] | P.cmask[n];
+      c.zb = choose_column_items(act, P.sz, P.nz + 1, items, lanes);
+    } else {
+      c.zb = choose_column_items(P.emask, P.sz, P.nz + 1, items, lanes);
+    }
     c.nzitems = int(items.size());
     if ((rc = c.upload(&c.zitems, items.data(), items.size()))) return rc;
     if ((rc = c.upload(&c.zlanes, lanes.data(), lanes.size()))) return rc;
@@ -687,6 +708,11 @@ int collect_mass_events(ibfe_ctx& c, int n) {
   return IBFE_OK;
 }
 
+// composite pressure operator: z-blocked walk (defined with the refined-lattice helpers)
+template <typename T>
+int launch_q(ibfe_ctx& c, const OpCSym<T, 1>& op, NodeList, const T* p, T* q, const KScal* sc,
+             hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+
 template <typename T, class Op>
 int run_cg(ibfe_ctx& c, const Op& op, NodeList nl, const T* b, T* x, T* r, T* p,
            T* q, int slot, double rtol, int max_iters, bool zero_guess, SolveOut& out,
@@ -905,6 +931,7 @@ struct RefBufs<double> {
   static double* yh(const ibfe_ctx& c) { return c.yh64; }
   static const double* dinvM(const ibfe_ctx& c) { return c.dinvM64; }
   static const double* dinvK(const ibfe_ctx& c) { return c.dinvK64; }
+  static double* extra(const ibfe_ctx& c) { return c.extra64; }
 };
 template <>
 struct RefBufs<float> {
@@ -912,6 +939,7 @@ struct RefBufs<float> {
   static float* yh(const ibfe_ctx& c) { return c.yh32; }
   static const float* dinvM(const ibfe_ctx& c) { return c.dinvM32; }
   static const float* dinvK(const ibfe_ctx& c) { return c.dinvK32; }
+  static float* extra(const ibfe_ctx& c) { return c.extra32; }
 };
 
 // alpha M + beta K of the composite mesh: coef(h) = alpha m(h) + beta k(h)
@@ -934,6 +962,49 @@ OpCSym<T, NC> csym_op(const ibfe_ctx& c, double alpha, double beta, uint32_t row
   op.pw = RefBufs<T>::pw(c);
   op.yh = RefBufs<T>::yh(c);
   return op;
+}
+
+// The z-blocked form of a composite symmetric operator: the fine-cell stencil
+// walked over the column items, the Jacobi diagonal D' and the extra terms of
+// the rows with coarse cells or hanging children (k_comp_extra, launched first).
+template <typename T, int NC>
+ZOp<T> zcomp_op(const ibfe_ctx& c, const OpCSym<T, NC>& o) {
+  ZOp<T> z{};
+  z.emask = o.emask;
+  z.flags = o.flags;
+  z.rowbit = o.rowbit;
+  z.sy = o.sy;
+  z.sz = o.sz;
+  z.nplanes = c.plan.nz + 1;
+  for (int t = 0; t < 4; ++t) z.c[t] = o.cf[t];
+  z.zb = c.zb;
+  z.lanes = c.zlanes;
+  z.dinv = o.dinv;
+  z.extra = RefBufs<T>::extra(c);
+  return z;
+}
+
+template <typename T, int NC>
+void launch_extra(ibfe_ctx& c, const OpCSym<T, NC>& o, const T* x, const KScal* sc) {
+  if (c.nxn == 0) return;
+  hipLaunchKernelGGL((k_comp_extra<T, NC>), dim3(blocks_lin(c.nxn)), dim3(kBlock), 0, c.stream, c.nxn,
+                     (const int32_t*)c.xnodes, o, x, RefBufs<T>::extra(c), sc);
+}
+
+// q = A p for the composite pressure operator (hanging rows already prepared).
+template <typename T>
+int launch_q(ibfe_ctx& c, const OpCSym<T, 1>& op, NodeList, const T* p, T* q, const KScal* sc,
+             hipEvent_t e0, hipEvent_t e1) {
+  launch_extra<T, 1>(c, op, p, sc);
+  const int nr = red_blocks(c.nzitems);
+  const ZOp<T> z = zcomp_op(c, op);
+  if (e0)
+    hipExtLaunchKernelGGL((k_cg_q_zb<T, 1>), dim3(nr), dim3(kBlock), 0, c.stream, e0, e1, 0,
+                          (const int*)c.zitems, c.nzitems, z, op.stride, p, q, c.partials, sc);
+  else
+    hipLaunchKernelGGL((k_cg_q_zb<T, 1>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
+                       c.nzitems, z, op.stride, p, q, c.partials, sc);
+  return nr;
 }
 
 template <typename T>
@@ -1006,7 +1077,8 @@ int run_cheb_gen(ibfe_ctx& c, const Op& op, const T* b, T* x, T* xalt, T* d, int
   T* alt = cur == x ? xalt : x;
   hipLaunchKernelGGL((k_cheb0_gen<T, Op>), dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
                      c.nl, op, b, d, cur, T(1.0 / theta), (const KScal*)nullptr);
-  const int nr = red_blocks(c.nchunks);
+  const int nr = red_blocks(c.nzitems);
+  const ZOp<T> zop = zcomp_op(c, op);
   int rc;
   T* const cur0 = cur;
   T* const alt0 = alt;
@@ -1020,14 +1092,16 @@ int run_cheb_gen(ibfe_ctx& c, const Op& op, const T* b, T* x, T* xalt, T* d, int
       if ((rc2 = pre_apply(c, op, cur, (const KScal*)nullptr))) return rc2;
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (c.timing && mass_events(c, size_t(k - 1), e0, e1)) return IBFE_EHIP;
+      constexpr int NC = Op::kNC;
+      launch_extra<T, NC>(c, op, cur, (const KScal*)nullptr);
       if (e0)
-        hipExtLaunchKernelGGL((k_cheb_gen<T, Op, false>), dim3(nr), dim3(kBlock), 0, c.stream, e0, e1, 0,
-                              c.nl, op, (const T*)cur, b, d, alt, c1, c2, c.partials,
-                              (const KScal*)nullptr);
+        hipExtLaunchKernelGGL((k_zb_cheb<T, false, NC>), dim3(nr), dim3(kBlock), 0, c.stream, e0, e1, 0,
+                              (const int*)c.zitems, c.nzitems, zop, (const T*)cur, b, d, alt, c1, c2,
+                              c.partials, (const KScal*)nullptr, op.stride, 1);
       else
-        hipLaunchKernelGGL((k_cheb_gen<T, Op, false>), dim3(nr), dim3(kBlock), 0, c.stream,
-                           c.nl, op, (const T*)cur, b, d, alt, c1, c2, c.partials,
-                           (const KScal*)nullptr);
+        hipLaunchKernelGGL((k_zb_cheb<T, false, NC>), dim3(nr), dim3(kBlock), 0, c.stream,
+                           (const int*)c.zitems, c.nzitems, zop, (const T*)cur, b, d, alt, c1, c2,
+                           c.partials, (const KScal*)nullptr, op.stride, 1);
       std::swap(cur, alt);
     }
     CHECK_LAUNCH();
@@ -1097,8 +1171,9 @@ int smooth_comp(ibfe_ctx& c, const MGDev<T>& L, const T* b, T*& x, T*& alt, int 
                 bool dot, const KScal* sc, int& nparts) {
   const Cheb ch = cheb_coefs(m);
   const auto op = csym_op<T, 1>(c, 0.0, 1.0, kMgRow, RefBufs<T>::dinvK(c));
+  const ZOp<T> zop = zcomp_op(c, op);
   using Op = OpCSym<T, 1>;
-  const int nr = red_blocks(c.nchunks), nb = blocks_for(c.nchunks);
+  const int nr = red_blocks(c.nzitems), nb = blocks_for(c.nchunks);
   int rc;
   for (int k = 0; k < m; ++k) {
     const bool last = k == m - 1;
@@ -1109,10 +1184,13 @@ int smooth_comp(ibfe_ctx& c, const MGDev<T>& L, const T* b, T*& x, T*& alt, int 
     if (k == 0 && zero_start)
       hipLaunchKernelGGL((k_cheb0_gen<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, c.nl, op, b, L.d, x, T(0), sc);
     if ((rc = pre_apply(c, op, x, sc))) return rc;
+    launch_extra<T, 1>(c, op, x, sc);
     if (last && dot)
-      hipLaunchKernelGGL((k_cheb_gen<T, Op, true>), dim3(nr), dim3(kBlock), 0, c.stream, c.nl, op, (const T*)x, b, L.d, alt, T(ch.c1[k]), T(ch.c2[k]), c.partials, sc);
+      hipLaunchKernelGGL((k_zb_cheb<T, true>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
+                         c.nzitems, zop, (const T*)x, b, L.d, alt, T(ch.c1[k]), T(ch.c2[k]), c.partials, sc);
     else
-      hipLaunchKernelGGL((k_cheb_gen<T, Op, false>), dim3(nr), dim3(kBlock), 0, c.stream, c.nl, op, (const T*)x, b, L.d, alt, T(ch.c1[k]), T(ch.c2[k]), c.partials, sc);
+      hipLaunchKernelGGL((k_zb_cheb<T, false>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
+                         c.nzitems, zop, (const T*)x, b, L.d, alt, T(ch.c1[k]), T(ch.c2[k]), c.partials, sc);
     std::swap(x, alt);
   }
   nparts = nr;
@@ -1177,8 +1255,9 @@ int vcycle(ibfe_ctx& c, std::vector<MGDev<T>>& lv, const T* r0, T* z0, const KSc
     if (A.composite) {
       const auto op = csym_op<T, 1>(c, 0.0, 1.0, kMgRow, RefBufs<T>::dinvK(c));
       if ((rc = pre_apply(c, op, cur[l], sc))) return rc;
-      hipLaunchKernelGGL((k_resid_gen<T, OpCSym<T, 1>>), dim3(blocks_for(c.nchunks)), dim3(kBlock), 0,
-                         c.stream, c.nl, op, (const T*)cur[l], b, A.r, sc);
+      launch_extra<T, 1>(c, op, cur[l], sc);
+      hipLaunchKernelGGL(k_zb_resid<T>, dim3(red_blocks(c.nzitems)), dim3(kBlock), 0, c.stream,
+                         (const int*)c.zitems, c.nzitems, zcomp_op(c, op), (const T*)cur[l], b, A.r, sc);
     } else {
       hipLaunchKernelGGL(k_zb_resid<T>, dim3(red_blocks(A.nzitems)), dim3(kBlock), 0, c.stream,
                          (const int*)A.zitems, A.nzitems, level_op(A), (const T*)cur[l], b, A.r, sc);

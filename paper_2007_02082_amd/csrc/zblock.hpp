@@ -17,6 +17,11 @@ namespace ibfe {
 
 constexpr int kZB = 8;
 
+// Node whose operator row has terms beyond the fine cells of its emask (on a
+// refined lattice: unrefined cells around it, or hanging children); their sum
+// is precomputed into op.extra before the walk.
+constexpr uint32_t kFlagExtra = 128u;
+
 // Symmetric masked operator of one grid level.
 template <typename T>
 struct ZOp {
@@ -27,6 +32,10 @@ struct ZOp {
   T c[4];
   int zb;             // planes per column item (<= kZB)
   const int* lanes;   // 64 in-plane positions per item, -1 = none
+  // refined lattice: inverse Jacobi diagonal per node (else c[0] x kept cells)
+  // and the precomputed extra terms of kFlagExtra rows (planes of the field stride)
+  const T* dinv = nullptr;
+  const T* extra = nullptr;
 };
 
 // Walk the column items of this block; epi(node, lane_ok, row, emask, Ax, x_centre).
@@ -39,7 +48,8 @@ constexpr int kZBPF = 2;
 
 template <typename T, class Epi>
 __device__ __forceinline__ void zb_walk(const int* __restrict__ items, int nitems, const ZOp<T>& op,
-                                        const T* __restrict__ x, Epi& epi) {
+                                        const T* __restrict__ x, Epi& epi,
+                                        const T* __restrict__ extra = nullptr) {
   constexpr int R = kZBPF + 3;
   const int lane = threadIdx.x & 63;
   const int sy = op.sy, sz = op.sz;
@@ -82,7 +92,8 @@ __device__ __forceinline__ void zb_walk(const int* __restrict__ items, int nitem
       // the constant stencil when every row lane has all 8 cells (non-row lanes'
       // results are discarded by the epilogues)
       const bool interior = __all((!rw) || e == 0xFFu);
-      const T y = window_apply<T>(w[k % R], w[(k + 1) % R], w[(k + 2) % R], e, interior, c);
+      T y = window_apply<T>(w[k % R], w[(k + 1) % R], w[(k + 2) % R], e, interior, c);
+      if (extra != nullptr && rw && (fl[k % R] & kFlagExtra)) y += extra[node];
       epi(node, lane_ok, rw, e, y, w[(k + 1) % R][4]);
     }
   }
@@ -104,7 +115,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_q_zb(const int* __restrict__ item
       if (ok) qd[node] = qv;
       dot[0] += double(xc) * double(qv);
     };
-    zb_walk<T>(items, nitems, op, p + d * stride, epi);
+    zb_walk<T>(items, nitems, op, p + d * stride, epi, op.extra ? op.extra + d * stride : nullptr);
   }
   block_partials<1>(dot, partials);
 }
@@ -118,7 +129,7 @@ __global__ __launch_bounds__(kBlock) void k_zb_resid(const int* __restrict__ ite
   auto epi = [&](int node, bool ok, bool rw, uint32_t, T y, T) {
     if (ok) r[node] = rw ? T(b[node] - y) : T(0);
   };
-  zb_walk<T>(items, nitems, op, x, epi);
+  zb_walk<T>(items, nitems, op, x, epi, op.extra);
 }
 
 // Chebyshev-Jacobi step on rows, NC identical components (planes of `stride`):
@@ -143,7 +154,7 @@ __global__ __launch_bounds__(kBlock) void k_zb_cheb(const int* __restrict__ item
     auto epi = [&](int node, bool ok, bool rw, uint32_t e, T y, T xc) {
       if (!ok) return;
       if (rw) {
-        const T dinv = T(1) / (c0 * T(__builtin_popcount(e)));
+        const T dinv = op.dinv ? op.dinv[node] : T(1) / (c0 * T(__builtin_popcount(e)));
         const T dold = (c1 != T(0)) ? dq[node] : T(0);
         const T dn = c1 * dold + c2 * dinv * (bq[node] - y);
         const T xn = xc + dn;
@@ -155,7 +166,7 @@ __global__ __launch_bounds__(kBlock) void k_zb_cheb(const int* __restrict__ item
         xq[node] = T(0);
       }
     };
-    zb_walk<T>(items, nitems, op, x_in + q * stride, epi);
+    zb_walk<T>(items, nitems, op, x_in + q * stride, epi, op.extra ? op.extra + q * stride : nullptr);
   }
   if (DOT) block_partials<1>(dot, partials);
 }
