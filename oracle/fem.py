@@ -10,6 +10,11 @@ assembled over the kept cells only:
     K_ij     = int grad N_i . grad N_j           (stiffness, viscous term mu (grad u, grad v))
     G_d,ij   = int N_i d_d N_j                   (weak gradient; divergence B = [G_1 G_2 G_3])
     C(a)_ij  = int N_i (a_h . grad N_j)          (advection with a_h = sum_k a_k N_k)
+    X_de,ij  = int d_e N_i d_d N_j               (the part of the strain-rate form
+               2 mu (eps(u), eps(v)) beyond mu (grad u, grad v): the viscous form of
+               the momentum equation, Section 2.1, written with eps(u) = (grad u +
+               grad u^T)/2, couples component d of the test function with
+               component e of the trial function through mu X_de)
 
 Local corner a of a cell has offsets (a & 1, (a >> 1) & 1, (a >> 2) & 1).
 """
@@ -51,6 +56,12 @@ def element_matrices(h: float):
 
     Returns Me (8,8), Ke (8,8), Ge (3,8,8) and Ce (8,8,3,8) with
     C^e(a)_{ib} = sum_{c,d} a_{c,d} Ce[i, c, d, b]."""
+    Me, Ke, Ge, Ce, _ = element_matrices_all(h)
+    return Me, Ke, Ge, Ce
+
+
+def element_matrices_all(h: float):
+    """element_matrices plus Xe (3,3,8,8): Xe[d, e, i, j] = int d_e N_i d_d N_j."""
     Nv, dNxi = _reference_shape()
     dV = (h / 2.0) ** 3
     dN = dNxi * (2.0 / h)                       # physical derivatives
@@ -58,7 +69,8 @@ def element_matrices(h: float):
     Ke = np.einsum("gad,gbd->ab", dN, dN) * dV
     Ge = np.einsum("ga,gbd->dab", Nv, dN) * dV
     Ce = np.einsum("gi,gc,gbd->icdb", Nv, Nv, dN) * dV
-    return Me, Ke, Ge, Ce
+    Xe = np.einsum("gie,gjd->deij", dN, dN) * dV
+    return Me, Ke, Ge, Ce, Xe
 
 
 def _assemble(corners: np.ndarray, local: np.ndarray, N: int) -> sp.csr_matrix:
@@ -80,10 +92,19 @@ class Operators:
     def __init__(self, sets, h: float):
         self.N = sets.in_P.size
         self.corners = sets.corners
-        self.Me, self.Ke, self.Ge, self.Ce = element_matrices(h)
+        self.Me, self.Ke, self.Ge, self.Ce, self.Xe = element_matrices_all(h)
         self.M = _assemble(self.corners, self.Me, self.N)
         self.K = _assemble(self.corners, self.Ke, self.N)
         self.G = [_assemble(self.corners, self.Ge[d], self.N) for d in range(3)]
+        self._X = None
+
+    def strain_cross(self):
+        """X[d][e] = int d_e N_i d_d N_j assembled (3 x 3 list of N x N), so that the
+        strain-rate viscous form is mu (K delta_de + X[d][e]) between test component d
+        and trial component e."""
+        if self._X is None:
+            self._X = [[_assemble(self.corners, self.Xe[d, e], self.N) for e in range(3)] for d in range(3)]
+        return self._X
 
     def advection(self, a: np.ndarray) -> sp.csr_matrix:
         """C(a) for the nodal velocity field a (3, N) (all nodes, Dirichlet values

@@ -12,6 +12,9 @@ the IB-corrected velocity):
    with explicit advection (the fully explicit convection of Eq. 13, an option):
    A = (rho/dt) M + mu K (symmetric positive definite) and the right-hand side
    also carries - rho (C(u^n) u^n)_F;
+   with the strain-rate viscous form 2 mu (eps(u), eps(v)) (an option) the three
+   components couple: block (d, e) of the operator is A delta_de + mu X_de, and
+   the three components are solved as one system;
 2.-4. BCE-IB force and velocity correction (Eqs. 15-24): u_ib = u* + I_F^T Lambda with
    (I_F I_F^T) Lambda = U_B - I u*;
 5. pressure increment (Eq. 12 with rho): K_{P'P'} Phi = -(rho/dt) (B u_ib)_{P'},
@@ -47,11 +50,17 @@ class Problem:
     """Everything that depends only on the geometry and the parameters."""
 
     def __init__(self, nx, ny, nz, h, origin, node_mask, bc_tag, X, dS, U_B, rho, mu, dt,
-                 inlet_K, inlet_omega, inlet_ids, inlet_shape, refine_cell=None, advection=0):
+                 inlet_K, inlet_omega, inlet_ids, inlet_shape, refine_cell=None, advection=0,
+                 viscous=0):
         self.nx, self.ny, self.nz, self.h = nx, ny, nz, float(h)
         if advection not in (0, 1):
             raise ValueError("advection must be 0 (semi-implicit) or 1 (explicit)")
+        if viscous not in (0, 1):
+            raise ValueError("viscous must be 0 (mu (grad u, grad v)) or 1 (2 mu (eps(u), eps(v)))")
+        if viscous == 1 and refine_cell is not None:
+            raise ValueError("the strain-rate viscous form is built on uniform grids only")
         self.advection = int(advection)
+        self.viscous = int(viscous)
         self.origin = np.asarray(origin, np.float64)
         self.mask = np.asarray(node_mask, np.uint8)
         self.rho, self.mu, self.dt = float(rho), float(mu), float(dt)
@@ -81,10 +90,10 @@ class Problem:
         self._pressure_setup()
 
     @classmethod
-    def from_case(cls, c, advection=0):
+    def from_case(cls, c, advection=0, viscous=0):
         return cls(c.nx, c.ny, c.nz, c.h, c.origin, c.node_mask, c.bc_tag, c.X, c.dS, c.U_B,
                    c.rho, c.mu, c.dt, c.inlet_K, c.inlet_omega, c.inlet_ids, c.inlet_shape,
-                   getattr(c, "refine_cell", None), advection)
+                   getattr(c, "refine_cell", None), advection, viscous)
 
     def _check_support_in_fine_band(self):
         """Reading of the refined band: the kernel support of every Lagrangian point
@@ -139,7 +148,30 @@ class Problem:
         A_FF = A[F][:, F].tocsr()
         diag = A_FF.diagonal()
         u_star = np.zeros_like(u)
-        for d in range(3):
+        if self.viscous == 1:
+            # coupled components: blocks A delta_de + mu X_de, one solve on all three
+            # (BiCGStab; CG with explicit advection, where the blocks are symmetric)
+            X = ops.strain_cross()
+            full = [[(A if d == e else sp.csr_matrix(A.shape)) + mu * X[d][e] for e in range(3)]
+                    for d in range(3)]
+            rhs = []
+            for d in range(3):
+                r = (rho / dt) * (ops.M @ u[d]) - ops.G[d] @ p
+                for e in range(3):
+                    r = r - full[d][e] @ g[e]
+                if self.advection == 1:
+                    r = r - rho * (C @ u[d])
+                rhs.append(r[F])
+            AF = sp.bmat([[full[d][e][F][:, F] for e in range(3)] for d in range(3)]).tocsr()
+            solve = krylov.bicgstab if self.advection == 0 else krylov.cg
+            x, it, res = solve(AF, np.concatenate(rhs), x0=np.concatenate([u[d][F] for d in range(3)]),
+                               diag=AF.diagonal())
+            nf = F.size
+            for d in range(3):
+                u_star[d] = g[d]
+                u_star[d][F] = x[d * nf:(d + 1) * nf]
+                iters[f"s1_{d}"], resid[f"s1_{d}"] = it, res
+        for d in range(3 if self.viscous == 0 else 0):
             rhs = (rho / dt) * (ops.M @ u[d]) - ops.G[d] @ p - A @ g[d]
             if self.advection == 0:
                 x, it, res = krylov.bicgstab(A_FF, rhs[F], x0=u[d][F], diag=diag)
