@@ -14,9 +14,6 @@ import synth
 from oracle import fem, ipcs
 
 
-def _phi(i, x):
-    return 1.0 - x if i == 0 else x
-
 
 def test_element_cross_blocks_match_tensor_products():
     h = 0.37
