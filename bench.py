@@ -200,6 +200,8 @@ def main() -> int:
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--precond", choices=["mg", "jacobi"], default="mg",
                     help="pressure preconditioner: geometric multigrid or Jacobi")
+    ap.add_argument("--viscous", choices=["laplacian", "strain"], default="laplacian",
+                    help="viscous form: mu (grad u, grad v) or the strain-rate form 2 mu (eps(u), eps(v))")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", action="store_true",
                     help="also run the same steps in FP64 mode and report the difference")
@@ -228,7 +230,8 @@ def main() -> int:
             "aorta": synth.aorta_case}[args.workload]()
     prec = 1 if args.precision == "mixed" else 0
     pc = 2 if args.precond == "mg" else 0
-    s = ibfe.Solver(**ibfe.inputs_from_case(case, precision=prec, precond=pc))
+    visc = 1 if args.viscous == "strain" else 0
+    s = ibfe.Solver(**ibfe.inputs_from_case(case, precision=prec, precond=pc, viscous=visc))
     n = s.n_u
     u0 = np.zeros(3 * n)
     p0 = np.zeros(n)
@@ -287,7 +290,7 @@ def main() -> int:
                                                       "s1_outer", "s3_outer", "s4_outer")}}
     if args.check:
         u_a, p_a, _ = s.get_state()
-        ref = ibfe.Solver(**ibfe.inputs_from_case(case, precision=0, precond=pc))
+        ref = ibfe.Solver(**ibfe.inputs_from_case(case, precision=0, precond=pc, viscous=visc))
         ref.set_state(u0, p0, 0.0)
         ref.step(args.warmup + args.steps)
         u_b, p_b, _ = ref.get_state()
@@ -312,7 +315,8 @@ def main() -> int:
         "config": {"workload": case.name, "grid": [case.nx, case.ny, case.nz], "n_nodes": case.N,
                    "refined_cells": int(case.refine_cell.sum()) if refined else 0,
                    "n_active": n_p, "lagrangian_points": case.M, "dt": case.dt,
-                   "precision": args.precision, "pressure_preconditioner": args.precond},
+                   "precision": args.precision, "pressure_preconditioner": args.precond,
+                   "viscous_form": args.viscous},
         "roofline": roof,
     }
     out.update(extra)

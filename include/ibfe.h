@@ -133,6 +133,11 @@ typedef struct ibfe_ib {
  *                 of Eq. 13 at the old velocity on the right-hand side; CG on the
  *                 symmetric (rho/dt) M + mu K)
  *   ib_rtol     : relative residual target of the IB force solve (<= 0: 1e-13)
+ *   viscous     : viscous form of the momentum equation (Section 2.1): 0 = the
+ *                 component-wise mu (grad u, grad v); 1 = the strain-rate form
+ *                 2 mu (eps(u), eps(v)), eps(u) = (grad u + grad u^T)/2, which
+ *                 couples the three components of the tentative-velocity system
+ *                 (uniform grids with advection = 0 only; IBFE_EINVAL otherwise)
  */
 typedef struct ibfe_params {
   double rho, mu, dt;
@@ -142,6 +147,7 @@ typedef struct ibfe_params {
   int32_t precond;
   int32_t advection;
   double ib_rtol;
+  int32_t viscous;
 } ibfe_params;
 
 /*
@@ -251,6 +257,8 @@ int ibfe_get_field(ibfe_ctx* ctx, int which, double* out, int on_device);
  *   IBFE_OP_DIV     y = sum_d G_d x_d  x: 3 x n_u,  y: n_p
  *   IBFE_OP_ADVDIFF y_d = A x_d with A = (rho/dt) M + rho C(u) + mu K and u the
  *                   current state velocity      x: 3 x n_u, y: 3 x n_u
+ *                   (viscous = 1: plus mu sum_c X_dc x_c, the strain-rate cross
+ *                   blocks X_dc = int d_c N_i d_d N_j)
  *   IBFE_OP_INTERP  y = I x            x: 3 x n_u,  y: M x 3 (row major)
  *   IBFE_OP_SPREAD  y = I_F^T x        x: M x 3,    y: 3 x n_u
  * precision 0 runs the FP64 kernels, 1 the FP32 kernels (MASS, STIFF, ADVDIFF;

@@ -19,6 +19,7 @@
 #include "mg.hpp"
 #include "composite.hpp"
 #include "ib_pcg.hpp"
+#include "strain.hpp"
 
 using namespace ibfe;
 
@@ -904,6 +905,18 @@ OpStencil<T, 3> stencil_op(const ibfe_ctx& c, const T* coef, uint32_t rowbit) {
   return op;
 }
 
+// The tentative-velocity operator with the strain-rate cross blocks.
+template <typename T>
+OpStencilStrain<T> strain_op(const ibfe_ctx& c, const T* coef, uint32_t rowbit) {
+  OpStencilStrain<T> op{};
+  op.base = stencil_op<T>(c, coef, rowbit);
+  op.emask = c.emask;
+  op.mu = T(c.plan.params.mu);
+  op.h = T(c.plan.h);
+  op.stride = c.stride;
+  return op;
+}
+
 OpCSR<3> gram_op(const ibfe_ctx& c) {
   OpCSR<3> op{};
   op.ptr = c.G_ptr;
@@ -1609,20 +1622,28 @@ int step_once(ibfe_ctx& c) {
                        c.flags, c.coef64, c.u, c.p, c.g, b1, S, sy, sz, cm[0], cm[1], cm[2], cm[3],
                        c.fc.g2[0], c.fc.g2[1], c.fc.g2[2]);
     CHECK_LAUNCH();
+    if (P.params.viscous == 1) {
+      hipLaunchKernelGGL(k_strain_lift, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, (const uint8_t*)c.emask,
+                         (const uint8_t*)c.flags, kFlagF, (const double*)c.g, b1, S, P.params.mu, P.h, sy, sz);
+      CHECK_LAUNCH();
+    }
     hipLaunchKernelGGL((k_masked_copy<double, double>), dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.flags, kFlagF, c.u, x1, 3, S);
     CHECK_LAUNCH();
-    auto op = stencil_op<double>(c, c.coef64, kFlagF);
     SolveOut so;
-    if (mixed) {
-      auto op32 = stencil_op<float>(c, c.coef32, kFlagF);
-      rc = run_refined(c, op, kFlagF, 3, b1, x1, c.v32[8], c.v32[9], rtol, so,
-                       [&](const float* r32, float* d32, double tol, SolveOut& o) {
-                         hipLaunchKernelGGL(k_zero<float>, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, d32, 3, S);
-                         return run_bicgstab<float>(c, op32, r32, d32, c.v32, kScS1, tol, maxit, o);
-                       });
-    } else {
-      rc = run_bicgstab<double>(c, op, b1, x1, c.w, kScS1, rtol, maxit, so);
-    }
+    auto solve = [&](const auto& op, const auto& op32) -> int {
+      if (mixed)
+        return run_refined(c, op, kFlagF, 3, b1, x1, c.v32[8], c.v32[9], rtol, so,
+                           [&](const float* r32, float* d32, double tol, SolveOut& o) {
+                             hipLaunchKernelGGL(k_zero<float>, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, d32, 3,
+                                                S);
+                             return run_bicgstab<float>(c, op32, r32, d32, c.v32, kScS1, tol, maxit, o);
+                           });
+      return run_bicgstab<double>(c, op, b1, x1, c.w, kScS1, rtol, maxit, so);
+    };
+    if (P.params.viscous == 1)
+      rc = solve(strain_op<double>(c, c.coef64, kFlagF), strain_op<float>(c, c.coef32, kFlagF));
+    else
+      rc = solve(stencil_op<double>(c, c.coef64, kFlagF), stencil_op<float>(c, c.coef32, kFlagF));
     if (rc) return rc;
     c.stats.s1_iters = so.iters;
     c.stats.s1_res = so.res;
@@ -2375,17 +2396,24 @@ int ibfe_apply(ibfe_ctx* c, int op, int precision, const double* x, double* y, i
         c32 = C.coef32;
       }
       if ((rc = build_s1(C))) return rc;
+      const bool strain = P.params.viscous == 1;
       if (precision == 0) {
-        auto o = stencil_op<double>(C, C.coef64, kFlagP);
-        hipLaunchKernelGGL((k_apply<double, 3, OpStencil<double, 3>>), dim3(nb), dim3(kBlock), 0, C.stream,
-                           C.nl, o, xin, yout);
+        if (strain)
+          hipLaunchKernelGGL((k_apply<double, 3, OpStencilStrain<double>>), dim3(nb), dim3(kBlock), 0, C.stream,
+                             C.nl, strain_op<double>(C, C.coef64, kFlagP), xin, yout);
+        else
+          hipLaunchKernelGGL((k_apply<double, 3, OpStencil<double, 3>>), dim3(nb), dim3(kBlock), 0, C.stream,
+                             C.nl, stencil_op<double>(C, C.coef64, kFlagP), xin, yout);
       } else {
         float* x32 = C.v32[0];
         float* y32 = C.v32[1];
         hipLaunchKernelGGL((k_masked_copy<double, float>), dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, xin, x32, 3, S);
-        auto o = stencil_op<float>(C, c32, kFlagP);
-        hipLaunchKernelGGL((k_apply<float, 3, OpStencil<float, 3>>), dim3(nb), dim3(kBlock), 0, C.stream,
-                           C.nl, o, x32, y32);
+        if (strain)
+          hipLaunchKernelGGL((k_apply<float, 3, OpStencilStrain<float>>), dim3(nb), dim3(kBlock), 0, C.stream,
+                             C.nl, strain_op<float>(C, c32, kFlagP), x32, y32);
+        else
+          hipLaunchKernelGGL((k_apply<float, 3, OpStencil<float, 3>>), dim3(nb), dim3(kBlock), 0, C.stream,
+                             C.nl, stencil_op<float>(C, c32, kFlagP), x32, y32);
         hipLaunchKernelGGL((k_masked_copy<float, double>), dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, y32, yout, 3, S);
       }
       CHECK_LAUNCH();

@@ -122,6 +122,14 @@ int build_plan(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* para
     return IBFE_EINVAL;
   }
   P.refined = grid->refine_cell != nullptr;
+  if (pr.viscous < 0 || pr.viscous > 1) {
+    err = "viscous must be 0 (mu (grad u, grad v)) or 1 (2 mu (eps(u), eps(v)))";
+    return IBFE_EINVAL;
+  }
+  if (pr.viscous == 1 && (P.refined || pr.advection != 0)) {
+    err = "the strain-rate viscous form is built on uniform grids with semi-implicit advection only";
+    return IBFE_EINVAL;
+  }
   if (P.refined) {
     // every node array lives on the fine lattice of spacing h/2
     if (grid->nx > (1 << 29) || grid->ny > (1 << 29) || grid->nz > (1 << 29)) {

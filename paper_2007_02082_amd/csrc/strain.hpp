@@ -1,0 +1,115 @@
+// Strain-rate viscous form on the masked uniform grid.
+//
+// The viscous stress of the momentum equation (Section 2.1) in the form
+// 2 mu (eps(u), eps(v)), eps(u) = (grad u + grad u^T)/2, equals the
+// component-wise mu (grad u, grad v) plus the cross blocks
+//   mu X_dc,   (X_dc)_{n, n+o} = sum over the kept cells shared by n and n + o of
+//              int d_c N_n d_d N_{n+o}
+// between test component d and trial component c.  On a cube of side h the
+// entry is a product of 1-D integrals: int phi_i' phi_j = s_i / 2 (s_0 = -1,
+// s_1 = +1) in the direction of the test derivative, int phi_i phi_j' = s_j / 2
+// in the direction of the trial derivative, int phi_i' phi_j' = s_i s_j / h when
+// both derivatives share a direction, and the 1-D mass h/3 or h/6 in the rest.
+// With the cell bits of emask (bit s = sx + 2 sy + 4 sz: the cell on side s of
+// the node), the node's local coordinate in cell s is 1 - s along each axis, so
+// every sign is a function of o and of the side bits, and the sums over shared
+// cells are popcounts of emask & compat(o) restricted to sides.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace ibfe {
+
+// sum over the cells in S of (1 - 2 s_a) (1 - 2 s_b) for axes a != b
+__device__ __forceinline__ int side_pair_sum(uint32_t S, int a, int b) {
+  const uint32_t a0 = S & side_mask(a, -1), a1 = S & side_mask(a, 1);
+  const uint32_t b0 = side_mask(b, -1);
+  return __builtin_popcount(a0 & b0) - __builtin_popcount(a0 & ~b0) - __builtin_popcount(a1 & b0) +
+         __builtin_popcount(a1 & ~b0);
+}
+
+// y_d += mu sum_c sum_o w_dc(o) x_c(n + o) over the 27 neighbours (the cross
+// blocks X_dc of the strain-rate form, including d = c).
+template <typename T>
+__device__ __forceinline__ void apply_strain_cross(const T* __restrict__ x, int64_t stride, int n, uint32_t e,
+                                                   T mu, T h, int sy, int sz, T (&y)[3]) {
+  const T m3 = h / T(3), m6 = h / T(6);
+#pragma unroll
+  for (int oz = -1; oz <= 1; ++oz)
+#pragma unroll
+    for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
+      for (int ox = -1; ox <= 1; ++ox) {
+        const uint32_t S = e & compat(ox, oy, oz);
+        if (S == 0u) continue;
+        const int o[3] = {ox, oy, oz};
+        const int m = n + ox + sy * oy + sz * oz;
+        const T xv[3] = {x[m], x[stride + m], x[2 * stride + m]};
+        const int cnt = __builtin_popcount(S);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          T acc = T(0);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            T w;
+            if (c == d) {
+              // int d_d N_n d_d N_{n+o}: (s s' / h) times the 1-D masses across
+              T mm = T(1);
+#pragma unroll
+              for (int f = 0; f < 3; ++f)
+                if (f != d) mm *= o[f] != 0 ? m6 : m3;
+              w = T(o[d] != 0 ? -cnt : cnt) * mm / h;
+            } else {
+              const int f = 3 - c - d;  // the remaining axis
+              int sum;
+              if (o[c] != 0 && o[d] != 0) {
+                sum = -o[c] * o[d] * cnt;
+              } else if (o[c] != 0) {
+                sum = -o[c] * (__builtin_popcount(S & side_mask(d, -1)) - __builtin_popcount(S & side_mask(d, 1)));
+              } else if (o[d] != 0) {
+                sum = o[d] * (__builtin_popcount(S & side_mask(c, -1)) - __builtin_popcount(S & side_mask(c, 1)));
+              } else {
+                sum = side_pair_sum(S, c, d);
+              }
+              w = T(sum) * (o[f] != 0 ? m6 : m3) / T(4);
+            }
+            acc += w * xv[c];
+          }
+          y[d] += mu * acc;
+        }
+      }
+}
+
+// The stored tentative-velocity stencil (identical for the three components)
+// plus the strain-rate cross blocks; Jacobi diagonal of the stored stencil (a
+// preconditioner only: the block diagonals mu X_dd are left out of it).
+template <typename T>
+struct OpStencilStrain {
+  static constexpr int kNC = 3;
+  OpStencil<T, 3> base;
+  const uint8_t* emask;
+  T mu, h;
+  int64_t stride;
+  __device__ __forceinline__ bool row(int n) const { return base.row(n); }
+  __device__ __forceinline__ void apply(int n, const T* __restrict__ x, T (&y)[3]) const {
+    base.apply(n, x, y);
+    apply_strain_cross<T>(x, stride, n, emask[n], mu, h, base.sy, base.sz, y);
+  }
+  __device__ __forceinline__ T inv_diag(int n) const { return base.inv_diag(n); }
+};
+
+// b_d -= mu sum_c (X_dc g_c) on the rows (the strain-rate part of the lifting of
+// the Dirichlet data in the tentative-velocity right-hand side).
+__global__ __launch_bounds__(kBlock) void k_strain_lift(NodeList nl, const uint8_t* __restrict__ emask,
+                                                        const uint8_t* __restrict__ flags, uint32_t rowbit,
+                                                        const double* __restrict__ g, double* __restrict__ b,
+                                                        int64_t stride, double mu, double h, int sy, int sz) {
+  const int n = chunk_node(nl);
+  if (n < 0 || !(flags[n] & rowbit)) return;
+  double y[3] = {0.0, 0.0, 0.0};
+  apply_strain_cross<double>(g, stride, n, emask[n], mu, h, sy, sz, y);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) b[d * stride + n] -= y[d];
+}
+
+}  // namespace ibfe

@@ -30,7 +30,8 @@ def rel_l2(a: np.ndarray, b: np.ndarray) -> float:
 def run_pair(case, nsteps, t0=0.0, **solver_kw):
     """Run the oracle and the GPU library from the case's initial state; returns a list
     of per-step dicts with both sides' u*, u_ib, Phi, u, p in canonical order."""
-    pr = ipcs.Problem.from_case(case, advection=solver_kw.get("advection", 0))
+    pr = ipcs.Problem.from_case(case, advection=solver_kw.get("advection", 0),
+                                viscous=solver_kw.get("viscous", 0))
     u, p = pr.initial_state(case.u0, case.p0)
     s = make_solver(case, **solver_kw)
     assert (s.node_ids() == pr.sets.P).all()

@@ -311,3 +311,42 @@ def test_step_parity_explicit_advection(make, precision, tol):
     say("case", case.name, "explicit advection, precision", precision)
     _, out = run_pair(case, 3, t0=0.05, precision=precision, precond=2, advection=1)
     _check_steps(out, tol, case.name + "/explicit")
+
+
+# ---------------------------------------------------------------------------
+# strain-rate viscous form 2 mu (eps(u), eps(v)) (components coupled in S1)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-13), (1, 2e-6)])
+def test_advection_diffusion_apply_strain(precision, tol):
+    case = _ops_case()
+    pr = ipcs.Problem.from_case(case, viscous=1)
+    s = make_solver(case, viscous=1)
+    P = pr.sets.P
+    rng = np.random.default_rng(17)
+    u = rng.standard_normal((3, P.size))
+    s.set_state(u.ravel(), np.zeros(P.size), 0.0)
+    uf = np.zeros((3, case.N))
+    uf[:, P] = u
+    A = ((pr.rho / pr.dt) * pr.ops.M + pr.rho * pr.ops.advection(uf) + pr.mu * pr.ops.K).tocsr()
+    X = pr.ops.strain_cross()
+    x = rng.standard_normal((3, P.size))
+    xf = np.zeros((3, case.N))
+    xf[:, P] = x
+    y = s.apply(ibfe.OP_ADVDIFF, x.ravel(), precision).reshape(3, -1)
+    for d in range(3):
+        ref = A @ xf[d] + pr.mu * sum(X[d][c] @ xf[c] for c in range(3))
+        bound = _bound(A, xf[d]) + pr.mu * sum(_bound(X[d][c], xf[c]) for c in range(3))
+        assert np.all(np.abs(y[d] - ref[P]) <= tol * bound[P] + 1e-300), d
+    s.close()
+
+
+@pytest.mark.parametrize("precision,tol", [(0, TOL64), (1, TOL_MIXED)])
+@pytest.mark.parametrize("make", [lambda: synth.random_blob_case(seed=3),
+                                  lambda: synth.small_cylinder(8, 16, pulsatile=True, nsteps=3),
+                                  lambda: synth.poiseuille_c1()])
+def test_step_parity_strain_rate_form(make, precision, tol):
+    case = make()
+    say("case", case.name, "strain-rate viscous form, precision", precision)
+    _, out = run_pair(case, 3, t0=0.05, precision=precision, precond=2, viscous=1)
+    _check_steps(out, tol, case.name + "/strain")
