@@ -29,10 +29,15 @@ __device__ __forceinline__ int side_pair_sum(uint32_t S, int a, int b) {
 }
 
 // y_d += mu sum_c sum_o w_dc(o) x_c(n + o) over the 27 neighbours (the cross
-// blocks X_dc of the strain-rate form, including d = c).
-template <typename T>
-__device__ __forceinline__ void apply_strain_cross(const T* __restrict__ x, int64_t stride, int n, uint32_t e,
-                                                   T mu, T h, int sy, int sz, T (&y)[3]) {
+// blocks X_dc of the strain-rate form, including d = c); with STENCIL also
+// y_d += coef_t(n) x_d(n + o), the stored stencil of plane t (one pass over the
+// neighbours: each value of x is loaded once).  With FULL every cell around the
+// node is kept: the cell sets are then compile-time constants and the weights
+// fold to constants times h.
+template <typename T, bool FULL, bool STENCIL>
+__device__ __forceinline__ void strain_cross_body(const T* __restrict__ x, int64_t stride, int n, uint32_t e,
+                                                  T mu, T h, int sy, int sz, const T* __restrict__ coef,
+                                                  T (&y)[3]) {
   const T m3 = h / T(3), m6 = h / T(6);
 #pragma unroll
   for (int oz = -1; oz <= 1; ++oz)
@@ -40,11 +45,16 @@ __device__ __forceinline__ void apply_strain_cross(const T* __restrict__ x, int6
     for (int oy = -1; oy <= 1; ++oy)
 #pragma unroll
       for (int ox = -1; ox <= 1; ++ox) {
-        const uint32_t S = e & compat(ox, oy, oz);
-        if (S == 0u) continue;
+        const uint32_t S = FULL ? compat(ox, oy, oz) : e & compat(ox, oy, oz);
+        if (!STENCIL && S == 0u) continue;
         const int o[3] = {ox, oy, oz};
         const int m = n + ox + sy * oy + sz * oz;
         const T xv[3] = {x[m], x[stride + m], x[2 * stride + m]};
+        if (STENCIL) {
+          const T w0 = coef[((ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)) * stride + n];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) y[d] += w0 * xv[d];
+        }
         const int cnt = __builtin_popcount(S);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
@@ -80,6 +90,16 @@ __device__ __forceinline__ void apply_strain_cross(const T* __restrict__ x, int6
       }
 }
 
+template <typename T, bool STENCIL>
+__device__ __forceinline__ void apply_strain_cross(const T* __restrict__ x, int64_t stride, int n, uint32_t e,
+                                                   T mu, T h, int sy, int sz, const T* __restrict__ coef,
+                                                   T (&y)[3]) {
+  if (__all(e == 0xFFu))
+    strain_cross_body<T, true, STENCIL>(x, stride, n, e, mu, h, sy, sz, coef, y);
+  else
+    strain_cross_body<T, false, STENCIL>(x, stride, n, e, mu, h, sy, sz, coef, y);
+}
+
 // The stored tentative-velocity stencil (identical for the three components)
 // plus the strain-rate cross blocks; Jacobi diagonal of the stored stencil (a
 // preconditioner only: the block diagonals mu X_dd are left out of it).
@@ -92,8 +112,8 @@ struct OpStencilStrain {
   int64_t stride;
   __device__ __forceinline__ bool row(int n) const { return base.row(n); }
   __device__ __forceinline__ void apply(int n, const T* __restrict__ x, T (&y)[3]) const {
-    base.apply(n, x, y);
-    apply_strain_cross<T>(x, stride, n, emask[n], mu, h, base.sy, base.sz, y);
+    y[0] = y[1] = y[2] = T(0);
+    apply_strain_cross<T, true>(x, stride, n, emask[n], mu, h, base.sy, base.sz, base.coef, y);
   }
   __device__ __forceinline__ T inv_diag(int n) const { return base.inv_diag(n); }
 };
@@ -107,7 +127,7 @@ __global__ __launch_bounds__(kBlock) void k_strain_lift(NodeList nl, const uint8
   const int n = chunk_node(nl);
   if (n < 0 || !(flags[n] & rowbit)) return;
   double y[3] = {0.0, 0.0, 0.0};
-  apply_strain_cross<double>(g, stride, n, emask[n], mu, h, sy, sz, y);
+  apply_strain_cross<double, false>(g, stride, n, emask[n], mu, h, sy, sz, nullptr, y);
 #pragma unroll
   for (int d = 0; d < 3; ++d) b[d * stride + n] -= y[d];
 }
