@@ -240,6 +240,20 @@ int ibfe_set_kernel_timing(ibfe_ctx* ctx, int enable);
  * results are bitwise the same either way.  Switching frees the graphs. */
 int ibfe_set_graphs(ibfe_ctx* ctx, int enable);
 
+/* Wall shear stress at the Lagrangian points for the current velocity (the
+ * paper's clinical output of Section 4, evaluated at the immersed wall points):
+ * the nodal velocity gradient by the lumped L2 projection of the Q1 gradient,
+ * g_de = (G_e u_d) / m with m the row sum of the mass matrix, its symmetric part
+ * eps interpolated to each point with the kernel of Eq. 18 (the weights of the
+ * IB interpolation), and the tangential part tau = t - (t . n) n of the traction
+ * t = 2 mu eps n.
+ *   normals : M x 3 row major, wall normal of each point (scaled to unit length;
+ *             host memory, or device memory with on_device = 1)
+ *   tau     : M x 3 row major output, same memory kind
+ * Uniform grids only; IBFE_EINVAL on a refined grid or without points.  Uses the
+ * context's work space and synchronizes its stream. */
+int ibfe_wall_shear(ibfe_ctx* ctx, const double* normals, double* tau, int on_device);
+
 /* Intermediate fields of the last step, canonical order:
  *   IBFE_FIELD_USTAR (3 x n_u)  tentative velocity after the first sub-step
  *   IBFE_FIELD_UIB   (3 x n_u)  velocity after the IB correction

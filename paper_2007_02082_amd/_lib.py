@@ -102,6 +102,7 @@ SIGNATURES = {
     "ibfe_set_graphs": (C.c_int, [C.c_void_p, C.c_int]),
     "ibfe_get_field": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int]),
     "ibfe_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
+    "ibfe_wall_shear": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "ibfe_destroy": (None, [C.c_void_p]),
     "ibfe_last_error": (C.c_char_p, []),
     "ibfe_request_footprint": (C.c_int, [C.POINTER(Request), C.POINTER(C.c_size_t)]),
@@ -351,6 +352,13 @@ class Solver:
         out = np.empty(n)
         check(load().ibfe_get_field(self._h, int(which), C.c_void_p(out.ctypes.data), 0))
         return out if which == FIELD_PHI else out.reshape(3, self.n_u)
+
+    def wall_shear(self, normals: np.ndarray) -> np.ndarray:
+        """(M, 3) wall shear stress at the Lagrangian points for the current velocity."""
+        n = np.ascontiguousarray(normals, np.float64).reshape(-1, 3)
+        out = np.empty_like(n)
+        check(load().ibfe_wall_shear(self._h, C.c_void_p(n.ctypes.data), C.c_void_p(out.ctypes.data), 0))
+        return out
 
     def apply(self, op: int, x: np.ndarray, precision: int = 0) -> np.ndarray:
         x = np.ascontiguousarray(x, np.float64)

@@ -20,6 +20,7 @@
 #include "composite.hpp"
 #include "ib_pcg.hpp"
 #include "strain.hpp"
+#include "wss.hpp"
 
 using namespace ibfe;
 
@@ -2311,6 +2312,36 @@ int ibfe_get_field(ibfe_ctx* c, int which, double* out, int on_device) {
     case IBFE_FIELD_PHI: return copy_out(*c, c->phi, 1, out, on_device);
     default: return fail(IBFE_EINVAL, "unknown field");
   }
+}
+
+int ibfe_wall_shear(ibfe_ctx* c, const double* normals, double* tau, int on_device) {
+  if (!c || !normals || !tau) return fail(IBFE_EINVAL, "NULL argument");
+  ibfe_ctx& C = *c;
+  const Plan& P = C.plan;
+  if (P.M == 0) return fail(IBFE_EINVAL, "no Lagrangian points");
+  if (P.refined) return fail(IBFE_EINVAL, "wall shear stress is built on uniform grids only");
+  const int M = int(P.M);
+  const size_t bytes = sizeof(double) * 3 * size_t(M);
+  // scratch: the strain planes in two 3-plane work fields, normals and result in
+  // the IB vectors that do not hold the force of the last step
+  double* ed = C.w[6];
+  double* eo = C.w[7];
+  const double* nrm = normals;
+  if (!on_device) {
+    HIP_TRY(hipMemcpyAsync(C.ibv[0], normals, bytes, hipMemcpyHostToDevice, C.stream));
+    nrm = C.ibv[0];
+  }
+  double* out = on_device ? tau : C.ibv[2];
+  hipLaunchKernelGGL(k_nodal_strain, dim3(blocks_for(C.nchunks)), dim3(kBlock), 0, C.stream, C.nl,
+                     (const uint8_t*)C.emask, (const uint8_t*)C.flags, (const double*)C.u, C.stride, P.h,
+                     C.fc.g2[0], C.fc.g2[1], C.fc.g2[2], int(P.sy), int(P.sz), ed, eo);
+  hipLaunchKernelGGL(k_wall_shear, dim3(blocks_lin(M)), dim3(kBlock), 0, C.stream, M, (const int32_t*)C.ib_idx,
+                     (const double*)C.ib_w, (const double*)ed, (const double*)eo, C.stride, nrm, P.params.mu,
+                     out);
+  CHECK_LAUNCH();
+  if (!on_device) HIP_TRY(hipMemcpyAsync(tau, C.ibv[2], bytes, hipMemcpyDeviceToHost, C.stream));
+  HIP_TRY(hipStreamSynchronize(C.stream));
+  return IBFE_OK;
 }
 
 int ibfe_apply(ibfe_ctx* c, int op, int precision, const double* x, double* y, int on_device) {

@@ -350,3 +350,34 @@ def test_step_parity_strain_rate_form(make, precision, tol):
     say("case", case.name, "strain-rate viscous form, precision", precision)
     _, out = run_pair(case, 3, t0=0.05, precision=precision, precond=2, viscous=1)
     _check_steps(out, tol, case.name + "/strain")
+
+
+# ---------------------------------------------------------------------------
+# wall shear stress at the Lagrangian points (survey NEXT-f2)
+# ---------------------------------------------------------------------------
+
+def _cyl_normals(case):
+    n = case.X.copy()
+    n[:, 2] = 0.0
+    return n / np.linalg.norm(n, axis=1)[:, None]
+
+
+@pytest.mark.parametrize("make", [lambda: synth.small_cylinder(8, 16, pulsatile=True, nsteps=3),
+                                  lambda: synth.poiseuille_c1(ic="poiseuille")])
+def test_wall_shear_parity(make):
+    from oracle import wss
+    case = make()
+    pr, out = run_pair(case, 2, t0=0.05)
+    s = make_solver(case)
+    P = pr.sets.P
+    # the state after the oracle's second step, on both sides
+    uf = np.zeros((3, case.N))
+    uf[:, P] = out[-1]["o_u"]
+    s.set_state(out[-1]["o_u"].ravel(), out[-1]["o_p"], out[-1]["o_t"])
+    n = _cyl_normals(case)
+    g = s.wall_shear(n)
+    o = wss.wall_shear(pr, uf, n)
+    err = np.abs(g - o).max() / np.abs(o).max()
+    say(case.name, "wall shear max", np.abs(o).max(), "rel err", err)
+    assert err < 1e-12
+    s.close()
