@@ -202,6 +202,8 @@ def main() -> int:
                     help="pressure preconditioner: geometric multigrid or Jacobi")
     ap.add_argument("--viscous", choices=["laplacian", "strain"], default="laplacian",
                     help="viscous form: mu (grad u, grad v) or the strain-rate form 2 mu (eps(u), eps(v))")
+    ap.add_argument("--wss", action="store_true",
+                    help="also time the wall shear stress at the Lagrangian points (after the timed steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", action="store_true",
                     help="also run the same steps in FP64 mode and report the difference")
@@ -288,6 +290,18 @@ def main() -> int:
 
     extra = {"iters_last_step": {k: st[k] for k in ("s1_iters", "ib_iters", "s3_iters", "s4_iters",
                                                       "s1_outer", "s3_outer", "s4_outer")}}
+    if args.wss and not refined:
+        # unit normals from the vessel axis of the point's tube (timing only: any unit vectors do)
+        nrm = case.X - case.X.mean(axis=0)
+        nrm[:, 2] = 0.0
+        nrm /= np.maximum(np.linalg.norm(nrm, axis=1), 1e-30)[:, None]
+        s.wall_shear(nrm)
+        torch.cuda.synchronize()
+        t0w = time.perf_counter()
+        for _ in range(5):
+            tau = s.wall_shear(nrm)
+        extra["wall_shear_ms"] = round(1e3 * (time.perf_counter() - t0w) / 5, 3)
+        extra["wall_shear_max"] = float(np.abs(tau).max())
     if args.check:
         u_a, p_a, _ = s.get_state()
         ref = ibfe.Solver(**ibfe.inputs_from_case(case, precision=0, precond=pc, viscous=visc))
