@@ -1287,7 +1287,7 @@ int vcycle(ibfe_ctx& c, std::vector<MGDev<T>>& lv, const T* r0, T* z0, const KSc
     const T* b = L == 1 ? r0 : C.b;
     if (C.m > 0) {
       if (L == 1) cur[0] = z0;  // single level: the dense solve is the whole cycle
-      hipLaunchKernelGGL(k_mg_dense<T>, dim3((C.m + kBlock - 1) / kBlock), dim3(kBlock), 0, c.stream, C.m,
+      hipLaunchKernelGGL(k_mg_dense<T>, dim3((C.m + 63) / 64), dim3(kBlock), 0, c.stream, C.m,
                          (const int64_t*)C.ids, (const T*)C.inv, b, cur[L - 1], sc);
       if (L == 1) {
         np = red_blocks(C.nchunks);

@@ -102,28 +102,36 @@ __global__ __launch_bounds__(kBlock) void k_mg_prolong(NodeList nl,
   xf[n] += acc;
 }
 
-// Coarsest level: x[u_i] = sum_j inv[i][j] b[u_j]; one thread per row, every
-// workgroup stages b in LDS (m <= 1024).
+// Coarsest level: x[u_i] = sum_j inv[i][j] b[u_j] (m <= 1024, inv column major).
+// Workgroup g forms rows 64 g .. 64 g + 63: its four wavefronts take a quarter of
+// the columns each (lane = row, coalesced along the column) and the four partial
+// sums are added in LDS in a fixed order.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_mg_dense(int m, const int64_t* __restrict__ ids,
                                                      const T* __restrict__ inv, const T* __restrict__ b,
                                                      T* __restrict__ x, const KScal* sc) {
+  static_assert(kWaves == 4, "four partial sums per row");
   if (sc->done) return;
   __shared__ T bs[1024];
+  __shared__ T part[kWaves][64];
   for (int j = threadIdx.x; j < m; j += kBlock) bs[j] = b[ids[j]];
   __syncthreads();
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= m) return;
-  T acc0 = T(0), acc1 = T(0), acc2 = T(0), acc3 = T(0);
-  int j = 0;
-  for (; j + 3 < m; j += 4) {
-    acc0 += inv[int64_t(j) * m + i] * bs[j];
-    acc1 += inv[int64_t(j + 1) * m + i] * bs[j + 1];
-    acc2 += inv[int64_t(j + 2) * m + i] * bs[j + 2];
-    acc3 += inv[int64_t(j + 3) * m + i] * bs[j + 3];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  const int jc = (m + kWaves - 1) / kWaves;
+  const int j0 = wave * jc, j1 = min(m, j0 + jc);
+  T acc0 = T(0), acc1 = T(0);
+  if (i < m) {
+    int j = j0;
+    for (; j + 1 < j1; j += 2) {
+      acc0 += inv[int64_t(j) * m + i] * bs[j];
+      acc1 += inv[int64_t(j + 1) * m + i] * bs[j + 1];
+    }
+    if (j < j1) acc0 += inv[int64_t(j) * m + i] * bs[j];
   }
-  for (; j < m; ++j) acc0 += inv[int64_t(j) * m + i] * bs[j];
-  x[ids[i]] = (acc0 + acc1) + (acc2 + acc3);
+  part[wave][lane] = acc0 + acc1;
+  __syncthreads();
+  if (wave == 0 && i < m) x[ids[i]] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
 }
 
 // partials of a.b over rows
