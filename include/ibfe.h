@@ -126,7 +126,7 @@ typedef struct ibfe_ib {
  *   precond     : preconditioner of the pressure increment CG (Jacobi for the
  *                 other solves): 0 = Jacobi; 1 = Chebyshev-Jacobi polynomial of
  *                 degree 16 on [lambda_max/4, lambda_max] of D^-1 K with the bound
- *                 lambda_max = 2; 2 = geometric multigrid V(2,2) cycle with
+ *                 lambda_max = 2; 2 = geometric multigrid V(1,1) cycle with
  *                 Chebyshev-Jacobi smoothing and a dense coarsest solve
  *   advection   : 0 = semi-implicit u^n . grad u* (BiCGStab on the advection-
  *                 diffusion operator); 1 = explicit u^n . grad u^n (the convection

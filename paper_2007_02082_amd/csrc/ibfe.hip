@@ -1155,7 +1155,7 @@ Cheb cheb_coefs(int m) {
   return ch;
 }
 
-constexpr int kSmooth = 2;        // Chebyshev degree of pre- and post-smoothing
+constexpr int kSmooth = 1;        // Chebyshev degree of pre- and post-smoothing
 constexpr int kCoarseSmooth = 16; // coarsest-level smoothing when no dense inverse; with a
                                   // single level this is the Chebyshev preconditioner
 
