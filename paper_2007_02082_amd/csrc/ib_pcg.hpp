@@ -12,49 +12,11 @@
 
 namespace ibfe {
 
-// q = G p (three components) and partial p.q.  kIBLanes consecutive lanes share
-// a row of the CSR matrix (about 25 entries for wall points 1.5 h apart), each
-// taking every kIBLanes-th entry, and are summed by shuffles: short dependent
-// chains and kIBLanes times the wavefronts of a row-per-lane walk.
+// kIBLanes consecutive lanes share a row of the CSR matrix of G (about 25 entries
+// for wall points 1.5 h apart), each taking every kIBLanes-th entry, summed by
+// shuffles: short dependent chains and kIBLanes times the wavefronts of a
+// row-per-lane walk.
 constexpr int kIBLanes = 8;
-
-__global__ __launch_bounds__(kBlock) void k_ibcg_q(int M, const int64_t* __restrict__ ptr,
-                                                   const int32_t* __restrict__ col,
-                                                   const double* __restrict__ val, int64_t stride,
-                                                   const double* __restrict__ p, double* __restrict__ q,
-                                                   double* __restrict__ partials, const KScal* sc) {
-  if (sc->done) return;
-  constexpr int kRows = kBlock / kIBLanes;
-  double v[1] = {0.0};
-  const int sub = threadIdx.x % kIBLanes;
-  for (int r0 = blockIdx.x * kRows; r0 < M; r0 += gridDim.x * kRows) {
-    const int row = r0 + int(threadIdx.x) / kIBLanes;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    if (row < M) {
-      const int64_t e = ptr[row + 1];
-      for (int64_t k = ptr[row] + sub; k < e; k += kIBLanes) {
-        const double w = val[k];
-        const int c = col[k];
-        a0 += w * p[c];
-        a1 += w * p[stride + c];
-        a2 += w * p[2 * stride + c];
-      }
-    }
-#pragma unroll
-    for (int off = kIBLanes / 2; off > 0; off >>= 1) {
-      a0 += __shfl_xor(a0, off, 64);
-      a1 += __shfl_xor(a1, off, 64);
-      a2 += __shfl_xor(a2, off, 64);
-    }
-    if (row < M && sub == 0) {
-      q[row] = a0;
-      q[stride + row] = a1;
-      q[2 * stride + row] = a2;
-      v[0] += p[row] * a0 + p[stride + row] * a1 + p[2 * stride + row] * a2;
-    }
-  }
-  block_partials<1>(v, partials);
-}
 
 // r = b - G x (x = 0 with zero_guess); partials r.r, b.b
 __global__ __launch_bounds__(kBlock) void k_ibcg_init(NodeList nl, OpCSR<3> op, const double* __restrict__ b,
@@ -112,43 +74,124 @@ __global__ __launch_bounds__(kBlock) void k_ib_bjac(int M, int nblk, const float
   block_partials<1>(v, partials);
 }
 
-// x += alpha p, r -= alpha q; partial r.r
-__global__ __launch_bounds__(kBlock) void k_ibcg_xr(NodeList nl, int M, int64_t stride, double* __restrict__ x,
-                                                    double* __restrict__ r, const double* __restrict__ p,
-                                                    const double* __restrict__ q, double* __restrict__ partials,
-                                                    const KScal* sc) {
+// ---- fused iteration: four kernels per CG step --------------------------------
+// (1) k_ibcg_qp: p_new = z + beta p_old (the search direction, written by its
+//     row) and q = G p_new with p_new formed on the fly from z and p_old for the
+//     neighbours (p ping-pongs between two buffers, so no row reads a value
+//     being overwritten); partial p_new.q;  (2) k_fin_cg_q: alpha;
+// (3) k_ib_xr_bjac: x += alpha p_new, r -= alpha q and z = blockdiag(G)^-1 r on
+//     each block of points; partials r.r and r.z;  (4) k_fin_ibcg: convergence
+//     test on r.r, beta from r.z.
+
+__global__ __launch_bounds__(kBlock) void k_ibcg_qp(int M, const int64_t* __restrict__ ptr,
+                                                    const int32_t* __restrict__ col,
+                                                    const double* __restrict__ val, int64_t stride,
+                                                    const double* __restrict__ z, const double* __restrict__ pold,
+                                                    double* __restrict__ pnew, double* __restrict__ q,
+                                                    double* __restrict__ partials, const KScal* sc) {
   if (sc->done) return;
-  const double alpha = sc->alpha;
+  constexpr int kRows = kBlock / kIBLanes;
+  const double beta = sc->beta;
   double v[1] = {0.0};
-  const ChunkRange cr = block_chunks(nl.n);
-  for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
-    const int n = nl.node(c);
-    if (n >= M) continue;
+  const int sub = threadIdx.x % kIBLanes;
+  for (int r0 = blockIdx.x * kRows; r0 < M; r0 += gridDim.x * kRows) {
+    const int row = r0 + int(threadIdx.x) / kIBLanes;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    if (row < M) {
+      const int64_t e = ptr[row + 1];
+      for (int64_t k = ptr[row] + sub; k < e; k += kIBLanes) {
+        const double w = val[k];
+        const int c = col[k];
+        a0 += w * (z[c] + beta * pold[c]);
+        a1 += w * (z[stride + c] + beta * pold[stride + c]);
+        a2 += w * (z[2 * stride + c] + beta * pold[2 * stride + c]);
+      }
+    }
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const int64_t i = d * stride + n;
-      x[i] += alpha * p[i];
-      const double ri = r[i] - alpha * q[i];
-      r[i] = ri;
-      v[0] += ri * ri;
+    for (int off = kIBLanes / 2; off > 0; off >>= 1) {
+      a0 += __shfl_xor(a0, off, 64);
+      a1 += __shfl_xor(a1, off, 64);
+      a2 += __shfl_xor(a2, off, 64);
+    }
+    if (row < M && sub == 0) {
+      const double p0 = z[row] + beta * pold[row];
+      const double p1 = z[stride + row] + beta * pold[stride + row];
+      const double p2 = z[2 * stride + row] + beta * pold[2 * stride + row];
+      pnew[row] = p0;
+      pnew[stride + row] = p1;
+      pnew[2 * stride + row] = p2;
+      q[row] = a0;
+      q[stride + row] = a1;
+      q[2 * stride + row] = a2;
+      v[0] += p0 * a0 + p1 * a1 + p2 * a2;
     }
   }
   block_partials<1>(v, partials);
 }
 
-// p = z + beta p
-__global__ __launch_bounds__(kBlock) void k_ibcg_p(NodeList nl, int M, int64_t stride,
-                                                   const double* __restrict__ z, double* __restrict__ p,
-                                                   const KScal* sc) {
+__global__ __launch_bounds__(kBlock) void k_ib_xr_bjac(int M, int nblk, const float* __restrict__ binv,
+                                                       double* __restrict__ x, double* __restrict__ r,
+                                                       const double* __restrict__ p, const double* __restrict__ q,
+                                                       double* __restrict__ z, int64_t stride,
+                                                       double* __restrict__ partials, const KScal* sc) {
   if (sc->done) return;
-  const double beta = sc->beta;
-  const int n = chunk_node(nl);
-  if (n < 0 || n >= M) return;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const int64_t i = d * stride + n;
-    p[i] = z[i] + beta * p[i];
+  __shared__ double rs[3][kIBBlock];
+  const double alpha = sc->alpha;
+  double v[2] = {0.0, 0.0};
+  const int t = threadIdx.x;
+  const int d = t / kIBBlock, i = t % kIBBlock;
+  for (int b = blockIdx.x; b < nblk; b += gridDim.x) {
+    const int gi = b * kIBBlock + i;
+    if (t < 3 * kIBBlock) {
+      double ri = 0.0;
+      if (gi < M) {
+        const int64_t k = d * stride + gi;
+        x[k] += alpha * p[k];
+        ri = r[k] - alpha * q[k];
+        r[k] = ri;
+        v[0] += ri * ri;
+      }
+      rs[d][i] = ri;
+    }
+    __syncthreads();
+    if (t < 3 * kIBBlock && gi < M) {
+      const float* colp = binv + size_t(b) * kIBBlock * kIBBlock + i;
+      double acc = 0.0;
+#pragma unroll 8
+      for (int j = 0; j < kIBBlock; ++j) acc += double(colp[j * kIBBlock]) * rs[d][j];
+      z[d * stride + gi] = acc;
+      v[1] += rs[d][i] * acc;
+    }
+    __syncthreads();
   }
+  block_partials<2>(v, partials);
+}
+
+// r.r -> iteration count and convergence test; r.z -> beta (breakdown if r.z <= 0)
+__global__ __launch_bounds__(kBlock) void k_fin_ibcg(const double* __restrict__ partials, int nb, KScal* sc) {
+  if (sc->done) return;
+  double tot[2];
+  sum_partials<2>(partials, nb, tot);
+  if (threadIdx.x != 0) return;
+  const double rr = tot[0], rz = tot[1];
+  sc->rr = rr;
+  sc->iters += 1;
+  if (bad(rr) || bad(rz)) {
+    sc->status = 2;
+    sc->done = 1;
+    return;
+  }
+  if (rr <= sc->tol2 * sc->bb || sc->iters >= sc->max_iters) {
+    sc->done = 1;
+    return;
+  }
+  if (!(rz > 0.0)) {
+    sc->status = 1;
+    sc->done = 1;
+    return;
+  }
+  sc->beta = rz / sc->rz;
+  sc->rz = rz;
 }
 
 }  // namespace ibfe

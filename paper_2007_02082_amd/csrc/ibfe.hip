@@ -132,7 +132,7 @@ struct ibfe_ctx {
   int64_t* sp_ptr = nullptr;
   int32_t* sp_pt = nullptr;
   double* sp_wt = nullptr;
-  double* ibv[6] = {};  // b, lam, r, p, q, z (3 planes of mstride)
+  double* ibv[7] = {};  // b, lam, r, p, q, z, p' (3 planes of mstride)
   // ibv[1] holds the force of the last step: the initial guess of the next force
   // solve (the right-hand side U_B - I u* changes little from step to step)
   bool lam_warm = false;
@@ -514,7 +514,7 @@ int setup_device(ibfe_ctx& c) {
     if ((rc = c.upload(&c.sp_ptr, P.sp_ptr.data(), P.sp_ptr.size()))) return rc;
     if ((rc = c.upload(&c.sp_pt, P.sp_pt.data(), P.sp_pt.size()))) return rc;
     if ((rc = c.upload(&c.sp_wt, P.sp_w.data(), P.sp_w.size()))) return rc;
-    for (int i = 0; i < 6; ++i) {
+    for (int i = 0; i < 7; ++i) {
       void* base = nullptr;
       if ((rc = c.dalloc(&base, sizeof(double) * 3 * c.mstride))) return rc;
       c.ibv[i] = reinterpret_cast<double*>(base);
@@ -1378,9 +1378,10 @@ int run_pcg_mg(ibfe_ctx& c, const Op& op, std::vector<MGDev<T>>& lv, const T* b,
 
 
 // Force system G Lambda = b of the IB correction (FP64): CG with the block-Jacobi
-// preconditioner of ib_pcg.hpp, from x (the last step's force) unless zero_guess.
-int run_ib_pcg(ibfe_ctx& c, const double* b, double* x, double* r, double* p, double* q, double* z,
-               int slot, double rtol, int max_iters, bool zero_guess, SolveOut& out) {
+// preconditioner of ib_pcg.hpp, from x (the last step's force) unless zero_guess;
+// four kernels per iteration, the search direction alternating between p and p2.
+int run_ib_pcg(ibfe_ctx& c, const double* b, double* x, double* r, double* p, double* p2, double* q,
+               double* z, int slot, double rtol, int max_iters, bool zero_guess, SolveOut& out) {
   const OpCSR<3> op = gram_op(c);
   const NodeList nl = c.ib_nl;
   const int M = int(c.plan.M);
@@ -1398,33 +1399,33 @@ int run_ib_pcg(ibfe_ctx& c, const double* b, double* x, double* r, double* p, do
   hipLaunchKernelGGL(k_ib_bjac, dim3(nj), dim3(kBlock), 0, c.stream, M, nblk, (const float*)c.G_binv,
                      (const double*)r, z, S, c.partials, csc);
   hipLaunchKernelGGL(k_fin_mgcg_rz, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nj, sc, 1);
-  hipLaunchKernelGGL(k_ibcg_p, dim3(nb), dim3(kBlock), 0, c.stream, nl, M, S, (const double*)z, p, csc);
+  // the first direction is z + 0 p: p must hold finite values
+  hipLaunchKernelGGL(k_zero<double>, dim3(nb), dim3(kBlock), 0, c.stream, nl, p, 3, S);
   CHECK_LAUNCH();
+  double* pb[2] = {p, p2};
+  int par = 0;  // pb[par] holds the current direction
   int launched = 0, rc;
   KScal s{};
   while (true) {
     const int batch = std::min(next_batch(c.est[slot], launched), max_iters + 1 - launched);
     auto body = [&]() -> int {
       for (int k = 0; k < batch; ++k) {
-        hipLaunchKernelGGL(k_ibcg_q, dim3(ng), dim3(kBlock), 0, c.stream, M, (const int64_t*)c.G_ptr,
-                           (const int32_t*)c.G_col, (const double*)c.G_val, S, (const double*)p, q, c.partials,
-                           csc);
+        const double* pold = pb[(par + k) % 2];
+        double* pnew = pb[(par + k + 1) % 2];
+        hipLaunchKernelGGL(k_ibcg_qp, dim3(ng), dim3(kBlock), 0, c.stream, M, (const int64_t*)c.G_ptr,
+                           (const int32_t*)c.G_col, (const double*)c.G_val, S, (const double*)z, pold, pnew, q,
+                           c.partials, csc);
         hipLaunchKernelGGL(k_fin_cg_q, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, ng, sc);
-        hipLaunchKernelGGL(k_ibcg_xr, dim3(nr), dim3(kBlock), 0, c.stream, nl, M, S, x, r, (const double*)p,
-                           (const double*)q, c.partials, csc);
-        hipLaunchKernelGGL(k_fin_mgcg_xr, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr,
-                           sc);
-        hipLaunchKernelGGL(k_ib_bjac, dim3(nj), dim3(kBlock), 0, c.stream, M, nblk, (const float*)c.G_binv,
-                           (const double*)r, z, S, c.partials, csc);
-        hipLaunchKernelGGL(k_fin_mgcg_rz, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nj,
-                           sc, 0);
-        hipLaunchKernelGGL(k_ibcg_p, dim3(nb), dim3(kBlock), 0, c.stream, nl, M, S, (const double*)z, p, csc);
+        hipLaunchKernelGGL(k_ib_xr_bjac, dim3(nj), dim3(kBlock), 0, c.stream, M, nblk, (const float*)c.G_binv,
+                           x, r, (const double*)pnew, (const double*)q, z, S, c.partials, csc);
+        hipLaunchKernelGGL(k_fin_ibcg, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nj, sc);
         CHECK_LAUNCH();
       }
       return IBFE_OK;
     };
-    if ((rc = graph_run(c, graph_key(kGsIbPcg, slot, sizeof(double), batch), body))) return rc;
+    if ((rc = graph_run(c, graph_key(kGsIbPcg, slot, sizeof(double), batch | (par << 20)), body))) return rc;
     launched += batch;
+    par = (par + batch) % 2;
     if ((rc = poll(c, slot, s))) return rc;
     if (s.done || launched > max_iters) break;
   }
@@ -1668,7 +1669,7 @@ int step_once(ibfe_ctx& c) {
     const bool warm = c.lam_warm;
     SolveOut so;
     c.lam_warm = false;
-    if ((rc = run_ib_pcg(c, c.ibv[0], c.ibv[1], c.ibv[2], c.ibv[3], c.ibv[4], c.ibv[5], kScIB,
+    if ((rc = run_ib_pcg(c, c.ibv[0], c.ibv[1], c.ibv[2], c.ibv[3], c.ibv[6], c.ibv[4], c.ibv[5], kScIB,
                          P.params.ib_rtol, maxit, !warm, so)))
       return rc;
     c.lam_warm = true;
@@ -1925,7 +1926,7 @@ int step_once_refined(ibfe_ctx& c) {
     const bool warm = c.lam_warm;
     SolveOut so;
     c.lam_warm = false;
-    if ((rc = run_ib_pcg(c, c.ibv[0], c.ibv[1], c.ibv[2], c.ibv[3], c.ibv[4], c.ibv[5], kScIB,
+    if ((rc = run_ib_pcg(c, c.ibv[0], c.ibv[1], c.ibv[2], c.ibv[3], c.ibv[6], c.ibv[4], c.ibv[5], kScIB,
                          P.params.ib_rtol, maxit, !warm, so)))
       return rc;
     c.lam_warm = true;
