@@ -250,8 +250,10 @@ int ibfe_set_graphs(ibfe_ctx* ctx, int enable);
  *   normals : M x 3 row major, wall normal of each point (scaled to unit length;
  *             host memory, or device memory with on_device = 1)
  *   tau     : M x 3 row major output, same memory kind
- * Uniform grids only; IBFE_EINVAL on a refined grid or without points.  Uses the
- * context's work space and synchronizes its stream. */
+ * On a refined lattice the gradients are the composite ones (hanging values
+ * constrained to their parents) and m the row sums of the constrained mass.
+ * IBFE_EINVAL without points.  Uses the context's work space and synchronizes
+ * its stream. */
 int ibfe_wall_shear(ibfe_ctx* ctx, const double* normals, double* tau, int on_device);
 
 /* Intermediate fields of the last step, canonical order:

@@ -169,6 +169,7 @@ struct ibfe_ctx {
   int32_t* xnodes = nullptr;  // nodes of P with kFlagExtra (coarse cells or hanging children)
   int nxn = 0;
   double* extra64 = nullptr;  // their extra row terms, 3 planes
+  double* lmass64 = nullptr;  // row sums of the constrained mass
   float* extra32 = nullptr;
 
   FormCoefs fc{};
@@ -330,6 +331,8 @@ int setup_refined(ibfe_ctx& c) {
     c.nxn = int(xn.size());
     if ((rc = c.upload(&c.xnodes, xn.data(), xn.size()))) return rc;
     if ((rc = c.field(&c.extra64, 3))) return rc;
+    if ((rc = c.field(&c.lmass64, 1))) return rc;
+    HIP_TRY(hipMemcpyAsync(c.lmass64, P.lmass.data(), sizeof(double) * P.N, hipMemcpyHostToDevice, c.stream));
     if (P.params.precision == 1 && (rc = c.field(&c.extra32, 3))) return rc;
   }
   if ((rc = c.upload(&c.hang_ids, P.hang_ids.data(), P.hang_ids.size()))) return rc;
@@ -2320,7 +2323,6 @@ int ibfe_wall_shear(ibfe_ctx* c, const double* normals, double* tau, int on_devi
   ibfe_ctx& C = *c;
   const Plan& P = C.plan;
   if (P.M == 0) return fail(IBFE_EINVAL, "no Lagrangian points");
-  if (P.refined) return fail(IBFE_EINVAL, "wall shear stress is built on uniform grids only");
   const int M = int(P.M);
   const size_t bytes = sizeof(double) * 3 * size_t(M);
   // scratch: the strain planes in two 3-plane work fields, normals and result in
@@ -2333,9 +2335,27 @@ int ibfe_wall_shear(ibfe_ctx* c, const double* normals, double* tau, int on_devi
     nrm = C.ibv[0];
   }
   double* out = on_device ? tau : C.ibv[2];
-  hipLaunchKernelGGL(k_nodal_strain, dim3(blocks_for(C.nchunks)), dim3(kBlock), 0, C.stream, C.nl,
-                     (const uint8_t*)C.emask, (const uint8_t*)C.flags, (const double*)C.u, C.stride, P.h,
-                     C.fc.g2[0], C.fc.g2[1], C.fc.g2[2], int(P.sy), int(P.sz), ed, eo);
+  if (P.refined) {
+    // composite weak gradients of each component: hanging entries filled with the
+    // parents' mean, hanging rows gathered into their parents
+    double* uc = C.w[5];
+    const int nb = blocks_for(C.nchunks);
+    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, C.stream, C.nl, 1.0, (const double*)C.u, 0.0,
+                       (const double*)C.u, uc, 3, C.stride);
+    CHECK_LAUNCH();
+    int rc;
+    if ((rc = fill_hanging<double>(C, uc, 3))) return rc;
+    double* g[3] = {C.w[2], C.w[3], C.w[4]};
+    for (int d = 0; d < 3; ++d)
+      if ((rc = comp_rows<double>(C, grad_elem(C, uc + d * C.stride), kFlagP, 0u, 1.0, g[d]))) return rc;
+    hipLaunchKernelGGL(k_strain_from_grad, dim3(nb), dim3(kBlock), 0, C.stream, C.nl, (const uint8_t*)C.flags,
+                       (const double*)g[0], (const double*)g[1], (const double*)g[2], (const double*)C.lmass64,
+                       C.stride, ed, eo);
+  } else {
+    hipLaunchKernelGGL(k_nodal_strain, dim3(blocks_for(C.nchunks)), dim3(kBlock), 0, C.stream, C.nl,
+                       (const uint8_t*)C.emask, (const uint8_t*)C.flags, (const double*)C.u, C.stride, P.h,
+                       C.fc.g2[0], C.fc.g2[1], C.fc.g2[2], int(P.sy), int(P.sz), ed, eo);
+  }
   hipLaunchKernelGGL(k_wall_shear, dim3(blocks_lin(M)), dim3(kBlock), 0, C.stream, M, (const int32_t*)C.ib_idx,
                      (const double*)C.ib_w, (const double*)ed, (const double*)eo, C.stride, nrm, P.params.mu,
                      out);

@@ -67,6 +67,9 @@ struct Plan {
   // lumped diagonals of the constrained mass and stiffness forms (refined only):
   // d'(n) = a_nn + sum over hanging children h of w_h a_hh
   std::vector<double> dmass, dstiff;
+  // row sums of the constrained mass C^T M C (the lumped mass of the wall-shear
+  // gradient recovery; refined only)
+  std::vector<double> lmass;
   double mass_lmin = 0.125;      // lower bound of eig(D'^-1 M) on F
   int64_t N = 0;                 // grid nodes
   int64_t sy = 0, sz = 0;        // id strides in y and z

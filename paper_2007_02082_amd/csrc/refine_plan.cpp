@@ -148,6 +148,16 @@ void composite_diagonals(Plan& P) {
     P.dmass[n] = mf * ef + mc * ec;
     P.dstiff[n] = kf * ef + kc * ec;
   }
+  // row sums: each kept cell gives an eighth of its volume to each of its corners
+  P.lmass.assign(N, 0.0);
+  for (int64_t n = 0; n < N; ++n) {
+    if (!(P.flags[n] & IBFE_FLAG_P)) continue;
+    P.lmass[n] = (hf * hf * hf / 8.0) * __builtin_popcount(P.emask[n]) +
+                 (hc * hc * hc / 8.0) * __builtin_popcount(P.cmask[n]);
+  }
+  for (size_t s = 0; s < P.par_ids.size(); ++s)
+    for (int32_t q = P.par_ptr[s]; q < P.par_ptr[s + 1]; ++q)
+      P.lmass[P.par_ids[s]] += P.par_w[q] * (hf * hf * hf / 8.0) * __builtin_popcount(P.emask[P.hang_ids[P.par_child[q]]]);
   std::vector<double> base_mass(P.dmass);
   for (size_t s = 0; s < P.par_ids.size(); ++s) {
     const int64_t n = P.par_ids[s];

@@ -47,6 +47,40 @@ __global__ __launch_bounds__(kBlock) void k_nodal_strain(NodeList nl, const uint
   }
 }
 
+// Refined lattice: eps from the composite weak gradients g_c = (G_0 u_c, G_1 u_c,
+// G_2 u_c) (3 planes each, hanging children already gathered) and the row sums m
+// of the constrained mass.
+__global__ __launch_bounds__(kBlock) void k_strain_from_grad(NodeList nl, const uint8_t* __restrict__ flags,
+                                                             const double* __restrict__ g0,
+                                                             const double* __restrict__ g1,
+                                                             const double* __restrict__ g2,
+                                                             const double* __restrict__ m, int64_t stride,
+                                                             double* __restrict__ ed, double* __restrict__ eo) {
+  const int n = chunk_node(nl);
+  if (n < 0) return;
+  double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if ((flags[n] & kFlagP) && m[n] > 0.0) {
+    const double inv_m = 1.0 / m[n];
+    const double* g[3] = {g0, g1, g2};
+    double a[3][3];  // a[d][e] = (G_e u_d) / m
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int e = 0; e < 3; ++e) a[d][e] = g[d][e * stride + n] * inv_m;
+    v[0] = a[0][0];
+    v[1] = a[1][1];
+    v[2] = a[2][2];
+    v[3] = 0.5 * (a[0][1] + a[1][0]);
+    v[4] = 0.5 * (a[0][2] + a[2][0]);
+    v[5] = 0.5 * (a[1][2] + a[2][1]);
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    ed[k * stride + n] = v[k];
+    eo[k * stride + n] = v[3 + k];
+  }
+}
+
 // tau_i = t - (t.n) n, t = 2 mu eps(X_i) n, eps(X_i) = sum_s w[s][i] eps(idx[s][i]);
 // normals and tau are M x 3 row major (the normal is scaled to unit length).
 __global__ __launch_bounds__(kBlock) void k_wall_shear(int M, const int32_t* __restrict__ idx,

@@ -153,3 +153,25 @@ def test_refined_step_parity_multigrid(make, precision, tol):
     mg_it, j_it = out[0]["stats"]["s3_iters"], out_j[0]["stats"]["s3_iters"]
     say("s3 iterations: multigrid", mg_it, "Jacobi", j_it)
     assert mg_it < j_it
+
+
+def test_refined_wall_shear_parity():
+    from oracle import wss
+    case = _cyl()
+    pr = ipcs.Problem.from_case(case)
+    s = make_solver(case)
+    P = pr.sets.P
+    rng = np.random.default_rng(41)
+    u = rng.standard_normal((3, P.size))
+    s.set_state(u.ravel(), np.zeros(P.size), 0.0)
+    uf = np.zeros((3, case.N))
+    uf[:, P] = u
+    n = case.X.copy()
+    n[:, 2] = 0.0
+    n /= np.linalg.norm(n, axis=1)[:, None]
+    g = s.wall_shear(n)
+    o = wss.wall_shear(pr, uf, n)
+    err = np.abs(g - o).max() / np.abs(o).max()
+    say("refined wall shear rel err", err)
+    assert err < 1e-12
+    s.close()

@@ -84,3 +84,19 @@ def test_plane_shear_magnitude():
     tau = wss.wall_shear(pr, u, n)
     ok = _interior_points(c, pr)
     assert np.allclose(tau[ok], np.tile([pr.mu * s_, 0.0, 0.0], (ok.sum(), 1)), rtol=0, atol=1e-14)
+
+
+def test_linear_field_exact_on_refined_lattice():
+    # every cell kept: the constrained space holds trilinear fields, the lumped
+    # projection of their gradient is exact at every node and the points' supports
+    # lie in the fine band away from the box faces
+    c = synth.refined_cylinder(8, 8, length=1.25, band=0.3, mask_all=True)
+    pr = ipcs.Problem.from_case(c)
+    rng = np.random.default_rng(8)
+    A = rng.standard_normal((3, 3))
+    u = (A @ c.node_coords().T) * pr.sets.in_P[None, :]
+    n = _normals(c)
+    tau = wss.wall_shear(pr, u, n)
+    t = pr.mu * np.einsum("de,ie->id", A + A.T, n)
+    ref = t - np.sum(t * n, axis=1)[:, None] * n
+    assert np.abs(tau - ref).max() < 1e-12 * np.abs(ref).max()
