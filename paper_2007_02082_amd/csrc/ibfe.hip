@@ -10,6 +10,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "ibfe.h"
@@ -1550,24 +1551,41 @@ int s1_explicit(ibfe_ctx& c) {
   hipLaunchKernelGGL(k_s1_rhs_explicit, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.emask,
                      c.flags, c.coef64, c.u, c.p, c.g, b1, S, int(P.sy), int(P.sz), cm[0], cm[1], cm[2], cm[3],
                      ca[0], ca[1], ca[2], ca[3], c.fc.g2[0], c.fc.g2[1], c.fc.g2[2]);
+  if (P.params.viscous == 1)
+    hipLaunchKernelGGL(k_strain_lift, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, (const uint8_t*)c.emask,
+                       (const uint8_t*)c.flags, kFlagF, (const double*)c.g, b1, S, mu, P.h, int(P.sy), int(P.sz));
   hipLaunchKernelGGL((k_masked_copy<double, double>), dim3(nb), dim3(kBlock), 0, c.stream, c.nl,
                      c.flags, kFlagF, c.u, x1, 3, S);
   CHECK_LAUNCH();
-  auto op = sym_op<double, 3>(c, ca, kFlagF);
   SolveOut so;
-  int rc;
   const int maxit = P.params.max_iters;
-  if (P.params.precision == 1) {
-    auto op32 = sym_op<float, 3>(c, ca, kFlagF);
-    float* const* v = c.v32;
-    rc = run_refined(c, op, kFlagF, 3, b1, x1, v[8], v[9], P.params.rtol, so,
-                     [&](const float* r32, float* d32, double tol, SolveOut& o) {
-                       return run_cg<float>(c, op32, c.nl, r32, d32, v[0], v[1], v[2], kScS1, tol,
-                                            maxit, true, o);
-                     });
+  auto solve = [&](const auto& op, const auto& op32) -> int {
+    if (P.params.precision == 1) {
+      float* const* v = c.v32;
+      return run_refined(c, op, kFlagF, 3, b1, x1, v[8], v[9], P.params.rtol, so,
+                         [&](const float* r32, float* d32, double tol, SolveOut& o) {
+                           return run_cg<float>(c, op32, c.nl, r32, d32, v[0], v[1], v[2], kScS1, tol,
+                                                maxit, true, o);
+                         });
+    }
+    return run_cg<double>(c, op, c.nl, b1, x1, c.w[0], c.w[1], c.w[2], kScS1, P.params.rtol, maxit, false,
+                          so);
+  };
+  int rc;
+  if (P.params.viscous == 1) {
+    auto strain = [&](auto base) {
+      using T = std::remove_reference_t<decltype(base.c[0])>;
+      OpSymStrain<T> o{};
+      o.base = base;
+      o.emask = c.emask;
+      o.mu = T(mu);
+      o.h = T(P.h);
+      o.stride = c.stride;
+      return o;
+    };
+    rc = solve(strain(sym_op<double, 3>(c, ca, kFlagF)), strain(sym_op<float, 3>(c, ca, kFlagF)));
   } else {
-    rc = run_cg<double>(c, op, c.nl, b1, x1, c.w[0], c.w[1], c.w[2], kScS1, P.params.rtol,
-                        maxit, false, so);
+    rc = solve(sym_op<double, 3>(c, ca, kFlagF), sym_op<float, 3>(c, ca, kFlagF));
   }
   if (rc) return rc;
   c.stats.s1_iters = so.iters;

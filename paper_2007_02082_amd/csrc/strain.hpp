@@ -118,6 +118,23 @@ struct OpStencilStrain {
   __device__ __forceinline__ T inv_diag(int n) const { return base.inv_diag(n); }
 };
 
+// (rho/dt) M + mu K (identical components, explicit advection) plus the
+// strain-rate cross blocks: symmetric positive definite, so CG applies.
+template <typename T>
+struct OpSymStrain {
+  static constexpr int kNC = 3;
+  OpSym<T, 3> base;
+  const uint8_t* emask;
+  T mu, h;
+  int64_t stride;
+  __device__ __forceinline__ bool row(int n) const { return base.row(n); }
+  __device__ __forceinline__ void apply(int n, const T* __restrict__ x, T (&y)[3]) const {
+    base.apply(n, x, y);
+    apply_strain_cross<T, false>(x, stride, n, emask[n], mu, h, base.sy, base.sz, nullptr, y);
+  }
+  __device__ __forceinline__ T inv_diag(int n) const { return base.inv_diag(n); }
+};
+
 // b_d -= mu sum_c (X_dc g_c) on the rows (the strain-rate part of the lifting of
 // the Dirichlet data in the tentative-velocity right-hand side).
 __global__ __launch_bounds__(kBlock) void k_strain_lift(NodeList nl, const uint8_t* __restrict__ emask,

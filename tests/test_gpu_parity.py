@@ -341,14 +341,15 @@ def test_advection_diffusion_apply_strain(precision, tol):
     s.close()
 
 
+@pytest.mark.parametrize("advection", [0, 1])
 @pytest.mark.parametrize("precision,tol", [(0, TOL64), (1, TOL_MIXED)])
 @pytest.mark.parametrize("make", [lambda: synth.random_blob_case(seed=3),
                                   lambda: synth.small_cylinder(8, 16, pulsatile=True, nsteps=3),
                                   lambda: synth.poiseuille_c1()])
-def test_step_parity_strain_rate_form(make, precision, tol):
+def test_step_parity_strain_rate_form(make, precision, tol, advection):
     case = make()
-    say("case", case.name, "strain-rate viscous form, precision", precision)
-    _, out = run_pair(case, 3, t0=0.05, precision=precision, precond=2, viscous=1)
+    say("case", case.name, "strain-rate viscous form, precision", precision, "advection", advection)
+    _, out = run_pair(case, 3, t0=0.05, precision=precision, precond=2, viscous=1, advection=advection)
     _check_steps(out, tol, case.name + "/strain")
 
 
