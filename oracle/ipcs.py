@@ -57,8 +57,6 @@ class Problem:
             raise ValueError("advection must be 0 (semi-implicit) or 1 (explicit)")
         if viscous not in (0, 1):
             raise ValueError("viscous must be 0 (mu (grad u, grad v)) or 1 (2 mu (eps(u), eps(v)))")
-        if viscous == 1 and refine_cell is not None:
-            raise ValueError("the strain-rate viscous form is built on uniform grids only")
         self.advection = int(advection)
         self.viscous = int(viscous)
         self.origin = np.asarray(origin, np.float64)

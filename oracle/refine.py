@@ -131,9 +131,11 @@ class CompositeOperators:
     def __init__(self, mesh: CompositeMesh):
         self.mesh = mesh
         self.N = mesh.N
-        Mf, Kf, Gf, Cf = fem.element_matrices(mesh.hf)
-        Mc, Kc, Gc, Cc = fem.element_matrices(mesh.h)
+        Mf, Kf, Gf, Cf, Xf = fem.element_matrices_all(mesh.hf)
+        Mc, Kc, Gc, Cc, Xc = fem.element_matrices_all(mesh.h)
         self._Cf, self._Cc = Cf, Cc
+        self._Xf, self._Xc = Xf, Xc
+        self._X = None
         C = mesh.C
 
         def both(lf, lc):
@@ -143,6 +145,16 @@ class CompositeOperators:
         self.M = both(Mf, Mc)
         self.K = both(Kf, Kc)
         self.G = [both(Gf[d], Gc[d]) for d in range(3)]
+
+    def strain_cross(self):
+        """C^T X_de C over the fine and coarse elements (3 x 3 list of N x N): the
+        cross blocks of the strain-rate viscous form on the composite mesh."""
+        if self._X is None:
+            m = self.mesh
+            self._X = [[(m.C.T @ (_assemble(m.fine, self._Xf[d, e], self.N) +
+                                  _assemble(m.coarse, self._Xc[d, e], self.N)) @ m.C).tocsr()
+                        for e in range(3)] for d in range(3)]
+        return self._X
 
     def advection(self, a: np.ndarray) -> sp.csr_matrix:
         """C^T C(a_full) C with a_full = C a (hanging values from their parents)."""

@@ -127,3 +127,39 @@ def test_strain_step_matches_dense_direct_solve(blob, advection):
     pr0 = ipcs.Problem.from_case(c, viscous=0, advection=advection)
     _, _, _, info0 = pr0.step(u, p, t)
     assert np.abs(info0.u_star - us).max() > 1e-6 * np.abs(us).max()
+
+
+def test_refined_strain_form_rigid_null_space_and_dense_step():
+    # composite mesh with every cell kept: rigid motions are in the constrained space
+    c = synth.refined_cylinder(6, 4, length=1.25 * 4 / 6, band=0.25, mask_all=True)
+    c.X = np.zeros((0, 3))      # the operator alone: no wall points needed
+    c.U_B = None
+    pr = ipcs.Problem.from_case(c, viscous=1)
+    Keps = _strain_op(pr)
+    assert abs(Keps - Keps.T).max() < 1e-14
+    xyz = c.node_coords()
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    P = pr.sets.in_P
+    zero = np.zeros(c.N)
+    for u in ((-y * P, x * P, zero), (zero, -z * P, y * P), (P * 1.0, zero, zero)):
+        r = Keps @ np.concatenate(u)
+        assert np.abs(r).max() < 1e-12
+    # a refined step equals the dense direct solve of the coupled composite system
+    cs = synth.refined_cylinder(8, 8, length=1.25, band=0.3)
+    pr = ipcs.Problem.from_case(cs, viscous=1)
+    ops, s = pr.ops, pr.sets
+    rng = np.random.default_rng(9)
+    u = np.where(s.in_P[None, :], rng.standard_normal((3, cs.N)) * 0.1, 0.0)
+    p = np.zeros(cs.N)
+    un, pn, t1, info = pr.step(u, p, 0.05)
+    F = s.F
+    g = pr.g(0.05 + pr.dt)
+    A = ((pr.rho / pr.dt) * ops.M + pr.rho * ops.advection(u) + pr.mu * ops.K).toarray()
+    X = [[ops.strain_cross()[d][e].toarray() for e in range(3)] for d in range(3)]
+    full = [[(A if d == e else 0.0) + pr.mu * X[d][e] for e in range(3)] for d in range(3)]
+    rhs = [((pr.rho / pr.dt) * (ops.M @ u[d]) - ops.G[d] @ p - sum(full[d][e] @ g[e] for e in range(3)))[F]
+           for d in range(3)]
+    big = np.block([[full[d][e][np.ix_(F, F)] for e in range(3)] for d in range(3)])
+    xs = np.linalg.solve(big, np.concatenate(rhs))
+    for d in range(3):
+        assert np.abs(info.u_star[d][F] - xs[d * F.size:(d + 1) * F.size]).max() < 1e-10 * np.abs(xs).max()
