@@ -633,6 +633,10 @@ int hang_prepare(ibfe_ctx& c, const Op& op, T* x, const KScal* sc) {
   CHECK_LAUNCH();
   return IBFE_OK;
 }
+template <typename T>
+int pre_apply(ibfe_ctx& c, const OpCStencilStrain<T>& op, T* x, const KScal* sc) {
+  return hang_prepare<T>(c, op, x, sc);
+}
 template <typename T, int NC>
 int pre_apply(ibfe_ctx& c, const OpCSym<T, NC>& op, T* x, const KScal* sc) {
   return hang_prepare<T>(c, op, x, sc);
@@ -1038,6 +1042,20 @@ OpCStencil<T, 3> cstencil_op(const ibfe_ctx& c, const T* coef, uint32_t rowbit) 
   op.ch = children_of(c);
   op.pw = RefBufs<T>::pw(c);
   op.yh = RefBufs<T>::yh(c);
+  return op;
+}
+
+// The composite tentative-velocity operator with the strain-rate cross blocks.
+template <typename T>
+OpCStencilStrain<T> cstrain_op(const ibfe_ctx& c, const T* coef, uint32_t rowbit) {
+  OpCStencilStrain<T> op{};
+  op.base = cstencil_op<T>(c, coef, rowbit);
+  op.emask = c.emask;
+  op.mu = T(c.plan.params.mu);
+  op.hf = T(c.plan.h);
+  op.hc = T(c.plan.hb);
+  op.stride = c.stride;
+  op.yh = op.base.yh;
   return op;
 }
 
@@ -1909,21 +1927,39 @@ int step_once_refined(ibfe_ctx& c) {
     f.grad = grad_elem(c, c.p);
     f.u = c.u;
     f.g = c.g;
-    if ((rc = comp_rows<double>(c, f, kFlagF, 0u, 1.0, b1))) return rc;
+    const bool strain = P.params.viscous == 1;
+    if (strain) {
+      S1RhsStrainElem fs{};
+      fs.base = f;
+      fs.emask = c.emask;
+      fs.cmask = c.cmask;
+      fs.mu = P.params.mu;
+      fs.hf = P.h;
+      fs.hc = P.hb;
+      fs.sy = int(P.sy);
+      fs.sz = int(P.sz);
+      fs.stride = c.stride;
+      if ((rc = comp_rows<double>(c, fs, kFlagF, 0u, 1.0, b1))) return rc;
+    } else if ((rc = comp_rows<double>(c, f, kFlagF, 0u, 1.0, b1))) {
+      return rc;
+    }
     hipLaunchKernelGGL((k_masked_copy<double, double>), dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.flags, kFlagF, c.u, x1, 3, S);
     CHECK_LAUNCH();
-    auto op = cstencil_op<double>(c, c.coef64, kFlagF);
     SolveOut so;
-    if (mixed) {
-      auto op32 = cstencil_op<float>(c, c.coef32, kFlagF);
-      rc = run_refined(c, op, kFlagF, 3, b1, x1, c.v32[8], c.v32[9], rtol, so,
-                       [&](const float* r32, float* d32, double tol, SolveOut& o) {
-                         hipLaunchKernelGGL(k_zero<float>, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, d32, 3, S);
-                         return run_bicgstab<float>(c, op32, r32, d32, c.v32, kScS1, tol, maxit, o);
-                       });
-    } else {
-      rc = run_bicgstab<double>(c, op, b1, x1, c.w, kScS1, rtol, maxit, so);
-    }
+    auto solve = [&](const auto& op, const auto& op32) -> int {
+      if (mixed)
+        return run_refined(c, op, kFlagF, 3, b1, x1, c.v32[8], c.v32[9], rtol, so,
+                           [&](const float* r32, float* d32, double tol, SolveOut& o) {
+                             hipLaunchKernelGGL(k_zero<float>, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, d32, 3,
+                                                S);
+                             return run_bicgstab<float>(c, op32, r32, d32, c.v32, kScS1, tol, maxit, o);
+                           });
+      return run_bicgstab<double>(c, op, b1, x1, c.w, kScS1, rtol, maxit, so);
+    };
+    if (strain)
+      rc = solve(cstrain_op<double>(c, c.coef64, kFlagF), cstrain_op<float>(c, c.coef32, kFlagF));
+    else
+      rc = solve(cstencil_op<double>(c, c.coef64, kFlagF), cstencil_op<float>(c, c.coef32, kFlagF));
     if (rc) return rc;
     c.stats.s1_iters = so.iters;
     c.stats.s1_res = so.res;
@@ -2132,6 +2168,9 @@ int apply_refined(ibfe_ctx& C, int op, int precision, double* xin, double* yout,
       if ((rc = build_s1_refined(C))) return rc;
       if (precision == 0) {
         if ((rc = fill_hanging<double>(C, xin, 3))) return rc;
+        if (P.params.viscous == 1)
+          return comp_rows<double>(C, OpElem<double, OpCStencilStrain<double>>{cstrain_op<double>(C, C.coef64, kFlagP), xin},
+                                   kFlagP, 0u, 1.0, yout);
         auto o = cstencil_op<double>(C, C.coef64, kFlagP);
         return comp_rows<double>(C, OpElem<double, OpCStencil<double, 3>>{o, xin}, kFlagP, 0u, 1.0, yout);
       }
@@ -2140,9 +2179,13 @@ int apply_refined(ibfe_ctx& C, int op, int precision, double* xin, double* yout,
       hipLaunchKernelGGL((k_masked_copy<double, float>), dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, xin, x32, 3, S);
       CHECK_LAUNCH();
       if ((rc = fill_hanging<float>(C, x32, 3))) return rc;
-      auto o = cstencil_op<float>(C, C.coef32, kFlagP);
-      if ((rc = comp_rows<float>(C, OpElem<float, OpCStencil<float, 3>>{o, x32}, kFlagP, 0u, 1.0f, y32)))
-        return rc;
+      if (P.params.viscous == 1)
+        rc = comp_rows<float>(C, OpElem<float, OpCStencilStrain<float>>{cstrain_op<float>(C, C.coef32, kFlagP), x32},
+                              kFlagP, 0u, 1.0f, y32);
+      else
+        rc = comp_rows<float>(C, OpElem<float, OpCStencil<float, 3>>{cstencil_op<float>(C, C.coef32, kFlagP), x32},
+                              kFlagP, 0u, 1.0f, y32);
+      if (rc) return rc;
       hipLaunchKernelGGL((k_masked_copy<float, double>), dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, y32, yout, 3, S);
       CHECK_LAUNCH();
       return IBFE_OK;

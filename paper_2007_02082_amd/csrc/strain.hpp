@@ -16,7 +16,7 @@
 // cells are popcounts of emask & compat(o) restricted to sides.
 #pragma once
 
-#include "kernels.hpp"
+#include "composite.hpp"
 
 namespace ibfe {
 
@@ -37,7 +37,7 @@ __device__ __forceinline__ int side_pair_sum(uint32_t S, int a, int b) {
 template <typename T, bool FULL, bool STENCIL>
 __device__ __forceinline__ void strain_cross_body(const T* __restrict__ x, int64_t stride, int n, uint32_t e,
                                                   T mu, T h, int sy, int sz, const T* __restrict__ coef,
-                                                  T (&y)[3]) {
+                                                  T (&y)[3], int st) {
   const T m3 = h / T(3), m6 = h / T(6);
 #pragma unroll
   for (int oz = -1; oz <= 1; ++oz)
@@ -48,7 +48,7 @@ __device__ __forceinline__ void strain_cross_body(const T* __restrict__ x, int64
         const uint32_t S = FULL ? compat(ox, oy, oz) : e & compat(ox, oy, oz);
         if (!STENCIL && S == 0u) continue;
         const int o[3] = {ox, oy, oz};
-        const int m = n + ox + sy * oy + sz * oz;
+        const int m = n + st * ox + sy * oy + sz * oz;
         const T xv[3] = {x[m], x[stride + m], x[2 * stride + m]};
         if (STENCIL) {
           const T w0 = coef[((ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)) * stride + n];
@@ -90,14 +90,16 @@ __device__ __forceinline__ void strain_cross_body(const T* __restrict__ x, int64
       }
 }
 
+// st = 2 with doubled sy, sz and the coarse h: the unrefined cells of a refined
+// lattice (corners at even lattice positions).
 template <typename T, bool STENCIL>
 __device__ __forceinline__ void apply_strain_cross(const T* __restrict__ x, int64_t stride, int n, uint32_t e,
                                                    T mu, T h, int sy, int sz, const T* __restrict__ coef,
-                                                   T (&y)[3]) {
+                                                   T (&y)[3], int st = 1) {
   if (__all(e == 0xFFu))
-    strain_cross_body<T, true, STENCIL>(x, stride, n, e, mu, h, sy, sz, coef, y);
+    strain_cross_body<T, true, STENCIL>(x, stride, n, e, mu, h, sy, sz, coef, y, st);
   else
-    strain_cross_body<T, false, STENCIL>(x, stride, n, e, mu, h, sy, sz, coef, y);
+    strain_cross_body<T, false, STENCIL>(x, stride, n, e, mu, h, sy, sz, coef, y, st);
 }
 
 // The stored tentative-velocity stencil (identical for the three components)
@@ -133,6 +135,56 @@ struct OpSymStrain {
     apply_strain_cross<T, false>(x, stride, n, emask[n], mu, h, base.sy, base.sz, nullptr, y);
   }
   __device__ __forceinline__ T inv_diag(int n) const { return base.inv_diag(n); }
+};
+
+// The stored composite tentative-velocity stencil (54 planes) plus the
+// strain-rate cross blocks of the fine cells (stride 1, h/2) and of the
+// unrefined cells (stride 2, h); the hanging constraint enters through the
+// element rows as for OpCStencil.
+template <typename T>
+struct OpCStencilStrain {
+  static constexpr int kNC = 3;
+  OpCStencil<T, 3> base;
+  const uint8_t* emask;
+  T mu, hf, hc;
+  int64_t stride;
+  const T* yh;  // the hanging rows (base.yh), filled before every apply
+  __device__ __forceinline__ bool row(int n) const { return base.row(n); }
+  __device__ __forceinline__ void elem(int n, const T* __restrict__ x, T (&y)[3]) const {
+    base.elem(n, x, y);
+    apply_strain_cross<T, false>(x, stride, n, emask[n], mu, hf, base.sy, base.sz, nullptr, y, 1);
+    const uint32_t m = base.cmask[n];
+    if (__any(m != 0u))
+      apply_strain_cross<T, false>(x, stride, n, m, mu, hc, 2 * base.sy, 2 * base.sz, nullptr, y, 2);
+  }
+  __device__ __forceinline__ void apply(int n, const T* __restrict__ x, T (&y)[3]) const {
+    elem(n, x, y);
+    if (base.flags[n] & kFlagPar) add_children<T, 3>(base.ch, base.pw, base.yh, n, y);
+  }
+  __device__ __forceinline__ T inv_diag(int n) const { return base.inv_diag(n); }
+};
+
+// Right-hand side of the tentative velocity with the strain-rate form on the
+// refined lattice: S1RhsElem minus mu sum_c (X_dc g_c) (the cross blocks of the
+// fine and the unrefined cells applied to the Dirichlet data).
+struct S1RhsStrainElem {
+  static constexpr int kNO = 3;
+  S1RhsElem base;
+  const uint8_t* emask;
+  const uint8_t* cmask;
+  double mu, hf, hc;
+  int sy, sz;
+  int64_t stride;
+  __device__ __forceinline__ void elem(int n, double (&y)[3]) const {
+    base.elem(n, y);
+    double ys[3] = {0.0, 0.0, 0.0};
+    apply_strain_cross<double, false>(base.g, stride, n, emask[n], mu, hf, sy, sz, nullptr, ys, 1);
+    const uint32_t m = cmask[n];
+    if (__any(m != 0u))
+      apply_strain_cross<double, false>(base.g, stride, n, m, mu, hc, 2 * sy, 2 * sz, nullptr, ys, 2);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) y[d] -= ys[d];
+  }
 };
 
 // b_d -= mu sum_c (X_dc g_c) on the rows (the strain-rate part of the lifting of

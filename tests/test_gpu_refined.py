@@ -98,6 +98,33 @@ def test_refined_advection_diffusion_apply(precision, tol):
     s.close()
 
 
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-6)])
+def test_refined_advection_diffusion_apply_strain(precision, tol):
+    # the composite operator plus the strain-rate cross blocks mu X_dc of the fine
+    # and of the unrefined cells (components coupled)
+    case = _cyl()
+    pr = ipcs.Problem.from_case(case, viscous=1)
+    s = make_solver(case, viscous=1)
+    P = pr.sets.P
+    rng = np.random.default_rng(29)
+    a = rng.standard_normal((3, P.size))
+    s.set_state(a, np.zeros(P.size), 0.0)
+    af = np.zeros((3, case.N))
+    af[:, P] = a
+    A = (case.rho / case.dt) * pr.ops.M + case.rho * pr.ops.advection(af) + case.mu * pr.ops.K
+    X = pr.ops.strain_cross()
+    x = rng.standard_normal((3, P.size))
+    xf = np.zeros((3, case.N))
+    xf[:, P] = x
+    y = s.apply(ibfe.OP_ADVDIFF, x.ravel(), precision).reshape(3, -1)
+    for d in range(3):
+        ref = A @ xf[d] + case.mu * sum(X[d][c] @ xf[c] for c in range(3))
+        e = rel_l2(y[d], ref[P])
+        say("advdiff strain", precision, d, e)
+        assert e <= tol
+    s.close()
+
+
 def _check(out, tol, label):
     for k, r in enumerate(out):
         errs = {f: rel_l2(r["g_" + f], r["o_" + f]) for f in ("ustar", "uib", "u", "p")}
@@ -175,3 +202,11 @@ def test_refined_wall_shear_parity():
     say("refined wall shear rel err", err)
     assert err < 1e-12
     s.close()
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-6)])
+def test_refined_step_parity_strain_rate_form(precision, tol):
+    case = _cyl()
+    say("case", case.name, "refined, strain-rate viscous form, precision", precision)
+    _, out = run_pair(case, 3, t0=0.05, precision=precision, precond=2, viscous=1)
+    _check(out, tol, case.name + "/strain")
