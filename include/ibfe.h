@@ -137,8 +137,7 @@ typedef struct ibfe_ib {
  *                 component-wise mu (grad u, grad v); 1 = the strain-rate form
  *                 2 mu (eps(u), eps(v)), eps(u) = (grad u + grad u^T)/2, which
  *                 couples the three components of the tentative-velocity system
- *                 (on a refined grid with advection = 0 only; advection = 1
- *                 there gives IBFE_EINVAL)
+ *                 (uniform and refined grids, either advection)
  */
 typedef struct ibfe_params {
   double rho, mu, dt;

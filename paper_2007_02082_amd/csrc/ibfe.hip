@@ -637,6 +637,10 @@ template <typename T>
 int pre_apply(ibfe_ctx& c, const OpCStencilStrain<T>& op, T* x, const KScal* sc) {
   return hang_prepare<T>(c, op, x, sc);
 }
+template <typename T>
+int pre_apply(ibfe_ctx& c, const OpCSymStrain<T>& op, T* x, const KScal* sc) {
+  return hang_prepare<T>(c, op, x, sc);
+}
 template <typename T, int NC>
 int pre_apply(ibfe_ctx& c, const OpCSym<T, NC>& op, T* x, const KScal* sc) {
   return hang_prepare<T>(c, op, x, sc);
@@ -1861,24 +1865,56 @@ int s1_explicit_refined(ibfe_ctx& c) {
   f.grad = grad_elem(c, c.p);
   f.u = c.u;
   f.g = c.g;
-  if ((rc = comp_rows<double>(c, f, kFlagF, 0u, 1.0, b1))) return rc;
+  const bool strain = P.params.viscous == 1;
+  if (strain) {
+    S1RhsStrainElem<S1RhsExplicitElem> fs{};
+    fs.base = f;
+    fs.emask = c.emask;
+    fs.cmask = c.cmask;
+    fs.mu = mu;
+    fs.hf = P.h;
+    fs.hc = P.hb;
+    fs.sy = int(P.sy);
+    fs.sz = int(P.sz);
+    fs.stride = c.stride;
+    if ((rc = comp_rows<double>(c, fs, kFlagF, 0u, 1.0, b1))) return rc;
+  } else if ((rc = comp_rows<double>(c, f, kFlagF, 0u, 1.0, b1))) {
+    return rc;
+  }
   hipLaunchKernelGGL((k_masked_copy<double, double>), dim3(nb), dim3(kBlock), 0, c.stream, c.nl,
                      c.flags, kFlagF, c.u, x1, 3, S);
   CHECK_LAUNCH();
-  auto op = csym_op<double, 3>(c, rdt, mu, kFlagF, c.dinvA64);
   SolveOut so;
   const int maxit = P.params.max_iters;
-  if (P.params.precision == 1) {
-    auto op32 = csym_op<float, 3>(c, rdt, mu, kFlagF, c.dinvA32);
-    float* const* v = c.v32;
-    rc = run_refined(c, op, kFlagF, 3, b1, x1, v[8], v[9], P.params.rtol, so,
-                     [&](const float* r32, float* d32, double tol, SolveOut& o) {
-                       return run_cg<float>(c, op32, c.nl, r32, d32, v[0], v[1], v[2], kScS1, tol,
-                                            maxit, true, o);
-                     });
+  auto solve = [&](const auto& op, const auto& op32) -> int {
+    if (P.params.precision == 1) {
+      float* const* v = c.v32;
+      return run_refined(c, op, kFlagF, 3, b1, x1, v[8], v[9], P.params.rtol, so,
+                         [&](const float* r32, float* d32, double tol, SolveOut& o) {
+                           return run_cg<float>(c, op32, c.nl, r32, d32, v[0], v[1], v[2], kScS1, tol,
+                                                maxit, true, o);
+                         });
+    }
+    return run_cg<double>(c, op, c.nl, b1, x1, c.w[0], c.w[1], c.w[2], kScS1, P.params.rtol, maxit,
+                          false, so);
+  };
+  auto op = csym_op<double, 3>(c, rdt, mu, kFlagF, c.dinvA64);
+  auto op32 = csym_op<float, 3>(c, rdt, mu, kFlagF, c.dinvA32);
+  if (strain) {
+    auto wrap = [&](const auto& base) {
+      using T = std::remove_const_t<std::remove_reference_t<decltype(base.cf[0])>>;
+      OpCSymStrain<T> o{};
+      o.base = base;
+      o.mu = T(mu);
+      o.hf = T(P.h);
+      o.hc = T(P.hb);
+      o.stride = base.stride;
+      o.yh = base.yh;
+      return o;
+    };
+    rc = solve(wrap(op), wrap(op32));
   } else {
-    rc = run_cg<double>(c, op, c.nl, b1, x1, c.w[0], c.w[1], c.w[2], kScS1, P.params.rtol,
-                        maxit, false, so);
+    rc = solve(op, op32);
   }
   if (rc) return rc;
   c.stats.s1_iters = so.iters;
@@ -1929,7 +1965,7 @@ int step_once_refined(ibfe_ctx& c) {
     f.g = c.g;
     const bool strain = P.params.viscous == 1;
     if (strain) {
-      S1RhsStrainElem fs{};
+      S1RhsStrainElem<S1RhsElem> fs{};
       fs.base = f;
       fs.emask = c.emask;
       fs.cmask = c.cmask;

@@ -126,10 +126,6 @@ int build_plan(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* para
     err = "viscous must be 0 (mu (grad u, grad v)) or 1 (2 mu (eps(u), eps(v)))";
     return IBFE_EINVAL;
   }
-  if (pr.viscous == 1 && P.refined && pr.advection != 0) {
-    err = "the strain-rate viscous form on a refined grid needs semi-implicit advection";
-    return IBFE_EINVAL;
-  }
   if (P.refined) {
     // every node array lives on the fine lattice of spacing h/2
     if (grid->nx > (1 << 29) || grid->ny > (1 << 29) || grid->nz > (1 << 29)) {

@@ -164,12 +164,39 @@ struct OpCStencilStrain {
   __device__ __forceinline__ T inv_diag(int n) const { return base.inv_diag(n); }
 };
 
+// The composite symmetric (rho/dt) M + mu K (explicit advection) plus the
+// strain-rate cross blocks of the fine and the unrefined cells: symmetric
+// positive definite on the constrained space, so CG applies.
+template <typename T>
+struct OpCSymStrain {
+  static constexpr int kNC = 3;
+  OpCSym<T, 3> base;
+  T mu, hf, hc;
+  int64_t stride;
+  const T* yh;  // the hanging rows (base.yh), filled before every apply
+  __device__ __forceinline__ bool row(int n) const { return base.row(n); }
+  __device__ __forceinline__ void elem(int n, const T* __restrict__ x, T (&y)[3]) const {
+    base.elem(n, x, y);
+    apply_strain_cross<T, false>(x, base.stride, n, base.emask[n], mu, hf, base.sy, base.sz, nullptr, y, 1);
+    const uint32_t m = base.cmask[n];
+    if (__any(m != 0u))
+      apply_strain_cross<T, false>(x, base.stride, n, m, mu, hc, 2 * base.sy, 2 * base.sz, nullptr, y, 2);
+  }
+  __device__ __forceinline__ void apply(int n, const T* __restrict__ x, T (&y)[3]) const {
+    elem(n, x, y);
+    if (base.flags[n] & kFlagPar) add_children<T, 3>(base.ch, base.pw, base.yh, n, y);
+  }
+  __device__ __forceinline__ T inv_diag(int n) const { return base.inv_diag(n); }
+};
+
 // Right-hand side of the tentative velocity with the strain-rate form on the
-// refined lattice: S1RhsElem minus mu sum_c (X_dc g_c) (the cross blocks of the
-// fine and the unrefined cells applied to the Dirichlet data).
+// refined lattice: the element rows of Rhs (S1RhsElem or S1RhsExplicitElem)
+// minus mu sum_c (X_dc g_c) (the cross blocks of the fine and the unrefined
+// cells applied to the Dirichlet data).
+template <typename Rhs>
 struct S1RhsStrainElem {
   static constexpr int kNO = 3;
-  S1RhsElem base;
+  Rhs base;
   const uint8_t* emask;
   const uint8_t* cmask;
   double mu, hf, hc;

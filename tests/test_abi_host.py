@@ -91,15 +91,14 @@ def test_input_errors():
     with pytest.raises(ibfe.IbfeError, match="EINVAL"):
         ibfe.Plan(**bad)
     ibfe.Plan(**dict(kw, advection=1, precond=1))
-    # strain-rate viscous form: 0/1 only; on a refined grid semi-implicit advection only
+    # strain-rate viscous form: 0/1 only, uniform and refined, either advection
     ibfe.Plan(**dict(kw, viscous=1))
     ibfe.Plan(**dict(kw, viscous=1, advection=1))
     with pytest.raises(ibfe.IbfeError, match="EINVAL"):
         ibfe.Plan(**dict(kw, viscous=2))
     rc = synth.refined_cylinder(8, 8, length=1.25, band=0.3)
     ibfe.Plan(**ibfe.inputs_from_case(rc, viscous=1))
-    with pytest.raises(ibfe.IbfeError, match="strain-rate"):
-        ibfe.Plan(**ibfe.inputs_from_case(rc, viscous=1, advection=1))
+    ibfe.Plan(**ibfe.inputs_from_case(rc, viscous=1, advection=1))
     # a Lagrangian point whose support holds no free node
     far = np.array([[100.0, 100.0, 100.0]])
     bad = dict(kw, X=far, U_B=None)

@@ -204,9 +204,10 @@ def test_refined_wall_shear_parity():
     s.close()
 
 
+@pytest.mark.parametrize("advection", [0, 1])
 @pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-6)])
-def test_refined_step_parity_strain_rate_form(precision, tol):
+def test_refined_step_parity_strain_rate_form(precision, tol, advection):
     case = _cyl()
-    say("case", case.name, "refined, strain-rate viscous form, precision", precision)
-    _, out = run_pair(case, 3, t0=0.05, precision=precision, precond=2, viscous=1)
+    say("case", case.name, "refined, strain-rate viscous form, precision", precision, "advection", advection)
+    _, out = run_pair(case, 3, t0=0.05, precision=precision, precond=2, viscous=1, advection=advection)
     _check(out, tol, case.name + "/strain")

@@ -163,3 +163,28 @@ def test_refined_strain_form_rigid_null_space_and_dense_step():
     xs = np.linalg.solve(big, np.concatenate(rhs))
     for d in range(3):
         assert np.abs(info.u_star[d][F] - xs[d * F.size:(d + 1) * F.size]).max() < 1e-10 * np.abs(xs).max()
+
+
+def test_refined_strain_explicit_step_matches_dense_direct_solve():
+    # explicit advection: the convection at u^n moves to the right-hand side and the
+    # coupled composite system (rho/dt) M + mu K + mu X is solved by CG
+    cs = synth.refined_cylinder(8, 8, length=1.25, band=0.3)
+    pr = ipcs.Problem.from_case(cs, viscous=1, advection=1)
+    ops, s = pr.ops, pr.sets
+    rng = np.random.default_rng(11)
+    u = np.where(s.in_P[None, :], rng.standard_normal((3, cs.N)) * 0.1, 0.0)
+    p = np.where(s.in_P, rng.standard_normal(cs.N) * 0.01, 0.0)
+    _, _, _, info = pr.step(u, p, 0.05)
+    F = s.F
+    g = pr.g(0.05 + pr.dt)
+    A = ((pr.rho / pr.dt) * ops.M + pr.mu * ops.K).toarray()
+    C = ops.advection(u)
+    X = [[ops.strain_cross()[d][e].toarray() for e in range(3)] for d in range(3)]
+    full = [[(A if d == e else 0.0) + pr.mu * X[d][e] for e in range(3)] for d in range(3)]
+    rhs = [((pr.rho / pr.dt) * (ops.M @ u[d]) - pr.rho * (C @ u[d]) - ops.G[d] @ p
+            - sum(full[d][e] @ g[e] for e in range(3)))[F] for d in range(3)]
+    big = np.block([[full[d][e][np.ix_(F, F)] for e in range(3)] for d in range(3)])
+    assert np.abs(big - big.T).max() < 1e-12 * np.abs(big).max()
+    xs = np.linalg.solve(big, np.concatenate(rhs))
+    for d in range(3):
+        assert np.abs(info.u_star[d][F] - xs[d * F.size:(d + 1) * F.size]).max() < 1e-10 * np.abs(xs).max()
