@@ -189,6 +189,64 @@ def serve_stream(n: int, slots: int, nsteps: int) -> dict:
             "wall_s": round(span, 2), "grid_nodes_total": int(sum(nodes))}
 
 
+def poiseuille_study(levels=(0, 1, 2), pressures=(1.0, 2.0), tol=1e-8, max_steps=8000) -> list:
+    """The pressure-driven tube of Section 3.1 on the three grids of Table 1 (h = 1, 0.5,
+    0.25 mm), run with the library's steady-state driver until the step-to-step NRMSE of
+    every velocity component is below tol.  Reported per run: steps, wall time, the
+    centre-line speed against U_max = R^2 p_in / (4 mu L), and the maximum and
+    root-mean-square velocity errors against the Poiseuille profile over the nodes
+    inside the tube; a run whose step fails is reported with the step it reached."""
+    import numpy as np
+
+    import paper_2007_02082_amd as ibfe
+    import synth
+    from synth import poiseuille as e1
+
+    rows = []
+    for level in levels:
+        for p_in in pressures:
+            case = synth.poiseuille_e1(level, p_in=p_in)
+            s = ibfe.Solver(**ibfe.inputs_from_case(case, precision=1, precond=2))
+            ids = s.node_ids()
+            s.set_state(np.zeros(3 * s.n_u), np.ascontiguousarray(case.p0[ids]), 0.0)
+            total, nr, err = 0, None, None
+            t0 = time.perf_counter()
+            while total < max_steps:
+                try:
+                    k, nr = s.run_steady(tol, min(500, max_steps - total))
+                except ibfe.IbfeError as e:
+                    err = str(e)
+                    break
+                total += k
+                print(f"[e1] h={case.h:g} p_in={p_in:g} steps={total} nrmse={np.max(nr):.3e}",
+                      file=sys.stderr, flush=True)
+                if np.all(nr < tol):
+                    break
+            wall = time.perf_counter() - t0
+            u, p, t = s.get_state()
+            s.close()
+            xyz = case.node_coords()[ids]
+            inside = case.node_mask[ids] == 1
+            r2 = xyz[inside, 0] ** 2 + xyz[inside, 1] ** 2
+            umax_exact = e1.R ** 2 * p_in / (4.0 * e1.MU * e1.L)
+            ex = np.zeros((3, int(inside.sum())))
+            ex[2] = umax_exact * (1.0 - r2 / e1.R ** 2)
+            e = u[:, inside] - ex
+            row = {"h": case.h, "p_in": p_in, "nodes": case.N, "n_u": int(ids.size), "M": case.M,
+                   "steps": total, "t": t, "wall_s": round(wall, 3),
+                   "steps_per_s": round(total / wall, 1) if wall > 0 else None,
+                   "steady": err is None and bool(np.all(nr < tol)),
+                   "nrmse": None if nr is None else [float(x) for x in nr],
+                   "u_max": float(u[2].max()), "u_max_exact": umax_exact,
+                   "Re": e1.RHO * float(u[2].max()) * e1.L / e1.MU,
+                   "L_inf": float(np.abs(e).max()), "L_2": float(np.sqrt((e * e).sum()) / e.shape[1]),
+                   "transverse_max": float(np.abs(u[:2]).max())}
+            if err is not None:
+                row["error"] = err
+            rows.append(row)
+    return rows
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -209,6 +267,9 @@ def main() -> int:
                     help="also run the same steps in FP64 mode and report the difference")
     ap.add_argument("--serve", action="store_true",
                     help="also run the serving stream (64 requests, Poisson arrivals at 4/s)")
+    ap.add_argument("--e1", action="store_true",
+                    help="also run the pressure-driven Poiseuille study of Section 3.1 to steady "
+                         "state on the three grids of Table 1 (after the timed steps)")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -336,6 +397,8 @@ def main() -> int:
     out.update(extra)
     if args.serve:
         out["serving"] = serve_stream(args.serve_requests, args.serve_slots, 50)
+    if args.e1:
+        out["poiseuille_e1"] = poiseuille_study()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = {"pulsatile": cpu_baseline, "aneurysm": lambda: cpu_baseline_aneurysm(n_p),
                                "aorta": lambda: cpu_baseline_aorta(n_p)}[args.workload]()

@@ -225,6 +225,18 @@ int ibfe_set_state(ibfe_ctx* ctx, const double* u, const double* p, double t, in
 /* Advance nsteps steps (Section 2.4).  On failure the state of the last
  * completed step is kept. */
 int ibfe_step(ibfe_ctx* ctx, int nsteps);
+/* Advance until the flow is steady (Section 3.1): after every step, the
+ * step-to-step normalised root-mean-square difference of each velocity
+ * component d,
+ *   L_d = sqrt(sum_i (u_d,i^{n+1} - u_d,i^n)^2 / N^2) / (max_i u_d,i^n - min_i u_d,i^n),
+ * over the N = n_u nodes of P (a component with max = min: 0 if it did not
+ * change, +inf if it did), is computed on the device; stop as soon as all three
+ * are below tol, or after max_steps steps.  steps (host) receives the number of
+ * steps taken, nrmse (host, 3 values) the last step's L_d (all +inf when no step
+ * was taken): the steady state was reached iff all three are below tol.  A
+ * failed step returns its error with the last completed state kept.
+ * Synchronises the stream once per step. */
+int ibfe_run_steady(ibfe_ctx* ctx, double tol, int64_t max_steps, int64_t* steps, double* nrmse);
 /* Read u, p (either may be NULL) and t; synchronises the stream for host output. */
 int ibfe_get_state(ibfe_ctx* ctx, double* u, double* p, double* t, int on_device);
 int ibfe_get_stats(const ibfe_ctx* ctx, ibfe_stats* stats);

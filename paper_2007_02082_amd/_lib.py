@@ -96,6 +96,7 @@ SIGNATURES = {
     "ibfe_get_node_ids": (C.c_int, [C.c_void_p, i64p, i64p]),
     "ibfe_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int]),
     "ibfe_step": (C.c_int, [C.c_void_p, C.c_int]),
+    "ibfe_run_steady": (C.c_int, [C.c_void_p, C.c_double, C.c_int64, C.c_void_p, C.c_void_p]),
     "ibfe_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, dp, C.c_int]),
     "ibfe_get_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
     "ibfe_set_kernel_timing": (C.c_int, [C.c_void_p, C.c_int]),
@@ -329,6 +330,15 @@ class Solver:
 
     def step(self, n: int = 1):
         check(load().ibfe_step(self._h, int(n)))
+
+    def run_steady(self, tol: float, max_steps: int):
+        """Step until the step-to-step NRMSE of every velocity component is below tol
+        (or max_steps steps); returns (steps taken, the last step's three NRMSE)."""
+        steps = C.c_int64()
+        nr = np.empty(3)
+        check(load().ibfe_run_steady(self._h, float(tol), int(max_steps), C.byref(steps),
+                                     C.c_void_p(nr.ctypes.data)))
+        return steps.value, nr
 
     def get_state(self):
         u = np.empty(3 * self.n_u)

@@ -22,6 +22,7 @@
 #include "ib_pcg.hpp"
 #include "strain.hpp"
 #include "wss.hpp"
+#include "steady.hpp"
 
 using namespace ibfe;
 
@@ -145,7 +146,9 @@ struct ibfe_ctx {
   // reductions
   double* partials = nullptr;
   double* res2 = nullptr;      // refinement residual: r.r, b.b
+  double* nrmse = nullptr;     // step-to-step NRMSE of the three components
   double* host_res2 = nullptr; // pinned
+  double* host_nrmse = nullptr; // pinned, 3 values
   KScal* scal = nullptr;
   KScal* host_scal = nullptr;  // pinned
 
@@ -198,6 +201,7 @@ struct ibfe_ctx {
     }
     if (host_scal) (void)hipHostFree(host_scal);
     if (host_res2) (void)hipHostFree(host_res2);
+    if (host_nrmse) (void)hipHostFree(host_nrmse);
   }
 
   int dalloc(void** out, size_t bytes) {
@@ -542,12 +546,15 @@ int setup_device(ibfe_ctx& c) {
     c.partials = reinterpret_cast<double*>(base);
     if ((rc = c.dalloc(&base, 256))) return rc;
     c.res2 = reinterpret_cast<double*>(base);
+    if ((rc = c.dalloc(&base, 256))) return rc;
+    c.nrmse = reinterpret_cast<double*>(base);
     if ((rc = c.dalloc(&base, sizeof(KScal) * kNumScal))) return rc;
     c.scal = reinterpret_cast<KScal*>(base);
   }
   HIP_TRY(hipHostMalloc((void**)&c.host_scal, sizeof(KScal) * kNumScal, hipHostMallocDefault));
   std::memset(c.host_scal, 0, sizeof(KScal) * kNumScal);
   HIP_TRY(hipHostMalloc((void**)&c.host_res2, 2 * sizeof(double), hipHostMallocDefault));
+  HIP_TRY(hipHostMalloc((void**)&c.host_nrmse, 3 * sizeof(double), hipHostMallocDefault));
   HIP_TRY(hipStreamSynchronize(c.stream));
   return IBFE_OK;
 }
@@ -2365,6 +2372,40 @@ int ibfe_step(ibfe_ctx* c, int nsteps) {
       c->t = t_save;  // u, p were not swapped: the last completed state is intact
       return rc;
     }
+  }
+  return IBFE_OK;
+}
+
+int ibfe_run_steady(ibfe_ctx* c, double tol, int64_t max_steps, int64_t* steps, double* nrmse) {
+  if (!c || !steps || !nrmse) return fail(IBFE_EINVAL, "NULL argument");
+  if (!(tol >= 0.0) || max_steps < 0) return fail(IBFE_EINVAL, "tol must be >= 0 and max_steps >= 0");
+  ibfe_ctx& C = *c;
+  *steps = 0;
+  nrmse[0] = nrmse[1] = nrmse[2] = HUGE_VAL;
+  // 9 partial rows per block within the kMaxRows x kRedBlocks buffer
+  const int nr = std::max(1, std::min(red_blocks(C.nchunks), kMaxRows * kRedBlocks / 9));
+  for (int64_t k = 0; k < max_steps; ++k) {
+    const double t_save = C.t;
+    int rc = C.plan.refined ? step_once_refined(C) : step_once(C);
+    if (rc) {
+      C.t = t_save;
+      return rc;
+    }
+    *steps = k + 1;
+    if (C.nP == 0) {
+      nrmse[0] = nrmse[1] = nrmse[2] = 0.0;
+    } else {
+      // after the step c.u holds u^{n+1} and c.u_next the previous state
+      hipLaunchKernelGGL(k_nrmse_part, dim3(nr), dim3(kBlock), 0, C.stream, C.nl, (const uint8_t*)C.flags,
+                         uint32_t(kFlagP), (const double*)C.u, (const double*)C.u_next, C.stride, C.partials);
+      hipLaunchKernelGGL(k_fin_nrmse, dim3(1), dim3(kBlock), 0, C.stream, (const double*)C.partials, nr,
+                         double(C.nP), C.nrmse);
+      CHECK_LAUNCH();
+      HIP_TRY(hipMemcpyAsync(C.host_nrmse, C.nrmse, 3 * sizeof(double), hipMemcpyDeviceToHost, C.stream));
+      HIP_TRY(hipStreamSynchronize(C.stream));
+      for (int d = 0; d < 3; ++d) nrmse[d] = C.host_nrmse[d];
+    }
+    if (nrmse[0] < tol && nrmse[1] < tol && nrmse[2] < tol) break;
   }
   return IBFE_OK;
 }
