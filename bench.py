@@ -247,6 +247,42 @@ def poiseuille_study(levels=(0, 1, 2), pressures=(1.0, 2.0), tol=1e-8, max_steps
     return rows
 
 
+def moving_points(s, case, nsteps: int = 20) -> dict:
+    """Moving Lagrangian points on the benchmark cylinder: the wall rings pulsate
+    radially (R(t) = R0 (1 + 0.02 sin 2 pi t)); every step first moves the points
+    (ibfe_set_points rebuilds the stencils, the spreading lists, G and its block
+    inverses on the device) and then advances.  Reports the rebuild time and the step
+    rate with a rebuild per step next to the rate without motion."""
+    import numpy as np
+    import torch
+
+    import synth
+
+    rings, per_ring = 256, 100
+    z = (np.arange(rings, dtype=np.float64) + 0.5) * (8.0 / rings)
+    wall = synth.PulsatingWall(0.5, z, per_ring, 0.02, 1.0)
+    _, _, t = s.get_state()
+    s.set_points(*wall.at(t + case.dt))     # first call: allocation
+    s.step(1)
+    t += case.dt
+    rebuild = []
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        X, U = wall.at(t + case.dt)
+        r0 = time.perf_counter()
+        s.set_points(X, U)
+        torch.cuda.synchronize()
+        rebuild.append(time.perf_counter() - r0)
+        s.step(1)
+        t += case.dt
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t0
+    st = s.stats()
+    return {"M": case.M, "steps": nsteps, "rebuild_ms_median": round(1e3 * float(np.median(rebuild)), 3),
+            "steps_per_s_with_rebuild": round(nsteps / wall_s, 2), "ib_iters_last": st["ib_iters"],
+            "amplitude": 0.02, "period": 1.0}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,6 +306,9 @@ def main() -> int:
     ap.add_argument("--e1", action="store_true",
                     help="also run the pressure-driven Poiseuille study of Section 3.1 to steady "
                          "state on the three grids of Table 1 (after the timed steps)")
+    ap.add_argument("--moving", action="store_true",
+                    help="also step the benchmark cylinder with its wall points moving radially "
+                         "(a device rebuild of the IB operators before every step)")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -372,6 +411,11 @@ def main() -> int:
         extra["rel_l2_vs_fp64"] = {"u": float(np.linalg.norm(u_a - u_b) / np.linalg.norm(u_b)),
                                    "p": float(np.linalg.norm(p_a - p_b) / np.linalg.norm(p_b))}
         ref.close()
+    if args.moving:
+        if args.workload != "pulsatile":
+            print("--moving runs on the pulsatile cylinder only", file=sys.stderr)
+            return 2
+        extra["moving_points"] = moving_points(s, case)
     s.close()
     if args.copy_calibration_mib > 0:
         nbytes = args.copy_calibration_mib << 20

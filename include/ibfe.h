@@ -225,6 +225,21 @@ int ibfe_set_state(ibfe_ctx* ctx, const double* u, const double* p, double t, in
 /* Advance nsteps steps (Section 2.4).  On failure the state of the last
  * completed step is kept. */
 int ibfe_step(ibfe_ctx* ctx, int nsteps);
+/* Move the Lagrangian points (Section 2.3 defines I, I_F and the force system
+ * G = I_F I_F^T for the current positions): X (M x 3, row major) are the
+ * positions and U_B (M x 3, NULL = 0) the prescribed velocities that the next
+ * steps enforce; M is the count given at ibfe_create.  The stencils of Eq. 17,
+ * the spreading lists, G and its block-Jacobi preconditioner are rebuilt on the
+ * device (deterministic: the same positions give the same G on every call).
+ * on_device != 0: X and U_B are device memory (not validated); else host memory
+ * (must be finite, IBFE_EINVAL).  Uniform grids only (IBFE_EINVAL on a refined
+ * grid).  IBFE_ESINGULAR if a point's support holds no free node; IBFE_EINVAL if
+ * the points are so dense that a row of G collects more than 1024 support
+ * products.  After an error the context refuses to step until a call succeeds.
+ * The first call allocates the rebuild buffers (about 100 bytes per support
+ * node of every point) and drops captured graphs; it synchronises the stream
+ * twice. */
+int ibfe_set_points(ibfe_ctx* ctx, const double* X, const double* U_B, int on_device);
 /* Advance until the flow is steady (Section 3.1): after every step, the
  * step-to-step normalised root-mean-square difference of each velocity
  * component d,

@@ -87,6 +87,19 @@ class Problem:
             self._check_support_in_fine_band()
         self._pressure_setup()
 
+    def set_points(self, X: np.ndarray, U_B: np.ndarray | None = None):
+        """Move the Lagrangian points (same count): the interpolation matrix of Eq. 17
+        is rebuilt at the new positions, U_B is their prescribed velocity (None = 0).
+        The next step enforces I u = U_B at these positions."""
+        X = np.asarray(X, np.float64).reshape(-1, 3)
+        if X.shape != self.X.shape:
+            raise ValueError("the number of Lagrangian points is fixed")
+        if self.mesh is not None:
+            raise ValueError("moving points are supported on uniform grids only")
+        self.X = X
+        self.U_B = np.zeros_like(X) if U_B is None else np.asarray(U_B, np.float64).reshape(-1, 3)
+        self.I = ib.interpolation_matrix(X, self.nx, self.ny, self.nz, self.h, self.origin)
+
     @classmethod
     def from_case(cls, c, advection=0, viscous=0):
         return cls(c.nx, c.ny, c.nz, c.h, c.origin, c.node_mask, c.bc_tag, c.X, c.dS, c.U_B,

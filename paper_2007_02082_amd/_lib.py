@@ -97,6 +97,7 @@ SIGNATURES = {
     "ibfe_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int]),
     "ibfe_step": (C.c_int, [C.c_void_p, C.c_int]),
     "ibfe_run_steady": (C.c_int, [C.c_void_p, C.c_double, C.c_int64, C.c_void_p, C.c_void_p]),
+    "ibfe_set_points": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "ibfe_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, dp, C.c_int]),
     "ibfe_get_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
     "ibfe_set_kernel_timing": (C.c_int, [C.c_void_p, C.c_int]),
@@ -330,6 +331,14 @@ class Solver:
 
     def step(self, n: int = 1):
         check(load().ibfe_step(self._h, int(n)))
+
+    def set_points(self, X: np.ndarray, U_B: np.ndarray | None = None):
+        """Move the Lagrangian points to X (M x 3) with prescribed velocities U_B (None = 0);
+        the IB operators are rebuilt on the device."""
+        X = np.ascontiguousarray(X, np.float64).reshape(-1, 3)
+        ub = None if U_B is None else np.ascontiguousarray(U_B, np.float64).reshape(-1, 3)
+        check(load().ibfe_set_points(self._h, C.c_void_p(X.ctypes.data),
+                                     None if ub is None else C.c_void_p(ub.ctypes.data), 0))
 
     def run_steady(self, tol: float, max_steps: int):
         """Step until the step-to-step NRMSE of every velocity component is below tol

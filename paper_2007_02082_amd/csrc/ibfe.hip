@@ -23,6 +23,9 @@
 #include "strain.hpp"
 #include "wss.hpp"
 #include "steady.hpp"
+#include "ib_move.hpp"
+
+#include <hipcub/hipcub.hpp>
 
 using namespace ibfe;
 
@@ -135,6 +138,21 @@ struct ibfe_ctx {
   int32_t* sp_pt = nullptr;
   double* sp_wt = nullptr;
   double* ibv[7] = {};  // b, lam, r, p, q, z, p' (3 planes of mstride)
+  int n_sp = 0;         // nodes of the spreading lists
+  // moving Lagrangian points: device rebuild buffers, allocated on the first
+  // ibfe_set_points (the spreading lists and G are then reallocated at their
+  // largest sizes)
+  struct Moving {
+    bool ready = false;
+    double* X = nullptr;  // M x 3
+    uint32_t *keys = nullptr, *vals = nullptr, *skeys = nullptr, *svals = nullptr;
+    int *flag = nullptr, *pos = nullptr, *counters = nullptr;
+    int64_t* cnt = nullptr;
+    void* temp = nullptr;
+    size_t temp_bytes = 0;
+    int64_t g_cap = 0;
+  } mv;
+  bool ib_valid = true;  // false after a failed ibfe_set_points
   // ibv[1] holds the force of the last step: the initial guess of the next force
   // solve (the right-hand side U_B - I u* changes little from step to step)
   bool lam_warm = false;
@@ -522,6 +540,7 @@ int setup_device(ibfe_ctx& c) {
     if ((rc = c.upload(&c.sp_ptr, P.sp_ptr.data(), P.sp_ptr.size()))) return rc;
     if ((rc = c.upload(&c.sp_pt, P.sp_pt.data(), P.sp_pt.size()))) return rc;
     if ((rc = c.upload(&c.sp_wt, P.sp_w.data(), P.sp_w.size()))) return rc;
+    c.n_sp = int(P.sp_node.size());
     for (int i = 0; i < 7; ++i) {
       void* base = nullptr;
       if ((rc = c.dalloc(&base, sizeof(double) * 3 * c.mstride))) return rc;
@@ -1725,7 +1744,7 @@ int step_once(ibfe_ctx& c) {
     c.lam_warm = true;
     c.stats.ib_iters = so.iters;
     c.stats.ib_res = so.res;
-    const int nn = int(P.sp_node.size());
+    const int nn = c.n_sp;
     hipLaunchKernelGGL(k_ib_spread, dim3(blocks_lin(nn)), dim3(kBlock), 0, c.stream, nn, c.sp_node,
                        c.sp_ptr, c.sp_pt, c.sp_wt, c.ibv[1], c.mstride, c.uib, S);
     CHECK_LAUNCH();
@@ -2032,7 +2051,7 @@ int step_once_refined(ibfe_ctx& c) {
     c.lam_warm = true;
     c.stats.ib_iters = so.iters;
     c.stats.ib_res = so.res;
-    const int nn = int(P.sp_node.size());
+    const int nn = c.n_sp;
     hipLaunchKernelGGL(k_ib_spread, dim3(blocks_lin(nn)), dim3(kBlock), 0, c.stream, nn, c.sp_node,
                        c.sp_ptr, c.sp_pt, c.sp_wt, c.ibv[1], c.mstride, c.uib, S);
     CHECK_LAUNCH();
@@ -2365,6 +2384,7 @@ int ibfe_set_state(ibfe_ctx* c, const double* u, const double* p, double t, int 
 
 int ibfe_step(ibfe_ctx* c, int nsteps) {
   if (!c || nsteps < 0) return fail(IBFE_EINVAL, "bad argument");
+  if (!c->ib_valid) return fail(IBFE_EINVAL, "the Lagrangian points are not set (a failed ibfe_set_points)");
   for (int k = 0; k < nsteps; ++k) {
     const double t_save = c->t;
     int rc = c->plan.refined ? step_once_refined(*c) : step_once(*c);
@@ -2376,12 +2396,154 @@ int ibfe_step(ibfe_ctx* c, int nsteps) {
   return IBFE_OK;
 }
 
+namespace {
+
+// Buffers of the device rebuild of the IB operators (first ibfe_set_points): the
+// pair arrays of the sort, scan scratch, and the spreading lists and G at their
+// largest sizes.  The captured graphs hold the old G pointers: they are dropped.
+int setup_moving(ibfe_ctx& C) {
+  const Plan& P = C.plan;
+  const int64_t M = P.M;
+  const int64_t np = 64 * M;
+  if (np > int64_t(INT32_MAX) - 1) return fail(IBFE_EINVAL, "too many Lagrangian points to move");
+  auto& mv = C.mv;
+  void* b = nullptr;
+  int rc;
+  auto take = [&](size_t bytes, void** out) { return C.dalloc(out, bytes); };
+  if ((rc = take(sizeof(double) * 3 * M, &b))) return rc;
+  mv.X = static_cast<double*>(b);
+  uint32_t** u32[4] = {&mv.keys, &mv.vals, &mv.skeys, &mv.svals};
+  for (auto p : u32) {
+    if ((rc = take(sizeof(uint32_t) * np, &b))) return rc;
+    *p = static_cast<uint32_t*>(b);
+  }
+  if ((rc = take(sizeof(int) * np, &b))) return rc;
+  mv.flag = static_cast<int*>(b);
+  if ((rc = take(sizeof(int) * np, &b))) return rc;
+  mv.pos = static_cast<int*>(b);
+  if ((rc = take(sizeof(int) * 8, &b))) return rc;
+  mv.counters = static_cast<int*>(b);
+  if ((rc = take(sizeof(int64_t) * (M + 1), &b))) return rc;  // cnt[M] stays 0
+  mv.cnt = static_cast<int64_t*>(b);
+  // spreading lists at their largest size (every support pair free)
+  if ((rc = take(sizeof(int32_t) * np, &b))) return rc;
+  C.sp_node = static_cast<int32_t*>(b);
+  if ((rc = take(sizeof(int64_t) * (np + 1), &b))) return rc;
+  C.sp_ptr = static_cast<int64_t*>(b);
+  if ((rc = take(sizeof(int32_t) * np, &b))) return rc;
+  C.sp_pt = static_cast<int32_t*>(b);
+  if ((rc = take(sizeof(double) * np, &b))) return rc;
+  C.sp_wt = static_cast<double*>(b);
+  // G: room for four times the entries at the initial positions, at least 128 per row
+  mv.g_cap = std::max<int64_t>(4 * int64_t(P.G_col.size()), 128 * M);
+  if ((rc = take(sizeof(int32_t) * mv.g_cap, &b))) return rc;
+  C.G_col = static_cast<int32_t*>(b);
+  if ((rc = take(sizeof(double) * mv.g_cap, &b))) return rc;
+  C.G_val = static_cast<double*>(b);
+  size_t b1 = 0, b2 = 0, b3 = 0;
+  HIP_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, b1, mv.keys, mv.skeys, mv.vals, mv.svals, int(np), 0, 32,
+                                             C.stream));
+  HIP_TRY(hipcub::DeviceScan::ExclusiveSum(nullptr, b2, mv.flag, mv.pos, int(np), C.stream));
+  HIP_TRY(hipcub::DeviceScan::ExclusiveSum(nullptr, b3, mv.cnt, C.G_ptr, int(M + 1), C.stream));
+  mv.temp_bytes = std::max(b1, std::max(b2, b3));
+  if ((rc = take(std::max<size_t>(mv.temp_bytes, 256), &mv.temp))) return rc;
+  HIP_TRY(hipStreamSynchronize(C.stream));
+  for (auto& kv : C.graph_cache) (void)hipGraphExecDestroy(kv.second);
+  C.graph_cache.clear();
+  mv.ready = true;
+  return IBFE_OK;
+}
+
+}  // namespace
+
+int ibfe_set_points(ibfe_ctx* c, const double* X, const double* U_B, int on_device) {
+  if (!c || !X) return fail(IBFE_EINVAL, "NULL argument");
+  ibfe_ctx& C = *c;
+  const Plan& P = C.plan;
+  const int64_t M = P.M;
+  if (M == 0) return IBFE_OK;
+  if (P.refined) return fail(IBFE_EINVAL, "moving Lagrangian points are supported on uniform grids only");
+  if (!on_device) {
+    for (int64_t q = 0; q < 3 * M; ++q)
+      if (!std::isfinite(X[q]) || (U_B && !std::isfinite(U_B[q])))
+        return fail(IBFE_EINVAL, "X and U_B must be finite");
+  }
+  int rc;
+  if (!C.mv.ready && (rc = setup_moving(C))) return rc;
+  auto& mv = C.mv;
+  C.ib_valid = false;
+  const size_t bytes = sizeof(double) * 3 * size_t(M);
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  HIP_TRY(hipMemcpyAsync(mv.X, X, bytes, kind, C.stream));
+  if (U_B)
+    HIP_TRY(hipMemcpyAsync(C.UB, U_B, bytes, kind, C.stream));
+  else
+    HIP_TRY(hipMemsetAsync(C.UB, 0, bytes, C.stream));
+  HIP_TRY(hipMemsetAsync(mv.counters, 0, sizeof(int) * 8, C.stream));
+  const int64_t np = 64 * M;
+  const uint32_t N = uint32_t(P.N);
+  GridGeom g{P.origin[0], P.origin[1], P.origin[2], P.h, P.nx, P.ny, P.nz, P.sy, P.sz};
+  hipLaunchKernelGGL(k_ib_stencil, dim3(blocks_lin(M)), dim3(kBlock), 0, C.stream, int(M), g,
+                     (const double*)mv.X, (const uint8_t*)C.flags, N, C.ib_idx, C.ib_w, mv.keys, mv.vals,
+                     mv.counters);
+  CHECK_LAUNCH();
+  int bits = 1;
+  while (bits < 32 && (uint64_t(1) << bits) <= uint64_t(N)) ++bits;
+  size_t tb = mv.temp_bytes;
+  HIP_TRY(hipcub::DeviceRadixSort::SortPairs(mv.temp, tb, mv.keys, mv.skeys, mv.vals, mv.svals, int(np), 0, bits,
+                                             C.stream));
+  const int nbp = int((np + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_sp_flags, dim3(nbp), dim3(kBlock), 0, C.stream, np, (const uint32_t*)mv.skeys, N,
+                     mv.flag);
+  CHECK_LAUNCH();
+  tb = mv.temp_bytes;
+  HIP_TRY(hipcub::DeviceScan::ExclusiveSum(mv.temp, tb, mv.flag, mv.pos, int(np), C.stream));
+  hipLaunchKernelGGL(k_sp_fill, dim3(nbp), dim3(kBlock), 0, C.stream, np, int(M), (const uint32_t*)mv.skeys,
+                     (const uint32_t*)mv.svals, N, (const int*)mv.flag, (const int*)mv.pos,
+                     (const double*)C.ib_w, C.sp_node, C.sp_ptr, C.sp_pt, C.sp_wt, mv.counters);
+  CHECK_LAUNCH();
+  int hc[8];
+  HIP_TRY(hipMemcpyAsync(hc, mv.counters, sizeof(hc), hipMemcpyDeviceToHost, C.stream));
+  HIP_TRY(hipStreamSynchronize(C.stream));
+  if (hc[0] > 0)
+    return fail(IBFE_ESINGULAR, std::to_string(hc[0]) + " Lagrangian point(s) without a free support node");
+  const int64_t nvalid = hc[3];
+  hipLaunchKernelGGL((k_gram_rows<false>), dim3(unsigned(M)), dim3(64), 0, C.stream, int(M),
+                     (const int32_t*)C.ib_idx, (const double*)C.ib_w, (const uint8_t*)C.flags,
+                     (const uint32_t*)mv.skeys, nvalid, (const int32_t*)C.sp_pt, (const double*)C.sp_wt, mv.cnt,
+                     (const int64_t*)nullptr, (int32_t*)nullptr, (double*)nullptr, (double*)nullptr,
+                     mv.counters);
+  CHECK_LAUNCH();
+  tb = mv.temp_bytes;
+  HIP_TRY(hipcub::DeviceScan::ExclusiveSum(mv.temp, tb, mv.cnt, C.G_ptr, int(M + 1), C.stream));
+  int64_t nnz = 0;
+  HIP_TRY(hipMemcpyAsync(&nnz, C.G_ptr + M, sizeof(int64_t), hipMemcpyDeviceToHost, C.stream));
+  HIP_TRY(hipMemcpyAsync(hc, mv.counters, sizeof(hc), hipMemcpyDeviceToHost, C.stream));
+  HIP_TRY(hipStreamSynchronize(C.stream));
+  if (hc[1] > 0)
+    return fail(IBFE_EINVAL, "a Lagrangian point overlaps more than " + std::to_string(kGramCap) +
+                                 " support products: the points are too dense");
+  if (nnz > mv.g_cap) return fail(IBFE_ENOMEM, "the force system exceeds its capacity");
+  hipLaunchKernelGGL((k_gram_rows<true>), dim3(unsigned(M)), dim3(64), 0, C.stream, int(M),
+                     (const int32_t*)C.ib_idx, (const double*)C.ib_w, (const uint8_t*)C.flags,
+                     (const uint32_t*)mv.skeys, nvalid, (const int32_t*)C.sp_pt, (const double*)C.sp_wt,
+                     (int64_t*)nullptr, (const int64_t*)C.G_ptr, C.G_col, C.G_val, C.G_diag, mv.counters);
+  const int nblk = int((M + kIBBlock - 1) / kIBBlock);
+  hipLaunchKernelGGL(k_gram_block_inv, dim3(nblk), dim3(kBlock), 0, C.stream, int(M), (const int64_t*)C.G_ptr,
+                     (const int32_t*)C.G_col, (const double*)C.G_val, C.G_binv);
+  CHECK_LAUNCH();
+  C.n_sp = hc[2];
+  C.ib_valid = true;
+  return IBFE_OK;
+}
+
 int ibfe_run_steady(ibfe_ctx* c, double tol, int64_t max_steps, int64_t* steps, double* nrmse) {
   if (!c || !steps || !nrmse) return fail(IBFE_EINVAL, "NULL argument");
   if (!(tol >= 0.0) || max_steps < 0) return fail(IBFE_EINVAL, "tol must be >= 0 and max_steps >= 0");
   ibfe_ctx& C = *c;
   *steps = 0;
   nrmse[0] = nrmse[1] = nrmse[2] = HUGE_VAL;
+  if (!C.ib_valid) return fail(IBFE_EINVAL, "the Lagrangian points are not set (a failed ibfe_set_points)");
   // 9 partial rows per block within the kMaxRows x kRedBlocks buffer
   const int nr = std::max(1, std::min(red_blocks(C.nchunks), kMaxRows * kRedBlocks / 9));
   for (int64_t k = 0; k < max_steps; ++k) {
@@ -2533,7 +2695,7 @@ int ibfe_apply(ibfe_ctx* c, int op, int precision, const double* x, double* y, i
       for (int d = 0; d < 3; ++d) h[d * C.mstride + i] = hx[3 * i + d];
     HIP_TRY(hipMemcpyAsync(C.ibv[1], h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, C.stream));
     HIP_TRY(hipMemsetAsync(yout - C.halo, 0, sizeof(double) * 3 * S, C.stream));
-    const int nn = int(P.sp_node.size());
+    const int nn = C.n_sp;
     hipLaunchKernelGGL(k_ib_spread, dim3(blocks_lin(nn)), dim3(kBlock), 0, C.stream, nn, C.sp_node, C.sp_ptr,
                        C.sp_pt, C.sp_wt, C.ibv[1], C.mstride, yout, S);
     CHECK_LAUNCH();
