@@ -156,6 +156,10 @@ struct ibfe_ctx {
   // ibv[1] holds the force of the last step: the initial guess of the next force
   // solve (the right-hand side U_B - I u* changes little from step to step)
   bool lam_warm = false;
+  // Phi and the mass correction delta of the last step start the next step's
+  // mixed-precision solves (both change little from step to step)
+  double* delta = nullptr;
+  bool phi_warm = false, delta_warm = false;
 
   // inlet
   int64_t* inlet_ids = nullptr;
@@ -502,6 +506,7 @@ int setup_device(ibfe_ctx& c) {
   if ((rc = c.field(&c.ustar, 3))) return rc;
   if ((rc = c.field(&c.uib, 3))) return rc;
   if ((rc = c.field(&c.phi, 1))) return rc;
+  if ((rc = c.field(&c.delta, 3))) return rc;
   const int ncoef = P.refined ? 54 : 27;
   if ((rc = c.field(&c.coef64, ncoef))) return rc;
   for (int i = 0; i < 10; ++i)
@@ -1763,8 +1768,9 @@ int step_once(ibfe_ctx& c) {
     const bool mg = P.params.precond >= 1;  // multigrid or Chebyshev (one level)
     if (mixed) {
       auto op32 = sym_op<float, 1>(c, kc, kFlagPp);
-      hipLaunchKernelGGL(k_zero<double>, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.phi, 1,
-                         S);
+      if (!c.phi_warm)
+        hipLaunchKernelGGL(k_zero<double>, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.phi, 1, S);
+      c.phi_warm = false;
       float* const* v = c.v32;
       rc = run_refined(c, op, kFlagPp, 1, b3, c.phi, v[8], v[9], rtol, so,
                        [&](const float* r32, float* d32, double tol, SolveOut& o) {
@@ -1786,19 +1792,21 @@ int step_once(ibfe_ctx& c) {
     c.stats.s3_res = so.res;
     c.stats.s3_outer = so.outer;
     if (P.n_floating > 0 && (rc = remove_slot_means(c, c.phi))) return rc;
+    c.phi_warm = mixed;
   }
 
   // 6. correction: M_FF delta = (G Phi)_F, u^{n+1} = u_ib - (dt/rho) delta, p^{n+1} = p^n + Phi
   {
     double* b4 = c.w[8];
-    double* delta = c.w[9];
+    double* delta = c.delta;
     hipLaunchKernelGGL(k_grad, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.emask, c.flags,
                        kFlagF, c.phi, b4, S, sy, sz, c.fc.g2[0], c.fc.g2[1], c.fc.g2[2]);
     CHECK_LAUNCH();
     const double mc[4] = {c.fc.m[0], c.fc.m[1], c.fc.m[2], c.fc.m[3]};
     auto op = sym_op<double, 3>(c, mc, kFlagF);
     SolveOut so;
-    hipLaunchKernelGGL(k_zero<double>, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, delta, 3, S);
+    if (!c.delta_warm) hipLaunchKernelGGL(k_zero<double>, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, delta, 3, S);
+    c.delta_warm = false;
     if (mixed) {
       float* const* v = c.v32;
       rc = run_refined(c, op, kFlagF, 3, b4, delta, v[8], v[9], rtol, so,
@@ -1830,6 +1838,7 @@ int step_once(ibfe_ctx& c) {
     c.stats.s4_iters = so.iters;
     c.stats.s4_res = so.res;
     c.stats.s4_outer = so.outer;
+    c.delta_warm = true;
     hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, c.uib,
                        -dt / rho, delta, c.u_next, 3, S);
     hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, c.p, 1.0,
@@ -2377,6 +2386,7 @@ int ibfe_set_state(ibfe_ctx* c, const double* u, const double* p, double t, int 
   c->t = t;
   c->steps = 0;
   c->lam_warm = false;
+  c->phi_warm = c->delta_warm = false;
   c->stats = ibfe_stats{};
   c->stats.t = t;
   return IBFE_OK;
