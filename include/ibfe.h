@@ -132,7 +132,8 @@ typedef struct ibfe_ib {
  *                 diffusion operator); 1 = explicit u^n . grad u^n (the convection
  *                 of Eq. 13 at the old velocity on the right-hand side; CG on the
  *                 symmetric (rho/dt) M + mu K)
- *   ib_rtol     : relative residual target of the IB force solve (<= 0: 1e-13)
+ *   ib_rtol     : relative residual target of the IB force solve (<= 0: 1e-13 with
+ *                 precision 0, 1e-10 with precision 1)
  *   viscous     : viscous form of the momentum equation (Section 2.1): 0 = the
  *                 component-wise mu (grad u, grad v); 1 = the strain-rate form
  *                 2 mu (eps(u), eps(v)), eps(u) = (grad u + grad u^T)/2, which

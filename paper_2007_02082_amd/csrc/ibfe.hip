@@ -2088,8 +2088,9 @@ int step_once_refined(ibfe_ctx& c) {
     SolveOut so;
     if (mixed) {
       auto op32 = csym_op<float, 1>(c, 0.0, 1.0, kFlagPp, c.dinvK32);
-      hipLaunchKernelGGL(k_zero<double>, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.phi, 1,
-                         S);
+      if (!c.phi_warm)
+        hipLaunchKernelGGL(k_zero<double>, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.phi, 1, S);
+      c.phi_warm = false;
       float* const* v = c.v32;
       rc = run_refined(c, op, kFlagPp, 1, b3, c.phi, v[8], v[9], rtol, so,
                        [&](const float* r32, float* d32, double tol, SolveOut& o) {
@@ -2111,18 +2112,20 @@ int step_once_refined(ibfe_ctx& c) {
     c.stats.s3_res = so.res;
     c.stats.s3_outer = so.outer;
     if (P.n_floating > 0 && (rc = remove_slot_means(c, c.phi))) return rc;
+    c.phi_warm = mixed;
   }
 
   // 6. correction: M_FF delta = (G Phi)_F with Chebyshev on [lmin, 27/8] of D'^-1 M
   {
     double* b4 = c.w[8];
-    double* delta = c.w[9];
+    double* delta = c.delta;
     if ((rc = fill_hanging<double>(c, c.phi, 1))) return rc;
     if ((rc = comp_rows<double>(c, grad_elem(c, c.phi), kFlagF, 0u, 1.0, b4))) return rc;
     auto op = csym_op<double, 3>(c, 1.0, 0.0, kFlagF, c.dinvM64);
     const double lmin = P.mass_lmin, lmax = kMassLmax;
     SolveOut so;
-    hipLaunchKernelGGL(k_zero<double>, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, delta, 3, S);
+    if (!c.delta_warm) hipLaunchKernelGGL(k_zero<double>, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, delta, 3, S);
+    c.delta_warm = false;
     if (mixed) {
       auto op32 = csym_op<float, 3>(c, 1.0, 0.0, kFlagF, c.dinvM32);
       float* const* v = c.v32;
@@ -2155,6 +2158,7 @@ int step_once_refined(ibfe_ctx& c) {
     c.stats.s4_iters = so.iters;
     c.stats.s4_res = so.res;
     c.stats.s4_outer = so.outer;
+    c.delta_warm = true;
     hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, c.uib,
                        -dt / rho, delta, c.u_next, 3, S);
     hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, c.p, 1.0,

@@ -167,7 +167,7 @@ int build_plan(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* para
   P.params = pr;
   if (P.params.rtol <= 0.0) P.params.rtol = pr.precision == 0 ? 1e-13 : 1e-8;
   if (P.params.max_iters <= 0) P.params.max_iters = 20000;
-  if (P.params.ib_rtol <= 0.0) P.params.ib_rtol = 1e-13;
+  if (P.params.ib_rtol <= 0.0) P.params.ib_rtol = pr.precision == 0 ? 1e-13 : 1e-10;
 
   const int64_t N = P.N;
   const int nx = P.nx, ny = P.ny, nz = P.nz;
