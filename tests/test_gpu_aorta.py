@@ -87,8 +87,9 @@ def _run(c4, sets, precision, tol):
         p_prev = p
         uf = np.zeros((3, c4.N))
         uf[:, ids] = uib.reshape(3, -1)
+        # the force solve stops at 1e-13 (FP64) or 1e-10 (mixed) relative residual
         for d in range(3):
-            assert np.abs(I @ uf[d]).max() < 1e-9
+            assert np.abs(I @ uf[d]).max() < (1e-9 if precision == 0 else 1e-7)
         # pressure increment: K phi = -(rho/dt) B u_ib on the pressure unknowns
         rhs3 = -(rho / dt) * s.apply(ibfe.OP_DIV, uib.ravel(), 0)
         r3 = s.apply(ibfe.OP_STIFF, phi, 0) - rhs3

@@ -206,7 +206,8 @@ def test_full_size_refined_step_equations(c3, plan_info, windows, precision, tol
     for d in range(3):
         uf = np.zeros(c3.N)
         uf[ids_p] = uib[d]
-        assert np.abs(I @ uf).max() <= 1e-9 * np.abs(uib[d]).max()
+        # the force solve stops at 1e-13 (FP64) or 1e-10 (mixed) relative residual
+        assert np.abs(I @ uf).max() <= (1e-9 if precision == 0 else 1e-7) * np.abs(uib[d]).max()
     rho, mu, dt = c3.rho, c3.mu, c3.dt
     for w in windows:
         g = lambda v: w.gather(v, w.pos)
