@@ -163,6 +163,8 @@ struct ibfe_ctx {
 
   // inlet
   int64_t* inlet_ids = nullptr;
+  int32_t* lift_rows = nullptr;   // free rows next to an inlet-table node
+  int nlift = 0;
   double* inlet_shape = nullptr;
 
   // reductions
@@ -554,6 +556,25 @@ int setup_device(ibfe_ctx& c) {
   }
   if (!P.inlet_ids.empty()) {
     if ((rc = c.upload(&c.inlet_ids, P.inlet_ids.data(), P.inlet_ids.size()))) return rc;
+    if (!P.refined) {
+      // the rows that see g: free nodes with an inlet-table node among their 27 neighbours
+      std::vector<int32_t> rows;
+      for (int64_t id : P.inlet_ids) {
+        const int64_t k = id / P.sz, j = (id % P.sz) / P.sy, i = id % P.sy;
+        for (int oz = -1; oz <= 1; ++oz)
+          for (int oy = -1; oy <= 1; ++oy)
+            for (int ox = -1; ox <= 1; ++ox) {
+              const int64_t ii = i + ox, jj = j + oy, kk = k + oz;
+              if (ii < 0 || jj < 0 || kk < 0 || ii > P.nx || jj > P.ny || kk > P.nz) continue;
+              const int64_t m = ii + P.sy * jj + P.sz * kk;
+              if (P.flags[m] & IBFE_FLAG_F) rows.push_back(int32_t(m));
+            }
+      }
+      std::sort(rows.begin(), rows.end());
+      rows.erase(std::unique(rows.begin(), rows.end()), rows.end());
+      c.nlift = int(rows.size());
+      if ((rc = c.upload(&c.lift_rows, rows.data(), rows.size()))) return rc;
+    }
     if ((rc = c.upload(&c.inlet_shape, P.inlet_shape.data(), P.inlet_shape.size()))) return rc;
   }
   if (P.params.precond >= 1) {
@@ -1604,9 +1625,10 @@ int s1_explicit(ibfe_ctx& c) {
   hipLaunchKernelGGL(k_s1_rhs_explicit, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.emask,
                      c.flags, c.coef64, c.u, c.p, c.g, b1, S, int(P.sy), int(P.sz), cm[0], cm[1], cm[2], cm[3],
                      ca[0], ca[1], ca[2], ca[3], c.fc.g2[0], c.fc.g2[1], c.fc.g2[2]);
-  if (P.params.viscous == 1)
-    hipLaunchKernelGGL(k_strain_lift, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, (const uint8_t*)c.emask,
-                       (const uint8_t*)c.flags, kFlagF, (const double*)c.g, b1, S, mu, P.h, int(P.sy), int(P.sz));
+  if (P.params.viscous == 1 && c.nlift > 0)
+    hipLaunchKernelGGL(k_strain_lift, dim3(blocks_lin(c.nlift)), dim3(kBlock), 0, c.stream, c.nlift,
+                       (const int32_t*)c.lift_rows, (const uint8_t*)c.emask, (const double*)c.g, b1, S, mu, P.h,
+                       int(P.sy), int(P.sz));
   hipLaunchKernelGGL((k_masked_copy<double, double>), dim3(nb), dim3(kBlock), 0, c.stream, c.nl,
                      c.flags, kFlagF, c.u, x1, 3, S);
   CHECK_LAUNCH();
@@ -1695,12 +1717,17 @@ int step_once(ibfe_ctx& c) {
     double cm[4];
     for (int t = 0; t < 4; ++t) cm[t] = rho / dt * c.fc.m[t];
     hipLaunchKernelGGL(k_s1_rhs, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.emask,
-                       c.flags, c.coef64, c.u, c.p, c.g, b1, S, sy, sz, cm[0], cm[1], cm[2], cm[3],
+                       c.flags, c.u, c.p, b1, S, sy, sz, cm[0], cm[1], cm[2], cm[3],
                        c.fc.g2[0], c.fc.g2[1], c.fc.g2[2]);
+    if (c.nlift > 0)
+      hipLaunchKernelGGL(k_s1_lift, dim3(blocks_lin(c.nlift)), dim3(kBlock), 0, c.stream, c.nlift,
+                         (const int32_t*)c.lift_rows, (const uint8_t*)c.flags, (const double*)c.coef64,
+                         (const double*)c.g, b1, S, sy, sz);
     CHECK_LAUNCH();
-    if (P.params.viscous == 1) {
-      hipLaunchKernelGGL(k_strain_lift, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, (const uint8_t*)c.emask,
-                         (const uint8_t*)c.flags, kFlagF, (const double*)c.g, b1, S, P.params.mu, P.h, sy, sz);
+    if (P.params.viscous == 1 && c.nlift > 0) {
+      hipLaunchKernelGGL(k_strain_lift, dim3(blocks_lin(c.nlift)), dim3(kBlock), 0, c.stream, c.nlift,
+                         (const int32_t*)c.lift_rows, (const uint8_t*)c.emask, (const double*)c.g, b1, S,
+                         P.params.mu, P.h, sy, sz);
       CHECK_LAUNCH();
     }
     hipLaunchKernelGGL((k_masked_copy<double, double>), dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.flags, kFlagF, c.u, x1, 3, S);

@@ -127,14 +127,13 @@ __global__ __launch_bounds__(kBlock) void k_s1_build(NodeList nl,
   }
 }
 
-// b_d = (rho/dt)(M u_d) - G_d p - A g_d on free rows, 0 elsewhere (Eq. 9 with
-// the Dirichlet lifting of g(t^{n+1})).
+// b_d = (rho/dt)(M u_d) - G_d p on free rows, 0 elsewhere (Eq. 9); the lifting
+// of the Dirichlet data, - A g_d, follows in k_s1_lift on the rows next to it.
 __global__ __launch_bounds__(kBlock) void k_s1_rhs(NodeList nl,
                                                    const uint8_t* __restrict__ emask,
                                                    const uint8_t* __restrict__ flags,
-                                                   const double* __restrict__ coef,
                                                    const double* __restrict__ u, const double* __restrict__ p,
-                                                   const double* __restrict__ g, double* __restrict__ b,
+                                                   double* __restrict__ b,
                                                    int64_t stride, int sy, int sz, double cm0,
                                                    double cm1, double cm2, double cm3, double g20,
                                                    double g21, double g22) {
@@ -151,12 +150,27 @@ __global__ __launch_bounds__(kBlock) void k_s1_rhs(NodeList nl,
   const double gp[3] = {apply_grad<double, 0>(p, n, e, g2, sy, sz),
                         apply_grad<double, 1>(p, n, e, g2, sy, sz),
                         apply_grad<double, 2>(p, n, e, g2, sy, sz)};
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    b[d * stride + n] = apply_sym<double>(u + d * stride, n, e, cm, sy, sz) - gp[d];
+}
+
+// b_d -= A g_d (stored stencil) on the listed rows: the free rows with an
+// inlet-table node among their 27 neighbours, the only rows where g(t^{n+1}),
+// zero off the inlet table, contributes.
+__global__ __launch_bounds__(kBlock) void k_s1_lift(int nrows, const int32_t* __restrict__ rows,
+                                                    const uint8_t* __restrict__ flags,
+                                                    const double* __restrict__ coef,
+                                                    const double* __restrict__ g, double* __restrict__ b,
+                                                    int64_t stride, int sy, int sz) {
+  const int q = blockIdx.x * kBlock + threadIdx.x;
+  if (q >= nrows) return;
+  const int n = rows[q];
   OpStencil<double, 3> A{coef, flags, kFlagF, sy, sz, stride};
   double ag[3];
   A.apply(n, g, ag);
 #pragma unroll
-  for (int d = 0; d < 3; ++d)
-    b[d * stride + n] = apply_sym<double>(u + d * stride, n, e, cm, sy, sz) - gp[d] - ag[d];
+  for (int d = 0; d < 3; ++d) b[d * stride + n] -= ag[d];
 }
 
 // Explicit advection: b_d = (rho/dt)(M u_d) - (rho C(u^n) u^n)_d - G_d p - A' g_d on

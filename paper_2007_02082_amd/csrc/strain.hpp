@@ -214,14 +214,16 @@ struct S1RhsStrainElem {
   }
 };
 
-// b_d -= mu sum_c (X_dc g_c) on the rows (the strain-rate part of the lifting of
-// the Dirichlet data in the tentative-velocity right-hand side).
-__global__ __launch_bounds__(kBlock) void k_strain_lift(NodeList nl, const uint8_t* __restrict__ emask,
-                                                        const uint8_t* __restrict__ flags, uint32_t rowbit,
+// b_d -= mu sum_c (X_dc g_c) on the listed rows (the strain-rate part of the
+// lifting of the Dirichlet data in the tentative-velocity right-hand side; the
+// free rows with an inlet-table node among their neighbours).
+__global__ __launch_bounds__(kBlock) void k_strain_lift(int nrows, const int32_t* __restrict__ rows,
+                                                        const uint8_t* __restrict__ emask,
                                                         const double* __restrict__ g, double* __restrict__ b,
                                                         int64_t stride, double mu, double h, int sy, int sz) {
-  const int n = chunk_node(nl);
-  if (n < 0 || !(flags[n] & rowbit)) return;
+  const int q = blockIdx.x * kBlock + threadIdx.x;
+  if (q >= nrows) return;
+  const int n = rows[q];
   double y[3] = {0.0, 0.0, 0.0};
   apply_strain_cross<double, false>(g, stride, n, emask[n], mu, h, sy, sz, nullptr, y);
 #pragma unroll
