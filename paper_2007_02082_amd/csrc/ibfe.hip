@@ -1340,10 +1340,14 @@ int vcycle(ibfe_ctx& c, std::vector<MGDev<T>>& lv, const T* r0, T* z0, const KSc
     alt[l] = lv[l].xt;
   }
   int np = 0, rc;
+  // with degree-1 pre-smoothing, the restriction onto a level that is not the
+  // coarsest also writes that level's pre-smoothed iterate (c2 D^-1 b from zero)
+  static_assert(kSmooth == 1, "the restriction forms the degree-1 pre-smoothing");
+  const T c2pre = T(cheb_coefs(kSmooth).c2[0]);
   for (int l = 0; l + 1 < L; ++l) {
     const MGDev<T>& A = lv[l];
     const T* b = l == 0 ? r0 : A.b;
-    if ((rc = smooth<T>(c, A, b, cur[l], alt[l], kSmooth, true, false, sc, np))) return rc;
+    if (l == 0 && (rc = smooth<T>(c, A, b, cur[l], alt[l], kSmooth, true, false, sc, np))) return rc;
     if (A.composite) {
       const auto op = csym_op<T, 1>(c, 0.0, 1.0, kMgRow, RefBufs<T>::dinvK(c));
       if ((rc = pre_apply(c, op, cur[l], sc))) return rc;
@@ -1355,9 +1359,12 @@ int vcycle(ibfe_ctx& c, std::vector<MGDev<T>>& lv, const T* r0, T* z0, const KSc
                          (const int*)A.zitems, A.nzitems, level_op(A), (const T*)cur[l], b, A.r, sc);
     }
     const MGDev<T>& C = lv[l + 1];
+    const bool fuse = l + 2 < L;  // level l + 1 is smoothed, not solved
     hipLaunchKernelGGL(k_mg_restrict<T>, dim3(blocks_for(C.nchunks)), dim3(kBlock), 0, c.stream,
                        C.nl, (const uint8_t*)C.flags, int(C.sy), int(C.sz),
-                       int(A.sy), int(A.sz), A.nx, A.ny, A.nz, (const T*)A.r, C.b, sc);
+                       int(A.sy), int(A.sz), A.nx, A.ny, A.nz, (const T*)A.r, C.b, sc,
+                       fuse ? (const uint8_t*)C.emask : (const uint8_t*)nullptr, T(C.kc[0]), c2pre,
+                       fuse ? cur[l + 1] : (T*)nullptr);
     CHECK_LAUNCH();
   }
   {

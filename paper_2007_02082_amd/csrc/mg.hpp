@@ -41,17 +41,22 @@ __device__ __forceinline__ void node_ijk(int n, int sy, int sz, int& i, int& j, 
 
 // bc[I] = sum_j P_jI rf[j] for coarse unknowns I (0 elsewhere); the fine nodes j
 // are the 27 around the node at the same place (2I), weight prod_d (1 - |o_d|/2).
+// With xc, also the coarse level's pre-smoothing from zero, xc = c2 D^-1 bc (the
+// first Chebyshev step; D = c0 times the kept cells), which saves its own pass.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_mg_restrict(NodeList nl,
                                                         const uint8_t* __restrict__ cflags, int csy,
                                                         int csz, int fsy, int fsz, int fnx, int fny,
                                                         int fnz, const T* __restrict__ rf,
-                                                        T* __restrict__ bc, const KScal* sc) {
+                                                        T* __restrict__ bc, const KScal* sc,
+                                                        const uint8_t* __restrict__ cemask = nullptr,
+                                                        T c0 = T(0), T c2 = T(0), T* __restrict__ xc = nullptr) {
   if (sc->done) return;
   const int n = chunk_node(nl);
   if (n < 0) return;
   if (!(cflags[n] & kMgRow)) {
     bc[n] = T(0);
+    if (xc) xc[n] = T(0);
     return;
   }
   int ic, jc, kc;
@@ -74,6 +79,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_restrict(NodeList nl,
     }
   }
   bc[n] = acc;
+  if (xc) xc[n] = T(c2 * acc * (T(1) / (c0 * T(__builtin_popcount(uint32_t(cemask[n]))))));
 }
 
 // xf[j] += sum_I P_jI xc[I] on fine unknowns (trilinear interpolation).
