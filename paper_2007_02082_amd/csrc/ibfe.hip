@@ -1328,8 +1328,11 @@ int smooth(ibfe_ctx& c, const MGDev<T>& L, const T* b, T*& x, T*& alt, int m, bo
 
 // z = V(r): one symmetric V(kSmooth, kSmooth) cycle.  Writes the partials of r.z
 // and returns their count in nparts.
+// pre0: the caller has already written the finest level's pre-smoothing into
+// lv[0].xt (fused into the CG update that produced r0).
 template <typename T>
-int vcycle(ibfe_ctx& c, std::vector<MGDev<T>>& lv, const T* r0, T* z0, const KScal* sc, int& nparts) {
+int vcycle(ibfe_ctx& c, std::vector<MGDev<T>>& lv, const T* r0, T* z0, const KScal* sc, int& nparts,
+           bool pre0 = false) {
   const int L = int(lv.size());
   std::vector<T*> cur(L), alt(L);
   // level 0 result must end in z0: pre (m-1 swaps) + post (m swaps) is odd
@@ -1347,7 +1350,7 @@ int vcycle(ibfe_ctx& c, std::vector<MGDev<T>>& lv, const T* r0, T* z0, const KSc
   for (int l = 0; l + 1 < L; ++l) {
     const MGDev<T>& A = lv[l];
     const T* b = l == 0 ? r0 : A.b;
-    if (l == 0 && (rc = smooth<T>(c, A, b, cur[l], alt[l], kSmooth, true, false, sc, np))) return rc;
+    if (l == 0 && !pre0 && (rc = smooth<T>(c, A, b, cur[l], alt[l], kSmooth, true, false, sc, np))) return rc;
     if (A.composite) {
       const auto op = csym_op<T, 1>(c, 0.0, 1.0, kMgRow, RefBufs<T>::dinvK(c));
       if ((rc = pre_apply(c, op, cur[l], sc))) return rc;
@@ -1407,12 +1410,18 @@ int run_pcg_mg(ibfe_ctx& c, const Op& op, std::vector<MGDev<T>>& lv, const T* b,
   KScal* sc = &c.scal[slot];
   const KScal* csc = sc;
   int rc, np = 0;
+  // the finest level's degree-1 pre-smoothing is formed by the CG kernels that
+  // produce the V-cycle's input (a uniform finest level with more levels below)
+  const bool pre0 = !lv[0].composite && lv.size() > 1;
+  const uint8_t* pe = pre0 ? (const uint8_t*)lv[0].emask : nullptr;
+  T* const px = pre0 ? lv[0].xt : nullptr;
+  const T pc0 = T(lv[0].kc[0]), pc2 = T(cheb_coefs(kSmooth).c2[0]);
   hipLaunchKernelGGL(k_mgcg_init<T>, dim3(nr), dim3(kBlock), 0, c.stream, c.nl,
-                     (const uint8_t*)c.flags, b, x, r, c.partials);
+                     (const uint8_t*)c.flags, b, x, r, c.partials, pe, pc0, pc2, px);
   hipLaunchKernelGGL(k_fin_mgcg_init, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr, sc,
                      rtol * rtol, max_iters);
   CHECK_LAUNCH();
-  if ((rc = vcycle<T>(c, lv, r, z, csc, np))) return rc;
+  if ((rc = vcycle<T>(c, lv, r, z, csc, np, pre0))) return rc;
   hipLaunchKernelGGL(k_fin_mgcg_rz, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, np, sc, 1);
   hipLaunchKernelGGL(k_mgcg_p<T>, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream, c.nl, (const uint8_t*)c.flags, (const T*)z, p, csc);
   CHECK_LAUNCH();
@@ -1429,11 +1438,12 @@ int run_pcg_mg(ibfe_ctx& c, const Op& op, std::vector<MGDev<T>>& lv, const T* b,
         const int nq = launch_q<T>(c, op, c.nl, (const T*)p, q, csc, e0, e1);
         hipLaunchKernelGGL(k_fin_cg_q, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nq, sc);
         hipLaunchKernelGGL(k_mgcg_xr<T>, dim3(nr), dim3(kBlock), 0, c.stream, c.nl,
-                           (const uint8_t*)c.flags, x, r, (const T*)p, (const T*)q, c.partials, csc);
+                           (const uint8_t*)c.flags, x, r, (const T*)p, (const T*)q, c.partials, csc, pe, pc0,
+                           pc2, px);
         hipLaunchKernelGGL(k_fin_mgcg_xr, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr,
                            sc);
         CHECK_LAUNCH();
-        if ((rc2 = vcycle<T>(c, lv, r, z, csc, np))) return rc2;
+        if ((rc2 = vcycle<T>(c, lv, r, z, csc, np, pre0))) return rc2;
         hipLaunchKernelGGL(k_fin_mgcg_rz, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, np,
                            sc, 0);
         hipLaunchKernelGGL(k_mgcg_p<T>, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,

@@ -160,17 +160,23 @@ __global__ __launch_bounds__(kBlock) void k_mg_dot(NodeList nl,
 
 // x = 0, r = b on rows (0 elsewhere); partials r.r, b.b
 template <typename T>
+// With xpre, also the finest level's pre-smoothing of the V-cycle that follows,
+// xpre = c2 D^-1 r from zero (D = c0 times the kept cells around the node).
 __global__ __launch_bounds__(kBlock) void k_mgcg_init(NodeList nl,
                                                       const uint8_t* __restrict__ flags,
                                                       const T* __restrict__ b, T* __restrict__ x,
-                                                      T* __restrict__ r, double* __restrict__ partials) {
+                                                      T* __restrict__ r, double* __restrict__ partials,
+                                                      const uint8_t* __restrict__ emask = nullptr,
+                                                      T c0 = T(0), T c2 = T(0), T* __restrict__ xpre = nullptr) {
   double v[2] = {0.0, 0.0};
   const ChunkRange cr = block_chunks(nl.n);
   for (int c = cr.c0 + int(threadIdx.x >> 6); c < cr.c1; c += kWaves) {
     const int n = nl.node(c);
-    const T bi = (flags[n] & kMgRow) ? b[n] : T(0);
+    const bool rw = flags[n] & kMgRow;
+    const T bi = rw ? b[n] : T(0);
     x[n] = T(0);
     r[n] = bi;
+    if (xpre) xpre[n] = rw ? T(c2 * bi * (T(1) / (c0 * T(__builtin_popcount(uint32_t(emask[n])))))) : T(0);
     v[0] += double(bi) * double(bi);
   }
   v[1] = v[0];
@@ -218,11 +224,14 @@ __global__ __launch_bounds__(kBlock) void k_fin_mgcg_rz(const double* __restrict
 
 // x += alpha p, r -= alpha q on rows; partial r.r
 template <typename T>
+// With xpre, also the finest level's pre-smoothing of the next V-cycle on the
+// rows (its off-row entries hold zeros from k_mgcg_init and the smoothing steps).
 __global__ __launch_bounds__(kBlock) void k_mgcg_xr(NodeList nl,
                                                     const uint8_t* __restrict__ flags, T* __restrict__ x,
                                                     T* __restrict__ r, const T* __restrict__ p,
                                                     const T* __restrict__ q, double* __restrict__ partials,
-                                                    const KScal* sc) {
+                                                    const KScal* sc, const uint8_t* __restrict__ emask = nullptr,
+                                                    T c0 = T(0), T c2 = T(0), T* __restrict__ xpre = nullptr) {
   if (sc->done) return;
   const T alpha = T(sc->alpha);
   double v[1] = {0.0};
@@ -233,6 +242,7 @@ __global__ __launch_bounds__(kBlock) void k_mgcg_xr(NodeList nl,
       x[n] += alpha * p[n];
       const T ri = r[n] - alpha * q[n];
       r[n] = ri;
+      if (xpre) xpre[n] = T(c2 * ri * (T(1) / (c0 * T(__builtin_popcount(uint32_t(emask[n]))))));
       v[0] += double(ri) * double(ri);
     }
   }
