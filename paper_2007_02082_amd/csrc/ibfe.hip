@@ -894,11 +894,28 @@ int run_bicgstab(ibfe_ctx& c, const Op& op, const T* b, T* x, T* const* wv, int 
 template <class Op64, typename TR>
 int ir_residual(ibfe_ctx& c, const Op64& op, const double* b, double* x, TR* r32, double& rr,
                 double& bb) {
-  const int nr = red_blocks(c.nchunks);
+  int nr = red_blocks(c.nchunks);
   int prc;
   if ((prc = pre_apply(c, op, x, (const KScal*)nullptr))) return prc;
-  hipLaunchKernelGGL((k_residual<Op64, TR>), dim3(nr), dim3(kBlock), 0, c.stream, c.nl, op, b,
-                     x, r32, c.partials);
+  if constexpr (std::is_same<Op64, OpSym<double, 1>>::value || std::is_same<Op64, OpSym<double, 3>>::value) {
+    // constant-coefficient symmetric forms of the uniform grid: the z-blocked walk
+    ZOp<double> z{};
+    z.emask = op.emask;
+    z.flags = op.flags;
+    z.rowbit = op.rowbit;
+    z.sy = op.sy;
+    z.sz = op.sz;
+    z.nplanes = c.plan.nz + 1;
+    z.lanes = c.zlanes;
+    z.zb = c.zb;
+    for (int t = 0; t < 4; ++t) z.c[t] = op.c[t];
+    nr = red_blocks(c.nzitems);
+    hipLaunchKernelGGL((k_zb_residual<TR, Op64::kNC>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
+                       c.nzitems, z, b, (const double*)x, r32, op.stride, c.partials);
+  } else {
+    hipLaunchKernelGGL((k_residual<Op64, TR>), dim3(nr), dim3(kBlock), 0, c.stream, c.nl, op, b,
+                       x, r32, c.partials);
+  }
   hipLaunchKernelGGL(k_fin_residual, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr,
                      c.res2);
   CHECK_LAUNCH();

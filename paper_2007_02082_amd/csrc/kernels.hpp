@@ -18,6 +18,8 @@
 // emask & X(ox) & Y(oy) & Z(oz), X(+1) = cells with sx = 1, X(-1) with sx = 0.
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -311,6 +313,24 @@ struct OpStencil {
         }
   }
   __device__ __forceinline__ T inv_diag(int n) const { return T(1) / coef[13 * stride + n]; }
+  // the same product with the loads staged: the 27 coefficients, then the 27
+  // neighbour values of one component at a time, each batch issued before any
+  // use (more loads in flight per wavefront for the FP64 refinement residual)
+  __device__ __forceinline__ void apply_staged(int n, const T* __restrict__ x, T (&y)[NC]) const {
+    T w[27];
+#pragma unroll
+    for (int t = 0; t < 27; ++t) w[t] = coef[t * stride + n];
+#pragma unroll
+    for (int d = 0; d < NC; ++d) {
+      T v[27];
+#pragma unroll
+      for (int t = 0; t < 27; ++t) v[t] = x[d * stride + n + (t % 3 - 1) + sy * ((t / 3) % 3 - 1) + sz * (t / 9 - 1)];
+      T acc = T(0);
+#pragma unroll
+      for (int t = 0; t < 27; ++t) acc += w[t] * v[t];
+      y[d] = acc;
+    }
+  }
 };
 
 // CSR matrix (the IB Gram matrix) over rows [0, nrows), NC right-hand sides.
@@ -758,7 +778,12 @@ __global__ __launch_bounds__(kBlock) void k_residual(NodeList nl, Op op,
     const int n = nl.node(c);
     const bool rw = op.row(n);
     double ax[NC];
-    if (rw) op.apply(n, x, ax);
+    if (rw) {
+      if constexpr (std::is_same<Op, OpStencil<double, 3>>::value)
+        op.apply_staged(n, x, ax);
+      else
+        op.apply(n, x, ax);
+    }
 #pragma unroll
     for (int d = 0; d < NC; ++d) {
       const int64_t i = d * op.stride + n;

@@ -120,6 +120,31 @@ __global__ __launch_bounds__(kBlock) void k_cg_q_zb(const int* __restrict__ item
   block_partials<1>(dot, partials);
 }
 
+// Refinement residual in FP64 on the z-blocked walk, NC identical components:
+// r32 = TR(b - A x) on rows (0 elsewhere) and the partial sums of r.r and b.b.
+template <typename TR, int NC>
+__global__ __launch_bounds__(kBlock) void k_zb_residual(const int* __restrict__ items, int nitems, ZOp<double> op,
+                                                        const double* __restrict__ b, const double* __restrict__ x,
+                                                        TR* __restrict__ r32, int64_t stride,
+                                                        double* __restrict__ partials) {
+  double v[2] = {0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    const double* bq = b + q * stride;
+    TR* rq = r32 + q * stride;
+    auto epi = [&](int node, bool ok, bool rw, uint32_t, double y, double) {
+      if (!ok) return;
+      const double bi = rw ? bq[node] : 0.0;
+      const double ri = rw ? bi - y : 0.0;
+      rq[node] = TR(ri);
+      v[0] += ri * ri;
+      v[1] += bi * bi;
+    };
+    zb_walk<double>(items, nitems, op, x + q * stride, epi, nullptr);
+  }
+  block_partials<2>(v, partials);
+}
+
 // r = b - A x on rows, 0 elsewhere (multigrid residual).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_zb_resid(const int* __restrict__ items, int nitems, ZOp<T> op,
