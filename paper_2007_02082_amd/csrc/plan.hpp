@@ -19,7 +19,7 @@ constexpr int kMaxFloating = 8; // outlet-less connected parts supported
 constexpr uint8_t kMgP = 1u, kMgPp = 16u;
 constexpr int kZBPlanes = 8;     // most planes per z-blocked column item
 constexpr int kZBMinItems = 4096;
-constexpr int kMgCoarsestMax = 512;
+constexpr int kMgCoarsestMax = 1024;
 
 // One level of the geometric multigrid hierarchy of the pressure Poisson
 // operator (level 0 = the grid itself).  Node flags use bit 0 = in P, bit 4 =
