@@ -332,13 +332,21 @@ class Solver:
     def step(self, n: int = 1):
         check(load().ibfe_step(self._h, int(n)))
 
-    def set_points(self, X: np.ndarray, U_B: np.ndarray | None = None):
+    def set_points(self, X, U_B=None):
         """Move the Lagrangian points to X (M x 3) with prescribed velocities U_B (None = 0);
-        the IB operators are rebuilt on the device."""
-        X = np.ascontiguousarray(X, np.float64).reshape(-1, 3)
-        ub = None if U_B is None else np.ascontiguousarray(U_B, np.float64).reshape(-1, 3)
-        check(load().ibfe_set_points(self._h, C.c_void_p(X.ctypes.data),
-                                     None if ub is None else C.c_void_p(ub.ctypes.data), 0))
+        the IB operators are rebuilt on the device.  X and U_B are numpy arrays, or
+        contiguous float64 CUDA tensors (read on the library's stream after the caller's)."""
+        if isinstance(X, np.ndarray):
+            X = np.ascontiguousarray(X, np.float64).reshape(-1, 3)
+            ub = None if U_B is None else np.ascontiguousarray(U_B, np.float64).reshape(-1, 3)
+            check(load().ibfe_set_points(self._h, C.c_void_p(X.ctypes.data),
+                                         None if ub is None else C.c_void_p(ub.ctypes.data), 0))
+            return
+        assert X.is_cuda and X.is_contiguous() and X.numel() == 3 * self.M
+        assert U_B is None or (U_B.is_cuda and U_B.is_contiguous() and U_B.numel() == 3 * self.M)
+        self._after_caller()
+        check(load().ibfe_set_points(self._h, C.c_void_p(X.data_ptr()),
+                                     None if U_B is None else C.c_void_p(U_B.data_ptr()), 1))
 
     def run_steady(self, tol: float, max_steps: int):
         """Step until the step-to-step NRMSE of every velocity component is below tol

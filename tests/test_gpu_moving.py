@@ -114,3 +114,27 @@ def test_set_points_errors_keep_the_context_safe():
     with pytest.raises(ibfe.IbfeError, match="uniform"):
         sr.set_points(rc.X)
     sr.close()
+
+
+def test_set_points_from_device_tensors():
+    """Device pointers (CUDA tensors) give the same rebuild as host arrays."""
+    import torch
+
+    case, wall = synth.pulsating_cylinder(nsteps=2)
+    pr = ipcs.Problem.from_case(case)
+    states = []
+    for on_device in (False, True):
+        s = make_solver(case, precision=0, precond=2)
+        s.set_state(*compact_state(pr, *pr.initial_state(case.u0, case.p0)), 0.0)
+        t = 0.0
+        for _ in range(2):
+            X, U = wall.at(t + case.dt)
+            if on_device:
+                s.set_points(torch.tensor(X, device="cuda"), torch.tensor(U, device="cuda"))
+            else:
+                s.set_points(X, U)
+            s.step(1)
+            t += case.dt
+        states.append(s.get_state())
+        s.close()
+    assert np.array_equal(states[0][0], states[1][0]) and np.array_equal(states[0][1], states[1][1])

@@ -100,3 +100,22 @@ def test_steady_poiseuille_half_millimetre_grid():
     assert uex - linf <= uu[2].max() <= uex
     assert np.abs(uu[:2]).max() <= 1e-2 * uex
     assert np.all(pp[case.p0[P] > 0.0] == 1.0)
+
+
+def test_run_steady_nrmse_on_refined_lattice():
+    """On a 2:1 refined lattice the NRMSE runs over the nodes of P (hanging nodes are
+    not unknowns)."""
+    case = synth.refined_cylinder(8, 8, length=1.25, band=0.3)
+    pr = ipcs.Problem.from_case(case)
+    s = make_solver(case, precision=0, precond=2)
+    u, p = pr.initial_state(case.u0, case.p0)
+    s.set_state(*compact_state(pr, u, p), 0.05)
+    s.step(2)
+    ua, _, _ = s.get_state()
+    steps, nr = s.run_steady(0.0, 1)
+    ub, _, _ = s.get_state()
+    s.close()
+    assert steps == 1
+    ref = steady.nrmse(_full(pr, case, ub), _full(pr, case, ua), pr.sets.P)
+    say("refined nrmse gpu", nr, "oracle formula", ref)
+    assert np.allclose(nr, ref, rtol=1e-12, atol=0.0)
