@@ -57,7 +57,7 @@ constexpr uint32_t kFlagPp = 16u;  // pressure unknown: node of P that is not an
 constexpr int kMaxRows = 8;        // partial rows per reduction (K <= 8)
 constexpr int kRedBlocks = 2048;   // workgroups of a reducing kernel (8 per CU)
 constexpr int kMaxSweeps = 12;     // refinement sweeps of a mixed-precision solve
-constexpr double kInnerRtol = 1e-4;
+constexpr double kInnerRtol = 1e-3;
 
 enum ScalSlot { kScS1 = 0, kScIB, kScS3, kScS4, kScS1i, kScS3i, kScS4i, kScMisc, kNumScal };
 
