@@ -57,6 +57,9 @@ constexpr uint32_t kFlagPp = 16u;  // pressure unknown: node of P that is not an
 constexpr int kMaxRows = 8;        // partial rows per reduction (K <= 8)
 constexpr int kRedBlocks = 2048;   // workgroups of a reducing kernel (8 per CU)
 constexpr int kMaxSweeps = 12;     // refinement sweeps of a mixed-precision solve
+// tightest relative target of an inner FP32 solve: each refinement sweep asks for
+// max(kInnerRtol, 0.5 rtol / residual); tighter floors cost more inner iterations
+// than the FP64 sweeps they save
 constexpr double kInnerRtol = 1e-3;
 
 enum ScalSlot { kScS1 = 0, kScIB, kScS3, kScS4, kScS1i, kScS3i, kScS4i, kScMisc, kNumScal };
