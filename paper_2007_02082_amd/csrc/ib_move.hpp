@@ -252,26 +252,26 @@ __global__ __launch_bounds__(64) void k_gram_rows(int M, const int32_t* __restri
 }
 
 // One workgroup per diagonal block of G: binv = (L L^T)^-1 = L^-T L^-1 in FP32,
-// zero outside the n x n leading part of the last block.
+// zero outside the n x n leading part of the last block.  One LDS array holds the
+// block: the Cholesky factor L overwrites its lower triangle, the inverse factor
+// Li = L^-1 (lower triangular) is kept transposed in the strict upper triangle
+// (Li[r][j] at A[j][r], r > j) with its diagonal in dli.
 __global__ __launch_bounds__(kBlock) void k_gram_block_inv(int M, const int64_t* __restrict__ ptr,
                                                            const int32_t* __restrict__ col,
                                                            const double* __restrict__ val,
                                                            float* __restrict__ binv) {
   constexpr int B = kIBBlock;
-  __shared__ double A[B][B + 1];   // the block, overwritten by L
-  __shared__ double Li[B][B + 1];
+  __shared__ double A[B][B + 1];
+  __shared__ double dli[B];
   const int b = blockIdx.x, t = threadIdx.x;
   const int i0 = b * B;
   const int n = min(B, M - i0);
-  for (int q = t; q < B * B; q += kBlock) {
-    A[q / B][q % B] = 0.0;
-    Li[q / B][q % B] = 0.0;
-  }
+  for (int q = t; q < B * B; q += kBlock) A[q / B][q % B] = 0.0;
   __syncthreads();
   for (int r = t; r < n; r += kBlock)
     for (int64_t q = ptr[i0 + r]; q < ptr[i0 + r + 1]; ++q) {
       const int k = col[q] - i0;
-      if (k >= 0 && k < n) A[r][k] = val[q];
+      if (k >= 0 && k <= r) A[r][k] = val[q];  // the lower triangle of the symmetric block
     }
   __syncthreads();
   // Cholesky, column by column: L_jj, then the column below it
@@ -289,13 +289,13 @@ __global__ __launch_bounds__(kBlock) void k_gram_block_inv(int M, const int64_t*
     }
     __syncthreads();
   }
-  // L^-1, one column per thread
+  // Li = L^-1, one column per thread (column j of Li goes to row j of the upper part)
   for (int j = t; j < n; j += kBlock) {
-    Li[j][j] = 1.0 / A[j][j];
+    dli[j] = 1.0 / A[j][j];
     for (int r = j + 1; r < n; ++r) {
-      double v = 0.0;
-      for (int k = j; k < r; ++k) v -= A[r][k] * Li[k][j];
-      Li[r][j] = v / A[r][r];
+      double v = -A[r][j] * dli[j];
+      for (int k = j + 1; k < r; ++k) v -= A[r][k] * A[j][k];
+      A[j][r] = v / A[r][r];
     }
   }
   __syncthreads();
@@ -304,9 +304,12 @@ __global__ __launch_bounds__(kBlock) void k_gram_block_inv(int M, const int64_t*
     const int r = q / B, c = q % B;
     float o = 0.0f;
     if (r < n && c < n) {
+      // sum over k >= max(r, c) of Li[k][r] Li[k][c]; Li[k][k] = dli[k], Li[k][m] = A[m][k]
       const int lo = r > c ? r : c;
-      double v = 0.0;
-      for (int k = lo; k < n; ++k) v += Li[k][r] * Li[k][c];
+      const double lr = lo == r ? dli[r] : A[r][lo];
+      const double lc = lo == c ? dli[c] : A[c][lo];
+      double v = lr * lc;
+      for (int k = lo + 1; k < n; ++k) v += A[r][k] * A[c][k];
       o = float(v);
     }
     out[r * B + c] = o;

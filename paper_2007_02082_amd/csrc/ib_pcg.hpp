@@ -44,24 +44,27 @@ __global__ __launch_bounds__(kBlock) void k_ibcg_init(NodeList nl, OpCSR<3> op, 
 }
 
 // z = blockdiag(G)^-1 r; partial r.z.  One workgroup per block of points: the
-// residual block (3 x kIBBlock) is staged in LDS, thread t < 3 kIBBlock forms
-// row t % kIBBlock of component t / kIBBlock from the column-major inverse
-// (coalesced reads along the rows).  Grid-stride over the blocks.
+// residual block (3 x kIBBlock) is staged in LDS and the threads take the
+// (component, row) tasks in turn, each forming its row from the column-major
+// inverse (coalesced reads along the rows).  Grid-stride over the blocks.
 __global__ __launch_bounds__(kBlock) void k_ib_bjac(int M, int nblk, const float* __restrict__ binv,
                                                     const double* __restrict__ r, double* __restrict__ z,
                                                     int64_t stride, double* __restrict__ partials,
                                                     const KScal* sc) {
-  static_assert(3 * kIBBlock <= kBlock, "one thread per row and component");
   if (sc && sc->done) return;
   __shared__ double rs[3][kIBBlock];
   double v[1] = {0.0};
   const int t = threadIdx.x;
-  const int d = t / kIBBlock, i = t % kIBBlock;
   for (int b = blockIdx.x; b < nblk; b += gridDim.x) {
     const int i0 = b * kIBBlock;
-    if (t < 3 * kIBBlock) rs[d][i] = (i0 + i < M) ? r[d * stride + i0 + i] : 0.0;
+    for (int task = t; task < 3 * kIBBlock; task += kBlock) {
+      const int d = task / kIBBlock, i = task % kIBBlock;
+      rs[d][i] = (i0 + i < M) ? r[d * stride + i0 + i] : 0.0;
+    }
     __syncthreads();
-    if (t < 3 * kIBBlock && i0 + i < M) {
+    for (int task = t; task < 3 * kIBBlock; task += kBlock) {
+      const int d = task / kIBBlock, i = task % kIBBlock;
+      if (i0 + i >= M) continue;
       const float* col = binv + size_t(b) * kIBBlock * kIBBlock + i;
       double acc = 0.0;
 #pragma unroll 8
@@ -139,10 +142,10 @@ __global__ __launch_bounds__(kBlock) void k_ib_xr_bjac(int M, int nblk, const fl
   const double alpha = sc->alpha;
   double v[2] = {0.0, 0.0};
   const int t = threadIdx.x;
-  const int d = t / kIBBlock, i = t % kIBBlock;
   for (int b = blockIdx.x; b < nblk; b += gridDim.x) {
-    const int gi = b * kIBBlock + i;
-    if (t < 3 * kIBBlock) {
+    for (int task = t; task < 3 * kIBBlock; task += kBlock) {
+      const int d = task / kIBBlock, i = task % kIBBlock;
+      const int gi = b * kIBBlock + i;
       double ri = 0.0;
       if (gi < M) {
         const int64_t k = d * stride + gi;
@@ -154,7 +157,10 @@ __global__ __launch_bounds__(kBlock) void k_ib_xr_bjac(int M, int nblk, const fl
       rs[d][i] = ri;
     }
     __syncthreads();
-    if (t < 3 * kIBBlock && gi < M) {
+    for (int task = t; task < 3 * kIBBlock; task += kBlock) {
+      const int d = task / kIBBlock, i = task % kIBBlock;
+      const int gi = b * kIBBlock + i;
+      if (gi >= M) continue;
       const float* colp = binv + size_t(b) * kIBBlock * kIBBlock + i;
       double acc = 0.0;
 #pragma unroll 8

@@ -11,8 +11,8 @@
 namespace ibfe {
 
 constexpr int kChunk = 64;      // nodes per chunk (one wavefront)
-constexpr double kLaneFill = 0.75;
-constexpr int kIBBlock = 64;     // points per diagonal block of the force-solve preconditioner  // per-lane node lists below this fill of the chunks
+constexpr double kLaneFill = 0.75;  // per-lane node lists below this fill of the chunks
+constexpr int kIBBlock = 128;       // points per diagonal block of the force-solve preconditioner
 constexpr int kMaxHarmonics = 16;
 constexpr int kMaxFloating = 8; // outlet-less connected parts supported
 
