@@ -1395,7 +1395,7 @@ int vcycle(ibfe_ctx& c, std::vector<MGDev<T>>& lv, const T* r0, T* z0, const KSc
     const T* b = L == 1 ? r0 : C.b;
     if (C.m > 0) {
       if (L == 1) cur[0] = z0;  // single level: the dense solve is the whole cycle
-      hipLaunchKernelGGL(k_mg_dense<T>, dim3((C.m + 63) / 64), dim3(kBlock), 0, c.stream, C.m,
+      hipLaunchKernelGGL(k_mg_dense<T>, dim3((C.m + kWaves - 1) / kWaves), dim3(kBlock), 0, c.stream, C.m,
                          (const int64_t*)C.ids, (const T*)C.inv, b, cur[L - 1], sc);
       if (L == 1) {
         np = red_blocks(C.nchunks);
@@ -1801,7 +1801,7 @@ int step_once(ibfe_ctx& c) {
   c.stats.ib_res = 0.0;
   if (P.M > 0) {
     const int M = int(P.M);
-    hipLaunchKernelGGL(k_ib_interp, dim3(blocks_lin(M)), dim3(kBlock), 0, c.stream, M, c.ib_idx, c.ib_w,
+    hipLaunchKernelGGL(k_ib_interp, dim3(blocks_lin(int64_t(M) * 8)), dim3(kBlock), 0, c.stream, M, c.ib_idx, c.ib_w,
                        c.UB, c.ustar, S, c.ibv[0], c.mstride, 1);
     CHECK_LAUNCH();
     const bool warm = c.lam_warm;
@@ -2112,7 +2112,7 @@ int step_once_refined(ibfe_ctx& c) {
   c.stats.ib_res = 0.0;
   if (P.M > 0) {
     const int M = int(P.M);
-    hipLaunchKernelGGL(k_ib_interp, dim3(blocks_lin(M)), dim3(kBlock), 0, c.stream, M, c.ib_idx, c.ib_w,
+    hipLaunchKernelGGL(k_ib_interp, dim3(blocks_lin(int64_t(M) * 8)), dim3(kBlock), 0, c.stream, M, c.ib_idx, c.ib_w,
                        c.UB, c.ustar, S, c.ibv[0], c.mstride, 1);
     CHECK_LAUNCH();
     const bool warm = c.lam_warm;
@@ -2852,7 +2852,7 @@ int ibfe_apply(ibfe_ctx* c, int op, int precision, const double* x, double* y, i
     case IBFE_OP_INTERP: {
       if (P.M == 0) return fail(IBFE_EINVAL, "no Lagrangian points");
       const int M = int(P.M);
-      hipLaunchKernelGGL(k_ib_interp, dim3(blocks_lin(M)), dim3(kBlock), 0, C.stream, M, C.ib_idx, C.ib_w,
+      hipLaunchKernelGGL(k_ib_interp, dim3(blocks_lin(int64_t(M) * 8)), dim3(kBlock), 0, C.stream, M, C.ib_idx, C.ib_w,
                          C.UB, xin, S, C.ibv[0], C.mstride, 0);
       CHECK_LAUNCH();
       std::vector<double> h(3 * C.mstride);

@@ -108,36 +108,27 @@ __global__ __launch_bounds__(kBlock) void k_mg_prolong(NodeList nl,
   xf[n] += acc;
 }
 
-// Coarsest level: x[u_i] = sum_j inv[i][j] b[u_j] (m <= 1024, inv column major).
-// Workgroup g forms rows 64 g .. 64 g + 63: its four wavefronts take a quarter of
-// the columns each (lane = row, coalesced along the column) and the four partial
-// sums are added in LDS in a fixed order.
+// Coarsest level: x[u_i] = sum_j inv[i][j] b[u_j] (m <= 1024).  The inverse is
+// symmetric (formed as L^-T L^-1 with both triangles written from the same sums),
+// so row i is the contiguous column i: one wavefront per row reads it coalesced
+// along the lanes, sums in FP64 and reduces across the wavefront in a fixed order;
+// the m rows spread over m / 4 workgroups.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_mg_dense(int m, const int64_t* __restrict__ ids,
                                                      const T* __restrict__ inv, const T* __restrict__ b,
                                                      T* __restrict__ x, const KScal* sc) {
-  static_assert(kWaves == 4, "four partial sums per row");
   if (sc->done) return;
   __shared__ T bs[1024];
-  __shared__ T part[kWaves][64];
   for (int j = threadIdx.x; j < m; j += kBlock) bs[j] = b[ids[j]];
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int i = blockIdx.x * 64 + lane;
-  const int jc = (m + kWaves - 1) / kWaves;
-  const int j0 = wave * jc, j1 = min(m, j0 + jc);
-  T acc0 = T(0), acc1 = T(0);
-  if (i < m) {
-    int j = j0;
-    for (; j + 1 < j1; j += 2) {
-      acc0 += inv[int64_t(j) * m + i] * bs[j];
-      acc1 += inv[int64_t(j + 1) * m + i] * bs[j + 1];
-    }
-    if (j < j1) acc0 += inv[int64_t(j) * m + i] * bs[j];
-  }
-  part[wave][lane] = acc0 + acc1;
-  __syncthreads();
-  if (wave == 0 && i < m) x[ids[i]] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+  const int i = blockIdx.x * kWaves + wave;
+  if (i >= m) return;
+  const T* row = inv + int64_t(i) * m;
+  double acc = 0.0;
+  for (int j = lane; j < m; j += 64) acc += double(row[j]) * double(bs[j]);
+  acc = wave_sum(acc);
+  if (lane == 0) x[ids[i]] = T(acc);
 }
 
 // partials of a.b over rows

@@ -265,24 +265,40 @@ __global__ __launch_bounds__(kBlock) void k_apply(NodeList nl, Op op,
 // ---------------------------------------------------------------------------
 
 // b_d[i] = U_B[i][d] - sum_s w[s][i] u_d[idx[s][i]]   (Eq. 23 with h^3 D = w)
+// Eight lanes per point: lane g * 8 + p of a wavefront sums slots 8 g .. 8 g + 7 of
+// point 8 w + p (w the wavefront's point group), so the lanes of one slot group
+// read 8 consecutive points of the slot-major stencil; the eight partial sums of a
+// point are added across the lanes in a fixed order.  Grid: ceil(M / 8) wavefronts.
 __global__ __launch_bounds__(kBlock) void k_ib_interp(int M, const int32_t* __restrict__ idx,
                                                       const double* __restrict__ w,
                                                       const double* __restrict__ UB,
                                                       const double* __restrict__ u, int64_t stride,
                                                       double* __restrict__ b, int64_t bstride,
                                                       int with_ub) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= M) return;
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 3, p = lane & 7;
+  const int i = (blockIdx.x * kWaves + int(threadIdx.x >> 6)) * 8 + p;
+  const bool ok = i < M;
   double acc[3] = {0.0, 0.0, 0.0};
-  for (int s = 0; s < 64; ++s) {
-    const int n = idx[int64_t(s) * M + i];
-    if (n < 0) continue;
-    const double ws = w[int64_t(s) * M + i];
+  if (ok) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) acc[d] += ws * u[d * stride + n];
+    for (int k = 0; k < 8; ++k) {
+      const int s = 8 * g + k;
+      const int n = idx[int64_t(s) * M + i];
+      if (n < 0) continue;
+      const double ws = w[int64_t(s) * M + i];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) acc[d] += ws * u[d * stride + n];
+    }
   }
 #pragma unroll
-  for (int d = 0; d < 3; ++d) b[d * bstride + i] = (with_ub ? UB[3 * i + d] : 0.0) - acc[d];
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int off = 8; off < 64; off <<= 1) acc[d] += __shfl_xor(acc[d], off, 64);
+  if (ok && g == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) b[d * bstride + i] = (with_ub ? UB[3 * i + d] : 0.0) - acc[d];
+  }
 }
 
 // u_d[node] += sum_{points} w lam_d[point] over free support nodes (I_F^T lam),
