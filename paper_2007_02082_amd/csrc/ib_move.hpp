@@ -276,10 +276,12 @@ __global__ __launch_bounds__(kBlock) void k_gram_block_inv(int M, const int64_t*
   __syncthreads();
   // Cholesky, column by column: L_jj, then the column below it
   for (int j = 0; j < n; ++j) {
-    if (t == 0) {
-      double d = A[j][j];
-      for (int k = 0; k < j; ++k) d -= A[j][k] * A[j][k];
-      A[j][j] = sqrt(fmax(d, 1e-300));
+    if (t < 64) {
+      // L_jj^2 = A_jj - sum_{k<j} L_jk^2, the sum split over the first wavefront
+      double d = 0.0;
+      for (int k = t; k < j; k += 64) d += A[j][k] * A[j][k];
+      d = wave_sum(d);
+      if (t == 0) A[j][j] = sqrt(fmax(A[j][j] - d, 1e-300));
     }
     __syncthreads();
     for (int r = j + 1 + t; r < n; r += kBlock) {
