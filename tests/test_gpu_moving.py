@@ -138,3 +138,35 @@ def test_set_points_from_device_tensors():
         states.append(s.get_state())
         s.close()
     assert np.array_equal(states[0][0], states[1][0]) and np.array_equal(states[0][1], states[1][1])
+
+
+def test_translating_ring_band_changes_the_force_pattern():
+    """A band of wall rings moved along the axis by 0.8 h per step (with the wall held
+    at rest: U_B is an input of its own, and a wall speed of 0.8 h / dt would dominate
+    the flow): the supports, the spreading lists and the sparsity of G change from
+    step to step; every step against the oracle (FP64), and the empty point set is
+    accepted."""
+    case = synth.small_cylinder(8, 16, nsteps=3)
+    th = 2 * np.pi * np.arange(12) / 12
+    zl = np.array([0.6, 0.75, 0.9, 1.05])
+    zz, tt = np.meshgrid(zl, th, indexing="ij")
+    X0 = np.stack([0.5 * np.cos(tt).ravel(), 0.5 * np.sin(tt).ravel(), zz.ravel()], axis=1)
+    v = 0.8 * case.h / case.dt
+    U = np.zeros_like(X0)
+    case.X, case.U_B = X0, U
+    case.dS = 0.1 * case.h
+
+    class Translate:
+        def at(self, t):
+            return X0 + np.array([0.0, 0.0, v * t]), U
+
+    out = _run_moving(case, Translate(), 3, 0.0, precision=0, precond=2)
+    _check_steps(out, TOL64, "translating band")
+    # no points at all: a no-op
+    c0 = synth.small_cylinder(8, 16, nsteps=1)
+    c0.X = np.zeros((0, 3))
+    c0.U_B = None
+    s = make_solver(c0, precision=0)
+    s.set_points(np.zeros((0, 3)))
+    s.step(1)
+    s.close()
