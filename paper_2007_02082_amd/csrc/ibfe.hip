@@ -849,45 +849,55 @@ int run_bicgstab(ibfe_ctx& c, const Op& op, const T* b, T* x, T* const* wv, int 
   KScal* sc = &c.scal[slot];
   const KScal* csc = sc;
   int prc;
-  if ((prc = pre_apply(c, op, x, (const KScal*)nullptr))) return prc;
-  hipLaunchKernelGGL((k_bi_init<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, nl, op, b, x, r, rhat, p,
-                     v, c.partials);
-  hipLaunchKernelGGL(k_fin_bi_init, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc, rtol * rtol, max_iters);
-  CHECK_LAUNCH();
-  int launched = 0;
+  // a breakdown (rhat.v = 0 or t.t = 0 before convergence) restarts the method from
+  // the current iterate with a fresh shadow residual, at most three times
+  int total = 0;
   KScal st{};
-  while (true) {
-    const int batch = std::min(next_batch(c.est[slot], launched), max_iters + 1 - launched);
-    auto body = [&]() -> int {
-      for (int k = 0; k < batch; ++k) {
-        int rc2;
-        hipLaunchKernelGGL((k_bi_p<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, nl, op, r, p, v, phat,
-                           csc);
-        if ((rc2 = pre_apply(c, op, phat, csc))) return rc2;
-        hipLaunchKernelGGL((k_bi_apply<T, Op, 0>), dim3(nr), dim3(kBlock), 0, c.stream, nl, op, phat, v,
-                           rhat, c.partials, csc);
-        hipLaunchKernelGGL(k_fin_bi_apply<0>, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc);
-        hipLaunchKernelGGL((k_bi_s<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, nl, op, r, v, s, shat,
-                           csc);
-        if ((rc2 = pre_apply(c, op, shat, csc))) return rc2;
-        hipLaunchKernelGGL((k_bi_apply<T, Op, 1>), dim3(nr), dim3(kBlock), 0, c.stream, nl, op, shat, t,
-                           s, c.partials, csc);
-        hipLaunchKernelGGL(k_fin_bi_apply<1>, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc);
-        hipLaunchKernelGGL((k_bi_x<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, nl, op, x, r, rhat,
-                           phat, shat, s, t, c.partials, csc);
-        hipLaunchKernelGGL(k_fin_bi_x, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc);
-        CHECK_LAUNCH();
-      }
-      return IBFE_OK;
-    };
-    if ((prc = graph_run(c, graph_key(kGsBicg, slot, sizeof(T), batch), body))) return prc;
-    launched += batch;
-    int rc = poll(c, slot, st);
-    if (rc) return rc;
-    if (st.done || launched > max_iters) break;
+  for (int restart = 0;; ++restart) {
+    if ((prc = pre_apply(c, op, x, (const KScal*)nullptr))) return prc;
+    hipLaunchKernelGGL((k_bi_init<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, nl, op, b, x, r, rhat, p,
+                       v, c.partials);
+    hipLaunchKernelGGL(k_fin_bi_init, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc, rtol * rtol,
+                       max_iters - total);
+    CHECK_LAUNCH();
+    int launched = 0;
+    while (true) {
+      const int batch = std::min(next_batch(c.est[slot], launched), max_iters - total + 1 - launched);
+      auto body = [&]() -> int {
+        for (int k = 0; k < batch; ++k) {
+          int rc2;
+          hipLaunchKernelGGL((k_bi_p<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, nl, op, r, p, v, phat,
+                             csc);
+          if ((rc2 = pre_apply(c, op, phat, csc))) return rc2;
+          hipLaunchKernelGGL((k_bi_apply<T, Op, 0>), dim3(nr), dim3(kBlock), 0, c.stream, nl, op, phat, v,
+                             rhat, c.partials, csc);
+          hipLaunchKernelGGL(k_fin_bi_apply<0>, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc);
+          hipLaunchKernelGGL((k_bi_s<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, nl, op, r, v, s, shat,
+                             csc);
+          if ((rc2 = pre_apply(c, op, shat, csc))) return rc2;
+          hipLaunchKernelGGL((k_bi_apply<T, Op, 1>), dim3(nr), dim3(kBlock), 0, c.stream, nl, op, shat, t,
+                             s, c.partials, csc);
+          hipLaunchKernelGGL(k_fin_bi_apply<1>, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc);
+          hipLaunchKernelGGL((k_bi_x<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, nl, op, x, r, rhat,
+                             phat, shat, s, t, c.partials, csc);
+          hipLaunchKernelGGL(k_fin_bi_x, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc);
+          CHECK_LAUNCH();
+        }
+        return IBFE_OK;
+      };
+      if ((prc = graph_run(c, graph_key(kGsBicg, slot, sizeof(T), batch), body))) return prc;
+      launched += batch;
+      int rc = poll(c, slot, st);
+      if (rc) return rc;
+      if (st.done || launched > max_iters - total) break;
+    }
+    total += st.iters;
+    if (st.status == 1 && restart < 3 && total < max_iters) continue;
+    break;
   }
-  c.est[slot] = std::max(1, st.iters);
-  out.iters = st.iters;
+  st.iters = total;
+  c.est[slot] = std::max(1, total);
+  out.iters = total;
   out.res = st.bb > 0.0 ? std::sqrt(st.rr / st.bb) : 0.0;
   return finish_status(st, "BiCGStab");
 }
