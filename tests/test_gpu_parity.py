@@ -354,7 +354,7 @@ def test_step_parity_strain_rate_form(make, precision, tol, advection):
 
 
 # ---------------------------------------------------------------------------
-# wall shear stress at the Lagrangian points (survey NEXT-f2)
+# wall shear stress at the Lagrangian points
 # ---------------------------------------------------------------------------
 
 def _cyl_normals(case):
