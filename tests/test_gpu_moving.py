@@ -170,3 +170,22 @@ def test_translating_ring_band_changes_the_force_pattern():
     s.set_points(np.zeros((0, 3)))
     s.step(1)
     s.close()
+
+
+def test_too_dense_points_are_rejected():
+    """All 96 points inside half a cell: a row of G would gather 64 x 96 support
+    products, more than the 1024 a row holds; the rebuild reports IBFE_EINVAL (the kernel checks the count
+    before it stages anything) and the context refuses to step until valid points
+    are set."""
+    case, wall = synth.pulsating_cylinder(nsteps=1)
+    s = make_solver(case, precision=0, precond=2)
+    rng = np.random.default_rng(5)
+    dense = case.X.copy()
+    dense[:] = np.array([0.3, 0.0, 1.0]) + 0.5 * case.h * rng.random((case.M, 3))
+    with pytest.raises(ibfe.IbfeError, match="EINVAL"):
+        s.set_points(dense)
+    with pytest.raises(ibfe.IbfeError, match="EINVAL"):
+        s.step(1)
+    s.set_points(*wall.at(case.dt))
+    s.step(1)
+    s.close()
