@@ -316,8 +316,8 @@ def main() -> int:
                          "kernel of known size for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (the boxes have one GPU); --gpus {args.gpus} "
-              "is not supported", file=sys.stderr)
+        print(f"bench.py measures the path on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU decomposition is a design, not an implementation)", file=sys.stderr)
         return 2
 
     import numpy as np
