@@ -82,7 +82,10 @@ __global__ __launch_bounds__(kBlock) void k_mg_restrict(NodeList nl,
   if (xc) xc[n] = T(c2 * acc * (T(1) / (c0 * T(__builtin_popcount(uint32_t(cemask[n]))))));
 }
 
-// xf[j] += sum_I P_jI xc[I] on fine unknowns (trilinear interpolation).
+// xf[j] += sum_I P_jI xc[I] on fine unknowns (trilinear interpolation).  All
+// eight corner loads are issued at once: along an axis with an even fine index
+// the second corner is the first one again with weight 0, so the sum (taken in
+// the fixed corner order) equals that over the parents alone.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_mg_prolong(NodeList nl,
                                                        const uint8_t* __restrict__ fflags, int fsy,
@@ -94,18 +97,20 @@ __global__ __launch_bounds__(kBlock) void k_mg_prolong(NodeList nl,
   if (n < 0 || !(fflags[n] & kMgRow)) return;
   int i, j, k;
   node_ijk(n, fsy, fsz, i, j, k);
-  const int i0 = i >> 1, j0 = j >> 1, k0 = k >> 1;
-  const int i1 = i0 + (i & 1), j1 = j0 + (j & 1), k1 = k0 + (k & 1);
-  const T wx = (i & 1) ? T(0.5) : T(1), wy = (j & 1) ? T(0.5) : T(1), wz = (k & 1) ? T(0.5) : T(1);
-  T acc = T(0);
-  const int cz[2] = {k0, k1}, cyy[2] = {j0, j1}, cx[2] = {i0, i1};
+  const int ox = i & 1, oy = j & 1, oz = k & 1;
+  const T* c0 = xc + (i >> 1) + csy * (j >> 1) + csz * (k >> 1);
+  const int dx = ox, dy = oy * csy, dz = oz * csz;
+  const T xold = xf[n];
+  T v[8];
 #pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const int a = c & 1, bq = (c >> 1) & 1, e = (c >> 2) & 1;
-    if ((a && !(i & 1)) || (bq && !(j & 1)) || (e && !(k & 1))) continue;
-    acc += wx * wy * wz * xc[cx[a] + csy * cyy[bq] + csz * cz[e]];
-  }
-  xf[n] += acc;
+  for (int c = 0; c < 8; ++c) v[c] = c0[(c & 1 ? dx : 0) + (c & 2 ? dy : 0) + (c & 4 ? dz : 0)];
+  const T wx[2] = {ox ? T(0.5) : T(1), ox ? T(0.5) : T(0)};
+  const T wy[2] = {oy ? T(0.5) : T(1), oy ? T(0.5) : T(0)};
+  const T wz[2] = {oz ? T(0.5) : T(1), oz ? T(0.5) : T(0)};
+  T acc = T(0);
+#pragma unroll
+  for (int c = 0; c < 8; ++c) acc += wx[c & 1] * wy[(c >> 1) & 1] * wz[(c >> 2) & 1] * v[c];
+  xf[n] = xold + acc;
 }
 
 // Coarsest level: x[u_i] = sum_j inv[i][j] b[u_j] (m <= 1024).  The inverse is
