@@ -63,21 +63,30 @@ __global__ __launch_bounds__(kBlock) void k_mg_restrict(NodeList nl,
   node_ijk(n, csy, csz, ic, jc, kc);
   const int fi = 2 * ic, fj = 2 * jc, fk = 2 * kc;
   const int fc = fi + fsy * fj + fsz * fk;
+  // per-axis offsets and weights; an offset that leaves the grid is replaced by
+  // the centre with weight 0, so all 27 loads issue at once and the sum (in the
+  // fixed order below) equals that over the nodes inside the grid
+  int dx[3], dy[3], dz[3];
+  T wx[3], wy[3], wz[3];
+#pragma unroll
+  for (int o = -1; o <= 1; ++o) {
+    const T wo = o ? T(0.5) : T(1);
+    const bool inx = fi + o >= 0 && fi + o <= fnx;
+    const bool iny = fj + o >= 0 && fj + o <= fny;
+    const bool inz = fk + o >= 0 && fk + o <= fnz;
+    dx[o + 1] = inx ? o : 0;
+    dy[o + 1] = iny ? o * fsy : 0;
+    dz[o + 1] = inz ? o * fsz : 0;
+    wx[o + 1] = inx ? wo : T(0);
+    wy[o + 1] = iny ? wo : T(0);
+    wz[o + 1] = inz ? wo : T(0);
+  }
+  T v[27];
+#pragma unroll
+  for (int q = 0; q < 27; ++q) v[q] = rf[fc + dx[q % 3] + dy[(q / 3) % 3] + dz[q / 9]];
   T acc = T(0);
 #pragma unroll
-  for (int oz = -1; oz <= 1; ++oz) {
-    if (fk + oz < 0 || fk + oz > fnz) continue;
-#pragma unroll
-    for (int oy = -1; oy <= 1; ++oy) {
-      if (fj + oy < 0 || fj + oy > fny) continue;
-#pragma unroll
-      for (int ox = -1; ox <= 1; ++ox) {
-        if (fi + ox < 0 || fi + ox > fnx) continue;
-        const int t = (ox != 0) + (oy != 0) + (oz != 0);
-        acc += T(1.0 / double(1 << t)) * rf[fc + ox + fsy * oy + fsz * oz];
-      }
-    }
-  }
+  for (int q = 0; q < 27; ++q) acc += (wx[q % 3] * wy[(q / 3) % 3] * wz[q / 9]) * v[q];
   bc[n] = acc;
   if (xc) xc[n] = T(c2 * acc * (T(1) / (c0 * T(__builtin_popcount(uint32_t(cemask[n]))))));
 }
