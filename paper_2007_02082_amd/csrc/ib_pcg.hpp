@@ -138,7 +138,9 @@ __global__ __launch_bounds__(kBlock) void k_ib_xr_bjac(int M, int nblk, const fl
                                                        double* __restrict__ z, int64_t stride,
                                                        double* __restrict__ partials, const KScal* sc) {
   if (sc->done) return;
+  static_assert(kBlock == 2 * kIBBlock, "two threads per row of a point block");
   __shared__ double rs[3][kIBBlock];
+  __shared__ double zh[3][kIBBlock];
   const double alpha = sc->alpha;
   double v[2] = {0.0, 0.0};
   const int t = threadIdx.x;
@@ -157,16 +159,36 @@ __global__ __launch_bounds__(kBlock) void k_ib_xr_bjac(int M, int nblk, const fl
       rs[d][i] = ri;
     }
     __syncthreads();
-    for (int task = t; task < 3 * kIBBlock; task += kBlock) {
-      const int d = task / kIBBlock, i = task % kIBBlock;
+    {
+      // row i of the block inverse, columns j in half h: each entry is loaded once
+      // and applied to the three components; the two halves are summed in LDS
+      const int i = t % kIBBlock, h = t / kIBBlock;
       const int gi = b * kIBBlock + i;
-      if (gi >= M) continue;
-      const float* colp = binv + size_t(b) * kIBBlock * kIBBlock + i;
-      double acc = 0.0;
-#pragma unroll 8
-      for (int j = 0; j < kIBBlock; ++j) acc += double(colp[j * kIBBlock]) * rs[d][j];
-      z[d * stride + gi] = acc;
-      v[1] += rs[d][i] * acc;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+      if (gi < M) {
+        const float* colp = binv + size_t(b) * kIBBlock * kIBBlock + i;
+        const int j0 = h * (kIBBlock / 2);
+#pragma unroll 16
+        for (int j = j0; j < j0 + kIBBlock / 2; ++j) {
+          const double g = double(colp[j * kIBBlock]);
+          a0 += g * rs[0][j];
+          a1 += g * rs[1][j];
+          a2 += g * rs[2][j];
+        }
+      }
+      if (h == 1) {
+        zh[0][i] = a0;
+        zh[1][i] = a1;
+        zh[2][i] = a2;
+      }
+      __syncthreads();
+      if (h == 0 && gi < M) {
+        const double z0 = a0 + zh[0][i], z1 = a1 + zh[1][i], z2 = a2 + zh[2][i];
+        z[gi] = z0;
+        z[stride + gi] = z1;
+        z[2 * stride + gi] = z2;
+        v[1] += rs[0][i] * z0 + rs[1][i] * z1 + rs[2][i] * z2;
+      }
     }
     __syncthreads();
   }
