@@ -152,7 +152,11 @@ typedef struct ibfe_params {
 } ibfe_params;
 
 /*
- * Inlet velocity table.  The prescribed velocity at table node q and time t is
+ * Inlet velocity table (the paper prescribes a parabolic inlet profile in the
+ * angle-tube test of Section 3.2 and a pulsatile inlet waveform with a parabolic
+ * profile in the coronary example of Section 4.1; a Fourier series in time with a
+ * spatial shape per harmonic covers both).  The prescribed velocity at table node
+ * q and time t is
  *   u_in = W_0 + sum_{k=1..K} [ Re W_k cos(k omega t) - Im W_k sin(k omega t) ]
  * (the real part of sum_k W_k e^{i k omega t}).  shape holds (2K+1) blocks of
  * n x 3 doubles: W_0, Re W_1, Im W_1, ..., Re W_K, Im W_K (each block row major
@@ -188,6 +192,8 @@ typedef struct ibfe_stats {
   int64_t poisson_applies;   /* number of those launches (timed if enabled)      */
   double mass_apply_ms;      /* summed duration of the mass Chebyshev steps of   */
   int64_t mass_applies;      /* the velocity correction, and their number        */
+  int32_t s1_restarts;       /* BiCGStab restarts after a breakdown (r^.v = 0 or  */
+  int32_t reserved_;         /* t.t = 0 before convergence), at most 3 per solve */
 } ibfe_stats;
 
 typedef struct ibfe_plan ibfe_plan;
@@ -255,6 +261,32 @@ int ibfe_set_points(ibfe_ctx* ctx, const double* X, const double* U_B, int on_de
 int ibfe_run_steady(ibfe_ctx* ctx, double tol, int64_t max_steps, int64_t* steps, double* nrmse);
 /* Read u, p (either may be NULL) and t; synchronises the stream for host output. */
 int ibfe_get_state(ibfe_ctx* ctx, double* u, double* p, double* t, int on_device);
+
+/* Checkpoint and restart of the time stepping (Section 2.4 advances (u^n, p^n) to
+ * (u^{n+1}, p^{n+1}); the library also carries, from one step to the next, the
+ * initial guesses of its iterative solves: the IB force Lambda of Eq. 23, the
+ * pressure increment Phi of Eq. 12 and the mass correction of the velocity
+ * update).  A checkpoint holds u, p, t, the step count and those three guesses, so
+ * that k steps, save, load into a context created from the same inputs, and
+ * N - k more steps give bitwise the state of N uninterrupted steps (ibfe_set_state
+ * instead starts the solves cold: the same state within the solver tolerances).
+ * Layout: a 48-byte header (magic "IBFECKP1", n_p, M, t, steps, flags), then FP64
+ * arrays in canonical order: u (3 x n_u), p (n_p), Phi (n_p), the mass correction
+ * (3 x n_u), Lambda (3 x M, component planes).  buf is host memory of at least
+ * ibfe_checkpoint_size bytes; the caller owns it.  Moved Lagrangian points are
+ * not part of the checkpoint: call ibfe_set_points again after a load.
+ * ibfe_checkpoint_load refuses (IBFE_EINVAL) a buffer whose header does not match
+ * the context's sizes.  Both calls synchronise the stream. */
+int ibfe_checkpoint_size(const ibfe_ctx* ctx, size_t* bytes);
+int ibfe_checkpoint_save(ibfe_ctx* ctx, void* buf, size_t bytes);
+int ibfe_checkpoint_load(ibfe_ctx* ctx, const void* buf, size_t bytes);
+
+/* Testing aid for the failure paths: make the next tentative-velocity BiCGStab
+ * solve of this context report a breakdown once its iteration count reaches
+ * `iteration` (> 0; 0 cancels), as if r^.v or t.t had vanished.  The solver then
+ * restarts from its current iterate (ibfe_stats.s1_restarts counts it).  No
+ * effect on the CG paths (advection = 1). */
+int ibfe_inject_breakdown(ibfe_ctx* ctx, int iteration);
 int ibfe_get_stats(const ibfe_ctx* ctx, ibfe_stats* stats);
 /* Enable (1) or disable (0) HIP-event timing of the pressure stiffness apply
  * and of the mass Chebyshev step of the velocity correction (both counters are
@@ -269,7 +301,7 @@ int ibfe_set_kernel_timing(ibfe_ctx* ctx, int enable);
 int ibfe_set_graphs(ibfe_ctx* ctx, int enable);
 
 /* Wall shear stress at the Lagrangian points for the current velocity (the
- * paper's clinical output of Section 4, evaluated at the immersed wall points):
+ * paper's clinical output, defined in Section 2.6, evaluated at the immersed wall points):
  * the nodal velocity gradient by the lumped L2 projection of the Q1 gradient,
  * g_de = (G_e u_d) / m with m the row sum of the mass matrix, its symmetric part
  * eps interpolated to each point with the kernel of Eq. 18 (the weights of the

@@ -1,8 +1,9 @@
 """Wall shear stress at the Lagrangian points (oracle; test infrastructure).
 
-The paper reports the wall shear stress of its patient vessels (Section 4),
-computed there on a body-fitted mesh.  Here it is evaluated at the immersed
-wall points from the grid velocity, in four plain steps:
+The paper defines the wall shear stress as the tangential part of the traction
+2 mu eps n (Section 2.6) and computes it on a body-fitted mesh of its vessels.
+Here it is evaluated at the immersed wall points from the grid velocity, in four
+plain steps:
 
 1. nodal velocity gradient by the lumped L2 projection of the Q1 gradient:
    g_de(j) = (G_e u_d)_j / m_j with the weak gradient G_e of the momentum

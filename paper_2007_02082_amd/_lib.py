@@ -58,7 +58,7 @@ class Stats(C.Structure):
                 ("s1_res", C.c_double), ("ib_res", C.c_double), ("s3_res", C.c_double),
                 ("s4_res", C.c_double), ("poisson_apply_ms", C.c_double),
                 ("poisson_applies", C.c_int64), ("mass_apply_ms", C.c_double),
-                ("mass_applies", C.c_int64)]
+                ("mass_applies", C.c_int64), ("s1_restarts", C.c_int32), ("reserved_", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -100,6 +100,10 @@ SIGNATURES = {
     "ibfe_set_points": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "ibfe_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, dp, C.c_int]),
     "ibfe_get_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
+    "ibfe_checkpoint_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    "ibfe_checkpoint_save": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "ibfe_checkpoint_load": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "ibfe_inject_breakdown": (C.c_int, [C.c_void_p, C.c_int]),
     "ibfe_set_kernel_timing": (C.c_int, [C.c_void_p, C.c_int]),
     "ibfe_set_graphs": (C.c_int, [C.c_void_p, C.c_int]),
     "ibfe_get_field": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int]),
@@ -274,6 +278,7 @@ class Solver:
             alloc = C.byref(a)
         import torch
 
+        self._dev = torch.cuda.current_device()
         if stream is None:
             # a stream of its own (default priority): the null stream cannot be captured
             # into graphs; device tensors passed in are ordered against the current stream
@@ -291,12 +296,36 @@ class Solver:
         self.M = self._in.X.shape[0]
 
     # -- helpers ---------------------------------------------------------------
-    @staticmethod
-    def _arg(x):
-        """(pointer, on_device) for a numpy array or a torch tensor."""
+    def _vec(self, x, n: int, what: str, writable: bool = False):
+        """(keep-alive object, pointer, on_device) for n float64 values held by a numpy
+        array (converted to a contiguous float64 copy when read-only use allows it) or
+        a torch tensor (float64, contiguous, exactly n elements; a CUDA tensor must be
+        on this solver's device).  Anything else raises ValueError before the library
+        sees the pointer, so a short or mistyped buffer never reaches a kernel."""
         if isinstance(x, np.ndarray):
-            return C.c_void_p(x.ctypes.data), 0
-        return C.c_void_p(x.data_ptr()), 1 if x.is_cuda else 0
+            if writable:
+                if x.dtype != np.float64 or not x.flags.c_contiguous or not x.flags.writeable:
+                    raise ValueError(f"{what}: need a writable C-contiguous float64 array")
+            else:
+                x = np.ascontiguousarray(x, np.float64)
+            if x.size != n:
+                raise ValueError(f"{what}: {x.size} values given, {n} expected")
+            return x, C.c_void_p(x.ctypes.data), 0
+        try:
+            import torch
+        except ImportError:  # pragma: no cover - torch is a dependency of the package
+            torch = None
+        if torch is None or not isinstance(x, torch.Tensor):
+            raise ValueError(f"{what}: need a numpy array or a torch tensor, got {type(x).__name__}")
+        if x.dtype != torch.float64:
+            raise ValueError(f"{what}: tensor dtype {x.dtype}, float64 expected")
+        if not x.is_contiguous():
+            raise ValueError(f"{what}: tensor is not contiguous")
+        if x.numel() != n:
+            raise ValueError(f"{what}: {x.numel()} values given, {n} expected")
+        if x.is_cuda and getattr(self, "_dev", None) is not None and x.device.index != self._dev:
+            raise ValueError(f"{what}: tensor on cuda:{x.device.index}, solver on cuda:{self._dev}")
+        return x, C.c_void_p(x.data_ptr()), 1 if x.is_cuda else 0
 
     def node_ids(self) -> np.ndarray:
         out = np.empty(self.n_u, np.int64)
@@ -319,14 +348,14 @@ class Solver:
         check(load().ibfe_set_graphs(self._h, 1 if enable else 0))
 
     def set_state(self, u, p, t: float = 0.0):
-        if not isinstance(u, np.ndarray):
+        """u: 3 x n_u values (SoA), p: n_p values; both numpy arrays or both tensors of
+        one kind (host or this solver's device)."""
+        u, pu, du = self._vec(u, 3 * self.n_u, "u")
+        p, pp, dp_ = self._vec(p, self.n_p, "p")
+        if du != dp_:
+            raise ValueError("u and p must both be host or both be device memory")
+        if du:
             self._after_caller()
-        if isinstance(u, np.ndarray):
-            u = np.ascontiguousarray(u, np.float64)
-            p = np.ascontiguousarray(p, np.float64)
-            assert u.size == 3 * self.n_u and p.size == self.n_p
-        pu, du = self._arg(u)
-        pp, _ = self._arg(p)
         check(load().ibfe_set_state(self._h, pu, pp, float(t), du))
 
     def step(self, n: int = 1):
@@ -336,17 +365,15 @@ class Solver:
         """Move the Lagrangian points to X (M x 3) with prescribed velocities U_B (None = 0);
         the IB operators are rebuilt on the device.  X and U_B are numpy arrays, or
         contiguous float64 CUDA tensors (read on the library's stream after the caller's)."""
-        if isinstance(X, np.ndarray):
-            X = np.ascontiguousarray(X, np.float64).reshape(-1, 3)
-            ub = None if U_B is None else np.ascontiguousarray(U_B, np.float64).reshape(-1, 3)
-            check(load().ibfe_set_points(self._h, C.c_void_p(X.ctypes.data),
-                                         None if ub is None else C.c_void_p(ub.ctypes.data), 0))
-            return
-        assert X.is_cuda and X.is_contiguous() and X.numel() == 3 * self.M
-        assert U_B is None or (U_B.is_cuda and U_B.is_contiguous() and U_B.numel() == 3 * self.M)
-        self._after_caller()
-        check(load().ibfe_set_points(self._h, C.c_void_p(X.data_ptr()),
-                                     None if U_B is None else C.c_void_p(U_B.data_ptr()), 1))
+        X, px, dx = self._vec(X, 3 * self.M, "X")
+        pb, db = None, dx
+        if U_B is not None:
+            U_B, pb, db = self._vec(U_B, 3 * self.M, "U_B")
+        if db != dx:
+            raise ValueError("X and U_B must both be host or both be device memory")
+        if dx:
+            self._after_caller()
+        check(load().ibfe_set_points(self._h, px, pb, dx))
 
     def run_steady(self, tol: float, max_steps: int):
         """Step until the step-to-step NRMSE of every velocity component is below tol
@@ -367,10 +394,13 @@ class Solver:
 
     def get_state_device(self, u, p):
         """Write the state into device tensors (3*n_u and n_p doubles) without a host copy."""
+        u, pu, du = self._vec(u, 3 * self.n_u, "u")
+        p, pp, dp_ = self._vec(p, self.n_p, "p")
+        if not (du and dp_):
+            raise ValueError("get_state_device writes CUDA tensors; use get_state for host arrays")
         t = C.c_double()
         self._after_caller()
-        check(load().ibfe_get_state(self._h, C.c_void_p(u.data_ptr()), C.c_void_p(p.data_ptr()),
-                                    C.byref(t), 1))
+        check(load().ibfe_get_state(self._h, pu, pp, C.byref(t), 1))
         self._before_caller()
         return t.value
 
@@ -382,19 +412,41 @@ class Solver:
 
     def wall_shear(self, normals: np.ndarray) -> np.ndarray:
         """(M, 3) wall shear stress at the Lagrangian points for the current velocity."""
-        n = np.ascontiguousarray(normals, np.float64).reshape(-1, 3)
+        n, _, _ = self._vec(np.asarray(normals), 3 * self.M, "normals")
+        n = n.reshape(-1, 3)
         out = np.empty_like(n)
         check(load().ibfe_wall_shear(self._h, C.c_void_p(n.ctypes.data), C.c_void_p(out.ctypes.data), 0))
         return out
 
     def apply(self, op: int, x: np.ndarray, precision: int = 0) -> np.ndarray:
-        x = np.ascontiguousarray(x, np.float64)
+        in_len = {OP_MASS: self.n_p, OP_STIFF: self.n_p, OP_GRAD: self.n_p, OP_DIV: 3 * self.n_u,
+                  OP_ADVDIFF: 3 * self.n_u, OP_INTERP: 3 * self.n_u, OP_SPREAD: 3 * self.M}[op]
+        x, _, _ = self._vec(np.asarray(x), in_len, "x")
         out_len = {OP_MASS: self.n_p, OP_STIFF: self.n_p, OP_GRAD: 3 * self.n_u, OP_DIV: self.n_p,
                    OP_ADVDIFF: 3 * self.n_u, OP_INTERP: 3 * self.M, OP_SPREAD: 3 * self.n_u}[op]
         y = np.empty(out_len)
         check(load().ibfe_apply(self._h, int(op), int(precision), C.c_void_p(x.ctypes.data),
                                 C.c_void_p(y.ctypes.data), 0))
         return y
+
+    def checkpoint(self) -> bytes:
+        """The time-stepping state (u, p, t, step count and the solvers' warm starts)
+        as bytes; load_checkpoint on a solver built from the same inputs continues
+        bit for bit."""
+        n = C.c_size_t()
+        check(load().ibfe_checkpoint_size(self._h, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        check(load().ibfe_checkpoint_save(self._h, buf, n))
+        return buf.raw
+
+    def load_checkpoint(self, data: bytes):
+        buf = C.create_string_buffer(bytes(data), len(data))
+        check(load().ibfe_checkpoint_load(self._h, buf, C.c_size_t(len(data))))
+
+    def inject_breakdown(self, iteration: int):
+        """Testing aid: the next tentative-velocity BiCGStab solve reports a breakdown at
+        this iteration (0 cancels)."""
+        check(load().ibfe_inject_breakdown(self._h, int(iteration)))
 
     def stats(self) -> dict:
         s = Stats()

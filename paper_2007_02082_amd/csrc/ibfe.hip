@@ -631,7 +631,8 @@ int finish_status(const KScal& s, const char* what) {
 struct SolveOut {
   int iters = 0;
   double res = 0.0;
-  int outer = 1;  // refinement sweeps (mixed precision)
+  int outer = 1;     // refinement sweeps (mixed precision)
+  int restarts = 0;  // BiCGStab restarts after a breakdown
 };
 
 int next_batch(int est, int done_so_far) {
@@ -851,9 +852,10 @@ int run_bicgstab(ibfe_ctx& c, const Op& op, const T* b, T* x, T* const* wv, int 
   int prc;
   // a breakdown (rhat.v = 0 or t.t = 0 before convergence) restarts the method from
   // the current iterate with a fresh shadow residual, at most three times
-  int total = 0;
+  int total = 0, restarts = 0;
   KScal st{};
   for (int restart = 0;; ++restart) {
+    restarts = restart;
     if ((prc = pre_apply(c, op, x, (const KScal*)nullptr))) return prc;
     hipLaunchKernelGGL((k_bi_init<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, nl, op, b, x, r, rhat, p,
                        v, c.partials);
@@ -898,6 +900,7 @@ int run_bicgstab(ibfe_ctx& c, const Op& op, const T* b, T* x, T* const* wv, int 
   st.iters = total;
   c.est[slot] = std::max(1, total);
   out.iters = total;
+  out.restarts = restarts;
   out.res = st.bb > 0.0 ? std::sqrt(st.rr / st.bb) : 0.0;
   return finish_status(st, "BiCGStab");
 }
@@ -959,6 +962,7 @@ int run_refined(ibfe_ctx& c, const Op64& op64, uint32_t rowbit, int nc, const do
     SolveOut so;
     rc = inner((const float*)r32, d32, tol_in, so);
     total += so.iters;
+    out.restarts += so.restarts;
     if (rc && rc != IBFE_ENOCONV) return rc;
     hipLaunchKernelGGL(k_add_correction<float>, dim3(nb), dim3(kBlock), 0, c.stream, c.nl,
                        c.flags, rowbit, (const float*)d32, x, nc, c.stride);
@@ -1713,6 +1717,7 @@ int s1_explicit(ibfe_ctx& c) {
   c.stats.s1_iters = so.iters;
   c.stats.s1_res = so.res;
   c.stats.s1_outer = so.outer;
+  c.stats.s1_restarts = so.restarts;
   return IBFE_OK;
 }
 
@@ -1798,6 +1803,7 @@ int step_once(ibfe_ctx& c) {
     c.stats.s1_iters = so.iters;
     c.stats.s1_res = so.res;
     c.stats.s1_outer = so.outer;
+    c.stats.s1_restarts = so.restarts;
   }
   hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, x1, 1.0, c.g,
                      c.ustar, 3, S);
@@ -2029,6 +2035,7 @@ int s1_explicit_refined(ibfe_ctx& c) {
   c.stats.s1_iters = so.iters;
   c.stats.s1_res = so.res;
   c.stats.s1_outer = so.outer;
+  c.stats.s1_restarts = so.restarts;
   return IBFE_OK;
 }
 
@@ -2109,6 +2116,7 @@ int step_once_refined(ibfe_ctx& c) {
     c.stats.s1_iters = so.iters;
     c.stats.s1_res = so.res;
     c.stats.s1_outer = so.outer;
+    c.stats.s1_restarts = so.restarts;
   }
   hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, x1, 1.0, c.g,
                      c.ustar, 3, S);
@@ -2666,6 +2674,104 @@ int ibfe_get_state(ibfe_ctx* c, double* u, double* p, double* t, int on_device) 
   if (u && (rc = copy_out(*c, c->u, 3, u, on_device))) return rc;
   if (p && (rc = copy_out(*c, c->p, 1, p, on_device))) return rc;
   if (t) *t = c->t;
+  return IBFE_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Checkpoint layout (host memory): header, then u (3 x n_p), p, Phi, delta (3 x n_p)
+// and Lambda (3 x M) as FP64 in canonical order.
+struct CkptHeader {
+  char magic[8];
+  int64_t n_p, M;
+  double t;
+  int64_t steps;
+  int32_t warm;  // bit 0: Lambda, bit 1: Phi, bit 2: delta hold the last step's values
+  int32_t reserved;
+};
+static_assert(sizeof(CkptHeader) == 48, "checkpoint header layout");
+constexpr char kCkptMagic[8] = {'I', 'B', 'F', 'E', 'C', 'K', 'P', '1'};
+
+size_t ckpt_bytes(const ibfe_ctx& c) {
+  return sizeof(CkptHeader) + sizeof(double) * (size_t(8) * size_t(c.nP) + size_t(3) * size_t(c.plan.M));
+}
+
+}  // namespace
+
+extern "C" {
+
+int ibfe_checkpoint_size(const ibfe_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return fail(IBFE_EINVAL, "NULL argument");
+  *bytes = ckpt_bytes(*c);
+  return IBFE_OK;
+}
+
+int ibfe_checkpoint_save(ibfe_ctx* c, void* buf, size_t bytes) {
+  if (!c || !buf) return fail(IBFE_EINVAL, "NULL argument");
+  if (bytes < ckpt_bytes(*c)) return fail(IBFE_EINVAL, "checkpoint buffer too small");
+  CkptHeader h{};
+  std::memcpy(h.magic, kCkptMagic, 8);
+  h.n_p = c->nP;
+  h.M = c->plan.M;
+  h.t = c->t;
+  h.steps = c->steps;
+  h.warm = (c->lam_warm ? 1 : 0) | (c->phi_warm ? 2 : 0) | (c->delta_warm ? 4 : 0);
+  std::memcpy(buf, &h, sizeof(h));
+  double* d = reinterpret_cast<double*>(static_cast<char*>(buf) + sizeof(h));
+  const int64_t n = c->nP;
+  int rc;
+  if ((rc = copy_out(*c, c->u, 3, d, 0))) return rc;
+  if ((rc = copy_out(*c, c->p, 1, d + 3 * n, 0))) return rc;
+  if ((rc = copy_out(*c, c->phi, 1, d + 4 * n, 0))) return rc;
+  if ((rc = copy_out(*c, c->delta, 3, d + 5 * n, 0))) return rc;
+  double* lam = d + 8 * n;
+  for (int k = 0; k < 3 && c->plan.M > 0; ++k)
+    HIP_TRY(hipMemcpyAsync(lam + k * c->plan.M, c->ibv[1] + k * c->mstride, sizeof(double) * c->plan.M,
+                           hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return IBFE_OK;
+}
+
+int ibfe_checkpoint_load(ibfe_ctx* c, const void* buf, size_t bytes) {
+  if (!c || !buf) return fail(IBFE_EINVAL, "NULL argument");
+  if (bytes < sizeof(CkptHeader)) return fail(IBFE_EINVAL, "checkpoint buffer too small");
+  CkptHeader h;
+  std::memcpy(&h, buf, sizeof(h));
+  if (std::memcmp(h.magic, kCkptMagic, 8) != 0) return fail(IBFE_EINVAL, "not a checkpoint");
+  if (h.n_p != c->nP || h.M != c->plan.M)
+    return fail(IBFE_EINVAL, "checkpoint sizes do not match the context");
+  if (bytes < ckpt_bytes(*c)) return fail(IBFE_EINVAL, "checkpoint buffer too small");
+  if (!std::isfinite(h.t) || h.steps < 0) return fail(IBFE_EINVAL, "bad checkpoint header");
+  const double* d = reinterpret_cast<const double*>(static_cast<const char*>(buf) + sizeof(h));
+  const int64_t n = c->nP;
+  int rc;
+  if ((rc = copy_in(*c, c->u, 3, d, 0))) return rc;
+  if ((rc = copy_in(*c, c->p, 1, d + 3 * n, 0))) return rc;
+  if ((rc = copy_in(*c, c->phi, 1, d + 4 * n, 0))) return rc;
+  if ((rc = copy_in(*c, c->delta, 3, d + 5 * n, 0))) return rc;
+  const double* lam = d + 8 * n;
+  for (int k = 0; k < 3 && c->plan.M > 0; ++k)
+    HIP_TRY(hipMemcpyAsync(c->ibv[1] + k * c->mstride, lam + k * c->plan.M, sizeof(double) * c->plan.M,
+                           hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->t = h.t;
+  c->steps = h.steps;
+  c->lam_warm = (h.warm & 1) != 0;
+  c->phi_warm = (h.warm & 2) != 0;
+  c->delta_warm = (h.warm & 4) != 0;
+  c->stats = ibfe_stats{};
+  c->stats.steps = c->steps;
+  c->stats.t = c->t;
+  return IBFE_OK;
+}
+
+int ibfe_inject_breakdown(ibfe_ctx* c, int iteration) {
+  if (!c || iteration < 0) return fail(IBFE_EINVAL, "bad argument");
+  const int32_t v = iteration;
+  HIP_TRY(hipMemcpyAsync(&c->scal[kScS1].brk_at, &v, sizeof(v), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
   return IBFE_OK;
 }
 

@@ -366,6 +366,9 @@ struct KScal {
   double rz, rr, bb, alpha, beta, tol2;        // CG
   double rho, rho_old, omega, ts, tt, rv;      // BiCGStab (alpha shared)
   int32_t done, iters, max_iters, status;      // status: 0 ok, 1 breakdown, 2 non-finite
+  // testing aid (BiCGStab only): report a breakdown once the iteration count reaches
+  // brk_at (> 0), then clear it; set from the host, never by the init kernels
+  int32_t brk_at, pad_;
 };
 
 __device__ __forceinline__ bool bad(double v) { return !(v == v) || v - v != 0.0; }
@@ -758,6 +761,10 @@ __global__ __launch_bounds__(kBlock) void k_fin_bi_x(const double* __restrict__ 
   } else if (sc->omega == 0.0 || tot[0] == 0.0) {
     sc->status = 1;
     sc->done = 1;
+  } else if (sc->brk_at > 0 && sc->iters >= sc->brk_at) {
+    sc->status = 1;
+    sc->done = 1;
+    sc->brk_at = 0;
   }
 }
 

@@ -1,5 +1,5 @@
 // Wall shear stress at the Lagrangian points (the paper's clinical output,
-// Section 4, evaluated at the immersed wall points): the nodal velocity
+// defined in Section 2.6, evaluated at the immersed wall points): the nodal velocity
 // gradient by the lumped L2 projection of the Q1 gradient, its symmetric part
 // interpolated to each point with the kernel of Eq. 18, and the tangential part
 // of the traction 2 mu eps n.

@@ -75,7 +75,7 @@ def test_aorta_oracle_step_invariants(quarter):
         assert np.abs(I @ info.u_ib[d]).max() <= 1e-12
     # prescribed inlet values at t1: Re sum_k C_k W_k e^{i k w t}
     sh = c.inlet_shape[:, :, 2]
-    w = c.inlet_omega * t1
-    val = sh[0] + sh[1] * math.cos(w) - sh[2] * math.sin(w) + sh[3] * math.cos(2 * w) - sh[4] * math.sin(2 * w)
+    W = [sh[0].astype(complex)] + [sh[2 * k - 1] + 1j * sh[2 * k] for k in range(1, c.inlet_K + 1)]
+    val = sum(W[k] * np.exp(1j * k * c.inlet_omega * t1) for k in range(len(W))).real
     assert np.allclose(u1[2][c.inlet_ids], val, rtol=0, atol=1e-14)
     assert np.isfinite(u1).all() and np.isfinite(p1).all()

@@ -7,7 +7,7 @@ import pytest
 
 import paper_2007_02082_amd as ibfe
 import synth
-from gpu_util import make_solver, rel_l2, run_pair, say
+from gpu_util import check_steps, make_solver, rel_l2, run_pair, say
 from oracle import fem, grid, ipcs, refine
 
 pytestmark = pytest.mark.gpu
@@ -126,14 +126,7 @@ def test_refined_advection_diffusion_apply_strain(precision, tol):
 
 
 def _check(out, tol, label):
-    for k, r in enumerate(out):
-        errs = {f: rel_l2(r["g_" + f], r["o_" + f]) for f in ("ustar", "uib", "u", "p")}
-        floor = max(np.linalg.norm(r["o_phi"]), np.linalg.norm(r["o_p"]))
-        errs["phi"] = float(np.linalg.norm(r["g_phi"] - r["o_phi"]) / floor)
-        say(f"{label} step {k}: " + " ".join(f"{f}={e:.2e}" for f, e in errs.items()),
-            "gpu iters", {x: r["stats"][x] for x in ("s1_iters", "ib_iters", "s3_iters", "s4_iters")})
-        for f, e in errs.items():
-            assert e <= tol, (label, k, f, e)
+    check_steps(out, tol, label)
 
 
 @pytest.mark.parametrize("make", [_cyl, _aneurysm])

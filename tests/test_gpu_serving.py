@@ -55,7 +55,7 @@ def test_alone_and_in_mix_are_bitwise_identical():
     target = synth.vessel_case("aneurysm", 1.0, (16, 16, 24), nsteps=6, seed=7)
     others = [synth.vessel_case("branch", 0.7, (16, 16, 16), seed=1),
               synth.vessel_case("cylinder", 1.3, (24, 24, 24)),
-              synth.pulsatile_c2() if False else synth.small_cylinder(12, 24),
+              synth.small_cylinder(12, 24),
               synth.vessel_case("aneurysm", 0.5, (32, 32, 32), seed=3),
               synth.vessel_case("branch", 2.0, (24, 24, 32), seed=9)]
     say("alone")
