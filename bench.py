@@ -1,27 +1,21 @@
 """Benchmark: IPCS + BCE-IB time steps per second on one MI355X.
 
-Default workload: pulsatile flow in a cylinder of radius 0.5 and length 8 on a
-64x64x512 Q1 grid (2.17 M nodes, 1.78 M pressure/velocity nodes after domain
-reduction), 25,600 Lagrangian wall points, inlet u_max(t) = 1 + 0.5 sin(2 pi t),
-dt = 0.005, synthetic inputs.  One step = tentative velocity solve, IB force solve
-and spreading, pressure increment solve, velocity/pressure correction, all on the
-GPU.  `--workload aneurysm` runs the synthetic aneurysm instead: a tube of radius 1
-along a sinusoidal centreline (amplitude 1, period 10, length 20) with a spherical
-bulge of radius 2.5, on a 128x128x320 base grid whose cells within 0.5 of the wall
-are split 2:1 (a 257x257x641 lattice, 2.8 M unknown nodes), parabolic inlet.
-`--workload aorta` runs the aorta-like arch (radius 1.2 along a cubic Bezier, three
-branches of radius 0.4-0.6) on a uniform 256x160x384 grid (15.9 M nodes, 5 % of
-them active), inlet and outlet disks on the same face, two-harmonic Womersley-type
-inlet, dt = 0.002.
+Default workload: the synthetic aneurysm, the largest single-GPU configuration: a tube of
+radius 1 along a sinusoidal centreline (amplitude 1, period 10, length 20) with a spherical
+bulge of radius 2.5, on a 128x128x320 base grid whose cells within 0.5 of the wall are
+split 2:1 (a 257x257x641 lattice of 42.3 M positions, 2.8 M unknown nodes), 46,602
+Lagrangian wall points, parabolic inlet, mixed precision (FP32 inner solves in FP64
+refinement), multigrid pressure solve.  One step = tentative velocity solve, IB force
+solve and spreading, pressure increment solve, velocity/pressure correction, all on the
+GPU.  `--workload pulsatile` runs the pulsatile cylinder (64x64x512, 1.78 M nodes) and
+`--workload aorta` the aorta-like arch (256x160x384, 5 % active) instead.
 
-Prints one JSON line.  The two matrix-free applies that carry the step are timed
-with HIP events on the library's stream over the timed region: the masked Q1
-stiffness apply inside the pressure CG, (2 s + b) algorithmic bytes per pressure
-node (read p, write q), and the masked Q1 mass Chebyshev step of the velocity
-correction, (15 s + b) per free node (three components, read x, b, d, write d,
-x); s = 4 in mixed mode, 8 in FP64 mode, b = 1/8 (one bit of domain data) or 1/4
-on the refined lattice (fine and coarse element bits).  `roofline` reports the
-one with the larger summed time; the other one is listed under `roofline.other`.
+Prints one JSON line.  During the timed steps every kernel dispatch records its own
+start and end HIP events on the library's stream; the durations are summed per kernel,
+and `roofline` reports the kernel with the largest summed time against the HBM peak,
+with its algorithmic bytes per dispatch (`kernel_model`).  By default the line also
+carries the relative error of the mixed-precision state against an FP64 run of the same
+steps, the rates of the other two workloads and the serving stream (64 requests).
 """
 from __future__ import annotations
 
@@ -283,14 +277,155 @@ def moving_points(s, case, nsteps: int = 20) -> dict:
             "amplitude": 0.02, "period": 1.0}
 
 
+WORKLOADS = {"pulsatile": "pulsatile_c2", "aneurysm": "aneurysm_case", "aorta": "aorta_case"}
+
+
+def make_case(workload: str):
+    import synth
+    return getattr(synth, WORKLOADS[workload])()
+
+
+def sizes_of(case, prec: int) -> dict:
+    """Node counts the byte models need: pressure nodes P, free velocity nodes F and the
+    active lattice nodes (P plus hanging nodes), from the host-only plan."""
+    import paper_2007_02082_amd as ibfe
+    pl = ibfe.Plan(**ibfe.inputs_from_case(case, precision=prec, precond=0))
+    sz = pl.sizes()
+    flags = pl.node_flags()
+    n_act = int(((flags & (ibfe.FLAG_P | ibfe.FLAG_HANG)) != 0).sum())
+    pl.close()
+    return {"n_p": sz["n_p"], "n_free": sz["n_free"], "n_act": n_act, "M": case.M,
+            "refined": getattr(case, "refine_cell", None) is not None}
+
+
+def kernel_model(name: str, z: dict):
+    """Algorithmic HBM bytes of one dispatch of a kernel (minimum bytes: each operand
+    read or written once, b = 1/8 B of domain data per node, 1/4 on a refined lattice),
+    with a short description; None for kernels without a model.  s = 4 for float
+    instantiations, 8 for double."""
+    s = 4 if "<float" in name else 8
+    b = 0.25 if z["refined"] else 0.125
+    n_p, n_f = z["n_p"], z["n_free"]
+    if name.startswith("k_zb_cheb<") and name.endswith(", false, 3>"):
+        return (15 * s + b) * n_f, "Q1 mass Chebyshev step, 3 components: read x, b, d; write d, x per free node"
+    if name.startswith("k_cg_q_zb<") and name.endswith(", 1>"):
+        return (2 * s + b) * n_p, "Q1 stiffness apply + p.q: read p, write q per pressure node"
+    if name.startswith("k_bi_apply<") and "OpCStencil<" in name:
+        return (63 * s) * n_f, ("stored composite advection-diffusion stencil, 3 components: 54 coefficient "
+                                "planes, read x and w, write y per free node")
+    if name.startswith("k_bi_apply<") and "OpStencil<" in name:
+        return (36 * s) * n_f, ("stored advection-diffusion stencil, 3 components: 27 coefficient planes, "
+                                "read x and w, write y per free node")
+    if name.startswith("k_residual<") and "OpCStencil<double, 3>" in name:
+        return (54 * 8 + 6 * 8 + 3 * 4) * n_f, ("FP64 residual of the composite stored stencil: 54 planes, "
+                                                 "read x, b, write r (FP32) per free node")
+    if name.startswith("k_residual<") and "OpStencil<double, 3>" in name:
+        return (27 * 8 + 6 * 8 + 3 * 4) * n_f, ("FP64 residual of the stored stencil: 27 planes, read x, b, "
+                                                 "write r (FP32) per free node")
+    if name == "k_s1_build":
+        planes = 54 if z["refined"] else 27
+        return (3 * 8 + planes * 12) * n_p, ("advection-diffusion stencil assembly: read u^n, write the "
+                                              "FP64 and FP32 coefficient planes per node")
+    return None
+
+
+def run_workload(workload: str, prec: int, pc: int, visc: int, steps: int, warmup: int, case=None,
+                 keep_state: bool = False, profile_steps: int = 3) -> dict:
+    """W untimed steps from rest; then `profile_steps` steps in which every kernel
+    dispatch records its own start and end HIP events (the whole-step breakdown, which
+    names the dominant kernel: the largest summed duration); then the K timed steps,
+    bracketed by torch.cuda.synchronize() and the host clock, in which only the dominant
+    kernel's dispatches carry events (events on every dispatch cost about 5 us each and
+    would slow the timed steps; one kernel's do not measurably)."""
+    import numpy as np
+    import torch
+
+    import paper_2007_02082_amd as ibfe
+
+    case = case if case is not None else make_case(workload)
+    z = sizes_of(case, prec)
+    print(f"[bench] {case.name}: {z['n_p']} nodes of P, {z['n_free']} free, M = {case.M}", file=sys.stderr,
+          flush=True)
+    s = ibfe.Solver(**ibfe.inputs_from_case(case, precision=prec, precond=pc, viscous=visc))
+    n = s.n_u
+    s.set_state(np.zeros(3 * n), np.zeros(n), 0.0)
+    s.step(warmup)
+    # profile pass: every kernel timed
+    s.set_kernel_timing(True)
+    s.step(profile_steps)
+    table = s.kernel_times()
+    s.set_kernel_timing(False)
+    dominant = table[0][0]
+    # timed steps: the dominant kernel's dispatches timed
+    s.set_kernel_timing_filter(dominant)
+    s.set_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = s.stats()
+    timed = {name: (ms, cnt) for name, ms, cnt in s.kernel_times()}
+    s.set_kernel_timing(False)
+    s.set_kernel_timing_filter(None)
+    total_ms = sum(ms for _, ms, _ in table)
+    rows = []
+    for name, ms, cnt in table:
+        m = kernel_model(name, z)
+        avg_us = 1e3 * ms / max(1, cnt)
+        row = {"kernel": name, "total_ms": round(ms, 3), "share": round(ms / total_ms, 4) if total_ms else 0.0,
+               "launches": cnt, "avg_us": round(avg_us, 3)}
+        if m is not None:
+            ach = m[0] / (avg_us * 1e-6) / 1e9
+            row.update({"alg_bytes_per_launch": int(m[0]), "achieved": round(ach, 1),
+                        "frac": round(ach / HBM_PEAK_GBS, 4), "what": m[1]})
+        rows.append(row)
+    dom = dict(rows[0])
+    ms, cnt = timed.get(dominant, (0.0, 0))
+    dom.update({"timed_launches": cnt, "timed_total_ms": round(ms, 3),
+                "avg_us": round(1e3 * ms / max(1, cnt), 3)})
+    m = kernel_model(dominant, z)
+    if m is not None and cnt > 0:
+        ach = m[0] / (1e-3 * ms / cnt) / 1e9
+        dom.update({"achieved": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4)})
+    out = {"case": case, "sizes": z, "steps_per_s": steps / elapsed, "ms_per_step": 1e3 * elapsed / steps,
+           "elapsed_s": elapsed, "stats": st, "kernels": rows, "dominant": dom,
+           "profile_steps": profile_steps, "kernel_ms_per_step": total_ms / profile_steps}
+    if keep_state:
+        out["state"] = s.get_state()
+        out["solver"] = s
+    else:
+        s.close()
+    return out
+
+
+def roofline_of(res: dict, workload: str, precision: str, pc: int) -> dict:
+    """The dominant kernel of the timed steps (largest summed duration over all kernels)
+    against the HBM peak."""
+    d = res["dominant"]
+    key = None
+    if d["kernel"].startswith("k_zb_cheb<") and d["kernel"].endswith(", false, 3>"):
+        key = "mass"
+    elif d["kernel"].startswith("k_cg_q_zb<"):
+        key = "pressure"
+    traffic = counted_traffic(workload, precision, key) if (key and pc == 2) else None
+    roof = {"bound": "hbm", "achieved": d.get("achieved"), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": d.get("frac"), "traffic": round(traffic) if traffic else None,
+            "kernel": d["kernel"], "share_of_kernel_time": d["share"], "avg_us": d["avg_us"],
+            "launches": d["timed_launches"], "alg_bytes_per_launch": d.get("alg_bytes_per_launch"),
+            "what": d.get("what")}
+    return roof
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["pulsatile", "aneurysm", "aorta"], default="pulsatile",
-                    help="pulsatile cylinder on 64x64x512 (default), the refined aneurysm or the "
-                         "aorta-like arch on 256x160x384")
+    ap.add_argument("--workload", choices=["pulsatile", "aneurysm", "aorta"], default="aneurysm",
+                    help="the refined aneurysm (default: the largest configuration, 2.8 M unknown nodes on "
+                         "a 257x257x641 lattice), the pulsatile cylinder on 64x64x512 or the aorta-like arch "
+                         "on 256x160x384")
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--precond", choices=["mg", "jacobi"], default="mg",
                     help="pressure preconditioner: geometric multigrid or Jacobi")
@@ -299,15 +434,16 @@ def main() -> int:
     ap.add_argument("--wss", action="store_true",
                     help="also time the wall shear stress at the Lagrangian points (after the timed steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--check", action="store_true",
-                    help="also run the same steps in FP64 mode and report the difference")
-    ap.add_argument("--serve", action="store_true",
-                    help="also run the serving stream (64 requests, Poisson arrivals at 4/s)")
+    ap.add_argument("--no-check", action="store_true",
+                    help="skip the FP64 run of the same steps (the mixed-vs-FP64 error of the line)")
+    ap.add_argument("--no-others", action="store_true",
+                    help="skip the steps/s of the other two workloads")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
     ap.add_argument("--e1", action="store_true",
                     help="also run the pressure-driven Poiseuille study of Section 3.1 to steady "
                          "state on the three grids of Table 1 (after the timed steps)")
     ap.add_argument("--moving", action="store_true",
-                    help="also step the benchmark cylinder with its wall points moving radially "
+                    help="also step the pulsatile cylinder with its wall points moving radially "
                          "(a device rebuild of the IB operators before every step)")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-slots", type=int, default=4)
@@ -323,73 +459,23 @@ def main() -> int:
     import numpy as np
     import torch
 
-    import paper_2007_02082_amd as ibfe
-    import synth
-
     torch.cuda.set_device(0)
-    refined = args.workload == "aneurysm"
-    case = {"pulsatile": synth.pulsatile_c2, "aneurysm": synth.aneurysm_case,
-            "aorta": synth.aorta_case}[args.workload]()
     prec = 1 if args.precision == "mixed" else 0
     pc = 2 if args.precond == "mg" else 0
     visc = 1 if args.viscous == "strain" else 0
-    s = ibfe.Solver(**ibfe.inputs_from_case(case, precision=prec, precond=pc, viscous=visc))
-    n = s.n_u
-    u0 = np.zeros(3 * n)
-    p0 = np.zeros(n)
-    s.set_state(u0, p0, 0.0)
-    s.step(args.warmup)
-    torch.cuda.synchronize()
-    s.set_kernel_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.step(args.steps)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    st = s.stats()
-    s.set_kernel_timing(False)
-    ms_per_step = 1e3 * elapsed / args.steps
-
-    bytes_per_value = 4 if prec == 1 else 8
-    n_p = s.n_p
-    n_free = ibfe.Plan(**ibfe.inputs_from_case(case, precision=prec, precond=0)).sizes()["n_free"]
-    bits = 0.25 if refined else 0.125
-    tname = "float" if prec == 1 else "double"
-    # the two matrix-free applies that carry most of the step, timed with HIP events
-    kernels = {
-        "pressure": {
-            "kernel": (f"k_cg_q_zb<{tname},1> (composite Q1 stiffness apply + p.q: fine-cell walk "
-                       "+ precomputed coarse/hanging terms)" if refined
-                       else f"k_cg_q_zb<{tname},1> (masked Q1 stiffness apply + p.q)"),
-            "ms": st["poisson_apply_ms"], "launches": st["poisson_applies"],
-            # read p, write q per pressure node
-            "alg_bytes_per_launch": (2 * bytes_per_value + bits) * n_p},
-        "mass": {
-            "kernel": (f"k_zb_cheb<{tname}, false, 3> (composite Q1 mass Chebyshev step: fine-cell walk "
-                       "+ precomputed coarse/hanging terms)"
-                       if refined else f"k_zb_cheb<{tname}, false, 3> (masked Q1 mass Chebyshev step)"),
-            "ms": st["mass_apply_ms"], "launches": st["mass_applies"],
-            # per free node and component: read x, b, d; write d, x
-            "alg_bytes_per_launch": (15 * bytes_per_value + bits) * n_free},
-    }
-    dominant = max(kernels, key=lambda k: kernels[k]["ms"])
-    rows = {}
-    for name, k in kernels.items():
-        avg_ms = k["ms"] / max(1, k["launches"])
-        ach = k["alg_bytes_per_launch"] / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-        rows[name] = {"kernel": k["kernel"], "achieved": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4),
-                      "avg_us": round(avg_ms * 1e3, 3), "launches": k["launches"],
-                      "total_ms": round(k["ms"], 3), "alg_bytes_per_launch": int(k["alg_bytes_per_launch"])}
-    d = rows[dominant]
-    traffic = counted_traffic(args.workload, args.precision, dominant) if pc == 2 else None
-    roof = {"bound": "hbm", "achieved": d["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": d["frac"], "traffic": round(traffic) if traffic else None,
-            "kernel": d["kernel"], "avg_us": d["avg_us"], "launches": d["launches"],
-            "alg_bytes_per_launch": d["alg_bytes_per_launch"],
-            "other": {k: v for k, v in rows.items() if k != dominant}}
+    refined = args.workload == "aneurysm"
+    case = make_case(args.workload)
+    res = run_workload(args.workload, prec, pc, visc, args.steps, args.warmup, case=case, keep_state=True)
+    s = res.pop("solver")
+    st = res["stats"]
+    print(f"[bench] {case.name}: {res['steps_per_s']:.2f} steps/s", file=sys.stderr, flush=True)
+    roof = roofline_of(res, args.workload, args.precision, pc)
 
     extra = {"iters_last_step": {k: st[k] for k in ("s1_iters", "ib_iters", "s3_iters", "s4_iters",
-                                                      "s1_outer", "s3_outer", "s4_outer")}}
+                                                      "s1_outer", "s3_outer", "s4_outer", "s1_restarts")},
+             "profile_pass": {"steps": res["profile_steps"],
+                              "kernel_ms_per_step": round(res["kernel_ms_per_step"], 3),
+                              "kernels_top": res["kernels"][:8]}}
     if args.wss and not refined:
         # unit normals from the vessel axis of the point's tube (timing only: any unit vectors do)
         nrm = case.X - case.X.mean(axis=0)
@@ -402,21 +488,32 @@ def main() -> int:
             tau = s.wall_shear(nrm)
         extra["wall_shear_ms"] = round(1e3 * (time.perf_counter() - t0w) / 5, 3)
         extra["wall_shear_max"] = float(np.abs(tau).max())
-    if args.check:
-        u_a, p_a, _ = s.get_state()
-        ref = ibfe.Solver(**ibfe.inputs_from_case(case, precision=0, precond=pc, viscous=visc))
-        ref.set_state(u0, p0, 0.0)
-        ref.step(args.warmup + args.steps)
-        u_b, p_b, _ = ref.get_state()
-        extra["rel_l2_vs_fp64"] = {"u": float(np.linalg.norm(u_a - u_b) / np.linalg.norm(u_b)),
-                                   "p": float(np.linalg.norm(p_a - p_b) / np.linalg.norm(p_b))}
-        ref.close()
     if args.moving:
         if args.workload != "pulsatile":
             print("--moving runs on the pulsatile cylinder only", file=sys.stderr)
             return 2
         extra["moving_points"] = moving_points(s, case)
+    u_a, p_a, _ = res["state"]
     s.close()
+    del res["state"]
+    if prec == 1 and not args.no_check:
+        # the same warm-up and timed steps in FP64: the accuracy the mixed-precision rate is quoted at
+        import paper_2007_02082_amd as ibfe
+        ref = ibfe.Solver(**ibfe.inputs_from_case(case, precision=0, precond=pc, viscous=visc))
+        ref.set_state(np.zeros(3 * ref.n_u), np.zeros(ref.n_p), 0.0)
+        t0r = time.perf_counter()
+        ref.step(args.warmup + res["profile_steps"] + args.steps)
+        u_b, p_b, _ = ref.get_state()
+        fp64_rate = (args.warmup + res["profile_steps"] + args.steps) / (time.perf_counter() - t0r)
+        ref.close()
+        extra["rel_vs_fp64"] = {
+            "steps": args.warmup + res["profile_steps"] + args.steps,
+            "u_rel_l2": float(np.linalg.norm(u_a - u_b) / np.linalg.norm(u_b)),
+            "p_rel_l2": float(np.linalg.norm(p_a - p_b) / np.linalg.norm(p_b)),
+            "u_rel_max": float(np.abs(u_a - u_b).max() / np.abs(u_b).max()),
+            "p_rel_max": float(np.abs(p_a - p_b).max() / np.abs(p_b).max()),
+            "fp64_steps_per_s": round(fp64_rate, 2)}
+        print(f"[bench] mixed vs FP64: {extra['rel_vs_fp64']}", file=sys.stderr, flush=True)
     if args.copy_calibration_mib > 0:
         nbytes = args.copy_calibration_mib << 20
         a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -427,23 +524,40 @@ def main() -> int:
         del a, b
 
     out = {
-        "metric": METRIC, "value": round(args.steps / elapsed, 3), "unit": "steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "metric": METRIC, "value": round(res["steps_per_s"], 3), "unit": "steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(res["ms_per_step"], 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32-inner/f64-outer" if prec == 1 else "f64", "data": "synthetic",
         "config": {"workload": case.name, "grid": [case.nx, case.ny, case.nz], "n_nodes": case.N,
                    "refined_cells": int(case.refine_cell.sum()) if refined else 0,
-                   "n_active": n_p, "lagrangian_points": case.M, "dt": case.dt,
+                   "n_active": res["sizes"]["n_p"], "lagrangian_points": case.M, "dt": case.dt,
                    "precision": args.precision, "pressure_preconditioner": args.precond,
                    "viscous_form": args.viscous},
         "roofline": roof,
     }
     out.update(extra)
-    if args.serve:
+    if not args.no_others:
+        others = {}
+        for w in ("pulsatile", "aneurysm", "aorta"):
+            if w == args.workload:
+                continue
+            r = run_workload(w, prec, pc, visc, args.steps, args.warmup)
+            rf = roofline_of(r, w, args.precision, pc)
+            others[r["case"].name] = {
+                "steps_per_s": round(r["steps_per_s"], 3), "ms_per_step": round(r["ms_per_step"], 3),
+                "n_active": r["sizes"]["n_p"], "lagrangian_points": r["case"].M,
+                "dominant_kernel": rf["kernel"], "dominant_share": rf["share_of_kernel_time"],
+                "dominant_avg_us": rf["avg_us"], "dominant_frac": rf["frac"],
+                "profile_kernels_top": r["kernels"][:4]}
+            print(f"[bench] {r['case'].name}: {r['steps_per_s']:.2f} steps/s", file=sys.stderr, flush=True)
+        out["other_workloads"] = others
+    if not args.no_serve:
         out["serving"] = serve_stream(args.serve_requests, args.serve_slots, 50)
+        print(f"[bench] serving: {out['serving']['solves_per_s']} solves/s", file=sys.stderr, flush=True)
     if args.e1:
         out["poiseuille_e1"] = poiseuille_study()
     if not args.no_cpu_baseline:
+        n_p = res["sizes"]["n_p"]
         out["cpu_baseline"] = {"pulsatile": cpu_baseline, "aneurysm": lambda: cpu_baseline_aneurysm(n_p),
                                "aorta": lambda: cpu_baseline_aorta(n_p)}[args.workload]()
     print(json.dumps(out), flush=True)

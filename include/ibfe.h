@@ -189,7 +189,7 @@ typedef struct ibfe_stats {
   int32_t s1_outer, s3_outer, s4_outer; /* refinement sweeps (mixed mode)       */
   double s1_res, ib_res, s3_res, s4_res; /* final relative residuals            */
   double poisson_apply_ms;   /* summed duration of the pressure stiffness apply  */
-  int64_t poisson_applies;   /* number of those launches (timed if enabled)      */
+  int64_t poisson_applies;   /* and its dispatches (kernel timing on, see below)  */
   double mass_apply_ms;      /* summed duration of the mass Chebyshev steps of   */
   int64_t mass_applies;      /* the velocity correction, and their number        */
   int32_t s1_restarts;       /* BiCGStab restarts after a breakdown (r^.v = 0 or  */
@@ -288,10 +288,31 @@ int ibfe_checkpoint_load(ibfe_ctx* ctx, const void* buf, size_t bytes);
  * effect on the CG paths (advection = 1). */
 int ibfe_inject_breakdown(ibfe_ctx* ctx, int iteration);
 int ibfe_get_stats(const ibfe_ctx* ctx, ibfe_stats* stats);
-/* Enable (1) or disable (0) HIP-event timing of the pressure stiffness apply
- * and of the mass Chebyshev step of the velocity correction (both counters are
- * reset by this call; statistics accumulate until the next call). */
+/* Enable (1) or disable (0) per-dispatch kernel timing: while on, every kernel
+ * dispatch of the context records its own start and end events, and the
+ * durations are summed per kernel name at the end of every step (dispatches of
+ * Krylov iterations past convergence, which return at once, are not counted).
+ * Graph replay is off meanwhile (the kernels are dispatched one by one, with the
+ * same results).  Both calls reset the sums, and the two summary fields of
+ * ibfe_stats: poisson_apply_ms / poisson_applies (the pressure stiffness apply
+ * k_cg_q_zb<*, 1>) and mass_apply_ms / mass_applies (the mass Chebyshev step of
+ * the velocity correction, k_zb_cheb<*, false, 3>). */
 int ibfe_set_kernel_timing(ibfe_ctx* ctx, int enable);
+
+/* Summed durations per kernel since timing was enabled, longest total first:
+ * up to cap entries are written to out (host memory), *n receives the number
+ * of kernels.  name is the kernel's instantiation as the compiler spells it
+ * (for example "k_zb_cheb<float, false, 3>").  Synchronises the stream. */
+typedef struct ibfe_kernel_time {
+  char name[120];
+  double total_ms;
+  int64_t launches;
+} ibfe_kernel_time;
+int ibfe_get_kernel_times(ibfe_ctx* ctx, ibfe_kernel_time* out, int32_t cap, int32_t* n);
+/* Time only the dispatches of the named kernel (a name as ibfe_get_kernel_times
+ * spells it), or every kernel (NULL or "").  Events on every dispatch slow the
+ * step (about 5 us per dispatch); one kernel's events do not measurably. */
+int ibfe_set_kernel_timing_filter(ibfe_ctx* ctx, const char* kernel);
 
 /* Replay the fixed kernel sequences of the solves (iteration batches between
  * convergence checks, Chebyshev sequences) through HIP graphs captured on their

@@ -64,6 +64,10 @@ class Stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class KernelTime(C.Structure):
+    _fields_ = [("name", C.c_char * 120), ("total_ms", C.c_double), ("launches", C.c_int64)]
+
+
 class Request(C.Structure):
     _fields_ = [("grid", C.POINTER(Grid)), ("ib", C.POINTER(IB)), ("params", C.POINTER(Params)),
                 ("inlet", C.POINTER(Inlet)), ("nsteps", C.c_int32), ("t0", C.c_double)]
@@ -105,6 +109,8 @@ SIGNATURES = {
     "ibfe_checkpoint_load": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "ibfe_inject_breakdown": (C.c_int, [C.c_void_p, C.c_int]),
     "ibfe_set_kernel_timing": (C.c_int, [C.c_void_p, C.c_int]),
+    "ibfe_get_kernel_times": (C.c_int, [C.c_void_p, C.POINTER(KernelTime), C.c_int32, C.POINTER(C.c_int32)]),
+    "ibfe_set_kernel_timing_filter": (C.c_int, [C.c_void_p, C.c_char_p]),
     "ibfe_set_graphs": (C.c_int, [C.c_void_p, C.c_int]),
     "ibfe_get_field": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int]),
     "ibfe_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
@@ -455,6 +461,18 @@ class Solver:
 
     def set_kernel_timing(self, on: bool):
         check(load().ibfe_set_kernel_timing(self._h, 1 if on else 0))
+
+    def set_kernel_timing_filter(self, kernel: str | None):
+        """Time only this kernel's dispatches (None: all kernels)."""
+        check(load().ibfe_set_kernel_timing_filter(self._h, None if kernel is None else kernel.encode()))
+
+    def kernel_times(self) -> list:
+        """[(kernel name, total ms, dispatches)] since timing was enabled, longest first."""
+        n = C.c_int32()
+        check(load().ibfe_get_kernel_times(self._h, None, 0, C.byref(n)))
+        buf = (KernelTime * max(1, n.value))()
+        check(load().ibfe_get_kernel_times(self._h, buf, n.value, C.byref(n)))
+        return [(buf[i].name.decode(), buf[i].total_ms, buf[i].launches) for i in range(n.value)]
 
     def close(self):
         if getattr(self, "_h", None):

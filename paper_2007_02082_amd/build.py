@@ -39,18 +39,22 @@ def _run(cmd, verbose):
 
 
 def build(verbose: bool = False) -> str:
+    from concurrent.futures import ThreadPoolExecutor
+
     os.makedirs(BUILD, exist_ok=True)
     inc = ["-I", INCLUDE, "-I", CSRC]
-    objs = []
+    jobs = []
     for src in ("plan.cpp", "mg_plan.cpp", "refine_plan.cpp"):
         obj = os.path.join(BUILD, src.replace(".cpp", ".o"))
-        _run(["g++", *CXX_FLAGS, *inc, "-I", os.path.join(ROCM, "include"), "-c",
-              os.path.join(CSRC, src), "-o", obj], verbose)
-        objs.append(obj)
+        jobs.append((["g++", *CXX_FLAGS, *inc, "-I", os.path.join(ROCM, "include"), "-c",
+                      os.path.join(CSRC, src), "-o", obj], obj))
     for src in ("ibfe.hip", "server.hip"):
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-        _run([HIPCC, *HIP_FLAGS, *inc, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
-        objs.append(obj)
+        jobs.append(([HIPCC, *HIP_FLAGS, *inc, "-c", os.path.join(CSRC, src), "-o", obj], obj))
+    # the translation units are independent: compile them side by side
+    with ThreadPoolExecutor(max_workers=min(len(jobs), os.cpu_count() or 1)) as ex:
+        list(ex.map(lambda j: _run(j[0], verbose), jobs))
+    objs = [obj for _, obj in jobs]
     tmp = LIB + ".tmp"
     _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)

@@ -4,7 +4,10 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <cxxabi.h>
+
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -90,6 +93,56 @@ struct MGDev {
   int m = 0;                    // coarsest: unknowns with a dense inverse
   int64_t* ids = nullptr;
   T* inv = nullptr;
+};
+
+// Per-dispatch kernel timer (ibfe_set_kernel_timing): while it is on, every
+// dispatch of the context carries a start/end event pair recorded by the
+// dispatch packet itself (hipExtLaunchKernelGGL, no extra packets), tagged with
+// the kernel's name.  The Krylov drivers mark where each iteration's dispatches
+// begin; dispatches of iterations past convergence (which return at once) are
+// dropped.  collect() resolves the pairs and sums them per kernel name.
+struct KTimer {
+  std::vector<hipEvent_t> ev;     // 2 per recorded dispatch (a pool, reused)
+  std::vector<const char*> tag;   // kernel name of each recorded dispatch
+  std::vector<uint8_t> skip;      // 1: dispatch past convergence, not counted
+  size_t used = 0;
+  std::vector<size_t> marks;      // first dispatch of each iteration of the current solve
+  struct Acc {
+    double ms = 0.0;
+    int64_t launches = 0;
+  };
+  std::map<std::string, Acc> acc;
+  std::string only;               // non-empty: time this kernel's dispatches only
+
+  ~KTimer() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+  // event pair for the next dispatch (false: no event could be created)
+  bool next(const char* name, hipEvent_t& e0, hipEvent_t& e1) {
+    while (ev.size() < 2 * used + 2) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return false;
+      ev.push_back(e);
+    }
+    if (tag.size() < used + 1) {
+      tag.resize(used + 1);
+      skip.resize(used + 1);
+    }
+    e0 = ev[2 * used];
+    e1 = ev[2 * used + 1];
+    tag[used] = name;
+    skip[used] = 0;
+    ++used;
+    return true;
+  }
+  void begin_solve() { marks.clear(); }
+  void mark() { marks.push_back(used); }
+  // iterations iters.. of the current solve returned at once: drop their dispatches
+  void drop_from(int iters) {
+    if (iters >= 0 && size_t(iters) < marks.size())
+      for (size_t i = marks[size_t(iters)]; i < used; ++i) skip[i] = 1;
+    marks.clear();
+  }
 };
 
 struct ibfe_ctx {
@@ -208,8 +261,7 @@ struct ibfe_ctx {
   int64_t steps = 0;
   ibfe_stats stats{};
   bool timing = false;
-  std::vector<hipEvent_t> ev;
-  std::vector<hipEvent_t> ev_mass;  // timer events of the mass Chebyshev steps
+  KTimer kt;
   // executable graphs of fixed kernel sequences (iteration batches, Chebyshev
   // sequences), captured on first use; only on a non-null stream
   bool graphs = true;
@@ -218,8 +270,6 @@ struct ibfe_ctx {
 
   ~ibfe_ctx() {
     for (auto& kv : graph_cache) (void)hipGraphExecDestroy(kv.second);
-    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
-    for (hipEvent_t e : ev_mass) (void)hipEventDestroy(e);
     for (void* b : blocks) {
       if (user_alloc)
         alloc.free(b, alloc.user);
@@ -270,6 +320,79 @@ struct ibfe_ctx {
 };
 
 namespace {
+
+// Readable name of a kernel instantiation from its symbol ("k_zb_cheb<float,
+// false, 3>"): demangled, without the return type, the parameter list and the
+// namespace.
+std::string kernel_label(const char* mangled) {
+  if (!mangled) return "kernel";
+  int status = 0;
+  char* dem = abi::__cxa_demangle(mangled, nullptr, nullptr, &status);
+  std::string n = (status == 0 && dem) ? std::string(dem) : std::string(mangled);
+  std::free(dem);
+  if (n.rfind("void ", 0) == 0) n.erase(0, 5);
+  int depth = 0;
+  for (size_t i = 0; i < n.size(); ++i) {
+    if (n[i] == '<') ++depth;
+    else if (n[i] == '>') --depth;
+    else if (n[i] == '(' && depth == 0 && n.compare(i, 11, "(anonymous ") != 0) {
+      n.resize(i);
+      break;
+    }
+  }
+  for (size_t q; (q = n.find("(anonymous namespace)::")) != std::string::npos;) n.erase(q, 23);
+  for (size_t q; (q = n.find("ibfe::")) != std::string::npos;) n.erase(q, 6);
+  return n;
+}
+
+template <auto K>
+const char* kname(hipStream_t stream) {
+  static const std::string name = kernel_label(hipKernelNameRefByPtr((const void*)K, stream));
+  return name.c_str();
+}
+
+// Every kernel of the library is dispatched through here: with the kernel timer
+// on, the dispatch records its own start and end events.
+template <auto K, typename... Args>
+inline void klaunch(ibfe_ctx& c, dim3 grid, dim3 block, uint32_t shmem, hipStream_t stream, Args... args) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c.timing && (c.kt.only.empty() || c.kt.only == kname<K>(stream)) && c.kt.next(kname<K>(stream), e0, e1))
+    hipExtLaunchKernelGGL(K, grid, block, shmem, stream, e0, e1, 0, args...);
+  else
+    hipLaunchKernelGGL(K, grid, block, shmem, stream, args...);
+}
+
+// Resolve the recorded event pairs (synchronises the stream) and add them to the
+// per-kernel sums; the mass Chebyshev step and the pressure stiffness apply also
+// feed the two summary fields of ibfe_stats.
+int collect_kernel_times(ibfe_ctx& c) {
+  KTimer& kt = c.kt;
+  if (kt.used == 0) return IBFE_OK;
+  HIP_TRY(hipEventSynchronize(kt.ev[2 * kt.used - 1]));
+  for (size_t i = 0; i < kt.used; ++i) {
+    if (kt.skip[i]) continue;
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, kt.ev[2 * i], kt.ev[2 * i + 1]));
+    const std::string name(kt.tag[i]);
+    KTimer::Acc& a = kt.acc[name];
+    a.ms += ms;
+    a.launches += 1;
+    static const std::string tail = ", false, 3>";
+    const bool mass = name.rfind("k_zb_cheb<", 0) == 0 && name.size() > tail.size() &&
+                      name.compare(name.size() - tail.size(), tail.size(), tail) == 0;
+    const bool pressure = name == "k_cg_q_zb<float, 1>" || name == "k_cg_q_zb<double, 1>";
+    if (mass) {
+      c.stats.mass_apply_ms += ms;
+      c.stats.mass_applies += 1;
+    } else if (pressure) {
+      c.stats.poisson_apply_ms += ms;
+      c.stats.poisson_applies += 1;
+    }
+  }
+  kt.used = 0;
+  kt.marks.clear();
+  return IBFE_OK;
+}
 
 // -------------------------------------------------------------------------
 // set-up
@@ -640,32 +763,20 @@ int next_batch(int est, int done_so_far) {
   return 8;
 }
 
-// q = A p with partial p.q; returns the number of partials written.  With
-// events, the dispatch itself records its start and end (no extra packets).
+// q = A p with partial p.q; returns the number of partials written.
 template <typename T, class Op>
-int launch_q(ibfe_ctx& c, const Op& op, NodeList nl, const T* p, T* q,
-             const KScal* sc, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+int launch_q(ibfe_ctx& c, const Op& op, NodeList nl, const T* p, T* q, const KScal* sc) {
   const int nr = red_blocks(nl.n);
-  if (e0)
-    hipExtLaunchKernelGGL((k_cg_q<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, e0, e1, 0, nl,
-                          op, p, q, c.partials, sc);
-  else
-    hipLaunchKernelGGL((k_cg_q<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, nl, op, p, q,
-                       c.partials, sc);
+  klaunch<(k_cg_q<T, Op>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, nl, op, p, q, c.partials, sc);
   return nr;
 }
 template <typename T, int NC>
-int launch_q(ibfe_ctx& c, const OpSym<T, NC>& op, NodeList, const T* p, T* q, const KScal* sc,
-             hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+int launch_q(ibfe_ctx& c, const OpSym<T, NC>& op, NodeList, const T* p, T* q, const KScal* sc) {
   const int nr = red_blocks(c.nzitems);
   ZOp<T> z{op.emask, op.flags, op.rowbit, op.sy, op.sz, c.plan.nz + 1,
            {op.c[0], op.c[1], op.c[2], op.c[3]}, c.zb, c.zlanes};
-  if (e0)
-    hipExtLaunchKernelGGL((k_cg_q_zb<T, NC>), dim3(nr), dim3(kBlock), 0, c.stream, e0, e1, 0,
-                          (const int*)c.zitems, c.nzitems, z, op.stride, p, q, c.partials, sc);
-  else
-    hipLaunchKernelGGL((k_cg_q_zb<T, NC>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
-                       c.nzitems, z, op.stride, p, q, c.partials, sc);
+  klaunch<(k_cg_q_zb<T, NC>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems, c.nzitems, z,
+                              op.stride, p, q, c.partials, sc);
   return nr;
 }
 
@@ -681,10 +792,10 @@ template <typename T, class Op>
 int hang_prepare(ibfe_ctx& c, const Op& op, T* x, const KScal* sc) {
   if (c.nh == 0) return IBFE_OK;
   const int nb = blocks_lin(c.nh);
-  hipLaunchKernelGGL(k_hang_fill<T>, dim3(nb), dim3(kBlock), 0, c.stream, c.nh, (const int32_t*)c.hang_ids,
+  klaunch<k_hang_fill<T>>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nh, (const int32_t*)c.hang_ids,
                      (const int32_t*)c.hang_par, x, int(Op::kNC), c.stride, sc);
   OpElem<T, Op> f{op, x};
-  hipLaunchKernelGGL((k_hang_elem<T, OpElem<T, Op>>), dim3(nb), dim3(kBlock), 0, c.stream, c.nh,
+  klaunch<(k_hang_elem<T, OpElem<T, Op>>)>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nh,
                      (const int32_t*)c.hang_ids, f, const_cast<T*>(op.yh), sc);
   CHECK_LAUNCH();
   return IBFE_OK;
@@ -704,18 +815,6 @@ int pre_apply(ibfe_ctx& c, const OpCSym<T, NC>& op, T* x, const KScal* sc) {
 template <typename T, int NC>
 int pre_apply(ibfe_ctx& c, const OpCStencil<T, NC>& op, T* x, const KScal* sc) {
   return hang_prepare<T>(c, op, x, sc);
-}
-
-// Event pair k of the kernel timer (created on first use).
-int timer_events(ibfe_ctx& c, size_t k, hipEvent_t& e0, hipEvent_t& e1) {
-  while (c.ev.size() < 2 * k + 2) {
-    hipEvent_t ne;
-    HIP_TRY(hipEventCreate(&ne));
-    c.ev.push_back(ne);
-  }
-  e0 = c.ev[2 * k];
-  e1 = c.ev[2 * k + 1];
-  return IBFE_OK;
 }
 
 // Graph keys: call site, Krylov slot, scalar size, sequence length.
@@ -753,86 +852,52 @@ int graph_run(ibfe_ctx& c, uint64_t key, Body&& body) {
   return IBFE_OK;
 }
 
-// Event pair k of the mass-step timer.
-int mass_events(ibfe_ctx& c, size_t k, hipEvent_t& e0, hipEvent_t& e1) {
-  while (c.ev_mass.size() < 2 * k + 2) {
-    hipEvent_t ne;
-    HIP_TRY(hipEventCreate(&ne));
-    c.ev_mass.push_back(ne);
-  }
-  e0 = c.ev_mass[2 * k];
-  e1 = c.ev_mass[2 * k + 1];
-  return IBFE_OK;
-}
-
-// Add the durations of the first n timed mass steps to the statistics.
-int collect_mass_events(ibfe_ctx& c, int n) {
-  if (n <= 0) return IBFE_OK;
-  HIP_TRY(hipEventSynchronize(c.ev_mass[2 * (n - 1) + 1]));
-  for (int k = 0; k < n; ++k) {
-    float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, c.ev_mass[2 * k], c.ev_mass[2 * k + 1]));
-    c.stats.mass_apply_ms += ms;
-    c.stats.mass_applies += 1;
-  }
-  return IBFE_OK;
-}
-
 // composite pressure operator: z-blocked walk (defined with the refined-lattice helpers)
 template <typename T>
-int launch_q(ibfe_ctx& c, const OpCSym<T, 1>& op, NodeList, const T* p, T* q, const KScal* sc,
-             hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+int launch_q(ibfe_ctx& c, const OpCSym<T, 1>& op, NodeList, const T* p, T* q, const KScal* sc);
 
 template <typename T, class Op>
 int run_cg(ibfe_ctx& c, const Op& op, NodeList nl, const T* b, T* x, T* r, T* p,
-           T* q, int slot, double rtol, int max_iters, bool zero_guess, SolveOut& out,
-           bool timed = false) {
+           T* q, int slot, double rtol, int max_iters, bool zero_guess, SolveOut& out) {
   const int nb = blocks_for(nl.n), nr = red_blocks(nl.n);
   KScal* sc = &c.scal[slot];
   int prc;
   if (!zero_guess && (prc = pre_apply(c, op, x, (const KScal*)nullptr))) return prc;
-  hipLaunchKernelGGL((k_cg_init<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, nl, op, b, x,
+  klaunch<(k_cg_init<T, Op>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, nl, op, b, x,
                      r, p, c.partials, zero_guess ? 1 : 0);
-  hipLaunchKernelGGL(k_fin_cg_init, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr, sc,
+  klaunch<k_fin_cg_init>(c, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr, sc,
                      rtol * rtol, max_iters);
   CHECK_LAUNCH();
   int launched = 0;
   KScal s{};
+  c.kt.begin_solve();
   while (true) {
     const int batch = std::min(next_batch(c.est[slot], launched), max_iters + 1 - launched);
     auto body = [&]() -> int {
       for (int k = 0; k < batch; ++k) {
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (timed && timer_events(c, size_t(launched + k), e0, e1)) return IBFE_EHIP;
+        if (c.timing) c.kt.mark();
         int rc2;
         if ((rc2 = pre_apply(c, op, p, (const KScal*)sc))) return rc2;
-        const int nq = launch_q<T>(c, op, nl, p, q, (const KScal*)sc, e0, e1);
-        hipLaunchKernelGGL(k_fin_cg_q, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nq, sc);
-        hipLaunchKernelGGL((k_cg_xr<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, nl, op, x, r,
+        const int nq = launch_q<T>(c, op, nl, p, q, (const KScal*)sc);
+        klaunch<k_fin_cg_q>(c, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nq, sc);
+        klaunch<(k_cg_xr<T, Op>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, nl, op, x, r,
                            p, q, c.partials, (const KScal*)sc);
-        hipLaunchKernelGGL(k_fin_cg_xr, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr,
+        klaunch<k_fin_cg_xr>(c, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr,
                            sc);
-        hipLaunchKernelGGL((k_cg_p<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, nl, op, r, p,
+        klaunch<(k_cg_p<T, Op>)>(c, dim3(nb), dim3(kBlock), 0, c.stream, nl, op, r, p,
                            (const KScal*)sc);
         CHECK_LAUNCH();
       }
       return IBFE_OK;
     };
-    if ((prc = timed ? body() : graph_run(c, graph_key(kGsCg, slot, sizeof(T), batch), body))) return prc;
+    if ((prc = graph_run(c, graph_key(kGsCg, slot, sizeof(T), batch), body))) return prc;
     launched += batch;
     int rc = poll(c, slot, s);
     if (rc) return rc;
     if (s.done || launched > max_iters) break;
   }
-  if (timed) {
-    // launches past convergence return at once; only the s.iters real applies count
-    for (int k = 0; k < s.iters && k < launched; ++k) {
-      float ms = 0.f;
-      HIP_TRY(hipEventElapsedTime(&ms, c.ev[2 * k], c.ev[2 * k + 1]));
-      c.stats.poisson_apply_ms += ms;
-      c.stats.poisson_applies += 1;
-    }
-  }
+  // dispatches past convergence returned at once
+  if (c.timing) c.kt.drop_from(s.iters);
   c.est[slot] = std::max(1, s.iters);
   out.iters = s.iters;
   out.res = s.bb > 0.0 ? std::sqrt(s.rr / s.bb) : 0.0;
@@ -857,32 +922,34 @@ int run_bicgstab(ibfe_ctx& c, const Op& op, const T* b, T* x, T* const* wv, int 
   for (int restart = 0;; ++restart) {
     restarts = restart;
     if ((prc = pre_apply(c, op, x, (const KScal*)nullptr))) return prc;
-    hipLaunchKernelGGL((k_bi_init<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, nl, op, b, x, r, rhat, p,
+    klaunch<(k_bi_init<T, Op>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, nl, op, b, x, r, rhat, p,
                        v, c.partials);
-    hipLaunchKernelGGL(k_fin_bi_init, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc, rtol * rtol,
+    klaunch<k_fin_bi_init>(c, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc, rtol * rtol,
                        max_iters - total);
     CHECK_LAUNCH();
     int launched = 0;
+    c.kt.begin_solve();
     while (true) {
       const int batch = std::min(next_batch(c.est[slot], launched), max_iters - total + 1 - launched);
       auto body = [&]() -> int {
         for (int k = 0; k < batch; ++k) {
+          if (c.timing) c.kt.mark();
           int rc2;
-          hipLaunchKernelGGL((k_bi_p<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, nl, op, r, p, v, phat,
+          klaunch<(k_bi_p<T, Op>)>(c, dim3(nb), dim3(kBlock), 0, c.stream, nl, op, r, p, v, phat,
                              csc);
           if ((rc2 = pre_apply(c, op, phat, csc))) return rc2;
-          hipLaunchKernelGGL((k_bi_apply<T, Op, 0>), dim3(nr), dim3(kBlock), 0, c.stream, nl, op, phat, v,
+          klaunch<(k_bi_apply<T, Op, 0>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, nl, op, phat, v,
                              rhat, c.partials, csc);
-          hipLaunchKernelGGL(k_fin_bi_apply<0>, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc);
-          hipLaunchKernelGGL((k_bi_s<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, nl, op, r, v, s, shat,
+          klaunch<k_fin_bi_apply<0>>(c, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc);
+          klaunch<(k_bi_s<T, Op>)>(c, dim3(nb), dim3(kBlock), 0, c.stream, nl, op, r, v, s, shat,
                              csc);
           if ((rc2 = pre_apply(c, op, shat, csc))) return rc2;
-          hipLaunchKernelGGL((k_bi_apply<T, Op, 1>), dim3(nr), dim3(kBlock), 0, c.stream, nl, op, shat, t,
+          klaunch<(k_bi_apply<T, Op, 1>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, nl, op, shat, t,
                              s, c.partials, csc);
-          hipLaunchKernelGGL(k_fin_bi_apply<1>, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc);
-          hipLaunchKernelGGL((k_bi_x<T, Op>), dim3(nr), dim3(kBlock), 0, c.stream, nl, op, x, r, rhat,
+          klaunch<k_fin_bi_apply<1>>(c, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc);
+          klaunch<(k_bi_x<T, Op>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, nl, op, x, r, rhat,
                              phat, shat, s, t, c.partials, csc);
-          hipLaunchKernelGGL(k_fin_bi_x, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc);
+          klaunch<k_fin_bi_x>(c, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc);
           CHECK_LAUNCH();
         }
         return IBFE_OK;
@@ -893,6 +960,7 @@ int run_bicgstab(ibfe_ctx& c, const Op& op, const T* b, T* x, T* const* wv, int 
       if (rc) return rc;
       if (st.done || launched > max_iters - total) break;
     }
+    if (c.timing) c.kt.drop_from(st.iters);
     total += st.iters;
     if (st.status == 1 && restart < 3 && total < max_iters) continue;
     break;
@@ -926,13 +994,13 @@ int ir_residual(ibfe_ctx& c, const Op64& op, const double* b, double* x, TR* r32
     z.zb = c.zb;
     for (int t = 0; t < 4; ++t) z.c[t] = op.c[t];
     nr = red_blocks(c.nzitems);
-    hipLaunchKernelGGL((k_zb_residual<TR, Op64::kNC>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
+    klaunch<(k_zb_residual<TR, Op64::kNC>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
                        c.nzitems, z, b, (const double*)x, r32, op.stride, c.partials);
   } else {
-    hipLaunchKernelGGL((k_residual<Op64, TR>), dim3(nr), dim3(kBlock), 0, c.stream, c.nl, op, b,
+    klaunch<(k_residual<Op64, TR>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, c.nl, op, b,
                        x, r32, c.partials);
   }
-  hipLaunchKernelGGL(k_fin_residual, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr,
+  klaunch<k_fin_residual>(c, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr,
                      c.res2);
   CHECK_LAUNCH();
   HIP_TRY(hipMemcpyAsync(c.host_res2, c.res2, 2 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
@@ -964,7 +1032,7 @@ int run_refined(ibfe_ctx& c, const Op64& op64, uint32_t rowbit, int nc, const do
     total += so.iters;
     out.restarts += so.restarts;
     if (rc && rc != IBFE_ENOCONV) return rc;
-    hipLaunchKernelGGL(k_add_correction<float>, dim3(nb), dim3(kBlock), 0, c.stream, c.nl,
+    klaunch<k_add_correction<float>>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl,
                        c.flags, rowbit, (const float*)d32, x, nc, c.stride);
     CHECK_LAUNCH();
   }
@@ -1099,23 +1167,18 @@ ZOp<T> zcomp_op(const ibfe_ctx& c, const OpCSym<T, NC>& o) {
 template <typename T, int NC>
 void launch_extra(ibfe_ctx& c, const OpCSym<T, NC>& o, const T* x, const KScal* sc) {
   if (c.nxn == 0) return;
-  hipLaunchKernelGGL((k_comp_extra<T, NC>), dim3(blocks_lin(c.nxn)), dim3(kBlock), 0, c.stream, c.nxn,
+  klaunch<(k_comp_extra<T, NC>)>(c, dim3(blocks_lin(c.nxn)), dim3(kBlock), 0, c.stream, c.nxn,
                      (const int32_t*)c.xnodes, o, x, RefBufs<T>::extra(c), sc);
 }
 
 // q = A p for the composite pressure operator (hanging rows already prepared).
 template <typename T>
-int launch_q(ibfe_ctx& c, const OpCSym<T, 1>& op, NodeList, const T* p, T* q, const KScal* sc,
-             hipEvent_t e0, hipEvent_t e1) {
+int launch_q(ibfe_ctx& c, const OpCSym<T, 1>& op, NodeList, const T* p, T* q, const KScal* sc) {
   launch_extra<T, 1>(c, op, p, sc);
   const int nr = red_blocks(c.nzitems);
   const ZOp<T> z = zcomp_op(c, op);
-  if (e0)
-    hipExtLaunchKernelGGL((k_cg_q_zb<T, 1>), dim3(nr), dim3(kBlock), 0, c.stream, e0, e1, 0,
-                          (const int*)c.zitems, c.nzitems, z, op.stride, p, q, c.partials, sc);
-  else
-    hipLaunchKernelGGL((k_cg_q_zb<T, 1>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
-                       c.nzitems, z, op.stride, p, q, c.partials, sc);
+  klaunch<(k_cg_q_zb<T, 1>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems, c.nzitems, z,
+                             op.stride, p, q, c.partials, sc);
   return nr;
 }
 
@@ -1167,7 +1230,7 @@ GradElem grad_elem(const ibfe_ctx& c, const double* x) {
 template <typename T>
 int fill_hanging(ibfe_ctx& c, T* x, int nc) {
   if (c.nh == 0) return IBFE_OK;
-  hipLaunchKernelGGL(k_hang_fill<T>, dim3(blocks_lin(c.nh)), dim3(kBlock), 0, c.stream, c.nh,
+  klaunch<k_hang_fill<T>>(c, dim3(blocks_lin(c.nh)), dim3(kBlock), 0, c.stream, c.nh,
                      (const int32_t*)c.hang_ids, (const int32_t*)c.hang_par, x, nc, c.stride,
                      (const KScal*)nullptr);
   CHECK_LAUNCH();
@@ -1179,9 +1242,9 @@ template <typename T, class F>
 int comp_rows(ibfe_ctx& c, const F& f, uint32_t rowbit, uint32_t exclude, T scale, T* out) {
   T* yh = RefBufs<T>::yh(c);
   if (c.nh)
-    hipLaunchKernelGGL((k_hang_elem<T, F>), dim3(blocks_lin(c.nh)), dim3(kBlock), 0, c.stream, c.nh,
+    klaunch<(k_hang_elem<T, F>)>(c, dim3(blocks_lin(c.nh)), dim3(kBlock), 0, c.stream, c.nh,
                        (const int32_t*)c.hang_ids, f, yh, (const KScal*)nullptr);
-  hipLaunchKernelGGL((k_comp_rows<T, F>), dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
+  klaunch<(k_comp_rows<T, F>)>(c, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
                      c.nl, f, (const uint8_t*)c.flags, rowbit, exclude, scale,
                      children_of(c), RefBufs<T>::pw(c), (const T*)yh, out, c.stride);
   CHECK_LAUNCH();
@@ -1201,7 +1264,7 @@ int run_cheb_gen(ibfe_ctx& c, const Op& op, const T* b, T* x, T* xalt, T* d, int
   const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
   T* cur = ((iters - 1) % 2 == 0) ? x : xalt;
   T* alt = cur == x ? xalt : x;
-  hipLaunchKernelGGL((k_cheb0_gen<T, Op>), dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
+  klaunch<(k_cheb0_gen<T, Op>)>(c, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
                      c.nl, op, b, d, cur, T(1.0 / theta), (const KScal*)nullptr);
   const int nr = red_blocks(c.nzitems);
   const ZOp<T> zop = zcomp_op(c, op);
@@ -1216,18 +1279,11 @@ int run_cheb_gen(ibfe_ctx& c, const Op& op, const T* b, T* x, T* xalt, T* d, int
       const T c1 = T(rn * rho), c2 = T(2.0 * rn / delta);
       rho = rn;
       if ((rc2 = pre_apply(c, op, cur, (const KScal*)nullptr))) return rc2;
-      hipEvent_t e0 = nullptr, e1 = nullptr;
-      if (c.timing && mass_events(c, size_t(k - 1), e0, e1)) return IBFE_EHIP;
       constexpr int NC = Op::kNC;
       launch_extra<T, NC>(c, op, cur, (const KScal*)nullptr);
-      if (e0)
-        hipExtLaunchKernelGGL((k_zb_cheb<T, false, NC>), dim3(nr), dim3(kBlock), 0, c.stream, e0, e1, 0,
-                              (const int*)c.zitems, c.nzitems, zop, (const T*)cur, b, d, alt, c1, c2,
-                              c.partials, (const KScal*)nullptr, op.stride, 1);
-      else
-        hipLaunchKernelGGL((k_zb_cheb<T, false, NC>), dim3(nr), dim3(kBlock), 0, c.stream,
-                           (const int*)c.zitems, c.nzitems, zop, (const T*)cur, b, d, alt, c1, c2,
-                           c.partials, (const KScal*)nullptr, op.stride, 1);
+      klaunch<(k_zb_cheb<T, false, NC>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
+                                         c.nzitems, zop, (const T*)cur, b, d, alt, c1, c2, c.partials,
+                                         (const KScal*)nullptr, op.stride, 1);
       std::swap(cur, alt);
     }
     CHECK_LAUNCH();
@@ -1236,7 +1292,6 @@ int run_cheb_gen(ibfe_ctx& c, const Op& op, const T* b, T* x, T* xalt, T* d, int
   if ((rc = graph_run(c, graph_key(kGsChebGen, 0, sizeof(T), iters), body))) return rc;
   // the sequence swaps the buffers iters - 1 times (a graph replay does not run body)
   cur = ((iters - 1) % 2 == 0) ? cur0 : alt0;
-  if (c.timing && (rc = collect_mass_events(c, iters - 1))) return rc;
   if (cur != x) return fail(IBFE_EINVAL, "internal: Chebyshev result buffer");
   return IBFE_OK;
 }
@@ -1304,19 +1359,19 @@ int smooth_comp(ibfe_ctx& c, const MGDev<T>& L, const T* b, T*& x, T*& alt, int 
   for (int k = 0; k < m; ++k) {
     const bool last = k == m - 1;
     if (k == 0 && zero_start && !(last && dot)) {
-      hipLaunchKernelGGL((k_cheb0_gen<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, c.nl, op, b, L.d, x, T(ch.c2[0]), sc);
+      klaunch<(k_cheb0_gen<T, Op>)>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, op, b, L.d, x, T(ch.c2[0]), sc);
       continue;
     }
     if (k == 0 && zero_start)
-      hipLaunchKernelGGL((k_cheb0_gen<T, Op>), dim3(nb), dim3(kBlock), 0, c.stream, c.nl, op, b, L.d, x, T(0), sc);
+      klaunch<(k_cheb0_gen<T, Op>)>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, op, b, L.d, x, T(0), sc);
     if ((rc = pre_apply(c, op, x, sc))) return rc;
     launch_extra<T, 1>(c, op, x, sc);
     if (last && dot)
-      hipLaunchKernelGGL((k_zb_cheb<T, true>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
-                         c.nzitems, zop, (const T*)x, b, L.d, alt, T(ch.c1[k]), T(ch.c2[k]), c.partials, sc);
+      klaunch<(k_zb_cheb<T, true>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
+                         c.nzitems, zop, (const T*)x, b, L.d, alt, T(ch.c1[k]), T(ch.c2[k]), c.partials, sc, int64_t(0), 1);
     else
-      hipLaunchKernelGGL((k_zb_cheb<T, false>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
-                         c.nzitems, zop, (const T*)x, b, L.d, alt, T(ch.c1[k]), T(ch.c2[k]), c.partials, sc);
+      klaunch<(k_zb_cheb<T, false>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
+                         c.nzitems, zop, (const T*)x, b, L.d, alt, T(ch.c1[k]), T(ch.c2[k]), c.partials, sc, int64_t(0), 1);
     std::swap(x, alt);
   }
   nparts = nr;
@@ -1334,25 +1389,25 @@ int smooth(ibfe_ctx& c, const MGDev<T>& L, const T* b, T*& x, T*& alt, int m, bo
   for (int k = 0; k < m; ++k) {
     const bool last = k == m - 1;
     if (k == 0 && zero_start && !(last && dot)) {
-      hipLaunchKernelGGL(k_mg_cheb0<T>, dim3(blocks_for(L.nchunks)), dim3(kBlock), 0, c.stream,
+      klaunch<k_mg_cheb0<T>>(c, dim3(blocks_for(L.nchunks)), dim3(kBlock), 0, c.stream,
                          L.nl, (const uint8_t*)L.emask, (const uint8_t*)L.flags,
-                         T(L.kc[0]), T(ch.c2[0]), b, L.d, x, sc);
+                         T(L.kc[0]), T(ch.c2[0]), b, L.d, x, sc, kMgRow, int64_t(0));
       continue;  // x already holds the result: no swap
     }
     const T* xin = x;
     if (k == 0 && zero_start) {
       // degree-1 smoothing from zero with a dot: x is zero on entry
-      hipLaunchKernelGGL(k_mg_cheb0<T>, dim3(blocks_for(L.nchunks)), dim3(kBlock), 0, c.stream,
+      klaunch<k_mg_cheb0<T>>(c, dim3(blocks_for(L.nchunks)), dim3(kBlock), 0, c.stream,
                          L.nl, (const uint8_t*)L.emask, (const uint8_t*)L.flags,
-                         T(L.kc[0]), T(0), b, L.d, x, sc);
+                         T(L.kc[0]), T(0), b, L.d, x, sc, kMgRow, int64_t(0));
       xin = x;
     }
     if (last && dot)
-      hipLaunchKernelGGL((k_zb_cheb<T, true>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)L.zitems,
-                         L.nzitems, op, xin, b, L.d, alt, T(ch.c1[k]), T(ch.c2[k]), c.partials, sc);
+      klaunch<(k_zb_cheb<T, true>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)L.zitems,
+                         L.nzitems, op, xin, b, L.d, alt, T(ch.c1[k]), T(ch.c2[k]), c.partials, sc, int64_t(0), 1);
     else
-      hipLaunchKernelGGL((k_zb_cheb<T, false>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)L.zitems,
-                         L.nzitems, op, xin, b, L.d, alt, T(ch.c1[k]), T(ch.c2[k]), c.partials, sc);
+      klaunch<(k_zb_cheb<T, false>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)L.zitems,
+                         L.nzitems, op, xin, b, L.d, alt, T(ch.c1[k]), T(ch.c2[k]), c.partials, sc, int64_t(0), 1);
     std::swap(x, alt);
   }
   nparts = nr;
@@ -1389,15 +1444,15 @@ int vcycle(ibfe_ctx& c, std::vector<MGDev<T>>& lv, const T* r0, T* z0, const KSc
       const auto op = csym_op<T, 1>(c, 0.0, 1.0, kMgRow, RefBufs<T>::dinvK(c));
       if ((rc = pre_apply(c, op, cur[l], sc))) return rc;
       launch_extra<T, 1>(c, op, cur[l], sc);
-      hipLaunchKernelGGL(k_zb_resid<T>, dim3(red_blocks(c.nzitems)), dim3(kBlock), 0, c.stream,
+      klaunch<k_zb_resid<T>>(c, dim3(red_blocks(c.nzitems)), dim3(kBlock), 0, c.stream,
                          (const int*)c.zitems, c.nzitems, zcomp_op(c, op), (const T*)cur[l], b, A.r, sc);
     } else {
-      hipLaunchKernelGGL(k_zb_resid<T>, dim3(red_blocks(A.nzitems)), dim3(kBlock), 0, c.stream,
+      klaunch<k_zb_resid<T>>(c, dim3(red_blocks(A.nzitems)), dim3(kBlock), 0, c.stream,
                          (const int*)A.zitems, A.nzitems, level_op(A), (const T*)cur[l], b, A.r, sc);
     }
     const MGDev<T>& C = lv[l + 1];
     const bool fuse = l + 2 < L;  // level l + 1 is smoothed, not solved
-    hipLaunchKernelGGL(k_mg_restrict<T>, dim3(blocks_for(C.nchunks)), dim3(kBlock), 0, c.stream,
+    klaunch<k_mg_restrict<T>>(c, dim3(blocks_for(C.nchunks)), dim3(kBlock), 0, c.stream,
                        C.nl, (const uint8_t*)C.flags, int(C.sy), int(C.sz),
                        int(A.sy), int(A.sz), A.nx, A.ny, A.nz, (const T*)A.r, C.b, sc,
                        fuse ? (const uint8_t*)C.emask : (const uint8_t*)nullptr, T(C.kc[0]), c2pre,
@@ -1409,11 +1464,11 @@ int vcycle(ibfe_ctx& c, std::vector<MGDev<T>>& lv, const T* r0, T* z0, const KSc
     const T* b = L == 1 ? r0 : C.b;
     if (C.m > 0) {
       if (L == 1) cur[0] = z0;  // single level: the dense solve is the whole cycle
-      hipLaunchKernelGGL(k_mg_dense<T>, dim3((C.m + kWaves - 1) / kWaves), dim3(kBlock), 0, c.stream, C.m,
+      klaunch<k_mg_dense<T>>(c, dim3((C.m + kWaves - 1) / kWaves), dim3(kBlock), 0, c.stream, C.m,
                          (const int64_t*)C.ids, (const T*)C.inv, b, cur[L - 1], sc);
       if (L == 1) {
         np = red_blocks(C.nchunks);
-        hipLaunchKernelGGL(k_mg_dot<T>, dim3(np), dim3(kBlock), 0, c.stream, C.nl,
+        klaunch<k_mg_dot<T>>(c, dim3(np), dim3(kBlock), 0, c.stream, C.nl,
                            (const uint8_t*)C.flags, b, (const T*)z0, c.partials, sc);
       }
       CHECK_LAUNCH();
@@ -1424,7 +1479,7 @@ int vcycle(ibfe_ctx& c, std::vector<MGDev<T>>& lv, const T* r0, T* z0, const KSc
   for (int l = L - 2; l >= 0; --l) {
     const MGDev<T>& A = lv[l];
     const MGDev<T>& C = lv[l + 1];
-    hipLaunchKernelGGL(k_mg_prolong<T>, dim3(blocks_for(A.nchunks)), dim3(kBlock), 0, c.stream,
+    klaunch<k_mg_prolong<T>>(c, dim3(blocks_for(A.nchunks)), dim3(kBlock), 0, c.stream,
                        A.nl, (const uint8_t*)A.flags, int(A.sy), int(A.sz),
                        int(C.sy), int(C.sz), (const T*)cur[l + 1], cur[l], sc);
     CHECK_LAUNCH();
@@ -1439,7 +1494,7 @@ int vcycle(ibfe_ctx& c, std::vector<MGDev<T>>& lv, const T* r0, T* z0, const KSc
 // CG on K_{P'P'} x = b preconditioned by one V-cycle per iteration; x starts at 0.
 template <typename T, class Op>
 int run_pcg_mg(ibfe_ctx& c, const Op& op, std::vector<MGDev<T>>& lv, const T* b, T* x, T* r, T* p, T* q,
-               T* z, int slot, double rtol, int max_iters, SolveOut& out, bool timed) {
+               T* z, int slot, double rtol, int max_iters, SolveOut& out) {
   const int nr = red_blocks(c.nchunks);
   KScal* sc = &c.scal[slot];
   const KScal* csc = sc;
@@ -1450,55 +1505,48 @@ int run_pcg_mg(ibfe_ctx& c, const Op& op, std::vector<MGDev<T>>& lv, const T* b,
   const uint8_t* pe = pre0 ? (const uint8_t*)lv[0].emask : nullptr;
   T* const px = pre0 ? lv[0].xt : nullptr;
   const T pc0 = T(lv[0].kc[0]), pc2 = T(cheb_coefs(kSmooth).c2[0]);
-  hipLaunchKernelGGL(k_mgcg_init<T>, dim3(nr), dim3(kBlock), 0, c.stream, c.nl,
+  klaunch<k_mgcg_init<T>>(c, dim3(nr), dim3(kBlock), 0, c.stream, c.nl,
                      (const uint8_t*)c.flags, b, x, r, c.partials, pe, pc0, pc2, px);
-  hipLaunchKernelGGL(k_fin_mgcg_init, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr, sc,
+  klaunch<k_fin_mgcg_init>(c, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr, sc,
                      rtol * rtol, max_iters);
   CHECK_LAUNCH();
   if ((rc = vcycle<T>(c, lv, r, z, csc, np, pre0))) return rc;
-  hipLaunchKernelGGL(k_fin_mgcg_rz, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, np, sc, 1);
-  hipLaunchKernelGGL(k_mgcg_p<T>, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream, c.nl, (const uint8_t*)c.flags, (const T*)z, p, csc);
+  klaunch<k_fin_mgcg_rz>(c, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, np, sc, 1);
+  klaunch<k_mgcg_p<T>>(c, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream, c.nl, (const uint8_t*)c.flags, (const T*)z, p, csc);
   CHECK_LAUNCH();
   int launched = 0;
   KScal s{};
+  c.kt.begin_solve();
   while (true) {
     const int batch = std::min(launched == 0 ? std::max(2, c.est[slot] - 1) : 2, max_iters + 1 - launched);
     auto body = [&]() -> int {
       for (int k = 0; k < batch; ++k) {
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (timed && timer_events(c, size_t(launched + k), e0, e1)) return IBFE_EHIP;
+        if (c.timing) c.kt.mark();
         int rc2;
         if ((rc2 = pre_apply(c, op, p, csc))) return rc2;
-        const int nq = launch_q<T>(c, op, c.nl, (const T*)p, q, csc, e0, e1);
-        hipLaunchKernelGGL(k_fin_cg_q, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nq, sc);
-        hipLaunchKernelGGL(k_mgcg_xr<T>, dim3(nr), dim3(kBlock), 0, c.stream, c.nl,
+        const int nq = launch_q<T>(c, op, c.nl, (const T*)p, q, csc);
+        klaunch<k_fin_cg_q>(c, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nq, sc);
+        klaunch<k_mgcg_xr<T>>(c, dim3(nr), dim3(kBlock), 0, c.stream, c.nl,
                            (const uint8_t*)c.flags, x, r, (const T*)p, (const T*)q, c.partials, csc, pe, pc0,
                            pc2, px);
-        hipLaunchKernelGGL(k_fin_mgcg_xr, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr,
+        klaunch<k_fin_mgcg_xr>(c, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr,
                            sc);
         CHECK_LAUNCH();
         if ((rc2 = vcycle<T>(c, lv, r, z, csc, np, pre0))) return rc2;
-        hipLaunchKernelGGL(k_fin_mgcg_rz, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, np,
+        klaunch<k_fin_mgcg_rz>(c, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, np,
                            sc, 0);
-        hipLaunchKernelGGL(k_mgcg_p<T>, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
+        klaunch<k_mgcg_p<T>>(c, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
                            c.nl, (const uint8_t*)c.flags, (const T*)z, p, csc);
         CHECK_LAUNCH();
       }
       return IBFE_OK;
     };
-    if ((rc = timed ? body() : graph_run(c, graph_key(kGsPcgMg, slot, sizeof(T), batch), body))) return rc;
+    if ((rc = graph_run(c, graph_key(kGsPcgMg, slot, sizeof(T), batch), body))) return rc;
     launched += batch;
     if ((rc = poll(c, slot, s))) return rc;
     if (s.done || launched > max_iters) break;
   }
-  if (timed) {
-    for (int k = 0; k < s.iters && k < launched; ++k) {
-      float ms = 0.f;
-      HIP_TRY(hipEventElapsedTime(&ms, c.ev[2 * k], c.ev[2 * k + 1]));
-      c.stats.poisson_apply_ms += ms;
-      c.stats.poisson_applies += 1;
-    }
-  }
+  if (c.timing) c.kt.drop_from(s.iters);
   c.est[slot] = std::max(1, s.iters);
   out.iters = s.iters;
   out.res = s.bb > 0.0 ? std::sqrt(s.rr / s.bb) : 0.0;
@@ -1521,33 +1569,35 @@ int run_ib_pcg(ibfe_ctx& c, const double* b, double* x, double* r, double* p, do
   const int64_t S = c.mstride;
   KScal* sc = &c.scal[slot];
   const KScal* csc = sc;
-  hipLaunchKernelGGL(k_ibcg_init, dim3(nr), dim3(kBlock), 0, c.stream, nl, op, b, x, r, c.partials,
+  klaunch<k_ibcg_init>(c, dim3(nr), dim3(kBlock), 0, c.stream, nl, op, b, x, r, c.partials,
                      zero_guess ? 1 : 0);
-  hipLaunchKernelGGL(k_fin_mgcg_init, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr, sc,
+  klaunch<k_fin_mgcg_init>(c, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr, sc,
                      rtol * rtol, max_iters);
-  hipLaunchKernelGGL(k_ib_bjac, dim3(nj), dim3(kBlock), 0, c.stream, M, nblk, (const float*)c.G_binv,
+  klaunch<k_ib_bjac>(c, dim3(nj), dim3(kBlock), 0, c.stream, M, nblk, (const float*)c.G_binv,
                      (const double*)r, z, S, c.partials, csc);
-  hipLaunchKernelGGL(k_fin_mgcg_rz, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nj, sc, 1);
+  klaunch<k_fin_mgcg_rz>(c, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nj, sc, 1);
   // the first direction is z + 0 p: p must hold finite values
-  hipLaunchKernelGGL(k_zero<double>, dim3(nb), dim3(kBlock), 0, c.stream, nl, p, 3, S);
+  klaunch<k_zero<double>>(c, dim3(nb), dim3(kBlock), 0, c.stream, nl, p, 3, S);
   CHECK_LAUNCH();
   double* pb[2] = {p, p2};
   int par = 0;  // pb[par] holds the current direction
   int launched = 0, rc;
   KScal s{};
+  c.kt.begin_solve();
   while (true) {
     const int batch = std::min(next_batch(c.est[slot], launched), max_iters + 1 - launched);
     auto body = [&]() -> int {
       for (int k = 0; k < batch; ++k) {
+        if (c.timing) c.kt.mark();
         const double* pold = pb[(par + k) % 2];
         double* pnew = pb[(par + k + 1) % 2];
-        hipLaunchKernelGGL(k_ibcg_qp, dim3(ng), dim3(kBlock), 0, c.stream, M, (const int64_t*)c.G_ptr,
+        klaunch<k_ibcg_qp>(c, dim3(ng), dim3(kBlock), 0, c.stream, M, (const int64_t*)c.G_ptr,
                            (const int32_t*)c.G_col, (const double*)c.G_val, S, (const double*)z, pold, pnew, q,
                            c.partials, csc);
-        hipLaunchKernelGGL(k_fin_cg_q, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, ng, sc);
-        hipLaunchKernelGGL(k_ib_xr_bjac, dim3(nj), dim3(kBlock), 0, c.stream, M, nblk, (const float*)c.G_binv,
+        klaunch<k_fin_cg_q>(c, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, ng, sc);
+        klaunch<k_ib_xr_bjac>(c, dim3(nj), dim3(kBlock), 0, c.stream, M, nblk, (const float*)c.G_binv,
                            x, r, (const double*)pnew, (const double*)q, z, S, c.partials, csc);
-        hipLaunchKernelGGL(k_fin_ibcg, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nj, sc);
+        klaunch<k_fin_ibcg>(c, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nj, sc);
         CHECK_LAUNCH();
       }
       return IBFE_OK;
@@ -1558,6 +1608,7 @@ int run_ib_pcg(ibfe_ctx& c, const double* b, double* x, double* r, double* p, do
     if ((rc = poll(c, slot, s))) return rc;
     if (s.done || launched > max_iters) break;
   }
+  if (c.timing) c.kt.drop_from(s.iters);
   c.est[slot] = std::max(1, s.iters);
   out.iters = s.iters;
   out.res = s.bb > 0.0 ? std::sqrt(s.rr / s.bb) : 0.0;
@@ -1598,7 +1649,7 @@ int run_cheb_mass(ibfe_ctx& c, const T* b, T* x, T* xalt, T* d, int iters) {
   for (int t = 0; t < 4; ++t) op.c[t] = T(c.fc.m[t]);
   T* cur = ((iters - 1) % 2 == 0) ? x : xalt;
   T* alt = cur == x ? xalt : x;
-  hipLaunchKernelGGL((k_mg_cheb0<T, 3>), dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
+  klaunch<(k_mg_cheb0<T, 3>)>(c, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
                      c.nl, (const uint8_t*)c.emask, (const uint8_t*)c.flags,
                      T(c.fc.m[0]), T(1.0 / theta), b, d, cur, (const KScal*)nullptr, kFlagF, c.stride);
   const int nr = red_blocks(c.nzitems);
@@ -1610,19 +1661,12 @@ int run_cheb_mass(ibfe_ctx& c, const T* b, T* x, T* xalt, T* d, int iters) {
       const double rn = 1.0 / (2.0 * sigma - rho);
       const T c1 = T(rn * rho), c2 = T(2.0 * rn / delta);
       rho = rn;
-      hipEvent_t e0 = nullptr, e1 = nullptr;
-      if (c.timing && mass_events(c, size_t(k - 1), e0, e1)) return IBFE_EHIP;
       // the first step writes the zeros off the free rows into the second buffer
       // (the zero-start step did so for the first one and for d)
       const int zero_off = k == 1 ? 1 : 0;
-      if (e0)
-        hipExtLaunchKernelGGL((k_zb_cheb<T, false, 3>), dim3(nr), dim3(kBlock), 0, c.stream, e0, e1, 0,
-                              (const int*)c.zitems, c.nzitems, op, (const T*)cur, b, d, alt, c1, c2, c.partials,
-                              (const KScal*)nullptr, c.stride, zero_off);
-      else
-        hipLaunchKernelGGL((k_zb_cheb<T, false, 3>), dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
-                           c.nzitems, op, (const T*)cur, b, d, alt, c1, c2, c.partials, (const KScal*)nullptr,
-                           c.stride, zero_off);
+      klaunch<(k_zb_cheb<T, false, 3>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
+                                        c.nzitems, op, (const T*)cur, b, d, alt, c1, c2, c.partials,
+                                        (const KScal*)nullptr, c.stride, zero_off);
       std::swap(cur, alt);
     }
     CHECK_LAUNCH();
@@ -1631,10 +1675,6 @@ int run_cheb_mass(ibfe_ctx& c, const T* b, T* x, T* xalt, T* d, int iters) {
   if (int rcb = graph_run(c, graph_key(kGsChebMass, 0, sizeof(T), iters), body)) return rcb;
   // the sequence swaps the buffers iters - 1 times (a graph replay does not run body)
   cur = ((iters - 1) % 2 == 0) ? cur0 : alt0;
-  if (c.timing) {
-    int rc = collect_mass_events(c, iters - 1);
-    if (rc) return rc;
-  }
   if (cur != x) return fail(IBFE_EINVAL, "internal: Chebyshev result buffer");
   return IBFE_OK;
 }
@@ -1648,7 +1688,7 @@ int build_s1(ibfe_ctx& c) {
   const double rdt = P.params.rho / P.params.dt, mu = P.params.mu;
   double cm[4];
   for (int t = 0; t < 4; ++t) cm[t] = rdt * c.fc.m[t] + mu * c.fc.k[t];
-  hipLaunchKernelGGL(k_s1_build, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream, c.nl, c.emask, c.flags, c.u, c.stride, int(P.sy), int(P.sz), P.h, cm[0], cm[1],
+  klaunch<k_s1_build>(c, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream, c.nl, c.emask, c.flags, c.u, c.stride, int(P.sy), int(P.sz), P.h, cm[0], cm[1],
                      cm[2], cm[3], P.params.rho, c.coef64, c.coef32, 1, kFlagP);
   CHECK_LAUNCH();
   return IBFE_OK;
@@ -1665,7 +1705,7 @@ int s1_explicit(ibfe_ctx& c) {
   const int64_t S = c.stride;
   double* b1 = c.w[8];
   double* x1 = c.w[9];
-  hipLaunchKernelGGL(k_s1_build, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.emask, c.flags,
+  klaunch<k_s1_build>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.emask, c.flags,
                      c.u, S, int(P.sy), int(P.sz), P.h, 0.0, 0.0, 0.0, 0.0, rho, c.coef64, (float*)nullptr, 1,
                      kFlagP);
   double cm[4], ca[4];
@@ -1673,14 +1713,14 @@ int s1_explicit(ibfe_ctx& c) {
     cm[t] = rdt * c.fc.m[t];
     ca[t] = rdt * c.fc.m[t] + mu * c.fc.k[t];
   }
-  hipLaunchKernelGGL(k_s1_rhs_explicit, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.emask,
+  klaunch<k_s1_rhs_explicit>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.emask,
                      c.flags, c.coef64, c.u, c.p, c.g, b1, S, int(P.sy), int(P.sz), cm[0], cm[1], cm[2], cm[3],
                      ca[0], ca[1], ca[2], ca[3], c.fc.g2[0], c.fc.g2[1], c.fc.g2[2]);
   if (P.params.viscous == 1 && c.nlift > 0)
-    hipLaunchKernelGGL(k_strain_lift, dim3(blocks_lin(c.nlift)), dim3(kBlock), 0, c.stream, c.nlift,
+    klaunch<k_strain_lift>(c, dim3(blocks_lin(c.nlift)), dim3(kBlock), 0, c.stream, c.nlift,
                        (const int32_t*)c.lift_rows, (const uint8_t*)c.emask, (const double*)c.g, b1, S, mu, P.h,
                        int(P.sy), int(P.sz));
-  hipLaunchKernelGGL((k_masked_copy<double, double>), dim3(nb), dim3(kBlock), 0, c.stream, c.nl,
+  klaunch<(k_masked_copy<double, double>)>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl,
                      c.flags, kFlagF, c.u, x1, 3, S);
   CHECK_LAUNCH();
   SolveOut so;
@@ -1724,11 +1764,11 @@ int s1_explicit(ibfe_ctx& c) {
 int remove_slot_means(ibfe_ctx& c, double* x) {
   const Plan& P = c.plan;
   const int nr = red_blocks(c.nchunks);
-  hipLaunchKernelGGL(k_slot_sum, dim3(nr), dim3(kBlock), 0, c.stream, c.nl, c.slot,
+  klaunch<k_slot_sum>(c, dim3(nr), dim3(kBlock), 0, c.stream, c.nl, c.slot,
                      (const double*)x, c.partials);
-  hipLaunchKernelGGL(k_fin_slot, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr,
+  klaunch<k_fin_slot>(c, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr,
                      P.n_floating, (const double*)c.float_count, c.float_means);
-  hipLaunchKernelGGL(k_slot_sub, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream, c.nl,
+  klaunch<k_slot_sub>(c, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream, c.nl,
                      c.slot, x, (const double*)c.float_means);
   CHECK_LAUNCH();
   return IBFE_OK;
@@ -1754,7 +1794,7 @@ int step_once(ibfe_ctx& c) {
       hm.c[k - 1] = std::cos(k * P.omega * t1);
       hm.s[k - 1] = std::sin(k * P.omega * t1);
     }
-    hipLaunchKernelGGL(k_inlet, dim3(blocks_lin(int64_t(P.inlet_ids.size()))), dim3(kBlock), 0,
+    klaunch<k_inlet>(c, dim3(blocks_lin(int64_t(P.inlet_ids.size()))), dim3(kBlock), 0,
                        c.stream, int(P.inlet_ids.size()), c.inlet_ids, c.inlet_shape, hm, c.g, S);
     CHECK_LAUNCH();
   }
@@ -1768,28 +1808,28 @@ int step_once(ibfe_ctx& c) {
     if ((rc = build_s1(c))) return rc;
     double cm[4];
     for (int t = 0; t < 4; ++t) cm[t] = rho / dt * c.fc.m[t];
-    hipLaunchKernelGGL(k_s1_rhs, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.emask,
+    klaunch<k_s1_rhs>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.emask,
                        c.flags, c.u, c.p, b1, S, sy, sz, cm[0], cm[1], cm[2], cm[3],
                        c.fc.g2[0], c.fc.g2[1], c.fc.g2[2]);
     if (c.nlift > 0)
-      hipLaunchKernelGGL(k_s1_lift, dim3(blocks_lin(c.nlift)), dim3(kBlock), 0, c.stream, c.nlift,
+      klaunch<k_s1_lift>(c, dim3(blocks_lin(c.nlift)), dim3(kBlock), 0, c.stream, c.nlift,
                          (const int32_t*)c.lift_rows, (const uint8_t*)c.flags, (const double*)c.coef64,
                          (const double*)c.g, b1, S, sy, sz);
     CHECK_LAUNCH();
     if (P.params.viscous == 1 && c.nlift > 0) {
-      hipLaunchKernelGGL(k_strain_lift, dim3(blocks_lin(c.nlift)), dim3(kBlock), 0, c.stream, c.nlift,
+      klaunch<k_strain_lift>(c, dim3(blocks_lin(c.nlift)), dim3(kBlock), 0, c.stream, c.nlift,
                          (const int32_t*)c.lift_rows, (const uint8_t*)c.emask, (const double*)c.g, b1, S,
                          P.params.mu, P.h, sy, sz);
       CHECK_LAUNCH();
     }
-    hipLaunchKernelGGL((k_masked_copy<double, double>), dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.flags, kFlagF, c.u, x1, 3, S);
+    klaunch<(k_masked_copy<double, double>)>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.flags, kFlagF, c.u, x1, 3, S);
     CHECK_LAUNCH();
     SolveOut so;
     auto solve = [&](const auto& op, const auto& op32) -> int {
       if (mixed)
         return run_refined(c, op, kFlagF, 3, b1, x1, c.v32[8], c.v32[9], rtol, so,
                            [&](const float* r32, float* d32, double tol, SolveOut& o) {
-                             hipLaunchKernelGGL(k_zero<float>, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, d32, 3,
+                             klaunch<k_zero<float>>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, d32, 3,
                                                 S);
                              return run_bicgstab<float>(c, op32, r32, d32, c.v32, kScS1, tol, maxit, o);
                            });
@@ -1805,19 +1845,19 @@ int step_once(ibfe_ctx& c) {
     c.stats.s1_outer = so.outer;
     c.stats.s1_restarts = so.restarts;
   }
-  hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, x1, 1.0, c.g,
+  klaunch<k_axpby>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, x1, 1.0, c.g,
                      c.ustar, 3, S);
   CHECK_LAUNCH();
 
   // 2.-4. BCE-IB correction: G Lambda = U_B - I u*, u_ib = u* + I_F^T Lambda (FP64)
-  hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, c.ustar,
+  klaunch<k_axpby>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, c.ustar,
                      0.0, c.ustar, c.uib, 3, S);
   CHECK_LAUNCH();
   c.stats.ib_iters = 0;
   c.stats.ib_res = 0.0;
   if (P.M > 0) {
     const int M = int(P.M);
-    hipLaunchKernelGGL(k_ib_interp, dim3(blocks_lin(int64_t(M) * 8)), dim3(kBlock), 0, c.stream, M, c.ib_idx, c.ib_w,
+    klaunch<k_ib_interp>(c, dim3(blocks_lin(int64_t(M) * 8)), dim3(kBlock), 0, c.stream, M, c.ib_idx, c.ib_w,
                        c.UB, c.ustar, S, c.ibv[0], c.mstride, 1);
     CHECK_LAUNCH();
     const bool warm = c.lam_warm;
@@ -1830,7 +1870,7 @@ int step_once(ibfe_ctx& c) {
     c.stats.ib_iters = so.iters;
     c.stats.ib_res = so.res;
     const int nn = c.n_sp;
-    hipLaunchKernelGGL(k_ib_spread, dim3(blocks_lin(nn)), dim3(kBlock), 0, c.stream, nn, c.sp_node,
+    klaunch<k_ib_spread>(c, dim3(blocks_lin(nn)), dim3(kBlock), 0, c.stream, nn, c.sp_node,
                        c.sp_ptr, c.sp_pt, c.sp_wt, c.ibv[1], c.mstride, c.uib, S);
     CHECK_LAUNCH();
   }
@@ -1838,7 +1878,7 @@ int step_once(ibfe_ctx& c) {
   // 5. pressure increment: K_{P'P'} Phi = -(rho/dt) (B u_ib)_{P'}
   double* b3 = c.w[8];
   {
-    hipLaunchKernelGGL(k_div, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.emask, c.flags,
+    klaunch<k_div>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.emask, c.flags,
                        kFlagPp, 0u, c.uib, b3, S, sy, sz, c.fc.g2[0], c.fc.g2[1], c.fc.g2[2], -rho / dt);
     CHECK_LAUNCH();
     if (P.n_floating > 0 && (rc = remove_slot_means(c, b3))) return rc;
@@ -1849,23 +1889,23 @@ int step_once(ibfe_ctx& c) {
     if (mixed) {
       auto op32 = sym_op<float, 1>(c, kc, kFlagPp);
       if (!c.phi_warm)
-        hipLaunchKernelGGL(k_zero<double>, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.phi, 1, S);
+        klaunch<k_zero<double>>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.phi, 1, S);
       c.phi_warm = false;
       float* const* v = c.v32;
       rc = run_refined(c, op, kFlagPp, 1, b3, c.phi, v[8], v[9], rtol, so,
                        [&](const float* r32, float* d32, double tol, SolveOut& o) {
                          if (mg)
                            return run_pcg_mg<float>(c, op32, c.mg32, r32, d32, v[0], v[1], v[2], v[3], kScS3,
-                                                    tol, maxit, o, c.timing);
+                                                    tol, maxit, o);
                          return run_cg<float>(c, op32, c.nl, r32, d32, v[0], v[1], v[2], kScS3,
-                                              tol, maxit, true, o, c.timing);
+                                              tol, maxit, true, o);
                        });
     } else if (mg) {
       rc = run_pcg_mg<double>(c, op, c.mg64, b3, c.phi, c.w[0], c.w[1], c.w[2], c.w[3], kScS3, rtol, maxit,
-                              so, c.timing);
+                              so);
     } else {
       rc = run_cg<double>(c, op, c.nl, b3, c.phi, c.w[0], c.w[1], c.w[2], kScS3, rtol, maxit,
-                          true, so, c.timing);
+                          true, so);
     }
     if (rc) return rc;
     c.stats.s3_iters = so.iters;
@@ -1879,13 +1919,13 @@ int step_once(ibfe_ctx& c) {
   {
     double* b4 = c.w[8];
     double* delta = c.delta;
-    hipLaunchKernelGGL(k_grad, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.emask, c.flags,
+    klaunch<k_grad>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.emask, c.flags,
                        kFlagF, c.phi, b4, S, sy, sz, c.fc.g2[0], c.fc.g2[1], c.fc.g2[2]);
     CHECK_LAUNCH();
     const double mc[4] = {c.fc.m[0], c.fc.m[1], c.fc.m[2], c.fc.m[3]};
     auto op = sym_op<double, 3>(c, mc, kFlagF);
     SolveOut so;
-    if (!c.delta_warm) hipLaunchKernelGGL(k_zero<double>, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, delta, 3, S);
+    if (!c.delta_warm) klaunch<k_zero<double>>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, delta, 3, S);
     c.delta_warm = false;
     if (mixed) {
       float* const* v = c.v32;
@@ -1906,7 +1946,7 @@ int step_once(ibfe_ctx& c) {
         if (so.res <= rtol || sweep == 4) break;
         const int it = mass_cheb_steps(std::max(rtol / std::max(so.res, 1e-300), 1e-15));
         if ((rc = run_cheb_mass<double>(c, (const double*)r64, c.w[0], c.w[1], c.w[2], it))) return rc;
-        hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, delta, 1.0,
+        klaunch<k_axpby>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, delta, 1.0,
                            c.w[0], delta, 3, S);
         CHECK_LAUNCH();
         so.iters += it;
@@ -1919,9 +1959,9 @@ int step_once(ibfe_ctx& c) {
     c.stats.s4_res = so.res;
     c.stats.s4_outer = so.outer;
     c.delta_warm = true;
-    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, c.uib,
+    klaunch<k_axpby>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, c.uib,
                        -dt / rho, delta, c.u_next, 3, S);
-    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, c.p, 1.0,
+    klaunch<k_axpby>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, c.p, 1.0,
                        c.phi, c.p_next, 1, S);
     CHECK_LAUNCH();
   }
@@ -1931,7 +1971,7 @@ int step_once(ibfe_ctx& c) {
   c.steps += 1;
   c.stats.steps = c.steps;
   c.stats.t = c.t;
-  return IBFE_OK;
+  return c.timing ? collect_kernel_times(c) : IBFE_OK;
 }
 
 // Tentative-velocity stencil of the composite mesh: fine-element part (rows of
@@ -1946,10 +1986,10 @@ int build_s1_refined(ibfe_ctx& c) {
   }
   const int nb = blocks_for(c.nchunks);
   const int64_t S = c.stride;
-  hipLaunchKernelGGL(k_s1_build, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.emask, c.flags,
+  klaunch<k_s1_build>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.emask, c.flags,
                      c.u, S, int(P.sy), int(P.sz), P.h, cf[0], cf[1], cf[2], cf[3], P.params.rho, c.coef64,
                      c.coef32, 1, kFlagP | kFlagHang);
-  hipLaunchKernelGGL(k_s1_build, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.cmask, c.flags,
+  klaunch<k_s1_build>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.cmask, c.flags,
                      c.u, S, int(P.sy), int(P.sz), P.hb, cc[0], cc[1], cc[2], cc[3], P.params.rho,
                      c.coef64 + 27 * S, c.coef32 ? c.coef32 + 27 * S : nullptr, 2, kFlagP);
   CHECK_LAUNCH();
@@ -1965,10 +2005,10 @@ int s1_explicit_refined(ibfe_ctx& c) {
   const int64_t S = c.stride;
   double* b1 = c.w[8];
   double* x1 = c.w[9];
-  hipLaunchKernelGGL(k_s1_build, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.emask, c.flags,
+  klaunch<k_s1_build>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.emask, c.flags,
                      c.u, S, int(P.sy), int(P.sz), P.h, 0.0, 0.0, 0.0, 0.0, rho, c.coef64, (float*)nullptr, 1,
                      kFlagP | kFlagHang);
-  hipLaunchKernelGGL(k_s1_build, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.cmask, c.flags,
+  klaunch<k_s1_build>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.cmask, c.flags,
                      c.u, S, int(P.sy), int(P.sz), P.hb, 0.0, 0.0, 0.0, 0.0, rho, c.coef64 + 27 * S,
                      (float*)nullptr, 2, kFlagP);
   CHECK_LAUNCH();
@@ -1996,7 +2036,7 @@ int s1_explicit_refined(ibfe_ctx& c) {
   } else if ((rc = comp_rows<double>(c, f, kFlagF, 0u, 1.0, b1))) {
     return rc;
   }
-  hipLaunchKernelGGL((k_masked_copy<double, double>), dim3(nb), dim3(kBlock), 0, c.stream, c.nl,
+  klaunch<(k_masked_copy<double, double>)>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl,
                      c.flags, kFlagF, c.u, x1, 3, S);
   CHECK_LAUNCH();
   SolveOut so;
@@ -2057,7 +2097,7 @@ int step_once_refined(ibfe_ctx& c) {
       hm.c[k - 1] = std::cos(k * P.omega * t1);
       hm.s[k - 1] = std::sin(k * P.omega * t1);
     }
-    hipLaunchKernelGGL(k_inlet, dim3(blocks_lin(int64_t(P.inlet_ids.size()))), dim3(kBlock), 0,
+    klaunch<k_inlet>(c, dim3(blocks_lin(int64_t(P.inlet_ids.size()))), dim3(kBlock), 0,
                        c.stream, int(P.inlet_ids.size()), c.inlet_ids, c.inlet_shape, hm, c.g, S);
     CHECK_LAUNCH();
   }
@@ -2095,14 +2135,14 @@ int step_once_refined(ibfe_ctx& c) {
     } else if ((rc = comp_rows<double>(c, f, kFlagF, 0u, 1.0, b1))) {
       return rc;
     }
-    hipLaunchKernelGGL((k_masked_copy<double, double>), dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.flags, kFlagF, c.u, x1, 3, S);
+    klaunch<(k_masked_copy<double, double>)>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.flags, kFlagF, c.u, x1, 3, S);
     CHECK_LAUNCH();
     SolveOut so;
     auto solve = [&](const auto& op, const auto& op32) -> int {
       if (mixed)
         return run_refined(c, op, kFlagF, 3, b1, x1, c.v32[8], c.v32[9], rtol, so,
                            [&](const float* r32, float* d32, double tol, SolveOut& o) {
-                             hipLaunchKernelGGL(k_zero<float>, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, d32, 3,
+                             klaunch<k_zero<float>>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, d32, 3,
                                                 S);
                              return run_bicgstab<float>(c, op32, r32, d32, c.v32, kScS1, tol, maxit, o);
                            });
@@ -2118,19 +2158,19 @@ int step_once_refined(ibfe_ctx& c) {
     c.stats.s1_outer = so.outer;
     c.stats.s1_restarts = so.restarts;
   }
-  hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, x1, 1.0, c.g,
+  klaunch<k_axpby>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, x1, 1.0, c.g,
                      c.ustar, 3, S);
   CHECK_LAUNCH();
 
   // 2.-4. BCE-IB correction (every support node is a fine, non-hanging node)
-  hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, c.ustar,
+  klaunch<k_axpby>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, c.ustar,
                      0.0, c.ustar, c.uib, 3, S);
   CHECK_LAUNCH();
   c.stats.ib_iters = 0;
   c.stats.ib_res = 0.0;
   if (P.M > 0) {
     const int M = int(P.M);
-    hipLaunchKernelGGL(k_ib_interp, dim3(blocks_lin(int64_t(M) * 8)), dim3(kBlock), 0, c.stream, M, c.ib_idx, c.ib_w,
+    klaunch<k_ib_interp>(c, dim3(blocks_lin(int64_t(M) * 8)), dim3(kBlock), 0, c.stream, M, c.ib_idx, c.ib_w,
                        c.UB, c.ustar, S, c.ibv[0], c.mstride, 1);
     CHECK_LAUNCH();
     const bool warm = c.lam_warm;
@@ -2143,7 +2183,7 @@ int step_once_refined(ibfe_ctx& c) {
     c.stats.ib_iters = so.iters;
     c.stats.ib_res = so.res;
     const int nn = c.n_sp;
-    hipLaunchKernelGGL(k_ib_spread, dim3(blocks_lin(nn)), dim3(kBlock), 0, c.stream, nn, c.sp_node,
+    klaunch<k_ib_spread>(c, dim3(blocks_lin(nn)), dim3(kBlock), 0, c.stream, nn, c.sp_node,
                        c.sp_ptr, c.sp_pt, c.sp_wt, c.ibv[1], c.mstride, c.uib, S);
     CHECK_LAUNCH();
   }
@@ -2171,23 +2211,23 @@ int step_once_refined(ibfe_ctx& c) {
     if (mixed) {
       auto op32 = csym_op<float, 1>(c, 0.0, 1.0, kFlagPp, c.dinvK32);
       if (!c.phi_warm)
-        hipLaunchKernelGGL(k_zero<double>, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.phi, 1, S);
+        klaunch<k_zero<double>>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.phi, 1, S);
       c.phi_warm = false;
       float* const* v = c.v32;
       rc = run_refined(c, op, kFlagPp, 1, b3, c.phi, v[8], v[9], rtol, so,
                        [&](const float* r32, float* d32, double tol, SolveOut& o) {
                          if (mg)
                            return run_pcg_mg<float>(c, op32, c.mg32, r32, d32, v[0], v[1], v[2], v[3], kScS3,
-                                                    tol, maxit, o, c.timing);
+                                                    tol, maxit, o);
                          return run_cg<float>(c, op32, c.nl, r32, d32, v[0], v[1], v[2], kScS3,
-                                              tol, maxit, true, o, c.timing);
+                                              tol, maxit, true, o);
                        });
     } else if (mg) {
       rc = run_pcg_mg<double>(c, op, c.mg64, b3, c.phi, c.w[0], c.w[1], c.w[2], c.w[3], kScS3, rtol, maxit,
-                              so, c.timing);
+                              so);
     } else {
       rc = run_cg<double>(c, op, c.nl, b3, c.phi, c.w[0], c.w[1], c.w[2], kScS3, rtol, maxit,
-                          true, so, c.timing);
+                          true, so);
     }
     if (rc) return rc;
     c.stats.s3_iters = so.iters;
@@ -2206,7 +2246,7 @@ int step_once_refined(ibfe_ctx& c) {
     auto op = csym_op<double, 3>(c, 1.0, 0.0, kFlagF, c.dinvM64);
     const double lmin = P.mass_lmin, lmax = kMassLmax;
     SolveOut so;
-    if (!c.delta_warm) hipLaunchKernelGGL(k_zero<double>, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, delta, 3, S);
+    if (!c.delta_warm) klaunch<k_zero<double>>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, delta, 3, S);
     c.delta_warm = false;
     if (mixed) {
       auto op32 = csym_op<float, 3>(c, 1.0, 0.0, kFlagF, c.dinvM32);
@@ -2228,7 +2268,7 @@ int step_once_refined(ibfe_ctx& c) {
         const int it = cheb_steps(std::max(rtol / std::max(so.res, 1e-300), 1e-15), lmin, lmax);
         if ((rc = run_cheb_gen<double>(c, op, (const double*)r64, c.w[0], c.w[1], c.w[2], it, lmin, lmax)))
           return rc;
-        hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, delta, 1.0,
+        klaunch<k_axpby>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, delta, 1.0,
                            c.w[0], delta, 3, S);
         CHECK_LAUNCH();
         so.iters += it;
@@ -2241,9 +2281,9 @@ int step_once_refined(ibfe_ctx& c) {
     c.stats.s4_res = so.res;
     c.stats.s4_outer = so.outer;
     c.delta_warm = true;
-    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, c.uib,
+    klaunch<k_axpby>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, c.uib,
                        -dt / rho, delta, c.u_next, 3, S);
-    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, c.p, 1.0,
+    klaunch<k_axpby>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, 1.0, c.p, 1.0,
                        c.phi, c.p_next, 1, S);
     CHECK_LAUNCH();
   }
@@ -2253,7 +2293,7 @@ int step_once_refined(ibfe_ctx& c) {
   c.steps += 1;
   c.stats.steps = c.steps;
   c.stats.t = c.t;
-  return IBFE_OK;
+  return c.timing ? collect_kernel_times(c) : IBFE_OK;
 }
 
 // FP32 work vectors for the verification applies of an FP64-mode context
@@ -2286,12 +2326,12 @@ int apply_refined(ibfe_ctx& C, int op, int precision, double* xin, double* yout,
       if ((rc = ensure_fp32_work(C))) return rc;
       float* x32 = C.v32[0];
       float* y32 = C.v32[1];
-      hipLaunchKernelGGL((k_masked_copy<double, float>), dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, xin, x32, 1, S);
+      klaunch<(k_masked_copy<double, float>)>(C, dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, xin, x32, 1, S);
       CHECK_LAUNCH();
       if ((rc = fill_hanging<float>(C, x32, 1))) return rc;
       auto o = csym_op<float, 1>(C, a, b, kFlagP, C.dinvM32);
       if ((rc = comp_rows<float>(C, OpElem<float, OpCSym<float, 1>>{o, x32}, kFlagP, 0u, 1.0f, y32))) return rc;
-      hipLaunchKernelGGL((k_masked_copy<float, double>), dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, y32, yout, 1, S);
+      klaunch<(k_masked_copy<float, double>)>(C, dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, y32, yout, 1, S);
       CHECK_LAUNCH();
       return IBFE_OK;
     }
@@ -2333,7 +2373,7 @@ int apply_refined(ibfe_ctx& C, int op, int precision, double* xin, double* yout,
       }
       float* x32 = C.v32[0];
       float* y32 = C.v32[1];
-      hipLaunchKernelGGL((k_masked_copy<double, float>), dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, xin, x32, 3, S);
+      klaunch<(k_masked_copy<double, float>)>(C, dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, xin, x32, 3, S);
       CHECK_LAUNCH();
       if ((rc = fill_hanging<float>(C, x32, 3))) return rc;
       if (P.params.viscous == 1)
@@ -2343,7 +2383,7 @@ int apply_refined(ibfe_ctx& C, int op, int precision, double* xin, double* yout,
         rc = comp_rows<float>(C, OpElem<float, OpCStencil<float, 3>>{cstencil_op<float>(C, C.coef32, kFlagP), x32},
                               kFlagP, 0u, 1.0f, y32);
       if (rc) return rc;
-      hipLaunchKernelGGL((k_masked_copy<float, double>), dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, y32, yout, 3, S);
+      klaunch<(k_masked_copy<float, double>)>(C, dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, y32, yout, 3, S);
       CHECK_LAUNCH();
       return IBFE_OK;
     }
@@ -2359,7 +2399,7 @@ int copy_in(ibfe_ctx& c, double* dense, int nc, const double* src, int on_device
     comp = c.compact;
   }
   HIP_TRY(hipMemsetAsync(dense - c.halo, 0, sizeof(double) * c.stride * nc, c.stream));
-  hipLaunchKernelGGL(k_scatter, dim3(blocks_lin(n)), dim3(kBlock), 0, c.stream, n, c.pids, comp, dense, nc,
+  klaunch<k_scatter>(c, dim3(blocks_lin(n)), dim3(kBlock), 0, c.stream, n, c.pids, comp, dense, nc,
                      c.stride);
   CHECK_LAUNCH();
   if (!on_device) HIP_TRY(hipStreamSynchronize(c.stream));
@@ -2369,7 +2409,7 @@ int copy_in(ibfe_ctx& c, double* dense, int nc, const double* src, int on_device
 int copy_out(ibfe_ctx& c, const double* dense, int nc, double* dst, int on_device) {
   const int64_t n = c.nP;
   double* comp = on_device ? dst : c.compact;
-  hipLaunchKernelGGL(k_gather, dim3(blocks_lin(n)), dim3(kBlock), 0, c.stream, n, c.pids, dense, comp, nc,
+  klaunch<k_gather>(c, dim3(blocks_lin(n)), dim3(kBlock), 0, c.stream, n, c.pids, dense, comp, nc,
                      c.stride);
   CHECK_LAUNCH();
   if (!on_device) {
@@ -2579,7 +2619,7 @@ int ibfe_set_points(ibfe_ctx* c, const double* X, const double* U_B, int on_devi
   const int64_t np = 64 * M;
   const uint32_t N = uint32_t(P.N);
   GridGeom g{P.origin[0], P.origin[1], P.origin[2], P.h, P.nx, P.ny, P.nz, P.sy, P.sz};
-  hipLaunchKernelGGL(k_ib_stencil, dim3(blocks_lin(M)), dim3(kBlock), 0, C.stream, int(M), g,
+  klaunch<k_ib_stencil>(C, dim3(blocks_lin(M)), dim3(kBlock), 0, C.stream, int(M), g,
                      (const double*)mv.X, (const uint8_t*)C.flags, N, C.ib_idx, C.ib_w, mv.keys, mv.vals,
                      mv.counters);
   CHECK_LAUNCH();
@@ -2589,12 +2629,12 @@ int ibfe_set_points(ibfe_ctx* c, const double* X, const double* U_B, int on_devi
   HIP_TRY(hipcub::DeviceRadixSort::SortPairs(mv.temp, tb, mv.keys, mv.skeys, mv.vals, mv.svals, int(np), 0, bits,
                                              C.stream));
   const int nbp = int((np + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_sp_flags, dim3(nbp), dim3(kBlock), 0, C.stream, np, (const uint32_t*)mv.skeys, N,
+  klaunch<k_sp_flags>(C, dim3(nbp), dim3(kBlock), 0, C.stream, np, (const uint32_t*)mv.skeys, N,
                      mv.flag);
   CHECK_LAUNCH();
   tb = mv.temp_bytes;
   HIP_TRY(hipcub::DeviceScan::ExclusiveSum(mv.temp, tb, mv.flag, mv.pos, int(np), C.stream));
-  hipLaunchKernelGGL(k_sp_fill, dim3(nbp), dim3(kBlock), 0, C.stream, np, int(M), (const uint32_t*)mv.skeys,
+  klaunch<k_sp_fill>(C, dim3(nbp), dim3(kBlock), 0, C.stream, np, int(M), (const uint32_t*)mv.skeys,
                      (const uint32_t*)mv.svals, N, (const int*)mv.flag, (const int*)mv.pos,
                      (const double*)C.ib_w, C.sp_node, C.sp_ptr, C.sp_pt, C.sp_wt, mv.counters);
   CHECK_LAUNCH();
@@ -2604,7 +2644,7 @@ int ibfe_set_points(ibfe_ctx* c, const double* X, const double* U_B, int on_devi
   if (hc[0] > 0)
     return fail(IBFE_ESINGULAR, std::to_string(hc[0]) + " Lagrangian point(s) without a free support node");
   const int64_t nvalid = hc[3];
-  hipLaunchKernelGGL((k_gram_rows<false>), dim3(unsigned(M)), dim3(64), 0, C.stream, int(M),
+  klaunch<(k_gram_rows<false>)>(C, dim3(unsigned(M)), dim3(64), 0, C.stream, int(M),
                      (const int32_t*)C.ib_idx, (const double*)C.ib_w, (const uint8_t*)C.flags,
                      (const uint32_t*)mv.skeys, nvalid, (const int32_t*)C.sp_pt, (const double*)C.sp_wt, mv.cnt,
                      (const int64_t*)nullptr, (int32_t*)nullptr, (double*)nullptr, (double*)nullptr,
@@ -2620,12 +2660,12 @@ int ibfe_set_points(ibfe_ctx* c, const double* X, const double* U_B, int on_devi
     return fail(IBFE_EINVAL, "a Lagrangian point overlaps more than " + std::to_string(kGramCap) +
                                  " support products: the points are too dense");
   if (nnz > mv.g_cap) return fail(IBFE_ENOMEM, "the force system exceeds its capacity");
-  hipLaunchKernelGGL((k_gram_rows<true>), dim3(unsigned(M)), dim3(64), 0, C.stream, int(M),
+  klaunch<(k_gram_rows<true>)>(C, dim3(unsigned(M)), dim3(64), 0, C.stream, int(M),
                      (const int32_t*)C.ib_idx, (const double*)C.ib_w, (const uint8_t*)C.flags,
                      (const uint32_t*)mv.skeys, nvalid, (const int32_t*)C.sp_pt, (const double*)C.sp_wt,
                      (int64_t*)nullptr, (const int64_t*)C.G_ptr, C.G_col, C.G_val, C.G_diag, mv.counters);
   const int nblk = int((M + kIBBlock - 1) / kIBBlock);
-  hipLaunchKernelGGL(k_gram_block_inv, dim3(nblk), dim3(kBlock), 0, C.stream, int(M), (const int64_t*)C.G_ptr,
+  klaunch<k_gram_block_inv>(C, dim3(nblk), dim3(kBlock), 0, C.stream, int(M), (const int64_t*)C.G_ptr,
                      (const int32_t*)C.G_col, (const double*)C.G_val, C.G_binv);
   CHECK_LAUNCH();
   C.n_sp = hc[2];
@@ -2654,9 +2694,9 @@ int ibfe_run_steady(ibfe_ctx* c, double tol, int64_t max_steps, int64_t* steps, 
       nrmse[0] = nrmse[1] = nrmse[2] = 0.0;
     } else {
       // after the step c.u holds u^{n+1} and c.u_next the previous state
-      hipLaunchKernelGGL(k_nrmse_part, dim3(nr), dim3(kBlock), 0, C.stream, C.nl, (const uint8_t*)C.flags,
+      klaunch<k_nrmse_part>(C, dim3(nr), dim3(kBlock), 0, C.stream, C.nl, (const uint8_t*)C.flags,
                          uint32_t(kFlagP), (const double*)C.u, (const double*)C.u_next, C.stride, C.partials);
-      hipLaunchKernelGGL(k_fin_nrmse, dim3(1), dim3(kBlock), 0, C.stream, (const double*)C.partials, nr,
+      klaunch<k_fin_nrmse>(C, dim3(1), dim3(kBlock), 0, C.stream, (const double*)C.partials, nr,
                          double(C.nP), C.nrmse);
       CHECK_LAUNCH();
       HIP_TRY(hipMemcpyAsync(C.host_nrmse, C.nrmse, 3 * sizeof(double), hipMemcpyDeviceToHost, C.stream));
@@ -2783,11 +2823,38 @@ int ibfe_get_stats(const ibfe_ctx* c, ibfe_stats* stats) {
 
 int ibfe_set_kernel_timing(ibfe_ctx* c, int enable) {
   if (!c) return fail(IBFE_EINVAL, "ctx is NULL");
+  int rc_;
+  if (c->timing && (rc_ = collect_kernel_times(*c))) return rc_;
   c->timing = enable != 0;
+  c->kt.acc.clear();
   c->stats.poisson_apply_ms = 0.0;
   c->stats.poisson_applies = 0;
   c->stats.mass_apply_ms = 0.0;
   c->stats.mass_applies = 0;
+  return IBFE_OK;
+}
+
+int ibfe_set_kernel_timing_filter(ibfe_ctx* c, const char* kernel) {
+  if (!c) return fail(IBFE_EINVAL, "ctx is NULL");
+  int rc;
+  if ((rc = collect_kernel_times(*c))) return rc;
+  c->kt.only = kernel ? std::string(kernel) : std::string();
+  return IBFE_OK;
+}
+
+int ibfe_get_kernel_times(ibfe_ctx* c, ibfe_kernel_time* out, int32_t cap, int32_t* n) {
+  if (!c || !n || cap < 0 || (cap > 0 && !out)) return fail(IBFE_EINVAL, "bad argument");
+  int rc;
+  if ((rc = collect_kernel_times(*c))) return rc;
+  std::vector<std::pair<std::string, KTimer::Acc>> v(c->kt.acc.begin(), c->kt.acc.end());
+  std::sort(v.begin(), v.end(), [](const auto& a, const auto& b) { return a.second.ms > b.second.ms; });
+  *n = int32_t(v.size());
+  for (int32_t i = 0; i < cap && i < int32_t(v.size()); ++i) {
+    std::memset(out[i].name, 0, sizeof(out[i].name));
+    std::strncpy(out[i].name, v[i].first.c_str(), sizeof(out[i].name) - 1);
+    out[i].total_ms = v[i].second.ms;
+    out[i].launches = v[i].second.launches;
+  }
   return IBFE_OK;
 }
 
@@ -2834,7 +2901,7 @@ int ibfe_wall_shear(ibfe_ctx* c, const double* normals, double* tau, int on_devi
     // parents' mean, hanging rows gathered into their parents
     double* uc = C.w[5];
     const int nb = blocks_for(C.nchunks);
-    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(kBlock), 0, C.stream, C.nl, 1.0, (const double*)C.u, 0.0,
+    klaunch<k_axpby>(C, dim3(nb), dim3(kBlock), 0, C.stream, C.nl, 1.0, (const double*)C.u, 0.0,
                        (const double*)C.u, uc, 3, C.stride);
     CHECK_LAUNCH();
     int rc;
@@ -2842,15 +2909,15 @@ int ibfe_wall_shear(ibfe_ctx* c, const double* normals, double* tau, int on_devi
     double* g[3] = {C.w[2], C.w[3], C.w[4]};
     for (int d = 0; d < 3; ++d)
       if ((rc = comp_rows<double>(C, grad_elem(C, uc + d * C.stride), kFlagP, 0u, 1.0, g[d]))) return rc;
-    hipLaunchKernelGGL(k_strain_from_grad, dim3(nb), dim3(kBlock), 0, C.stream, C.nl, (const uint8_t*)C.flags,
+    klaunch<k_strain_from_grad>(C, dim3(nb), dim3(kBlock), 0, C.stream, C.nl, (const uint8_t*)C.flags,
                        (const double*)g[0], (const double*)g[1], (const double*)g[2], (const double*)C.lmass64,
                        C.stride, ed, eo);
   } else {
-    hipLaunchKernelGGL(k_nodal_strain, dim3(blocks_for(C.nchunks)), dim3(kBlock), 0, C.stream, C.nl,
+    klaunch<k_nodal_strain>(C, dim3(blocks_for(C.nchunks)), dim3(kBlock), 0, C.stream, C.nl,
                        (const uint8_t*)C.emask, (const uint8_t*)C.flags, (const double*)C.u, C.stride, P.h,
                        C.fc.g2[0], C.fc.g2[1], C.fc.g2[2], int(P.sy), int(P.sz), ed, eo);
   }
-  hipLaunchKernelGGL(k_wall_shear, dim3(blocks_lin(M)), dim3(kBlock), 0, C.stream, M, (const int32_t*)C.ib_idx,
+  klaunch<k_wall_shear>(C, dim3(blocks_lin(M)), dim3(kBlock), 0, C.stream, M, (const int32_t*)C.ib_idx,
                      (const double*)C.ib_w, (const double*)ed, (const double*)eo, C.stride, nrm, P.params.mu,
                      out);
   CHECK_LAUNCH();
@@ -2890,7 +2957,7 @@ int ibfe_apply(ibfe_ctx* c, int op, int precision, const double* x, double* y, i
     HIP_TRY(hipMemcpyAsync(C.ibv[1], h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, C.stream));
     HIP_TRY(hipMemsetAsync(yout - C.halo, 0, sizeof(double) * 3 * S, C.stream));
     const int nn = C.n_sp;
-    hipLaunchKernelGGL(k_ib_spread, dim3(blocks_lin(nn)), dim3(kBlock), 0, C.stream, nn, C.sp_node, C.sp_ptr,
+    klaunch<k_ib_spread>(C, dim3(blocks_lin(nn)), dim3(kBlock), 0, C.stream, nn, C.sp_node, C.sp_ptr,
                        C.sp_pt, C.sp_wt, C.ibv[1], C.mstride, yout, S);
     CHECK_LAUNCH();
     return copy_out(C, yout, 3, y, on_device);
@@ -2908,28 +2975,28 @@ int ibfe_apply(ibfe_ctx* c, int op, int precision, const double* x, double* y, i
       const double cf[4] = {f[0], f[1], f[2], f[3]};
       if (precision == 0) {
         auto o = sym_op<double, 1>(C, cf, kFlagP);
-        hipLaunchKernelGGL((k_apply<double, 1, OpSym<double, 1>>), dim3(nb), dim3(kBlock), 0, C.stream,
+        klaunch<(k_apply<double, 1, OpSym<double, 1>>)>(C, dim3(nb), dim3(kBlock), 0, C.stream,
                            C.nl, o, xin, yout);
       } else {
         if ((rc = ensure_fp32_work(C))) return rc;
         float* x32 = C.v32[0];
         float* y32 = C.v32[1];
-        hipLaunchKernelGGL((k_masked_copy<double, float>), dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, xin, x32, 1, S);
+        klaunch<(k_masked_copy<double, float>)>(C, dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, xin, x32, 1, S);
         auto o = sym_op<float, 1>(C, cf, kFlagP);
-        hipLaunchKernelGGL((k_apply<float, 1, OpSym<float, 1>>), dim3(nb), dim3(kBlock), 0, C.stream,
+        klaunch<(k_apply<float, 1, OpSym<float, 1>>)>(C, dim3(nb), dim3(kBlock), 0, C.stream,
                            C.nl, o, x32, y32);
-        hipLaunchKernelGGL((k_masked_copy<float, double>), dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, y32, yout, 1, S);
+        klaunch<(k_masked_copy<float, double>)>(C, dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, y32, yout, 1, S);
       }
       CHECK_LAUNCH();
       return copy_out(C, yout, 1, y, on_device);
     }
     case IBFE_OP_GRAD:
-      hipLaunchKernelGGL(k_grad, dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.emask, C.flags,
+      klaunch<k_grad>(C, dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.emask, C.flags,
                          kFlagP, xin, yout, S, sy, sz, C.fc.g2[0], C.fc.g2[1], C.fc.g2[2]);
       CHECK_LAUNCH();
       return copy_out(C, yout, 3, y, on_device);
     case IBFE_OP_DIV:
-      hipLaunchKernelGGL(k_div, dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.emask, C.flags,
+      klaunch<k_div>(C, dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.emask, C.flags,
                          kFlagP, 0u, xin, yout, S, sy, sz, C.fc.g2[0], C.fc.g2[1], C.fc.g2[2], 1.0);
       CHECK_LAUNCH();
       return copy_out(C, yout, 1, y, on_device);
@@ -2945,22 +3012,22 @@ int ibfe_apply(ibfe_ctx* c, int op, int precision, const double* x, double* y, i
       const bool strain = P.params.viscous == 1;
       if (precision == 0) {
         if (strain)
-          hipLaunchKernelGGL((k_apply<double, 3, OpStencilStrain<double>>), dim3(nb), dim3(kBlock), 0, C.stream,
+          klaunch<(k_apply<double, 3, OpStencilStrain<double>>)>(C, dim3(nb), dim3(kBlock), 0, C.stream,
                              C.nl, strain_op<double>(C, C.coef64, kFlagP), xin, yout);
         else
-          hipLaunchKernelGGL((k_apply<double, 3, OpStencil<double, 3>>), dim3(nb), dim3(kBlock), 0, C.stream,
+          klaunch<(k_apply<double, 3, OpStencil<double, 3>>)>(C, dim3(nb), dim3(kBlock), 0, C.stream,
                              C.nl, stencil_op<double>(C, C.coef64, kFlagP), xin, yout);
       } else {
         float* x32 = C.v32[0];
         float* y32 = C.v32[1];
-        hipLaunchKernelGGL((k_masked_copy<double, float>), dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, xin, x32, 3, S);
+        klaunch<(k_masked_copy<double, float>)>(C, dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, xin, x32, 3, S);
         if (strain)
-          hipLaunchKernelGGL((k_apply<float, 3, OpStencilStrain<float>>), dim3(nb), dim3(kBlock), 0, C.stream,
+          klaunch<(k_apply<float, 3, OpStencilStrain<float>>)>(C, dim3(nb), dim3(kBlock), 0, C.stream,
                              C.nl, strain_op<float>(C, c32, kFlagP), x32, y32);
         else
-          hipLaunchKernelGGL((k_apply<float, 3, OpStencil<float, 3>>), dim3(nb), dim3(kBlock), 0, C.stream,
+          klaunch<(k_apply<float, 3, OpStencil<float, 3>>)>(C, dim3(nb), dim3(kBlock), 0, C.stream,
                              C.nl, stencil_op<float>(C, c32, kFlagP), x32, y32);
-        hipLaunchKernelGGL((k_masked_copy<float, double>), dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, y32, yout, 3, S);
+        klaunch<(k_masked_copy<float, double>)>(C, dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, y32, yout, 3, S);
       }
       CHECK_LAUNCH();
       return copy_out(C, yout, 3, y, on_device);
@@ -2968,7 +3035,7 @@ int ibfe_apply(ibfe_ctx* c, int op, int precision, const double* x, double* y, i
     case IBFE_OP_INTERP: {
       if (P.M == 0) return fail(IBFE_EINVAL, "no Lagrangian points");
       const int M = int(P.M);
-      hipLaunchKernelGGL(k_ib_interp, dim3(blocks_lin(int64_t(M) * 8)), dim3(kBlock), 0, C.stream, M, C.ib_idx, C.ib_w,
+      klaunch<k_ib_interp>(C, dim3(blocks_lin(int64_t(M) * 8)), dim3(kBlock), 0, C.stream, M, C.ib_idx, C.ib_w,
                          C.UB, xin, S, C.ibv[0], C.mstride, 0);
       CHECK_LAUNCH();
       std::vector<double> h(3 * C.mstride);
