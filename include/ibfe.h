@@ -243,9 +243,8 @@ int ibfe_step(ibfe_ctx* ctx, int nsteps);
  * grid).  IBFE_ESINGULAR if a point's support holds no free node; IBFE_EINVAL if
  * the points are so dense that a row of G collects more than 1024 support
  * products.  After an error the context refuses to step until a call succeeds.
- * The first call allocates the rebuild buffers (about 100 bytes per support
- * node of every point) and drops captured graphs; it synchronises the stream
- * twice. */
+ * The first call allocates the rebuild buffers (about 1.6 KB per point) and
+ * drops captured graphs; every call synchronises the stream twice. */
 int ibfe_set_points(ibfe_ctx* ctx, const double* X, const double* U_B, int on_device);
 /* Advance until the flow is steady (Section 3.1): after every step, the
  * step-to-step normalised root-mean-square difference of each velocity

@@ -371,6 +371,9 @@ class Solver:
         """Move the Lagrangian points to X (M x 3) with prescribed velocities U_B (None = 0);
         the IB operators are rebuilt on the device.  X and U_B are numpy arrays, or
         contiguous float64 CUDA tensors (read on the library's stream after the caller's)."""
+        self._set_points(X, U_B, load().ibfe_set_points)
+
+    def _set_points(self, X, U_B, fn):
         X, px, dx = self._vec(X, 3 * self.M, "X")
         pb, db = None, dx
         if U_B is not None:
@@ -379,7 +382,7 @@ class Solver:
             raise ValueError("X and U_B must both be host or both be device memory")
         if dx:
             self._after_caller()
-        check(load().ibfe_set_points(self._h, px, pb, dx))
+        check(fn(self._h, px, pb, dx))
 
     def run_steady(self, tol: float, max_steps: int):
         """Step until the step-to-step NRMSE of every velocity component is below tol

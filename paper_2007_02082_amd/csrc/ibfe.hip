@@ -27,8 +27,8 @@
 #include "wss.hpp"
 #include "steady.hpp"
 #include "ib_move.hpp"
+#include "sort_scan.hpp"
 
-#include <hipcub/hipcub.hpp>
 
 using namespace ibfe;
 
@@ -204,10 +204,11 @@ struct ibfe_ctx {
     uint32_t *keys = nullptr, *vals = nullptr, *skeys = nullptr, *svals = nullptr;
     int *flag = nullptr, *pos = nullptr, *counters = nullptr;
     int64_t* cnt = nullptr;
-    void* temp = nullptr;
-    size_t temp_bytes = 0;
-    int64_t g_cap = 0;
+    uint32_t* hist = nullptr;  // radix digit counts, 256 per tile of the pairs
+    void* sums = nullptr;      // tile sums of the scans (8 bytes per tile)
+    int64_t g_cap = 0;         // entries of G the device arrays hold
   } mv;
+  int device = 0;          // HIP device the context was created on
   bool ib_valid = true;  // false after a failed ibfe_set_points
   // ibv[1] holds the force of the last step: the initial guess of the next force
   // solve (the right-hand side U_B - I u* changes little from step to step)
@@ -664,15 +665,23 @@ int setup_device(ibfe_ctx& c) {
     if ((rc = c.upload(&c.ib_idx, P.ib_idx.data(), P.ib_idx.size()))) return rc;
     if ((rc = c.upload(&c.ib_w, P.ib_w.data(), P.ib_w.size()))) return rc;
     if ((rc = c.upload(&c.UB, P.U_B.data(), P.U_B.size()))) return rc;
+    // uniform grids may move their points (ibfe_set_points): the spreading lists
+    // and G are held at their largest sizes from the start (every support pair
+    // free; four times the entries of G at the initial positions, at least 128
+    // per row), so that a rebuild writes them in place
+    const bool movable = !P.refined;
+    const int64_t np = movable ? 64 * M : 0;
+    c.mv.g_cap = movable ? std::max<int64_t>(4 * int64_t(P.G_col.size()), 128 * M) : int64_t(P.G_col.size());
+    const size_t gc = size_t(c.mv.g_cap);
     if ((rc = c.upload(&c.G_ptr, P.G_ptr.data(), P.G_ptr.size()))) return rc;
-    if ((rc = c.upload(&c.G_col, P.G_col.data(), P.G_col.size()))) return rc;
-    if ((rc = c.upload(&c.G_val, P.G_val.data(), P.G_val.size()))) return rc;
+    if ((rc = c.upload(&c.G_col, P.G_col.data(), P.G_col.size(), gc))) return rc;
+    if ((rc = c.upload(&c.G_val, P.G_val.data(), P.G_val.size(), gc))) return rc;
     if ((rc = c.upload(&c.G_diag, P.G_diag.data(), P.G_diag.size()))) return rc;
     if ((rc = c.upload(&c.G_binv, P.G_binv.data(), P.G_binv.size()))) return rc;
-    if ((rc = c.upload(&c.sp_node, P.sp_node.data(), P.sp_node.size()))) return rc;
-    if ((rc = c.upload(&c.sp_ptr, P.sp_ptr.data(), P.sp_ptr.size()))) return rc;
-    if ((rc = c.upload(&c.sp_pt, P.sp_pt.data(), P.sp_pt.size()))) return rc;
-    if ((rc = c.upload(&c.sp_wt, P.sp_w.data(), P.sp_w.size()))) return rc;
+    if ((rc = c.upload(&c.sp_node, P.sp_node.data(), P.sp_node.size(), size_t(np)))) return rc;
+    if ((rc = c.upload(&c.sp_ptr, P.sp_ptr.data(), P.sp_ptr.size(), size_t(np + 1)))) return rc;
+    if ((rc = c.upload(&c.sp_pt, P.sp_pt.data(), P.sp_pt.size(), size_t(np)))) return rc;
+    if ((rc = c.upload(&c.sp_wt, P.sp_w.data(), P.sp_w.size(), size_t(np)))) return rc;
     c.n_sp = int(P.sp_node.size());
     for (int i = 0; i < 7; ++i) {
       void* base = nullptr;
@@ -2480,6 +2489,7 @@ int ibfe_create(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* par
   int rc = build_plan(grid, ib, params, inlet, c->plan, err);
   if (rc) return fail(rc, err);
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  if (hipGetDevice(&c->device) != hipSuccess) return fail(IBFE_EHIP, "hipGetDevice failed");
   if (alloc && alloc->alloc && alloc->free) {
     c->alloc = *alloc;
     c->user_alloc = true;
@@ -2532,57 +2542,109 @@ int ibfe_step(ibfe_ctx* c, int nsteps) {
   return IBFE_OK;
 }
 
+}  // extern "C"
+
 namespace {
 
-// Buffers of the device rebuild of the IB operators (first ibfe_set_points): the
-// pair arrays of the sort, scan scratch, and the spreading lists and G at their
-// largest sizes.  The captured graphs hold the old G pointers: they are dropped.
-int setup_moving(ibfe_ctx& C) {
-  const Plan& P = C.plan;
-  const int64_t M = P.M;
+// Scratch of one device rebuild of the IB operators for M points (np = 64 M
+// support pairs): the positions, the (node, slot) pairs and their sorted copies,
+// segment flags and positions, counters, the row lengths of G and the scan/sort
+// work arrays.  Every section starts on a 256-byte boundary.
+struct RebuildBufs {
+  double* X = nullptr;
+  uint32_t *keys = nullptr, *vals = nullptr, *skeys = nullptr, *svals = nullptr;
+  int *flag = nullptr, *pos = nullptr, *counters = nullptr;
+  int64_t* cnt = nullptr;
+  uint32_t* hist = nullptr;
+  void* sums = nullptr;
+};
+
+// Byte offsets of the sections (base may be null: then only the size is wanted).
+size_t rebuild_layout(int64_t M, char* base, RebuildBufs* out) {
   const int64_t np = 64 * M;
-  if (np > int64_t(INT32_MAX) - 1) return fail(IBFE_EINVAL, "too many Lagrangian points to move");
-  auto& mv = C.mv;
+  const int nb = scan_tiles(np);
+  const int64_t sums_tiles = std::max<int64_t>({int64_t(scan_tiles(int64_t(kRadixBins) * nb)), int64_t(nb),
+                                                int64_t(scan_tiles(M + 1)), int64_t(1)});
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~size_t(255);
+    return base ? base + o : nullptr;
+  };
+  RebuildBufs b;
+  b.X = reinterpret_cast<double*>(take(sizeof(double) * 3 * M));
+  b.keys = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * np));
+  b.vals = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * np));
+  b.skeys = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * np));
+  b.svals = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * np));
+  b.flag = reinterpret_cast<int*>(take(sizeof(int) * np));
+  b.pos = reinterpret_cast<int*>(take(sizeof(int) * np));
+  b.counters = reinterpret_cast<int*>(take(sizeof(int) * 8));
+  b.cnt = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * (M + 1)));
+  b.hist = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kRadixBins * size_t(nb)));
+  b.sums = take(sizeof(int64_t) * size_t(sums_tiles));
+  if (out) *out = b;
+  return off;
+}
+
+// Exclusive prefix sums of n values (in may be out); sums holds scan_tiles(n) values.
+template <typename T>
+int exclusive_scan(ibfe_ctx& c, const T* in, T* out, int64_t n, T* sums) {
+  const int nb = scan_tiles(n);
+  if (nb == 0) return IBFE_OK;
+  klaunch<k_tile_sums<T>>(c, dim3(nb), dim3(kBlock), 0, c.stream, in, n, sums);
+  klaunch<k_scan_sums<T>>(c, dim3(1), dim3(kBlock), 0, c.stream, sums, nb);
+  klaunch<k_scan_tiles<T>>(c, dim3(nb), dim3(kBlock), 0, c.stream, in, out, n, (const T*)sums);
+  CHECK_LAUNCH();
+  return IBFE_OK;
+}
+
+// Stable sort of n (key, value) pairs by the low `bits` bits of the key, 8 bits per
+// pass; k0/v0 are overwritten, the result ends in k1/v1.
+int radix_sort_pairs(ibfe_ctx& c, uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n, int bits,
+                     uint32_t* hist, uint32_t* sums) {
+  const int nb = scan_tiles(n);
+  if (nb == 0) return IBFE_OK;
+  const int passes = std::max(1, (bits + 7) / 8);
+  uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
+  int rc;
+  for (int p = 0; p < passes; ++p) {
+    klaunch<k_rs_hist>(c, dim3(nb), dim3(kBlock), 0, c.stream, (const uint32_t*)ki, n, 8 * p, hist, nb);
+    if ((rc = exclusive_scan<uint32_t>(c, hist, hist, int64_t(kRadixBins) * nb, sums))) return rc;
+    klaunch<k_rs_scatter>(c, dim3(nb), dim3(kBlock), 0, c.stream, (const uint32_t*)ki, (const uint32_t*)vi, ko, vo,
+                          n, 8 * p, (const uint32_t*)hist, nb);
+    CHECK_LAUNCH();
+    std::swap(ki, ko);
+    std::swap(vi, vo);
+  }
+  if (ki != k1) {
+    HIP_TRY(hipMemcpyAsync(k1, ki, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, c.stream));
+    HIP_TRY(hipMemcpyAsync(v1, vi, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, c.stream));
+  }
+  return IBFE_OK;
+}
+
+// Rebuild buffers of ibfe_set_points, allocated on its first call.  The captured
+// graphs are dropped: they may have been captured before the first rebuild.
+int setup_moving(ibfe_ctx& C) {
+  const int64_t M = C.plan.M;
   void* b = nullptr;
   int rc;
-  auto take = [&](size_t bytes, void** out) { return C.dalloc(out, bytes); };
-  if ((rc = take(sizeof(double) * 3 * M, &b))) return rc;
-  mv.X = static_cast<double*>(b);
-  uint32_t** u32[4] = {&mv.keys, &mv.vals, &mv.skeys, &mv.svals};
-  for (auto p : u32) {
-    if ((rc = take(sizeof(uint32_t) * np, &b))) return rc;
-    *p = static_cast<uint32_t*>(b);
-  }
-  if ((rc = take(sizeof(int) * np, &b))) return rc;
-  mv.flag = static_cast<int*>(b);
-  if ((rc = take(sizeof(int) * np, &b))) return rc;
-  mv.pos = static_cast<int*>(b);
-  if ((rc = take(sizeof(int) * 8, &b))) return rc;
-  mv.counters = static_cast<int*>(b);
-  if ((rc = take(sizeof(int64_t) * (M + 1), &b))) return rc;  // cnt[M] stays 0
-  mv.cnt = static_cast<int64_t*>(b);
-  // spreading lists at their largest size (every support pair free)
-  if ((rc = take(sizeof(int32_t) * np, &b))) return rc;
-  C.sp_node = static_cast<int32_t*>(b);
-  if ((rc = take(sizeof(int64_t) * (np + 1), &b))) return rc;
-  C.sp_ptr = static_cast<int64_t*>(b);
-  if ((rc = take(sizeof(int32_t) * np, &b))) return rc;
-  C.sp_pt = static_cast<int32_t*>(b);
-  if ((rc = take(sizeof(double) * np, &b))) return rc;
-  C.sp_wt = static_cast<double*>(b);
-  // G: room for four times the entries at the initial positions, at least 128 per row
-  mv.g_cap = std::max<int64_t>(4 * int64_t(P.G_col.size()), 128 * M);
-  if ((rc = take(sizeof(int32_t) * mv.g_cap, &b))) return rc;
-  C.G_col = static_cast<int32_t*>(b);
-  if ((rc = take(sizeof(double) * mv.g_cap, &b))) return rc;
-  C.G_val = static_cast<double*>(b);
-  size_t b1 = 0, b2 = 0, b3 = 0;
-  HIP_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, b1, mv.keys, mv.skeys, mv.vals, mv.svals, int(np), 0, 32,
-                                             C.stream));
-  HIP_TRY(hipcub::DeviceScan::ExclusiveSum(nullptr, b2, mv.flag, mv.pos, int(np), C.stream));
-  HIP_TRY(hipcub::DeviceScan::ExclusiveSum(nullptr, b3, mv.cnt, C.G_ptr, int(M + 1), C.stream));
-  mv.temp_bytes = std::max(b1, std::max(b2, b3));
-  if ((rc = take(std::max<size_t>(mv.temp_bytes, 256), &mv.temp))) return rc;
+  if ((rc = C.dalloc(&b, rebuild_layout(M, nullptr, nullptr)))) return rc;
+  RebuildBufs r;
+  rebuild_layout(M, static_cast<char*>(b), &r);
+  auto& mv = C.mv;
+  mv.X = r.X;
+  mv.keys = r.keys;
+  mv.vals = r.vals;
+  mv.skeys = r.skeys;
+  mv.svals = r.svals;
+  mv.flag = r.flag;
+  mv.pos = r.pos;
+  mv.counters = r.counters;
+  mv.cnt = r.cnt;
+  mv.hist = r.hist;
+  mv.sums = r.sums;
   HIP_TRY(hipStreamSynchronize(C.stream));
   for (auto& kv : C.graph_cache) (void)hipGraphExecDestroy(kv.second);
   C.graph_cache.clear();
@@ -2590,87 +2652,111 @@ int setup_moving(ibfe_ctx& C) {
   return IBFE_OK;
 }
 
-}  // namespace
-
-int ibfe_set_points(ibfe_ctx* c, const double* X, const double* U_B, int on_device) {
-  if (!c || !X) return fail(IBFE_EINVAL, "NULL argument");
-  ibfe_ctx& C = *c;
+// The device rebuild for new positions X (and velocities U_B, NULL = 0) into the
+// context's IB operators, with the scratch B: stencils of Eq. 17, the spreading
+// lists (pairs sorted by node), G = I_F I_F^T row by row and its block inverses.
+// Synchronises the stream twice (error counts, the size of G).
+int rebuild_points(ibfe_ctx& C, const RebuildBufs& B, const double* X, const double* U_B, int on_device) {
   const Plan& P = C.plan;
   const int64_t M = P.M;
-  if (M == 0) return IBFE_OK;
-  if (P.refined) return fail(IBFE_EINVAL, "moving Lagrangian points are supported on uniform grids only");
-  if (!on_device) {
-    for (int64_t q = 0; q < 3 * M; ++q)
-      if (!std::isfinite(X[q]) || (U_B && !std::isfinite(U_B[q])))
-        return fail(IBFE_EINVAL, "X and U_B must be finite");
-  }
-  int rc;
-  if (!C.mv.ready && (rc = setup_moving(C))) return rc;
-  auto& mv = C.mv;
   C.ib_valid = false;
   const size_t bytes = sizeof(double) * 3 * size_t(M);
   const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-  HIP_TRY(hipMemcpyAsync(mv.X, X, bytes, kind, C.stream));
+  HIP_TRY(hipMemcpyAsync(B.X, X, bytes, kind, C.stream));
   if (U_B)
     HIP_TRY(hipMemcpyAsync(C.UB, U_B, bytes, kind, C.stream));
   else
-    HIP_TRY(hipMemsetAsync(C.UB, 0, bytes, C.stream));
-  HIP_TRY(hipMemsetAsync(mv.counters, 0, sizeof(int) * 8, C.stream));
+    klaunch<k_fill_f64>(C, dim3(blocks_lin(3 * M)), dim3(kBlock), 0, C.stream, C.UB, int64_t(3 * M), 0.0);
+  klaunch<k_fill_i32>(C, dim3(1), dim3(kBlock), 0, C.stream, B.counters, int64_t(8), 0);
   const int64_t np = 64 * M;
   const uint32_t N = uint32_t(P.N);
   GridGeom g{P.origin[0], P.origin[1], P.origin[2], P.h, P.nx, P.ny, P.nz, P.sy, P.sz};
-  klaunch<k_ib_stencil>(C, dim3(blocks_lin(M)), dim3(kBlock), 0, C.stream, int(M), g,
-                     (const double*)mv.X, (const uint8_t*)C.flags, N, C.ib_idx, C.ib_w, mv.keys, mv.vals,
-                     mv.counters);
+  klaunch<k_ib_stencil>(C, dim3(blocks_lin(M)), dim3(kBlock), 0, C.stream, int(M), g, (const double*)B.X,
+                        (const uint8_t*)C.flags, N, C.ib_idx, C.ib_w, B.keys, B.vals, B.counters);
   CHECK_LAUNCH();
   int bits = 1;
   while (bits < 32 && (uint64_t(1) << bits) <= uint64_t(N)) ++bits;
-  size_t tb = mv.temp_bytes;
-  HIP_TRY(hipcub::DeviceRadixSort::SortPairs(mv.temp, tb, mv.keys, mv.skeys, mv.vals, mv.svals, int(np), 0, bits,
-                                             C.stream));
+  int rc;
+  if ((rc = radix_sort_pairs(C, B.keys, B.vals, B.skeys, B.svals, np, bits, B.hist,
+                             static_cast<uint32_t*>(B.sums))))
+    return rc;
   const int nbp = int((np + kBlock - 1) / kBlock);
-  klaunch<k_sp_flags>(C, dim3(nbp), dim3(kBlock), 0, C.stream, np, (const uint32_t*)mv.skeys, N,
-                     mv.flag);
+  klaunch<k_sp_flags>(C, dim3(nbp), dim3(kBlock), 0, C.stream, np, (const uint32_t*)B.skeys, N, B.flag);
   CHECK_LAUNCH();
-  tb = mv.temp_bytes;
-  HIP_TRY(hipcub::DeviceScan::ExclusiveSum(mv.temp, tb, mv.flag, mv.pos, int(np), C.stream));
-  klaunch<k_sp_fill>(C, dim3(nbp), dim3(kBlock), 0, C.stream, np, int(M), (const uint32_t*)mv.skeys,
-                     (const uint32_t*)mv.svals, N, (const int*)mv.flag, (const int*)mv.pos,
-                     (const double*)C.ib_w, C.sp_node, C.sp_ptr, C.sp_pt, C.sp_wt, mv.counters);
+  if ((rc = exclusive_scan<int>(C, B.flag, B.pos, np, static_cast<int*>(B.sums)))) return rc;
+  klaunch<k_sp_fill>(C, dim3(nbp), dim3(kBlock), 0, C.stream, np, int(M), (const uint32_t*)B.skeys,
+                     (const uint32_t*)B.svals, N, (const int*)B.flag, (const int*)B.pos, (const double*)C.ib_w,
+                     C.sp_node, C.sp_ptr, C.sp_pt, C.sp_wt, B.counters);
   CHECK_LAUNCH();
   int hc[8];
-  HIP_TRY(hipMemcpyAsync(hc, mv.counters, sizeof(hc), hipMemcpyDeviceToHost, C.stream));
+  HIP_TRY(hipMemcpyAsync(hc, B.counters, sizeof(hc), hipMemcpyDeviceToHost, C.stream));
   HIP_TRY(hipStreamSynchronize(C.stream));
   if (hc[0] > 0)
     return fail(IBFE_ESINGULAR, std::to_string(hc[0]) + " Lagrangian point(s) without a free support node");
   const int64_t nvalid = hc[3];
-  klaunch<(k_gram_rows<false>)>(C, dim3(unsigned(M)), dim3(64), 0, C.stream, int(M),
-                     (const int32_t*)C.ib_idx, (const double*)C.ib_w, (const uint8_t*)C.flags,
-                     (const uint32_t*)mv.skeys, nvalid, (const int32_t*)C.sp_pt, (const double*)C.sp_wt, mv.cnt,
-                     (const int64_t*)nullptr, (int32_t*)nullptr, (double*)nullptr, (double*)nullptr,
-                     mv.counters);
+  klaunch<(k_gram_rows<false>)>(C, dim3(unsigned(M)), dim3(64), 0, C.stream, int(M), (const int32_t*)C.ib_idx,
+                                (const double*)C.ib_w, (const uint8_t*)C.flags, (const uint32_t*)B.skeys, nvalid,
+                                (const int32_t*)C.sp_pt, (const double*)C.sp_wt, B.cnt, (const int64_t*)nullptr,
+                                (int32_t*)nullptr, (double*)nullptr, (double*)nullptr, B.counters);
   CHECK_LAUNCH();
-  tb = mv.temp_bytes;
-  HIP_TRY(hipcub::DeviceScan::ExclusiveSum(mv.temp, tb, mv.cnt, C.G_ptr, int(M + 1), C.stream));
+  if ((rc = exclusive_scan<int64_t>(C, B.cnt, C.G_ptr, M + 1, static_cast<int64_t*>(B.sums)))) return rc;
   int64_t nnz = 0;
   HIP_TRY(hipMemcpyAsync(&nnz, C.G_ptr + M, sizeof(int64_t), hipMemcpyDeviceToHost, C.stream));
-  HIP_TRY(hipMemcpyAsync(hc, mv.counters, sizeof(hc), hipMemcpyDeviceToHost, C.stream));
+  HIP_TRY(hipMemcpyAsync(hc, B.counters, sizeof(hc), hipMemcpyDeviceToHost, C.stream));
   HIP_TRY(hipStreamSynchronize(C.stream));
   if (hc[1] > 0)
     return fail(IBFE_EINVAL, "a Lagrangian point overlaps more than " + std::to_string(kGramCap) +
                                  " support products: the points are too dense");
-  if (nnz > mv.g_cap) return fail(IBFE_ENOMEM, "the force system exceeds its capacity");
-  klaunch<(k_gram_rows<true>)>(C, dim3(unsigned(M)), dim3(64), 0, C.stream, int(M),
-                     (const int32_t*)C.ib_idx, (const double*)C.ib_w, (const uint8_t*)C.flags,
-                     (const uint32_t*)mv.skeys, nvalid, (const int32_t*)C.sp_pt, (const double*)C.sp_wt,
-                     (int64_t*)nullptr, (const int64_t*)C.G_ptr, C.G_col, C.G_val, C.G_diag, mv.counters);
+  if (nnz > C.mv.g_cap) return fail(IBFE_ENOMEM, "the force system exceeds its capacity");
+  klaunch<(k_gram_rows<true>)>(C, dim3(unsigned(M)), dim3(64), 0, C.stream, int(M), (const int32_t*)C.ib_idx,
+                               (const double*)C.ib_w, (const uint8_t*)C.flags, (const uint32_t*)B.skeys, nvalid,
+                               (const int32_t*)C.sp_pt, (const double*)C.sp_wt, (int64_t*)nullptr,
+                               (const int64_t*)C.G_ptr, C.G_col, C.G_val, C.G_diag, B.counters);
   const int nblk = int((M + kIBBlock - 1) / kIBBlock);
   klaunch<k_gram_block_inv>(C, dim3(nblk), dim3(kBlock), 0, C.stream, int(M), (const int64_t*)C.G_ptr,
-                     (const int32_t*)C.G_col, (const double*)C.G_val, C.G_binv);
+                            (const int32_t*)C.G_col, (const double*)C.G_val, C.G_binv);
   CHECK_LAUNCH();
   C.n_sp = hc[2];
   C.ib_valid = true;
   return IBFE_OK;
+}
+
+int check_points(const ibfe_ctx& C, const double* X, const double* U_B, int on_device) {
+  const Plan& P = C.plan;
+  if (P.refined) return fail(IBFE_EINVAL, "moving Lagrangian points are supported on uniform grids only");
+  if (64 * P.M > int64_t(INT32_MAX) - 1) return fail(IBFE_EINVAL, "too many Lagrangian points to move");
+  if (!on_device) {
+    for (int64_t q = 0; q < 3 * P.M; ++q)
+      if (!std::isfinite(X[q]) || (U_B && !std::isfinite(U_B[q])))
+        return fail(IBFE_EINVAL, "X and U_B must be finite");
+  }
+  return IBFE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ibfe_set_points(ibfe_ctx* c, const double* X, const double* U_B, int on_device) {
+  if (!c || !X) return fail(IBFE_EINVAL, "NULL argument");
+  ibfe_ctx& C = *c;
+  if (C.plan.M == 0) return IBFE_OK;
+  int rc;
+  if ((rc = check_points(C, X, U_B, on_device))) return rc;
+  if (!C.mv.ready && (rc = setup_moving(C))) return rc;
+  RebuildBufs B;
+  B.X = C.mv.X;
+  B.keys = C.mv.keys;
+  B.vals = C.mv.vals;
+  B.skeys = C.mv.skeys;
+  B.svals = C.mv.svals;
+  B.flag = C.mv.flag;
+  B.pos = C.mv.pos;
+  B.counters = C.mv.counters;
+  B.cnt = C.mv.cnt;
+  B.hist = C.mv.hist;
+  B.sums = C.mv.sums;
+  return rebuild_points(C, B, X, U_B, on_device);
 }
 
 int ibfe_run_steady(ibfe_ctx* c, double tol, int64_t max_steps, int64_t* steps, double* nrmse) {
