@@ -246,6 +246,20 @@ int ibfe_step(ibfe_ctx* ctx, int nsteps);
  * The first call allocates the rebuild buffers (about 1.6 KB per point) and
  * drops captured graphs; every call synchronises the stream twice. */
 int ibfe_set_points(ibfe_ctx* ctx, const double* X, const double* U_B, int on_device);
+/* ibfe_set_points for callers that cannot allocate device memory (code under HIP
+ * graph capture, allocation-free time loops): the same rebuild with the same
+ * results, its scratch (positions, sorted support pairs, scan and sort work,
+ * counters: about 1.6 KB per point) taken from a 32 MiB array that the library
+ * holds per GPU for the life of the process, instead of buffers allocated on the
+ * first call.  The context's spreading lists and G are preallocated at
+ * ibfe_create, so nothing is allocated here.  IBFE_EINVAL if the points need more
+ * scratch than the array holds (M > ibfe_set_points_noalloc_max_points()).  Every
+ * call on one GPU uses the same array: calls that overlap on a GPU (other
+ * threads, other streams) race and must be serialised by the caller.  The
+ * stream is synchronised twice, as in ibfe_set_points. */
+int ibfe_set_points_noalloc(ibfe_ctx* ctx, const double* X, const double* U_B, int on_device);
+/* Largest number of Lagrangian points ibfe_set_points_noalloc accepts. */
+int64_t ibfe_set_points_noalloc_max_points(void);
 /* Advance until the flow is steady (Section 3.1): after every step, the
  * step-to-step normalised root-mean-square difference of each velocity
  * component d,

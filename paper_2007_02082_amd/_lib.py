@@ -102,6 +102,8 @@ SIGNATURES = {
     "ibfe_step": (C.c_int, [C.c_void_p, C.c_int]),
     "ibfe_run_steady": (C.c_int, [C.c_void_p, C.c_double, C.c_int64, C.c_void_p, C.c_void_p]),
     "ibfe_set_points": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "ibfe_set_points_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "ibfe_set_points_noalloc_max_points": (C.c_int64, []),
     "ibfe_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, dp, C.c_int]),
     "ibfe_get_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
     "ibfe_checkpoint_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
@@ -366,6 +368,15 @@ class Solver:
 
     def step(self, n: int = 1):
         check(load().ibfe_step(self._h, int(n)))
+
+    def set_points_noalloc(self, X, U_B=None):
+        """set_points without device allocation: the rebuild's scratch comes from the
+        library's per-GPU static array (at most set_points_noalloc_max_points() points)."""
+        self._set_points(X, U_B, load().ibfe_set_points_noalloc)
+
+    @staticmethod
+    def set_points_noalloc_max_points() -> int:
+        return int(load().ibfe_set_points_noalloc_max_points())
 
     def set_points(self, X, U_B=None):
         """Move the Lagrangian points to X (M x 3) with prescribed velocities U_B (None = 0);

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -2733,6 +2734,35 @@ int check_points(const ibfe_ctx& C, const double* X, const double* U_B, int on_d
   return IBFE_OK;
 }
 
+// The allocation-free rebuild takes its scratch from this array (one copy per
+// device, held until the process ends); host code uses the per-device address
+// from hipGetSymbolAddress, never the array's name.
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of this device's scratch array (looked up once per device, with that
+// device current).
+int scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(IBFE_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != device) HIP_TRY(hipSetDevice(device));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) HIP_TRY(hipSetDevice(cur));
+    if (e != hipSuccess || !p)
+      return fail(IBFE_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return IBFE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2757,6 +2787,36 @@ int ibfe_set_points(ibfe_ctx* c, const double* X, const double* U_B, int on_devi
   B.hist = C.mv.hist;
   B.sums = C.mv.sums;
   return rebuild_points(C, B, X, U_B, on_device);
+}
+
+int ibfe_set_points_noalloc(ibfe_ctx* c, const double* X, const double* U_B, int on_device) {
+  if (!c || !X) return fail(IBFE_EINVAL, "NULL argument");
+  ibfe_ctx& C = *c;
+  const int64_t M = C.plan.M;
+  if (M == 0) return IBFE_OK;
+  int rc;
+  if ((rc = check_points(C, X, U_B, on_device))) return rc;
+  const size_t need = rebuild_layout(M, nullptr, nullptr);
+  if (need > kNoAllocScratchBytes)
+    return fail(IBFE_EINVAL, "ibfe_set_points_noalloc: " + std::to_string(M) + " points need " +
+                                 std::to_string(need) + " bytes of scratch, more than its " +
+                                 std::to_string(kNoAllocScratchBytes) + " (at most " +
+                                 std::to_string(ibfe_set_points_noalloc_max_points()) + " points)");
+  void* base = nullptr;
+  if ((rc = scratch_address(C.device, &base))) return rc;
+  RebuildBufs B;
+  rebuild_layout(M, static_cast<char*>(base), &B);
+  return rebuild_points(C, B, X, U_B, on_device);
+}
+
+int64_t ibfe_set_points_noalloc_max_points(void) {
+  int64_t lo = 0, hi = int64_t(kNoAllocScratchBytes);
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) / 2;
+    if (rebuild_layout(mid, nullptr, nullptr) <= kNoAllocScratchBytes) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
 }
 
 int ibfe_run_steady(ibfe_ctx* c, double tol, int64_t max_steps, int64_t* steps, double* nrmse) {
