@@ -259,6 +259,9 @@ struct ibfe_ctx {
   float* extra32 = nullptr;
 
   FormCoefs fc{};
+  // lower end of the Chebyshev interval of the mass correction on a refined
+  // lattice (the proven bound, or the Lanczos estimate when it is larger)
+  double mass_lmin = 0.125;
   double t = 0.0;
   int64_t steps = 0;
   ibfe_stats stats{};
@@ -782,7 +785,7 @@ int launch_q(ibfe_ctx& c, const Op& op, NodeList nl, const T* p, T* q, const KSc
 }
 template <typename T, int NC>
 int launch_q(ibfe_ctx& c, const OpSym<T, NC>& op, NodeList, const T* p, T* q, const KScal* sc) {
-  const int nr = red_blocks(c.nzitems);
+  const int nr = red_blocks(c.nzitems * NC);
   ZOp<T> z{op.emask, op.flags, op.rowbit, op.sy, op.sz, c.plan.nz + 1,
            {op.c[0], op.c[1], op.c[2], op.c[3]}, c.zb, c.zlanes};
   klaunch<(k_cg_q_zb<T, NC>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems, c.nzitems, z,
@@ -1003,7 +1006,7 @@ int ir_residual(ibfe_ctx& c, const Op64& op, const double* b, double* x, TR* r32
     z.lanes = c.zlanes;
     z.zb = c.zb;
     for (int t = 0; t < 4; ++t) z.c[t] = op.c[t];
-    nr = red_blocks(c.nzitems);
+    nr = red_blocks(c.nzitems * Op64::kNC);
     klaunch<(k_zb_residual<TR, Op64::kNC>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
                        c.nzitems, z, b, (const double*)x, r32, op.stride, c.partials);
   } else {
@@ -1276,7 +1279,7 @@ int run_cheb_gen(ibfe_ctx& c, const Op& op, const T* b, T* x, T* xalt, T* d, int
   T* alt = cur == x ? xalt : x;
   klaunch<(k_cheb0_gen<T, Op>)>(c, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
                      c.nl, op, b, d, cur, T(1.0 / theta), (const KScal*)nullptr);
-  const int nr = red_blocks(c.nzitems);
+  const int nr = red_blocks(c.nzitems * Op::kNC);
   const ZOp<T> zop = zcomp_op(c, op);
   int rc;
   T* const cur0 = cur;
@@ -1291,9 +1294,11 @@ int run_cheb_gen(ibfe_ctx& c, const Op& op, const T* b, T* x, T* xalt, T* d, int
       if ((rc2 = pre_apply(c, op, cur, (const KScal*)nullptr))) return rc2;
       constexpr int NC = Op::kNC;
       launch_extra<T, NC>(c, op, cur, (const KScal*)nullptr);
+      // the first step writes the zeros off the rows into the second buffer (the
+      // zero-start step did so for the first one and for d, over every active node)
       klaunch<(k_zb_cheb<T, false, NC>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
                                          c.nzitems, zop, (const T*)cur, b, d, alt, c1, c2, c.partials,
-                                         (const KScal*)nullptr, op.stride, 1);
+                                         (const KScal*)nullptr, op.stride, k == 1 ? 1 : 0);
       std::swap(cur, alt);
     }
     CHECK_LAUNCH();
@@ -1662,7 +1667,7 @@ int run_cheb_mass(ibfe_ctx& c, const T* b, T* x, T* xalt, T* d, int iters) {
   klaunch<(k_mg_cheb0<T, 3>)>(c, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
                      c.nl, (const uint8_t*)c.emask, (const uint8_t*)c.flags,
                      T(c.fc.m[0]), T(1.0 / theta), b, d, cur, (const KScal*)nullptr, kFlagF, c.stride);
-  const int nr = red_blocks(c.nzitems);
+  const int nr = red_blocks(c.nzitems * 3);
   T* const cur0 = cur;
   T* const alt0 = alt;
   auto body = [&]() -> int {
@@ -2254,7 +2259,7 @@ int step_once_refined(ibfe_ctx& c) {
     if ((rc = fill_hanging<double>(c, c.phi, 1))) return rc;
     if ((rc = comp_rows<double>(c, grad_elem(c, c.phi), kFlagF, 0u, 1.0, b4))) return rc;
     auto op = csym_op<double, 3>(c, 1.0, 0.0, kFlagF, c.dinvM64);
-    const double lmin = P.mass_lmin, lmax = kMassLmax;
+    const double lmin = c.mass_lmin, lmax = kMassLmax;
     SolveOut so;
     if (!c.delta_warm) klaunch<k_zero<double>>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, delta, 3, S);
     c.delta_warm = false;
@@ -2401,6 +2406,80 @@ int apply_refined(ibfe_ctx& C, int op, int precision, double* xin, double* yout,
   }
 }
 
+// Smallest eigenvalue of D'^-1 C^T M C on the free rows of a refined lattice, by
+// Lanczos: preconditioned CG on the FP64 composite mass from a pseudo-random
+// right-hand side; its step lengths alpha_j and ratios beta_j give the Lanczos
+// tridiagonal of the Jacobi-scaled operator (diagonal 1/alpha_j +
+// beta_{j-1}/alpha_{j-1}, off-diagonal sqrt(beta_j)/alpha_j), whose smallest
+// eigenvalue (bisection on the Sturm sequence) is a Ritz value and so lies
+// above the true one.  The mass correction's Chebyshev interval starts at 0.9 of
+// it, never below the proven bound (1/8) min a_nn / D'(n): error components
+// below the interval are reduced less but not amplified, and the FP64
+// refinement measures the true residual.
+int estimate_mass_lmin(ibfe_ctx& c) {
+  const Plan& P = c.plan;
+  c.mass_lmin = P.mass_lmin;
+  if (!P.refined || P.n_free == 0) return IBFE_OK;
+  constexpr int kLanczos = 40;
+  auto op = csym_op<double, 1>(c, 1.0, 0.0, kFlagF, c.dinvM64);
+  double *b = c.w[0], *x = c.w[1], *r = c.w[2], *p = c.w[3], *q = c.w[4];
+  const NodeList nl = c.nl;
+  const int nb = blocks_for(nl.n), nr = red_blocks(nl.n);
+  KScal* sc = &c.scal[kScMisc];
+  klaunch<k_fill_hash>(c, dim3(nb), dim3(kBlock), 0, c.stream, nl, (const uint8_t*)c.flags, kFlagF, b);
+  klaunch<(k_cg_init<double, decltype(op)>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, nl, op, (const double*)b, x,
+                                              r, p, c.partials, 1);
+  klaunch<k_fin_cg_init>(c, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr, sc, 0.0,
+                         kLanczos);
+  CHECK_LAUNCH();
+  std::vector<double> alpha, beta;
+  for (int j = 0; j < kLanczos; ++j) {
+    int rc;
+    if ((rc = pre_apply(c, op, p, (const KScal*)sc))) return rc;
+    const int nq = launch_q<double>(c, op, nl, p, q, (const KScal*)sc);
+    klaunch<k_fin_cg_q>(c, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nq, sc);
+    klaunch<(k_cg_xr<double, decltype(op)>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, nl, op, x, r,
+                                             (const double*)p, (const double*)q, c.partials, (const KScal*)sc);
+    klaunch<k_fin_cg_xr>(c, dim3(1), dim3(kBlock), 0, c.stream, (const double*)c.partials, nr, sc);
+    klaunch<(k_cg_p<double, decltype(op)>)>(c, dim3(nb), dim3(kBlock), 0, c.stream, nl, op, (const double*)r, p,
+                                            (const KScal*)sc);
+    CHECK_LAUNCH();
+    KScal s{};
+    if ((rc = poll(c, kScMisc, s))) return rc;
+    if (s.status != 0 || !(s.alpha > 0.0) || !std::isfinite(s.beta)) break;
+    alpha.push_back(s.alpha);
+    beta.push_back(s.beta);
+    if (s.done) break;
+  }
+  const int k = int(alpha.size());
+  if (k < 8) return IBFE_OK;  // too few steps for an estimate: keep the bound
+  std::vector<double> d(k), e(k, 0.0);
+  for (int j = 0; j < k; ++j) {
+    d[j] = 1.0 / alpha[j] + (j > 0 ? beta[j - 1] / alpha[j - 1] : 0.0);
+    if (j + 1 < k) e[j] = std::sqrt(beta[j]) / alpha[j];
+  }
+  // number of eigenvalues of the tridiagonal below s (Sturm sequence)
+  auto below = [&](double s) {
+    int cnt = 0;
+    double qv = 1.0;
+    for (int j = 0; j < k; ++j) {
+      qv = d[j] - s - (j > 0 ? e[j - 1] * e[j - 1] / qv : 0.0);
+      if (qv == 0.0) qv = -1e-300;
+      if (qv < 0.0) ++cnt;
+    }
+    return cnt;
+  };
+  double lo = 0.0, hi = kMassLmax * 2.0;
+  for (int it = 0; it < 100; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (below(mid) >= 1) hi = mid;
+    else lo = mid;
+  }
+  const double ritz = 0.5 * (lo + hi);
+  if (ritz > 0.0 && ritz < 1.0) c.mass_lmin = std::max(P.mass_lmin, 0.9 * ritz);
+  return IBFE_OK;
+}
+
 int copy_in(ibfe_ctx& c, double* dense, int nc, const double* src, int on_device) {
   const int64_t n = c.nP;
   const double* comp = src;
@@ -2496,6 +2575,7 @@ int ibfe_create(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* par
     c->user_alloc = true;
   }
   if ((rc = setup_device(*c))) return rc;
+  if ((rc = estimate_mass_lmin(*c))) return rc;
   *out = c.release();
   return IBFE_OK;
 }

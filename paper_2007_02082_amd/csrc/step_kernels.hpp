@@ -386,6 +386,19 @@ __global__ __launch_bounds__(kBlock) void k_zero(NodeList nl,
   for (int d = 0; d < nc; ++d) x[d * stride + n] = T(0);
 }
 
+// x = a fixed pseudo-random value in [-1, 1) on rows (a hash of the node id), 0
+// elsewhere: a start vector with every spectral component present
+__global__ __launch_bounds__(kBlock) void k_fill_hash(NodeList nl, const uint8_t* __restrict__ flags,
+                                                      uint32_t rowbit, double* __restrict__ x) {
+  const int n = chunk_node(nl);
+  if (n < 0) return;
+  uint32_t h = uint32_t(n) * 2654435761u;
+  h ^= h >> 16;
+  h *= 2246822519u;
+  h ^= h >> 13;
+  x[n] = (flags[n] & rowbit) ? double(h) * (2.0 / 4294967296.0) - 1.0 : 0.0;
+}
+
 // x += TO(d) on rows (mixed precision update of an FP64 iterate by an FP32 correction)
 template <typename TD>
 __global__ __launch_bounds__(kBlock) void k_add_correction(NodeList nl,

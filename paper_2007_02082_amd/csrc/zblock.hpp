@@ -38,24 +38,33 @@ struct ZOp {
   const T* extra = nullptr;
 };
 
-// Walk the column items of this block; epi(node, lane_ok, row, emask, Ax, x_centre).
-// The 3-plane window slides through a ring of kZBPF + 3 planes: the row loads of
+// Walk the column items of this block.  The 3-plane window slides through a ring of kZBPF + 3 planes: the row loads of
 // the plane kZBPF + 1 steps ahead are issued before the current output is formed,
 // so each wavefront keeps 9 (kZBPF + 1) row loads in flight while computing, and
 // the window takes 9 (kZBPF + 3) registers instead of 9 (kZB + 2) (more waves per
 // SIMD to hide the memory latency).
 constexpr int kZBPF = 2;
 
-template <typename T, class Epi>
+// NC components (planes of `stride`) are separate work units: unit u is item
+// u / NC, component u % NC, so that the launch spreads NC times as many equal
+// units over the wavefronts (one unit per wavefront at a time; with one unit per
+// item the last round of items leaves most of the chip idle) and the components
+// of an item run close together (its cell bits and flags stay in the caches).
+// epi(component, node, lane_ok, row, emask, Ax, x_centre, extra_row).
+template <typename T, int NC, class Epi>
 __device__ __forceinline__ void zb_walk(const int* __restrict__ items, int nitems, const ZOp<T>& op,
-                                        const T* __restrict__ x, Epi& epi,
-                                        const T* __restrict__ extra = nullptr) {
+                                        const T* __restrict__ x0, int64_t stride, Epi& epi,
+                                        const T* __restrict__ extra0 = nullptr) {
   constexpr int R = kZBPF + 3;
   const int lane = threadIdx.x & 63;
   const int sy = op.sy, sz = op.sz;
   const T c[4] = {op.c[0], op.c[1], op.c[2], op.c[3]};
-  const ChunkRange cr = block_chunks(nitems);
-  for (int it = cr.c0 + int(threadIdx.x >> 6); it < cr.c1; it += kWaves) {
+  const ChunkRange cr = block_chunks(nitems * NC);
+  for (int u = cr.c0 + int(threadIdx.x >> 6); u < cr.c1; u += kWaves) {
+    const int it = NC == 1 ? u : u / NC;
+    const int comp = NC == 1 ? 0 : u - it * NC;
+    const T* __restrict__ x = x0 + comp * stride;
+    const T* __restrict__ extra = extra0 ? extra0 + comp * stride : nullptr;
     const int pb = items[it];
     const int inplane = op.lanes[it * 64 + lane];
     const bool lane_ok = inplane >= 0;
@@ -94,7 +103,7 @@ __device__ __forceinline__ void zb_walk(const int* __restrict__ items, int nitem
       const bool interior = __all((!rw) || e == 0xFFu);
       T y = window_apply<T>(w[k % R], w[(k + 1) % R], w[(k + 2) % R], e, interior, c);
       if (extra != nullptr && rw && (fl[k % R] & kFlagExtra)) y += extra[node];
-      epi(node, lane_ok, rw, e, y, w[(k + 1) % R][4]);
+      epi(comp, node, lane_ok, rw, e, y, w[(k + 1) % R][4], (fl[k % R] & kFlagExtra) != 0u);
     }
   }
 }
@@ -107,16 +116,12 @@ __global__ __launch_bounds__(kBlock) void k_cg_q_zb(const int* __restrict__ item
                                                     const KScal* sc) {
   if (sc->done) return;
   double dot[1] = {0.0};
-#pragma unroll
-  for (int d = 0; d < NC; ++d) {
-    T* qd = q + d * stride;
-    auto epi = [&](int node, bool ok, bool rw, uint32_t, T y, T xc) {
-      const T qv = rw ? y : T(0);
-      if (ok) qd[node] = qv;
-      dot[0] += double(xc) * double(qv);
-    };
-    zb_walk<T>(items, nitems, op, p + d * stride, epi, op.extra ? op.extra + d * stride : nullptr);
-  }
+  auto epi = [&](int d, int node, bool ok, bool rw, uint32_t, T y, T xc, bool) {
+    const T qv = rw ? y : T(0);
+    if (ok) q[d * stride + node] = qv;
+    dot[0] += double(xc) * double(qv);
+  };
+  zb_walk<T, NC>(items, nitems, op, p, stride, epi, op.extra);
   block_partials<1>(dot, partials);
 }
 
@@ -128,20 +133,16 @@ __global__ __launch_bounds__(kBlock) void k_zb_residual(const int* __restrict__ 
                                                         TR* __restrict__ r32, int64_t stride,
                                                         double* __restrict__ partials) {
   double v[2] = {0.0, 0.0};
-#pragma unroll
-  for (int q = 0; q < NC; ++q) {
-    const double* bq = b + q * stride;
-    TR* rq = r32 + q * stride;
-    auto epi = [&](int node, bool ok, bool rw, uint32_t, double y, double) {
-      if (!ok) return;
-      const double bi = rw ? bq[node] : 0.0;
-      const double ri = rw ? bi - y : 0.0;
-      rq[node] = TR(ri);
-      v[0] += ri * ri;
-      v[1] += bi * bi;
-    };
-    zb_walk<double>(items, nitems, op, x + q * stride, epi, nullptr);
-  }
+  auto epi = [&](int q, int node, bool ok, bool rw, uint32_t, double y, double, bool) {
+    if (!ok) return;
+    const int64_t i = q * stride + node;
+    const double bi = rw ? b[i] : 0.0;
+    const double ri = rw ? bi - y : 0.0;
+    r32[i] = TR(ri);
+    v[0] += ri * ri;
+    v[1] += bi * bi;
+  };
+  zb_walk<double, NC>(items, nitems, op, x, stride, epi, nullptr);
   block_partials<2>(v, partials);
 }
 
@@ -151,10 +152,10 @@ __global__ __launch_bounds__(kBlock) void k_zb_resid(const int* __restrict__ ite
                                                      const T* __restrict__ x, const T* __restrict__ b,
                                                      T* __restrict__ r, const KScal* sc) {
   if (sc->done) return;
-  auto epi = [&](int node, bool ok, bool rw, uint32_t, T y, T) {
+  auto epi = [&](int, int node, bool ok, bool rw, uint32_t, T y, T, bool) {
     if (ok) r[node] = rw ? T(b[node] - y) : T(0);
   };
-  zb_walk<T>(items, nitems, op, x, epi, op.extra);
+  zb_walk<T, 1>(items, nitems, op, x, 0, epi, op.extra);
 }
 
 // Chebyshev-Jacobi step on rows, NC identical components (planes of `stride`):
@@ -171,28 +172,26 @@ __global__ __launch_bounds__(kBlock) void k_zb_cheb(const int* __restrict__ item
   if (sc && sc->done) return;
   double dot[1] = {0.0};
   const T c0 = op.c[0];
-#pragma unroll
-  for (int q = 0; q < NC; ++q) {
-    const T* bq = b + q * stride;
-    T* dq = d + q * stride;
-    T* xq = x_out + q * stride;
-    auto epi = [&](int node, bool ok, bool rw, uint32_t e, T y, T xc) {
-      if (!ok) return;
-      if (rw) {
-        const T dinv = op.dinv ? op.dinv[node] : T(1) / (c0 * T(__builtin_popcount(e)));
-        const T dold = (c1 != T(0)) ? dq[node] : T(0);
-        const T dn = c1 * dold + c2 * dinv * (bq[node] - y);
-        const T xn = xc + dn;
-        dq[node] = dn;
-        xq[node] = xn;
-        if (DOT) dot[0] += double(bq[node]) * double(xn);
-      } else if (zero_off_rows) {
-        dq[node] = T(0);
-        xq[node] = T(0);
-      }
-    };
-    zb_walk<T>(items, nitems, op, x_in + q * stride, epi, op.extra ? op.extra + q * stride : nullptr);
-  }
+  auto epi = [&](int q, int node, bool ok, bool rw, uint32_t e, T y, T xc, bool xrow) {
+    if (!ok) return;
+    const int64_t i = q * stride + node;
+    if (rw) {
+      // the stored diagonal only where the row has terms beyond its fine cells:
+      // elsewhere it is c0 times the number of kept fine cells
+      const T dinv = (op.dinv && xrow) ? op.dinv[node] : T(1) / (c0 * T(__builtin_popcount(e)));
+      const T dold = (c1 != T(0)) ? d[i] : T(0);
+      const T bi = b[i];
+      const T dn = c1 * dold + c2 * dinv * (bi - y);
+      const T xn = xc + dn;
+      d[i] = dn;
+      x_out[i] = xn;
+      if (DOT) dot[0] += double(bi) * double(xn);
+    } else if (zero_off_rows) {
+      d[i] = T(0);
+      x_out[i] = T(0);
+    }
+  };
+  zb_walk<T, NC>(items, nitems, op, x_in, stride, epi, op.extra);
   if (DOT) block_partials<1>(dot, partials);
 }
 
