@@ -445,6 +445,8 @@ def main() -> int:
     ap.add_argument("--moving", action="store_true",
                     help="also step the pulsatile cylinder with its wall points moving radially "
                          "(a device rebuild of the IB operators before every step)")
+    ap.add_argument("--kernel-table", type=int, default=8,
+                    help="kernels listed from the profile pass (largest summed time first)")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -475,7 +477,7 @@ def main() -> int:
                                                       "s1_outer", "s3_outer", "s4_outer", "s1_restarts")},
              "profile_pass": {"steps": res["profile_steps"],
                               "kernel_ms_per_step": round(res["kernel_ms_per_step"], 3),
-                              "kernels_top": res["kernels"][:8]}}
+                              "kernels_top": res["kernels"][:args.kernel_table]}}
     if args.wss and not refined:
         # unit normals from the vessel axis of the point's tube (timing only: any unit vectors do)
         nrm = case.X - case.X.mean(axis=0)

@@ -917,6 +917,14 @@ int run_cg(ibfe_ctx& c, const Op& op, NodeList nl, const T* b, T* x, T* r, T* p,
   return finish_status(s, "CG");
 }
 
+// y = A xin with the BiCGStab products of step MODE; returns the number of partials.
+template <typename T, int MODE, class Op>
+int launch_bi_apply(ibfe_ctx& c, const Op& op, NodeList nl, const T* xin, T* y, const T* w, const KScal* sc) {
+  const int nr = red_blocks(nl.n);
+  klaunch<(k_bi_apply<T, Op, MODE>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, nl, op, xin, y, w, c.partials, sc);
+  return nr;
+}
+
 template <typename T, class Op>
 int run_bicgstab(ibfe_ctx& c, const Op& op, const T* b, T* x, T* const* wv, int slot, double rtol,
                  int max_iters, SolveOut& out) {
@@ -951,15 +959,13 @@ int run_bicgstab(ibfe_ctx& c, const Op& op, const T* b, T* x, T* const* wv, int 
           klaunch<(k_bi_p<T, Op>)>(c, dim3(nb), dim3(kBlock), 0, c.stream, nl, op, r, p, v, phat,
                              csc);
           if ((rc2 = pre_apply(c, op, phat, csc))) return rc2;
-          klaunch<(k_bi_apply<T, Op, 0>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, nl, op, phat, v,
-                             rhat, c.partials, csc);
-          klaunch<k_fin_bi_apply<0>>(c, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc);
+          const int na = launch_bi_apply<T, 0>(c, op, nl, (const T*)phat, v, (const T*)rhat, csc);
+          klaunch<k_fin_bi_apply<0>>(c, dim3(1), dim3(kBlock), 0, c.stream, pa, na, sc);
           klaunch<(k_bi_s<T, Op>)>(c, dim3(nb), dim3(kBlock), 0, c.stream, nl, op, r, v, s, shat,
                              csc);
           if ((rc2 = pre_apply(c, op, shat, csc))) return rc2;
-          klaunch<(k_bi_apply<T, Op, 1>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, nl, op, shat, t,
-                             s, c.partials, csc);
-          klaunch<k_fin_bi_apply<1>>(c, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc);
+          const int nt = launch_bi_apply<T, 1>(c, op, nl, (const T*)shat, t, (const T*)s, csc);
+          klaunch<k_fin_bi_apply<1>>(c, dim3(1), dim3(kBlock), 0, c.stream, pa, nt, sc);
           klaunch<(k_bi_x<T, Op>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, nl, op, x, r, rhat,
                              phat, shat, s, t, c.partials, csc);
           klaunch<k_fin_bi_x>(c, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc);
@@ -986,6 +992,11 @@ int run_bicgstab(ibfe_ctx& c, const Op& op, const T* b, T* x, T* const* wv, int 
   return finish_status(st, "BiCGStab");
 }
 
+template <typename T, int NC>
+void launch_extra(ibfe_ctx& c, const OpCSym<T, NC>& o, const T* x, const KScal* sc);
+template <typename T, int NC>
+ZOp<T> zcomp_op(const ibfe_ctx& c, const OpCSym<T, NC>& o);
+
 // FP64 residual of the refinement loop: returns |r|^2 and |b|^2 on the host and
 // leaves r in FP32 in r32.
 template <class Op64, typename TR>
@@ -1009,6 +1020,14 @@ int ir_residual(ibfe_ctx& c, const Op64& op, const double* b, double* x, TR* r32
     nr = red_blocks(c.nzitems * Op64::kNC);
     klaunch<(k_zb_residual<TR, Op64::kNC>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
                        c.nzitems, z, b, (const double*)x, r32, op.stride, c.partials);
+  } else if constexpr (std::is_same<Op64, OpCSym<double, 1>>::value ||
+                       std::is_same<Op64, OpCSym<double, 3>>::value) {
+    // composite symmetric forms: the fine-cell walk plus the precomputed extra rows
+    launch_extra<double, Op64::kNC>(c, op, (const double*)x, (const KScal*)nullptr);
+    const ZOp<double> z = zcomp_op(c, op);
+    nr = red_blocks(c.nzitems * Op64::kNC);
+    klaunch<(k_zb_residual<TR, Op64::kNC>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
+                                            c.nzitems, z, b, (const double*)x, r32, op.stride, c.partials);
   } else {
     klaunch<(k_residual<Op64, TR>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, c.nl, op, b,
                        x, r32, c.partials);

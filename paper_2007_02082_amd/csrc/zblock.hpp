@@ -142,7 +142,7 @@ __global__ __launch_bounds__(kBlock) void k_zb_residual(const int* __restrict__ 
     v[0] += ri * ri;
     v[1] += bi * bi;
   };
-  zb_walk<double, NC>(items, nitems, op, x, stride, epi, nullptr);
+  zb_walk<double, NC>(items, nitems, op, x, stride, epi, op.extra);
   block_partials<2>(v, partials);
 }
 
