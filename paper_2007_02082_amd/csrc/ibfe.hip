@@ -785,7 +785,7 @@ int launch_q(ibfe_ctx& c, const Op& op, NodeList nl, const T* p, T* q, const KSc
 }
 template <typename T, int NC>
 int launch_q(ibfe_ctx& c, const OpSym<T, NC>& op, NodeList, const T* p, T* q, const KScal* sc) {
-  const int nr = red_blocks(c.nzitems * NC);
+  const int nr = red_blocks(c.nzitems);
   ZOp<T> z{op.emask, op.flags, op.rowbit, op.sy, op.sz, c.plan.nz + 1,
            {op.c[0], op.c[1], op.c[2], op.c[3]}, c.zb, c.zlanes};
   klaunch<(k_cg_q_zb<T, NC>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems, c.nzitems, z,
@@ -1017,7 +1017,7 @@ int ir_residual(ibfe_ctx& c, const Op64& op, const double* b, double* x, TR* r32
     z.lanes = c.zlanes;
     z.zb = c.zb;
     for (int t = 0; t < 4; ++t) z.c[t] = op.c[t];
-    nr = red_blocks(c.nzitems * Op64::kNC);
+    nr = red_blocks(c.nzitems);
     klaunch<(k_zb_residual<TR, Op64::kNC>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
                        c.nzitems, z, b, (const double*)x, r32, op.stride, c.partials);
   } else if constexpr (std::is_same<Op64, OpCSym<double, 1>>::value ||
@@ -1025,7 +1025,7 @@ int ir_residual(ibfe_ctx& c, const Op64& op, const double* b, double* x, TR* r32
     // composite symmetric forms: the fine-cell walk plus the precomputed extra rows
     launch_extra<double, Op64::kNC>(c, op, (const double*)x, (const KScal*)nullptr);
     const ZOp<double> z = zcomp_op(c, op);
-    nr = red_blocks(c.nzitems * Op64::kNC);
+    nr = red_blocks(c.nzitems);
     klaunch<(k_zb_residual<TR, Op64::kNC>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
                                             c.nzitems, z, b, (const double*)x, r32, op.stride, c.partials);
   } else {
@@ -1298,7 +1298,7 @@ int run_cheb_gen(ibfe_ctx& c, const Op& op, const T* b, T* x, T* xalt, T* d, int
   T* alt = cur == x ? xalt : x;
   klaunch<(k_cheb0_gen<T, Op>)>(c, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
                      c.nl, op, b, d, cur, T(1.0 / theta), (const KScal*)nullptr);
-  const int nr = red_blocks(c.nzitems * Op::kNC);
+  const int nr = red_blocks(c.nzitems);
   const ZOp<T> zop = zcomp_op(c, op);
   int rc;
   T* const cur0 = cur;
@@ -1686,7 +1686,7 @@ int run_cheb_mass(ibfe_ctx& c, const T* b, T* x, T* xalt, T* d, int iters) {
   klaunch<(k_mg_cheb0<T, 3>)>(c, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
                      c.nl, (const uint8_t*)c.emask, (const uint8_t*)c.flags,
                      T(c.fc.m[0]), T(1.0 / theta), b, d, cur, (const KScal*)nullptr, kFlagF, c.stride);
-  const int nr = red_blocks(c.nzitems * 3);
+  const int nr = red_blocks(c.nzitems);
   T* const cur0 = cur;
   T* const alt0 = alt;
   auto body = [&]() -> int {

@@ -45,11 +45,10 @@ struct ZOp {
 // SIMD to hide the memory latency).
 constexpr int kZBPF = 2;
 
-// NC components (planes of `stride`) are separate work units: unit u is item
-// u / NC, component u % NC, so that the launch spreads NC times as many equal
-// units over the wavefronts (one unit per wavefront at a time; with one unit per
-// item the last round of items leaves most of the chip idle) and the components
-// of an item run close together (its cell bits and flags stay in the caches).
+// A wavefront walks its item once per component (planes of `stride`): the cell
+// bits and flags of the item stay in its caches.  (Spreading the (item,
+// component) pairs over different wavefronts was measured slower: 32 -> 35 us
+// for the pulsatile mass step.)
 // epi(component, node, lane_ok, row, emask, Ax, x_centre, extra_row).
 template <typename T, int NC, class Epi>
 __device__ __forceinline__ void zb_walk(const int* __restrict__ items, int nitems, const ZOp<T>& op,
@@ -59,10 +58,9 @@ __device__ __forceinline__ void zb_walk(const int* __restrict__ items, int nitem
   const int lane = threadIdx.x & 63;
   const int sy = op.sy, sz = op.sz;
   const T c[4] = {op.c[0], op.c[1], op.c[2], op.c[3]};
-  const ChunkRange cr = block_chunks(nitems * NC);
-  for (int u = cr.c0 + int(threadIdx.x >> 6); u < cr.c1; u += kWaves) {
-    const int it = NC == 1 ? u : u / NC;
-    const int comp = NC == 1 ? 0 : u - it * NC;
+  const ChunkRange cr = block_chunks(nitems);
+  for (int it = cr.c0 + int(threadIdx.x >> 6); it < cr.c1; it += kWaves)
+  for (int comp = 0; comp < NC; ++comp) {
     const T* __restrict__ x = x0 + comp * stride;
     const T* __restrict__ extra = extra0 ? extra0 + comp * stride : nullptr;
     const int pb = items[it];

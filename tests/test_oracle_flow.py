@@ -153,8 +153,31 @@ def test_poiseuille_closed_form_converges_under_refinement():
     discretisation level and falls under refinement."""
     e8 = _poiseuille_error(8)
     e16 = _poiseuille_error(16)
-    assert e16 < 0.3
-    assert e16 < 0.5 * e8
+    # the mask holds the fluid inside the tube only: the zero Dirichlet nodes just
+    # outside pull the no-slip about h inward (61 % and 19 % errors), falling like
+    # h^1.7 under refinement
+    assert e16 < 0.22
+    assert e16 < 0.4 * e8
+
+
+def _tube_in_box_error(cells):
+    c, disk = synth.tube_in_box(cells)
+    pr = ipcs.Problem.from_case(c)
+    u, _, _, _ = pr.run(c.u0, c.p0, c.nsteps)
+    xyz = c.node_coords()
+    exact = 1.0 - (xyz[disk, 0] ** 2 + xyz[disk, 1] ** 2) / 0.25
+    return np.linalg.norm(u[2][disk] - exact) / np.linalg.norm(exact)
+
+
+@pytest.mark.slow
+def test_poiseuille_closed_form_tube_in_box():
+    """Section 3.1 meshes the whole box: with fluid on both sides of the immersed wall
+    the velocity inside the tube stays within 10 % of the closed form after the
+    start-up transient at 16 cells per diameter (8.4 %; 27 % at 8)."""
+    e8 = _tube_in_box_error(8)
+    e16 = _tube_in_box_error(16)
+    assert e16 < 0.10
+    assert e16 < 0.4 * e8
 
 
 def test_paper_poiseuille_numbers():
