@@ -239,8 +239,9 @@ int ibfe_step(ibfe_ctx* ctx, int nsteps);
  * the spreading lists, G and its block-Jacobi preconditioner are rebuilt on the
  * device (deterministic: the same positions give the same G on every call).
  * on_device != 0: X and U_B are device memory (not validated); else host memory
- * (must be finite, IBFE_EINVAL).  Uniform grids only (IBFE_EINVAL on a refined
- * grid).  IBFE_ESINGULAR if a point's support holds no free node; IBFE_EINVAL if
+ * (must be finite, IBFE_EINVAL).  On a refined lattice every support node must
+ * stay in the closure of a flagged cell and not be hanging, as at ibfe_create
+ * (else IBFE_EINVAL).  IBFE_ESINGULAR if a point's support holds no free node; IBFE_EINVAL if
  * the points are so dense that a row of G collects more than 1024 support
  * products.  After an error the context refuses to step until a call succeeds.
  * The first call allocates the rebuild buffers (about 1.6 KB per point) and

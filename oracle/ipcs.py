@@ -94,11 +94,14 @@ class Problem:
         X = np.asarray(X, np.float64).reshape(-1, 3)
         if X.shape != self.X.shape:
             raise ValueError("the number of Lagrangian points is fixed")
-        if self.mesh is not None:
-            raise ValueError("moving points are supported on uniform grids only")
         self.X = X
         self.U_B = np.zeros_like(X) if U_B is None else np.asarray(U_B, np.float64).reshape(-1, 3)
-        self.I = ib.interpolation_matrix(X, self.nx, self.ny, self.nz, self.h, self.origin)
+        if self.mesh is not None:
+            # the kernel on the fine lattice; the supports must stay in the band
+            self.I = ib.interpolation_matrix(X, 2 * self.nx, 2 * self.ny, 2 * self.nz, self.h / 2.0, self.origin)
+            self._check_support_in_fine_band()
+        else:
+            self.I = ib.interpolation_matrix(X, self.nx, self.ny, self.nz, self.h, self.origin)
 
     @classmethod
     def from_case(cls, c, advection=0, viscous=0):

@@ -44,12 +44,14 @@ struct GridGeom {
 };
 
 // counters[0]: points without free support, [1]: rows whose candidates exceed
-// kGramCap, [2]: n_sp (spreading nodes), [3]: entries of the spreading lists.
+// kGramCap, [2]: n_sp (spreading nodes), [3]: entries of the spreading lists,
+// [4]: support nodes outside `band` (refined lattice: the closure of the flagged
+// cells minus the hanging nodes; NULL on a uniform grid).
 __global__ __launch_bounds__(kBlock) void k_ib_stencil(int M, GridGeom g, const double* __restrict__ X,
                                                        const uint8_t* __restrict__ flags, uint32_t N,
                                                        int32_t* __restrict__ idx, double* __restrict__ w,
                                                        uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                                                       int* __restrict__ counters) {
+                                                       int* __restrict__ counters, const uint8_t* __restrict__ band) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= M) return;
   const double o[3] = {g.ox, g.oy, g.oz};
@@ -78,6 +80,7 @@ __global__ __launch_bounds__(kBlock) void k_ib_stencil(int M, GridGeom g, const 
         uint32_t key = N;
         if (ii >= 0 && jj >= 0 && kk >= 0 && ii <= dims[0] && jj <= dims[1] && kk <= dims[2]) {
           n = int32_t(ii + g.sy * jj + g.sz * kk);
+          if (band && !band[n]) atomicAdd(&counters[4], 1);
           ws = wd[0][a] * wd[1][b] * wd[2][c];
           if (flags[n] & IBFE_FLAG_F) {
             free2 += ws * ws;

@@ -194,6 +194,7 @@ struct ibfe_ctx {
   int64_t* sp_ptr = nullptr;
   int32_t* sp_pt = nullptr;
   double* sp_wt = nullptr;
+  uint8_t* ib_band = nullptr;  // refined lattice: nodes a kernel support may touch
   double* ibv[7] = {};  // b, lam, r, p, q, z, p' (3 planes of mstride)
   int n_sp = 0;         // nodes of the spreading lists
   // moving Lagrangian points: device rebuild buffers, allocated on the first
@@ -669,13 +670,17 @@ int setup_device(ibfe_ctx& c) {
     if ((rc = c.upload(&c.ib_idx, P.ib_idx.data(), P.ib_idx.size()))) return rc;
     if ((rc = c.upload(&c.ib_w, P.ib_w.data(), P.ib_w.size()))) return rc;
     if ((rc = c.upload(&c.UB, P.U_B.data(), P.U_B.size()))) return rc;
-    // uniform grids may move their points (ibfe_set_points): the spreading lists
-    // and G are held at their largest sizes from the start (every support pair
-    // free; four times the entries of G at the initial positions, at least 128
-    // per row), so that a rebuild writes them in place
-    const bool movable = !P.refined;
-    const int64_t np = movable ? 64 * M : 0;
-    c.mv.g_cap = movable ? std::max<int64_t>(4 * int64_t(P.G_col.size()), 128 * M) : int64_t(P.G_col.size());
+    // the points may move (ibfe_set_points): the spreading lists and G are held at
+    // their largest sizes from the start (every support pair free; four times the
+    // entries of G at the initial positions, at least 128 per row), so that a
+    // rebuild writes them in place
+    const int64_t np = 64 * M;
+    c.mv.g_cap = std::max<int64_t>(4 * int64_t(P.G_col.size()), 128 * M);
+    if (P.refined) {
+      std::vector<uint8_t> band;
+      ib_band_mask(P, band);
+      if ((rc = c.upload(&c.ib_band, band.data(), band.size()))) return rc;
+    }
     const size_t gc = size_t(c.mv.g_cap);
     if ((rc = c.upload(&c.G_ptr, P.G_ptr.data(), P.G_ptr.size()))) return rc;
     if ((rc = c.upload(&c.G_col, P.G_col.data(), P.G_col.size(), gc))) return rc;
@@ -2772,7 +2777,8 @@ int rebuild_points(ibfe_ctx& C, const RebuildBufs& B, const double* X, const dou
   const uint32_t N = uint32_t(P.N);
   GridGeom g{P.origin[0], P.origin[1], P.origin[2], P.h, P.nx, P.ny, P.nz, P.sy, P.sz};
   klaunch<k_ib_stencil>(C, dim3(blocks_lin(M)), dim3(kBlock), 0, C.stream, int(M), g, (const double*)B.X,
-                        (const uint8_t*)C.flags, N, C.ib_idx, C.ib_w, B.keys, B.vals, B.counters);
+                        (const uint8_t*)C.flags, N, C.ib_idx, C.ib_w, B.keys, B.vals, B.counters,
+                        (const uint8_t*)C.ib_band);
   CHECK_LAUNCH();
   int bits = 1;
   while (bits < 32 && (uint64_t(1) << bits) <= uint64_t(N)) ++bits;
@@ -2791,6 +2797,10 @@ int rebuild_points(ibfe_ctx& C, const RebuildBufs& B, const double* X, const dou
   int hc[8];
   HIP_TRY(hipMemcpyAsync(hc, B.counters, sizeof(hc), hipMemcpyDeviceToHost, C.stream));
   HIP_TRY(hipStreamSynchronize(C.stream));
+  if (hc[4] > 0)
+    return fail(IBFE_EINVAL, std::to_string(hc[4]) +
+                                 " support node(s) of the moved points leave the refined band (the closure of the "
+                                 "flagged cells without the hanging nodes)");
   if (hc[0] > 0)
     return fail(IBFE_ESINGULAR, std::to_string(hc[0]) + " Lagrangian point(s) without a free support node");
   const int64_t nvalid = hc[3];
@@ -2823,7 +2833,6 @@ int rebuild_points(ibfe_ctx& C, const RebuildBufs& B, const double* X, const dou
 
 int check_points(const ibfe_ctx& C, const double* X, const double* U_B, int on_device) {
   const Plan& P = C.plan;
-  if (P.refined) return fail(IBFE_EINVAL, "moving Lagrangian points are supported on uniform grids only");
   if (64 * P.M > int64_t(INT32_MAX) - 1) return fail(IBFE_EINVAL, "too many Lagrangian points to move");
   if (!on_device) {
     for (int64_t q = 0; q < 3 * P.M; ++q)

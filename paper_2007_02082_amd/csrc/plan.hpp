@@ -132,6 +132,9 @@ int build_composite_cells(Plan& plan, UnionFind& uf, std::string& err);
 void composite_diagonals(Plan& plan);
 // Every IB support node inside the closure of a refined cell and not hanging.
 int check_ib_support_refined(const Plan& plan, std::string& err);
+// Lattice nodes an IB kernel support may touch on a refined lattice: nodes in the
+// closure of a flagged cell that are not hanging (1), all others 0.
+void ib_band_mask(const Plan& plan, std::vector<uint8_t>& ok);
 
 // Returns IBFE_OK or an error code with `err` set.
 int build_plan(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* params,

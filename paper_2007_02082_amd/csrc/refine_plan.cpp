@@ -177,8 +177,8 @@ void composite_diagonals(Plan& P) {
   P.mass_lmin = 0.125 * ratio;
 }
 
-int check_ib_support_refined(const Plan& P, std::string& err) {
-  std::vector<uint8_t> ok(P.N, 0);
+void ib_band_mask(const Plan& P, std::vector<uint8_t>& ok) {
+  ok.assign(P.N, 0);
   for (int bk = 0; bk < P.bnz; ++bk)
     for (int bj = 0; bj < P.bny; ++bj)
       for (int bi = 0; bi < P.bnx; ++bi) {
@@ -189,6 +189,11 @@ int check_ib_support_refined(const Plan& P, std::string& err) {
               ok[(2 * bi + dx) + P.sy * (2 * bj + dy) + P.sz * (2 * bk + dz)] = 1;
       }
   for (int32_t n : P.hang_ids) ok[n] = 0;
+}
+
+int check_ib_support_refined(const Plan& P, std::string& err) {
+  std::vector<uint8_t> ok;
+  ib_band_mask(P, ok);
   for (int64_t q = 0; q < int64_t(P.ib_idx.size()); ++q) {
     const int32_t n = P.ib_idx[q];
     if (n >= 0 && !ok[n]) {

@@ -65,12 +65,10 @@ size_t footprint_of(const ibfe_grid& g, int64_t M, const ibfe_params& pr) {
     if (pr.precision == 1) bytes += double(stride) * 27.0 * 4.0;
   }
   if (pr.precond >= 1) bytes += 0.15 * double(stride) * (5.0 * (pr.precision == 1 ? 4 : 8) + 2.0);
-  // IB arrays: stencils, spreading lists and G (on uniform grids held at the sizes a
-  // rebuild for moved points may need: 64 pairs per point, four times G's entries)
-  if (ref)
-    bytes += double(M) * (64.0 * 12.0 * 2.0 + 150.0 * 12.0 + 15.0 * 8.0 + 64.0);
-  else
-    bytes += double(M) * (64.0 * 12.0 + 64.0 * 24.0 + 4.0 * 150.0 * 12.0 + 15.0 * 8.0 + 64.0);
+  // IB arrays: stencils, spreading lists and G, held at the sizes a rebuild for
+  // moved points may need (64 pairs per point, four times G's entries)
+  bytes += double(M) * (64.0 * 12.0 + 64.0 * 24.0 + 4.0 * 150.0 * 12.0 + 15.0 * 8.0 + 64.0);
+  if (ref && M > 0) bytes += double(N);  // the band of allowed support nodes
   bytes += 3.0 * 8.0 * double(N + M) + 8.0 * 2048.0 * 8.0;         // compact copies, partials
   return size_t(bytes * 1.05) + (16u << 20);
 }

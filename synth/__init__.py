@@ -6,4 +6,4 @@ from .serving import GRIDS, Request, request_stream, vessel_case  # noqa: F401,E
 from .aneurysm import aneurysm_case  # noqa: F401,E402
 from .aorta import aorta_case, womersley_shapes  # noqa: F401,E402
 from .poiseuille import poiseuille_e1, tube_in_box  # noqa: F401,E402
-from .moving import PulsatingWall, pulsating_cylinder  # noqa: F401,E402
+from .moving import PulsatingWall, pulsating_cylinder, pulsating_refined_cylinder  # noqa: F401,E402

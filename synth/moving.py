@@ -11,7 +11,7 @@ import math
 
 import numpy as np
 
-from .cases import Case, small_cylinder
+from .cases import Case, refined_cylinder, small_cylinder
 
 
 class PulsatingWall:
@@ -44,4 +44,20 @@ def pulsating_cylinder(cells_xy: int = 8, cells_z: int = 16, length: float = 2.0
     wall = PulsatingWall(0.5, z_levels, per_ring, amp, period)
     c.X, c.U_B = wall.at(0.0)
     c.name = f"pulsating_wall_{cells_xy}x{cells_xy}x{cells_z}"
+    return c, wall
+
+
+def pulsating_refined_cylinder(amp: float = 0.03, period: float = 0.2, nsteps: int = 3) -> tuple[Case, PulsatingWall]:
+    """The refined test cylinder (8 x 8 x 8 base cells of 1.25/8, 2:1 band of 0.3 around
+    R0 = 0.5) with its wall rings moving radially; the supports stay in the band for
+    amplitudes up to a few percent.  The case holds the positions at t = 0."""
+    c = refined_cylinder(8, 8, length=1.25, band=0.3, nsteps=nsteps)
+    z = np.unique(np.round(c.X[:, 2], 12))
+    per_ring = c.M // z.size
+    wall = PulsatingWall(0.5, z, per_ring, amp, period)
+    X0, U0 = wall.at(0.0)
+    if not np.allclose(np.sort(X0[:, 2]), np.sort(c.X[:, 2])):
+        raise ValueError("ring layout differs from the refined cylinder's")
+    c.X, c.U_B = X0, U0
+    c.name = "pulsating_wall_refined_8x8x8"
     return c, wall

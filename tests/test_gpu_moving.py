@@ -109,11 +109,33 @@ def test_set_points_errors_keep_the_context_safe():
     s.set_points(*wall.at(case.dt))
     s.step(1)
     s.close()
-    rc = synth.refined_cylinder(8, 8, length=1.25, band=0.3)
-    sr = make_solver(rc, precision=0)
-    with pytest.raises(ibfe.IbfeError, match="uniform"):
-        sr.set_points(rc.X)
-    sr.close()
+
+
+@pytest.mark.parametrize("precision,tol", [(0, TOL64), (1, TOL_MIXED)])
+def test_moving_wall_refined_lattice_parity(precision, tol):
+    """Moving points on the 2:1 refined lattice: the kernel on the fine lattice, the
+    supports re-checked against the band at every rebuild, against the oracle."""
+    case, wall = synth.pulsating_refined_cylinder(nsteps=3)
+    say("case", case.name, "M", case.M, "precision", precision)
+    out = _run_moving(case, wall, 3, 0.0, precision=precision, precond=2)
+    _check_steps(out, tol, case.name)
+
+
+def test_refined_points_leaving_the_band_are_refused():
+    case, wall = synth.pulsating_refined_cylinder(nsteps=1)
+    X, U = wall.at(case.dt)
+    inward = X * np.array([0.6, 0.6, 1.0])   # supports reach the unrefined core
+    pr = ipcs.Problem.from_case(case)
+    with pytest.raises(ValueError):
+        pr.set_points(inward, U)
+    s = make_solver(case, precision=0, precond=2)
+    with pytest.raises(ibfe.IbfeError, match="refined band"):
+        s.set_points(inward, U)
+    with pytest.raises(ibfe.IbfeError, match="EINVAL"):
+        s.step(1)
+    s.set_points(X, U)
+    s.step(1)
+    s.close()
 
 
 def test_set_points_from_device_tensors():
