@@ -119,3 +119,57 @@ def test_served_vessels_match_oracle(kind):
     e32 = (rel_l2(u32, u[:, P]), rel_l2(p32, p[P]))
     say("fp64", e64, "mixed", e32)
     assert max(e64) <= 1e-10 and max(e32) <= 1e-6
+
+
+def test_request_footprint_bounds_real_allocation():
+    """The admission footprint is an upper bound of what a request really allocates
+    (largest serving grid, 128 x 128 x 256 cells)."""
+    import torch
+    case = synth.vessel_case("cylinder", 1.0, (128, 128, 256), nsteps=2, seed=5)
+    kw = _kw(case, precision=1, precond=2)
+    fp = ibfe.request_footprint(**kw)
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    s = ibfe.Solver(**kw)
+    s.set_state(np.zeros(3 * s.n_u), np.zeros(s.n_u), 0.0)
+    s.step(1)
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    s.close()
+    used = free0 - free1
+    say("footprint", fp, "allocated", used)
+    assert 0 < used <= fp
+
+
+def test_request_stream_under_4gb_budget():
+    """Serving requests of the seeded stream (grids up to 128 x 128 x 256) under a
+    4 GiB device budget: every request completes, requests queue, the footprints of
+    the requests running at any admission never exceed the budget, and the largest
+    request's result is bitwise the one it has when run alone."""
+    budget = 4 << 30
+    reqs = synth.request_stream(n=10, nsteps=2)
+    kws = [_kw(r.case, precision=1, precond=2) for r in reqs]
+    fps = [ibfe.request_footprint(**kw) for kw in kws]
+    say("footprints GiB", [round(f / 2**30, 2) for f in fps])
+    assert max(fps) <= budget < sum(fps)
+    srv = ibfe.Server(budget_bytes=budget, max_slots=4)
+    ids = [srv.submit(2, **kw) for kw in kws]
+    res = []
+    for rid in ids:
+        r, u, p, _ = _collect(srv, rid)
+        res.append((r, u, p))
+    peak = srv.peak_concurrency()
+    srv.close()
+    spans = [(r["t_admit"], r["t_done"], r["footprint"]) for r, _, _ in res]
+    for a, _, _ in spans:
+        held = sum(f for a2, d2, f in spans if a2 <= a < d2)
+        assert held <= budget, (a, held)
+    big = int(np.argmax(fps))
+    # the largest request is submitted behind smaller ones that fill fewer than all
+    # slots but leave too little memory, so it waits for one of them to finish
+    assert big < 4 and sum(fps[:big + 1]) > budget
+    assert res[big][0]["t_admit"] >= min(r["t_done"] for r, _, _ in res[:big])
+    say("peak concurrency", peak)
+    assert peak >= 2
+    ua, pa, _ = _run_direct(reqs[big].case, 2, precision=1, precond=2)
+    assert np.array_equal(res[big][1], ua) and np.array_equal(res[big][2], pa)
