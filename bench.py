@@ -323,6 +323,12 @@ def kernel_model(name: str, z: dict):
     if name.startswith("k_residual<") and "OpStencil<double, 3>" in name:
         return (27 * 8 + 6 * 8 + 3 * 4) * n_f, ("FP64 residual of the stored stencil: 27 planes, read x, b, "
                                                  "write r (FP32) per free node")
+    if name.startswith("k_bi_apply<") and ("OpConv<" in name or "OpCConv<" in name):
+        return (12 * s + b) * n_f, ("matrix-free advection-diffusion apply, 3 components: read x, u^n and w, "
+                                    "write y per free node (rows formed on the fly)")
+    if name.startswith("k_residual<") and ("OpConv<double>" in name or "OpCConv<double>" in name):
+        return (9 * 8 + 3 * 4 + b) * n_f, ("FP64 matrix-free residual: read x, u^n, b, write r (FP32) per free "
+                                           "node (rows formed on the fly)")
     if name == "k_s1_build":
         planes = 54 if z["refined"] else 27
         return (3 * 8 + planes * 12) * n_p, ("advection-diffusion stencil assembly: read u^n, write the "
@@ -331,7 +337,7 @@ def kernel_model(name: str, z: dict):
 
 
 def run_workload(workload: str, prec: int, pc: int, visc: int, steps: int, warmup: int, case=None,
-                 keep_state: bool = False, profile_steps: int = 3) -> dict:
+                 keep_state: bool = False, profile_steps: int = 3, advdiff: int = 0) -> dict:
     """W untimed steps from rest; then `profile_steps` steps in which every kernel
     dispatch records its own start and end HIP events (the whole-step breakdown, which
     names the dominant kernel: the largest summed duration); then the K timed steps,
@@ -347,7 +353,7 @@ def run_workload(workload: str, prec: int, pc: int, visc: int, steps: int, warmu
     z = sizes_of(case, prec)
     print(f"[bench] {case.name}: {z['n_p']} nodes of P, {z['n_free']} free, M = {case.M}", file=sys.stderr,
           flush=True)
-    s = ibfe.Solver(**ibfe.inputs_from_case(case, precision=prec, precond=pc, viscous=visc))
+    s = ibfe.Solver(**ibfe.inputs_from_case(case, precision=prec, precond=pc, viscous=visc, advdiff=advdiff))
     n = s.n_u
     s.set_state(np.zeros(3 * n), np.zeros(n), 0.0)
     s.step(warmup)
@@ -432,6 +438,9 @@ def main() -> int:
                     help="pressure preconditioner: geometric multigrid or Jacobi")
     ap.add_argument("--viscous", choices=["laplacian", "strain"], default="laplacian",
                     help="viscous form: mu (grad u, grad v) or the strain-rate form 2 mu (eps(u), eps(v))")
+    ap.add_argument("--advdiff", choices=["matrix-free", "stencil"], default="matrix-free",
+                    help="tentative-velocity operator: rows formed on the fly, or the stencil "
+                         "assembled once per step")
     ap.add_argument("--wss", action="store_true",
                     help="also time the wall shear stress at the Lagrangian points (after the timed steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -469,9 +478,11 @@ def main() -> int:
     prec = 1 if args.precision == "mixed" else 0
     pc = 2 if args.precond == "mg" else 0
     visc = 1 if args.viscous == "strain" else 0
+    ad = 1 if args.advdiff == "stencil" else 0
     refined = args.workload == "aneurysm"
     case = make_case(args.workload)
-    res = run_workload(args.workload, prec, pc, visc, args.steps, args.warmup, case=case, keep_state=True)
+    res = run_workload(args.workload, prec, pc, visc, args.steps, args.warmup, case=case, keep_state=True,
+                       advdiff=ad)
     s = res.pop("solver")
     st = res["stats"]
     print(f"[bench] {case.name}: {res['steps_per_s']:.2f} steps/s", file=sys.stderr, flush=True)
@@ -505,7 +516,7 @@ def main() -> int:
     if prec == 1 and not args.no_check:
         # the same warm-up and timed steps in FP64: the accuracy the mixed-precision rate is quoted at
         import paper_2007_02082_amd as ibfe
-        ref = ibfe.Solver(**ibfe.inputs_from_case(case, precision=0, precond=pc, viscous=visc))
+        ref = ibfe.Solver(**ibfe.inputs_from_case(case, precision=0, precond=pc, viscous=visc, advdiff=ad))
         ref.set_state(np.zeros(3 * ref.n_u), np.zeros(ref.n_p), 0.0)
         t0r = time.perf_counter()
         ref.step(args.warmup + res["profile_steps"] + args.steps)
@@ -538,7 +549,7 @@ def main() -> int:
                    "refined_cells": int(case.refine_cell.sum()) if refined else 0,
                    "n_active": res["sizes"]["n_p"], "lagrangian_points": case.M, "dt": case.dt,
                    "precision": args.precision, "pressure_preconditioner": args.precond,
-                   "viscous_form": args.viscous},
+                   "viscous_form": args.viscous, "advdiff_operator": args.advdiff},
         "roofline": roof,
     }
     out.update(extra)
@@ -547,7 +558,7 @@ def main() -> int:
         for w in ("pulsatile", "aneurysm", "aorta"):
             if w == args.workload:
                 continue
-            r = run_workload(w, prec, pc, visc, args.steps, args.warmup)
+            r = run_workload(w, prec, pc, visc, args.steps, args.warmup, advdiff=ad)
             rf = roofline_of(r, w, args.precision, pc)
             others[r["case"].name] = {
                 "steps_per_s": round(r["steps_per_s"], 3), "ms_per_step": round(r["ms_per_step"], 3),

@@ -139,6 +139,14 @@ typedef struct ibfe_ib {
  *                 2 mu (eps(u), eps(v)), eps(u) = (grad u + grad u^T)/2, which
  *                 couples the three components of the tentative-velocity system
  *                 (uniform and refined grids, either advection)
+ *   advdiff     : how the semi-implicit tentative-velocity operator
+ *                 (rho/dt) M + rho C(u^n) + mu K of Eq. 9 is applied: 0 = matrix-free
+ *                 (each row formed from the cell bits and u^n at its 27 neighbours
+ *                 on every apply; nothing stored); 1 = a stencil of 27 coefficients
+ *                 per node (54 on a refined lattice) assembled once per step and
+ *                 streamed by every apply.  Both give the same operator up to
+ *                 rounding.  The explicit advection option always assembles the
+ *                 stencil of rho C(u^n) for its one product per step.
  */
 typedef struct ibfe_params {
   double rho, mu, dt;
@@ -149,6 +157,7 @@ typedef struct ibfe_params {
   int32_t advection;
   double ib_rtol;
   int32_t viscous;
+  int32_t advdiff;
 } ibfe_params;
 
 /*

@@ -201,22 +201,29 @@ struct GradElem {
 
 // (rho/dt) M u_d - G_d p - A g_d (right-hand side of the tentative velocity,
 // Eq. 9 with the Dirichlet lifting) on the composite mesh.
-struct S1RhsElem {
+// g vanishes off the inlet table, so A g is formed only inside the lattice box
+// [lo, hi] (the inlet-table nodes' bounding box widened by 4 lattice steps: a
+// coarse element reaches 2 steps, a hanging child's parents 2 more).
+template <class AOp = OpCStencil<double, 3>>
+struct S1RhsElemT {
   static constexpr int kNO = 3;
   OpCSym<double, 3> mass;     // (rho/dt) M
-  OpCStencil<double, 3> A;    // stored advection-diffusion operator
+  AOp A;                      // advection-diffusion operator (stored or matrix-free)
   GradElem grad;              // on p
   const double* u;
   const double* g;
+  int lo[3], hi[3];
   __device__ __forceinline__ void elem(int n, double (&y)[3]) const {
-    double mu_[3], gp[3], ag[3];
+    double mu_[3], gp[3], ag[3] = {0.0, 0.0, 0.0};
     mass.elem(n, u, mu_);
     grad.elem(n, gp);
-    A.elem(n, g, ag);
+    const int k = n / A.sz, j = (n - k * A.sz) / A.sy, i = n - k * A.sz - j * A.sy;
+    if (i >= lo[0] && i <= hi[0] && j >= lo[1] && j <= hi[1] && k >= lo[2] && k <= hi[2]) A.elem(n, g, ag);
 #pragma unroll
     for (int d = 0; d < 3; ++d) y[d] = mu_[d] - gp[d] - ag[d];
   }
 };
+using S1RhsElem = S1RhsElemT<>;
 
 // Explicit advection on the composite mesh:
 // (rho/dt) M u_d - rho C(u^n) u_d - G_d p - A' g_d with A' = (rho/dt) M + mu K.

@@ -23,6 +23,7 @@
 #include "zblock.hpp"
 #include "mg.hpp"
 #include "composite.hpp"
+#include "conv.hpp"
 #include "ib_pcg.hpp"
 #include "strain.hpp"
 #include "wss.hpp"
@@ -175,8 +176,12 @@ struct ibfe_ctx {
   // state and fields (node-0 pointers; velocities have 3 planes)
   double *u = nullptr, *p = nullptr, *u_next = nullptr, *p_next = nullptr;
   double *g = nullptr, *ustar = nullptr, *uib = nullptr, *phi = nullptr;
-  double* coef64 = nullptr;
+  double* coef64 = nullptr;     // assembled advection-diffusion stencil (advdiff 1)
   float* coef32 = nullptr;
+  double* dinvS64 = nullptr;     // matrix-free form: inverse Jacobi diagonal of the rows
+  float* dinvS32 = nullptr;
+  double* w64 = nullptr;         // u^n copied per step: the matrix-free operators' advecting velocity
+  float* w32 = nullptr;          // (FP64, and FP32 in mixed mode)
   double* w[10] = {};   // FP64 Krylov work vectors, 3 planes each
   float* v32[10] = {};  // FP32 Krylov work vectors (mixed mode), 3 planes each
   double* compact = nullptr;
@@ -224,6 +229,7 @@ struct ibfe_ctx {
   int64_t* inlet_ids = nullptr;
   int32_t* lift_rows = nullptr;   // free rows next to an inlet-table node
   int nlift = 0;
+  int lift_lo[3] = {1, 1, 1}, lift_hi[3] = {0, 0, 0};  // refined: lattice box of the rows that see g
   double* inlet_shape = nullptr;
 
   // reductions
@@ -642,12 +648,15 @@ int setup_device(ibfe_ctx& c) {
   if ((rc = c.field(&c.phi, 1))) return rc;
   if ((rc = c.field(&c.delta, 3))) return rc;
   const int ncoef = P.refined ? 54 : 27;
-  if ((rc = c.field(&c.coef64, ncoef))) return rc;
+  const bool stencil = P.params.advdiff == 1 || P.params.advection == 1;
+  if (stencil && (rc = c.field(&c.coef64, ncoef))) return rc;
+  if (!stencil && ((rc = c.field(&c.dinvS64, 1)) || (rc = c.field(&c.w64, 3)))) return rc;
   for (int i = 0; i < 10; ++i)
     if ((rc = c.field(&c.w[i], 3))) return rc;
   if (P.refined && (rc = setup_refined(c))) return rc;
   if (P.params.precision == 1) {
-    if ((rc = c.field(&c.coef32, ncoef))) return rc;
+    if (stencil && (rc = c.field(&c.coef32, ncoef))) return rc;
+    if (!stencil && ((rc = c.field(&c.dinvS32, 1)) || (rc = c.field(&c.w32, 3)))) return rc;
     for (int i = 0; i < 10; ++i)
       if ((rc = c.field(&c.v32[i], 3))) return rc;
   }
@@ -700,6 +709,22 @@ int setup_device(ibfe_ctx& c) {
   }
   if (!P.inlet_ids.empty()) {
     if ((rc = c.upload(&c.inlet_ids, P.inlet_ids.data(), P.inlet_ids.size()))) return rc;
+    if (P.refined) {
+      // the inlet-table nodes' bounding box widened by 4 lattice steps
+      const int64_t ext[3] = {P.sy - 1, P.sz / P.sy - 1, P.N / P.sz - 1};
+      int64_t lo[3] = {ext[0], ext[1], ext[2]}, hi[3] = {0, 0, 0};
+      for (int64_t id : P.inlet_ids) {
+        const int64_t q[3] = {id % P.sy, (id % P.sz) / P.sy, id / P.sz};
+        for (int a = 0; a < 3; ++a) {
+          lo[a] = std::min(lo[a], q[a]);
+          hi[a] = std::max(hi[a], q[a]);
+        }
+      }
+      for (int a = 0; a < 3; ++a) {
+        c.lift_lo[a] = int(std::max<int64_t>(0, lo[a] - 4));
+        c.lift_hi[a] = int(std::min<int64_t>(ext[a], hi[a] + 4));
+      }
+    }
     if (!P.refined) {
       // the rows that see g: free nodes with an inlet-table node among their 27 neighbours
       std::vector<int32_t> rows;
@@ -818,8 +843,12 @@ int hang_prepare(ibfe_ctx& c, const Op& op, T* x, const KScal* sc) {
   CHECK_LAUNCH();
   return IBFE_OK;
 }
+template <typename T, class B>
+int pre_apply(ibfe_ctx& c, const OpCStencilStrain<T, B>& op, T* x, const KScal* sc) {
+  return hang_prepare<T>(c, op, x, sc);
+}
 template <typename T>
-int pre_apply(ibfe_ctx& c, const OpCStencilStrain<T>& op, T* x, const KScal* sc) {
+int pre_apply(ibfe_ctx& c, const OpCConv<T>& op, T* x, const KScal* sc) {
   return hang_prepare<T>(c, op, x, sc);
 }
 template <typename T>
@@ -1247,6 +1276,108 @@ OpCStencilStrain<T> cstrain_op(const ibfe_ctx& c, const T* coef, uint32_t rowbit
   op.stride = c.stride;
   op.yh = op.base.yh;
   return op;
+}
+
+// The matrix-free tentative-velocity operator: rows from the cell bits and u^n
+// (FP64 u, or its FP32 copy w32 for the inner solves).
+template <typename T>
+OpConv<T> conv_op(const ibfe_ctx& c, uint32_t rowbit) {
+  const Plan& P = c.plan;
+  const double rdt = P.params.rho / P.params.dt, mu = P.params.mu;
+  OpConv<T> op{};
+  op.emask = c.emask;
+  op.flags = c.flags;
+  op.rowbit = rowbit;
+  op.sy = int(P.sy);
+  op.sz = int(P.sz);
+  op.stride = c.stride;
+  for (int t = 0; t < 4; ++t) op.c[t] = T(rdt * c.fc.m[t] + mu * c.fc.k[t]);
+  op.rh2 = T(P.params.rho * P.h * P.h);
+  if constexpr (std::is_same<T, double>::value) {
+    op.w = c.w64;
+    op.dinv = c.dinvS64;
+  } else {
+    op.w = c.w32;
+    op.dinv = c.dinvS32;
+  }
+  return op;
+}
+
+template <typename T>
+OpConvStrain<T> conv_strain_op(const ibfe_ctx& c, uint32_t rowbit) {
+  OpConvStrain<T> op{};
+  op.base = conv_op<T>(c, rowbit);
+  op.mu = T(c.plan.params.mu);
+  op.h = T(c.plan.h);
+  op.stride = c.stride;
+  return op;
+}
+
+template <typename T>
+OpCConv<T> cconv_op(const ibfe_ctx& c, uint32_t rowbit) {
+  const Plan& P = c.plan;
+  const double rdt = P.params.rho / P.params.dt, mu = P.params.mu;
+  OpCConv<T> op{};
+  op.emask = c.emask;
+  op.cmask = c.cmask;
+  op.flags = c.flags;
+  op.rowbit = rowbit;
+  op.sy = int(P.sy);
+  op.sz = int(P.sz);
+  op.stride = c.stride;
+  for (int t = 0; t < 4; ++t) {
+    op.cf[t] = T(rdt * c.fc.m[t] + mu * c.fc.k[t]);
+    op.cc[t] = T(rdt * c.fcc.m[t] + mu * c.fcc.k[t]);
+  }
+  op.rh2f = T(P.params.rho * P.h * P.h);
+  op.rh2c = T(P.params.rho * P.hb * P.hb);
+  if constexpr (std::is_same<T, double>::value) {
+    op.w = c.w64;
+    op.dinv = c.dinvS64;
+  } else {
+    op.w = c.w32;
+    op.dinv = c.dinvS32;
+  }
+  op.ch = children_of(c);
+  op.pw = RefBufs<T>::pw(c);
+  op.yh = RefBufs<T>::yh(c);
+  return op;
+}
+
+template <typename T>
+OpCStencilStrain<T, OpCConv<T>> cconv_strain_op(const ibfe_ctx& c, uint32_t rowbit) {
+  OpCStencilStrain<T, OpCConv<T>> op{};
+  op.base = cconv_op<T>(c, rowbit);
+  op.emask = c.emask;
+  op.mu = T(c.plan.params.mu);
+  op.hf = T(c.plan.h);
+  op.hc = T(c.plan.hb);
+  op.stride = c.stride;
+  op.yh = op.base.yh;
+  return op;
+}
+
+// Per step, matrix-free form: the inverse Jacobi diagonal of the rows of P (FP64,
+// and with fp32 its FP32 rounding) and the FP32 copy of u^n (with fp32); u^n
+// holds its hanging values.
+int prep_s1_mf(ibfe_ctx& c, bool fp32) {
+  const int nb = blocks_for(c.nchunks);
+  float* d32 = fp32 ? c.dinvS32 : nullptr;
+  float* w32 = fp32 ? c.w32 : nullptr;
+  // the diagonal reads u^n itself (the copies are being written by the same kernel)
+  if (c.plan.refined) {
+    CConvDiag<double> f{cconv_op<double>(c, kFlagP), c.stride};
+    f.op.w = c.u;
+    klaunch<(k_conv_prep<CConvDiag<double>>)>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, f,
+                                              (const double*)c.u, c.w64, w32, c.dinvS64, d32);
+  } else {
+    ConvDiag<double> f{conv_op<double>(c, kFlagP), c.stride};
+    f.op.w = c.u;
+    klaunch<(k_conv_prep<ConvDiag<double>>)>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, f,
+                                             (const double*)c.u, c.w64, w32, c.dinvS64, d32);
+  }
+  CHECK_LAUNCH();
+  return IBFE_OK;
 }
 
 GradElem grad_elem(const ibfe_ctx& c, const double* x) {
@@ -1844,13 +1975,18 @@ int step_once(ibfe_ctx& c) {
   if (P.params.advection == 1) {
     if ((rc = s1_explicit(c))) return rc;
   } else {
-    if ((rc = build_s1(c))) return rc;
+    const bool mf = P.params.advdiff == 0;
+    if ((rc = mf ? prep_s1_mf(c, P.params.precision == 1) : build_s1(c))) return rc;
     double cm[4];
     for (int t = 0; t < 4; ++t) cm[t] = rho / dt * c.fc.m[t];
     klaunch<k_s1_rhs>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.emask,
                        c.flags, c.u, c.p, b1, S, sy, sz, cm[0], cm[1], cm[2], cm[3],
                        c.fc.g2[0], c.fc.g2[1], c.fc.g2[2]);
-    if (c.nlift > 0)
+    if (c.nlift > 0 && mf)
+      klaunch<(k_lift_rows<OpConv<double>>)>(c, dim3(blocks_lin(c.nlift)), dim3(kBlock), 0, c.stream, c.nlift,
+                                              (const int32_t*)c.lift_rows, conv_op<double>(c, kFlagF),
+                                              (const double*)c.g, b1);
+    else if (c.nlift > 0)
       klaunch<k_s1_lift>(c, dim3(blocks_lin(c.nlift)), dim3(kBlock), 0, c.stream, c.nlift,
                          (const int32_t*)c.lift_rows, (const uint8_t*)c.flags, (const double*)c.coef64,
                          (const double*)c.g, b1, S, sy, sz);
@@ -1874,8 +2010,12 @@ int step_once(ibfe_ctx& c) {
                            });
       return run_bicgstab<double>(c, op, b1, x1, c.w, kScS1, rtol, maxit, so);
     };
-    if (P.params.viscous == 1)
+    if (P.params.viscous == 1 && mf)
+      rc = solve(conv_strain_op<double>(c, kFlagF), conv_strain_op<float>(c, kFlagF));
+    else if (P.params.viscous == 1)
       rc = solve(strain_op<double>(c, c.coef64, kFlagF), strain_op<float>(c, c.coef32, kFlagF));
+    else if (mf)
+      rc = solve(conv_op<double>(c, kFlagF), conv_op<float>(c, kFlagF));
     else
       rc = solve(stencil_op<double>(c, c.coef64, kFlagF), stencil_op<float>(c, c.coef32, kFlagF));
     if (rc) return rc;
@@ -2151,16 +2291,22 @@ int step_once_refined(ibfe_ctx& c) {
   if (P.params.advection == 1) {
     if ((rc = s1_explicit_refined(c))) return rc;
   } else {
-    if ((rc = build_s1_refined(c))) return rc;
-    S1RhsElem f{};
-    f.mass = csym_op<double, 3>(c, rho / dt, 0.0, kFlagF, c.dinvM64);
-    f.A = cstencil_op<double>(c, c.coef64, kFlagF);
-    f.grad = grad_elem(c, c.p);
-    f.u = c.u;
-    f.g = c.g;
+    const bool mf = P.params.advdiff == 0;
     const bool strain = P.params.viscous == 1;
-    if (strain) {
-      S1RhsStrainElem<S1RhsElem> fs{};
+    // b1 = (rho/dt) M u^n - G p^n - A g (and the strain-rate lifting)
+    auto rhs = [&](auto A) -> int {
+      S1RhsElemT<decltype(A)> f{};
+      f.mass = csym_op<double, 3>(c, rho / dt, 0.0, kFlagF, c.dinvM64);
+      f.A = A;
+      f.grad = grad_elem(c, c.p);
+      f.u = c.u;
+      f.g = c.g;
+      for (int a = 0; a < 3; ++a) {
+        f.lo[a] = c.lift_lo[a];
+        f.hi[a] = c.lift_hi[a];
+      }
+      if (!strain) return comp_rows<double>(c, f, kFlagF, 0u, 1.0, b1);
+      S1RhsStrainElem<S1RhsElemT<decltype(A)>> fs{};
       fs.base = f;
       fs.emask = c.emask;
       fs.cmask = c.cmask;
@@ -2170,9 +2316,12 @@ int step_once_refined(ibfe_ctx& c) {
       fs.sy = int(P.sy);
       fs.sz = int(P.sz);
       fs.stride = c.stride;
-      if ((rc = comp_rows<double>(c, fs, kFlagF, 0u, 1.0, b1))) return rc;
-    } else if ((rc = comp_rows<double>(c, f, kFlagF, 0u, 1.0, b1))) {
-      return rc;
+      return comp_rows<double>(c, fs, kFlagF, 0u, 1.0, b1);
+    };
+    if (mf) {
+      if ((rc = prep_s1_mf(c, P.params.precision == 1)) || (rc = rhs(cconv_op<double>(c, kFlagF)))) return rc;
+    } else {
+      if ((rc = build_s1_refined(c)) || (rc = rhs(cstencil_op<double>(c, c.coef64, kFlagF)))) return rc;
     }
     klaunch<(k_masked_copy<double, double>)>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, c.flags, kFlagF, c.u, x1, 3, S);
     CHECK_LAUNCH();
@@ -2187,8 +2336,12 @@ int step_once_refined(ibfe_ctx& c) {
                            });
       return run_bicgstab<double>(c, op, b1, x1, c.w, kScS1, rtol, maxit, so);
     };
-    if (strain)
+    if (strain && mf)
+      rc = solve(cconv_strain_op<double>(c, kFlagF), cconv_strain_op<float>(c, kFlagF));
+    else if (strain)
       rc = solve(cstrain_op<double>(c, c.coef64, kFlagF), cstrain_op<float>(c, c.coef32, kFlagF));
+    else if (mf)
+      rc = solve(cconv_op<double>(c, kFlagF), cconv_op<float>(c, kFlagF));
     else
       rc = solve(cstencil_op<double>(c, c.coef64, kFlagF), cstencil_op<float>(c, c.coef32, kFlagF));
     if (rc) return rc;
@@ -2396,6 +2549,41 @@ int apply_refined(ibfe_ctx& C, int op, int precision, double* xin, double* yout,
     }
     case IBFE_OP_ADVDIFF: {
       nc_out = 3;
+      if (!C.coef64) {
+        // matrix-free context
+        if (precision == 1 && !C.w32) {
+          if ((rc = C.field(&C.w32, 3)) || (rc = C.field(&C.dinvS32, 1))) return rc;
+          if ((rc = ensure_fp32_work(C))) return rc;
+        }
+        if ((rc = fill_hanging<double>(C, C.u, 3))) return rc;
+        if ((rc = prep_s1_mf(C, precision == 1 || P.params.precision == 1))) return rc;
+        const bool strain = P.params.viscous == 1;
+        if (precision == 0) {
+          if ((rc = fill_hanging<double>(C, xin, 3))) return rc;
+          if (strain)
+            return comp_rows<double>(C, OpElem<double, OpCStencilStrain<double, OpCConv<double>>>{
+                                            cconv_strain_op<double>(C, kFlagP), xin},
+                                     kFlagP, 0u, 1.0, yout);
+          return comp_rows<double>(C, OpElem<double, OpCConv<double>>{cconv_op<double>(C, kFlagP), xin}, kFlagP,
+                                   0u, 1.0, yout);
+        }
+        float* x32 = C.v32[0];
+        float* y32 = C.v32[1];
+        klaunch<(k_masked_copy<double, float>)>(C, dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, xin, x32, 3, S);
+        CHECK_LAUNCH();
+        if ((rc = fill_hanging<float>(C, x32, 3))) return rc;
+        if (strain)
+          rc = comp_rows<float>(C, OpElem<float, OpCStencilStrain<float, OpCConv<float>>>{
+                                       cconv_strain_op<float>(C, kFlagP), x32},
+                                kFlagP, 0u, 1.0f, y32);
+        else
+          rc = comp_rows<float>(C, OpElem<float, OpCConv<float>>{cconv_op<float>(C, kFlagP), x32}, kFlagP, 0u,
+                                1.0f, y32);
+        if (rc) return rc;
+        klaunch<(k_masked_copy<float, double>)>(C, dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, y32, yout, 3, S);
+        CHECK_LAUNCH();
+        return IBFE_OK;
+      }
       if (precision == 1 && !C.coef32) {
         if ((rc = C.field(&C.coef32, 54))) return rc;
         if ((rc = ensure_fp32_work(C))) return rc;
@@ -3255,6 +3443,36 @@ int ibfe_apply(ibfe_ctx* c, int op, int precision, const double* x, double* y, i
       CHECK_LAUNCH();
       return copy_out(C, yout, 1, y, on_device);
     case IBFE_OP_ADVDIFF: {
+      if (!C.coef64) {
+        // matrix-free context
+        if (precision == 1 && !C.w32) {
+          if ((rc = C.field(&C.w32, 3)) || (rc = C.field(&C.dinvS32, 1))) return rc;
+          if ((rc = ensure_fp32_work(C))) return rc;
+        }
+        if ((rc = prep_s1_mf(C, precision == 1 || P.params.precision == 1))) return rc;
+        const bool strain = P.params.viscous == 1;
+        if (precision == 0) {
+          if (strain)
+            klaunch<(k_apply<double, 3, OpConvStrain<double>>)>(C, dim3(nb), dim3(kBlock), 0, C.stream, C.nl,
+                                                                 conv_strain_op<double>(C, kFlagP), xin, yout);
+          else
+            klaunch<(k_apply<double, 3, OpConv<double>>)>(C, dim3(nb), dim3(kBlock), 0, C.stream, C.nl,
+                                                           conv_op<double>(C, kFlagP), xin, yout);
+        } else {
+          float* x32 = C.v32[0];
+          float* y32 = C.v32[1];
+          klaunch<(k_masked_copy<double, float>)>(C, dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, xin, x32, 3, S);
+          if (strain)
+            klaunch<(k_apply<float, 3, OpConvStrain<float>>)>(C, dim3(nb), dim3(kBlock), 0, C.stream, C.nl,
+                                                               conv_strain_op<float>(C, kFlagP), x32, y32);
+          else
+            klaunch<(k_apply<float, 3, OpConv<float>>)>(C, dim3(nb), dim3(kBlock), 0, C.stream, C.nl,
+                                                         conv_op<float>(C, kFlagP), x32, y32);
+          klaunch<(k_masked_copy<float, double>)>(C, dim3(nb), dim3(kBlock), 0, C.stream, C.nl, C.flags, kFlagP, y32, yout, 3, S);
+        }
+        CHECK_LAUNCH();
+        return copy_out(C, yout, 3, y, on_device);
+      }
       float* c32 = C.coef32;
       if (precision == 1 && !c32) {
         // FP64-mode context: build an FP32 copy of the stencil in extra work space

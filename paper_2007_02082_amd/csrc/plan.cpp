@@ -122,6 +122,10 @@ int build_plan(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* para
     return IBFE_EINVAL;
   }
   P.refined = grid->refine_cell != nullptr;
+  if (pr.advdiff < 0 || pr.advdiff > 1) {
+    err = "advdiff must be 0 (matrix-free) or 1 (assembled stencil)";
+    return IBFE_EINVAL;
+  }
   if (pr.viscous < 0 || pr.viscous > 1) {
     err = "viscous must be 0 (mu (grad u, grad v)) or 1 (2 mu (eps(u), eps(v)))";
     return IBFE_EINVAL;

@@ -57,13 +57,20 @@ size_t footprint_of(const ibfe_grid& g, int64_t M, const ibfe_params& pr) {
   const int64_t N = sz * (f * g.nz + 1);
   const int64_t halo = ((f * (sz + sy + 1) + 63) / 64) * 64;
   const int64_t stride = 2 * halo + ((N + 63) / 64) * 64;
-  double bytes = double(stride) * (75.0 * 8.0 + 3.0);              // FP64 fields, node bytes
-  if (pr.precision == 1) bytes += double(stride) * 57.0 * 4.0;     // FP32 stencil and work space
-  if (ref) {
-    // coarse stencil planes, coarse cell bits, parent slots, inverse diagonals
-    bytes += double(stride) * (27.0 * 8.0 + 1.0 + 4.0 + 24.0);
-    if (pr.precision == 1) bytes += double(stride) * 27.0 * 4.0;
+  // the assembled advection-diffusion stencil (27 planes, 54 when refined, FP64
+  // and in mixed mode FP32) or, matrix-free, the inverse diagonals and u^n in FP32
+  const bool stencil = pr.advdiff == 1 || pr.advection == 1;
+  const double planes = ref ? 54.0 : 27.0;
+  double bytes = double(stride) * (48.0 * 8.0 + 3.0);              // FP64 fields, node bytes
+  if (pr.precision == 1) bytes += double(stride) * 30.0 * 4.0;     // FP32 work space
+  if (stencil) {
+    bytes += double(stride) * planes * 8.0;
+    if (pr.precision == 1) bytes += double(stride) * planes * 4.0;
+  } else {
+    bytes += double(stride) * (32.0 + (pr.precision == 1 ? 16.0 : 0.0));
   }
+  // refined: coarse cell bits, parent slots, inverse diagonals
+  if (ref) bytes += double(stride) * (1.0 + 4.0 + 24.0);
   if (pr.precond >= 1) bytes += 0.15 * double(stride) * (5.0 * (pr.precision == 1 ? 4 : 8) + 2.0);
   // IB arrays: stencils, spreading lists and G, held at the sizes a rebuild for
   // moved points may need (64 pairs per point, four times G's entries)

@@ -137,14 +137,15 @@ struct OpSymStrain {
   __device__ __forceinline__ T inv_diag(int n) const { return base.inv_diag(n); }
 };
 
-// The stored composite tentative-velocity stencil (54 planes) plus the
-// strain-rate cross blocks of the fine cells (stride 1, h/2) and of the
-// unrefined cells (stride 2, h); the hanging constraint enters through the
-// element rows as for OpCStencil.
-template <typename T>
+// The composite tentative-velocity operator (the stored 54-plane stencil, or
+// the matrix-free form with the same member names) plus the strain-rate cross
+// blocks of the fine cells (stride 1, h/2) and of the unrefined cells (stride
+// 2, h); the hanging constraint enters through the element rows as for
+// OpCStencil.
+template <typename T, class Base = OpCStencil<T, 3>>
 struct OpCStencilStrain {
   static constexpr int kNC = 3;
-  OpCStencil<T, 3> base;
+  Base base;
   const uint8_t* emask;
   T mu, hf, hc;
   int64_t stride;

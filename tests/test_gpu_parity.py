@@ -117,11 +117,13 @@ def test_gradient_divergence_interp_spread_fp64():
     s.close()
 
 
+@pytest.mark.parametrize("advdiff", [0, 1])
 @pytest.mark.parametrize("precision,tol", [(0, 1e-13), (1, 2e-6)])
-def test_advection_diffusion_apply(precision, tol):
+def test_advection_diffusion_apply(precision, tol, advdiff):
+    # advdiff 0: rows formed on the fly (matrix-free); 1: assembled stencil
     case = _ops_case()
     pr = ipcs.Problem.from_case(case)
-    s = make_solver(case)
+    s = make_solver(case, advdiff=advdiff)
     P = pr.sets.P
     rng = np.random.default_rng(13)
     u = rng.standard_normal((3, P.size))
@@ -260,16 +262,18 @@ def test_full_size_advection_diffusion_rows_sampled(c2):
     uf[:, P] = u
     xf = np.zeros((3, c2.N))
     xf[:, P] = x
-    s = make_solver(c2)
-    s.set_state(u.ravel(), np.zeros(P.size), 0.0)
     pick = rng.choice(P.size, 300, replace=False)
     ref, bound = _advdiff_rows(sets, xf, uf, P[pick], c2.nx, c2.ny, c2.h, c2.rho, c2.mu, c2.dt)
-    for prec, tol in ((0, 1e-12), (1, 1e-5)):
-        y = s.apply(ibfe.OP_ADVDIFF, x.ravel(), prec).reshape(3, -1)
-        err = np.abs(y[:, pick] - ref) / bound
-        say("full-size advection-diffusion apply, precision", prec, "max rel", float(err.max()))
-        assert np.all(err <= tol)
-    s.close()
+    for advdiff in (0, 1):  # matrix-free rows, then the assembled stencil
+        s = make_solver(c2, advdiff=advdiff)
+        s.set_state(u.ravel(), np.zeros(P.size), 0.0)
+        for prec, tol in ((0, 1e-12), (1, 1e-5)):
+            y = s.apply(ibfe.OP_ADVDIFF, x.ravel(), prec).reshape(3, -1)
+            err = np.abs(y[:, pick] - ref) / bound
+            say("full-size advection-diffusion apply, advdiff", advdiff, "precision", prec,
+                "max rel", float(err.max()))
+            assert np.all(err <= tol)
+        s.close()
 
 
 def _c2_steps(c2, sets, precision, tol):
@@ -393,6 +397,9 @@ def test_step_parity_multigrid_small(make, precision, tol):
     say("case", case.name, "multigrid, precision", precision)
     _, out = run_pair(case, 3, precision=precision, precond=2)
     _check_steps(out, tol, case.name + "/mg")
+    # the same steps with the assembled advection-diffusion stencil
+    _, out = run_pair(case, 3, precision=precision, precond=2, advdiff=1)
+    _check_steps(out, tol, case.name + "/mg/stencil")
 
 
 @pytest.mark.parametrize("precision,tol", [(0, TOL64), (1, TOL_MIXED)])
@@ -442,11 +449,12 @@ def test_step_parity_explicit_advection(make, precision, tol):
 # strain-rate viscous form 2 mu (eps(u), eps(v)) (components coupled in S1)
 # ---------------------------------------------------------------------------
 
+@pytest.mark.parametrize("advdiff", [0, 1])
 @pytest.mark.parametrize("precision,tol", [(0, 1e-13), (1, 2e-6)])
-def test_advection_diffusion_apply_strain(precision, tol):
+def test_advection_diffusion_apply_strain(precision, tol, advdiff):
     case = _ops_case()
     pr = ipcs.Problem.from_case(case, viscous=1)
-    s = make_solver(case, viscous=1)
+    s = make_solver(case, viscous=1, advdiff=advdiff)
     P = pr.sets.P
     rng = np.random.default_rng(17)
     u = rng.standard_normal((3, P.size))

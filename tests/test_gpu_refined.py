@@ -75,11 +75,13 @@ def test_refined_gradient_divergence_fp64():
     s.close()
 
 
+@pytest.mark.parametrize("advdiff", [0, 1])
 @pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-6)])
-def test_refined_advection_diffusion_apply(precision, tol):
+def test_refined_advection_diffusion_apply(precision, tol, advdiff):
+    # advdiff 0: rows formed on the fly (matrix-free); 1: assembled 54-plane stencil
     case = _cyl()
     pr = ipcs.Problem.from_case(case)
-    s = make_solver(case)
+    s = make_solver(case, advdiff=advdiff)
     P = pr.sets.P
     rng = np.random.default_rng(23)
     a = rng.standard_normal((3, P.size))
@@ -98,13 +100,14 @@ def test_refined_advection_diffusion_apply(precision, tol):
     s.close()
 
 
+@pytest.mark.parametrize("advdiff", [0, 1])
 @pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-6)])
-def test_refined_advection_diffusion_apply_strain(precision, tol):
+def test_refined_advection_diffusion_apply_strain(precision, tol, advdiff):
     # the composite operator plus the strain-rate cross blocks mu X_dc of the fine
     # and of the unrefined cells (components coupled)
     case = _cyl()
     pr = ipcs.Problem.from_case(case, viscous=1)
-    s = make_solver(case, viscous=1)
+    s = make_solver(case, viscous=1, advdiff=advdiff)
     P = pr.sets.P
     rng = np.random.default_rng(29)
     a = rng.standard_normal((3, P.size))
@@ -169,6 +172,8 @@ def test_refined_step_parity_multigrid(make, precision, tol):
     say("refined multigrid", case.name, precision)
     _, out = run_pair(case, 3, precision=precision, precond=2)
     _check(out, tol, f"{case.name} mg p{precision}")
+    _, out = run_pair(case, 2, precision=precision, precond=2, advdiff=1)
+    _check(out, tol, f"{case.name} mg p{precision} stencil")
     _, out_j = run_pair(case, 1, precision=precision, precond=0)
     mg_it, j_it = out[0]["stats"]["s3_iters"], out_j[0]["stats"]["s3_iters"]
     say("s3 iterations: multigrid", mg_it, "Jacobi", j_it)
