@@ -137,7 +137,7 @@ def cpu_baseline(seconds_hint: float = 15.0) -> dict:
                       f"node ratio {scale:.2f} to the 64x64x512 grid"}
 
 
-def serve_stream(n: int, slots: int, nsteps: int) -> dict:
+def serve_stream(n: int, slots: int, nsteps: int, batch_window_us: float | None = None) -> dict:
     """Serving stream: n seeded requests (cylinder / aneurysm / Y-branch vessels, radius
     0.4-2.5, grids 32^3 .. 128x128x256, 50 steps each, mixed precision, multigrid) submitted
     at their Poisson arrival times (4 per second) to a server with `slots` concurrent
@@ -150,7 +150,7 @@ def serve_stream(n: int, slots: int, nsteps: int) -> dict:
 
     reqs = synth.request_stream(n=n, nsteps=nsteps)
     kws = [ibfe.inputs_from_case(r.case, precision=1, precond=2) for r in reqs]
-    srv = ibfe.Server(max_slots=slots)
+    srv = ibfe.Server(max_slots=slots, batch_window_us=batch_window_us)
     ids = []
     t0 = time.perf_counter()
     for r, kw in zip(reqs, kws):
@@ -160,6 +160,7 @@ def serve_stream(n: int, slots: int, nsteps: int) -> dict:
         ids.append(srv.submit(nsteps, **kw))
     res = [srv.wait(i) for i in ids]
     peak = srv.peak_concurrency()
+    bstats = srv.batch_stats()
     for i, r in zip(ids, res):
         if r["status"] == ibfe.REQ_DONE:
             srv.fetch(i, r["n_u"], r["n_p"])
@@ -180,7 +181,8 @@ def serve_stream(n: int, slots: int, nsteps: int) -> dict:
             "p99_latency_s": round(nearest_rank(lat, 0.99), 3), "mean_latency_s": round(float(lat.mean()), 3),
             "mean_admission_wait_s": round(float(wait.mean()), 3),
             "mean_concurrency": round(busy / span, 2), "peak_concurrency": peak,
-            "wall_s": round(span, 2), "grid_nodes_total": int(sum(nodes))}
+            "wall_s": round(span, 2), "grid_nodes_total": int(sum(nodes)),
+            "batch_window_us": batch_window_us, "mass_batches": bstats}
 
 
 def poiseuille_study(levels=(0, 1, 2), pressures=(1.0, 2.0), tol=1e-8, max_steps=8000, domain="box") -> list:
@@ -462,6 +464,9 @@ def main() -> int:
                     help="kernels listed from the profile pass (largest summed time first)")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-batch-window-us", type=float, default=200.0,
+                    help="batching window of the second serving run (mass-correction kernels joined "
+                         "across running requests)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the run, copy a device buffer of this size 5 times (a plain copy "
                          "kernel of known size for scaling hardware byte counters)")
@@ -571,6 +576,10 @@ def main() -> int:
     if not args.no_serve:
         out["serving"] = serve_stream(args.serve_requests, args.serve_slots, 50)
         print(f"[bench] serving: {out['serving']['solves_per_s']} solves/s", file=sys.stderr, flush=True)
+        out["serving_batched"] = serve_stream(args.serve_requests, args.serve_slots, 50,
+                                              batch_window_us=args.serve_batch_window_us)
+        print(f"[bench] serving, batched mass steps: {out['serving_batched']['solves_per_s']} solves/s",
+              file=sys.stderr, flush=True)
     if args.e1:
         out["poiseuille_e1"] = poiseuille_study(domain=args.e1_domain)
     if not args.no_cpu_baseline:

@@ -395,6 +395,35 @@ int ibfe_apply(ibfe_ctx* ctx, int op, int precision, const double* x, double* y,
 void ibfe_destroy(ibfe_ctx* ctx);
 const char* ibfe_last_error(void);
 
+/* ---- batched kernels across contexts ------------------------------------- */
+
+/*
+ * A batcher joins the consistent-mass Chebyshev sequences of several contexts
+ * into single launches (the velocity correction, the last step of the scheme
+ * of Section 2.2 and of the algorithm of Section 2.4, is taken with the
+ * consistent mass and solved by Chebyshev iteration inside the FP64
+ * refinement): each Chebyshev step is one kernel over the column items of every
+ * context that reached that stage, instead of one kernel per context.  It
+ * applies to mixed-precision contexts on uniform grids (others keep their own
+ * launches).  A context whose thread reaches the stage waits up to
+ * window_us microseconds for the other attached contexts to join (not at all
+ * when it is the only one attached); the batch runs on the batcher's own
+ * stream, ordered after each member's earlier work by events, and each member's
+ * stream waits for the batch before its next kernel.  Every node's arithmetic
+ * is that of the context's own launch, so results are bitwise identical with
+ * and without a batcher.  Contexts that step from different host threads share
+ * it; a context must be detached (or destroyed) before its batcher is.
+ */
+typedef struct ibfe_batcher ibfe_batcher;
+/* Create a batcher on the current HIP device. */
+int ibfe_batcher_create(double window_us, ibfe_batcher** out);
+/* Attach ctx to batcher b (NULL detaches); IBFE_EINVAL for another device. */
+int ibfe_attach_batcher(ibfe_ctx* ctx, ibfe_batcher* b);
+/* Batches launched, member sequences they carried, and the widest batch. */
+int ibfe_batcher_stats(ibfe_batcher* b, int64_t* batches, int64_t* members, int32_t* widest);
+/* Release a batcher with no attached context (IBFE_EINVAL otherwise). */
+int ibfe_batcher_destroy(ibfe_batcher* b);
+
 /* ---- serving: continuous batching of independent flow solves ------------- */
 
 /* One flow solve: the inputs of ibfe_create plus the number of steps, starting
@@ -448,6 +477,12 @@ int ibfe_server_wait(ibfe_server* srv, int64_t id, double timeout_s, ibfe_result
 int ibfe_server_fetch(ibfe_server* srv, int64_t id, double* u, double* p, int64_t* node_ids);
 /* Largest number of requests that ran at the same time so far. */
 int ibfe_server_peak_concurrency(const ibfe_server* srv, int32_t* peak);
+/* Batch the mass-correction kernels of the running requests (a batcher with
+ * the given window shared by every request admitted after the call; see
+ * ibfe_batcher_create); call before submitting.  stats as ibfe_batcher_stats
+ * (zeros when batching is off). */
+int ibfe_server_set_batching(ibfe_server* srv, double window_us);
+int ibfe_server_batch_stats(ibfe_server* srv, int64_t* batches, int64_t* members, int32_t* widest);
 /* Finish running requests, fail the queued ones, release everything. */
 void ibfe_server_destroy(ibfe_server* srv);
 

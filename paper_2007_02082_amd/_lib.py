@@ -126,7 +126,15 @@ SIGNATURES = {
     "ibfe_server_wait": (C.c_int, [C.c_void_p, C.c_int64, C.c_double, C.POINTER(Result)]),
     "ibfe_server_fetch": (C.c_int, [C.c_void_p, C.c_int64, dp, dp, i64p]),
     "ibfe_server_peak_concurrency": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "ibfe_server_set_batching": (C.c_int, [C.c_void_p, C.c_double]),
+    "ibfe_server_batch_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                          C.POINTER(C.c_int32)]),
     "ibfe_server_destroy": (None, [C.c_void_p]),
+    "ibfe_batcher_create": (C.c_int, [C.c_double, C.POINTER(C.c_void_p)]),
+    "ibfe_attach_batcher": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "ibfe_batcher_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                     C.POINTER(C.c_int32)]),
+    "ibfe_batcher_destroy": (C.c_int, [C.c_void_p]),
 }
 
 _lib = None
@@ -513,15 +521,49 @@ def request_footprint(**kw) -> int:
     return out.value
 
 
+class Batcher:
+    """Joins the mass-correction Chebyshev launches of the attached solvers
+    (ibfe_batcher_*); solvers stepping from different threads batch together."""
+
+    def __init__(self, window_us: float = 100.0):
+        h = C.c_void_p()
+        check(load().ibfe_batcher_create(float(window_us), C.byref(h)))
+        self._h = h
+
+    def attach(self, solver):
+        check(load().ibfe_attach_batcher(solver._h, self._h))
+
+    @staticmethod
+    def detach(solver):
+        check(load().ibfe_attach_batcher(solver._h, None))
+
+    def stats(self) -> dict:
+        b, m, w = C.c_int64(), C.c_int64(), C.c_int32()
+        check(load().ibfe_batcher_stats(self._h, C.byref(b), C.byref(m), C.byref(w)))
+        return {"batches": b.value, "members": m.value, "widest": w.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            check(load().ibfe_batcher_destroy(self._h))
+            self._h = None
+
+
 class Server:
     """Continuous-batching server (ibfe_server_*): requests run concurrently in
     worker slots, each on its own HIP stream, admitted by device footprint."""
 
-    def __init__(self, budget_bytes: int = 0, max_slots: int = 4):
+    def __init__(self, budget_bytes: int = 0, max_slots: int = 4, batch_window_us: float | None = None):
         lib = load()
         h = C.c_void_p()
         check(lib.ibfe_server_create(C.c_size_t(int(budget_bytes)), int(max_slots), C.byref(h)))
         self._h = h
+        if batch_window_us is not None:
+            check(lib.ibfe_server_set_batching(self._h, float(batch_window_us)))
+
+    def batch_stats(self) -> dict:
+        b, m, w = C.c_int64(), C.c_int64(), C.c_int32()
+        check(load().ibfe_server_batch_stats(self._h, C.byref(b), C.byref(m), C.byref(w)))
+        return {"batches": b.value, "members": m.value, "widest": w.value}
 
     def submit(self, nsteps: int, t0: float = 0.0, **kw) -> int:
         inp = _Inputs(**kw)

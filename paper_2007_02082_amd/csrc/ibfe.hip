@@ -12,6 +12,8 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <chrono>
+#include <condition_variable>
 #include <mutex>
 #include <string>
 #include <type_traits>
@@ -216,6 +218,8 @@ struct ibfe_ctx {
     int64_t g_cap = 0;         // entries of G the device arrays hold
   } mv;
   int device = 0;          // HIP device the context was created on
+  ibfe_batcher* batcher = nullptr;            // joins the mass-correction sequences of contexts
+  hipEvent_t ev_ready = nullptr, ev_done = nullptr;
   bool ib_valid = true;  // false after a failed ibfe_set_points
   // ibv[1] holds the force of the last step: the initial guess of the next force
   // solve (the right-hand side U_B - I u* changes little from step to step)
@@ -281,6 +285,8 @@ struct ibfe_ctx {
   int est[kNumScal] = {};
 
   ~ibfe_ctx() {
+    if (ev_ready) (void)hipEventDestroy(ev_ready);
+    if (ev_done) (void)hipEventDestroy(ev_done);
     for (auto& kv : graph_cache) (void)hipGraphExecDestroy(kv.second);
     for (void* b : blocks) {
       if (user_alloc)
@@ -1849,6 +1855,128 @@ int run_cheb_mass(ibfe_ctx& c, const T* b, T* x, T* xalt, T* d, int iters) {
   return IBFE_OK;
 }
 
+}  // namespace
+extern "C" {
+struct ibfe_batcher {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  double window_us = 0.0;
+  std::mutex mu;
+  std::condition_variable cv;
+  struct Pending {
+    ibfe::ChebJob<float> job{};
+    ibfe_ctx* ctx = nullptr;
+    bool launched = false;
+    int rc = 0;
+  };
+  std::vector<Pending*> queue;
+  int members = 0;       // attached contexts
+  bool leading = false;  // a member thread is forming and launching a batch
+  int64_t batches = 0, jobs = 0;
+  int32_t widest = 0;
+};
+}  // extern "C"
+namespace {
+
+// Launch one batch on the batcher's stream: after every member's ready event,
+// the Chebyshev steps 1 .. max iters - 1 over all members' items, then each
+// member's done event.
+int launch_cheb_batch(ibfe_batcher& B, const std::vector<ibfe_batcher::Pending*>& take) {
+  const double theta = 0.5 * (kMassLmax + kMassLmin), delta = 0.5 * (kMassLmax - kMassLmin);
+  const double sigma = theta / delta;
+  ChebBatch<float> cb{};
+  cb.njobs = int(take.size());
+  cb.off[0] = 0;
+  int maxit = 1;
+  for (int i = 0; i < cb.njobs; ++i) {
+    HIP_TRY(hipStreamWaitEvent(B.stream, take[i]->ctx->ev_ready, 0));
+    cb.job[i] = take[i]->job;
+    cb.off[i + 1] = cb.off[i] + cb.job[i].nblocks;
+    maxit = std::max(maxit, cb.job[i].iters);
+  }
+  double rho = 1.0 / sigma;
+  for (int k = 1; k < maxit; ++k) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    const float c1 = float(rn * rho), c2 = float(2.0 * rn / delta);
+    rho = rn;
+    hipLaunchKernelGGL((k_zb_cheb_batch<float, 3>), dim3(cb.off[cb.njobs]), dim3(kBlock), 0, B.stream, cb, k, c1,
+                       c2);
+  }
+  HIP_TRY(hipGetLastError());
+  for (auto* p : take) HIP_TRY(hipEventRecord(p->ctx->ev_done, B.stream));
+  return IBFE_OK;
+}
+
+// run_cheb_mass<float> through the context's batcher: the zero-start step on
+// the context's stream, then steps 1 .. iters - 1 in a batch with the other
+// members that reach this stage within the window.
+int batched_cheb_mass(ibfe_ctx& c, const float* b, float* x, float* xalt, float* d, int iters) {
+  const Plan& P = c.plan;
+  const double theta = 0.5 * (kMassLmax + kMassLmin);
+  float* cur0 = ((iters - 1) % 2 == 0) ? x : xalt;
+  float* alt0 = cur0 == x ? xalt : x;
+  klaunch<(k_mg_cheb0<float, 3>)>(c, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
+                     c.nl, (const uint8_t*)c.emask, (const uint8_t*)c.flags,
+                     float(c.fc.m[0]), float(1.0 / theta), b, d, cur0, (const KScal*)nullptr, kFlagF, c.stride);
+  CHECK_LAUNCH();
+  if (iters <= 1) return IBFE_OK;
+  ibfe_batcher& B = *c.batcher;
+  ibfe_batcher::Pending me;
+  ChebJob<float>& J = me.job;
+  J.items = c.zitems;
+  J.nitems = c.nzitems;
+  J.nblocks = red_blocks(c.nzitems);
+  J.iters = iters;
+  J.op.emask = c.emask;
+  J.op.flags = c.flags;
+  J.op.rowbit = kFlagF;
+  J.op.sy = int(P.sy);
+  J.op.sz = int(P.sz);
+  J.op.nplanes = P.nz + 1;
+  J.op.lanes = c.zlanes;
+  J.op.zb = c.zb;
+  for (int t = 0; t < 4; ++t) J.op.c[t] = float(c.fc.m[t]);
+  J.b = b;
+  J.d = d;
+  J.buf0 = cur0;
+  J.buf1 = alt0;
+  J.stride = c.stride;
+  me.ctx = &c;
+  HIP_TRY(hipEventRecord(c.ev_ready, c.stream));
+  std::unique_lock<std::mutex> lk(B.mu);
+  B.queue.push_back(&me);
+  B.cv.notify_all();
+  while (!me.launched) {
+    if (B.leading) {
+      B.cv.wait(lk, [&] { return me.launched || !B.leading; });
+      continue;
+    }
+    B.leading = true;
+    const int want = std::min(B.members, kMaxBatch);
+    B.cv.wait_for(lk, std::chrono::duration<double, std::micro>(B.window_us),
+                  [&] { return int(B.queue.size()) >= want; });
+    const size_t n = std::min<size_t>(B.queue.size(), kMaxBatch);
+    std::vector<ibfe_batcher::Pending*> take(B.queue.begin(), B.queue.begin() + n);
+    B.queue.erase(B.queue.begin(), B.queue.begin() + n);
+    lk.unlock();
+    const int rc = launch_cheb_batch(B, take);
+    lk.lock();
+    for (auto* p : take) {
+      p->rc = rc;
+      p->launched = true;
+    }
+    B.batches += 1;
+    B.jobs += int64_t(n);
+    B.widest = std::max(B.widest, int32_t(n));
+    B.leading = false;
+    B.cv.notify_all();
+  }
+  lk.unlock();
+  if (me.rc) return me.rc;
+  HIP_TRY(hipStreamWaitEvent(c.stream, c.ev_done, 0));
+  return IBFE_OK;
+}
+
 // -------------------------------------------------------------------------
 // one time step
 // -------------------------------------------------------------------------
@@ -2111,6 +2239,7 @@ int step_once(ibfe_ctx& c) {
       rc = run_refined(c, op, kFlagF, 3, b4, delta, v[8], v[9], rtol, so,
                        [&](const float* r32, float* d32, double tol, SolveOut& o) {
                          o.iters = mass_cheb_steps(tol);
+                         if (c.batcher) return batched_cheb_mass(c, r32, d32, v[0], v[1], o.iters);
                          return run_cheb_mass<float>(c, r32, d32, v[0], v[1], o.iters);
                        });
     } else {
@@ -3531,7 +3660,61 @@ int ibfe_apply(ibfe_ctx* c, int op, int precision, const double* x, double* y, i
 void ibfe_destroy(ibfe_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  (void)ibfe_attach_batcher(c, nullptr);
   delete c;
+}
+
+int ibfe_batcher_create(double window_us, ibfe_batcher** out) {
+  if (!out || !(window_us >= 0.0)) return fail(IBFE_EINVAL, "need window_us >= 0 and an output pointer");
+  *out = nullptr;
+  std::unique_ptr<ibfe_batcher> B(new (std::nothrow) ibfe_batcher());
+  if (!B) return fail(IBFE_ENOMEM, "host allocation failed");
+  HIP_TRY(hipGetDevice(&B->device));
+  HIP_TRY(hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking));
+  B->window_us = window_us;
+  *out = B.release();
+  return IBFE_OK;
+}
+
+int ibfe_attach_batcher(ibfe_ctx* c, ibfe_batcher* b) {
+  if (!c) return fail(IBFE_EINVAL, "NULL context");
+  if (b && b->device != c->device) return fail(IBFE_EINVAL, "batcher and context are on different devices");
+  if (c->batcher == b) return IBFE_OK;
+  if (c->batcher) {
+    (void)hipStreamSynchronize(c->stream);
+    std::lock_guard<std::mutex> lk(c->batcher->mu);
+    c->batcher->members -= 1;
+    c->batcher->cv.notify_all();
+    c->batcher = nullptr;
+  }
+  if (!b) return IBFE_OK;
+  if (!c->ev_ready) HIP_TRY(hipEventCreateWithFlags(&c->ev_ready, hipEventDisableTiming));
+  if (!c->ev_done) HIP_TRY(hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming));
+  std::lock_guard<std::mutex> lk(b->mu);
+  b->members += 1;
+  c->batcher = b;
+  return IBFE_OK;
+}
+
+int ibfe_batcher_stats(ibfe_batcher* b, int64_t* batches, int64_t* members, int32_t* widest) {
+  if (!b) return fail(IBFE_EINVAL, "NULL batcher");
+  std::lock_guard<std::mutex> lk(b->mu);
+  if (batches) *batches = b->batches;
+  if (members) *members = b->jobs;
+  if (widest) *widest = b->widest;
+  return IBFE_OK;
+}
+
+int ibfe_batcher_destroy(ibfe_batcher* b) {
+  if (!b) return IBFE_OK;
+  {
+    std::lock_guard<std::mutex> lk(b->mu);
+    if (b->members != 0) return fail(IBFE_EINVAL, "contexts are still attached to the batcher");
+  }
+  (void)hipStreamSynchronize(b->stream);
+  (void)hipStreamDestroy(b->stream);
+  delete b;
+  return IBFE_OK;
 }
 
 }  // extern "C"

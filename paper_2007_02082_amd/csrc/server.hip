@@ -2,8 +2,10 @@
 // footprint into a fixed number of worker slots.  Each slot owns a HIP stream
 // and drives one request at a time through the C ABI (create, step, read,
 // destroy); slots run concurrently, so the kernels of admitted requests overlap
-// on the GPU.  A request's arithmetic does not depend on what else runs, so its
-// result is identical alone and in a mix.
+// on the GPU.  With batching on, the running requests share a batcher that
+// joins their mass-correction Chebyshev steps into single launches over all of
+// their column items.  A request's arithmetic does not depend on what else
+// runs, so its result is identical alone and in a mix.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -88,6 +90,7 @@ double now_s(std::chrono::steady_clock::time_point t0) {
 
 struct ibfe_server {
   int device = 0;
+  ibfe_batcher* batcher = nullptr;  // joins the running requests' mass-correction kernels
   size_t budget = 0, used = 0;
   int32_t running = 0, peak = 0;
   bool stop = false;
@@ -102,9 +105,10 @@ struct ibfe_server {
 
 namespace {
 
-void run_job(Job& J, hipStream_t stream) {
+void run_job(Job& J, hipStream_t stream, ibfe_batcher* batcher) {
   ibfe_ctx* ctx = nullptr;
   int rc = ibfe_create(&J.grid, &J.ib, &J.params, &J.inlet, nullptr, stream, &ctx);
+  if (rc == IBFE_OK && batcher) rc = ibfe_attach_batcher(ctx, batcher);
   if (rc == IBFE_OK) {
     int64_t nu = 0, np = 0;
     ibfe_num_nodes(ctx, &nu, &np);
@@ -146,7 +150,7 @@ void worker_loop(ibfe_server* S) {
       job->res.status = IBFE_REQ_RUNNING;
       job->res.t_admit = now_s(S->t0);
     }
-    run_job(*job, stream);
+    run_job(*job, stream, S->batcher);
     {
       std::lock_guard<std::mutex> lk(S->mu);
       S->used -= job->footprint;
@@ -295,6 +299,25 @@ int ibfe_server_fetch(ibfe_server* S, int64_t id, double* u, double* p, int64_t*
   return IBFE_OK;
 }
 
+int ibfe_server_set_batching(ibfe_server* S, double window_us) {
+  if (!S) return sfail(IBFE_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (S->batcher) return sfail(IBFE_EINVAL, "batching is already on");
+  if (S->running != 0 || !S->queue.empty()) return sfail(IBFE_EINVAL, "set batching before submitting");
+  return ibfe_batcher_create(window_us, &S->batcher);
+}
+
+int ibfe_server_batch_stats(ibfe_server* S, int64_t* batches, int64_t* members, int32_t* widest) {
+  if (!S) return sfail(IBFE_EINVAL, "NULL argument");
+  if (!S->batcher) {
+    if (batches) *batches = 0;
+    if (members) *members = 0;
+    if (widest) *widest = 0;
+    return IBFE_OK;
+  }
+  return ibfe_batcher_stats(S->batcher, batches, members, widest);
+}
+
 int ibfe_server_peak_concurrency(const ibfe_server* S, int32_t* peak) {
   if (!S || !peak) return sfail(IBFE_EINVAL, "NULL argument");
   *peak = S->peak;
@@ -316,6 +339,7 @@ void ibfe_server_destroy(ibfe_server* S) {
   }
   S->cv.notify_all();
   for (auto& t : S->workers) t.join();
+  if (S->batcher) (void)ibfe_batcher_destroy(S->batcher);
   delete S;
 }
 

@@ -50,15 +50,16 @@ constexpr int kZBPF = 2;
 // component) pairs over different wavefronts was measured slower: 32 -> 35 us
 // for the pulsatile mass step.)
 // epi(component, node, lane_ok, row, emask, Ax, x_centre, extra_row).
+// zb_walk_range walks the items [cr.c0, cr.c1); zb_walk, this block's share of
+// all nitems items.
 template <typename T, int NC, class Epi>
-__device__ __forceinline__ void zb_walk(const int* __restrict__ items, int nitems, const ZOp<T>& op,
-                                        const T* __restrict__ x0, int64_t stride, Epi& epi,
-                                        const T* __restrict__ extra0 = nullptr) {
+__device__ __forceinline__ void zb_walk_range(const int* __restrict__ items, ChunkRange cr, const ZOp<T>& op,
+                                              const T* __restrict__ x0, int64_t stride, Epi& epi,
+                                              const T* __restrict__ extra0 = nullptr) {
   constexpr int R = kZBPF + 3;
   const int lane = threadIdx.x & 63;
   const int sy = op.sy, sz = op.sz;
   const T c[4] = {op.c[0], op.c[1], op.c[2], op.c[3]};
-  const ChunkRange cr = block_chunks(nitems);
   for (int it = cr.c0 + int(threadIdx.x >> 6); it < cr.c1; it += kWaves)
   for (int comp = 0; comp < NC; ++comp) {
     const T* __restrict__ x = x0 + comp * stride;
@@ -104,6 +105,13 @@ __device__ __forceinline__ void zb_walk(const int* __restrict__ items, int nitem
       epi(comp, node, lane_ok, rw, e, y, w[(k + 1) % R][4], (fl[k % R] & kFlagExtra) != 0u);
     }
   }
+}
+
+template <typename T, int NC, class Epi>
+__device__ __forceinline__ void zb_walk(const int* __restrict__ items, int nitems, const ZOp<T>& op,
+                                        const T* __restrict__ x0, int64_t stride, Epi& epi,
+                                        const T* __restrict__ extra0 = nullptr) {
+  zb_walk_range<T, NC>(items, block_chunks(nitems), op, x0, stride, epi, extra0);
 }
 
 // q = A p on rows (0 elsewhere), partial p.q; NC identical components.
@@ -159,16 +167,11 @@ __global__ __launch_bounds__(kBlock) void k_zb_resid(const int* __restrict__ ite
 // Chebyshev-Jacobi step on rows, NC identical components (planes of `stride`):
 //   d <- c1 d + c2 D^-1 (b - A x_in),  x_out = x_in + d;  0 off rows.
 // With DOT, also the partial sum of b . x_out (the preconditioned residual dot).
-template <typename T, bool DOT, int NC = 1>
-__global__ __launch_bounds__(kBlock) void k_zb_cheb(const int* __restrict__ items, int nitems, ZOp<T> op,
-                                                    const T* __restrict__ x_in, const T* __restrict__ b,
-                                                    T* __restrict__ d, T* __restrict__ x_out, T c1, T c2,
-                                                    double* __restrict__ partials, const KScal* sc,
-                                                    int64_t stride = 0, int zero_off_rows = 1) {
-  // zero_off_rows = 0: d and x_out already hold 0 off rows (written by an earlier
-  // step of the same sequence), so only the rows are stored
-  if (sc && sc->done) return;
-  double dot[1] = {0.0};
+template <typename T, bool DOT, int NC>
+__device__ __forceinline__ void zb_cheb_body(const int* __restrict__ items, ChunkRange cr, const ZOp<T>& op,
+                                             const T* __restrict__ x_in, const T* __restrict__ b,
+                                             T* __restrict__ d, T* __restrict__ x_out, T c1, T c2,
+                                             double (&dot)[1], int64_t stride, int zero_off_rows) {
   const T c0 = op.c[0];
   auto epi = [&](int q, int node, bool ok, bool rw, uint32_t e, T y, T xc, bool xrow) {
     if (!ok) return;
@@ -189,8 +192,63 @@ __global__ __launch_bounds__(kBlock) void k_zb_cheb(const int* __restrict__ item
       x_out[i] = T(0);
     }
   };
-  zb_walk<T, NC>(items, nitems, op, x_in, stride, epi, op.extra);
+  zb_walk_range<T, NC>(items, cr, op, x_in, stride, epi, op.extra);
+}
+
+template <typename T, bool DOT, int NC = 1>
+__global__ __launch_bounds__(kBlock) void k_zb_cheb(const int* __restrict__ items, int nitems, ZOp<T> op,
+                                                    const T* __restrict__ x_in, const T* __restrict__ b,
+                                                    T* __restrict__ d, T* __restrict__ x_out, T c1, T c2,
+                                                    double* __restrict__ partials, const KScal* sc,
+                                                    int64_t stride = 0, int zero_off_rows = 1) {
+  // zero_off_rows = 0: d and x_out already hold 0 off rows (written by an earlier
+  // step of the same sequence), so only the rows are stored
+  if (sc && sc->done) return;
+  double dot[1] = {0.0};
+  zb_cheb_body<T, DOT, NC>(items, block_chunks(nitems), op, x_in, b, d, x_out, c1, c2, dot, stride,
+                           zero_off_rows);
   if (DOT) block_partials<1>(dot, partials);
+}
+
+// Chebyshev step k of the consistent-mass correction for several requests at
+// once (one launch over the column items of all of them).  Request r owns the
+// logical blocks [off[r], off[r+1]) and splits its items over them as its own
+// launch would; a request whose sequence is shorter than k returns at once.
+// Buffer buf0 holds the iterate after the odd steps' inputs: step k reads buf0
+// when k is odd and writes buf1, and the other way round when k is even.
+constexpr int kMaxBatch = 16;
+template <typename T>
+struct ChebJob {
+  const int* items;
+  int nitems, nblocks, iters;
+  ZOp<T> op;
+  const T* b;
+  T* d;
+  T* buf0;
+  T* buf1;
+  int64_t stride;
+};
+template <typename T>
+struct ChebBatch {
+  ChebJob<T> job[kMaxBatch];
+  int off[kMaxBatch + 1];
+  int njobs;
+};
+template <typename T, int NC>
+__global__ __launch_bounds__(kBlock) void k_zb_cheb_batch(ChebBatch<T> B, int k, T c1, T c2) {
+  const int L = xcd_block();
+  int r = 0;
+  while (r + 1 < B.njobs && L >= B.off[r + 1]) ++r;
+  const ChebJob<T>& J = B.job[r];
+  if (k >= J.iters) return;
+  const int lb = L - B.off[r];
+  const int per = J.nitems / J.nblocks, rem = J.nitems % J.nblocks;
+  const int c0 = lb * per + (lb < rem ? lb : rem);
+  const ChunkRange cr{c0, c0 + per + (lb < rem ? 1 : 0)};
+  double dot[1] = {0.0};
+  const T* x_in = (k & 1) ? J.buf0 : J.buf1;
+  T* x_out = (k & 1) ? J.buf1 : J.buf0;
+  zb_cheb_body<T, false, NC>(J.items, cr, J.op, x_in, J.b, J.d, x_out, c1, c2, dot, J.stride, k == 1 ? 1 : 0);
 }
 
 }  // namespace ibfe
