@@ -15,7 +15,9 @@ start and end HIP events on the library's stream; the durations are summed per k
 and `roofline` reports the kernel with the largest summed time against the HBM peak,
 with its algorithmic bytes per dispatch (`kernel_model`).  By default the line also
 carries the relative error of the mixed-precision state against an FP64 run of the same
-steps, the rates of the other two workloads and the serving stream (64 requests).
+steps, the rates of the other two workloads and the serving stream (64 requests arriving
+at 4 per second, served plain and with the mass-correction kernels batched across the
+running requests, and the same requests submitted at once with twice the slots).
 """
 from __future__ import annotations
 
@@ -137,7 +139,8 @@ def cpu_baseline(seconds_hint: float = 15.0) -> dict:
                       f"node ratio {scale:.2f} to the 64x64x512 grid"}
 
 
-def serve_stream(n: int, slots: int, nsteps: int, batch_window_us: float | None = None) -> dict:
+def serve_stream(n: int, slots: int, nsteps: int, batch_window_us: float | None = None,
+                 rate: float = 4.0) -> dict:
     """Serving stream: n seeded requests (cylinder / aneurysm / Y-branch vessels, radius
     0.4-2.5, grids 32^3 .. 128x128x256, 50 steps each, mixed precision, multigrid) submitted
     at their Poisson arrival times (4 per second) to a server with `slots` concurrent
@@ -148,7 +151,7 @@ def serve_stream(n: int, slots: int, nsteps: int, batch_window_us: float | None 
     import paper_2007_02082_amd as ibfe
     import synth
 
-    reqs = synth.request_stream(n=n, nsteps=nsteps)
+    reqs = synth.request_stream(n=n, rate=rate, nsteps=nsteps)
     kws = [ibfe.inputs_from_case(r.case, precision=1, precond=2) for r in reqs]
     srv = ibfe.Server(max_slots=slots, batch_window_us=batch_window_us)
     ids = []
@@ -579,6 +582,10 @@ def main() -> int:
         out["serving_batched"] = serve_stream(args.serve_requests, args.serve_slots, 50,
                                               batch_window_us=args.serve_batch_window_us)
         print(f"[bench] serving, batched mass steps: {out['serving_batched']['solves_per_s']} solves/s",
+              file=sys.stderr, flush=True)
+        # capacity: the same requests all submitted at once, twice the slots
+        out["serving_saturated"] = serve_stream(args.serve_requests, 2 * args.serve_slots, 50, rate=1e9)
+        print(f"[bench] serving, all submitted at once: {out['serving_saturated']['solves_per_s']} solves/s",
               file=sys.stderr, flush=True)
     if args.e1:
         out["poiseuille_e1"] = poiseuille_study(domain=args.e1_domain)
