@@ -188,13 +188,17 @@ def serve_stream(n: int, slots: int, nsteps: int, batch_window_us: float | None 
             "batch_window_us": batch_window_us, "mass_batches": bstats}
 
 
-def poiseuille_study(levels=(0, 1, 2), pressures=(1.0, 2.0), tol=1e-8, max_steps=8000, domain="box") -> list:
+def poiseuille_study(levels=(0, 1, 2), pressures=(1.0, 2.0), tol=1e-8, max_steps=8000, domain="box",
+                     band_h=None) -> list:
     """The pressure-driven tube of Section 3.1 on the three grids of Table 1 (h = 1, 0.5,
     0.25 mm), run with the library's steady-state driver until the step-to-step NRMSE of
     every velocity component is below tol.  Reported per run: steps, wall time, the
-    centre-line speed against U_max = R^2 p_in / (4 mu L), and the maximum and
+    centre-line speed against U_max = R^2 p_in / (4 mu L), the maximum and
     root-mean-square velocity errors against the Poiseuille profile over the nodes
-    inside the tube; a run whose step fails is reported with the step it reached."""
+    inside the tube, and the parabola u_z = U (1 - r^2 / R_eff^2) fitted (least squares)
+    to the nodes inside the tube between 0.2 L and 0.8 L (the effective radius at which
+    the immersed wall holds the flow); a run whose step fails is reported with the step
+    it reached.  band_h: cells within band_h * h of the wall split 2:1."""
     import numpy as np
 
     import paper_2007_02082_amd as ibfe
@@ -204,7 +208,9 @@ def poiseuille_study(levels=(0, 1, 2), pressures=(1.0, 2.0), tol=1e-8, max_steps
     rows = []
     for level in levels:
         for p_in in pressures:
-            case = synth.poiseuille_e1(level, p_in=p_in, domain=domain)
+            h = 1e-3 / 2 ** level
+            case = synth.poiseuille_e1(level, p_in=p_in, domain=domain,
+                                       refine_band=None if band_h is None else band_h * h)
             s = ibfe.Solver(**ibfe.inputs_from_case(case, precision=1, precond=2))
             ids = s.node_ids()
             s.set_state(np.zeros(3 * s.n_u), np.ascontiguousarray(case.p0[ids]), 0.0)
@@ -241,6 +247,13 @@ def poiseuille_study(levels=(0, 1, 2), pressures=(1.0, 2.0), tol=1e-8, max_steps
                    "Re": e1.RHO * float(u[2][inside].max()) * e1.L / e1.MU,
                    "L_inf": float(np.abs(e).max()), "L_2": float(np.sqrt((e * e).sum()) / e.shape[1]),
                    "transverse_max": float(np.abs(u[:2][:, inside]).max())}
+            mid = inside & (xyz[:, 2] > 0.2 * e1.L) & (xyz[:, 2] < 0.8 * e1.L)
+            if err is None and mid.sum() > 3:
+                rr = xyz[mid, 0] ** 2 + xyz[mid, 1] ** 2
+                a, b = np.linalg.lstsq(np.stack([np.ones_like(rr), rr], 1), u[2][mid], rcond=None)[0]
+                row["fit_U"] = float(a)
+                row["fit_R_eff"] = float(np.sqrt(-a / b)) if b < 0 < a else None
+            row["band_h"] = band_h
             if err is not None:
                 row["error"] = err
             rows.append(row)
@@ -457,6 +470,10 @@ def main() -> int:
     ap.add_argument("--e1", action="store_true",
                     help="also run the pressure-driven Poiseuille study of Section 3.1 to steady "
                          "state on the three grids of Table 1 (after the timed steps)")
+    ap.add_argument("--e1-band", type=float, default=None,
+                    help="split the cells within this many h of the tube wall 2:1 in the --e1 runs")
+    ap.add_argument("--e1-levels", type=int, nargs="+", default=[0, 1, 2],
+                    help="grid levels of the --e1 runs (0, 1, 2 = h 1, 0.5, 0.25 mm)")
     ap.add_argument("--e1-domain", choices=["box", "reduced"], default="box",
                     help="the pressure-driven tube in the whole box (the paper's mesh, default) or in the "
                          "domain reduced to the tube")
@@ -588,7 +605,8 @@ def main() -> int:
         print(f"[bench] serving, all submitted at once: {out['serving_saturated']['solves_per_s']} solves/s",
               file=sys.stderr, flush=True)
     if args.e1:
-        out["poiseuille_e1"] = poiseuille_study(domain=args.e1_domain)
+        out["poiseuille_e1"] = poiseuille_study(domain=args.e1_domain, band_h=args.e1_band,
+                                                levels=tuple(args.e1_levels))
     if not args.no_cpu_baseline:
         n_p = res["sizes"]["n_p"]
         out["cpu_baseline"] = {"pulsatile": cpu_baseline, "aneurysm": lambda: cpu_baseline_aneurysm(n_p),

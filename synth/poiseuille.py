@@ -25,8 +25,13 @@ DT = 2.5e-3
 
 
 def poiseuille_e1(level: int = 0, p_in: float = 1.0, spacing: float = 1.5, nsteps: int = 3,
-                  domain: str = "reduced") -> Case:
+                  domain: str = "reduced", refine_band: float | None = None) -> Case:
     """The tube on grid `level` (0, 1, 2 = h 1, 0.5, 0.25 mm).
+
+    With refine_band (metres), the base cells whose centre lies within refine_band of
+    the wall radius R are split 2:1: every node array lives on the fine lattice of
+    spacing h/2, and the Lagrangian points follow the fine spacing (the IB kernel uses
+    the lattice spacing).
 
     * mask: nodes with x^2 + y^2 < R^2 (domain = "reduced"), or every node of the box
       (domain = "box": the whole box is fluid and the immersed wall separates the
@@ -40,22 +45,32 @@ def poiseuille_e1(level: int = 0, p_in: float = 1.0, spacing: float = 1.5, nstep
     f = 2 ** int(level)
     h = 1e-3 / f
     nxy, nz = 12 * f, 50 * f
-    per_ring = int(round(2.0 * math.pi * R / (spacing * h)))
-    rings = int(round(L / (spacing * h)))
+    refine = None
+    if refine_band is not None:
+        ci = (np.arange(nxy) + 0.5) * h - HALF_WIDTH
+        _, cy, cx = np.meshgrid(np.arange(nz), ci, ci, indexing="ij")
+        refine = (np.abs(np.sqrt(cx * cx + cy * cy) - R) <= refine_band).astype(np.uint8).ravel()
+    g = 2 if refine is not None else 1      # lattice steps per base cell
+    hl = h / g                              # lattice spacing (the IB kernel's h)
+    per_ring = int(round(2.0 * math.pi * R / (spacing * hl)))
+    rings = int(round(L / (spacing * hl)))
     c = Case(
         name=f"poiseuille_e1_h{h:g}_p{p_in:g}", nx=nxy, ny=nxy, nz=nz, h=h,
         origin=np.array([-HALF_WIDTH, -HALF_WIDTH, 0.0]),
         node_mask=np.zeros(0, np.uint8), bc_tag=None, X=np.zeros((0, 3)), dS=0.0, U_B=None,
         rho=RHO, mu=MU, dt=DT, nsteps=nsteps, inlet_K=0, inlet_omega=0.0,
         inlet_ids=np.zeros(0, np.int64), inlet_shape=np.zeros((1, 0, 3)),
-        u0=np.zeros((3, 0)), p0=np.zeros(0))
+        u0=np.zeros((3, 0)), p0=np.zeros(0), refine_cell=refine)
+    if refine is not None:
+        c.name += f"_band{refine_band:g}"
+    nxy, nz = g * nxy, g * nz               # lattice cells
     N = c.N
     k = np.arange(N)
     i = k % (nxy + 1)
     j = (k // (nxy + 1)) % (nxy + 1)
     kz = k // ((nxy + 1) * (nxy + 1))
-    x = c.origin[0] + i * h
-    y = c.origin[1] + j * h
+    x = c.origin[0] + i * hl
+    y = c.origin[1] + j * hl
     disk = (x * x + y * y < R * R)
     if domain == "reduced":
         mask = disk.astype(np.uint8)

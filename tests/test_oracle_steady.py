@@ -115,3 +115,23 @@ def test_e1_grids_and_pressure_boundaries():
     inlet = disk & (xyz[:, 2] == 0.0)
     assert np.all(p[inlet] == 1.0) and np.all(p[disk & ~inlet] == 0.0)
     assert u[2][c.node_mask == 1].mean() > 0.0
+
+
+def test_e1_wall_band_lattice():
+    # the 2:1 wall band variant: arrays on the fine lattice, the split cells are those
+    # whose centre lies within the band of the wall radius, the pressure disks and the
+    # wall rings follow the fine spacing
+    from synth import poiseuille as e1
+    band = 2e-3
+    c = synth.poiseuille_e1(0, p_in=1.0, domain="box", refine_band=band)
+    assert c.refine_cell is not None and c.N == 25 * 25 * 101
+    ci = (np.arange(12) + 0.5) * 1e-3 - e1.HALF_WIDTH
+    _, cy, cx = np.meshgrid(np.arange(50), ci, ci, indexing="ij")
+    expect = np.abs(np.hypot(cx, cy) - e1.R) <= band
+    assert np.array_equal(c.refine_cell.astype(bool), expect.ravel())
+    xyz = c.node_coords()
+    disk = (xyz[:, 0] ** 2 + xyz[:, 1] ** 2 < e1.R ** 2) & ((xyz[:, 2] == 0.0) | (np.abs(xyz[:, 2] - e1.L) < 1e-12))
+    assert np.array_equal(c.bc_tag == synth.TAG_OUTLET, disk)
+    plain = synth.poiseuille_e1(0, p_in=1.0, domain="box")
+    assert c.M > 3.5 * plain.M       # points at 1.5 fine spacings: about 4 times as many
+    assert c.dS * c.M == pytest.approx(2.0 * np.pi * e1.R * e1.L)
