@@ -171,6 +171,13 @@ struct ibfe_ctx {
   int* zitems = nullptr;          // z-blocked column items (plane block of each item)
   int* zlanes = nullptr;          // their 64 in-plane positions (-1 = none)
   int nzitems = 0, zb = kZBPlanes;
+  // the walked positions' cell bits and flags in walk order, and mixed mode's
+  // walk-order vectors of the mass correction (its residual and Chebyshev d)
+  uint8_t* em_im = nullptr;
+  uint8_t* fl_im = nullptr;
+  int64_t imstride = 0;
+  float* rim = nullptr;
+  float* dim = nullptr;
   int64_t* pids = nullptr;
   double* float_count = nullptr;
   double* float_means = nullptr;
@@ -395,9 +402,11 @@ int collect_kernel_times(ibfe_ctx& c) {
     KTimer::Acc& a = kt.acc[name];
     a.ms += ms;
     a.launches += 1;
-    static const std::string tail = ", false, 3>";
-    const bool mass = name.rfind("k_zb_cheb<", 0) == 0 && name.size() > tail.size() &&
-                      name.compare(name.size() - tail.size(), tail.size(), tail) == 0;
+    // the mass Chebyshev step (three components, lattice or walk-order vectors)
+    auto ends = [&](const std::string& tail) {
+      return name.size() > tail.size() && name.compare(name.size() - tail.size(), tail.size(), tail) == 0;
+    };
+    const bool mass = name.rfind("k_zb_cheb<", 0) == 0 && (ends(", false, 3>") || ends(", false, 3, true>"));
     const bool pressure = name == "k_cg_q_zb<float, 1>" || name == "k_cg_q_zb<double, 1>";
     if (mass) {
       c.stats.mass_apply_ms += ms;
@@ -634,6 +643,25 @@ int setup_device(ibfe_ctx& c) {
     c.nzitems = int(items.size());
     if ((rc = c.upload(&c.zitems, items.data(), items.size()))) return rc;
     if ((rc = c.upload(&c.zlanes, lanes.data(), lanes.size()))) return rc;
+    // walk order: (item, plane, lane) -> cell bits and flags of that lattice position
+    c.imstride = int64_t(c.nzitems) * c.zb * 64;
+    std::vector<uint8_t> emi(size_t(std::max<int64_t>(1, c.imstride)), 0), fli(emi.size(), 0);
+    for (int it = 0; it < c.nzitems; ++it) {
+      const int k0 = items[it] * c.zb;
+      const int kend = std::min<int>(c.zb, int(P.nz + 1) - k0);
+      for (int lane = 0; lane < 64; ++lane) {
+        const int inplane = lanes[size_t(it) * 64 + lane];
+        if (inplane < 0) continue;
+        for (int k = 0; k < kend; ++k) {
+          const int64_t node = int64_t(k0 + k) * P.sz + inplane;
+          const size_t im = (size_t(it) * c.zb + k) * 64 + lane;
+          emi[im] = P.emask[node];
+          fli[im] = fl[node];
+        }
+      }
+    }
+    if ((rc = c.upload(&c.em_im, emi.data(), emi.size()))) return rc;
+    if ((rc = c.upload(&c.fl_im, fli.data(), fli.size()))) return rc;
   }
   if ((rc = c.upload(&c.pids, P.P_ids.data(), P.P_ids.size()))) return rc;
   {
@@ -665,6 +693,11 @@ int setup_device(ibfe_ctx& c) {
     if (!stencil && ((rc = c.field(&c.dinvS32, 1)) || (rc = c.field(&c.w32, 3)))) return rc;
     for (int i = 0; i < 10; ++i)
       if ((rc = c.field(&c.v32[i], 3))) return rc;
+    void* base = nullptr;
+    if ((rc = c.dalloc(&base, sizeof(float) * 3 * std::max<int64_t>(1, c.imstride)))) return rc;
+    c.rim = reinterpret_cast<float*>(base);
+    if ((rc = c.dalloc(&base, sizeof(float) * 3 * std::max<int64_t>(1, c.imstride)))) return rc;
+    c.dim = reinterpret_cast<float*>(base);
   }
   {
     void* base = nullptr;
@@ -812,6 +845,17 @@ int next_batch(int est, int done_so_far) {
   return 8;
 }
 
+// The walk-order cell bits and flags serve every walk over the context's own
+// column items with the context's own bits and flags.
+template <typename T>
+ZOp<T> with_im(const ibfe_ctx& c, ZOp<T> z) {
+  if (z.lanes == c.zlanes && z.emask == c.emask && z.flags == c.flags) {
+    z.em_im = c.em_im;
+    z.fl_im = c.fl_im;
+  }
+  return z;
+}
+
 // q = A p with partial p.q; returns the number of partials written.
 template <typename T, class Op>
 int launch_q(ibfe_ctx& c, const Op& op, NodeList nl, const T* p, T* q, const KScal* sc) {
@@ -824,6 +868,7 @@ int launch_q(ibfe_ctx& c, const OpSym<T, NC>& op, NodeList, const T* p, T* q, co
   const int nr = red_blocks(c.nzitems);
   ZOp<T> z{op.emask, op.flags, op.rowbit, op.sy, op.sz, c.plan.nz + 1,
            {op.c[0], op.c[1], op.c[2], op.c[3]}, c.zb, c.zlanes};
+  z = with_im(c, z);
   klaunch<(k_cg_q_zb<T, NC>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems, c.nzitems, z,
                               op.stride, p, q, c.partials, sc);
   return nr;
@@ -1041,7 +1086,7 @@ ZOp<T> zcomp_op(const ibfe_ctx& c, const OpCSym<T, NC>& o);
 // leaves r in FP32 in r32.
 template <class Op64, typename TR>
 int ir_residual(ibfe_ctx& c, const Op64& op, const double* b, double* x, TR* r32, double& rr,
-                double& bb) {
+                double& bb, bool r_im = false) {
   int nr = red_blocks(c.nchunks);
   int prc;
   if ((prc = pre_apply(c, op, x, (const KScal*)nullptr))) return prc;
@@ -1057,18 +1102,30 @@ int ir_residual(ibfe_ctx& c, const Op64& op, const double* b, double* x, TR* r32
     z.lanes = c.zlanes;
     z.zb = c.zb;
     for (int t = 0; t < 4; ++t) z.c[t] = op.c[t];
+    z = with_im(c, z);
     nr = red_blocks(c.nzitems);
-    klaunch<(k_zb_residual<TR, Op64::kNC>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
-                       c.nzitems, z, b, (const double*)x, r32, op.stride, c.partials);
+    if (r_im)
+      klaunch<(k_zb_residual<TR, Op64::kNC, true>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
+                         c.nzitems, z, b, (const double*)x, r32, op.stride, c.partials, c.imstride);
+    else
+      klaunch<(k_zb_residual<TR, Op64::kNC>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
+                         c.nzitems, z, b, (const double*)x, r32, op.stride, c.partials, int64_t(0));
   } else if constexpr (std::is_same<Op64, OpCSym<double, 1>>::value ||
                        std::is_same<Op64, OpCSym<double, 3>>::value) {
     // composite symmetric forms: the fine-cell walk plus the precomputed extra rows
     launch_extra<double, Op64::kNC>(c, op, (const double*)x, (const KScal*)nullptr);
     const ZOp<double> z = zcomp_op(c, op);
     nr = red_blocks(c.nzitems);
-    klaunch<(k_zb_residual<TR, Op64::kNC>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
-                                            c.nzitems, z, b, (const double*)x, r32, op.stride, c.partials);
+    if (r_im)
+      klaunch<(k_zb_residual<TR, Op64::kNC, true>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
+                                                    c.nzitems, z, b, (const double*)x, r32, op.stride, c.partials,
+                                                    c.imstride);
+    else
+      klaunch<(k_zb_residual<TR, Op64::kNC>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
+                                              c.nzitems, z, b, (const double*)x, r32, op.stride, c.partials,
+                                              int64_t(0));
   } else {
+    if (r_im) return fail(IBFE_EINVAL, "internal: walk-order residual of a per-node operator");
     klaunch<(k_residual<Op64, TR>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, c.nl, op, b,
                        x, r32, c.partials);
   }
@@ -1088,13 +1145,13 @@ int ir_residual(ibfe_ctx& c, const Op64& op, const double* b, double* x, TR* r32
 // initial guess (zero off rows).
 template <class Op64, class Inner>
 int run_refined(ibfe_ctx& c, const Op64& op64, uint32_t rowbit, int nc, const double* b, double* x,
-                float* r32, float* d32, double rtol, SolveOut& out, Inner&& inner) {
+                float* r32, float* d32, double rtol, SolveOut& out, Inner&& inner, bool r_im = false) {
   const int nb = blocks_for(c.nchunks);
   int total = 0;
   double rr = 0, bb = 0, res = 0;
   int sweeps = 0;
   for (; sweeps <= kMaxSweeps; ++sweeps) {
-    int rc = ir_residual(c, op64, b, x, r32, rr, bb);
+    int rc = ir_residual(c, op64, b, x, r32, rr, bb, r_im);
     if (rc) return rc;
     res = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
     if (res <= rtol || sweeps == kMaxSweeps) break;
@@ -1233,6 +1290,7 @@ ZOp<T> zcomp_op(const ibfe_ctx& c, const OpCSym<T, NC>& o) {
   z.lanes = c.zlanes;
   z.dinv = o.dinv;
   z.extra = RefBufs<T>::extra(c);
+  z = with_im(c, z);
   return z;
 }
 
@@ -1432,16 +1490,22 @@ int cheb_steps(double tol, double lmin, double lmax) {
 }
 
 // x = Cheb_iters(b) from x = 0 for any operator on [lmin, lmax] of D^-1 A.
-template <typename T, class Op>
+// With IMV, b and d are in walk order (the mass correction's residual and
+// Chebyshev direction), x and xalt on the lattice.
+template <typename T, class Op, bool IMV = false>
 int run_cheb_gen(ibfe_ctx& c, const Op& op, const T* b, T* x, T* xalt, T* d, int iters, double lmin,
                  double lmax) {
   const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
   T* cur = ((iters - 1) % 2 == 0) ? x : xalt;
   T* alt = cur == x ? xalt : x;
-  klaunch<(k_cheb0_gen<T, Op>)>(c, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
-                     c.nl, op, b, d, cur, T(1.0 / theta), (const KScal*)nullptr);
   const int nr = red_blocks(c.nzitems);
   const ZOp<T> zop = zcomp_op(c, op);
+  if (IMV)
+    klaunch<(k_cheb0_im<T, Op::kNC>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems, c.nzitems,
+                                      zop, b, d, cur, T(1.0 / theta), c.stride, c.imstride);
+  else
+    klaunch<(k_cheb0_gen<T, Op>)>(c, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
+                       c.nl, op, b, d, cur, T(1.0 / theta), (const KScal*)nullptr);
   int rc;
   T* const cur0 = cur;
   T* const alt0 = alt;
@@ -1457,15 +1521,16 @@ int run_cheb_gen(ibfe_ctx& c, const Op& op, const T* b, T* x, T* xalt, T* d, int
       launch_extra<T, NC>(c, op, cur, (const KScal*)nullptr);
       // the first step writes the zeros off the rows into the second buffer (the
       // zero-start step did so for the first one and for d, over every active node)
-      klaunch<(k_zb_cheb<T, false, NC>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
-                                         c.nzitems, zop, (const T*)cur, b, d, alt, c1, c2, c.partials,
-                                         (const KScal*)nullptr, op.stride, k == 1 ? 1 : 0);
+      klaunch<(k_zb_cheb<T, false, NC, IMV>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
+                                              c.nzitems, zop, (const T*)cur, b, d, alt, c1, c2, c.partials,
+                                              (const KScal*)nullptr, op.stride, k == 1 ? 1 : 0,
+                                              IMV ? c.imstride : int64_t(0));
       std::swap(cur, alt);
     }
     CHECK_LAUNCH();
     return IBFE_OK;
   };
-  if ((rc = graph_run(c, graph_key(kGsChebGen, 0, sizeof(T), iters), body))) return rc;
+  if ((rc = graph_run(c, graph_key(kGsChebGen, IMV ? 1 : 0, sizeof(T), iters), body))) return rc;
   // the sequence swaps the buffers iters - 1 times (a graph replay does not run body)
   cur = ((iters - 1) % 2 == 0) ? cur0 : alt0;
   if (cur != x) return fail(IBFE_EINVAL, "internal: Chebyshev result buffer");
@@ -1544,10 +1609,10 @@ int smooth_comp(ibfe_ctx& c, const MGDev<T>& L, const T* b, T*& x, T*& alt, int 
     launch_extra<T, 1>(c, op, x, sc);
     if (last && dot)
       klaunch<(k_zb_cheb<T, true>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
-                         c.nzitems, zop, (const T*)x, b, L.d, alt, T(ch.c1[k]), T(ch.c2[k]), c.partials, sc, int64_t(0), 1);
+                         c.nzitems, zop, (const T*)x, b, L.d, alt, T(ch.c1[k]), T(ch.c2[k]), c.partials, sc, int64_t(0), 1, int64_t(0));
     else
       klaunch<(k_zb_cheb<T, false>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
-                         c.nzitems, zop, (const T*)x, b, L.d, alt, T(ch.c1[k]), T(ch.c2[k]), c.partials, sc, int64_t(0), 1);
+                         c.nzitems, zop, (const T*)x, b, L.d, alt, T(ch.c1[k]), T(ch.c2[k]), c.partials, sc, int64_t(0), 1, int64_t(0));
     std::swap(x, alt);
   }
   nparts = nr;
@@ -1580,10 +1645,10 @@ int smooth(ibfe_ctx& c, const MGDev<T>& L, const T* b, T*& x, T*& alt, int m, bo
     }
     if (last && dot)
       klaunch<(k_zb_cheb<T, true>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)L.zitems,
-                         L.nzitems, op, xin, b, L.d, alt, T(ch.c1[k]), T(ch.c2[k]), c.partials, sc, int64_t(0), 1);
+                         L.nzitems, op, xin, b, L.d, alt, T(ch.c1[k]), T(ch.c2[k]), c.partials, sc, int64_t(0), 1, int64_t(0));
     else
       klaunch<(k_zb_cheb<T, false>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)L.zitems,
-                         L.nzitems, op, xin, b, L.d, alt, T(ch.c1[k]), T(ch.c2[k]), c.partials, sc, int64_t(0), 1);
+                         L.nzitems, op, xin, b, L.d, alt, T(ch.c1[k]), T(ch.c2[k]), c.partials, sc, int64_t(0), 1, int64_t(0));
     std::swap(x, alt);
   }
   nparts = nr;
@@ -1808,7 +1873,7 @@ int mass_cheb_steps(double tol) {
 }
 
 // x = Cheb_iters(b) from x = 0 (x, xalt, d: 3-plane vectors).
-template <typename T>
+template <typename T, bool IMV = false>
 int run_cheb_mass(ibfe_ctx& c, const T* b, T* x, T* xalt, T* d, int iters) {
   const Plan& P = c.plan;
   const double theta = 0.5 * (kMassLmax + kMassLmin), delta = 0.5 * (kMassLmax - kMassLmin);
@@ -1823,12 +1888,17 @@ int run_cheb_mass(ibfe_ctx& c, const T* b, T* x, T* xalt, T* d, int iters) {
   op.lanes = c.zlanes;
   op.zb = c.zb;
   for (int t = 0; t < 4; ++t) op.c[t] = T(c.fc.m[t]);
+  op = with_im(c, op);
   T* cur = ((iters - 1) % 2 == 0) ? x : xalt;
   T* alt = cur == x ? xalt : x;
-  klaunch<(k_mg_cheb0<T, 3>)>(c, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
-                     c.nl, (const uint8_t*)c.emask, (const uint8_t*)c.flags,
-                     T(c.fc.m[0]), T(1.0 / theta), b, d, cur, (const KScal*)nullptr, kFlagF, c.stride);
   const int nr = red_blocks(c.nzitems);
+  if (IMV)
+    klaunch<(k_cheb0_im<T, 3>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems, c.nzitems, op, b,
+                                d, cur, T(1.0 / theta), c.stride, c.imstride);
+  else
+    klaunch<(k_mg_cheb0<T, 3>)>(c, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
+                       c.nl, (const uint8_t*)c.emask, (const uint8_t*)c.flags,
+                       T(c.fc.m[0]), T(1.0 / theta), b, d, cur, (const KScal*)nullptr, kFlagF, c.stride);
   T* const cur0 = cur;
   T* const alt0 = alt;
   auto body = [&]() -> int {
@@ -1840,15 +1910,16 @@ int run_cheb_mass(ibfe_ctx& c, const T* b, T* x, T* xalt, T* d, int iters) {
       // the first step writes the zeros off the free rows into the second buffer
       // (the zero-start step did so for the first one and for d)
       const int zero_off = k == 1 ? 1 : 0;
-      klaunch<(k_zb_cheb<T, false, 3>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
-                                        c.nzitems, op, (const T*)cur, b, d, alt, c1, c2, c.partials,
-                                        (const KScal*)nullptr, c.stride, zero_off);
+      klaunch<(k_zb_cheb<T, false, 3, IMV>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, (const int*)c.zitems,
+                                             c.nzitems, op, (const T*)cur, b, d, alt, c1, c2, c.partials,
+                                             (const KScal*)nullptr, c.stride, zero_off,
+                                             IMV ? c.imstride : int64_t(0));
       std::swap(cur, alt);
     }
     CHECK_LAUNCH();
     return IBFE_OK;
   };
-  if (int rcb = graph_run(c, graph_key(kGsChebMass, 0, sizeof(T), iters), body)) return rcb;
+  if (int rcb = graph_run(c, graph_key(kGsChebMass, IMV ? 1 : 0, sizeof(T), iters), body)) return rcb;
   // the sequence swaps the buffers iters - 1 times (a graph replay does not run body)
   cur = ((iters - 1) % 2 == 0) ? cur0 : alt0;
   if (cur != x) return fail(IBFE_EINVAL, "internal: Chebyshev result buffer");
@@ -1915,12 +1986,6 @@ int batched_cheb_mass(ibfe_ctx& c, const float* b, float* x, float* xalt, float*
   const double theta = 0.5 * (kMassLmax + kMassLmin);
   float* cur0 = ((iters - 1) % 2 == 0) ? x : xalt;
   float* alt0 = cur0 == x ? xalt : x;
-  klaunch<(k_mg_cheb0<float, 3>)>(c, dim3(blocks_for(c.nchunks)), dim3(kBlock), 0, c.stream,
-                     c.nl, (const uint8_t*)c.emask, (const uint8_t*)c.flags,
-                     float(c.fc.m[0]), float(1.0 / theta), b, d, cur0, (const KScal*)nullptr, kFlagF, c.stride);
-  CHECK_LAUNCH();
-  if (iters <= 1) return IBFE_OK;
-  ibfe_batcher& B = *c.batcher;
   ibfe_batcher::Pending me;
   ChebJob<float>& J = me.job;
   J.items = c.zitems;
@@ -1936,11 +2001,18 @@ int batched_cheb_mass(ibfe_ctx& c, const float* b, float* x, float* xalt, float*
   J.op.lanes = c.zlanes;
   J.op.zb = c.zb;
   for (int t = 0; t < 4; ++t) J.op.c[t] = float(c.fc.m[t]);
+  J.op = with_im(c, J.op);
   J.b = b;
   J.d = d;
   J.buf0 = cur0;
   J.buf1 = alt0;
   J.stride = c.stride;
+  J.imstride = c.imstride;
+  klaunch<(k_cheb0_im<float, 3>)>(c, dim3(J.nblocks), dim3(kBlock), 0, c.stream, (const int*)c.zitems, c.nzitems,
+                                  J.op, b, d, cur0, float(1.0 / theta), c.stride, c.imstride);
+  CHECK_LAUNCH();
+  if (iters <= 1) return IBFE_OK;
+  ibfe_batcher& B = *c.batcher;
   me.ctx = &c;
   HIP_TRY(hipEventRecord(c.ev_ready, c.stream));
   std::unique_lock<std::mutex> lk(B.mu);
@@ -2236,12 +2308,13 @@ int step_once(ibfe_ctx& c) {
     c.delta_warm = false;
     if (mixed) {
       float* const* v = c.v32;
-      rc = run_refined(c, op, kFlagF, 3, b4, delta, v[8], v[9], rtol, so,
+      // the residual and the Chebyshev direction in walk order
+      rc = run_refined(c, op, kFlagF, 3, b4, delta, c.rim, v[9], rtol, so,
                        [&](const float* r32, float* d32, double tol, SolveOut& o) {
                          o.iters = mass_cheb_steps(tol);
-                         if (c.batcher) return batched_cheb_mass(c, r32, d32, v[0], v[1], o.iters);
-                         return run_cheb_mass<float>(c, r32, d32, v[0], v[1], o.iters);
-                       });
+                         if (c.batcher) return batched_cheb_mass(c, r32, d32, v[0], c.dim, o.iters);
+                         return run_cheb_mass<float, true>(c, r32, d32, v[0], c.dim, o.iters);
+                       }, true);
     } else {
       // FP64: refinement sweeps whose corrections are FP64 Chebyshev solves
       double* r64 = c.w[3];
@@ -2572,11 +2645,13 @@ int step_once_refined(ibfe_ctx& c) {
     if (mixed) {
       auto op32 = csym_op<float, 3>(c, 1.0, 0.0, kFlagF, c.dinvM32);
       float* const* v = c.v32;
-      rc = run_refined(c, op, kFlagF, 3, b4, delta, v[8], v[9], rtol, so,
+      // the residual and the Chebyshev direction in walk order
+      rc = run_refined(c, op, kFlagF, 3, b4, delta, c.rim, v[9], rtol, so,
                        [&](const float* r32, float* d32, double tol, SolveOut& o) {
                          o.iters = cheb_steps(tol, lmin, lmax);
-                         return run_cheb_gen<float>(c, op32, r32, d32, v[0], v[1], o.iters, lmin, lmax);
-                       });
+                         return run_cheb_gen<float, decltype(op32), true>(c, op32, r32, d32, v[0], c.dim, o.iters,
+                                                                          lmin, lmax);
+                       }, true);
     } else {
       double* r64 = c.w[3];
       so.iters = 0;

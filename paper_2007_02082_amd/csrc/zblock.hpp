@@ -36,7 +36,17 @@ struct ZOp {
   // and the precomputed extra terms of kFlagExtra rows (planes of the field stride)
   const T* dinv = nullptr;
   const T* extra = nullptr;
+  // the cell bits and flags of the walked positions in walk order (item, plane,
+  // lane: one coalesced 64-byte load per plane), or nullptr to read them from
+  // the lattice arrays
+  const uint8_t* em_im = nullptr;
+  const uint8_t* fl_im = nullptr;
 };
+
+// Walk order: position (item it, plane k of the item, lane) has index
+// (it * zb + k) * 64 + lane.  Vectors that the walks read and write only at the
+// walked node itself can live in this order (dense, whole cache lines) instead
+// of on the lattice, where a vessel's columns fill part of each line.
 
 // Walk the column items of this block.  The 3-plane window slides through a ring of kZBPF + 3 planes: the row loads of
 // the plane kZBPF + 1 steps ahead are issued before the current output is formed,
@@ -49,7 +59,7 @@ constexpr int kZBPF = 2;
 // bits and flags of the item stay in its caches.  (Spreading the (item,
 // component) pairs over different wavefronts was measured slower: 32 -> 35 us
 // for the pulsatile mass step.)
-// epi(component, node, lane_ok, row, emask, Ax, x_centre, extra_row).
+// epi(component, node, lane_ok, row, emask, Ax, x_centre, extra_row, walk-order index).
 // zb_walk_range walks the items [cr.c0, cr.c1); zb_walk, this block's share of
 // all nitems items.
 template <typename T, int NC, class Epi>
@@ -61,6 +71,7 @@ __device__ __forceinline__ void zb_walk_range(const int* __restrict__ items, Chu
   const int sy = op.sy, sz = op.sz;
   const T c[4] = {op.c[0], op.c[1], op.c[2], op.c[3]};
   for (int it = cr.c0 + int(threadIdx.x >> 6); it < cr.c1; it += kWaves)
+#pragma unroll
   for (int comp = 0; comp < NC; ++comp) {
     const T* __restrict__ x = x0 + comp * stride;
     const T* __restrict__ extra = extra0 ? extra0 + comp * stride : nullptr;
@@ -70,6 +81,11 @@ __device__ __forceinline__ void zb_walk_range(const int* __restrict__ items, Chu
     const int k0 = pb * op.zb;
     const int kend = min(op.zb, op.nplanes - k0);
     const int base = k0 * sz + (lane_ok ? inplane : 0);
+    const int imb = (it * op.zb) * 64 + lane;
+    // cell bits and flags of plane k at emp[k * estep], flp[k * estep]
+    const uint8_t* __restrict__ emp = op.em_im ? op.em_im + imb : op.emask + base;
+    const uint8_t* __restrict__ flp = op.fl_im ? op.fl_im + imb : op.flags + base;
+    const int estep = op.em_im ? 64 : sz;
     // plane j of the item is grid plane k0 - 1 + j (j = 0 .. kend + 1), kept in
     // slot j % R; the cell bits and flags of output plane k in slot k % R
     T w[R][9];
@@ -80,8 +96,8 @@ __device__ __forceinline__ void zb_walk_range(const int* __restrict__ items, Chu
 #pragma unroll
     for (int k = 0; k <= kZBPF; ++k)
       if (k < kend) {
-        em[k % R] = op.emask[base + k * sz];
-        fl[k % R] = op.flags[base + k * sz];
+        em[k % R] = emp[k * estep];
+        fl[k % R] = flp[k * estep];
       }
 #pragma unroll
     for (int k = 0; k < kZB; ++k) {
@@ -91,8 +107,8 @@ __device__ __forceinline__ void zb_walk_range(const int* __restrict__ items, Chu
       if (j < kZB + 2 && j < kend + 2) load_plane(x, base + (j - 1) * sz, sy, w[j % R]);
       const int kn = k + kZBPF + 1;
       if (kn < kZB && kn < kend) {
-        em[kn % R] = op.emask[base + kn * sz];
-        fl[kn % R] = op.flags[base + kn * sz];
+        em[kn % R] = emp[kn * estep];
+        fl[kn % R] = flp[kn * estep];
       }
       const int node = base + k * sz;
       const uint32_t e = em[k % R];
@@ -102,7 +118,7 @@ __device__ __forceinline__ void zb_walk_range(const int* __restrict__ items, Chu
       const bool interior = __all((!rw) || e == 0xFFu);
       T y = window_apply<T>(w[k % R], w[(k + 1) % R], w[(k + 2) % R], e, interior, c);
       if (extra != nullptr && rw && (fl[k % R] & kFlagExtra)) y += extra[node];
-      epi(comp, node, lane_ok, rw, e, y, w[(k + 1) % R][4], (fl[k % R] & kFlagExtra) != 0u);
+      epi(comp, node, lane_ok, rw, e, y, w[(k + 1) % R][4], (fl[k % R] & kFlagExtra) != 0u, imb + 64 * k);
     }
   }
 }
@@ -122,7 +138,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_q_zb(const int* __restrict__ item
                                                     const KScal* sc) {
   if (sc->done) return;
   double dot[1] = {0.0};
-  auto epi = [&](int d, int node, bool ok, bool rw, uint32_t, T y, T xc, bool) {
+  auto epi = [&](int d, int node, bool ok, bool rw, uint32_t, T y, T xc, bool, int) {
     const T qv = rw ? y : T(0);
     if (ok) q[d * stride + node] = qv;
     dot[0] += double(xc) * double(qv);
@@ -133,18 +149,19 @@ __global__ __launch_bounds__(kBlock) void k_cg_q_zb(const int* __restrict__ item
 
 // Refinement residual in FP64 on the z-blocked walk, NC identical components:
 // r32 = TR(b - A x) on rows (0 elsewhere) and the partial sums of r.r and b.b.
-template <typename TR, int NC>
+// With IMO, r32 is stored in walk order (planes of imstride).
+template <typename TR, int NC, bool IMO = false>
 __global__ __launch_bounds__(kBlock) void k_zb_residual(const int* __restrict__ items, int nitems, ZOp<double> op,
                                                         const double* __restrict__ b, const double* __restrict__ x,
                                                         TR* __restrict__ r32, int64_t stride,
-                                                        double* __restrict__ partials) {
+                                                        double* __restrict__ partials, int64_t imstride = 0) {
   double v[2] = {0.0, 0.0};
-  auto epi = [&](int q, int node, bool ok, bool rw, uint32_t, double y, double, bool) {
+  auto epi = [&](int q, int node, bool ok, bool rw, uint32_t, double y, double, bool, int im) {
     if (!ok) return;
     const int64_t i = q * stride + node;
     const double bi = rw ? b[i] : 0.0;
     const double ri = rw ? bi - y : 0.0;
-    r32[i] = TR(ri);
+    r32[IMO ? int64_t(q * int(imstride) + im) : i] = TR(ri);
     v[0] += ri * ri;
     v[1] += bi * bi;
   };
@@ -158,7 +175,7 @@ __global__ __launch_bounds__(kBlock) void k_zb_resid(const int* __restrict__ ite
                                                      const T* __restrict__ x, const T* __restrict__ b,
                                                      T* __restrict__ r, const KScal* sc) {
   if (sc->done) return;
-  auto epi = [&](int, int node, bool ok, bool rw, uint32_t, T y, T, bool) {
+  auto epi = [&](int, int node, bool ok, bool rw, uint32_t, T y, T, bool, int) {
     if (ok) r[node] = rw ? T(b[node] - y) : T(0);
   };
   zb_walk<T, 1>(items, nitems, op, x, 0, epi, op.extra);
@@ -167,46 +184,85 @@ __global__ __launch_bounds__(kBlock) void k_zb_resid(const int* __restrict__ ite
 // Chebyshev-Jacobi step on rows, NC identical components (planes of `stride`):
 //   d <- c1 d + c2 D^-1 (b - A x_in),  x_out = x_in + d;  0 off rows.
 // With DOT, also the partial sum of b . x_out (the preconditioned residual dot).
-template <typename T, bool DOT, int NC>
+// With IMV, b and d are in walk order (planes of imstride; d is neither read nor
+// written off the rows), x_in and x_out on the lattice.
+template <typename T, bool DOT, int NC, bool IMV = false>
 __device__ __forceinline__ void zb_cheb_body(const int* __restrict__ items, ChunkRange cr, const ZOp<T>& op,
                                              const T* __restrict__ x_in, const T* __restrict__ b,
                                              T* __restrict__ d, T* __restrict__ x_out, T c1, T c2,
-                                             double (&dot)[1], int64_t stride, int zero_off_rows) {
+                                             double (&dot)[1], int64_t stride, int zero_off_rows,
+                                             int64_t imstride = 0) {
   const T c0 = op.c[0];
-  auto epi = [&](int q, int node, bool ok, bool rw, uint32_t e, T y, T xc, bool xrow) {
+  auto epi = [&](int q, int node, bool ok, bool rw, uint32_t e, T y, T xc, bool xrow, int im) {
     if (!ok) return;
     const int64_t i = q * stride + node;
+    const int64_t iv = IMV ? int64_t(q * int(imstride) + im) : i;
     if (rw) {
       // the stored diagonal only where the row has terms beyond its fine cells:
       // elsewhere it is c0 times the number of kept fine cells
       const T dinv = (op.dinv && xrow) ? op.dinv[node] : T(1) / (c0 * T(__builtin_popcount(e)));
-      const T dold = (c1 != T(0)) ? d[i] : T(0);
-      const T bi = b[i];
+      const T dold = (c1 != T(0)) ? d[iv] : T(0);
+      const T bi = b[iv];
       const T dn = c1 * dold + c2 * dinv * (bi - y);
       const T xn = xc + dn;
-      d[i] = dn;
+      d[iv] = dn;
       x_out[i] = xn;
       if (DOT) dot[0] += double(bi) * double(xn);
     } else if (zero_off_rows) {
-      d[i] = T(0);
+      if (!IMV) d[i] = T(0);
       x_out[i] = T(0);
     }
   };
   zb_walk_range<T, NC>(items, cr, op, x_in, stride, epi, op.extra);
 }
 
-template <typename T, bool DOT, int NC = 1>
+// Chebyshev start from x = 0 in walk order: d = x = c2 D^-1 b on the rows of the
+// walked positions (b, d in walk order, x on the lattice, 0 off the rows), with
+// the diagonal the walk uses.
+template <typename T, int NC>
+__global__ __launch_bounds__(kBlock) void k_cheb0_im(const int* __restrict__ items, int nitems, ZOp<T> op,
+                                                     const T* __restrict__ b, T* __restrict__ d,
+                                                     T* __restrict__ x, T c2, int64_t stride, int64_t imstride) {
+  const int lane = threadIdx.x & 63;
+  const T c0 = op.c[0];
+  const ChunkRange cr = block_chunks(nitems);
+  for (int it = cr.c0 + int(threadIdx.x >> 6); it < cr.c1; it += kWaves) {
+    const int inplane = op.lanes[it * 64 + lane];
+    if (inplane < 0) continue;
+    const int k0 = items[it] * op.zb;
+    const int kend = min(op.zb, op.nplanes - k0);
+    const int64_t imb = int64_t(it) * op.zb * 64 + lane;
+    for (int k = 0; k < kend; ++k) {
+      const int node = (k0 + k) * op.sz + inplane;
+      const int64_t im = imb + 64 * k;
+      const uint32_t e = op.em_im ? op.em_im[im] : op.emask[node];
+      const uint32_t f = op.fl_im ? op.fl_im[im] : op.flags[node];
+      const bool rw = f & op.rowbit;
+      const T dinv = !rw ? T(0)
+                         : (op.dinv && (f & kFlagExtra)) ? op.dinv[node] : T(1) / (c0 * T(__builtin_popcount(e)));
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        const T v = rw ? T(c2 * b[q * imstride + im] * dinv) : T(0);
+        if (rw) d[q * imstride + im] = v;
+        x[q * stride + node] = v;
+      }
+    }
+  }
+}
+
+template <typename T, bool DOT, int NC = 1, bool IMV = false>
 __global__ __launch_bounds__(kBlock) void k_zb_cheb(const int* __restrict__ items, int nitems, ZOp<T> op,
                                                     const T* __restrict__ x_in, const T* __restrict__ b,
                                                     T* __restrict__ d, T* __restrict__ x_out, T c1, T c2,
                                                     double* __restrict__ partials, const KScal* sc,
-                                                    int64_t stride = 0, int zero_off_rows = 1) {
+                                                    int64_t stride = 0, int zero_off_rows = 1,
+                                                    int64_t imstride = 0) {
   // zero_off_rows = 0: d and x_out already hold 0 off rows (written by an earlier
   // step of the same sequence), so only the rows are stored
   if (sc && sc->done) return;
   double dot[1] = {0.0};
-  zb_cheb_body<T, DOT, NC>(items, block_chunks(nitems), op, x_in, b, d, x_out, c1, c2, dot, stride,
-                           zero_off_rows);
+  zb_cheb_body<T, DOT, NC, IMV>(items, block_chunks(nitems), op, x_in, b, d, x_out, c1, c2, dot, stride,
+                                zero_off_rows, imstride);
   if (DOT) block_partials<1>(dot, partials);
 }
 
@@ -226,7 +282,7 @@ struct ChebJob {
   T* d;
   T* buf0;
   T* buf1;
-  int64_t stride;
+  int64_t stride, imstride;  // b and d in walk order
 };
 template <typename T>
 struct ChebBatch {
@@ -248,7 +304,8 @@ __global__ __launch_bounds__(kBlock) void k_zb_cheb_batch(ChebBatch<T> B, int k,
   double dot[1] = {0.0};
   const T* x_in = (k & 1) ? J.buf0 : J.buf1;
   T* x_out = (k & 1) ? J.buf1 : J.buf0;
-  zb_cheb_body<T, false, NC>(J.items, cr, J.op, x_in, J.b, J.d, x_out, c1, c2, dot, J.stride, k == 1 ? 1 : 0);
+  zb_cheb_body<T, false, NC, true>(J.items, cr, J.op, x_in, J.b, J.d, x_out, c1, c2, dot, J.stride, k == 1 ? 1 : 0,
+                                   J.imstride);
 }
 
 }  // namespace ibfe
