@@ -325,7 +325,7 @@ def kernel_model(name: str, z: dict):
     s = 4 if "<float" in name else 8
     b = 0.25 if z["refined"] else 0.125
     n_p, n_f = z["n_p"], z["n_free"]
-    if name.startswith("k_zb_cheb<") and (name.endswith(", false, 3>") or name.endswith(", false, 3, true>")):
+    if name.startswith("k_zb_cheb<") and name.endswith((", false, 3>", ", false, 3, true>", ", false, 3, false>")):
         return (15 * s + b) * n_f, "Q1 mass Chebyshev step, 3 components: read x, b, d; write d, x per free node"
     if name.startswith("k_cg_q_zb<") and name.endswith(", 1>"):
         return (2 * s + b) * n_p, "Q1 stiffness apply + p.q: read p, write q per pressure node"
@@ -429,8 +429,8 @@ def roofline_of(res: dict, workload: str, precision: str, pc: int) -> dict:
     against the HBM peak."""
     d = res["dominant"]
     key = None
-    if d["kernel"].startswith("k_zb_cheb<") and (d["kernel"].endswith(", false, 3>")
-                                                  or d["kernel"].endswith(", false, 3, true>")):
+    if d["kernel"].startswith("k_zb_cheb<") and d["kernel"].endswith((", false, 3>", ", false, 3, true>",
+                                                                      ", false, 3, false>")):
         key = "mass"
     elif d["kernel"].startswith("k_cg_q_zb<"):
         key = "pressure"

@@ -406,7 +406,8 @@ int collect_kernel_times(ibfe_ctx& c) {
     auto ends = [&](const std::string& tail) {
       return name.size() > tail.size() && name.compare(name.size() - tail.size(), tail.size(), tail) == 0;
     };
-    const bool mass = name.rfind("k_zb_cheb<", 0) == 0 && (ends(", false, 3>") || ends(", false, 3, true>"));
+    const bool mass = name.rfind("k_zb_cheb<", 0) == 0 &&
+                      (ends(", false, 3>") || ends(", false, 3, true>") || ends(", false, 3, false>"));
     const bool pressure = name == "k_cg_q_zb<float, 1>" || name == "k_cg_q_zb<double, 1>";
     if (mass) {
       c.stats.mass_apply_ms += ms;
