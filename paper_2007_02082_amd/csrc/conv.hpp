@@ -20,6 +20,7 @@
 #pragma once
 
 #include "strain.hpp"
+#include "zblock.hpp"
 
 namespace ibfe {
 
@@ -245,6 +246,10 @@ struct OpCConv {
   Children ch;
   const T* pw;
   const T* yh;
+  // with extra: the coarse-cell part and the hanging children of the rows flagged
+  // kFlagExtra (about 7 % of them) precomputed there by k_conv_extra before the
+  // apply, so the other rows' wavefronts skip them; without: both in the row
+  const T* extra = nullptr;
   __device__ __forceinline__ bool row(int n) const { return flags[n] & rowbit; }
   __device__ __forceinline__ void elem(int n, const T* __restrict__ x, T (&y)[3]) const {
     y[0] = y[1] = y[2] = T(0);
@@ -255,19 +260,45 @@ struct OpCConv {
       advdiff_row<T>(w, stride, n, e, c4, rh2f, sy, sz, 1, A);
       row_apply<T, 3>(A, x, stride, n, sy, sz, 1, y);
     }
-    if (__any(m != 0u)) {
-      T A[27];
-      const T c4[4] = {cc[0], cc[1], cc[2], cc[3]};
-      advdiff_row<T>(w, stride, n, m, c4, rh2c, 2 * sy, 2 * sz, 2, A);
-      row_apply<T, 3>(A, x, stride, n, 2 * sy, 2 * sz, 2, y);
-    }
+    if (!extra && __any(m != 0u)) coarse(n, m, x, y);
+  }
+  __device__ __forceinline__ void coarse(int n, uint32_t m, const T* __restrict__ x, T (&y)[3]) const {
+    T A[27];
+    const T c4[4] = {cc[0], cc[1], cc[2], cc[3]};
+    advdiff_row<T>(w, stride, n, m, c4, rh2c, 2 * sy, 2 * sz, 2, A);
+    row_apply<T, 3>(A, x, stride, n, 2 * sy, 2 * sz, 2, y);
   }
   __device__ __forceinline__ void apply(int n, const T* __restrict__ x, T (&y)[3]) const {
     elem(n, x, y);
-    if (flags[n] & kFlagPar) add_children<T, 3>(ch, pw, yh, n, y);
+    if (extra) {
+      if (flags[n] & kFlagExtra) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) y[d] += extra[d * stride + n];
+      }
+    } else if (flags[n] & kFlagPar) {
+      add_children<T, 3>(ch, pw, yh, n, y);
+    }
   }
   __device__ __forceinline__ T inv_diag(int n) const { return dinv[n]; }
 };
+
+// extra[d][n] = coarse-cell part of the row of n plus its hanging children's rows
+// (yh, filled before) at the listed nodes (those flagged kFlagExtra).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_conv_extra(int nn, const int32_t* __restrict__ ids, OpCConv<T> op,
+                                                       const T* __restrict__ x, T* __restrict__ extra,
+                                                       const KScal* sc) {
+  if (sc && sc->done) return;
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= nn) return;
+  const int n = ids[k];
+  T y[3] = {T(0), T(0), T(0)};
+  const uint32_t m = op.cmask[n];
+  if (m) op.coarse(n, m, x, y);
+  if (op.flags[n] & kFlagPar) add_children<T, 3>(op.ch, op.pw, op.yh, n, y);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) extra[d * op.stride + n] = y[d];
+}
 
 // The matrix-free operator plus the strain-rate cross blocks (uniform grid);
 // the Jacobi diagonal leaves the block diagonals mu X_dd out, as for the stored

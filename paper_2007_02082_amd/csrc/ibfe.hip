@@ -901,7 +901,12 @@ int pre_apply(ibfe_ctx& c, const OpCStencilStrain<T, B>& op, T* x, const KScal* 
 }
 template <typename T>
 int pre_apply(ibfe_ctx& c, const OpCConv<T>& op, T* x, const KScal* sc) {
-  return hang_prepare<T>(c, op, x, sc);
+  int rc = hang_prepare<T>(c, op, x, sc);
+  if (rc || !op.extra || c.nxn == 0) return rc;
+  klaunch<k_conv_extra<T>>(c, dim3(blocks_lin(c.nxn)), dim3(kBlock), 0, c.stream, c.nxn,
+                           (const int32_t*)c.xnodes, op, (const T*)x, const_cast<T*>(op.extra), sc);
+  CHECK_LAUNCH();
+  return IBFE_OK;
 }
 template <typename T>
 int pre_apply(ibfe_ctx& c, const OpCSymStrain<T>& op, T* x, const KScal* sc) {
@@ -1406,6 +1411,15 @@ OpCConv<T> cconv_op(const ibfe_ctx& c, uint32_t rowbit) {
   op.ch = children_of(c);
   op.pw = RefBufs<T>::pw(c);
   op.yh = RefBufs<T>::yh(c);
+  return op;
+}
+
+// The same for the Krylov solves and refinement residuals, whose pre_apply
+// precomputes the coarse-cell and hanging-children terms of the flagged rows.
+template <typename T>
+OpCConv<T> cconv_solver_op(const ibfe_ctx& c, uint32_t rowbit) {
+  OpCConv<T> op = cconv_op<T>(c, rowbit);
+  op.extra = RefBufs<T>::extra(c);
   return op;
 }
 
@@ -2544,7 +2558,7 @@ int step_once_refined(ibfe_ctx& c) {
     else if (strain)
       rc = solve(cstrain_op<double>(c, c.coef64, kFlagF), cstrain_op<float>(c, c.coef32, kFlagF));
     else if (mf)
-      rc = solve(cconv_op<double>(c, kFlagF), cconv_op<float>(c, kFlagF));
+      rc = solve(cconv_solver_op<double>(c, kFlagF), cconv_solver_op<float>(c, kFlagF));
     else
       rc = solve(cstencil_op<double>(c, c.coef64, kFlagF), cstencil_op<float>(c, c.coef32, kFlagF));
     if (rc) return rc;
