@@ -1018,7 +1018,7 @@ int launch_bi_apply(ibfe_ctx& c, const Op& op, NodeList nl, const T* xin, T* y, 
 
 template <typename T, class Op>
 int run_bicgstab(ibfe_ctx& c, const Op& op, const T* b, T* x, T* const* wv, int slot, double rtol,
-                 int max_iters, SolveOut& out) {
+                 int max_iters, SolveOut& out, bool zero_guess = false) {
   const int nb = blocks_for(c.nchunks), nr = red_blocks(c.nchunks);
   const NodeList nl = c.nl;
   const double* pa = c.partials;
@@ -1033,9 +1033,11 @@ int run_bicgstab(ibfe_ctx& c, const Op& op, const T* b, T* x, T* const* wv, int 
   KScal st{};
   for (int restart = 0;; ++restart) {
     restarts = restart;
-    if ((prc = pre_apply(c, op, x, (const KScal*)nullptr))) return prc;
+    // x = 0 at the first start of an inner correction solve: r = b, no apply
+    const int zg = (zero_guess && restart == 0) ? 1 : 0;
+    if (!zg && (prc = pre_apply(c, op, x, (const KScal*)nullptr))) return prc;
     klaunch<(k_bi_init<T, Op>)>(c, dim3(nr), dim3(kBlock), 0, c.stream, nl, op, b, x, r, rhat, p,
-                       v, c.partials);
+                       v, c.partials, zg);
     klaunch<k_fin_bi_init>(c, dim3(1), dim3(kBlock), 0, c.stream, pa, nr, sc, rtol * rtol,
                        max_iters - total);
     CHECK_LAUNCH();
@@ -2221,7 +2223,7 @@ int step_once(ibfe_ctx& c) {
                            [&](const float* r32, float* d32, double tol, SolveOut& o) {
                              klaunch<k_zero<float>>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, d32, 3,
                                                 S);
-                             return run_bicgstab<float>(c, op32, r32, d32, c.v32, kScS1, tol, maxit, o);
+                             return run_bicgstab<float>(c, op32, r32, d32, c.v32, kScS1, tol, maxit, o, true);
                            });
       return run_bicgstab<double>(c, op, b1, x1, c.w, kScS1, rtol, maxit, so);
     };
@@ -2549,7 +2551,7 @@ int step_once_refined(ibfe_ctx& c) {
                            [&](const float* r32, float* d32, double tol, SolveOut& o) {
                              klaunch<k_zero<float>>(c, dim3(nb), dim3(kBlock), 0, c.stream, c.nl, d32, 3,
                                                 S);
-                             return run_bicgstab<float>(c, op32, r32, d32, c.v32, kScS1, tol, maxit, o);
+                             return run_bicgstab<float>(c, op32, r32, d32, c.v32, kScS1, tol, maxit, o, true);
                            });
       return run_bicgstab<double>(c, op, b1, x1, c.w, kScS1, rtol, maxit, so);
     };

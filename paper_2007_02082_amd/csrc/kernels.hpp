@@ -551,7 +551,8 @@ __global__ __launch_bounds__(kBlock) void k_bi_init(NodeList nl, Op op,
                                                     const T* __restrict__ b, const T* __restrict__ x,
                                                     T* __restrict__ r, T* __restrict__ rhat,
                                                     T* __restrict__ p, T* __restrict__ v,
-                                                    double* __restrict__ partials) {
+                                                    double* __restrict__ partials, int zero_guess) {
+  // zero_guess: x = 0, so r = b without an apply
   constexpr int NC = Op::kNC;
   double s[2] = {0.0, 0.0};
   const ChunkRange cr = block_chunks(nl.n);
@@ -559,7 +560,9 @@ __global__ __launch_bounds__(kBlock) void k_bi_init(NodeList nl, Op op,
     const int n = nl.node(c);
     const bool rw = op.row(n);
     T ax[NC];
-    if (rw) op.apply(n, x, ax);
+#pragma unroll
+    for (int d = 0; d < NC; ++d) ax[d] = T(0);
+    if (rw && !zero_guess) op.apply(n, x, ax);
 #pragma unroll
     for (int d = 0; d < NC; ++d) {
       const int64_t i = d * op.stride + n;
