@@ -152,7 +152,9 @@ def serve_stream(n: int, slots: int, nsteps: int, batch_window_us: float | None 
     import synth
 
     reqs = synth.request_stream(n=n, rate=rate, nsteps=nsteps)
-    kws = [ibfe.inputs_from_case(r.case, precision=1, precond=2) for r in reqs]
+    # the batcher joins the Jacobi-preconditioned mass corrections only
+    mp = 0 if batch_window_us is not None else 1
+    kws = [ibfe.inputs_from_case(r.case, precision=1, precond=2, mass_precond=mp) for r in reqs]
     srv = ibfe.Server(max_slots=slots, batch_window_us=batch_window_us)
     ids = []
     t0 = time.perf_counter()

@@ -35,7 +35,8 @@ class Params(C.Structure):
     _fields_ = [("rho", C.c_double), ("mu", C.c_double), ("dt", C.c_double),
                 ("precision", C.c_int32), ("rtol", C.c_double), ("max_iters", C.c_int32),
                 ("precond", C.c_int32), ("advection", C.c_int32), ("ib_rtol", C.c_double),
-                ("viscous", C.c_int32), ("advdiff", C.c_int32)]
+                ("viscous", C.c_int32), ("advdiff", C.c_int32),
+                ("mass_precond", C.c_int32)]
 
 
 class Inlet(C.Structure):
@@ -187,7 +188,7 @@ class _Inputs:
     def __init__(self, nx, ny, nz, h, origin, node_mask, bc_tag, X, dS, U_B, rho, mu, dt,
                  inlet_K, inlet_omega, inlet_ids, inlet_shape, precision=0, rtol=0.0,
                  max_iters=0, ib_rtol=0.0, precond=0, advection=0, refine_cell=None, viscous=0,
-                 advdiff=0):
+                 advdiff=0, mass_precond=1):
         self.mask = np.ascontiguousarray(node_mask, dtype=np.uint8)
         self.refine = None if refine_cell is None else np.ascontiguousarray(refine_cell, dtype=np.uint8)
         self.tag = None if bc_tag is None else np.ascontiguousarray(bc_tag, dtype=np.uint8)
@@ -202,7 +203,7 @@ class _Inputs:
                      _ptr(self.UB, C.c_double))
         self.params = Params(float(rho), float(mu), float(dt), int(precision), float(rtol),
                              int(max_iters), int(precond), int(advection), float(ib_rtol), int(viscous),
-                             int(advdiff))
+                             int(advdiff), int(mass_precond))
         self.inlet = Inlet(int(inlet_K), float(inlet_omega), self.ids.size,
                            _ptr(self.ids, C.c_int64) if self.ids.size else None,
                            _ptr(self.shape, C.c_double) if self.shape.size else None)

@@ -126,6 +126,10 @@ int build_plan(const ibfe_grid* grid, const ibfe_ib* ib, const ibfe_params* para
     err = "advdiff must be 0 (matrix-free) or 1 (assembled stencil)";
     return IBFE_EINVAL;
   }
+  if (pr.mass_precond < 0 || pr.mass_precond > 1) {
+    err = "mass_precond must be 0 (Jacobi) or 1 (tensor-product approximate inverse)";
+    return IBFE_EINVAL;
+  }
   if (pr.viscous < 0 || pr.viscous > 1) {
     err = "viscous must be 0 (mu (grad u, grad v)) or 1 (2 mu (eps(u), eps(v)))";
     return IBFE_EINVAL;

@@ -308,4 +308,226 @@ __global__ __launch_bounds__(kBlock) void k_zb_cheb_batch(ChebBatch<T> B, int k,
                                    J.imstride);
 }
 
+// ---------------------------------------------------------------------------
+// Consistent-mass correction with a tensor-product preconditioner.
+//
+// On a uniform grid the Q1 mass stencil is the product over the three axes of
+// (1, 4, 1) h/6; scaled by its diagonal, each axis contributes the symbol
+// 1 + cos(th)/2 in [1/2, 3/2], which is where the Jacobi interval [1/8, 27/8]
+// comes from.  The preconditioner P = D^-1/2 T D^-1/2, with T the product over
+// the axes of the three-point stencil (-1/4, 1, -1/4) restricted to the free
+// rows (a principal submatrix of a positive definite product stencil, hence
+// itself positive definite), gives each axis the symbol
+// (1 + cos/2)(1 - cos/2) = 1 - cos^2/4 in [3/4, 1]: the interior spectrum of
+// P M lies in [27/64, 1] (condition 2.4 instead of 27).  Rows at the vessel wall
+// move it outward.  On a refined lattice T is block diagonal: the stride-1
+// product stencil among the rows with fine cells only, the stride-2 one among
+// the rows with coarse cells or hanging children (kFlagExtra).
+//
+// One Chebyshev step is two passes: w = D^-1/2 (b - M x) on the lattice (the mass
+// walk), then d = c1 d + c2 D^-1/2 T w, x += d (a walk with the constant
+// product stencil over w).  x is updated in place: the second pass reads x only
+// at the node itself.
+// ---------------------------------------------------------------------------
+
+// weight of the one-dimensional three-point stencil (-t, 1, -t)
+constexpr double kTensorT = 0.25;
+
+// w = D^-1/2 b on the rows of the walked positions, 0 at the others; on a
+// refined lattice the kFlagExtra rows go to wx and w holds 0 there.  With IMV,
+// b is in walk order.
+template <typename T, int NC, bool IMV>
+__global__ __launch_bounds__(kBlock) void k_tm_scale(const int* __restrict__ items, int nitems, ZOp<T> op,
+                                                     const T* __restrict__ b, T* __restrict__ w,
+                                                     T* __restrict__ wx, int64_t stride, int64_t imstride) {
+  const int lane = threadIdx.x & 63;
+  const T c0 = op.c[0];
+  const ChunkRange cr = block_chunks(nitems);
+  for (int it = cr.c0 + int(threadIdx.x >> 6); it < cr.c1; it += kWaves) {
+    const int inplane = op.lanes[it * 64 + lane];
+    if (inplane < 0) continue;
+    const int k0 = items[it] * op.zb;
+    const int kend = min(op.zb, op.nplanes - k0);
+    const int64_t imb = int64_t(it) * op.zb * 64 + lane;
+    for (int k = 0; k < kend; ++k) {
+      const int node = (k0 + k) * op.sz + inplane;
+      const int64_t im = imb + 64 * k;
+      const uint32_t e = op.em_im ? op.em_im[im] : op.emask[node];
+      const uint32_t f = op.fl_im ? op.fl_im[im] : op.flags[node];
+      const bool rw = f & op.rowbit;
+      const bool xr = wx != nullptr && (f & kFlagExtra);
+      const T sd = !rw ? T(0)
+                       : sqrt((op.dinv && (f & kFlagExtra)) ? op.dinv[node]
+                                                            : T(1) / (c0 * T(__builtin_popcount(e))));
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        const int64_t i = q * stride + node;
+        const T v = rw ? sd * b[IMV ? q * imstride + im : i] : T(0);
+        if (xr) {
+          if (rw) wx[i] = v;
+          w[i] = T(0);
+        } else {
+          w[i] = v;
+        }
+      }
+    }
+  }
+}
+
+// w = D^-1/2 (b - M x) on the rows (the mass walk; on a refined lattice with the
+// extra terms of op.extra), 0 at the other walked positions; kFlagExtra rows into
+// wx as in k_tm_scale.
+template <typename T, int NC, bool IMV>
+__global__ __launch_bounds__(kBlock) void k_tm_resid(const int* __restrict__ items, int nitems, ZOp<T> op,
+                                                     const T* __restrict__ x, const T* __restrict__ b,
+                                                     T* __restrict__ w, T* __restrict__ wx, int64_t stride,
+                                                     int64_t imstride) {
+  const T c0 = op.c[0];
+  auto epi = [&](int q, int node, bool ok, bool rw, uint32_t e, T y, T, bool xrow, int im) {
+    if (!ok) return;
+    const int64_t i = q * stride + node;
+    T v = T(0);
+    if (rw) {
+      const T dinv = (op.dinv && xrow) ? op.dinv[node] : T(1) / (c0 * T(__builtin_popcount(e)));
+      v = sqrt(dinv) * (b[IMV ? int64_t(q * int(imstride) + im) : i] - y);
+    }
+    if (wx != nullptr && xrow) {
+      if (rw) wx[i] = v;
+      w[i] = T(0);
+    } else {
+      w[i] = v;
+    }
+  };
+  zb_walk<T, NC>(items, nitems, op, x, stride, epi, op.extra);
+}
+
+// The stride-2 product stencil on the kFlagExtra rows of a refined lattice (the
+// listed nodes xn; lattice planes sy, sz, nplanes): zx = sum over o in
+// {-1,0,1}^3 of (-t)^{|o|} wx[n + 2o], neighbours outside the lattice dropped.
+template <typename T, int NC>
+__global__ __launch_bounds__(kBlock) void k_tm_extra(int nxn, const int32_t* __restrict__ xn,
+                                                     const uint8_t* __restrict__ flags, uint32_t rowbit,
+                                                     const T* __restrict__ wx, T* __restrict__ zx, T tw, int sy,
+                                                     int sz, int nplanes, int64_t stride) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nxn) return;
+  const int n = xn[t];
+  if (!(flags[n] & rowbit)) return;
+  const int ix = n % sy, iy = (n % sz) / sy, iz = n / sz;
+  const int ny = sz / sy;
+  const T wt[3] = {-tw, T(1), -tw};
+  T acc[NC];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) acc[q] = T(0);
+  for (int oz = -1; oz <= 1; ++oz) {
+    const int jz = iz + 2 * oz;
+    if (jz < 0 || jz >= nplanes) continue;
+    for (int oy = -1; oy <= 1; ++oy) {
+      const int jy = iy + 2 * oy;
+      if (jy < 0 || jy >= ny) continue;
+#pragma unroll
+      for (int ox = -1; ox <= 1; ++ox) {
+        const int jx = ix + 2 * ox;
+        if (jx < 0 || jx >= sy) continue;
+        const int m = jz * sz + jy * sy + jx;
+        const T wgt = wt[oz + 1] * wt[oy + 1] * wt[ox + 1];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) acc[q] += wgt * wx[q * stride + m];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NC; ++q) zx[q * stride + n] = acc[q];
+}
+
+// d = c1 d + c2 D^-1/2 (T w), x += d on the rows (FIRST: d = x = c2 D^-1/2 T w, and
+// x = 0 at the other walked positions).  The stride-1 product stencil is walked
+// like the mass apply, with the constant weights and the window entries whose x
+// or y neighbour lies outside the lattice set to 0; on a refined lattice the
+// kFlagExtra rows take their sum from zx.  op.c[0] is the mass cell diagonal.
+// With IMV, d is in walk order.
+template <typename T, int NC, bool IMV, bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_tm_cheb(const int* __restrict__ items, int nitems, ZOp<T> op,
+                                                    const T* __restrict__ w0, const T* __restrict__ zx,
+                                                    T* __restrict__ d, T* __restrict__ x, T c1, T c2, T tw,
+                                                    int64_t stride, int64_t imstride) {
+  constexpr int R = kZBPF + 3;
+  const int lane = threadIdx.x & 63;
+  const int sy = op.sy, sz = op.sz;
+  const int ny = sz / sy;
+  const T c0 = op.c[0];
+  // per neighbour class (centre, face, edge, corner), in the form window_apply
+  // takes for its constant stencil
+  const T ct[4] = {T(0.125), -tw * T(0.25), tw * tw * T(0.5), -tw * tw * tw};
+  const ChunkRange cr = block_chunks(nitems);
+  for (int it = cr.c0 + int(threadIdx.x >> 6); it < cr.c1; it += kWaves)
+#pragma unroll
+  for (int comp = 0; comp < NC; ++comp) {
+    const T* __restrict__ w = w0 + comp * stride;
+    const int pb = items[it];
+    const int inplane = op.lanes[it * 64 + lane];
+    const bool lane_ok = inplane >= 0;
+    const int ip = lane_ok ? inplane : 0;
+    const int ix = ip % sy, iy = ip / sy;
+    // window entry (y + 1) * 3 + (x + 1) of offsets x, y in {-1, 0, 1}
+    uint32_t vm = 0x1FFu;
+    if (ix == 0) vm &= ~0x49u;
+    if (ix == sy - 1) vm &= ~0x124u;
+    if (iy == 0) vm &= ~0x7u;
+    if (iy == ny - 1) vm &= ~0x1C0u;
+    const int k0 = pb * op.zb;
+    const int kend = min(op.zb, op.nplanes - k0);
+    const int base = k0 * sz + ip;
+    const int imb = (it * op.zb) * 64 + lane;
+    const uint8_t* __restrict__ emp = op.em_im ? op.em_im + imb : op.emask + base;
+    const uint8_t* __restrict__ flp = op.fl_im ? op.fl_im + imb : op.flags + base;
+    const int estep = op.em_im ? 64 : sz;
+    T wr[R][9];
+    uint32_t em[R], fl[R];
+    // plane load with the entries outside the lattice set to 0
+    auto ldm = [&](int node, T(&dst)[9]) {
+      load_plane(w, node, sy, dst);
+#pragma unroll
+      for (int q = 0; q < 9; ++q)
+        if (!((vm >> q) & 1u)) dst[q] = T(0);
+    };
+#pragma unroll
+    for (int j = 0; j < kZBPF + 2; ++j)
+      if (j < kend + 2) ldm(base + (j - 1) * sz, wr[j % R]);
+#pragma unroll
+    for (int k = 0; k <= kZBPF; ++k)
+      if (k < kend) {
+        em[k % R] = emp[k * estep];
+        fl[k % R] = flp[k * estep];
+      }
+#pragma unroll
+    for (int k = 0; k < kZB; ++k) {
+      if (k >= kend) break;
+      const int j = k + kZBPF + 2;
+      if (j < kZB + 2 && j < kend + 2) ldm(base + (j - 1) * sz, wr[j % R]);
+      const int kn = k + kZBPF + 1;
+      if (kn < kZB && kn < kend) {
+        em[kn % R] = emp[kn * estep];
+        fl[kn % R] = flp[kn * estep];
+      }
+      const T y = window_apply<T>(wr[k % R], wr[(k + 1) % R], wr[(k + 2) % R], 0xFFu, true, ct);
+      if (!lane_ok) continue;
+      const int node = base + k * sz;
+      const int64_t i = comp * stride + node;
+      const int64_t iv = IMV ? int64_t(comp * imstride + imb + 64 * k) : i;
+      const uint32_t f = fl[k % R];
+      if (f & op.rowbit) {
+        const bool xrow = (f & kFlagExtra) != 0u;
+        const T dinv = (op.dinv && xrow) ? op.dinv[node] : T(1) / (c0 * T(__builtin_popcount(em[k % R])));
+        const T z = sqrt(dinv) * ((zx != nullptr && xrow) ? zx[i] : y);
+        const T dn = FIRST ? c2 * z : c1 * d[iv] + c2 * z;
+        d[iv] = dn;
+        x[i] = FIRST ? dn : x[i] + dn;
+      } else if (FIRST) {
+        x[i] = T(0);
+      }
+    }
+  }
+}
+
 }  // namespace ibfe

@@ -20,7 +20,7 @@ CASES = [lambda: synth.small_cylinder(8, 16, pulsatile=True),
 
 
 def _alone(case, nsteps):
-    s = ibfe.Solver(**ibfe.inputs_from_case(case, precision=1, precond=2))
+    s = ibfe.Solver(**ibfe.inputs_from_case(case, precision=1, precond=2, mass_precond=0))
     s.set_state(np.zeros(3 * s.n_u), np.zeros(s.n_u), 0.0)
     s.step(nsteps)
     u, p, _ = s.get_state()
@@ -33,7 +33,7 @@ def test_threads_with_shared_batcher_bitwise():
     cases = [mk() for mk in CASES]
     ref = [_alone(c, 4) for c in cases]
     say("alone s4 iterations", [r[2] for r in ref])
-    solvers = [ibfe.Solver(**ibfe.inputs_from_case(c, precision=1, precond=2)) for c in cases]
+    solvers = [ibfe.Solver(**ibfe.inputs_from_case(c, precision=1, precond=2, mass_precond=0)) for c in cases]
     b = ibfe.Batcher(window_us=5000.0)
     for s in solvers:
         s.set_state(np.zeros(3 * s.n_u), np.zeros(s.n_u), 0.0)
@@ -67,7 +67,7 @@ def test_served_with_batching_bitwise():
     cases = [mk() for mk in CASES]
     ref = [_alone(c, 3) for c in cases]
     srv = ibfe.Server(max_slots=4, batch_window_us=5000.0)
-    ids = [srv.submit(3, **ibfe.inputs_from_case(c, precision=1, precond=2)) for c in cases]
+    ids = [srv.submit(3, **ibfe.inputs_from_case(c, precision=1, precond=2, mass_precond=0)) for c in cases]
     out = []
     for rid in ids:
         r = srv.wait(rid, 300.0)
@@ -83,7 +83,7 @@ def test_served_with_batching_bitwise():
 
 
 def test_batcher_refuses_destroy_with_members():
-    s = ibfe.Solver(**ibfe.inputs_from_case(synth.small_cylinder(8, 16), precision=1, precond=2))
+    s = ibfe.Solver(**ibfe.inputs_from_case(synth.small_cylinder(8, 16), precision=1, precond=2, mass_precond=0))
     b = ibfe.Batcher()
     b.attach(s)
     with pytest.raises(ibfe.IbfeError):
