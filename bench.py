@@ -31,30 +31,38 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# published vector peaks of MI355X (256 CUs at 2.4 GHz); the library is built
+# without packed FP32 instructions, which halves the FP32 figure in practice
+FP32_VECTOR_TFLOPS = 157.3
+FP64_VECTOR_TFLOPS = 78.6
 CSRC = os.path.join(ROOT, "paper_2007_02082_amd", "csrc")
 
 
-KERNEL_SOURCES = {"pulsatile": ("kernels.hpp", "zblock.hpp"),
-                  "aneurysm": ("kernels.hpp", "zblock.hpp", "composite.hpp"),
-                  "aorta": ("kernels.hpp", "zblock.hpp")}
+def kernel_sources_hash() -> str:
+    """Hash of every device header of the library (the kernels' sources)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith(".hpp"):
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def counted_traffic(workload: str, precision: str, kernel: str):
-    """HBM bytes per dispatch of the dominant apply (`pressure` or `mass`) from the
-    committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, scaled by a copy of
-    known size), or None when the kernel sources changed after the counters were taken."""
-    import hashlib
-
-    path = os.path.join(ROOT, "profiles", f"{kernel}_apply_traffic_{workload}_{precision}.json")
+    """HBM bytes per dispatch of `kernel` from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by a copy of known size), or None when the
+    summary is for another kernel or the kernel sources changed after the counters
+    were taken."""
+    path = os.path.join(ROOT, "profiles", f"dominant_traffic_{workload}_{precision}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    h = hashlib.sha256()
-    for name in KERNEL_SOURCES[workload]:
-        with open(os.path.join(CSRC, name), "rb") as f:
-            h.update(f.read())
-    return rec["traffic_bytes"] if h.hexdigest()[:16] == rec["source_hash"] else None
+    if rec.get("kernel") != kernel or rec.get("source_hash") != kernel_sources_hash():
+        return None
+    return rec["traffic_bytes"]
 
 
 METRIC = "IPCS steps/sec + apply HBM GB/s at 1e-6 rel; served solves/sec, p50/p99"
@@ -319,45 +327,74 @@ def sizes_of(case, prec: int) -> dict:
             "refined": getattr(case, "refine_cell", None) is not None}
 
 
+# Floating-point operations of one matrix-free advection-diffusion row where all 8
+# cells are kept (the factorised form, an FMA counted as 2): eight 1-D passes of 9
+# lines at 5 operations (360), the two sums of the direction blocks (54) and the
+# scaled accumulation into the 27 entries (54), then the product with the three
+# components of x (81 FMA, 162).
+CONV_ROW_FLOPS = 360 + 54 + 54 + 162
+
+
 def kernel_model(name: str, z: dict):
-    """Algorithmic HBM bytes of one dispatch of a kernel (minimum bytes: each operand
-    read or written once, b = 1/8 B of domain data per node, 1/4 on a refined lattice),
-    with a short description; None for kernels without a model.  s = 4 for float
-    instantiations, 8 for double."""
+    """Algorithmic work of one dispatch of a kernel, with a short description and the
+    bound: "hbm" (minimum bytes: each operand read or written once, b = 1/8 B of
+    domain data per node, 1/4 on a refined lattice) or "alu" (floating-point
+    operations of the minimum-work formulation); None for kernels without a model.
+    s = 4 for float instantiations, 8 for double."""
     s = 4 if "<float" in name else 8
     b = 0.25 if z["refined"] else 0.125
     n_p, n_f = z["n_p"], z["n_free"]
     if name.startswith("k_zb_cheb<") and name.endswith((", false, 3>", ", false, 3, true>", ", false, 3, false>")):
-        return (15 * s + b) * n_f, "Q1 mass Chebyshev step, 3 components: read x, b, d; write d, x per free node"
+        return (15 * s + b) * n_f, "Q1 mass Chebyshev step, 3 components: read x, b, d; write d, x per free node", "hbm"
+    if name.startswith("k_tm_cheb<") and name.endswith(", false>"):
+        return (15 * s + b) * n_f, ("tensor-preconditioned mass Chebyshev update, 3 components: read the scaled "
+                                    "residual w, d, x; write d, x per free node"), "hbm"
+    if name.startswith("k_tm_resid<"):
+        return (9 * s + b) * n_f, "scaled mass residual, 3 components: read x, b; write w per free node", "hbm"
     if name.startswith("k_cg_q_zb<") and name.endswith(", 1>"):
-        return (2 * s + b) * n_p, "Q1 stiffness apply + p.q: read p, write q per pressure node"
+        return (2 * s + b) * n_p, "Q1 stiffness apply + p.q: read p, write q per pressure node", "hbm"
     if name.startswith("k_bi_apply<") and "OpCStencil<" in name:
         return (63 * s) * n_f, ("stored composite advection-diffusion stencil, 3 components: 54 coefficient "
-                                "planes, read x and w, write y per free node")
+                                "planes, read x and w, write y per free node"), "hbm"
     if name.startswith("k_bi_apply<") and "OpStencil<" in name:
         return (36 * s) * n_f, ("stored advection-diffusion stencil, 3 components: 27 coefficient planes, "
-                                "read x and w, write y per free node")
+                                "read x and w, write y per free node"), "hbm"
     if name.startswith("k_residual<") and "OpCStencil<double, 3>" in name:
         return (54 * 8 + 6 * 8 + 3 * 4) * n_f, ("FP64 residual of the composite stored stencil: 54 planes, "
-                                                 "read x, b, write r (FP32) per free node")
+                                                 "read x, b, write r (FP32) per free node"), "hbm"
     if name.startswith("k_residual<") and "OpStencil<double, 3>" in name:
         return (27 * 8 + 6 * 8 + 3 * 4) * n_f, ("FP64 residual of the stored stencil: 27 planes, read x, b, "
-                                                 "write r (FP32) per free node")
+                                                 "write r (FP32) per free node"), "hbm"
     if name.startswith("k_bi_apply<") and ("OpConv<" in name or "OpCConv<" in name):
-        return (12 * s + b) * n_f, ("matrix-free advection-diffusion apply, 3 components: read x, u^n and w, "
-                                    "write y per free node (rows formed on the fly)")
+        return CONV_ROW_FLOPS * n_f, ("matrix-free advection-diffusion apply, 3 components: each row formed "
+                                      "from u^n at its 27 neighbours and applied to x, %d operations per free "
+                                      "node in the factorised form (%.2f B of operands)" % (CONV_ROW_FLOPS, 12 * s + b)), "alu"
     if name.startswith("k_residual<") and ("OpConv<double>" in name or "OpCConv<double>" in name):
         return (9 * 8 + 3 * 4 + b) * n_f, ("FP64 matrix-free residual: read x, u^n, b, write r (FP32) per free "
-                                           "node (rows formed on the fly)")
+                                           "node (rows formed on the fly)"), "hbm"
     if name == "k_s1_build":
         planes = 54 if z["refined"] else 27
         return (3 * 8 + planes * 12) * n_p, ("advection-diffusion stencil assembly: read u^n, write the "
-                                              "FP64 and FP32 coefficient planes per node")
+                                              "FP64 and FP32 coefficient planes per node"), "hbm"
     return None
 
 
+def achieved_of(name: str, m, seconds: float) -> dict:
+    """Achieved rate of one dispatch of `seconds` for the kernel model m against its
+    peak: HBM GB/s, or vector TFLOP/s (FP32 or FP64 by the instantiation)."""
+    amount, what, bound = m
+    if bound == "alu":
+        peak = FP32_VECTOR_TFLOPS if "<float" in name else FP64_VECTOR_TFLOPS
+        ach = amount / seconds / 1e12
+        return {"bound": "alu", "alg_flops_per_launch": int(amount), "achieved": round(ach, 3),
+                "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 4), "what": what}
+    ach = amount / seconds / 1e9
+    return {"bound": "hbm", "alg_bytes_per_launch": int(amount), "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "what": what}
+
+
 def run_workload(workload: str, prec: int, pc: int, visc: int, steps: int, warmup: int, case=None,
-                 keep_state: bool = False, profile_steps: int = 3, advdiff: int = 0) -> dict:
+                 keep_state: bool = False, profile_steps: int = 3, advdiff: int = 0, mass_precond: int = 1) -> dict:
     """W untimed steps from rest; then `profile_steps` steps in which every kernel
     dispatch records its own start and end HIP events (the whole-step breakdown, which
     names the dominant kernel: the largest summed duration); then the K timed steps,
@@ -373,7 +410,8 @@ def run_workload(workload: str, prec: int, pc: int, visc: int, steps: int, warmu
     z = sizes_of(case, prec)
     print(f"[bench] {case.name}: {z['n_p']} nodes of P, {z['n_free']} free, M = {case.M}", file=sys.stderr,
           flush=True)
-    s = ibfe.Solver(**ibfe.inputs_from_case(case, precision=prec, precond=pc, viscous=visc, advdiff=advdiff))
+    s = ibfe.Solver(**ibfe.inputs_from_case(case, precision=prec, precond=pc, viscous=visc, advdiff=advdiff,
+                                            mass_precond=mass_precond))
     n = s.n_u
     s.set_state(np.zeros(3 * n), np.zeros(n), 0.0)
     s.step(warmup)
@@ -403,9 +441,7 @@ def run_workload(workload: str, prec: int, pc: int, visc: int, steps: int, warmu
         row = {"kernel": name, "total_ms": round(ms, 3), "share": round(ms / total_ms, 4) if total_ms else 0.0,
                "launches": cnt, "avg_us": round(avg_us, 3)}
         if m is not None:
-            ach = m[0] / (avg_us * 1e-6) / 1e9
-            row.update({"alg_bytes_per_launch": int(m[0]), "achieved": round(ach, 1),
-                        "frac": round(ach / HBM_PEAK_GBS, 4), "what": m[1]})
+            row.update(achieved_of(name, m, avg_us * 1e-6))
         rows.append(row)
     dom = dict(rows[0])
     ms, cnt = timed.get(dominant, (0.0, 0))
@@ -413,8 +449,7 @@ def run_workload(workload: str, prec: int, pc: int, visc: int, steps: int, warmu
                 "avg_us": round(1e3 * ms / max(1, cnt), 3)})
     m = kernel_model(dominant, z)
     if m is not None and cnt > 0:
-        ach = m[0] / (1e-3 * ms / cnt) / 1e9
-        dom.update({"achieved": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4)})
+        dom.update(achieved_of(dominant, m, 1e-3 * ms / cnt))
     out = {"case": case, "sizes": z, "steps_per_s": steps / elapsed, "ms_per_step": 1e3 * elapsed / steps,
            "elapsed_s": elapsed, "stats": st, "kernels": rows, "dominant": dom,
            "profile_steps": profile_steps, "kernel_ms_per_step": total_ms / profile_steps}
@@ -430,18 +465,14 @@ def roofline_of(res: dict, workload: str, precision: str, pc: int) -> dict:
     """The dominant kernel of the timed steps (largest summed duration over all kernels)
     against the HBM peak."""
     d = res["dominant"]
-    key = None
-    if d["kernel"].startswith("k_zb_cheb<") and d["kernel"].endswith((", false, 3>", ", false, 3, true>",
-                                                                      ", false, 3, false>")):
-        key = "mass"
-    elif d["kernel"].startswith("k_cg_q_zb<"):
-        key = "pressure"
-    traffic = counted_traffic(workload, precision, key) if (key and pc == 2) else None
-    roof = {"bound": "hbm", "achieved": d.get("achieved"), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": d.get("frac"), "traffic": round(traffic) if traffic else None,
+    traffic = counted_traffic(workload, precision, d["kernel"]) if pc == 2 else None
+    roof = {"bound": d.get("bound", "hbm"), "achieved": d.get("achieved"), "peak": d.get("peak", HBM_PEAK_GBS),
+            "unit": d.get("unit", "GB/s"), "frac": d.get("frac"), "traffic": round(traffic) if traffic else None,
             "kernel": d["kernel"], "share_of_kernel_time": d["share"], "avg_us": d["avg_us"],
-            "launches": d["timed_launches"], "alg_bytes_per_launch": d.get("alg_bytes_per_launch"),
-            "what": d.get("what")}
+            "launches": d["timed_launches"], "what": d.get("what")}
+    for k in ("alg_bytes_per_launch", "alg_flops_per_launch"):
+        if k in d:
+            roof[k] = d[k]
     return roof
 
 
@@ -455,6 +486,9 @@ def main() -> int:
                          "a 257x257x641 lattice), the pulsatile cylinder on 64x64x512 or the aorta-like arch "
                          "on 256x160x384")
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--mass-precond", choices=["tensor", "jacobi"], default="tensor",
+                    help="preconditioner of the consistent-mass correction's Chebyshev iteration: the "
+                         "tensor-product approximate inverse of the Q1 mass or Jacobi")
     ap.add_argument("--precond", choices=["mg", "jacobi"], default="mg",
                     help="pressure preconditioner: geometric multigrid or Jacobi")
     ap.add_argument("--viscous", choices=["laplacian", "strain"], default="laplacian",
@@ -509,8 +543,9 @@ def main() -> int:
     ad = 1 if args.advdiff == "stencil" else 0
     refined = args.workload == "aneurysm"
     case = make_case(args.workload)
+    mp = 1 if args.mass_precond == "tensor" else 0
     res = run_workload(args.workload, prec, pc, visc, args.steps, args.warmup, case=case, keep_state=True,
-                       advdiff=ad)
+                       advdiff=ad, mass_precond=mp)
     s = res.pop("solver")
     st = res["stats"]
     print(f"[bench] {case.name}: {res['steps_per_s']:.2f} steps/s", file=sys.stderr, flush=True)
@@ -544,7 +579,8 @@ def main() -> int:
     if prec == 1 and not args.no_check:
         # the same warm-up and timed steps in FP64: the accuracy the mixed-precision rate is quoted at
         import paper_2007_02082_amd as ibfe
-        ref = ibfe.Solver(**ibfe.inputs_from_case(case, precision=0, precond=pc, viscous=visc, advdiff=ad))
+        ref = ibfe.Solver(**ibfe.inputs_from_case(case, precision=0, precond=pc, viscous=visc, advdiff=ad,
+                                                  mass_precond=mp))
         ref.set_state(np.zeros(3 * ref.n_u), np.zeros(ref.n_p), 0.0)
         t0r = time.perf_counter()
         ref.step(args.warmup + res["profile_steps"] + args.steps)
@@ -577,7 +613,8 @@ def main() -> int:
                    "refined_cells": int(case.refine_cell.sum()) if refined else 0,
                    "n_active": res["sizes"]["n_p"], "lagrangian_points": case.M, "dt": case.dt,
                    "precision": args.precision, "pressure_preconditioner": args.precond,
-                   "viscous_form": args.viscous, "advdiff_operator": args.advdiff},
+                   "viscous_form": args.viscous, "advdiff_operator": args.advdiff,
+                   "mass_preconditioner": args.mass_precond},
         "roofline": roof,
     }
     out.update(extra)
@@ -586,7 +623,7 @@ def main() -> int:
         for w in ("pulsatile", "aneurysm", "aorta"):
             if w == args.workload:
                 continue
-            r = run_workload(w, prec, pc, visc, args.steps, args.warmup, advdiff=ad)
+            r = run_workload(w, prec, pc, visc, args.steps, args.warmup, advdiff=ad, mass_precond=mp)
             rf = roofline_of(r, w, args.precision, pc)
             others[r["case"].name] = {
                 "steps_per_s": round(r["steps_per_s"], 3), "ms_per_step": round(r["ms_per_step"], 3),

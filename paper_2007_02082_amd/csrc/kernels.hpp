@@ -631,8 +631,15 @@ __global__ __launch_bounds__(kBlock) void k_bi_p(NodeList nl, Op op,
 }
 
 // y = A xin; partials w.y (and y.y for MODE 1)
+// waves per SIMD the apply is compiled for (operators may raise it)
+template <class Op>
+struct ApplyWaves {
+  static constexpr int value = 1;
+};
+
 template <typename T, class Op, int MODE>
-__global__ __launch_bounds__(kBlock) void k_bi_apply(NodeList nl, Op op,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ApplyWaves<Op>::value)))
+void k_bi_apply(NodeList nl, Op op,
                                                      const T* __restrict__ xin, T* __restrict__ y,
                                                      const T* __restrict__ w,
                                                      double* __restrict__ partials, const KScal* sc) {
