@@ -280,6 +280,9 @@ struct ibfe_ctx {
   // lattice, its kFlagExtra rows (3 planes; 0 elsewhere)
   double *tmw64 = nullptr, *tmwx64 = nullptr;
   float *tmw32 = nullptr, *tmwx32 = nullptr;
+  // BiCGStab's r, rhat, p, v, s, t in node-list order (6 vectors of 3 x 64 nchunks)
+  double* bc64 = nullptr;
+  float* bc32 = nullptr;
 
   FormCoefs fc{};
   // lower end of the Chebyshev interval of the mass correction on a refined
@@ -703,6 +706,18 @@ int setup_device(ibfe_ctx& c) {
       if (P.refined && (rc = c.field(&c.tmwx64, 3))) return rc;
     }
   }
+  if (P.params.advection == 0 && c.nl.per_lane) {
+    // the tentative-velocity BiCGStab (FP32 inner solves with the mixed scheme)
+    const size_t nbc = size_t(6) * 3 * size_t(c.nchunks) * 64;
+    void* base = nullptr;
+    if (P.params.precision == 1) {
+      if ((rc = c.dalloc(&base, sizeof(float) * nbc))) return rc;
+      c.bc32 = reinterpret_cast<float*>(base);
+    } else {
+      if ((rc = c.dalloc(&base, sizeof(double) * nbc))) return rc;
+      c.bc64 = reinterpret_cast<double*>(base);
+    }
+  }
   if (P.refined && (rc = setup_refined(c))) return rc;
   if (P.params.precision == 1) {
     if (stencil && (rc = c.field(&c.coef32, ncoef))) return rc;
@@ -1031,14 +1046,35 @@ int launch_bi_apply(ibfe_ctx& c, const Op& op, NodeList nl, const T* xin, T* y, 
   return nr;
 }
 
+template <typename T>
+T* bicg_bufs(const ibfe_ctx& c);
+template <>
+double* bicg_bufs<double>(const ibfe_ctx& c) { return c.bc64; }
+template <>
+float* bicg_bufs<float>(const ibfe_ctx& c) { return c.bc32; }
+
+// wv: 8 lattice vectors (r, rhat, p, v, phat, s, shat, t); with a per-lane node
+// list only phat and shat are used, the others come from the node-list buffers
 template <typename T, class Op>
 int run_bicgstab(ibfe_ctx& c, const Op& op, const T* b, T* x, T* const* wv, int slot, double rtol,
                  int max_iters, SolveOut& out, bool zero_guess = false) {
   const int nb = blocks_for(c.nchunks), nr = red_blocks(c.nchunks);
   const NodeList nl = c.nl;
   const double* pa = c.partials;
+  // with a per-lane node list, r, rhat, p, v, s, t in node-list order
+  T* bc = bicg_bufs<T>(c);
+  if (nl.per_lane && bc == nullptr) return fail(IBFE_EINVAL, "internal: BiCGStab buffers not allocated");
+  const int64_t cv = int64_t(3) * c.nchunks * 64;
   T *r = wv[0], *rhat = wv[1], *p = wv[2], *v = wv[3], *phat = wv[4], *s = wv[5], *shat = wv[6],
     *t = wv[7];
+  if (nl.per_lane) {
+    r = bc;
+    rhat = bc + cv;
+    p = bc + 2 * cv;
+    v = bc + 3 * cv;
+    s = bc + 4 * cv;
+    t = bc + 5 * cv;
+  }
   KScal* sc = &c.scal[slot];
   const KScal* csc = sc;
   int prc;

@@ -542,8 +542,20 @@ __global__ __launch_bounds__(kBlock) void k_cg_p(NodeList nl, Op op,
 }
 
 // ---------------------------------------------------------------------------
-// BiCGStab (right Jacobi preconditioning), NC-plane vectors
+// BiCGStab (right Jacobi preconditioning), NC-plane vectors.  x, b and the
+// preconditioned directions phat, shat (read at the neighbours by the applies)
+// live on the lattice.  With a per-lane node list the other vectors (r, rhat,
+// p, v, s, t), touched only at the row itself, are kept in node-list order:
+// component d of the node of lane l of chunk c at d * 64 nl.n + 64 c + l (dense,
+// whole cache lines where a vessel's rows fill part of each lattice line); with
+// a list of lattice chunks they stay on the lattice (measured: the chunk order
+// made the uniform cylinder's apply slower, 78 -> 94 us).
 // ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int64_t nl_index(const NodeList& nl, int c, int d, int n, int64_t stride) {
+  return nl.per_lane ? int64_t(d) * (int64_t(nl.n) * 64) + int64_t(c) * 64 + int(threadIdx.x & 63)
+                     : int64_t(d) * stride + n;
+}
 
 // r = b - A x, rhat = r, p = v = 0; partials r.r, b.b
 template <typename T, class Op>
@@ -566,12 +578,13 @@ __global__ __launch_bounds__(kBlock) void k_bi_init(NodeList nl, Op op,
 #pragma unroll
     for (int d = 0; d < NC; ++d) {
       const int64_t i = d * op.stride + n;
+      const int64_t q = nl_index(nl, c, d, n, op.stride);
       const T bi = rw ? b[i] : T(0);
       const T ri = rw ? T(bi - ax[d]) : T(0);
-      r[i] = ri;
-      rhat[i] = ri;
-      p[i] = T(0);
-      v[i] = T(0);
+      r[q] = ri;
+      rhat[q] = ri;
+      p[q] = T(0);
+      v[q] = T(0);
       s[0] += double(ri) * double(ri);
       s[1] += double(bi) * double(bi);
     }
@@ -618,10 +631,10 @@ __global__ __launch_bounds__(kBlock) void k_bi_p(NodeList nl, Op op,
       const T di = op.inv_diag(n);
 #pragma unroll
       for (int d = 0; d < NC; ++d) {
-        const int64_t i = d * op.stride + n;
-        const T pi = r[i] + beta * (p[i] - omega * v[i]);
-        p[i] = pi;
-        phat[i] = pi * di;
+        const int64_t q = nl_index(nl, c, d, n, op.stride);
+        const T pi = r[q] + beta * (p[q] - omega * v[q]);
+        p[q] = pi;
+        phat[d * op.stride + n] = pi * di;
       }
     } else {
 #pragma unroll
@@ -630,12 +643,14 @@ __global__ __launch_bounds__(kBlock) void k_bi_p(NodeList nl, Op op,
   }
 }
 
-// y = A xin; partials w.y (and y.y for MODE 1)
 // waves per SIMD the apply is compiled for (operators may raise it)
 template <class Op>
 struct ApplyWaves {
   static constexpr int value = 1;
 };
+
+// y = A xin (xin on the lattice, y and w in node-list order); partials w.y (and
+// y.y for MODE 1)
 
 template <typename T, class Op, int MODE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ApplyWaves<Op>::value)))
@@ -654,10 +669,10 @@ void k_bi_apply(NodeList nl, Op op,
     if (rw) op.apply(n, xin, ay);
 #pragma unroll
     for (int d = 0; d < NC; ++d) {
-      const int64_t i = d * op.stride + n;
+      const int64_t q = nl_index(nl, c, d, n, op.stride);
       const T yi = rw ? ay[d] : T(0);
-      y[i] = yi;
-      s[0] += double(w[i]) * double(yi);
+      y[q] = yi;
+      s[0] += double(w[q]) * double(yi);
       if (MODE == 1) s[1] += double(yi) * double(yi);
     }
   }
@@ -708,15 +723,15 @@ __global__ __launch_bounds__(kBlock) void k_bi_s(NodeList nl, Op op,
       const T di = op.inv_diag(n);
 #pragma unroll
       for (int d = 0; d < NC; ++d) {
-        const int64_t i = d * op.stride + n;
-        const T si = r[i] - alpha * v[i];
-        s[i] = si;
-        shat[i] = si * di;
+        const int64_t q = nl_index(nl, c, d, n, op.stride);
+        const T si = r[q] - alpha * v[q];
+        s[q] = si;
+        shat[d * op.stride + n] = si * di;
       }
     } else {
 #pragma unroll
       for (int d = 0; d < NC; ++d) {
-        s[d * op.stride + n] = T(0);
+        s[nl_index(nl, c, d, n, op.stride)] = T(0);
         shat[d * op.stride + n] = T(0);
       }
     }
@@ -742,10 +757,11 @@ __global__ __launch_bounds__(kBlock) void k_bi_x(NodeList nl, Op op,
 #pragma unroll
       for (int d = 0; d < NC; ++d) {
         const int64_t i = d * op.stride + n;
+        const int64_t q = nl_index(nl, c, d, n, op.stride);
         x[i] += alpha * phat[i] + omega * shat[i];
-        const T ri = s[i] - omega * t[i];
-        r[i] = ri;
-        v[0] += double(rhat[i]) * double(ri);
+        const T ri = s[q] - omega * t[q];
+        r[q] = ri;
+        v[0] += double(rhat[q]) * double(ri);
         v[1] += double(ri) * double(ri);
       }
     }

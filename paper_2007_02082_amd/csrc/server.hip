@@ -76,6 +76,9 @@ size_t footprint_of(const ibfe_grid& g, int64_t M, const ibfe_params& pr) {
   // the tensor-preconditioned mass correction: scaled residual (and its rows with
   // coarse cells), 3 planes each
   if (pr.mass_precond == 1) bytes += double(stride) * 3.0 * (ref ? 2.0 : 1.0) * (pr.precision == 1 ? 4.0 : 8.0);
+  // the tentative-velocity BiCGStab's six node-list-order vectors (at most one
+  // entry per lattice position and component)
+  if (pr.advection == 0) bytes += double(stride) * 18.0 * (pr.precision == 1 ? 4.0 : 8.0);
   if (pr.precond >= 1) bytes += 0.15 * double(stride) * (5.0 * (pr.precision == 1 ? 4 : 8) + 2.0);
   // IB arrays: stencils, spreading lists and G, held at the sizes a rebuild for
   // moved points may need (64 pairs per point, four times G's entries)
