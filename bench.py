@@ -55,14 +55,14 @@ def counted_traffic(workload: str, precision: str, kernel: str):
     (FETCH_SIZE and WRITE_SIZE, scaled by a copy of known size), or None when the
     summary is for another kernel or the kernel sources changed after the counters
     were taken."""
-    path = os.path.join(ROOT, "profiles", f"dominant_traffic_{workload}_{precision}.json")
+    path = os.path.join(ROOT, "profiles", f"kernel_traffic_{workload}_{precision}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("kernel") != kernel or rec.get("source_hash") != kernel_sources_hash():
+    if rec.get("source_hash") != kernel_sources_hash() or kernel not in rec.get("kernels", {}):
         return None
-    return rec["traffic_bytes"]
+    return rec["kernels"][kernel]["traffic_bytes"]
 
 
 METRIC = "IPCS steps/sec + apply HBM GB/s at 1e-6 rel; served solves/sec, p50/p99"
