@@ -96,6 +96,10 @@ def test_input_errors():
     ibfe.Plan(**dict(kw, viscous=1, advection=1))
     with pytest.raises(ibfe.IbfeError, match="EINVAL"):
         ibfe.Plan(**dict(kw, viscous=2))
+    # mass-correction preconditioner: 0 (Jacobi) or 1 (tensor product)
+    ibfe.Plan(**dict(kw, mass_precond=0))
+    with pytest.raises(ibfe.IbfeError, match="mass_precond"):
+        ibfe.Plan(**dict(kw, mass_precond=2))
     rc = synth.refined_cylinder(8, 8, length=1.25, band=0.3)
     ibfe.Plan(**ibfe.inputs_from_case(rc, viscous=1))
     ibfe.Plan(**ibfe.inputs_from_case(rc, viscous=1, advection=1))
