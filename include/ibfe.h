@@ -207,7 +207,7 @@ typedef struct ibfe_stats {
   int32_t s1_iters;       /* tentative velocity solve (BiCGStab iterations)     */
   int32_t ib_iters;       /* IB force solve (CG iterations)                     */
   int32_t s3_iters;       /* pressure increment solve (CG iterations)           */
-  int32_t s4_iters;       /* velocity correction solve (CG iterations)          */
+  int32_t s4_iters;       /* velocity correction solve (Chebyshev steps)        */
   int32_t s1_outer, s3_outer, s4_outer; /* refinement sweeps (mixed mode)       */
   double s1_res, ib_res, s3_res, s4_res; /* final relative residuals            */
   double poisson_apply_ms;   /* summed duration of the pressure stiffness apply  */
@@ -332,7 +332,8 @@ int ibfe_get_stats(const ibfe_ctx* ctx, ibfe_stats* stats);
  * same results).  Both calls reset the sums, and the two summary fields of
  * ibfe_stats: poisson_apply_ms / poisson_applies (the pressure stiffness apply
  * k_cg_q_zb<*, 1>) and mass_apply_ms / mass_applies (the mass Chebyshev step of
- * the velocity correction, k_zb_cheb<*, false, 3>). */
+ * the velocity correction: k_zb_cheb<*, false, 3, *> with mass_precond = 0, the
+ * update pass k_tm_cheb<*, 3, *, *> with mass_precond = 1). */
 int ibfe_set_kernel_timing(ibfe_ctx* ctx, int enable);
 
 /* Summed durations per kernel since timing was enabled, longest total first:

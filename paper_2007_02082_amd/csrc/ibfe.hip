@@ -414,12 +414,14 @@ int collect_kernel_times(ibfe_ctx& c) {
     KTimer::Acc& a = kt.acc[name];
     a.ms += ms;
     a.launches += 1;
-    // the mass Chebyshev step (three components, lattice or walk-order vectors)
+    // the mass Chebyshev step (three components, lattice or walk-order vectors):
+    // the Jacobi step, or the update pass of the tensor-preconditioned one
     auto ends = [&](const std::string& tail) {
       return name.size() > tail.size() && name.compare(name.size() - tail.size(), tail.size(), tail) == 0;
     };
-    const bool mass = name.rfind("k_zb_cheb<", 0) == 0 &&
-                      (ends(", false, 3>") || ends(", false, 3, true>") || ends(", false, 3, false>"));
+    const bool mass = (name.rfind("k_zb_cheb<", 0) == 0 &&
+                       (ends(", false, 3>") || ends(", false, 3, true>") || ends(", false, 3, false>"))) ||
+                      name.rfind("k_tm_cheb<", 0) == 0;
     const bool pressure = name == "k_cg_q_zb<float, 1>" || name == "k_cg_q_zb<double, 1>";
     if (mass) {
       c.stats.mass_apply_ms += ms;
