@@ -309,7 +309,8 @@ __global__ __launch_bounds__(kBlock) void k_zb_cheb_batch(ChebBatch<T> B, int k,
 }
 
 // ---------------------------------------------------------------------------
-// Consistent-mass correction with a tensor-product preconditioner.
+// Consistent-mass correction with a tensor-product preconditioner (the
+// velocity correction M_FF delta = (G Phi)_F of Sections 2.2 and 2.4).
 //
 // On a uniform grid the Q1 mass stencil is the product over the three axes of
 // (1, 4, 1) h/6; scaled by its diagonal, each axis contributes the symbol
