@@ -881,8 +881,12 @@ struct SolveOut {
 // last solve's count first, then 2 at a time (iterations launched past
 // convergence return at once but still cost a dispatch each; batches of 8 after
 // the first cost about 1 % of the step against batches of 2)
+// The first batch is capped: a solve that ran into its iteration cap leaves an
+// estimate of up to max_iters, and one graph of that many iterations (hundreds
+// of thousands of kernel nodes) is more than capture and instantiation handle.
+constexpr int kMaxGraphIters = 32;
 int next_batch(int est, int done_so_far) {
-  if (done_so_far == 0) return std::max(4, est - 2);
+  if (done_so_far == 0) return std::min(kMaxGraphIters, std::max(4, est - 2));
   return 2;
 }
 
@@ -1838,7 +1842,7 @@ int run_pcg_mg(ibfe_ctx& c, const Op& op, std::vector<MGDev<T>>& lv, const T* b,
   KScal s{};
   c.kt.begin_solve();
   while (true) {
-    const int batch = std::min(launched == 0 ? std::max(2, c.est[slot] - 1) : 2, max_iters + 1 - launched);
+    const int batch = std::min(launched == 0 ? std::min(kMaxGraphIters, std::max(2, c.est[slot] - 1)) : 2, max_iters + 1 - launched);
     auto body = [&]() -> int {
       for (int k = 0; k < batch; ++k) {
         if (c.timing) c.kt.mark();
