@@ -884,7 +884,7 @@ struct SolveOut {
 // The first batch is capped: a solve that ran into its iteration cap leaves an
 // estimate of up to max_iters, and one graph of that many iterations (hundreds
 // of thousands of kernel nodes) is more than capture and instantiation handle.
-constexpr int kMaxGraphIters = 32;
+constexpr int kMaxGraphIters = 256;
 int next_batch(int est, int done_so_far) {
   if (done_so_far == 0) return std::min(kMaxGraphIters, std::max(4, est - 2));
   return 2;
